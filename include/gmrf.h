@@ -1,0 +1,183 @@
+/*
+ * gmrf.h -- C ABI of the MI355X (gfx950) Krylov sampler and log-determinant library.
+ *
+ * Method: Simpson, Turner, Strickland & Pettitt, "Scalable iterative methods for sampling
+ * from massive Gaussian random vectors" (arXiv 1312.1476).
+ *   - Algorithm 1 (Section 4): Lanczos approximation x_m = ||z|| V_m T_m^{-1/2} e_1 of
+ *     x = Q^{-1/2} z for a sparse SPD precision Q, only products Q v being needed (Section 2).
+ *   - Theorem 1 (Section 4): the error is bounded by lambda_min^{-1/2} ||r_m||, r_m the
+ *     conjugate-gradient residual of Q y = z; its relative size rho_m is the stopping test.
+ *   - Proposition 1 (Section 5): sampling with a factored preconditioner M = F F^T; here M is
+ *     the periodic (block-circulant) version of a lattice Q, applied with 2D FFTs (Section 5.1).
+ *   - Section 6: Hutchinson estimate of log det Q with Rademacher probes, each quadratic form
+ *     v^T log(Q) v evaluated by Lanczos (Gauss) quadrature; Section 6.2: preconditioned split
+ *     log det Q = log det(F^{-1} Q F^{-T}) + 2 log det F.
+ *
+ * Conventions shared by every entry point
+ *   - Functions never abort or throw; they return a gmrf_status.  A thread-local message for
+ *     the last failure is available from gmrf_last_error().
+ *   - Vectors are column-major blocks: n rows (lattice points, row-major lattice order
+ *     i = (i1*N2 + i2)*N3 + i3) times k columns (right-hand sides, probes).
+ *   - "Device" pointers are HIP device allocations on the current device; "host" pointers
+ *     are ordinary host memory.  The caller owns every buffer it passes; the library owns
+ *     the memory behind a gmrf_op handle and its own scratch.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Sample and log-det calls are
+ *     blocking: they return after the results (and `info`) are complete.
+ *   - Calls that share one gmrf_op may run concurrently; each call has its own scratch.
+ */
+#ifndef GMRF_H
+#define GMRF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GMRF_OK = 0,
+    GMRF_EINVAL = 1,        /* bad argument; outputs untouched                              */
+    GMRF_ENOTSPD = 2,       /* alpha_j <= 0, a pivot d_j <= 0 or T_m not positive definite   */
+    GMRF_ENOCONV = 3,       /* per right-hand side: rho_m > tol at m = m_max (X holds x_m)   */
+    GMRF_ENOMEM = 4,        /* device allocation failed or the HBM budget would be exceeded  */
+    GMRF_EDEVICE = 5,       /* no usable gfx950 device, or a HIP runtime error               */
+    GMRF_EUNSUPPORTED = 6   /* valid request outside this build (e.g. FFT on non-2^p sides)   */
+} gmrf_status;
+
+typedef enum { GMRF_F64 = 0, GMRF_F32 = 1 } gmrf_dtype;   /* storage of Krylov vectors + Q */
+typedef enum { GMRF_FREE = 0, GMRF_PERIODIC = 1 } gmrf_boundary;
+
+typedef struct gmrf_op gmrf_op;       /* opaque, device resident */
+
+/* Per right-hand-side result of gmrf_sample.
+ *   m_used       Krylov dimension m of the returned x_m
+ *   status       GMRF_OK, GMRF_ENOCONV, GMRF_ENOTSPD or GMRF_EINVAL (non-finite column of Z)
+ *   rel_residual rho_m = ||r_m|| / ||z||, r_m the CG residual of Theorem 1 (of A = F^{-1}QF^{-T}
+ *                when preconditioned), from the LDL^T pivots of T_m
+ *   err_bound    lambda_lb^{-1/2} rho_m: Theorem 1's a posteriori bound on ||x - x_m|| / ||z||
+ *                (on ||u - u_m|| / ||z|| when preconditioned) using an analytic lower bound
+ *                lambda_lb on lambda_min (tau*kappa2 for first-order lattices, tau*kappa2^2 for
+ *                second order); NaN when no bound is known (CSR, preconditioned).          */
+typedef struct {
+    int32_t m_used;
+    int32_t status;
+    double rel_residual;
+    double err_bound;
+} gmrf_info;
+
+/* ---- operators (Section 2: Q is only accessed through products Q v) -------------------- */
+
+/* Lattice precision on a regular 1D/2D/3D lattice with shape[0..ndim-1] points per axis:
+ *   order 1:  Q = tau (kappa2 I + L)        (5-point in 2D, 7-point in 3D)
+ *   order 2:  Q = tau (kappa2 I + L)^2      (13-point in 2D)
+ * L is the graph Laplacian of the grid (bc = GMRF_FREE) or torus (bc = GMRF_PERIODIC) graph.
+ * Matrix free: no coefficients are stored.  storage selects FP64 or FP32 Krylov vectors
+ * (Lanczos scalars, reductions and the tridiagonal step are FP64 in both).
+ * EINVAL: ndim not in 1..3, a side < 1, order not 1/2, tau <= 0, non-finite kappa2.        */
+gmrf_status gmrf_op_create_lattice(int ndim, const int64_t* shape, int order, double kappa2,
+                                   double tau, gmrf_boundary bc, gmrf_dtype storage,
+                                   gmrf_op** out);
+
+/* General sparse SPD Q in CSR form (host arrays, copied to the device; 0-based indices,
+ * row_ptr[n] = nnz).  Symmetry is the caller's responsibility; a non-SPD Q is reported as
+ * GMRF_ENOTSPD by the sampling calls.  EINVAL: n < 1, bad row_ptr or out-of-range column. */
+gmrf_status gmrf_op_create_csr(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                               const double* values, gmrf_dtype storage, gmrf_op** out);
+
+/* Proposition 1 with M = the periodic version of a 2D lattice Q (block circulant), F = M^{1/2}
+ * its symmetric root, applied with 2D FFTs (Section 5.1).  Sampling then runs Algorithm 1 on
+ * A = M^{-1/2} Q M^{-1/2} and returns x = M^{-1/2} u_m; log det adds log det M (Section 6.2).
+ * EUNSUPPORTED: not a 2D lattice, or a side that is not a power of two in [8, 4096].      */
+gmrf_status gmrf_op_set_circulant_precond(gmrf_op* Q, int enable);
+
+/* Device bytes one gmrf_sample call needs for k right-hand sides and m_max steps (Krylov
+ * basis, work vectors, partial sums, FFT scratch), plus what the handle keeps resident.    */
+gmrf_status gmrf_op_bytes(const gmrf_op* Q, int64_t k, int32_t m_max, int reorth, size_t* bytes);
+
+/* Lattice size n of the operator. */
+gmrf_status gmrf_op_size(const gmrf_op* Q, int64_t* n);
+
+/* Y = Q X for k columns, X and Y device buffers in the operator's storage dtype (n x k,
+ * column-major).  The SpMV/SpMM kernel of the sampler on its own (Section 2).            */
+gmrf_status gmrf_op_apply(const gmrf_op* Q, const void* X, void* Y, int64_t k, void* stream);
+
+/* Y = M^{-1/2} X (real space, storage dtype, device) for a handle with circulant
+ * preconditioning enabled: the FFT multiplier of Proposition 1 on its own.              */
+gmrf_status gmrf_precond_apply(const gmrf_op* Q, const void* X, void* Y, int64_t k, void* stream);
+
+void gmrf_op_destroy(gmrf_op* Q);
+
+/* ---- sampling: Algorithm 1 (Section 4), Proposition 1 (Section 5) ---------------------- */
+
+/* X[:, r] = x_m for each column z = Z[:, r] (Z, X: device FP64, n x k column-major).
+ * tol > 0: stop at the first m with rho_m <= tol (or at breakdown), else at m_max with
+ *          status GMRF_ENOCONV for that column;  tol <= 0: exactly m_max steps.
+ * reorth:  0 = plain three-term recurrence, 1 = full reorthogonalisation (classical
+ *          Gram-Schmidt applied twice against all stored basis vectors).
+ * info:    host array of k entries (may be NULL).
+ * Returns GMRF_OK when every column ended OK or ENOCONV; GMRF_ENOTSPD if some column was
+ * not positive definite (its X column is NaN); EINVAL/ENOMEM/EDEVICE on call failure.    */
+gmrf_status gmrf_sample(const gmrf_op* Q, const double* Z, int64_t k, double tol,
+                        int32_t m_max, int reorth, double* X, gmrf_info* info, void* stream);
+
+/* As gmrf_sample, and also copies the Lanczos coefficients out (host arrays, may be NULL):
+ * alpha[r * m_max + j - 1] = alpha_j (j = 1..m_used), beta[r * (m_max + 1) + j] = beta_j
+ * (j = 0..m_used, beta_0 = ||z||).                                                         */
+gmrf_status gmrf_sample_ex(const gmrf_op* Q, const double* Z, int64_t k, double tol,
+                           int32_t m_max, int reorth, double* X, gmrf_info* info,
+                           double* alpha, double* beta, void* stream);
+
+/* ---- log-determinant: Section 6 (Hutchinson + Lanczos quadrature) ---------------------- */
+
+/* log det Q ~= N^{-1} sum_p Gamma_p with Gamma_p = ||v_p||^2 e_1^T log(T_m) e_1 from m steps
+ * of the recurrence started at probe v_p (no reorthogonalisation).
+ * probes: NULL = Rademacher probes from `seed` (Philox4x64-10 rule, see gmrf_rademacher),
+ *         else a device int8 n x n_probes block of +-1 entries.
+ * Outputs (host): *logdet = mean, *std_err = sd(Gamma)/sqrt(N) (NaN for N = 1),
+ * per_probe[p] = Gamma_p (may be NULL).  With circulant preconditioning the estimate is
+ * Hutchinson on A = M^{-1/2} Q M^{-1/2} plus the closed-form log det M (Section 6.2, with the
+ * sign that makes det(F^{-1} Q F^{-T}) = det Q / det(F)^2 hold).                            */
+gmrf_status gmrf_logdet(const gmrf_op* Q, int32_t n_probes, int32_t m, uint64_t seed,
+                        const int8_t* probes, double* logdet, double* std_err,
+                        double* per_probe, void* stream);
+
+/* Rademacher probes (Section 6) into a device int8 n x n_probes block:
+ *   v_p[i] = +1 if bit (i mod 256) mod 64 of word (i mod 256) / 64 of
+ *            Philox4x64-10(counter = (i / 256, p, 0, 0), key = (seed, 0)) is 0, else -1.
+ * Philox4x64-10 is the counter-based generator of Salmon et al. (SC'11).                    */
+gmrf_status gmrf_rademacher(uint64_t seed, int64_t n, int32_t n_probes, int8_t* out,
+                            void* stream);
+
+/* ---- the tridiagonal step on its own (Algorithm 1, final step; Section 6 quadrature) --- */
+
+/* For each of k tridiagonal matrices T_r = tridiag(beta_r, alpha_r, beta_r) of size m[r]
+ * (device arrays: alpha[r * ld + i], beta[r * ld + i] the off-diagonal (i < m[r] - 1),
+ * m[r] <= ld):  y[r * ld + i] = (T_r^{-1/2} e_1)_i.  Computed by a trapezoidal rule for
+ * lambda^{-1/2} = (2/pi) int exp(s) / (exp(2s) + lambda) ds on the real line: the rational
+ * approximation of T^{-1/2} that the caption of Algorithm 1 suggests.  status[r] (device)
+ * = GMRF_OK or GMRF_ENOTSPD.                                                               */
+gmrf_status gmrf_tridiag_invsqrt_e1(const double* alpha, const double* beta, const int32_t* m,
+                                    int32_t k, int32_t ld, double* y, int32_t* status,
+                                    void* stream);
+
+/* out[r] = e_1^T log(T_r) e_1 (device), same layout; log(lambda) =
+ * int exp(s) (1/(1 + exp(s)) - 1/(lambda + exp(s))) ds by the trapezoidal rule.            */
+gmrf_status gmrf_tridiag_log_e1(const double* alpha, const double* beta, const int32_t* m,
+                                int32_t k, int32_t ld, double* out, int32_t* status,
+                                void* stream);
+
+/* ---- memory budget and errors ---------------------------------------------------------- */
+
+/* Cap on device bytes held by the library's scratch pool (0 = no cap).  Calls that would
+ * exceed it return GMRF_ENOMEM without running.                                             */
+gmrf_status gmrf_set_hbm_budget(size_t bytes);
+size_t gmrf_hbm_in_use(void);
+
+const char* gmrf_strerror(gmrf_status s);
+const char* gmrf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GMRF_H */

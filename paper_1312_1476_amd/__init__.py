@@ -1,0 +1,216 @@
+"""MI355X (gfx950) Krylov sampler and Lanczos log-determinant for Gaussian Markov random fields.
+
+Simpson, Turner, Strickland & Pettitt, "Scalable iterative methods for sampling from massive
+Gaussian random vectors" (arXiv 1312.1476): Algorithm 1 (Lanczos approximation of
+Q^{-1/2} z), Proposition 1 with the block-circulant preconditioner of Section 5.1, and the
+Hutchinson log-determinant with Lanczos quadrature of Section 6.
+
+This module only marshals arguments to the C ABI of libgmrf.so (include/gmrf.h); every
+step of the computation runs in the library's HIP kernels.  Device buffers are torch CUDA
+(HIP) tensors; blocks of vectors are (k, n) tensors, row r being right-hand side r (the
+column-major n x k block of the C ABI).
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _abi
+from ._abi import GMRF_F32, GMRF_F64, GMRF_FREE, GMRF_PERIODIC, GmrfError, Info, check, lib
+
+__all__ = ["Operator", "rademacher", "tridiag_invsqrt_e1", "tridiag_log_e1", "set_hbm_budget",
+           "hbm_in_use", "GmrfError", "STATUS"]
+
+STATUS = _abi.STATUS_NAMES
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _storage_code(storage):
+    if storage in ("f64", "float64", GMRF_F64):
+        return GMRF_F64
+    if storage in ("f32", "float32", GMRF_F32):
+        return GMRF_F32
+    raise ValueError("storage must be 'f64' or 'f32'")
+
+
+class Operator:
+    """A device-resident precision operator (gmrf_op handle)."""
+
+    def __init__(self, handle, n, storage, shape=None):
+        self._h = handle
+        self.n = int(n)
+        self.storage = storage
+        self.shape = shape
+
+    # -- construction ---------------------------------------------------------------------
+    @classmethod
+    def lattice(cls, shape, order=1, kappa2=1.0, tau=1.0, boundary="free", storage="f64"):
+        shape = tuple(int(s) for s in shape)
+        arr = (C.c_int64 * len(shape))(*shape)
+        h = C.c_void_p()
+        bc = GMRF_PERIODIC if boundary == "periodic" else GMRF_FREE
+        sc = _storage_code(storage)
+        check(lib().gmrf_op_create_lattice(len(shape), arr, int(order), float(kappa2), float(tau), bc, sc,
+                                           C.byref(h)), "gmrf_op_create_lattice")
+        return cls(h, int(np.prod(shape)), sc, shape)
+
+    @classmethod
+    def csr(cls, n, indptr, indices, data, storage="f64"):
+        rp = np.ascontiguousarray(indptr, dtype=np.int64)
+        ci = np.ascontiguousarray(indices, dtype=np.int32)
+        va = np.ascontiguousarray(data, dtype=np.float64)
+        h = C.c_void_p()
+        sc = _storage_code(storage)
+        check(lib().gmrf_op_create_csr(int(n), rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p),
+                                       va.ctypes.data_as(C.c_void_p), sc, C.byref(h)), "gmrf_op_create_csr")
+        return cls(h, n, sc)
+
+    def set_circulant_precond(self, enable=True):
+        check(lib().gmrf_op_set_circulant_precond(self._h, 1 if enable else 0), "gmrf_op_set_circulant_precond")
+        return self
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().gmrf_op_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def torch_dtype(self):
+        torch = _torch()
+        return torch.float64 if self.storage == GMRF_F64 else torch.float32
+
+    def bytes(self, k, m_max, reorth=False):
+        out = C.c_size_t()
+        check(lib().gmrf_op_bytes(self._h, int(k), int(m_max), int(bool(reorth)), C.byref(out)), "gmrf_op_bytes")
+        return out.value
+
+    # -- kernels -----------------------------------------------------------------------------
+    def _check_block(self, X, dtype, name):
+        if X.dim() != 2 or X.shape[1] != self.n or not X.is_contiguous() or X.dtype != dtype or not X.is_cuda:
+            raise ValueError(f"{name} must be a contiguous CUDA ({dtype}) tensor of shape (k, {self.n})")
+
+    def apply(self, X, out=None, stream=None):
+        """Y = Q X in the storage dtype (rows of X are vectors)."""
+        torch = _torch()
+        self._check_block(X, self.torch_dtype, "X")
+        Y = out if out is not None else torch.empty_like(X)
+        check(lib().gmrf_op_apply(self._h, _dptr(X), _dptr(Y), X.shape[0], _stream_ptr(stream)), "gmrf_op_apply")
+        return Y
+
+    def precond_apply(self, X, out=None, stream=None):
+        """Y = M^{-1/2} X (circulant preconditioning must be enabled)."""
+        torch = _torch()
+        self._check_block(X, self.torch_dtype, "X")
+        Y = out if out is not None else torch.empty_like(X)
+        check(lib().gmrf_precond_apply(self._h, _dptr(X), _dptr(Y), X.shape[0], _stream_ptr(stream)),
+              "gmrf_precond_apply")
+        return Y
+
+    def sample(self, Z, tol=1e-8, m_max=200, reorth=False, out=None, coeffs=False, stream=None):
+        """X[r] = x_m for z = Z[r] (FP64 CUDA tensors of shape (k, n)).  Returns (X, info) or,
+        with coeffs=True, (X, info, alpha, beta) as numpy arrays."""
+        torch = _torch()
+        self._check_block(Z, torch.float64, "Z")
+        k = Z.shape[0]
+        X = out if out is not None else torch.empty_like(Z)
+        info = (Info * k)()
+        if coeffs:
+            alpha = np.zeros((k, m_max))
+            beta = np.zeros((k, m_max + 1))
+            st = lib().gmrf_sample_ex(self._h, _dptr(Z), k, float(tol), int(m_max), int(bool(reorth)), _dptr(X),
+                                      info, alpha.ctypes.data_as(C.c_void_p), beta.ctypes.data_as(C.c_void_p),
+                                      _stream_ptr(stream))
+        else:
+            st = lib().gmrf_sample(self._h, _dptr(Z), k, float(tol), int(m_max), int(bool(reorth)), _dptr(X), info,
+                                   _stream_ptr(stream))
+        if st not in (_abi.GMRF_OK, _abi.GMRF_ENOTSPD, _abi.GMRF_EINVAL) or (
+                st == _abi.GMRF_EINVAL and not any(i.status == _abi.GMRF_EINVAL for i in info)):
+            raise GmrfError(st, "gmrf_sample")
+        infos = [dict(m_used=i.m_used, status=STATUS[i.status], rel_residual=i.rel_residual,
+                      err_bound=i.err_bound) for i in info]
+        if coeffs:
+            return X, infos, alpha, beta
+        return X, infos
+
+    def logdet(self, n_probes, m, seed=0, probes=None, stream=None):
+        """Hutchinson estimate (mean, standard error, per-probe values as numpy)."""
+        torch = _torch()
+        mean, se = C.c_double(), C.c_double()
+        per = np.zeros(n_probes)
+        pp = C.c_void_p(0)
+        if probes is not None:
+            if probes.dtype != torch.int8 or tuple(probes.shape) != (n_probes, self.n) or not probes.is_contiguous():
+                raise ValueError("probes must be a contiguous int8 CUDA tensor of shape (n_probes, n)")
+            pp = _dptr(probes)
+        check(lib().gmrf_logdet(self._h, int(n_probes), int(m), C.c_uint64(seed & (2 ** 64 - 1)), pp,
+                                C.byref(mean), C.byref(se), per.ctypes.data_as(C.c_void_p), _stream_ptr(stream)),
+              "gmrf_logdet")
+        return mean.value, se.value, per
+
+
+def rademacher(seed, n, n_probes, stream=None):
+    """(n_probes, n) int8 CUDA tensor of +-1 probes from the Philox4x64-10 rule."""
+    torch = _torch()
+    out = torch.empty((n_probes, n), dtype=torch.int8, device="cuda")
+    check(lib().gmrf_rademacher(C.c_uint64(seed & (2 ** 64 - 1)), int(n), int(n_probes), _dptr(out),
+                                _stream_ptr(stream)), "gmrf_rademacher")
+    return out
+
+
+def _tri_args(alpha, beta, m):
+    torch = _torch()
+    for t, nm in ((alpha, "alpha"), (beta, "beta")):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2:
+            raise ValueError(f"{nm} must be a contiguous (k, ld) float64 CUDA tensor")
+    if m.dtype != torch.int32 or not m.is_cuda:
+        raise ValueError("m must be an int32 CUDA tensor")
+    return alpha.shape[0], alpha.shape[1]
+
+
+def tridiag_invsqrt_e1(alpha, beta, m, stream=None):
+    """y[r] = T_r^{-1/2} e_1 for tridiag(beta[r], alpha[r], beta[r]) of size m[r]."""
+    torch = _torch()
+    k, ld = _tri_args(alpha, beta, m)
+    y = torch.zeros_like(alpha)
+    status = torch.zeros(k, dtype=torch.int32, device=alpha.device)
+    check(lib().gmrf_tridiag_invsqrt_e1(_dptr(alpha), _dptr(beta), _dptr(m), k, ld, _dptr(y), _dptr(status),
+                                        _stream_ptr(stream)), "gmrf_tridiag_invsqrt_e1")
+    return y, status
+
+
+def tridiag_log_e1(alpha, beta, m, stream=None):
+    """out[r] = e_1^T log(T_r) e_1."""
+    torch = _torch()
+    k, ld = _tri_args(alpha, beta, m)
+    out = torch.zeros(k, dtype=torch.float64, device=alpha.device)
+    status = torch.zeros(k, dtype=torch.int32, device=alpha.device)
+    check(lib().gmrf_tridiag_log_e1(_dptr(alpha), _dptr(beta), _dptr(m), k, ld, _dptr(out), _dptr(status),
+                                    _stream_ptr(stream)), "gmrf_tridiag_log_e1")
+    return out, status
+
+
+def set_hbm_budget(nbytes):
+    check(lib().gmrf_set_hbm_budget(int(nbytes)), "gmrf_set_hbm_budget")
+
+
+def hbm_in_use():
+    return int(lib().gmrf_hbm_in_use())

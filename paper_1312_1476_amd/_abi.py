@@ -1,0 +1,81 @@
+"""ctypes declarations of the C ABI in include/gmrf.h (argument marshalling only).
+
+The shared library is built in-tree by ``paper_1312_1476_amd.build`` (or
+``__graft_entry__.build()``).  There is no fallback: if libgmrf.so is missing this module
+raises ImportError, and on a machine without a gfx950 GPU every compute entry point
+returns GMRF_EDEVICE.
+"""
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgmrf.so")
+
+GMRF_OK, GMRF_EINVAL, GMRF_ENOTSPD, GMRF_ENOCONV, GMRF_ENOMEM, GMRF_EDEVICE, GMRF_EUNSUPPORTED = range(7)
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOTSPD", 3: "ENOCONV", 4: "ENOMEM", 5: "EDEVICE", 6: "EUNSUPPORTED"}
+GMRF_F64, GMRF_F32 = 0, 1
+GMRF_FREE, GMRF_PERIODIC = 0, 1
+
+
+class Info(C.Structure):
+    _fields_ = [("m_used", C.c_int32), ("status", C.c_int32),
+                ("rel_residual", C.c_double), ("err_bound", C.c_double)]
+
+
+# name -> (restype, argtypes); mirrors include/gmrf.h one to one
+SIGNATURES = {
+    "gmrf_op_create_lattice": (C.c_int, [C.c_int, C.POINTER(C.c_int64), C.c_int, C.c_double, C.c_double,
+                                         C.c_int, C.c_int, C.POINTER(C.c_void_p)]),
+    "gmrf_op_create_csr": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                     C.POINTER(C.c_void_p)]),
+    "gmrf_op_set_circulant_precond": (C.c_int, [C.c_void_p, C.c_int]),
+    "gmrf_op_bytes": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int, C.POINTER(C.c_size_t)]),
+    "gmrf_op_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "gmrf_op_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "gmrf_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "gmrf_op_destroy": (None, [C.c_void_p]),
+    "gmrf_sample": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.c_int,
+                              C.c_void_p, C.POINTER(Info), C.c_void_p]),
+    "gmrf_sample_ex": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.c_int,
+                                 C.c_void_p, C.POINTER(Info), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gmrf_logdet": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p,
+                              C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
+    "gmrf_rademacher": (C.c_int, [C.c_uint64, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p]),
+    "gmrf_tridiag_invsqrt_e1": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                          C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gmrf_tridiag_log_e1": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                      C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gmrf_set_hbm_budget": (C.c_int, [C.c_size_t]),
+    "gmrf_hbm_in_use": (C.c_size_t, []),
+    "gmrf_strerror": (C.c_char_p, [C.c_int]),
+    "gmrf_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libgmrf.so once and attach the prototypes."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1312_1476_amd.build.build()")
+        handle = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+class GmrfError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = lib().gmrf_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+
+
+def check(status, where):
+    if status != GMRF_OK:
+        raise GmrfError(status, where)
+    return status

@@ -1,0 +1,185 @@
+// Shared device-side definitions of the gfx950 Krylov sampler: the Lanczos state, the
+// deterministic reductions and the per-iteration scalar step of Algorithm 1.
+//
+// Vector layout: each right-hand side r owns one contiguous vector of L storage elements
+// (a real lattice field, or a packed 2D half spectrum viewed as 2*N1*(N2/2) reals).  The
+// Krylov basis keeps w_j = beta_j v_{j+1} unnormalised in slot j (slot 0 holds z), so
+// v_{t+1} = V[t] / beta_t is formed on the fly by whichever kernel reads it: the division of
+// Algorithm 1's normalisation step costs no pass over memory.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gmrf {
+
+enum : int { kOK = 0, kEINVAL = 1, kENOTSPD = 2, kENOCONV = 3 };
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kEwThreads = 256;  // elementwise kernels: threads per block
+constexpr int kEwPerThread = 8;  // elements per thread
+constexpr int kEwChunk = kEwThreads * kEwPerThread;  // elements per block
+
+// Per-call Lanczos state, all device memory.  Index conventions (1-based j as in
+// Algorithm 1): alpha[r*(m_max+1) + j] = alpha_j, beta[r*(m_max+2) + j] = beta_j with
+// beta_0 = ||z||, dpiv[r*(m_max+1) + j] = d_j (LDL^T pivot of T_j), rho[..+ j] = rho_j.
+struct LzState {
+  int k;
+  int m_max;
+  double tol;           // <= 0: run exactly m_max steps
+  double* alpha;
+  double* beta;
+  double* dpiv;
+  double* rho;
+  int* m_used;
+  int* status;
+  int* active;
+  double* part_a;       // [k][pstride] partial sums of v_j^T q (op kernels)
+  double* part_b;       // [k][pstride] partial sums of ||w||^2 (elementwise kernels)
+  int Pa;               // number of partials the op kernel writes per RHS
+  int Pb;               // number of partials the elementwise kernels write per RHS
+  int pstride;
+  int weighted;         // 1: packed half-spectrum inner product (column 0 weight 1, else 2)
+  int H;                // packed columns per spectral row (weighted mode)
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+// Sum over the block; every thread receives the same value.  Fixed association order
+// (butterfly inside a wave, then waves in index order), hence bitwise reproducible.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  constexpr int NW = NT / kWave;
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) lds[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) s += lds[i];
+  return s;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double* lds) {
+  constexpr int NW = NT / kWave;
+  v = wave_max(v);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) lds[w] = v;
+  __syncthreads();
+  double s = lds[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) s = fmax(s, lds[i]);
+  return s;
+}
+
+// Sum of P partials in fixed order: thread t adds p[t], p[t+NT], ... then block_sum.
+template <int NT>
+__device__ __forceinline__ double sum_partials(const double* p, int P, double* lds) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < P; i += NT) s += p[i];
+  return block_sum<NT>(s, lds);
+}
+
+__device__ __forceinline__ int lz_ia(const LzState& S, int r, int j) { return r * (S.m_max + 1) + j; }
+__device__ __forceinline__ int lz_ib(const LzState& S, int r, int j) { return r * (S.m_max + 2) + j; }
+
+// Block-uniform read of active[r]: the opener's writer block may clear it while other
+// blocks of the same launch read it, so one thread reads and broadcasts through LDS.
+__device__ __forceinline__ bool block_active(const LzState& S, int r, int* lds_flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) lds_flag[0] = S.active[r];
+  __syncthreads();
+  return lds_flag[0] != 0;
+}
+
+// Scalar step that opens iteration j for RHS r (Algorithm 1 with the Theorem 1 stopping
+// quantity).  Every block working on RHS r calls it with identical inputs and so reaches
+// the same decision; only `writer` stores it.  For j >= 2 it finishes iteration j-1:
+//   beta_{j-1} = ||w_{j-1}|| from the partial sums, d_{j-1} = alpha_{j-1} - beta_{j-2}^2/d_{j-2},
+//   rho_{j-1} = rho_{j-2} beta_{j-1} / d_{j-1}; stop on non-positive alpha or pivot
+//   (not SPD), on breakdown beta_{j-1} <= 64 eps (|alpha_{j-1}| + beta_{j-2}), or on
+//   rho_{j-1} <= tol.  For j = 1 it forms beta_0 = ||z|| (zero z: x = 0 with m = 0;
+//   non-finite z: EINVAL).  With j = m_max + 1 it also closes a run that hit m_max.
+// On continuation it returns s_cur = 1/beta_{j-1} (scale of slot j-1, giving v_j),
+// s_prev = 1/beta_{j-2} (slot j-2, giving v_{j-1}) and bprev = beta_{j-1}.
+template <int NT>
+__device__ bool lz_open(const LzState& S, int r, int j, bool writer, double* lds, int* lds_flag,
+                        double& s_cur, double& s_prev, double& bprev) {
+  if (!block_active(S, r, lds_flag)) return false;
+  const double bsq = sum_partials<NT>(S.part_b + (size_t)r * S.pstride, S.Pb, lds);
+  const double b = sqrt(bsq);
+  if (j == 1) {
+    bool ok = (b > 0.0) && isfinite(b);
+    if (writer) {
+      S.beta[lz_ib(S, r, 0)] = b;
+      S.rho[lz_ia(S, r, 0)] = 1.0;
+      if (!ok) {
+        S.m_used[r] = 0;
+        S.status[r] = (b == 0.0) ? kOK : kEINVAL;
+        S.active[r] = 0;
+      }
+    }
+    s_cur = ok ? 1.0 / b : 0.0;
+    s_prev = 0.0;
+    bprev = 0.0;
+    return ok;
+  }
+  const int jm = j - 1;                        // iteration being closed
+  const double a = S.alpha[lz_ia(S, r, jm)];
+  const double bpp = (jm >= 2) ? S.beta[lz_ib(S, r, jm - 1)] : 0.0;   // beta_{j-2}
+  const double d = (jm == 1) ? a : a - bpp * bpp / S.dpiv[lz_ia(S, r, jm - 1)];
+  const double rh = S.rho[lz_ia(S, r, jm - 1)] * b / d;
+  int st = kOK;
+  bool stop = false;
+  if (!(a > 0.0) || !(d > 0.0) || !isfinite(b)) {
+    st = kENOTSPD;
+    stop = true;
+  } else if (b <= 64.0 * 2.220446049250313e-16 * (fabs(a) + bpp) || (S.tol > 0.0 && rh <= S.tol)) {
+    stop = true;
+  } else if (j > S.m_max) {
+    stop = true;
+    st = (S.tol > 0.0) ? kENOCONV : kOK;
+  }
+  if (writer) {
+    S.beta[lz_ib(S, r, jm)] = b;
+    S.dpiv[lz_ia(S, r, jm)] = d;
+    S.rho[lz_ia(S, r, jm)] = rh;
+    if (stop) {
+      S.m_used[r] = jm;
+      S.status[r] = st;
+      S.active[r] = 0;
+    }
+  }
+  if (stop) return false;
+  s_cur = 1.0 / b;
+  s_prev = 1.0 / S.beta[lz_ib(S, r, jm - 1)];
+  bprev = b;
+  return true;
+}
+
+// Inner-product weight of storage element e (real index) of a vector.
+__device__ __forceinline__ double ip_weight(const LzState& S, long e) {
+  if (!S.weighted) return 1.0;
+  const long c = (e >> 1) % S.H;
+  return c == 0 ? 1.0 : 2.0;
+}
+
+}  // namespace gmrf

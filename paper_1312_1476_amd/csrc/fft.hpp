@@ -1,0 +1,62 @@
+// 2D FFT machinery for the block-circulant preconditioner of Proposition 1 (Section 5.1):
+// M = periodic version of the lattice precision, applied as M^{-1/2} v = F^H lambda_M^{-1/2} F v.
+//
+// Spectral Lanczos.  F is the unitary 2D DFT.  Since A = M^{-1/2} Q M^{-1/2} is real symmetric,
+// running Algorithm 1 on A_hat = F A F^H from z_hat = F z produces the same alpha_j, beta_j and
+// u_m = F^H u_hat_m (inner products are preserved by a unitary map).  With the Krylov vectors
+// held in the spectral basis, each step applies
+//     A_hat v_hat = Lambda^{-1/2} F Q F^H Lambda^{-1/2} v_hat
+// i.e. one inverse and one forward 2D FFT around the stencil: two FFTs per step instead of the
+// four of the real-space formulation (Section 5.1 counts four), and x = F^H Lambda^{-1/2} u_hat_m.
+//
+// Packed half spectrum of a real N1 x N2 field (N2 even): per row, columns c = 1..N2/2-1 hold the
+// row-DFT coefficients, column 0 holds X[0] + i X[N2/2] (both real for a real row); the column
+// FFT then acts on all N2/2 packed columns alike.  Unitary inner products become
+//     <a, b> = sum_{c = 0} Re(conj a b) + 2 sum_{c >= 1} Re(conj a b),
+// and the diagonal multiplier couples k1 with -k1 in column 0 only.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/gmrf.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace gmrf {
+
+struct FftPlan {
+  int N1 = 0, N2 = 0, H = 0;
+  double* tw64_1 = nullptr;   // e^{-2 pi i k / N1}, k < N1 (interleaved re, im)
+  double* tw64_2 = nullptr;   // e^{-2 pi i k / N2}, k < N2
+  float* tw32_1 = nullptr;
+  float* tw32_2 = nullptr;
+};
+
+gmrf_status fft_plan_create(FftPlan& p, int N1, int N2);
+void fft_plan_destroy(FftPlan& p);
+int fft_col_blocks(const FftPlan& p);
+
+// Y = M^{-1/2} X for k real fields (storage T); tmp holds k packed spectra.
+template <typename T>
+void fft_apply_inv_sqrt_M(const FftPlan& p, const T* mult, const T* X, T* Y, T* tmp, int k, hipStream_t st);
+
+// slot 0 <- F z (unitary, packed), partial sums of ||z_hat||^2 (ew tiling) into S.part_b.
+template <typename T>
+void fft_forward_init(const FftPlan& p, const double* Z, T* V0, T* tmp, const LzState& S, int k, hipStream_t st);
+
+// same for Rademacher probes (from seed, or from an int8 block when probes != nullptr).
+template <typename T>
+void fft_forward_init_probes(const FftPlan& p, uint64_t seed, const int8_t* probes, T* real_tmp, T* V0, T* tmp,
+                             const LzState& S, int k, hipStream_t st);
+
+// Opener + operator of iteration j in the spectral basis:
+//   q_hat = Lambda^{-1/2} F Q F^H Lambda^{-1/2} v_hat_j - beta_{j-1} v_hat_{j-1},  alpha partials.
+template <typename T>
+void fft_lanczos_operator(const FftPlan& p, const StencilGeom& g, int order, const void* mult, const T* Xj,
+                          const T* Xprev, T* Qb, T* F1, T* F2, const LzState& S, int j, int k, hipStream_t st);
+
+// X (FP64, real, n x k) = F^H Lambda^{-1/2} U_hat for the combined spectral vectors U_hat.
+template <typename T>
+void fft_backward_output(const FftPlan& p, const void* mult, const T* U, double* X, T* tmp, const LzState& S,
+                         int k, hipStream_t st);
+
+}  // namespace gmrf

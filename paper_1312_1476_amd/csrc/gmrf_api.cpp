@@ -1,0 +1,768 @@
+// Host runtime behind include/gmrf.h: operator handles, the device scratch pool with its
+// HBM budget, and the host-driven Lanczos loop that enqueues the gfx950 kernels.
+//
+// One iteration j of Algorithm 1 is two launches on the caller's stream (plus six for full
+// reorthogonalisation): the operator kernel opens the iteration (scalar step of the previous
+// one, stop decision), applies Q and fuses q -= beta v_{j-1} with the alpha partials; the
+// update kernel forms w_j = q - alpha_j v_j and the ||w_j||^2 partials.  The host only polls
+// the per-column `active` flags every few iterations, so the GPU never idles on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gmrf.h"
+#include "fft.hpp"
+#include "kernels.hpp"
+
+using namespace gmrf;
+
+// ---- errors ----------------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static gmrf_status fail(gmrf_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(GMRF_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---- device check --------------------------------------------------------------------------------
+static gmrf_status check_device() {
+  int dev = 0, count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+    return fail(GMRF_EDEVICE, "no HIP device available");
+  if (hipGetDevice(&dev) != hipSuccess) return fail(GMRF_EDEVICE, "hipGetDevice failed");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(GMRF_EDEVICE, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(GMRF_EDEVICE, "device %d is %s; this library is built for gfx950 only", dev, prop.gcnArchName);
+  return GMRF_OK;
+}
+
+// ---- scratch pool ---------------------------------------------------------------------------------
+namespace {
+struct Pool {
+  std::mutex mu;
+  std::multimap<size_t, void*> free_blocks;
+  size_t in_use = 0;
+  size_t budget = 0;
+
+  gmrf_status get(size_t bytes, void** out, size_t* actual) {
+    bytes = rounded(bytes);
+    std::lock_guard<std::mutex> lk(mu);
+    if (budget && in_use + bytes > budget)
+      return fail(GMRF_ENOMEM, "HBM budget %zu B exceeded (in use %zu B, request %zu B)", budget, in_use, bytes);
+    auto it = free_blocks.lower_bound(bytes);
+    if (it != free_blocks.end() && it->first <= bytes + bytes / 4) {
+      *out = it->second;
+      *actual = it->first;
+      in_use += it->first;
+      free_blocks.erase(it);
+      return GMRF_OK;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      for (auto& kv : free_blocks) (void)hipFree(kv.second);
+      free_blocks.clear();
+      if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(GMRF_ENOMEM, "hipMalloc of %zu B failed", bytes);
+      }
+    }
+    *out = p;
+    *actual = bytes;
+    in_use += bytes;
+    return GMRF_OK;
+  }
+  static size_t rounded(size_t bytes) { return (bytes + (2u << 20) - 1) & ~((size_t)(2u << 20) - 1); }
+  // `bytes` is the size the block was handed out with (its cached size)
+  void put(void* p, size_t bytes) {
+    std::lock_guard<std::mutex> lk(mu);
+    free_blocks.emplace(bytes, p);
+    in_use -= std::min(in_use, bytes);
+  }
+};
+Pool& pool() {
+  static Pool* p = new Pool();
+  return *p;
+}
+
+// Scratch of one call; returned to the pool (after the stream has drained) on destruction.
+struct Workspace {
+  hipStream_t stream;
+  std::vector<std::pair<void*, size_t>> blocks;
+  explicit Workspace(hipStream_t s) : stream(s) {}
+  ~Workspace() {
+    if (!blocks.empty()) (void)hipStreamSynchronize(stream);
+    for (auto& b : blocks) pool().put(b.first, b.second);
+  }
+  template <typename T>
+  gmrf_status alloc(size_t count, T** out) {
+    void* p = nullptr;
+    size_t actual = 0;
+    gmrf_status s = pool().get(std::max<size_t>(count * sizeof(T), 256), &p, &actual);
+    if (s != GMRF_OK) return s;
+    blocks.emplace_back(p, actual);
+    *out = static_cast<T*>(p);
+    return GMRF_OK;
+  }
+};
+}  // namespace
+
+// ---- operator handle -------------------------------------------------------------------------------
+struct gmrf_op {
+  int kind = 0;           // 0 lattice, 1 csr
+  int ndim = 0;
+  int64_t shape[3] = {1, 1, 1};
+  int order = 1;
+  double kappa2 = 0.0, tau = 1.0;
+  int bc = GMRF_FREE;
+  int storage = GMRF_F64;
+  int64_t n = 0;
+  StencilGeom geom{};
+  int dim = 1;
+  // CSR (device)
+  int64_t* rp = nullptr;
+  int32_t* ci = nullptr;
+  void* va = nullptr;
+  int64_t nnz = 0;
+  // circulant preconditioner
+  int precond = 0;
+  FftPlan plan{};
+  double logdet_M = 0.0;
+  double* mult64 = nullptr;  // lambda_M^{-1/2} tables (device)
+  float* mult32 = nullptr;
+  size_t resident_bytes = 0;
+};
+
+extern "C" {
+
+const char* gmrf_last_error(void) { return g_last_error.c_str(); }
+
+const char* gmrf_strerror(gmrf_status s) {
+  switch (s) {
+    case GMRF_OK: return "ok";
+    case GMRF_EINVAL: return "invalid argument";
+    case GMRF_ENOTSPD: return "operator is not symmetric positive definite";
+    case GMRF_ENOCONV: return "tolerance not reached within m_max steps";
+    case GMRF_ENOMEM: return "out of device memory or over the HBM budget";
+    case GMRF_EDEVICE: return "no usable gfx950 device or HIP runtime error";
+    case GMRF_EUNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+gmrf_status gmrf_set_hbm_budget(size_t bytes) {
+  std::lock_guard<std::mutex> lk(pool().mu);
+  pool().budget = bytes;
+  return GMRF_OK;
+}
+
+size_t gmrf_hbm_in_use(void) {
+  std::lock_guard<std::mutex> lk(pool().mu);
+  return pool().in_use;
+}
+
+gmrf_status gmrf_op_create_lattice(int ndim, const int64_t* shape, int order, double kappa2, double tau,
+                                   gmrf_boundary bc, gmrf_dtype storage, gmrf_op** out) {
+  if (!out) return fail(GMRF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (ndim < 1 || ndim > 3 || !shape) return fail(GMRF_EINVAL, "ndim must be 1..3");
+  if (order != 1 && order != 2) return fail(GMRF_EINVAL, "order must be 1 or 2");
+  if (!(tau > 0.0) || !std::isfinite(tau) || !std::isfinite(kappa2))
+    return fail(GMRF_EINVAL, "tau must be > 0 and finite, kappa2 finite");
+  if (bc != GMRF_FREE && bc != GMRF_PERIODIC) return fail(GMRF_EINVAL, "bad boundary");
+  if (storage != GMRF_F64 && storage != GMRF_F32) return fail(GMRF_EINVAL, "bad storage dtype");
+  int64_t n = 1;
+  for (int d = 0; d < ndim; ++d) {
+    if (shape[d] < 1 || shape[d] > (1 << 24)) return fail(GMRF_EINVAL, "shape[%d] out of range", d);
+    n *= shape[d];
+  }
+  if (n > ((int64_t)1 << 31)) return fail(GMRF_EINVAL, "lattice too large (n > 2^31)");
+  gmrf_status ds = check_device();
+  if (ds != GMRF_OK) return ds;
+  auto op = new gmrf_op();
+  op->kind = 0;
+  op->ndim = ndim;
+  for (int d = 0; d < 3; ++d) op->shape[d] = 1;
+  for (int d = 0; d < ndim; ++d) op->shape[3 - ndim + d] = shape[d];
+  op->order = order;
+  op->kappa2 = kappa2;
+  op->tau = tau;
+  op->bc = bc;
+  op->storage = storage;
+  op->n = n;
+  op->dim = ndim;
+  op->geom.n0 = (int)op->shape[0];
+  op->geom.n1 = (int)op->shape[1];
+  op->geom.n2 = (int)op->shape[2];
+  op->geom.periodic = bc == GMRF_PERIODIC;
+  op->geom.kappa2 = kappa2;
+  op->geom.tau = tau;
+  stencil_geom_tiles(op->geom, ndim);
+  *out = op;
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_op_create_csr(int64_t n, const int64_t* row_ptr, const int32_t* col_idx,
+                               const double* values, gmrf_dtype storage, gmrf_op** out) {
+  if (!out) return fail(GMRF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || n > ((int64_t)1 << 31) || !row_ptr || !col_idx || !values)
+    return fail(GMRF_EINVAL, "bad CSR arguments");
+  if (storage != GMRF_F64 && storage != GMRF_F32) return fail(GMRF_EINVAL, "bad storage dtype");
+  if (row_ptr[0] != 0) return fail(GMRF_EINVAL, "row_ptr[0] must be 0");
+  for (int64_t i = 0; i < n; ++i)
+    if (row_ptr[i + 1] < row_ptr[i]) return fail(GMRF_EINVAL, "row_ptr not non-decreasing at %lld", (long long)i);
+  const int64_t nnz = row_ptr[n];
+  for (int64_t e = 0; e < nnz; ++e)
+    if (col_idx[e] < 0 || col_idx[e] >= n) return fail(GMRF_EINVAL, "column index out of range at %lld", (long long)e);
+  for (int64_t e = 0; e < nnz; ++e)
+    if (!std::isfinite(values[e])) return fail(GMRF_EINVAL, "non-finite value at %lld", (long long)e);
+  gmrf_status ds = check_device();
+  if (ds != GMRF_OK) return ds;
+  auto op = std::make_unique<gmrf_op>();
+  op->kind = 1;
+  op->n = n;
+  op->nnz = nnz;
+  op->storage = storage;
+  op->shape[2] = n;
+  const size_t vb = storage == GMRF_F64 ? 8 : 4;
+  HIP_TRY(hipMalloc(&op->rp, (n + 1) * sizeof(int64_t)));
+  HIP_TRY(hipMalloc(&op->ci, std::max<int64_t>(nnz, 1) * sizeof(int32_t)));
+  HIP_TRY(hipMalloc(&op->va, std::max<int64_t>(nnz, 1) * vb));
+  HIP_TRY(hipMemcpy(op->rp, row_ptr, (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  if (nnz) HIP_TRY(hipMemcpy(op->ci, col_idx, nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (nnz) {
+    if (storage == GMRF_F64) {
+      HIP_TRY(hipMemcpy(op->va, values, nnz * 8, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> tmp(values, values + nnz);
+      HIP_TRY(hipMemcpy(op->va, tmp.data(), nnz * 4, hipMemcpyHostToDevice));
+    }
+  }
+  op->resident_bytes = (n + 1) * 8 + nnz * (4 + vb);
+  *out = op.release();
+  return GMRF_OK;
+}
+
+void gmrf_op_destroy(gmrf_op* Q) {
+  if (!Q) return;
+  if (Q->rp) (void)hipFree(Q->rp);
+  if (Q->ci) (void)hipFree(Q->ci);
+  if (Q->va) (void)hipFree(Q->va);
+  if (Q->mult64) (void)hipFree(Q->mult64);
+  if (Q->mult32) (void)hipFree(Q->mult32);
+  fft_plan_destroy(Q->plan);
+  delete Q;
+}
+
+gmrf_status gmrf_op_size(const gmrf_op* Q, int64_t* n) {
+  if (!Q || !n) return fail(GMRF_EINVAL, "NULL argument");
+  *n = Q->n;
+  return GMRF_OK;
+}
+
+}  // extern "C"
+
+// ---- circulant preconditioner: lambda_M^{-1/2} table on the packed spectrum ----------------------
+// M = periodic version of the lattice precision; lambda_M(k1, k2) = tau (kappa2 + mu1 + mu2)^order
+// with mu = 4 sin^2(pi k / N) (cycle spectra).  The table stores lambda^{-1/2} for every packed
+// coefficient: [k1][c] for c = 1..N2/2-1 and, in column 0, the pair (k2 = 0, k2 = N2/2).
+static gmrf_status build_precond(gmrf_op* Q) {
+  const int N1 = (int)Q->shape[1], N2 = (int)Q->shape[2];
+  const int H = N2 / 2;
+  std::vector<double> mu1(N1), mu2(N2);
+  for (int k = 0; k < N1; ++k) {
+    const double s = std::sin(M_PI * (double)k / N1);
+    mu1[k] = 4.0 * s * s;
+  }
+  for (int k = 0; k < N2; ++k) {
+    const double s = std::sin(M_PI * (double)k / N2);
+    mu2[k] = 4.0 * s * s;
+  }
+  auto lam = [&](int k1, int k2) {
+    const double b = Q->kappa2 + mu1[k1] + mu2[k2];
+    return Q->order == 1 ? Q->tau * b : Q->tau * b * b;
+  };
+  // table layout: [k1][H + 1]: entries 0..H-1 for columns (col 0 -> k2 = 0), entry H -> k2 = N2/2
+  std::vector<double> t((size_t)N1 * (H + 1));
+  double ld = 0.0;
+  for (int k1 = 0; k1 < N1; ++k1) {
+    for (int c = 0; c < H; ++c) t[(size_t)k1 * (H + 1) + c] = 1.0 / std::sqrt(lam(k1, c));
+    t[(size_t)k1 * (H + 1) + H] = 1.0 / std::sqrt(lam(k1, H));
+    for (int k2 = 0; k2 < N2; ++k2) {
+      const double l = lam(k1, k2);
+      if (!(l > 0.0)) return fail(GMRF_ENOTSPD, "periodic preconditioner is singular (kappa2 <= 0)");
+      ld += std::log(l);
+    }
+  }
+  Q->logdet_M = ld;
+  HIP_TRY(hipMalloc(&Q->mult64, t.size() * sizeof(double)));
+  HIP_TRY(hipMemcpy(Q->mult64, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+  std::vector<float> t32(t.begin(), t.end());
+  HIP_TRY(hipMalloc(&Q->mult32, t32.size() * sizeof(float)));
+  HIP_TRY(hipMemcpy(Q->mult32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice));
+  Q->resident_bytes += t.size() * 12;
+  return GMRF_OK;
+}
+
+static bool pow2_in(int64_t v, int64_t lo, int64_t hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+extern "C" gmrf_status gmrf_op_set_circulant_precond(gmrf_op* Q, int enable) {
+  if (!Q) return fail(GMRF_EINVAL, "NULL operator");
+  if (!enable) {
+    Q->precond = 0;
+    return GMRF_OK;
+  }
+  if (Q->kind != 0 || Q->ndim != 2)
+    return fail(GMRF_EUNSUPPORTED, "circulant preconditioning needs a 2D lattice operator");
+  if (!pow2_in(Q->shape[1], 8, 4096) || !pow2_in(Q->shape[2], 8, 4096))
+    return fail(GMRF_EUNSUPPORTED, "circulant preconditioning needs power-of-two sides in [8, 4096]");
+  if (!Q->mult64) {
+    gmrf_status s = build_precond(Q);
+    if (s != GMRF_OK) return s;
+    s = fft_plan_create(Q->plan, (int)Q->shape[1], (int)Q->shape[2]);
+    if (s != GMRF_OK) return fail(s, "FFT plan creation failed");
+  }
+  Q->precond = 1;
+  return GMRF_OK;
+}
+
+// ---- sizes ------------------------------------------------------------------------------------------
+namespace {
+struct Sizes {
+  long L;          // storage elements per vector
+  int slots;       // Krylov slots kept
+  int Pa, Pb, pstride;
+  size_t vec_bytes;
+};
+
+Sizes sizes_for(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3) {
+  Sizes z{};
+  z.L = (long)Q->n;  // packed half spectrum has exactly n reals too
+  z.slots = ring3 ? 3 : m_max + 1;
+  if (Q->precond) z.Pa = fft_col_blocks(Q->plan);
+  else z.Pa = Q->kind == 0 ? stencil_blocks(Q->geom) : csr_blocks((long)Q->n);
+  z.Pb = ew_blocks(z.L);
+  z.pstride = std::max(z.Pa, z.Pb);
+  z.vec_bytes = (size_t)z.L * (Q->storage == GMRF_F64 ? 8 : 4);
+  (void)k;
+  (void)reorth;
+  return z;
+}
+
+size_t call_bytes(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3) {
+  Sizes z = sizes_for(Q, k, m_max, reorth, ring3);
+  size_t b = (size_t)z.slots * k * z.vec_bytes;       // Krylov basis
+  b += (size_t)k * z.vec_bytes;                       // q
+  if (Q->precond) b += 2 * (size_t)k * z.vec_bytes;   // FFT intermediates
+  b += (size_t)k * (m_max + 2) * 8 * 4 + (size_t)k * 16;  // scalars
+  b += 2 * (size_t)k * z.pstride * 8;                 // partials
+  if (reorth) b += (size_t)k * (m_max + 1) * (z.Pb + 1) * 8;
+  if (!ring3) b += (size_t)k * m_max * 8 + tri_scratch_doubles((int)k, m_max) * 8;
+  return b;
+}
+}  // namespace
+
+extern "C" gmrf_status gmrf_op_bytes(const gmrf_op* Q, int64_t k, int32_t m_max, int reorth, size_t* bytes) {
+  if (!Q || !bytes || k < 1 || m_max < 1) return fail(GMRF_EINVAL, "bad arguments");
+  *bytes = call_bytes(Q, k, m_max, reorth, false) + Q->resident_bytes;
+  return GMRF_OK;
+}
+
+// ---- operator application --------------------------------------------------------------------------
+template <typename T>
+static void op_apply_lz(const gmrf_op* Q, const T* X, T* Y, const T* Xprev, const LzState& S, int j, int k,
+                        hipStream_t st) {
+  if (Q->kind == 0)
+    launch_stencil<T>(Q->geom, Q->order, Q->dim, true, X, Q->n, Y, Q->n, Xprev, S, j, k, st);
+  else
+    launch_csr<T>((long)Q->n, Q->rp, Q->ci, (const T*)Q->va, true, X, Q->n, Y, Q->n, Xprev, S, j, k, st);
+}
+
+template <typename T>
+static void op_apply_plain(const gmrf_op* Q, const T* X, T* Y, int k, hipStream_t st) {
+  LzState S{};
+  if (Q->kind == 0)
+    launch_stencil<T>(Q->geom, Q->order, Q->dim, false, X, Q->n, Y, Q->n, nullptr, S, 0, k, st);
+  else
+    launch_csr<T>((long)Q->n, Q->rp, Q->ci, (const T*)Q->va, false, X, Q->n, Y, Q->n, nullptr, S, 0, k, st);
+}
+
+extern "C" gmrf_status gmrf_op_apply(const gmrf_op* Q, const void* X, void* Y, int64_t k, void* stream) {
+  if (!Q || !X || !Y || k < 1 || k > 65535) return fail(GMRF_EINVAL, "bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  if (Q->storage == GMRF_F64) op_apply_plain<double>(Q, (const double*)X, (double*)Y, (int)k, st);
+  else op_apply_plain<float>(Q, (const float*)X, (float*)Y, (int)k, st);
+  HIP_TRY(hipGetLastError());
+  return GMRF_OK;
+}
+
+extern "C" gmrf_status gmrf_precond_apply(const gmrf_op* Q, const void* X, void* Y, int64_t k, void* stream) {
+  if (!Q || !X || !Y || k < 1 || k > 65535) return fail(GMRF_EINVAL, "bad arguments");
+  if (!Q->precond) return fail(GMRF_EINVAL, "circulant preconditioning is not enabled on this operator");
+  hipStream_t st = (hipStream_t)stream;
+  Workspace ws(st);
+  gmrf_status s;
+  if (Q->storage == GMRF_F64) {
+    double* tmp;
+    if ((s = ws.alloc(Q->n * k, &tmp)) != GMRF_OK) return s;
+    fft_apply_inv_sqrt_M<double>(Q->plan, Q->mult64, (const double*)X, (double*)Y, tmp, (int)k, st);
+  } else {
+    float* tmp;
+    if ((s = ws.alloc(Q->n * k, &tmp)) != GMRF_OK) return s;
+    fft_apply_inv_sqrt_M<float>(Q->plan, Q->mult32, (const float*)X, (float*)Y, tmp, (int)k, st);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return GMRF_OK;
+}
+
+// ---- the Lanczos driver --------------------------------------------------------------------------------
+namespace {
+
+struct Scalars {
+  double *alpha, *beta, *dpiv, *rho;
+  int *m_used, *status, *active;
+  double *part_a, *part_b;
+};
+
+template <typename T>
+struct Run {
+  const gmrf_op* Q;
+  int k, m_max, reorth;
+  double tol;
+  hipStream_t st;
+  Sizes z;
+  LzState S{};
+  T* V = nullptr;        // slots x k x L
+  T* Qb = nullptr;       // k x L
+  T* F1 = nullptr;       // FFT intermediates (preconditioned)
+  T* F2 = nullptr;
+  double* part_h = nullptr;
+  double* h = nullptr;
+  bool ring3 = false;
+
+  T* slot(int t) const {
+    const int s = ring3 ? (t % 3) : t;
+    return V + (size_t)s * k * z.L;
+  }
+};
+
+template <typename T>
+gmrf_status setup(Run<T>& R, Workspace& ws) {
+  const gmrf_op* Q = R.Q;
+  R.z = sizes_for(Q, R.k, R.m_max, R.reorth, R.ring3);
+  const int k = R.k, m = R.m_max;
+  gmrf_status s;
+  if ((s = ws.alloc((size_t)R.z.slots * k * R.z.L, &R.V)) != GMRF_OK) return s;
+  if ((s = ws.alloc((size_t)k * R.z.L, &R.Qb)) != GMRF_OK) return s;
+  if (Q->precond) {
+    if ((s = ws.alloc((size_t)k * R.z.L, &R.F1)) != GMRF_OK) return s;
+    if ((s = ws.alloc((size_t)k * R.z.L, &R.F2)) != GMRF_OK) return s;
+  }
+  double* dbuf;
+  const size_t nd = (size_t)k * (m + 1) * 3 + (size_t)k * (m + 2) + 2 * (size_t)k * R.z.pstride;
+  if ((s = ws.alloc(nd, &dbuf)) != GMRF_OK) return s;
+  int* ibuf;
+  if ((s = ws.alloc((size_t)3 * k, &ibuf)) != GMRF_OK) return s;
+  LzState& S = R.S;
+  S.k = k;
+  S.m_max = m;
+  S.tol = R.tol;
+  S.alpha = dbuf;
+  S.dpiv = S.alpha + (size_t)k * (m + 1);
+  S.rho = S.dpiv + (size_t)k * (m + 1);
+  S.beta = S.rho + (size_t)k * (m + 1);
+  S.part_a = S.beta + (size_t)k * (m + 2);
+  S.part_b = S.part_a + (size_t)k * R.z.pstride;
+  S.m_used = ibuf;
+  S.status = ibuf + k;
+  S.active = ibuf + 2 * k;
+  S.Pa = R.z.Pa;
+  S.Pb = R.z.Pb;
+  S.pstride = R.z.pstride;
+  S.weighted = Q->precond ? 1 : 0;
+  S.H = Q->precond ? (int)(Q->shape[2] / 2) : 1;
+  HIP_TRY(hipMemsetAsync(dbuf, 0, nd * sizeof(double), R.st));
+  HIP_TRY(hipMemsetAsync(ibuf, 0, 2 * k * sizeof(int), R.st));
+  HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)S.active, 1, k, R.st));
+  if (R.reorth) {
+    if ((s = ws.alloc((size_t)k * (m + 1) * R.z.Pb, &R.part_h)) != GMRF_OK) return s;
+    if ((s = ws.alloc((size_t)k * (m + 1), &R.h)) != GMRF_OK) return s;
+  }
+  return GMRF_OK;
+}
+
+// pinned polling buffer per host thread
+int* poll_buffer(int k) {
+  static thread_local int* buf = nullptr;
+  static thread_local int cap = 0;
+  if (cap < k) {
+    if (buf) (void)hipHostFree(buf);
+    buf = nullptr;
+    if (hipHostMalloc((void**)&buf, (size_t)std::max(k, 64) * sizeof(int), hipHostMallocDefault) != hipSuccess)
+      return nullptr;
+    cap = std::max(k, 64);
+  }
+  return buf;
+}
+
+// One iteration j: operator (opener) + update (+ reorth).
+template <typename T>
+void iterate(Run<T>& R, int j) {
+  const gmrf_op* Q = R.Q;
+  T* xj = R.slot(j - 1);
+  T* xp = j >= 2 ? R.slot(j - 2) : R.slot(0);
+  if (Q->precond) {
+    fft_lanczos_operator<T>(Q->plan, Q->geom, Q->order, Q->storage == GMRF_F64 ? (const void*)Q->mult64 : (const void*)Q->mult32,
+                            xj, xp, R.Qb, R.F1, R.F2, R.S, j, R.k, R.st);
+  } else {
+    op_apply_lz<T>(Q, xj, R.Qb, xp, R.S, j, R.k, R.st);
+  }
+  launch_update<T>(R.Qb, xj, R.slot(j), R.z.L, j, R.reorth ? 0 : 1, R.S, R.st);
+  if (R.reorth) launch_reorth<T>(R.V, R.z.L, j, R.part_h, R.h, R.m_max + 1, R.S, R.st);
+}
+
+// Runs iterations until every column stopped or m_max; returns the last j launched.
+template <typename T>
+gmrf_status run_loop(Run<T>& R) {
+  int* pb = poll_buffer(R.k);
+  if (!pb) return fail(GMRF_ENOMEM, "pinned host buffer allocation failed");
+  int poll = 8;
+  for (int j = 1; j <= R.m_max; ++j) {
+    iterate<T>(R, j);
+    if (j % poll == 0 && j < R.m_max) {
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(pb, R.S.active, R.k * sizeof(int), hipMemcpyDeviceToHost, R.st));
+      HIP_TRY(hipStreamSynchronize(R.st));
+      bool any = false;
+      for (int r = 0; r < R.k; ++r) any |= pb[r] != 0;
+      if (!any) break;
+      poll = std::min(poll * 2, 32);
+    }
+  }
+  launch_finalize(R.S, R.st);
+  HIP_TRY(hipGetLastError());
+  return GMRF_OK;
+}
+
+}  // namespace
+
+template <typename T>
+static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, double tol, int m_max, int reorth,
+                               double* X, gmrf_info* info, double* alpha_out, double* beta_out,
+                               hipStream_t st) {
+  Workspace ws(st);
+  Run<T> R;
+  R.Q = Q;
+  R.k = (int)k;
+  R.m_max = m_max;
+  R.reorth = reorth;
+  R.tol = tol;
+  R.st = st;
+  gmrf_status s = setup<T>(R, ws);
+  if (s != GMRF_OK) return s;
+  // slot 0 <- z (preconditioned: z in the unitary spectral basis)
+  if (Q->precond) fft_forward_init<T>(Q->plan, Z, R.slot(0), R.F1, R.S, (int)k, st);
+  else launch_init_from_f64<T>(Z, Q->n, R.z.L, R.slot(0), R.S, st);
+  if ((s = run_loop<T>(R)) != GMRF_OK) return s;
+  // y = T_m^{-1/2} e_1, then x_m = ||z|| V_m y
+  double *y, *scr;
+  if ((s = ws.alloc((size_t)k * m_max, &y)) != GMRF_OK) return s;
+  if ((s = ws.alloc(tri_scratch_doubles((int)k, m_max), &scr)) != GMRF_OK) return s;
+  launch_tri_invsqrt(R.S.alpha, m_max + 1, 1, R.S.beta, m_max + 2, 1, R.S.m_used, 0, R.S.status, y, m_max,
+                     R.S.status, scr, m_max, (int)k, st);
+  if (Q->precond) {
+    launch_combine<T, T>(R.V, R.z.L, y, m_max, R.Qb, R.z.L, R.S, st);
+    fft_backward_output<T>(Q->plan, Q->storage == GMRF_F64 ? (const void*)Q->mult64 : (const void*)Q->mult32,
+                           R.Qb, X, R.F1, R.S, (int)k, st);
+  } else {
+    launch_combine<T, double>(R.V, R.z.L, y, m_max, X, Q->n, R.S, st);
+  }
+  HIP_TRY(hipGetLastError());
+  // results to host
+  std::vector<int> mu(k), stt(k);
+  std::vector<double> rho((size_t)k * (m_max + 1)), beta((size_t)k * (m_max + 2)), alpha;
+  HIP_TRY(hipMemcpyAsync(mu.data(), R.S.m_used, k * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(stt.data(), R.S.status, k * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(rho.data(), R.S.rho, rho.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(beta.data(), R.S.beta, beta.size() * 8, hipMemcpyDeviceToHost, st));
+  if (alpha_out) {
+    alpha.resize((size_t)k * (m_max + 1));
+    HIP_TRY(hipMemcpyAsync(alpha.data(), R.S.alpha, alpha.size() * 8, hipMemcpyDeviceToHost, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  double lam_lb = NAN;
+  if (Q->kind == 0 && !Q->precond && Q->kappa2 > 0.0)
+    lam_lb = Q->order == 1 ? Q->tau * Q->kappa2 : Q->tau * Q->kappa2 * Q->kappa2;
+  gmrf_status ret = GMRF_OK;
+  for (int r = 0; r < k; ++r) {
+    const int m = mu[r];
+    const double rr = rho[(size_t)r * (m_max + 1) + std::max(m, 0)];
+    if (info) {
+      info[r].m_used = m;
+      info[r].status = stt[r];
+      info[r].rel_residual = m > 0 ? rr : 0.0;
+      info[r].err_bound = (m > 0 && std::isfinite(lam_lb)) ? rr / std::sqrt(lam_lb) : NAN;
+    }
+    if (stt[r] == kENOTSPD) ret = GMRF_ENOTSPD;
+    if (stt[r] == kEINVAL && ret == GMRF_OK) ret = GMRF_EINVAL;
+    if (alpha_out)
+      for (int j = 1; j <= m_max; ++j)
+        alpha_out[(size_t)r * m_max + j - 1] = j <= m ? alpha[(size_t)r * (m_max + 1) + j] : 0.0;
+    if (beta_out)
+      for (int j = 0; j <= m_max; ++j)
+        beta_out[(size_t)r * (m_max + 1) + j] = j <= m ? beta[(size_t)r * (m_max + 2) + j] : 0.0;
+  }
+  if (ret == GMRF_ENOTSPD) fail(ret, "at least one column is not positive definite (see info)");
+  if (ret == GMRF_EINVAL) fail(ret, "at least one column of Z is not finite (see info)");
+  return ret;
+}
+
+extern "C" gmrf_status gmrf_sample_ex(const gmrf_op* Q, const double* Z, int64_t k, double tol, int32_t m_max,
+                                      int reorth, double* X, gmrf_info* info, double* alpha, double* beta,
+                                      void* stream) {
+  if (!Q || !Z || !X) return fail(GMRF_EINVAL, "NULL argument");
+  if (k < 1 || k > 65535) return fail(GMRF_EINVAL, "k must be in 1..65535");
+  if (m_max < 1 || m_max > tri_max_m()) return fail(GMRF_EINVAL, "m_max must be in 1..%d", tri_max_m());
+  if (!std::isfinite(tol)) return fail(GMRF_EINVAL, "tol must be finite");
+  if (reorth != 0 && reorth != 1) return fail(GMRF_EINVAL, "reorth must be 0 or 1");
+  hipStream_t st = (hipStream_t)stream;
+  if (Q->storage == GMRF_F64) return sample_impl<double>(Q, Z, k, tol, m_max, reorth, X, info, alpha, beta, st);
+  return sample_impl<float>(Q, Z, k, tol, m_max, reorth, X, info, alpha, beta, st);
+}
+
+extern "C" gmrf_status gmrf_sample(const gmrf_op* Q, const double* Z, int64_t k, double tol, int32_t m_max,
+                                   int reorth, double* X, gmrf_info* info, void* stream) {
+  return gmrf_sample_ex(Q, Z, k, tol, m_max, reorth, X, info, nullptr, nullptr, stream);
+}
+
+// ---- log-determinant ------------------------------------------------------------------------------------
+template <typename T>
+static gmrf_status logdet_impl(const gmrf_op* Q, int np, int m, uint64_t seed, const int8_t* probes,
+                               double* logdet, double* std_err, double* per_probe, hipStream_t st) {
+  Workspace ws(st);
+  Run<T> R;
+  R.Q = Q;
+  R.k = np;
+  R.m_max = m;
+  R.reorth = 0;
+  R.tol = 0.0;
+  R.st = st;
+  R.ring3 = true;
+  gmrf_status s = setup<T>(R, ws);
+  if (s != GMRF_OK) return s;
+  if (Q->precond) {
+    // probes in real space, then into the spectral basis
+    T* pr;
+    if ((s = ws.alloc((size_t)np * Q->n, &pr)) != GMRF_OK) return s;
+    fft_forward_init_probes<T>(Q->plan, seed, probes, pr, R.slot(0), R.F1, R.S, np, st);
+  } else if (probes) {
+    launch_init_from_i8<T>(probes, R.z.L, R.slot(0), R.S, st);
+  } else {
+    LzState S2 = R.S;
+    S2.Pb = rademacher_blocks(R.z.L);
+    launch_init_rademacher<T>(seed, R.z.L, R.slot(0), S2, st);
+    R.S.Pb = S2.Pb;  // opener of iteration 1 reduces the probe partials
+  }
+  // the opener of iteration 1 reads Pb partials written by the init kernel; from then on
+  // the elementwise kernels write ew_blocks(L) partials
+  {
+    const int pb_init = R.S.Pb;
+    // iteration 1 with the init partial count, the rest with the elementwise count
+    int* pb = poll_buffer(np);
+    if (!pb) return fail(GMRF_ENOMEM, "pinned host buffer allocation failed");
+    for (int j = 1; j <= m; ++j) {
+      R.S.Pb = (j == 1) ? pb_init : R.z.Pb;
+      iterate<T>(R, j);
+    }
+    R.S.Pb = R.z.Pb;
+    launch_finalize(R.S, st);
+  }
+  double* g;
+  if ((s = ws.alloc((size_t)np * 4, &g)) != GMRF_OK) return s;
+  launch_tri_log(R.S.alpha, m + 1, 1, R.S.beta, m + 2, 1, R.S.m_used, 0, R.S.status, g, 1, R.S.status, np, st);
+  double* agg = g + np;
+  launch_hutchinson_aggregate(g, R.S.beta, m + 2, np, Q->precond ? Q->logdet_M : 0.0, agg, st);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> gam(np), out(2);
+  std::vector<int> stt(np);
+  HIP_TRY(hipMemcpyAsync(gam.data(), agg + 2, np * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(out.data(), agg, 16, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(stt.data(), R.S.status, np * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int p = 0; p < np; ++p)
+    if (stt[p] == kENOTSPD) return fail(GMRF_ENOTSPD, "probe %d: operator is not positive definite", p);
+  if (logdet) *logdet = out[0];
+  if (std_err) *std_err = out[1];
+  if (per_probe) std::memcpy(per_probe, gam.data(), np * sizeof(double));
+  return GMRF_OK;
+}
+
+extern "C" gmrf_status gmrf_logdet(const gmrf_op* Q, int32_t n_probes, int32_t m, uint64_t seed,
+                                   const int8_t* probes, double* logdet, double* std_err, double* per_probe,
+                                   void* stream) {
+  if (!Q) return fail(GMRF_EINVAL, "NULL operator");
+  if (n_probes < 1 || n_probes > 65535) return fail(GMRF_EINVAL, "n_probes must be in 1..65535");
+  if (m < 1 || m > tri_max_m()) return fail(GMRF_EINVAL, "m must be in 1..%d", tri_max_m());
+  hipStream_t st = (hipStream_t)stream;
+  if (Q->storage == GMRF_F64) return logdet_impl<double>(Q, n_probes, m, seed, probes, logdet, std_err, per_probe, st);
+  return logdet_impl<float>(Q, n_probes, m, seed, probes, logdet, std_err, per_probe, st);
+}
+
+extern "C" gmrf_status gmrf_rademacher(uint64_t seed, int64_t n, int32_t n_probes, int8_t* out, void* stream) {
+  if (n < 1 || n_probes < 1 || n_probes > 65535 || !out) return fail(GMRF_EINVAL, "bad arguments");
+  gmrf_status ds = check_device();
+  if (ds != GMRF_OK) return ds;
+  launch_rademacher_i8(seed, (long)n, n_probes, out, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return GMRF_OK;
+}
+
+extern "C" gmrf_status gmrf_tridiag_invsqrt_e1(const double* alpha, const double* beta, const int32_t* m,
+                                               int32_t k, int32_t ld, double* y, int32_t* status,
+                                               void* stream) {
+  if (!alpha || !beta || !m || !y || k < 1 || k > 65535 || ld < 1 || ld > tri_max_m())
+    return fail(GMRF_EINVAL, "bad arguments (ld must be <= %d)", tri_max_m());
+  hipStream_t st = (hipStream_t)stream;
+  Workspace ws(st);
+  double* scr;
+  gmrf_status s = ws.alloc(tri_scratch_doubles(k, ld), &scr);
+  if (s != GMRF_OK) return s;
+  launch_tri_invsqrt(alpha, ld, 0, beta, ld, 0, m, 0, nullptr, y, ld, status, scr, ld, k, st);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return GMRF_OK;
+}
+
+extern "C" gmrf_status gmrf_tridiag_log_e1(const double* alpha, const double* beta, const int32_t* m,
+                                           int32_t k, int32_t ld, double* out, int32_t* status,
+                                           void* stream) {
+  if (!alpha || !beta || !m || !out || k < 1 || k > 65535 || ld < 1 || ld > tri_max_m())
+    return fail(GMRF_EINVAL, "bad arguments (ld must be <= %d)", tri_max_m());
+  launch_tri_log(alpha, ld, 0, beta, ld, 0, m, 0, nullptr, out, 1, status, k, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return GMRF_OK;
+}

@@ -1,0 +1,49 @@
+// Internal launcher declarations shared by the kernel translation units and the host
+// runtime (gmrf_api.cpp).  Not part of the public C ABI (include/gmrf.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace gmrf {
+
+// Lattice geometry as a 3D box (n0, n1, n2), n2 contiguous; 1D/2D lattices have leading 1s.
+struct StencilGeom {
+  int n0, n1, n2;
+  int periodic;
+  double kappa2, tau;
+  int tiles_x, tiles_y, tiles_z;
+};
+
+// lanczos_kernels.hip
+int ew_blocks(long L);
+int rademacher_blocks(long n);
+template <typename T> void launch_init_from_f64(const double* Z, long zld, long L, T* V0, const LzState& S, hipStream_t st);
+template <typename T> void launch_init_from_i8(const int8_t* P, long L, T* V0, const LzState& S, hipStream_t st);
+template <typename T> void launch_init_rademacher(uint64_t seed, long n, T* V0, const LzState& S, hipStream_t st);
+void launch_rademacher_i8(uint64_t seed, long n, int nprobes, int8_t* out, hipStream_t st);
+template <typename T> void launch_update(const T* Qb, const T* Vj, T* W, long L, int j, int with_norm, const LzState& S, hipStream_t st);
+void launch_hutchinson_aggregate(const double* g, const double* beta, int ldb, int np, double shift, double* out, hipStream_t st);
+void launch_finalize(const LzState& S, hipStream_t st);
+template <typename T> void launch_reorth(T* V, long L, int j, double* part_h, double* h, int hstride, const LzState& S, hipStream_t st);
+template <typename T, typename OutT> void launch_combine(const T* V, long L, const double* y, int ldy, OutT* out, long old, const LzState& S, hipStream_t st);
+
+// operator_kernels.hip
+void stencil_geom_tiles(StencilGeom& g, int dim);
+int stencil_blocks(const StencilGeom& g);
+template <typename T> void launch_stencil(const StencilGeom& g, int order, int dim, bool lz, const T* X, long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k, hipStream_t st);
+int csr_blocks(long n);
+template <typename T> void launch_csr(long n, const int64_t* rp, const int32_t* ci, const T* va, bool lz, const T* X, long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k, hipStream_t st);
+
+// tridiag_kernels.hip
+int tri_max_m();
+size_t tri_scratch_doubles(int k, int m_cap);
+void launch_tri_invsqrt(const double* alpha, int lda, int a_off, const double* beta, int ldb, int b_off,
+                        const int* m, int m_fixed, const int* status_in, double* y, int ldy,
+                        int* status_out, double* scratch, int scr_m, int k, hipStream_t st);
+void launch_tri_log(const double* alpha, int lda, int a_off, const double* beta, int ldb, int b_off,
+                    const int* m, int m_fixed, const int* status_in, double* out, int ldo,
+                    int* status_out, int k, hipStream_t st);
+
+}  // namespace gmrf

@@ -1,0 +1,392 @@
+// Elementwise kernels of the Lanczos recurrence (Algorithm 1), the full
+// reorthogonalisation, the final combination x_m = ||z|| V_m y and the Rademacher probes
+// of the Hutchinson estimator (Section 6).  All memory-bound: coalesced strided loops, FP64
+// arithmetic on values loaded from the storage type T, deterministic partial sums.
+#include "kernels.hpp"
+
+namespace gmrf {
+
+// Element e of block b, thread t, step q: b*chunk + q*NT + t  (each wave-load coalesced).
+#define EW_LOOP(q) for (int q = 0; q < kEwPerThread; ++q)
+
+// ---- init: slot 0 <- z (storage type), partial sums of ||z||^2 ------------------------------
+template <typename T>
+__global__ __launch_bounds__(kEwThreads) void k_init_from_f64(const double* __restrict__ Z, long zld,
+                                                              long L, T* __restrict__ V0, LzState S) {
+  __shared__ double lds[kEwThreads / kWave];
+  const int r = blockIdx.y;
+  const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
+  const double* z = Z + (size_t)r * zld;
+  T* v = V0 + (size_t)r * L;
+  double acc = 0.0;
+  EW_LOOP(q) {
+    const long e = base + (long)q * kEwThreads;
+    if (e < L) {
+      const T t = (T)z[e];
+      v[e] = t;
+      acc += ip_weight(S, e) * (double)t * (double)t;
+    }
+  }
+  const double s = block_sum<kEwThreads>(acc, lds);
+  if (threadIdx.x == 0) S.part_b[(size_t)r * S.pstride + blockIdx.x] = s;
+}
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+//   (hi0, lo0) = M0 c0, (hi1, lo1) = M1 c2, c <- (hi1^c1^k0, lo1, hi0^c3^k1, lo0), key += W.
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    if (rnd > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+// Rademacher probe entries: lane l of a wave generates the four Philox words of block
+// (wave_base + l) (256 entries); the wave then writes its 64 x 256 entries with coalesced
+// stores, reading each word from its owner lane.
+template <typename OutT>
+__device__ __forceinline__ void rademacher_wave(uint64_t seed, int p, long n, long wave_block0,
+                                                OutT* out, double& acc) {
+  const int lane = threadIdx.x & (kWave - 1);
+  uint64_t c[4] = {(uint64_t)(wave_block0 + lane), (uint64_t)p, 0ull, 0ull};
+  philox4x64_10(c, seed, 0ull);
+  const long e0 = wave_block0 * 256;
+  for (int q = 0; q < 256; ++q) {
+    // entry e0 + 64 q + lane lies in block (wave_block0 + q/4), word q%4, bit lane
+    const int src = q >> 2, wsel = q & 3;
+    const uint64_t wv = wsel == 0 ? c[0] : wsel == 1 ? c[1] : wsel == 2 ? c[2] : c[3];
+    const uint32_t lo = __shfl((uint32_t)(wv & 0xffffffffu), src, kWave);
+    const uint32_t hi = __shfl((uint32_t)(wv >> 32), src, kWave);
+    const uint64_t word = ((uint64_t)hi << 32) | lo;
+    const long e = e0 + 64L * q + lane;
+    if (e < n) {
+      const int bit = (int)((word >> lane) & 1ull);
+      const OutT v = bit ? (OutT)-1 : (OutT)1;
+      out[e] = v;
+      acc += 1.0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rademacher_i8(uint64_t seed, long n, int8_t* __restrict__ out) {
+  const int p = blockIdx.y;
+  const long wave_block0 = ((long)blockIdx.x * (256 / kWave) + threadIdx.x / kWave) * kWave;
+  if (wave_block0 * 256 >= n) return;
+  double acc = 0.0;
+  rademacher_wave<int8_t>(seed, p, n, wave_block0, out + (size_t)p * n, acc);
+}
+
+// Probes straight into Krylov slot 0 (storage type); ||v||^2 partials per block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_rademacher(uint64_t seed, long n, T* __restrict__ V0,
+                                                         LzState S) {
+  __shared__ double lds[256 / kWave];
+  const int p = blockIdx.y;
+  const long wave_block0 = ((long)blockIdx.x * (256 / kWave) + threadIdx.x / kWave) * kWave;
+  double acc = 0.0;
+  if (wave_block0 * 256 < n) rademacher_wave<T>(seed, p, n, wave_block0, V0 + (size_t)p * n, acc);
+  const double s = block_sum<256>(acc, lds);
+  if (threadIdx.x == 0) S.part_b[(size_t)p * S.pstride + blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kEwThreads) void k_init_from_i8(const int8_t* __restrict__ P, long L,
+                                                             T* __restrict__ V0, LzState S) {
+  __shared__ double lds[kEwThreads / kWave];
+  const int r = blockIdx.y;
+  const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
+  double acc = 0.0;
+  EW_LOOP(q) {
+    const long e = base + (long)q * kEwThreads;
+    if (e < L) {
+      const T t = (T)P[(size_t)r * L + e];
+      V0[(size_t)r * L + e] = t;
+      acc += (double)t * (double)t;
+    }
+  }
+  const double s = block_sum<kEwThreads>(acc, lds);
+  if (threadIdx.x == 0) S.part_b[(size_t)r * S.pstride + blockIdx.x] = s;
+}
+
+// ---- update: alpha_j from the op kernel's partials, w_j = q - alpha_j v_j into slot j ------
+template <typename T>
+__global__ __launch_bounds__(kEwThreads) void k_update(const T* __restrict__ Qb, const T* __restrict__ Vj,
+                                                       T* __restrict__ W, long L, int j, int with_norm,
+                                                       LzState S) {
+  __shared__ double lds[kEwThreads / kWave];
+  __shared__ int flag[1];
+  const int r = blockIdx.y;
+  if (!block_active(S, r, flag)) return;
+  const double a = sum_partials<kEwThreads>(S.part_a + (size_t)r * S.pstride, S.Pa, lds);
+  if (blockIdx.x == 0 && threadIdx.x == 0) S.alpha[lz_ia(S, r, j)] = a;
+  const double sc = 1.0 / S.beta[lz_ib(S, r, j - 1)];
+  const T* vj = Vj + (size_t)r * L;
+  T* w = W + (size_t)r * L;
+  const T* q = Qb + (size_t)r * L;
+  const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
+  double acc = 0.0;
+  EW_LOOP(qq) {
+    const long e = base + (long)qq * kEwThreads;
+    if (e < L) {
+      const double v = (double)(T)((double)vj[e] * sc);
+      const T t = (T)((double)q[e] - a * v);
+      w[e] = t;
+      acc += ip_weight(S, e) * (double)t * (double)t;
+    }
+  }
+  if (with_norm) {
+    const double s = block_sum<kEwThreads>(acc, lds);
+    if (threadIdx.x == 0) S.part_b[(size_t)r * S.pstride + blockIdx.x] = s;
+  }
+}
+
+// ---- closes runs that reached m_max ----------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize(LzState S) {
+  __shared__ double lds[256 / kWave];
+  __shared__ int flag[1];
+  double a, b, c;
+  lz_open<256>(S, blockIdx.x, S.m_max + 1, threadIdx.x == 0, lds, flag, a, b, c);
+}
+
+// ---- full reorthogonalisation, classical Gram-Schmidt ------------------------------------------
+// pass: h_t = v_{t+1}^T w for t < j (partials per block), then w -= sum_t h_t v_{t+1}.
+// Dot kernel: the block's chunk of w is staged in LDS; wave g takes basis vectors
+// t = g, g + NW, ... and reduces each with wave shuffles only.
+template <typename T>
+__global__ __launch_bounds__(kEwThreads) void k_reorth_dot(const T* __restrict__ V, long L, int j,
+                                                           double* __restrict__ part_h, int hstride,
+                                                           LzState S) {
+  __shared__ double wl[kEwChunk];
+  __shared__ int flag[1];
+  const int r = blockIdx.y;
+  if (!block_active(S, r, flag)) return;
+  const size_t vs = (size_t)S.k * L;
+  const long base = (long)blockIdx.x * kEwChunk;
+  const T* w = V + (size_t)j * vs + (size_t)r * L;
+  for (int i = threadIdx.x; i < kEwChunk; i += kEwThreads) {
+    const long e = base + i;
+    wl[i] = (e < L) ? ip_weight(S, e) * (double)w[e] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), g = threadIdx.x / kWave;
+  constexpr int NW = kEwThreads / kWave;
+  for (int t = g; t < j; t += NW) {
+    const T* vt = V + (size_t)t * vs + (size_t)r * L;
+    const double sc = 1.0 / S.beta[lz_ib(S, r, t)];
+    double acc = 0.0;
+    for (int i = lane; i < kEwChunk; i += kWave) {
+      const long e = base + i;
+      if (e < L) acc += (double)(T)((double)vt[e] * sc) * wl[i];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) part_h[((size_t)r * hstride + t) * gridDim.x + blockIdx.x] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reorth_reduce(const double* __restrict__ part_h, int hstride,
+                                                       int P, int j, double* __restrict__ h,
+                                                       LzState S) {
+  const int r = blockIdx.x;
+  if (!S.active[r]) return;
+  for (int t = threadIdx.x; t < j; t += 256) {
+    const double* p = part_h + ((size_t)r * hstride + t) * P;
+    double s = 0.0;
+    for (int b = 0; b < P; ++b) s += p[b];
+    h[(size_t)r * hstride + t] = s;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kEwThreads) void k_reorth_update(T* __restrict__ V, long L, int j,
+                                                              const double* __restrict__ h,
+                                                              int hstride, int with_norm,
+                                                              LzState S) {
+  __shared__ double cl[1024];
+  __shared__ double lds[kEwThreads / kWave];
+  __shared__ int flag[1];
+  const int r = blockIdx.y;
+  if (!block_active(S, r, flag)) return;
+  const size_t vs = (size_t)S.k * L;
+  T* w = V + (size_t)j * vs + (size_t)r * L;
+  const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
+  double acc[kEwPerThread];
+  EW_LOOP(q) {
+    const long e = base + (long)q * kEwThreads;
+    acc[q] = (e < L) ? (double)w[e] : 0.0;
+  }
+  for (int t0 = 0; t0 < j; t0 += 1024) {
+    const int tn = min(1024, j - t0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < tn; t += kEwThreads) cl[t] = h[(size_t)r * hstride + t0 + t];
+    __syncthreads();
+    for (int t = 0; t < tn; ++t) {
+      const T* vt = V + (size_t)(t0 + t) * vs + (size_t)r * L;
+      const double sc = 1.0 / S.beta[lz_ib(S, r, t0 + t)];
+      const double ht = cl[t];
+      EW_LOOP(q) {
+        const long e = base + (long)q * kEwThreads;
+        if (e < L) acc[q] -= ht * (double)(T)((double)vt[e] * sc);
+      }
+    }
+  }
+  double nrm = 0.0;
+  EW_LOOP(q) {
+    const long e = base + (long)q * kEwThreads;
+    if (e < L) {
+      const T t = (T)acc[q];
+      w[e] = t;
+      nrm += ip_weight(S, e) * (double)t * (double)t;
+    }
+  }
+  if (with_norm) {
+    const double s = block_sum<kEwThreads>(nrm, lds);
+    if (threadIdx.x == 0) S.part_b[(size_t)r * S.pstride + blockIdx.x] = s;
+  }
+}
+
+// ---- x_m = ||z|| V_m y  (Algorithm 1, final step) ---------------------------------------------
+// out[r*old + e] = beta_0 sum_{t < m} y_t v_{t+1}[e]; NaN for a column whose status is ENOTSPD
+// or EINVAL, zero for m = 0.
+template <typename T, typename OutT>
+__global__ __launch_bounds__(kEwThreads) void k_combine(const T* __restrict__ V, long L,
+                                                        const double* __restrict__ y, int ldy,
+                                                        OutT* __restrict__ out, long old, LzState S) {
+  __shared__ double cl[1024];
+  const int r = blockIdx.y;
+  const int m = S.m_used[r];
+  const int st = S.status[r];
+  const double beta0 = S.beta[lz_ib(S, r, 0)];
+  const size_t vs = (size_t)S.k * L;
+  const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
+  double acc[kEwPerThread];
+  EW_LOOP(q) acc[q] = 0.0;
+  const bool bad = (st == kENOTSPD || st == kEINVAL);
+  if (!bad) {
+    for (int t0 = 0; t0 < m; t0 += 1024) {
+      const int tn = min(1024, m - t0);
+      __syncthreads();
+      for (int t = threadIdx.x; t < tn; t += kEwThreads)
+        cl[t] = beta0 * y[(size_t)r * ldy + t0 + t] / S.beta[lz_ib(S, r, t0 + t)];
+      __syncthreads();
+      for (int t = 0; t < tn; ++t) {
+        const T* vt = V + (size_t)(t0 + t) * vs + (size_t)r * L;
+        const double ct = cl[t];
+        EW_LOOP(q) {
+          const long e = base + (long)q * kEwThreads;
+          if (e < L) acc[q] += ct * (double)vt[e];
+        }
+      }
+    }
+  }
+  const double nanv = __longlong_as_double(0x7ff8000000000000ll);
+  EW_LOOP(q) {
+    const long e = base + (long)q * kEwThreads;
+    if (e < L) out[(size_t)r * old + e] = (OutT)(bad ? nanv : acc[q]);
+  }
+}
+
+// ---- Hutchinson aggregate (Section 6): Gamma_p = ||v_p||^2 e_1^T log(T_m) e_1 + shift,
+// out[0] = mean, out[1] = sd / sqrt(N) (NaN for N = 1), out[2 + p] = Gamma_p.
+__global__ __launch_bounds__(256) void k_hutchinson(const double* __restrict__ g, const double* __restrict__ beta,
+                                                    int ldb, int np, double shift, double* __restrict__ out) {
+  __shared__ double lds[256 / kWave];
+  double s = 0.0;
+  for (int p = threadIdx.x; p < np; p += 256) {
+    const double b0 = beta[(size_t)p * ldb];
+    const double gam = b0 * b0 * g[p] + shift;
+    out[2 + p] = gam;
+    s += gam;
+  }
+  const double mean = block_sum<256>(s, lds) / np;
+  double v = 0.0;
+  for (int p = threadIdx.x; p < np; p += 256) {
+    const double b0 = beta[(size_t)p * ldb];
+    const double d = (b0 * b0 * g[p] + shift) - mean;
+    v += d * d;
+  }
+  const double ss = block_sum<256>(v, lds);
+  if (threadIdx.x == 0) {
+    out[0] = mean;
+    out[1] = np > 1 ? sqrt(ss / (np - 1) / np) : __longlong_as_double(0x7ff8000000000000ll);
+  }
+}
+
+void launch_hutchinson_aggregate(const double* g, const double* beta, int ldb, int np, double shift, double* out,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_hutchinson, dim3(1), dim3(256), 0, st, g, beta, ldb, np, shift, out);
+}
+
+// ---- host launchers ---------------------------------------------------------------------------
+static inline dim3 ew_grid(long L, int k) { return dim3((unsigned)((L + kEwChunk - 1) / kEwChunk), (unsigned)k); }
+int ew_blocks(long L) { return (int)((L + kEwChunk - 1) / kEwChunk); }
+
+template <typename T>
+void launch_init_from_f64(const double* Z, long zld, long L, T* V0, const LzState& S, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_from_f64<T>, ew_grid(L, S.k), dim3(kEwThreads), 0, st, Z, zld, L, V0, S);
+}
+template <typename T>
+void launch_init_from_i8(const int8_t* P, long L, T* V0, const LzState& S, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_from_i8<T>, ew_grid(L, S.k), dim3(kEwThreads), 0, st, P, L, V0, S);
+}
+int rademacher_blocks(long n) {
+  const long nb256 = (n + 255) / 256;       // Philox blocks
+  const long waves = (nb256 + kWave - 1) / kWave;
+  return (int)((waves + 3) / 4);
+}
+template <typename T>
+void launch_init_rademacher(uint64_t seed, long n, T* V0, const LzState& S, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_rademacher<T>, dim3(rademacher_blocks(n), S.k), dim3(256), 0, st, seed, n, V0, S);
+}
+void launch_rademacher_i8(uint64_t seed, long n, int nprobes, int8_t* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_rademacher_i8, dim3(rademacher_blocks(n), nprobes), dim3(256), 0, st, seed, n, out);
+}
+template <typename T>
+void launch_update(const T* Qb, const T* Vj, T* W, long L, int j, int with_norm, const LzState& S, hipStream_t st) {
+  hipLaunchKernelGGL(k_update<T>, ew_grid(L, S.k), dim3(kEwThreads), 0, st, Qb, Vj, W, L, j, with_norm, S);
+}
+void launch_finalize(const LzState& S, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(S.k), dim3(256), 0, st, S);
+}
+template <typename T>
+void launch_reorth(T* V, long L, int j, double* part_h, double* h, int hstride, const LzState& S,
+                   hipStream_t st) {
+  const dim3 g = ew_grid(L, S.k);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_reorth_dot<T>, g, dim3(kEwThreads), 0, st, V, L, j, part_h, hstride, S);
+    hipLaunchKernelGGL(k_reorth_reduce, dim3(S.k), dim3(256), 0, st, part_h, hstride, (int)g.x, j, h, S);
+    hipLaunchKernelGGL(k_reorth_update<T>, g, dim3(kEwThreads), 0, st, V, L, j, h, hstride,
+                       pass == 1 ? 1 : 0, S);
+  }
+}
+template <typename T, typename OutT>
+void launch_combine(const T* V, long L, const double* y, int ldy, OutT* out, long old, const LzState& S,
+                    hipStream_t st) {
+  hipLaunchKernelGGL((k_combine<T, OutT>), ew_grid(L, S.k), dim3(kEwThreads), 0, st, V, L, y, ldy, out, old, S);
+}
+
+#define INST(T)                                                                                  \
+  template void launch_init_from_f64<T>(const double*, long, long, T*, const LzState&, hipStream_t); \
+  template void launch_init_from_i8<T>(const int8_t*, long, T*, const LzState&, hipStream_t);      \
+  template void launch_init_rademacher<T>(uint64_t, long, T*, const LzState&, hipStream_t);        \
+  template void launch_update<T>(const T*, const T*, T*, long, int, int, const LzState&, hipStream_t); \
+  template void launch_reorth<T>(T*, long, int, double*, double*, int, const LzState&, hipStream_t); \
+  template void launch_combine<T, double>(const T*, long, const double*, int, double*, long,       \
+                                          const LzState&, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+template void launch_combine<float, float>(const float*, long, const double*, int, float*, long,
+                                           const LzState&, hipStream_t);
+
+}  // namespace gmrf

@@ -1,0 +1,240 @@
+// Operator kernels: q = Q v for the lattice precisions (matrix free) and for CSR matrices
+// (Section 2: the method touches Q only through products Q v).
+//
+// Lattice operators, with L the graph Laplacian of the grid (free) or torus (periodic):
+//   order 1: Q = tau (kappa2 I + L)      order 2: Q = tau (kappa2 I + L)^2
+// K = kappa2 I + L is evaluated in difference form, K v_p = kappa2 v_p + sum_{nb}(v_p - v_nb),
+// so smooth fields cancel exactly in FP32; order 2 applies K twice inside LDS (tile + 2-point
+// halo -> K on tile + 1 -> K on tile), the 13-point operator in 2D.
+//
+// In Lanczos mode the kernel opens iteration j (scalar step, see lz_open), reads
+// v_j = slot(j-1)/beta_{j-1} with the scale folded into the load, and fuses the first part
+// of Algorithm 1's loop body:  q = Q v_j - beta_{j-1} v_{j-1},  partial sums of v_j^T q.
+#include "kernels.hpp"
+
+namespace gmrf {
+
+template <int DIM> struct TileShape;
+template <> struct TileShape<1> { static constexpr int TZ = 1, TY = 1, TX = 256; };
+template <> struct TileShape<2> { static constexpr int TZ = 1, TY = 16, TX = 64; };
+template <> struct TileShape<3> { static constexpr int TZ = 4, TY = 8, TX = 32; };
+
+__device__ __forceinline__ int wrap_idx(int c, int n) {
+  c %= n;
+  return c < 0 ? c + n : c;
+}
+
+// K = kappa2 I + L at local point (lz, ly, lx) of an LDS box A of dims (AY, AX) per plane
+// whose origin sits at global (gz - lz, gy - ly, gx - lx).  Neighbour validity: periodic
+// always, free only inside the lattice.
+template <typename T, int DIM>
+__device__ __forceinline__ T apply_K(const T* A, int AY, int AX, int lz, int ly, int lx, int gz,
+                                     int gy, int gx, const StencilGeom& g, T k2) {
+  const int c = (lz * AY + ly) * AX + lx;
+  const T v = A[c];
+  T acc = k2 * v;
+  const bool per = g.periodic != 0;
+  if (per || gx - 1 >= 0) acc += v - A[c - 1];
+  if (per || gx + 1 < g.n2) acc += v - A[c + 1];
+  if (DIM >= 2) {
+    if (per || gy - 1 >= 0) acc += v - A[c - AX];
+    if (per || gy + 1 < g.n1) acc += v - A[c + AX];
+  }
+  if (DIM >= 3) {
+    if (per || gz - 1 >= 0) acc += v - A[c - AX * AY];
+    if (per || gz + 1 < g.n0) acc += v - A[c + AX * AY];
+  }
+  return acc;
+}
+
+template <typename T, int ORDER, int DIM, bool LZ>
+__global__ __launch_bounds__(256) void k_stencil(StencilGeom g, const T* __restrict__ X, long xld,
+                                                 T* __restrict__ Y, long yld,
+                                                 const T* __restrict__ Xprev, LzState S, int j) {
+  using TS = TileShape<DIM>;
+  constexpr int HZ = DIM >= 3 ? ORDER : 0, HY = DIM >= 2 ? ORDER : 0, HX = ORDER;
+  constexpr int RZ = TS::TZ + 2 * HZ, RY = TS::TY + 2 * HY, RX = TS::TX + 2 * HX;
+  constexpr int EZ = DIM >= 3 ? 1 : 0, EY = DIM >= 2 ? 1 : 0;
+  constexpr int QZ = TS::TZ + 2 * EZ, QY = TS::TY + 2 * EY, QX = TS::TX + 2;  // K-stage box
+  __shared__ T vs[RZ * RY * RX];
+  __shared__ T ts[ORDER == 2 ? QZ * QY * QX : 1];
+  __shared__ double red[256 / kWave];
+  __shared__ int flag[1];
+
+  const int r = blockIdx.y;
+  double s_cur = 1.0, s_prev = 0.0, bprev = 0.0;
+  if (LZ) {
+    if (!lz_open<256>(S, r, j, blockIdx.x == 0, red, flag, s_cur, s_prev, bprev)) return;
+  }
+  const int bid = blockIdx.x;
+  const int tx = bid % g.tiles_x, ty = (bid / g.tiles_x) % g.tiles_y, tz = bid / (g.tiles_x * g.tiles_y);
+  const int x0 = tx * TS::TX, y0 = ty * TS::TY, z0 = tz * TS::TZ;
+  const T* src = X + (size_t)r * xld;
+  const bool per = g.periodic != 0;
+
+  for (int idx = threadIdx.x; idx < RZ * RY * RX; idx += 256) {
+    const int lx = idx % RX, ly = (idx / RX) % RY, lz = idx / (RX * RY);
+    int gx = x0 + lx - HX, gy = y0 + ly - HY, gz = z0 + lz - HZ;
+    T val = (T)0;
+    bool ok;
+    if (per) {
+      gx = wrap_idx(gx, g.n2);
+      gy = wrap_idx(gy, g.n1);
+      gz = wrap_idx(gz, g.n0);
+      ok = true;
+    } else {
+      ok = gx >= 0 && gx < g.n2 && gy >= 0 && gy < g.n1 && gz >= 0 && gz < g.n0;
+    }
+    if (ok) {
+      const T raw = src[((size_t)gz * g.n1 + gy) * g.n2 + gx];
+      val = LZ ? (T)((double)raw * s_cur) : raw;
+    }
+    vs[idx] = val;
+  }
+  __syncthreads();
+  const T k2 = (T)g.kappa2;
+  const T* A = vs;
+  int AY = RY, AX = RX, oz = HZ, oy = HY, ox = HX;   // box origin offset vs tile origin
+  if (ORDER == 2) {
+    for (int idx = threadIdx.x; idx < QZ * QY * QX; idx += 256) {
+      const int lx = idx % QX, ly = (idx / QX) % QY, lz = idx / (QX * QY);
+      const int gx = x0 + lx - 1, gy = y0 + ly - EY, gz = z0 + lz - EZ;
+      const bool in = per || (gx >= 0 && gx < g.n2 && gy >= 0 && gy < g.n1 && gz >= 0 && gz < g.n0);
+      T t = (T)0;
+      if (in) t = apply_K<T, DIM>(vs, RY, RX, lz + (HZ - EZ), ly + (HY - EY), lx + (HX - 1), gz, gy, gx, g, k2);
+      ts[idx] = t;
+    }
+    __syncthreads();
+    A = ts;
+    AY = QY;
+    AX = QX;
+    oz = EZ;
+    oy = EY;
+    ox = 1;
+  }
+  const T tau = (T)g.tau;
+  T* dst = Y + (size_t)r * yld;
+  const T* prv = LZ ? Xprev + (size_t)r * xld : nullptr;
+  double acc = 0.0;
+  constexpr int TP = TS::TZ * TS::TY * TS::TX;
+  for (int idx = threadIdx.x; idx < TP; idx += 256) {
+    const int lx = idx % TS::TX, ly = (idx / TS::TX) % TS::TY, lz = idx / (TS::TX * TS::TY);
+    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+    if (gx >= g.n2 || gy >= g.n1 || gz >= g.n0) continue;
+    const T kv = apply_K<T, DIM>(A, AY, AX, lz + oz, ly + oy, lx + ox, gz, gy, gx, g, k2);
+    const T out = tau * kv;
+    const size_t gi = ((size_t)gz * g.n1 + gy) * g.n2 + gx;
+    if (LZ) {
+      double q = (double)out;
+      if (j > 1) q -= bprev * (double)(T)((double)prv[gi] * s_prev);
+      const T qt = (T)q;
+      dst[gi] = qt;
+      const T vj = vs[((lz + HZ) * RY + (ly + HY)) * RX + (lx + HX)];
+      acc += (double)vj * (double)qt;
+    } else {
+      dst[gi] = out;
+    }
+  }
+  if (LZ) {
+    const double s = block_sum<256>(acc, red);
+    if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + blockIdx.x] = s;
+  }
+}
+
+// ---- CSR: one thread per row ----------------------------------------------------------------
+template <typename T, bool LZ>
+__global__ __launch_bounds__(256) void k_csr(long n, const int64_t* __restrict__ rp,
+                                             const int32_t* __restrict__ ci, const T* __restrict__ va,
+                                             const T* __restrict__ X, long xld, T* __restrict__ Y,
+                                             long yld, const T* __restrict__ Xprev, LzState S, int j) {
+  __shared__ double red[256 / kWave];
+  __shared__ int flag[1];
+  const int r = blockIdx.y;
+  double s_cur = 1.0, s_prev = 0.0, bprev = 0.0;
+  if (LZ) {
+    if (!lz_open<256>(S, r, j, blockIdx.x == 0, red, flag, s_cur, s_prev, bprev)) return;
+  }
+  const long row = (long)blockIdx.x * 256 + threadIdx.x;
+  const T* src = X + (size_t)r * xld;
+  double acc = 0.0;
+  if (row < n) {
+    T s = (T)0;
+    for (int64_t e = rp[row]; e < rp[row + 1]; ++e) {
+      const T raw = src[ci[e]];
+      s += va[e] * (LZ ? (T)((double)raw * s_cur) : raw);
+    }
+    if (LZ) {
+      double q = (double)s;
+      if (j > 1) q -= bprev * (double)(T)((double)Xprev[(size_t)r * xld + row] * s_prev);
+      const T qt = (T)q;
+      Y[(size_t)r * yld + row] = qt;
+      acc = (double)(T)((double)src[row] * s_cur) * (double)qt;
+    } else {
+      Y[(size_t)r * yld + row] = s;
+    }
+  }
+  if (LZ) {
+    const double bs = block_sum<256>(acc, red);
+    if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + blockIdx.x] = bs;
+  }
+}
+
+// ---- host side --------------------------------------------------------------------------------
+void stencil_geom_tiles(StencilGeom& g, int dim) {
+  int TZ, TY, TX;
+  if (dim == 1) { TZ = TileShape<1>::TZ; TY = TileShape<1>::TY; TX = TileShape<1>::TX; }
+  else if (dim == 2) { TZ = TileShape<2>::TZ; TY = TileShape<2>::TY; TX = TileShape<2>::TX; }
+  else { TZ = TileShape<3>::TZ; TY = TileShape<3>::TY; TX = TileShape<3>::TX; }
+  g.tiles_x = (g.n2 + TX - 1) / TX;
+  g.tiles_y = (g.n1 + TY - 1) / TY;
+  g.tiles_z = (g.n0 + TZ - 1) / TZ;
+}
+
+int stencil_blocks(const StencilGeom& g) { return g.tiles_x * g.tiles_y * g.tiles_z; }
+
+template <typename T, int ORDER, int DIM, bool LZ>
+static void launch_stencil_t(const StencilGeom& g, const T* X, long xld, T* Y, long yld,
+                             const T* Xprev, const LzState& S, int j, int k, hipStream_t st) {
+  hipLaunchKernelGGL((k_stencil<T, ORDER, DIM, LZ>), dim3(stencil_blocks(g), k), dim3(256), 0, st, g,
+                     X, xld, Y, yld, Xprev, S, j);
+}
+
+template <typename T>
+void launch_stencil(const StencilGeom& g, int order, int dim, bool lz, const T* X, long xld, T* Y,
+                    long yld, const T* Xprev, const LzState& S, int j, int k, hipStream_t st) {
+#define CASE(O, D)                                                                      \
+  if (order == O && dim == D) {                                                          \
+    if (lz) launch_stencil_t<T, O, D, true>(g, X, xld, Y, yld, Xprev, S, j, k, st);      \
+    else launch_stencil_t<T, O, D, false>(g, X, xld, Y, yld, Xprev, S, j, k, st);        \
+    return;                                                                              \
+  }
+  CASE(1, 1) CASE(1, 2) CASE(1, 3) CASE(2, 1) CASE(2, 2) CASE(2, 3)
+#undef CASE
+}
+
+int csr_blocks(long n) { return (int)((n + 255) / 256); }
+
+template <typename T>
+void launch_csr(long n, const int64_t* rp, const int32_t* ci, const T* va, bool lz, const T* X,
+                long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k,
+                hipStream_t st) {
+  if (lz)
+    hipLaunchKernelGGL((k_csr<T, true>), dim3(csr_blocks(n), k), dim3(256), 0, st, n, rp, ci, va, X, xld,
+                       Y, yld, Xprev, S, j);
+  else
+    hipLaunchKernelGGL((k_csr<T, false>), dim3(csr_blocks(n), k), dim3(256), 0, st, n, rp, ci, va, X,
+                       xld, Y, yld, Xprev, S, j);
+}
+
+template void launch_stencil<double>(const StencilGeom&, int, int, bool, const double*, long, double*,
+                                     long, const double*, const LzState&, int, int, hipStream_t);
+template void launch_stencil<float>(const StencilGeom&, int, int, bool, const float*, long, float*,
+                                    long, const float*, const LzState&, int, int, hipStream_t);
+template void launch_csr<double>(long, const int64_t*, const int32_t*, const double*, bool,
+                                 const double*, long, double*, long, const double*, const LzState&,
+                                 int, int, hipStream_t);
+template void launch_csr<float>(long, const int64_t*, const int32_t*, const float*, bool,
+                                const float*, long, float*, long, const float*, const LzState&, int,
+                                int, hipStream_t);
+
+}  // namespace gmrf

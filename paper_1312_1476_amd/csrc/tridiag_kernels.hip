@@ -1,0 +1,191 @@
+// The m x m tridiagonal step (FP64): y = T^{-1/2} e_1 for the sample (Algorithm 1, final
+// step) and e_1^T log(T) e_1 for the Gauss quadrature of the log-det estimator (Section 6).
+//
+// The caption of Algorithm 1 suggests replacing T^{-1/2} by a rational approximation.  This
+// file uses one that needs no eigenvectors, so clustered or repeated Ritz values cost
+// nothing extra and every shift is independent (one GPU thread each):
+//   lambda^{-1/2} = (2/pi) int_R e^s / (e^{2s} + lambda) ds,
+//   log(lambda)   = int_R e^s ( 1/(1 + e^s) - 1/(lambda + e^s) ) ds,
+// discretised by the trapezoidal rule in s.  The integrands are analytic in the strips
+// |Im s| < pi/2 and |Im s| < pi, so steps h = 1/4 and h = 1/2 give errors near 1e-16; the
+// truncation points sit 37 e-folds beyond the spectrum [lo, hi] of T, whose upper end is a
+// Gershgorin bound and whose lower end comes from Sturm counts (LDL^T inertia of T - x I)
+// at x = hi * 2^{-t/2}, t = 0..255, which also certifies that T is positive definite.
+// Each node needs (T + sigma I)^{-1} e_1: with the backward pivots
+//   d_{m-1} = alpha_{m-1} + sigma,  d_i = alpha_i + sigma - beta_i^2 / d_{i+1},
+// its entries are y_0 = 1/d_0, y_{i+1} = -(beta_i / d_{i+1}) y_i, and (T+sigma)^{-1}_{00} = 1/d_0.
+// Sums over nodes are wave butterflies then a fixed-order sum over waves: deterministic.
+#include "kernels.hpp"
+
+namespace gmrf {
+
+constexpr int kTriThreads = 256;
+constexpr int kTriMaxM = 1024;
+constexpr double kPad = 37.0;
+
+struct TriArgs {
+  const double* alpha;
+  int lda, a_off;
+  const double* beta;
+  int ldb, b_off;
+  const int* m;         // nullptr: use m_fixed
+  int m_fixed;
+  const int* status_in; // nullptr or per-RHS status; a non-OK entry is skipped
+  double* out;          // y (ldy per RHS) or scalar per RHS
+  int ldy;
+  int* status_out;      // may be nullptr; only written (ENOTSPD) when T is not SPD
+  double* scratch;      // [k][scr_m][kTriThreads] for the sample
+  int scr_m;
+};
+
+// Spectrum bracket of T (LDS copies a, b of length m): returns false if T is not SPD.
+__device__ bool tri_bracket(const double* a, const double* b, int m, double* red, int* ired,
+                            double& lo, double& hi) {
+  double g = 0.0;
+  for (int i = threadIdx.x; i < m; i += kTriThreads) {
+    const double bl = i > 0 ? fabs(b[i - 1]) : 0.0, br = i + 1 < m ? fabs(b[i]) : 0.0;
+    g = fmax(g, a[i] + bl + br);
+  }
+  hi = block_max<kTriThreads>(g, red);
+  // Sturm count at x_t = hi 2^{-t/2}: number of negative pivots of T - x I
+  const int t = threadIdx.x;
+  const double x = hi * exp2(-0.5 * (double)t);
+  int neg = 0;
+  double d = a[0] - x;
+  if (d <= 0.0) ++neg;
+  for (int i = 1; i < m; ++i) {
+    if (d == 0.0) d = -1e-300;
+    d = a[i] - x - b[i - 1] * b[i - 1] / d;
+    if (d <= 0.0) ++neg;
+  }
+  int cand = (neg == 0) ? t : 1 << 30;
+  cand = wave_min_int(cand);
+  __syncthreads();
+  if ((threadIdx.x & (kWave - 1)) == 0) ired[threadIdx.x / kWave] = cand;
+  __syncthreads();
+  int best = 1 << 30;
+  for (int w = 0; w < kTriThreads / kWave; ++w) best = min(best, ired[w]);
+  if (!(hi > 0.0) || !isfinite(hi) || best >= (1 << 30)) return false;
+  lo = hi * exp2(-0.5 * (double)best);
+  return true;
+}
+
+__device__ void tri_load(const TriArgs& A, int r, int m, double* a, double* b) {
+  for (int i = threadIdx.x; i < m; i += kTriThreads) {
+    a[i] = A.alpha[(size_t)r * A.lda + A.a_off + i];
+    b[i] = (i + 1 < m) ? A.beta[(size_t)r * A.ldb + A.b_off + i] : 0.0;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
+  __shared__ double a[kTriMaxM], b[kTriMaxM];
+  __shared__ double yw[kTriThreads / kWave][kTriMaxM / 2];
+  __shared__ double red[kTriThreads / kWave];
+  __shared__ int ired[kTriThreads / kWave];
+  const int r = blockIdx.x;
+  // m never exceeds the LDS copy, the scratch rows or the output row
+  const int m = min(min(A.m ? A.m[r] : A.m_fixed, kTriMaxM), min(A.scr_m, A.ldy));
+  double* y = A.out + (size_t)r * A.ldy;
+  if (A.status_in && A.status_in[r] != kOK && A.status_in[r] != kENOCONV) return;
+  if (m <= 0) return;
+  tri_load(A, r, m, a, b);
+  double lo, hi;
+  const bool spd = tri_bracket(a, b, m, red, ired, lo, hi);
+  if (!spd) {
+    if (threadIdx.x == 0 && A.status_out) A.status_out[r] = kENOTSPD;
+    return;
+  }
+  const double h = 0.25;
+  const double s_lo = 0.5 * log(lo) - kPad, s_hi = 0.5 * log(hi) + kPad;
+  const int nq = (int)ceil((s_hi - s_lo) / h) + 1;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  // the LDS accumulator holds half of kTriMaxM per wave; longer T uses two sweeps over i
+  for (int i0 = 0; i0 < m; i0 += kTriMaxM / 2) {
+    const int iend = min(m, i0 + kTriMaxM / 2);
+    for (int i = lane; i < iend - i0; i += kWave) yw[wv][i] = 0.0;
+    for (int base = 0; base < nq; base += kTriThreads) {
+      const int l = base + threadIdx.x;
+      const bool act = l < nq;
+      const double s = s_lo + h * (double)l;
+      const double es = exp(s);
+      const double sigma = es * es;
+      const double wgt = act ? (2.0 / M_PI) * h * es : 0.0;
+      double* rs = A.scratch + (size_t)r * A.scr_m * kTriThreads;
+      // backward pivots; rs[i][t] = beta_i / d_{i+1}
+      double d = a[m - 1] + sigma;
+      for (int i = m - 2; i >= 0; --i) {
+        const double q = b[i] / d;
+        rs[(size_t)i * kTriThreads + threadIdx.x] = q;
+        d = a[i] + sigma - b[i] * q;
+      }
+      double yi = 1.0 / d;
+      for (int i = 0; i < iend; ++i) {
+        if (i > 0) yi = -rs[(size_t)(i - 1) * kTriThreads + threadIdx.x] * yi;
+        if (i >= i0) {
+          const double c = wave_sum(act ? wgt * yi : 0.0);
+          if (lane == 0) yw[wv][i - i0] += c;
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < iend - i0; i += kTriThreads) {
+      double s = 0.0;
+      for (int w = 0; w < kTriThreads / kWave; ++w) s += yw[w][i];
+      y[i0 + i] = s;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kTriThreads) void k_tri_log(TriArgs A) {
+  __shared__ double a[kTriMaxM], b[kTriMaxM];
+  __shared__ double red[kTriThreads / kWave];
+  __shared__ int ired[kTriThreads / kWave];
+  const int r = blockIdx.x;
+  const int m = min(A.m ? A.m[r] : A.m_fixed, min(kTriMaxM, A.lda));
+  if (A.status_in && A.status_in[r] != kOK && A.status_in[r] != kENOCONV) return;
+  if (m <= 0) return;
+  tri_load(A, r, m, a, b);
+  double lo, hi;
+  const bool spd = tri_bracket(a, b, m, red, ired, lo, hi);
+  if (!spd) {
+    if (threadIdx.x == 0) {
+      if (A.status_out) A.status_out[r] = kENOTSPD;
+      A.out[(size_t)r * A.ldy] = __longlong_as_double(0x7ff8000000000000ll);
+    }
+    return;
+  }
+  const double h = 0.5;
+  const double s_lo = log(lo) - kPad, s_hi = log(hi) + kPad;
+  const int nq = (int)ceil((s_hi - s_lo) / h) + 1;
+  double acc = 0.0;
+  for (int l = threadIdx.x; l < nq; l += kTriThreads) {
+    const double s = s_lo + h * (double)l;
+    const double sigma = exp(s);
+    double d = a[m - 1] + sigma;
+    for (int i = m - 2; i >= 0; --i) d = a[i] + sigma - b[i] * b[i] / d;
+    acc += h * sigma * (1.0 / (1.0 + sigma) - 1.0 / d);
+  }
+  const double tot = block_sum<kTriThreads>(acc, red);
+  if (threadIdx.x == 0) A.out[(size_t)r * A.ldy] = tot;
+}
+
+int tri_max_m() { return kTriMaxM; }
+size_t tri_scratch_doubles(int k, int m_cap) { return (size_t)k * m_cap * kTriThreads; }
+
+void launch_tri_invsqrt(const double* alpha, int lda, int a_off, const double* beta, int ldb, int b_off,
+                        const int* m, int m_fixed, const int* status_in, double* y, int ldy,
+                        int* status_out, double* scratch, int scr_m, int k, hipStream_t st) {
+  TriArgs A{alpha, lda, a_off, beta, ldb, b_off, m, m_fixed, status_in, y, ldy, status_out, scratch, scr_m};
+  hipLaunchKernelGGL(k_tri_invsqrt, dim3(k), dim3(kTriThreads), 0, st, A);
+}
+
+void launch_tri_log(const double* alpha, int lda, int a_off, const double* beta, int ldb, int b_off,
+                    const int* m, int m_fixed, const int* status_in, double* out, int ldo,
+                    int* status_out, int k, hipStream_t st) {
+  TriArgs A{alpha, lda, a_off, beta, ldb, b_off, m, m_fixed, status_in, out, ldo, status_out, nullptr, 0};
+  hipLaunchKernelGGL(k_tri_log, dim3(k), dim3(kTriThreads), 0, st, A);
+}
+
+}  // namespace gmrf
