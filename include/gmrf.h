@@ -167,6 +167,18 @@ gmrf_status gmrf_tridiag_log_e1(const double* alpha, const double* beta, const i
                                 int32_t k, int32_t ld, double* out, int32_t* status,
                                 void* stream);
 
+/* ---- measurement ------------------------------------------------------------------------ */
+
+/* Times one kernel of the sampling path on its own: `reps` launches between two HIP events
+ * recorded on `stream`, on scratch buffers of the handle's shape with k columns.
+ *   which 0: Y = Q X (the operator's SpMV/SpMM kernel),  1: spectral column pass of the
+ *   preconditioned operator with the Lanczos epilogue,  2: spectral column pass that opens
+ *   an iteration,  3: the update w = q - alpha v.
+ * Outputs (host): *avg_us = mean duration of one launch, *bytes = algorithmic bytes of one
+ * launch (inputs read once, outputs written once).  EINVAL for 1/2 without preconditioning. */
+gmrf_status gmrf_kernel_bench(const gmrf_op* Q, int which, int64_t k, int32_t reps, double* avg_us,
+                              double* bytes, void* stream);
+
 /* ---- memory budget and errors ---------------------------------------------------------- */
 
 /* Cap on device bytes held by the library's scratch pool (0 = no cap).  Calls that would

@@ -18,7 +18,7 @@ from . import _abi
 from ._abi import GMRF_F32, GMRF_F64, GMRF_FREE, GMRF_PERIODIC, GmrfError, Info, check, lib
 
 __all__ = ["Operator", "rademacher", "tridiag_invsqrt_e1", "tridiag_log_e1", "set_hbm_budget",
-           "hbm_in_use", "GmrfError", "STATUS"]
+           "hbm_in_use", "kernel_bench", "GmrfError", "STATUS"]
 
 STATUS = _abi.STATUS_NAMES
 
@@ -206,6 +206,19 @@ def tridiag_log_e1(alpha, beta, m, stream=None):
     check(lib().gmrf_tridiag_log_e1(_dptr(alpha), _dptr(beta), _dptr(m), k, ld, _dptr(out), _dptr(status),
                                     _stream_ptr(stream)), "gmrf_tridiag_log_e1")
     return out, status
+
+
+KERNELS = {"spmv": 0, "col_fwd_lz": 1, "col_inv_lz": 2, "update": 3}
+
+
+def kernel_bench(op, kernel, k, reps=50, stream=None):
+    """Average duration (us) and algorithmic bytes of one launch of a path kernel, timed with
+    HIP events on `stream` (default: torch's current stream)."""
+    us, nb = C.c_double(), C.c_double()
+    check(lib().gmrf_kernel_bench(op._h, KERNELS[kernel], int(k), int(reps), C.byref(us), C.byref(nb),
+                                  _stream_ptr(stream)), "gmrf_kernel_bench")
+    return {"kernel": kernel, "avg_us": us.value, "bytes": nb.value,
+            "achieved_gbs": nb.value / (us.value * 1e-6) / 1e9}
 
 
 def set_hbm_budget(nbytes):

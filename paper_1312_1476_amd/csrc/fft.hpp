@@ -34,6 +34,7 @@ struct FftPlan {
 gmrf_status fft_plan_create(FftPlan& p, int N1, int N2);
 void fft_plan_destroy(FftPlan& p);
 int fft_col_blocks(const FftPlan& p);
+int fft_col_blocks_for(const FftPlan& p, int storage);   // alpha partials per field
 
 // Y = M^{-1/2} X for k real fields (storage T); tmp holds k packed spectra.
 template <typename T>
@@ -48,11 +49,20 @@ template <typename T>
 void fft_forward_init_probes(const FftPlan& p, uint64_t seed, const int8_t* probes, T* real_tmp, T* V0, T* tmp,
                              const LzState& S, int k, hipStream_t st);
 
-// Opener + operator of iteration j in the spectral basis:
-//   q_hat = Lambda^{-1/2} F Q F^H Lambda^{-1/2} v_hat_j - beta_{j-1} v_hat_{j-1},  alpha partials.
+// Opener + operator of iteration j in the spectral basis, with A = I - M^{-1/2} D M^{-1/2}
+// (D = M - Q, nonzero only next to the boundary; the same A without the cancellation that
+// forming Q u of a smooth u = M^{-1/2} v costs in FP32):
+//   q_hat = v_hat_j - Lambda^{-1/2} F D F^H Lambda^{-1/2} v_hat_j - beta_{j-1} v_hat_{j-1},
+// plus the alpha partials.
 template <typename T>
 void fft_lanczos_operator(const FftPlan& p, const StencilGeom& g, int order, const void* mult, const T* Xj,
                           const T* Xprev, T* Qb, T* F1, T* F2, const LzState& S, int j, int k, hipStream_t st);
+
+// One column pass on its own (kernel timing): forward = 1 is the operator's second half with
+// the Lanczos epilogue, forward = 0 the first half that opens iteration j.
+template <typename T>
+void fft_col_pass_lz(const FftPlan& p, int forward, const void* mult, const T* in, T* out, const T* Xj,
+                     const T* Xprev, const LzState& S, int j, int k, hipStream_t st);
 
 // X (FP64, real, n x k) = F^H Lambda^{-1/2} U_hat for the combined spectral vectors U_hat.
 template <typename T>

@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -293,12 +294,13 @@ static gmrf_status build_precond(gmrf_op* Q) {
   const int N1 = (int)Q->shape[1], N2 = (int)Q->shape[2];
   const int H = N2 / 2;
   std::vector<double> mu1(N1), mu2(N2);
+  // mu(k) = mu(N - k) exactly: evaluate at min(k, N - k)
   for (int k = 0; k < N1; ++k) {
-    const double s = std::sin(M_PI * (double)k / N1);
+    const double s = std::sin(M_PI * (double)std::min(k, N1 - k) / N1);
     mu1[k] = 4.0 * s * s;
   }
   for (int k = 0; k < N2; ++k) {
-    const double s = std::sin(M_PI * (double)k / N2);
+    const double s = std::sin(M_PI * (double)std::min(k, N2 - k) / N2);
     mu2[k] = 4.0 * s * s;
   }
   auto lam = [&](int k1, int k2) {
@@ -362,7 +364,7 @@ Sizes sizes_for(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3) 
   Sizes z{};
   z.L = (long)Q->n;  // packed half spectrum has exactly n reals too
   z.slots = ring3 ? 3 : m_max + 1;
-  if (Q->precond) z.Pa = fft_col_blocks(Q->plan);
+  if (Q->precond) z.Pa = fft_col_blocks_for(Q->plan, Q->storage);
   else z.Pa = Q->kind == 0 ? stencil_blocks(Q->geom) : csr_blocks((long)Q->n);
   z.Pb = ew_blocks(z.L);
   z.pstride = std::max(z.Pa, z.Pb);
@@ -765,4 +767,82 @@ extern "C" gmrf_status gmrf_tridiag_log_e1(const double* alpha, const double* be
   launch_tri_log(alpha, ld, 0, beta, ld, 0, m, 0, nullptr, out, 1, status, k, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return GMRF_OK;
+}
+
+// ---- single-kernel timing (for the roofline of the step's dominant kernels) ----------------------------
+// which: 0 = lattice/CSR operator Y = Q X (SpMM over k columns, storage dtype)
+//        1 = spectral column pass, forward, with the Lanczos epilogue (preconditioned step)
+//        2 = spectral column pass, inverse, opening the iteration (preconditioned step)
+//        3 = update w = q - alpha v (any path)
+// Buffers are allocated before the first event; `reps` launches run between two HIP events
+// recorded on `stream`.  bytes = algorithmic bytes of one launch (each input read once, each
+// output written once).
+template <typename T>
+static gmrf_status kernel_bench_impl(const gmrf_op* Q, int which, int k, int reps, double* avg_us, double* bytes,
+                                     hipStream_t st) {
+  Workspace ws(st);
+  Run<T> R;
+  R.Q = Q;
+  R.k = k;
+  R.m_max = 4;
+  R.reorth = 0;
+  R.tol = 0.0;
+  R.st = st;
+  gmrf_status s = setup<T>(R, ws);
+  if (s != GMRF_OK) return s;
+  // beta_j = 1, partial sums = 1: every column active, no stop decision triggers
+  {
+    std::vector<double> ones((size_t)k * (R.m_max + 2), 1.0);
+    HIP_TRY(hipMemcpyAsync(R.S.beta, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, st));
+    std::vector<double> pones((size_t)k * R.z.pstride, 1.0);
+    HIP_TRY(hipMemcpyAsync(R.S.part_b, pones.data(), pones.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(R.S.part_a, pones.data(), pones.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  const size_t vb = (size_t)k * R.z.vec_bytes;
+  std::function<void()> launch;
+  double b = 0.0;
+  const void* mult = Q->storage == GMRF_F64 ? (const void*)Q->mult64 : (const void*)Q->mult32;
+  if (which == 0) {
+    launch = [&]() { op_apply_plain<T>(Q, R.slot(0), R.Qb, k, st); };
+    b = 2.0 * vb + (Q->kind == 1 ? (double)Q->resident_bytes : 0.0);
+  } else if (which == 1 || which == 2) {
+    if (!Q->precond) return fail(GMRF_EINVAL, "kernel %d needs circulant preconditioning", which);
+    if (which == 1) {
+      launch = [&]() { fft_col_pass_lz<T>(Q->plan, 1, mult, R.F2, R.Qb, R.slot(1), R.slot(0), R.S, 2, k, st); };
+      b = 4.0 * vb;   // read F2, v_j, v_{j-1}; write q
+    } else {
+      launch = [&]() { fft_col_pass_lz<T>(Q->plan, 0, mult, R.slot(0), R.F1, nullptr, nullptr, R.S, 1, k, st); };
+      b = 2.0 * vb;   // read v_j; write C1
+    }
+  } else if (which == 3) {
+    launch = [&]() { launch_update<T>(R.Qb, R.slot(0), R.slot(1), R.z.L, 1, 1, R.S, st); };
+    b = 3.0 * vb;
+  } else {
+    return fail(GMRF_EINVAL, "unknown kernel id %d", which);
+  }
+  for (int i = 0; i < 3; ++i) launch();
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, st));
+  for (int i = 0; i < reps; ++i) launch();
+  HIP_TRY(hipEventRecord(e1, st));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(hipGetLastError());
+  *avg_us = 1000.0 * ms / reps;
+  *bytes = b;
+  return GMRF_OK;
+}
+
+extern "C" gmrf_status gmrf_kernel_bench(const gmrf_op* Q, int which, int64_t k, int32_t reps, double* avg_us,
+                                         double* bytes, void* stream) {
+  if (!Q || !avg_us || !bytes || k < 1 || k > 65535 || reps < 1) return fail(GMRF_EINVAL, "bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  if (Q->storage == GMRF_F64) return kernel_bench_impl<double>(Q, which, (int)k, reps, avg_us, bytes, st);
+  return kernel_bench_impl<float>(Q, which, (int)k, reps, avg_us, bytes, st);
 }

@@ -26,6 +26,7 @@ void launch_rademacher_i8(uint64_t seed, long n, int nprobes, int8_t* out, hipSt
 template <typename T> void launch_update(const T* Qb, const T* Vj, T* W, long L, int j, int with_norm, const LzState& S, hipStream_t st);
 void launch_hutchinson_aggregate(const double* g, const double* beta, int ldb, int np, double shift, double* out, hipStream_t st);
 void launch_finalize(const LzState& S, hipStream_t st);
+template <typename T> void launch_norm_partials(const T* V0, long L, const LzState& S, hipStream_t st);
 template <typename T> void launch_reorth(T* V, long L, int j, double* part_h, double* h, int hstride, const LzState& S, hipStream_t st);
 template <typename T, typename OutT> void launch_combine(const T* V, long L, const double* y, int ldy, OutT* out, long old, const LzState& S, hipStream_t st);
 
@@ -33,6 +34,8 @@ template <typename T, typename OutT> void launch_combine(const T* V, long L, con
 void stencil_geom_tiles(StencilGeom& g, int dim);
 int stencil_blocks(const StencilGeom& g);
 template <typename T> void launch_stencil(const StencilGeom& g, int order, int dim, bool lz, const T* X, long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k, hipStream_t st);
+template <typename T> void launch_stencil_active(const StencilGeom& g, int order, const T* X, T* Y, const int* active, int k, hipStream_t st);
+template <typename T> void launch_bcorr(const StencilGeom& g, int order, const T* X, T* Y, const int* active, int k, hipStream_t st);
 int csr_blocks(long n);
 template <typename T> void launch_csr(long n, const int64_t* rp, const int32_t* ci, const T* va, bool lz, const T* X, long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k, hipStream_t st);
 

@@ -151,6 +151,24 @@ __global__ __launch_bounds__(kEwThreads) void k_update(const T* __restrict__ Qb,
   }
 }
 
+// ---- weighted ||v||^2 partials of slot 0 (after an FFT-based init) ------------------------------
+template <typename T>
+__global__ __launch_bounds__(kEwThreads) void k_norm_partials(const T* __restrict__ V0, long L, LzState S) {
+  __shared__ double lds[kEwThreads / kWave];
+  const int r = blockIdx.y;
+  const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
+  double acc = 0.0;
+  EW_LOOP(q) {
+    const long e = base + (long)q * kEwThreads;
+    if (e < L) {
+      const double t = (double)V0[(size_t)r * L + e];
+      acc += ip_weight(S, e) * t * t;
+    }
+  }
+  const double s = block_sum<kEwThreads>(acc, lds);
+  if (threadIdx.x == 0) S.part_b[(size_t)r * S.pstride + blockIdx.x] = s;
+}
+
 // ---- closes runs that reached m_max ----------------------------------------------------------
 __global__ __launch_bounds__(256) void k_finalize(LzState S) {
   __shared__ double lds[256 / kWave];
@@ -355,6 +373,10 @@ template <typename T>
 void launch_update(const T* Qb, const T* Vj, T* W, long L, int j, int with_norm, const LzState& S, hipStream_t st) {
   hipLaunchKernelGGL(k_update<T>, ew_grid(L, S.k), dim3(kEwThreads), 0, st, Qb, Vj, W, L, j, with_norm, S);
 }
+template <typename T>
+void launch_norm_partials(const T* V0, long L, const LzState& S, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm_partials<T>, ew_grid(L, S.k), dim3(kEwThreads), 0, st, V0, L, S);
+}
 void launch_finalize(const LzState& S, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(S.k), dim3(256), 0, st, S);
 }
@@ -380,6 +402,7 @@ void launch_combine(const T* V, long L, const double* y, int ldy, OutT* out, lon
   template void launch_init_from_i8<T>(const int8_t*, long, T*, const LzState&, hipStream_t);      \
   template void launch_init_rademacher<T>(uint64_t, long, T*, const LzState&, hipStream_t);        \
   template void launch_update<T>(const T*, const T*, T*, long, int, int, const LzState&, hipStream_t); \
+  template void launch_norm_partials<T>(const T*, long, const LzState&, hipStream_t);              \
   template void launch_reorth<T>(T*, long, int, double*, double*, int, const LzState&, hipStream_t); \
   template void launch_combine<T, double>(const T*, long, const double*, int, double*, long,       \
                                           const LzState&, hipStream_t);
