@@ -124,6 +124,18 @@ def main():
         dtl = (time.perf_counter() - t0) / max(1, args.steps // 2)
         extra[name] = {"samples_per_s": round(k / dtl, 2), "ms_per_step": round(1000 * dtl, 3),
                        "m_used": il[0]["m_used"], "rho": il[0]["rel_residual"], "x_col0": Xl[0].cpu().numpy()}
+    # plain single-sample FP64 Lanczos on the same operator and stopping rule (k = 1)
+    Z1 = Z[:1].contiguous()
+    op64.sample(Z1, tol=TOL_HEADLINE, m_max=M_MAX_HEADLINE)
+    torch.cuda.synchronize()
+    nplain = 4
+    t0 = time.perf_counter()
+    for r in range(nplain):
+        op64.sample(Z[r:r + 1].contiguous(), tol=TOL_HEADLINE, m_max=M_MAX_HEADLINE)
+    torch.cuda.synchronize()
+    dtp = (time.perf_counter() - t0) / nplain
+    result["plain_single_sample_fp64"] = {"samples_per_s": round(1.0 / dtp, 2), "ms_per_sample": round(1000 * dtp, 3),
+                                          "batched_speedup": round((k / dt) * dtp, 2)}
     # FP32 storage with the headline stopping rule (reaches its accuracy floor)
     step(op32, TOL_HEADLINE, M_MAX_HEADLINE)
     torch.cuda.synchronize()

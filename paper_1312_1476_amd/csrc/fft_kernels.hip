@@ -398,6 +398,230 @@ static void cols(const FftPlan& p, const T* in, T* out, const T* mult, T scale, 
                      (const C2<T>*)Xprev);
 }
 
+
+// ---- band pass: packed row spectra of u -> packed row spectra of D u --------------------------------
+// Replaces inverse row FFT + boundary correction + forward row FFT.  D = M - Q (M the periodic
+// version of Q) is nonzero only within one point of the boundary, so for interior rows
+// r = 2..N1-3 the row of D u is supported on columns {0, 1, N2-2, N2-1} and, with
+// e_r = u(r,0) - u(r,N2-1),
+//   order 1:  d0 = tau e_r,  d1 = 0
+//   order 2:  d0 = tau [K_f(Eu)(r,0) + K_p u(r,0) - K_p u(r,N2-1)],  d1 = -tau e_r,
+// with D u(r, N2-2) = -d1 and D u(r, N2-1) = -d0.  Such a row needs u only at those 4 columns
+// of rows r-1..r+1, evaluated straight from the half spectrum
+//   u[t] = X0 + (-1)^t X_{N2/2} + 2 sum_{c=1}^{N2/2-1} Re(X_c e^{+2 pi i c t / N2}),
+// and its forward transform is closed form: X_0 = 0, X_{N2/2} = 2 d0 - 2 d1,
+//   X_c = d0 (1 - conj w^c) + d1 (w^c - conj w^{2c}),  w = e^{-2 pi i / N2}.
+// Block 0 of each field handles the edge rows {0, 1, N1-2, N1-1} (full rows, y-wrap terms):
+// inverse FFTs of rows {0, 1, 2, N1-3, N1-2, N1-1} into global scratch, D u there by its
+// definition D u = tau [K_f (E u) + E (K_p u)] (order 2; tau E u for order 1), forward FFTs.
+constexpr int kBandRows = 14;   // interior rows per block (16 waves: 14 rows + 2 halo rows)
+
+template <typename T>
+__device__ __forceinline__ T band_u(const T* U, int N1, int N2, int r, int c) {
+  // scratch rows: 0, 1, 2, N1-3, N1-2, N1-1 -> slots 0..5
+  const int s = r <= 2 ? r : r - (N1 - 6);
+  return U[(size_t)s * N2 + ((c % N2) + N2) % N2];
+}
+
+template <typename T>
+__device__ T edge_Kp(const T* U, int N1, int N2, int r, int c, T k2) {
+  const T v = band_u(U, N1, N2, r, c);
+  const int rm = (r - 1 + N1) % N1, rp = (r + 1) % N1;
+  return k2 * v + (v - band_u(U, N1, N2, r, c - 1)) + (v - band_u(U, N1, N2, r, c + 1)) +
+         (v - band_u(U, N1, N2, rm, c)) + (v - band_u(U, N1, N2, rp, c));
+}
+
+template <typename T>
+__device__ T edge_Eu(const T* U, int N1, int N2, int r, int c) {
+  const T v = band_u(U, N1, N2, r, c);
+  T acc = (T)0;
+  if (c == 0) acc += v - band_u(U, N1, N2, r, N2 - 1);
+  if (c == N2 - 1) acc += v - band_u(U, N1, N2, r, 0);
+  if (r == 0) acc += v - band_u(U, N1, N2, N1 - 1, c);
+  if (r == N1 - 1) acc += v - band_u(U, N1, N2, 0, c);
+  return acc;
+}
+
+template <typename T>
+__device__ T edge_EKp(const T* U, int N1, int N2, int r, int c, T k2) {
+  const T v = edge_Kp(U, N1, N2, r, c, k2);
+  T acc = (T)0;
+  if (c == 0) acc += v - edge_Kp(U, N1, N2, r, N2 - 1, k2);
+  if (c == N2 - 1) acc += v - edge_Kp(U, N1, N2, r, 0, k2);
+  if (r == 0) acc += v - edge_Kp(U, N1, N2, N1 - 1, c, k2);
+  if (r == N1 - 1) acc += v - edge_Kp(U, N1, N2, 0, c, k2);
+  return acc;
+}
+
+template <typename T>
+__device__ T edge_KfEu(const T* U, int N1, int N2, int r, int c, T k2) {
+  const T e = edge_Eu(U, N1, N2, r, c);
+  T acc = k2 * e;
+  if (c > 0) acc += e - edge_Eu(U, N1, N2, r, c - 1);
+  if (c < N2 - 1) acc += e - edge_Eu(U, N1, N2, r, c + 1);
+  if (r > 0) acc += e - edge_Eu(U, N1, N2, r - 1, c);
+  if (r < N1 - 1) acc += e - edge_Eu(U, N1, N2, r + 1, c);
+  return acc;
+}
+
+template <typename T, int ORDER>
+__global__ __launch_bounds__(kFftThreads) void k_band(const C2<T>* __restrict__ in, C2<T>* __restrict__ out,
+                                                      int N1, int N2, const C2<T>* __restrict__ tw, T k2, T tau,
+                                                      T* __restrict__ scratch, const int* __restrict__ active,
+                                                      int periodic) {
+  __shared__ C2<T> buf[FftCfg<T>::ELEMS];
+  const int r = blockIdx.y;
+  if (active && !active[r]) return;
+  const int H = N2 / 2;
+  const size_t fsz = (size_t)N1 * H;
+  const C2<T>* src = in + (size_t)r * fsz;
+  C2<T>* dst = out + (size_t)r * fsz;
+  if (periodic) {
+    // a periodic Q is its own preconditioner: D = 0
+    const int ra = blockIdx.x == 0 ? 0 : 2 + (blockIdx.x - 1) * kBandRows;
+    const int rb = blockIdx.x == 0 ? 2 : min(N1 - 2, ra + kBandRows);
+    for (int idx = threadIdx.x; idx < (rb - ra) * H; idx += kFftThreads) {
+      dst[(size_t)ra * H + idx] = {(T)0, (T)0};
+      if (blockIdx.x == 0) dst[(size_t)(N1 - 2) * H + idx] = {(T)0, (T)0};
+    }
+    return;
+  }
+  if (blockIdx.x == 0) {
+    // ---- edge rows ----
+    T* U = scratch + (size_t)r * 10 * N2;     // 6 rows of u
+    T* Dr = U + (size_t)6 * N2;               // 4 rows of D u: 0, 1, N1-2, N1-1
+    const int rows_in[6] = {0, 1, 2, N1 - 3, N1 - 2, N1 - 1};
+    for (int pr = 0; pr < 3; ++pr) {
+      const C2<T>* PA = src + (size_t)rows_in[2 * pr] * H;
+      const C2<T>* PB = src + (size_t)rows_in[2 * pr + 1] * H;
+      for (int k = threadIdx.x; k < N2; k += kFftThreads) {
+        C2<T> a, b;
+        if (k == 0) { a = {PA[0].x, (T)0}; b = {PB[0].x, (T)0}; }
+        else if (k == H) { a = {PA[0].y, (T)0}; b = {PB[0].y, (T)0}; }
+        else if (k < H) { a = PA[k]; b = PB[k]; }
+        else { a = {PA[N2 - k].x, -PA[N2 - k].y}; b = {PB[N2 - k].x, -PB[N2 - k].y}; }
+        buf[k] = {a.x - b.y, a.y + b.x};
+      }
+      __syncthreads();
+      lds_fft<T, false>(buf, N2, 1, N2, 1, tw, true);
+      for (int t = threadIdx.x; t < N2; t += kFftThreads) {
+        U[(size_t)(2 * pr) * N2 + t] = buf[t].x;
+        U[(size_t)(2 * pr + 1) * N2 + t] = buf[t].y;
+      }
+      __syncthreads();
+    }
+    const int rows_out[4] = {0, 1, N1 - 2, N1 - 1};
+    for (int idx = threadIdx.x; idx < 4 * N2; idx += kFftThreads) {
+      const int q = idx / N2, c = idx % N2;
+      const int rr = rows_out[q];
+      T d;
+      if (ORDER == 1) d = tau * edge_Eu(U, N1, N2, rr, c);
+      else d = tau * (edge_KfEu(U, N1, N2, rr, c, k2) + edge_EKp(U, N1, N2, rr, c, k2));
+      Dr[(size_t)q * N2 + c] = d;
+    }
+    __syncthreads();
+    for (int pr = 0; pr < 2; ++pr) {
+      for (int t = threadIdx.x; t < N2; t += kFftThreads)
+        buf[t] = {Dr[(size_t)(2 * pr) * N2 + t], Dr[(size_t)(2 * pr + 1) * N2 + t]};
+      __syncthreads();
+      lds_fft<T, false>(buf, N2, 1, N2, 1, tw, false);
+      C2<T>* PA = dst + (size_t)rows_out[2 * pr] * H;
+      C2<T>* PB = dst + (size_t)rows_out[2 * pr + 1] * H;
+      const T h = (T)0.5;
+      for (int c = threadIdx.x; c < H; c += kFftThreads) {
+        if (c == 0) {
+          PA[0] = {buf[0].x, buf[H].x};
+          PB[0] = {buf[0].y, buf[H].y};
+        } else {
+          const C2<T> zk = buf[c], zm = buf[N2 - c];
+          PA[c] = {(zk.x + zm.x) * h, (zk.y - zm.y) * h};
+          PB[c] = {(zk.y + zm.y) * h, (zm.x - zk.x) * h};
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+  // ---- interior rows r0 .. r1-1 ----
+  T* ub = (T*)buf;   // [kBandRows + 2][4]: u at columns 0, 1, N2-2, N2-1
+  const int r0 = 2 + (blockIdx.x - 1) * kBandRows;
+  const int r1 = min(N1 - 2, r0 + kBandRows);
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  constexpr int NW = kFftThreads / kWave;
+  for (int q = wv; q < r1 - r0 + 2; q += NW) {
+    const int rr = r0 - 1 + q;
+    const C2<T>* P = src + (size_t)rr * H;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int c = lane; c < H; c += kWave) {
+      const C2<T> x = P[c];
+      if (c == 0) {
+        const double x0 = (double)x.x, xn = (double)x.y;
+        s0 += x0 + xn;          // t = 0
+        s1 += x0 - xn;          // t = 1
+        s2 += x0 + xn;          // t = N2 - 2
+        s3 += x0 - xn;          // t = N2 - 1
+      } else {
+        const C2<T> w1 = tw[c], w2 = tw[2 * c];
+        const double px = (double)x.x, py = (double)x.y;
+        s0 += 2.0 * px;
+        s1 += 2.0 * (px * (double)w1.x + py * (double)w1.y);   // Re(X conj w^c)
+        s2 += 2.0 * (px * (double)w2.x - py * (double)w2.y);   // Re(X w^{2c})
+        s3 += 2.0 * (px * (double)w1.x - py * (double)w1.y);   // Re(X w^c)
+      }
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    s3 = wave_sum(s3);
+    if (lane == 0) {
+      ub[4 * q + 0] = (T)s0;
+      ub[4 * q + 1] = (T)s1;
+      ub[4 * q + 2] = (T)s2;
+      ub[4 * q + 3] = (T)s3;
+    }
+  }
+  __syncthreads();
+  const int nr = r1 - r0;
+  for (int idx = threadIdx.x; idx < nr * H; idx += kFftThreads) {
+    const int q = idx / H + 1, c = idx % H;   // q indexes ub (row r0 - 1 + q)
+    const T u0 = ub[4 * q], u1 = ub[4 * q + 1], um2 = ub[4 * q + 2], um1 = ub[4 * q + 3];
+    const T e = u0 - um1;
+    T d0, d1;
+    if (ORDER == 1) {
+      d0 = tau * e;
+      d1 = (T)0;
+    } else {
+      const T em = ub[4 * (q - 1)] - ub[4 * (q - 1) + 3], ep = ub[4 * (q + 1)] - ub[4 * (q + 1) + 3];
+      const T kfe0 = k2 * e + e + (e - em) + (e - ep);
+      const T kp0 = k2 * u0 + (u0 - u1) + (u0 - um1) + (u0 - ub[4 * (q - 1)]) + (u0 - ub[4 * (q + 1)]);
+      const T kpm1 = k2 * um1 + (um1 - um2) + (um1 - u0) + (um1 - ub[4 * (q - 1) + 3]) + (um1 - ub[4 * (q + 1) + 3]);
+      d0 = tau * (kfe0 + kp0 - kpm1);
+      d1 = -tau * e;
+    }
+    C2<T> X;
+    if (c == 0) {
+      X = {(T)0, (T)2 * (d0 - d1)};
+    } else {
+      const C2<T> w1 = tw[c], w2 = tw[2 * c];
+      // d0 (1 - conj w1) + d1 (w1 - conj w2)
+      X = {d0 * ((T)1 - w1.x) + d1 * (w1.x - w2.x), d0 * w1.y + d1 * (w1.y + w2.y)};
+    }
+    dst[(size_t)(r0 - 1 + q) * H + c] = X;
+  }
+}
+
+template <typename T>
+static void band(const FftPlan& p, const StencilGeom& g, int order, const T* in, T* out, T* scratch,
+                 const int* active, int k, hipStream_t st) {
+  const dim3 grid(1 + (p.N1 - 4 + kBandRows - 1) / kBandRows, k);
+  if (order == 1)
+    hipLaunchKernelGGL((k_band<T, 1>), grid, dim3(kFftThreads), 0, st, (const C2<T>*)in, (C2<T>*)out, p.N1, p.N2,
+                       tw2<T>(p), (T)g.kappa2, (T)g.tau, scratch, active, g.periodic);
+  else
+    hipLaunchKernelGGL((k_band<T, 2>), grid, dim3(kFftThreads), 0, st, (const C2<T>*)in, (C2<T>*)out, p.N1, p.N2,
+                       tw2<T>(p), (T)g.kappa2, (T)g.tau, scratch, active, g.periodic);
+}
+
 template <typename T>
 void fft_apply_inv_sqrt_M(const FftPlan& p, const T* mult, const T* X, T* Y, T* tmp, int k, hipStream_t st) {
   const long n = (long)p.N1 * p.N2;
@@ -428,14 +652,13 @@ void fft_forward_init_probes(const FftPlan& p, uint64_t seed, const int8_t* prob
 
 template <typename T>
 void fft_lanczos_operator(const FftPlan& p, const StencilGeom& g, int order, const void* mult, const T* Xj,
-                          const T* Xprev, T* Qb, T* F1, T* F2, const LzState& S, int j, int k, hipStream_t st) {
+                          const T* Xprev, T* Qb, T* F1, T* F2, T* scratch, const LzState& S, int j, int k,
+                          hipStream_t st) {
   const long n = (long)p.N1 * p.N2;
   const T* m = (const T*)mult;
   // A = M^{-1/2} Q M^{-1/2} = I - M^{-1/2} D M^{-1/2} with D = M - Q supported near the boundary
   cols<T, kColInvLz>(p, Xj, F1, m, (T)(1.0 / (double)n), S, j, nullptr, nullptr, k, st);
-  rows_c2r<T, T>(p, F1, n / 2, F2, n, (T)1, S.active, k, st);
-  launch_bcorr<T>(g, order, F2, F1, S.active, k, st);
-  rows_r2c<T, T>(p, F1, n, F2, n / 2, (T)1, S.active, k, st);
+  band<T>(p, g, order, F1, F2, scratch, S.active, k, st);
   cols<T, kColFwdLz>(p, F2, Qb, m, (T)1, S, j, Xj, Xprev, k, st);
 }
 
@@ -467,7 +690,7 @@ int fft_col_blocks_for(const FftPlan& p, int storage) {
   template void fft_apply_inv_sqrt_M<T>(const FftPlan&, const T*, const T*, T*, T*, int, hipStream_t);     \
   template void fft_forward_init<T>(const FftPlan&, const double*, T*, T*, const LzState&, int, hipStream_t); \
   template void fft_forward_init_probes<T>(const FftPlan&, uint64_t, const int8_t*, T*, T*, T*, const LzState&, int, hipStream_t); \
-  template void fft_lanczos_operator<T>(const FftPlan&, const StencilGeom&, int, const void*, const T*, const T*, T*, T*, T*, const LzState&, int, int, hipStream_t); \
+  template void fft_lanczos_operator<T>(const FftPlan&, const StencilGeom&, int, const void*, const T*, const T*, T*, T*, T*, T*, const LzState&, int, int, hipStream_t); \
   template void fft_backward_output<T>(const FftPlan&, const void*, const T*, double*, T*, const LzState&, int, hipStream_t);
 INST(double)
 INST(float)

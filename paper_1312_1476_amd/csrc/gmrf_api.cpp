@@ -378,7 +378,7 @@ size_t call_bytes(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3
   Sizes z = sizes_for(Q, k, m_max, reorth, ring3);
   size_t b = (size_t)z.slots * k * z.vec_bytes;       // Krylov basis
   b += (size_t)k * z.vec_bytes;                       // q
-  if (Q->precond) b += 2 * (size_t)k * z.vec_bytes;   // FFT intermediates
+  if (Q->precond) b += 2 * (size_t)k * z.vec_bytes + (size_t)k * 10 * Q->shape[2] * 8;   // FFT intermediates
   b += (size_t)k * (m_max + 2) * 8 * 4 + (size_t)k * 16;  // scalars
   b += 2 * (size_t)k * z.pstride * 8;                 // partials
   if (reorth) b += (size_t)k * (m_max + 1) * (z.Pb + 1) * 8;
@@ -462,6 +462,7 @@ struct Run {
   T* Qb = nullptr;       // k x L
   T* F1 = nullptr;       // FFT intermediates (preconditioned)
   T* F2 = nullptr;
+  T* F3 = nullptr;       // edge-row scratch of the band pass
   double* part_h = nullptr;
   double* h = nullptr;
   bool ring3 = false;
@@ -483,6 +484,7 @@ gmrf_status setup(Run<T>& R, Workspace& ws) {
   if (Q->precond) {
     if ((s = ws.alloc((size_t)k * R.z.L, &R.F1)) != GMRF_OK) return s;
     if ((s = ws.alloc((size_t)k * R.z.L, &R.F2)) != GMRF_OK) return s;
+    if ((s = ws.alloc((size_t)k * 10 * Q->shape[2], &R.F3)) != GMRF_OK) return s;
   }
   double* dbuf;
   const size_t nd = (size_t)k * (m + 1) * 3 + (size_t)k * (m + 2) + 2 * (size_t)k * R.z.pstride;
@@ -539,7 +541,7 @@ void iterate(Run<T>& R, int j) {
   T* xp = j >= 2 ? R.slot(j - 2) : R.slot(0);
   if (Q->precond) {
     fft_lanczos_operator<T>(Q->plan, Q->geom, Q->order, Q->storage == GMRF_F64 ? (const void*)Q->mult64 : (const void*)Q->mult32,
-                            xj, xp, R.Qb, R.F1, R.F2, R.S, j, R.k, R.st);
+                            xj, xp, R.Qb, R.F1, R.F2, R.F3, R.S, j, R.k, R.st);
   } else {
     op_apply_lz<T>(Q, xj, R.Qb, xp, R.S, j, R.k, R.st);
   }

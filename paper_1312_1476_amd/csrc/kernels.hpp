@@ -34,8 +34,6 @@ template <typename T, typename OutT> void launch_combine(const T* V, long L, con
 void stencil_geom_tiles(StencilGeom& g, int dim);
 int stencil_blocks(const StencilGeom& g);
 template <typename T> void launch_stencil(const StencilGeom& g, int order, int dim, bool lz, const T* X, long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k, hipStream_t st);
-template <typename T> void launch_stencil_active(const StencilGeom& g, int order, const T* X, T* Y, const int* active, int k, hipStream_t st);
-template <typename T> void launch_bcorr(const StencilGeom& g, int order, const T* X, T* Y, const int* active, int k, hipStream_t st);
 int csr_blocks(long n);
 template <typename T> void launch_csr(long n, const int64_t* rp, const int32_t* ci, const T* va, bool lz, const T* X, long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k, hipStream_t st);
 

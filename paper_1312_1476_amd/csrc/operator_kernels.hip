@@ -144,102 +144,6 @@ __global__ __launch_bounds__(256) void k_stencil(StencilGeom g, const T* __restr
   }
 }
 
-// ---- boundary correction D = M - Q of the circulant preconditioner ----------------------------------
-// M is Q with the lattice closed into a torus.  With E = L_per - L_free (the Laplacian of the
-// wrap-around edges) and K_f = kappa2 I + L_free, K_p = K_f + E:
-//   order 1:  D = tau E
-//   order 2:  D = tau (K_p^2 - K_f^2) = tau (K_f E + E K_p),  i.e.  D u = tau [K_f (E u) + E (K_p u)].
-// Every term differences values across the wrap or acts on the boundary-supported E u, so no
-// smooth-field cancellation occurs (K_f^2 u and K_p^2 u of a smooth u are small differences of
-// large values).  D u vanishes beyond distance order-1 of the boundary; tiles there write zeros
-// without loading anything; for a periodic Q (M = Q) D is zero.  2D lattices only.
-template <typename T>
-__device__ __forceinline__ T apply_E(const T* A, int AX, int c, int gy, int gx, const StencilGeom& g) {
-  const T v = A[c];
-  T acc = (T)0;
-  if (gx == 0) acc += v - A[c - 1];            // wrap neighbour (gy, N2-1) sits in the left halo
-  if (gx == g.n2 - 1) acc += v - A[c + 1];
-  if (gy == 0) acc += v - A[c - AX];
-  if (gy == g.n1 - 1) acc += v - A[c + AX];
-  return acc;
-}
-
-template <typename T, int ORDER>
-__global__ __launch_bounds__(256) void k_bcorr(StencilGeom g, const T* __restrict__ X, T* __restrict__ Y,
-                                               const int* __restrict__ active) {
-  using TS = TileShape<2>;
-  constexpr int H = ORDER;
-  constexpr int RY = TS::TY + 2 * H, RX = TS::TX + 2 * H;
-  constexpr int QY = TS::TY + 2, QX = TS::TX + 2;
-  __shared__ T vs[RY * RX];
-  __shared__ T ps[ORDER == 2 ? QY * QX : 1];
-  __shared__ T ws[ORDER == 2 ? QY * QX : 1];
-  const int r = blockIdx.y;
-  if (active && !active[r]) return;
-  const int bid = blockIdx.x;
-  const int tx = bid % g.tiles_x, ty = bid / g.tiles_x;
-  const int x0 = tx * TS::TX, y0 = ty * TS::TY;
-  const size_t n = (size_t)g.n1 * g.n2;
-  const T* src = X + (size_t)r * n;
-  T* dst = Y + (size_t)r * n;
-  const int band = ORDER - 1;   // D u is zero farther than this from the boundary
-  // a periodic Q is its own preconditioner: D = 0
-  const bool touches = !g.periodic && (x0 <= band || y0 <= band || x0 + TS::TX - 1 >= g.n2 - 1 - band ||
-                                       y0 + TS::TY - 1 >= g.n1 - 1 - band);
-  if (!touches) {
-    for (int idx = threadIdx.x; idx < TS::TX * TS::TY; idx += 256) {
-      const int lx = idx % TS::TX, ly = idx / TS::TX;
-      const int gx = x0 + lx, gy = y0 + ly;
-      if (gx < g.n2 && gy < g.n1) dst[(size_t)gy * g.n2 + gx] = (T)0;
-    }
-    return;
-  }
-  for (int idx = threadIdx.x; idx < RY * RX; idx += 256) {
-    const int lx = idx % RX, ly = idx / RX;
-    const int gx = wrap_idx(x0 + lx - H, g.n2), gy = wrap_idx(y0 + ly - H, g.n1);
-    vs[idx] = src[(size_t)gy * g.n2 + gx];
-  }
-  __syncthreads();
-  const T k2 = (T)g.kappa2, tau = (T)g.tau;
-  StencilGeom gf = g;
-  gf.periodic = 0;
-  StencilGeom gp = g;
-  gp.periodic = 1;
-  if (ORDER == 2) {
-    // P = K_p u and W = E u on the tile + 1 box
-    for (int idx = threadIdx.x; idx < QY * QX; idx += 256) {
-      const int lx = idx % QX, ly = idx / QX;
-      const int gx = wrap_idx(x0 + lx - 1, g.n2), gy = wrap_idx(y0 + ly - 1, g.n1);
-      const int c = (ly + 1) * RX + (lx + 1);
-      ps[idx] = apply_K<T, 2>(vs, RY, RX, 0, ly + 1, lx + 1, 0, gy, gx, gp, k2);
-      ws[idx] = apply_E<T>(vs, RX, c, gy, gx, g);
-    }
-    __syncthreads();
-  }
-  for (int idx = threadIdx.x; idx < TS::TX * TS::TY; idx += 256) {
-    const int lx = idx % TS::TX, ly = idx / TS::TX;
-    const int gx = x0 + lx, gy = y0 + ly;
-    if (gx >= g.n2 || gy >= g.n1) continue;
-    T out;
-    if (ORDER == 1) {
-      out = tau * apply_E<T>(vs, RX, (ly + H) * RX + (lx + H), gy, gx, g);
-    } else {
-      const int c = (ly + 1) * QX + (lx + 1);
-      out = tau * (apply_K<T, 2>(ws, QY, QX, 0, ly + 1, lx + 1, 0, gy, gx, gf, k2) + apply_E<T>(ps, QX, c, gy, gx, g));
-    }
-    dst[(size_t)gy * g.n2 + gx] = out;
-  }
-}
-
-template <typename T>
-void launch_bcorr(const StencilGeom& g, int order, const T* X, T* Y, const int* active, int k, hipStream_t st) {
-  const dim3 grid(g.tiles_x * g.tiles_y, k);
-  if (order == 1) hipLaunchKernelGGL((k_bcorr<T, 1>), grid, dim3(256), 0, st, g, X, Y, active);
-  else hipLaunchKernelGGL((k_bcorr<T, 2>), grid, dim3(256), 0, st, g, X, Y, active);
-}
-template void launch_bcorr<double>(const StencilGeom&, int, const double*, double*, const int*, int, hipStream_t);
-template void launch_bcorr<float>(const StencilGeom&, int, const float*, float*, const int*, int, hipStream_t);
-
 // ---- CSR: one thread per row ----------------------------------------------------------------
 template <typename T, bool LZ>
 __global__ __launch_bounds__(256) void k_csr(long n, const int64_t* __restrict__ rp,
@@ -299,16 +203,6 @@ static void launch_stencil_t(const StencilGeom& g, const T* X, long xld, T* Y, l
                      X, xld, Y, yld, Xprev, S, j, active);
 }
 
-// Plain 2D application Y = Q X skipping fields whose Lanczos run has stopped.
-template <typename T>
-void launch_stencil_active(const StencilGeom& g, int order, const T* X, T* Y, const int* active, int k,
-                           hipStream_t st) {
-  const long n = (long)g.n0 * g.n1 * g.n2;
-  LzState S{};
-  if (order == 1) launch_stencil_t<T, 1, 2, false>(g, X, n, Y, n, nullptr, S, 0, k, st, active);
-  else launch_stencil_t<T, 2, 2, false>(g, X, n, Y, n, nullptr, S, 0, k, st, active);
-}
-
 template <typename T>
 void launch_stencil(const StencilGeom& g, int order, int dim, bool lz, const T* X, long xld, T* Y,
                     long yld, const T* Xprev, const LzState& S, int j, int k, hipStream_t st) {
@@ -340,10 +234,6 @@ template void launch_stencil<double>(const StencilGeom&, int, int, bool, const d
                                      long, const double*, const LzState&, int, int, hipStream_t);
 template void launch_stencil<float>(const StencilGeom&, int, int, bool, const float*, long, float*,
                                     long, const float*, const LzState&, int, int, hipStream_t);
-template void launch_stencil_active<double>(const StencilGeom&, int, const double*, double*, const int*, int,
-                                            hipStream_t);
-template void launch_stencil_active<float>(const StencilGeom&, int, const float*, float*, const int*, int,
-                                           hipStream_t);
 template void launch_csr<double>(long, const int64_t*, const int32_t*, const double*, bool,
                                  const double*, long, double*, long, const double*, const LzState&,
                                  int, int, hipStream_t);
