@@ -128,6 +128,17 @@ gmrf_status gmrf_sample_ex(const gmrf_op* Q, const double* Z, int64_t k, double 
                            int32_t m_max, int reorth, double* X, gmrf_info* info,
                            double* alpha, double* beta, void* stream);
 
+/* Uneven batch: Algorithm 1 for many independent lattice fields in one set of launches per
+ * Lanczos step (every kernel of the iteration covers all fields' columns).  Field f is
+ * ops[f] with k[f] right-hand sides; all fields share ndim, order and storage (shape, kappa2,
+ * tau and boundary may differ); no preconditioning (EUNSUPPORTED) and no reorthogonalisation.
+ * Z and X (device FP64) are the concatenation of the fields' n_f x k_f column-major blocks;
+ * info (host, may be NULL) has sum_f k[f] entries in the same order.  tol, m_max and the
+ * return value as for gmrf_sample.                                                          */
+gmrf_status gmrf_sample_batch(int32_t n_fields, const gmrf_op* const* ops, const int64_t* k,
+                              const double* Z, double tol, int32_t m_max, double* X,
+                              gmrf_info* info, void* stream);
+
 /* ---- log-determinant: Section 6 (Hutchinson + Lanczos quadrature) ---------------------- */
 
 /* log det Q ~= N^{-1} sum_p Gamma_p with Gamma_p = ||v_p||^2 e_1^T log(T_m) e_1 from m steps

@@ -18,7 +18,7 @@ from . import _abi
 from ._abi import GMRF_F32, GMRF_F64, GMRF_FREE, GMRF_PERIODIC, GmrfError, Info, check, lib
 
 __all__ = ["Operator", "rademacher", "tridiag_invsqrt_e1", "tridiag_log_e1", "set_hbm_budget",
-           "hbm_in_use", "kernel_bench", "GmrfError", "STATUS"]
+           "hbm_in_use", "kernel_bench", "sample_batch", "GmrfError", "STATUS"]
 
 STATUS = _abi.STATUS_NAMES
 
@@ -165,6 +165,35 @@ class Operator:
                                 C.byref(mean), C.byref(se), per.ctypes.data_as(C.c_void_p), _stream_ptr(stream)),
               "gmrf_logdet")
         return mean.value, se.value, per
+
+
+def sample_batch(ops, Zs, tol=1e-8, m_max=300, stream=None):
+    """Uneven batch: field f is ops[f] with right-hand sides Zs[f] ((k_f, n_f) FP64 CUDA
+    tensors).  All fields run in one set of launches per Lanczos step.  Returns ([X_f], info)
+    with info in field-then-column order."""
+    torch = _torch()
+    if len(ops) != len(Zs) or not ops:
+        raise ValueError("need one Z block per operator")
+    for op, Zf in zip(ops, Zs):
+        op._check_block(Zf, torch.float64, "Z")
+    Z = torch.cat([Zf.reshape(-1) for Zf in Zs])
+    X = torch.empty_like(Z)
+    ks = (C.c_int64 * len(ops))(*[Zf.shape[0] for Zf in Zs])
+    hs = (C.c_void_p * len(ops))(*[op._h.value for op in ops])
+    K = sum(Zf.shape[0] for Zf in Zs)
+    info = (Info * K)()
+    st = lib().gmrf_sample_batch(len(ops), hs, ks, _dptr(Z), float(tol), int(m_max), _dptr(X), info,
+                                 _stream_ptr(stream))
+    if st not in (_abi.GMRF_OK, _abi.GMRF_ENOTSPD, _abi.GMRF_EINVAL) or (
+            st == _abi.GMRF_EINVAL and not any(i.status == _abi.GMRF_EINVAL for i in info)):
+        raise GmrfError(st, "gmrf_sample_batch")
+    out, o = [], 0
+    for Zf in Zs:
+        out.append(X[o:o + Zf.numel()].view(Zf.shape))
+        o += Zf.numel()
+    infos = [dict(m_used=i.m_used, status=STATUS[i.status], rel_residual=i.rel_residual,
+                  err_bound=i.err_bound) for i in info]
+    return out, infos
 
 
 def rademacher(seed, n, n_probes, stream=None):

@@ -19,6 +19,14 @@ constexpr int kEwThreads = 256;  // elementwise kernels: threads per block
 constexpr int kEwPerThread = 8;  // elements per thread
 constexpr int kEwChunk = kEwThreads * kEwPerThread;  // elements per block
 
+// Lattice geometry as a 3D box (n0, n1, n2), n2 contiguous; 1D/2D lattices have leading 1s.
+struct StencilGeom {
+  int n0, n1, n2;
+  int periodic;
+  double kappa2, tau;
+  int tiles_x, tiles_y, tiles_z;
+};
+
 // Per-call Lanczos state, all device memory.  Index conventions (1-based j as in
 // Algorithm 1): alpha[r*(m_max+1) + j] = alpha_j, beta[r*(m_max+2) + j] = beta_j with
 // beta_0 = ||z||, dpiv[r*(m_max+1) + j] = d_j (LDL^T pivot of T_j), rho[..+ j] = rho_j.
@@ -40,7 +48,24 @@ struct LzState {
   int pstride;
   int weighted;         // 1: packed half-spectrum inner product (column 0 weight 1, else 2)
   int H;                // packed columns per spectral row (weighted mode)
+  // Uneven batches (many fields in one launch): per-column tables, all nullptr otherwise.
+  const int64_t* col_off;         // offset of column r inside a slot (default r * L)
+  const int* col_len;             // length of column r (default L)
+  const int* col_pa;              // op-kernel partials of column r (default Pa)
+  const int* col_pb;              // elementwise partials of column r (default Pb)
+  const StencilGeom* col_geom;    // lattice of column r (default: the kernel's geometry)
+  int64_t slot_stride;            // elements per Krylov slot (default k * L)
 };
+
+__device__ __forceinline__ size_t lz_off(const LzState& S, int r, long L) {
+  return S.col_off ? (size_t)S.col_off[r] : (size_t)r * (size_t)L;
+}
+__device__ __forceinline__ long lz_len(const LzState& S, int r, long L) { return S.col_len ? (long)S.col_len[r] : L; }
+__device__ __forceinline__ int lz_pa(const LzState& S, int r) { return S.col_pa ? S.col_pa[r] : S.Pa; }
+__device__ __forceinline__ int lz_pb(const LzState& S, int r) { return S.col_pb ? S.col_pb[r] : S.Pb; }
+__device__ __forceinline__ size_t lz_slot(const LzState& S, long L) {
+  return S.slot_stride ? (size_t)S.slot_stride : (size_t)S.k * (size_t)L;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -124,7 +149,7 @@ template <int NT>
 __device__ bool lz_open(const LzState& S, int r, int j, bool writer, double* lds, int* lds_flag,
                         double& s_cur, double& s_prev, double& bprev) {
   if (!block_active(S, r, lds_flag)) return false;
-  const double bsq = sum_partials<NT>(S.part_b + (size_t)r * S.pstride, S.Pb, lds);
+  const double bsq = sum_partials<NT>(S.part_b + (size_t)r * S.pstride, lz_pb(S, r), lds);
   const double b = sqrt(bsq);
   if (j == 1) {
     bool ok = (b > 0.0) && isfinite(b);

@@ -65,6 +65,7 @@ struct Pool {
   std::mutex mu;
   std::multimap<size_t, void*> free_blocks;
   size_t in_use = 0;
+  size_t cached = 0;
   size_t budget = 0;
 
   gmrf_status get(size_t bytes, void** out, size_t* actual) {
@@ -77,14 +78,22 @@ struct Pool {
       *out = it->second;
       *actual = it->first;
       in_use += it->first;
+      cached -= it->first;
       free_blocks.erase(it);
       return GMRF_OK;
+    }
+    // cached blocks count against the budget: release them before allocating fresh memory
+    if (budget && in_use + cached + bytes > budget) {
+      for (auto& kv : free_blocks) (void)hipFree(kv.second);
+      free_blocks.clear();
+      cached = 0;
     }
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
       (void)hipGetLastError();
       for (auto& kv : free_blocks) (void)hipFree(kv.second);
       free_blocks.clear();
+      cached = 0;
       if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return fail(GMRF_ENOMEM, "hipMalloc of %zu B failed", bytes);
@@ -100,6 +109,7 @@ struct Pool {
   void put(void* p, size_t bytes) {
     std::lock_guard<std::mutex> lk(mu);
     free_blocks.emplace(bytes, p);
+    cached += bytes;
     in_use -= std::min(in_use, bytes);
   }
 };
@@ -847,4 +857,153 @@ extern "C" gmrf_status gmrf_kernel_bench(const gmrf_op* Q, int which, int64_t k,
   hipStream_t st = (hipStream_t)stream;
   if (Q->storage == GMRF_F64) return kernel_bench_impl<double>(Q, which, (int)k, reps, avg_us, bytes, st);
   return kernel_bench_impl<float>(Q, which, (int)k, reps, avg_us, bytes, st);
+}
+
+// ---- uneven batch: many fields, one set of launches per Lanczos step ----------------------------------
+template <typename T>
+static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const int64_t* kf, const double* Z, double tol,
+                                     int m_max, double* X, gmrf_info* info, hipStream_t st) {
+  const gmrf_op* Q0 = ops[0];
+  std::vector<int64_t> off;
+  std::vector<int> len, pa, pb, field;
+  std::vector<StencilGeom> geom;
+  int64_t tot = 0;
+  int max_tiles = 1;
+  long max_len = 1;
+  for (int f = 0; f < nf; ++f) {
+    const gmrf_op* Q = ops[f];
+    const int tiles = stencil_blocks(Q->geom);
+    max_tiles = std::max(max_tiles, tiles);
+    max_len = std::max<long>(max_len, (long)Q->n);
+    for (int64_t r = 0; r < kf[f]; ++r) {
+      off.push_back(tot);
+      len.push_back((int)Q->n);
+      pa.push_back(tiles);
+      pb.push_back(ew_blocks((long)Q->n));
+      geom.push_back(Q->geom);
+      field.push_back(f);
+      tot += Q->n;
+    }
+  }
+  const int K = (int)off.size();
+  Workspace ws(st);
+  gmrf_status s;
+  T *V, *Qb;
+  if ((s = ws.alloc((size_t)(m_max + 1) * tot, &V)) != GMRF_OK) return s;
+  if ((s = ws.alloc((size_t)tot, &Qb)) != GMRF_OK) return s;
+  const int pstride = std::max(max_tiles, ew_blocks(max_len));
+  double* dbuf;
+  const size_t nd = (size_t)K * (m_max + 1) * 3 + (size_t)K * (m_max + 2) + 2 * (size_t)K * pstride;
+  if ((s = ws.alloc(nd, &dbuf)) != GMRF_OK) return s;
+  int* ibuf;
+  if ((s = ws.alloc((size_t)6 * K, &ibuf)) != GMRF_OK) return s;
+  int64_t* doff;
+  if ((s = ws.alloc((size_t)K, &doff)) != GMRF_OK) return s;
+  StencilGeom* dgeom;
+  if ((s = ws.alloc((size_t)K, &dgeom)) != GMRF_OK) return s;
+  LzState S{};
+  S.k = K;
+  S.m_max = m_max;
+  S.tol = tol;
+  S.alpha = dbuf;
+  S.dpiv = S.alpha + (size_t)K * (m_max + 1);
+  S.rho = S.dpiv + (size_t)K * (m_max + 1);
+  S.beta = S.rho + (size_t)K * (m_max + 1);
+  S.part_a = S.beta + (size_t)K * (m_max + 2);
+  S.part_b = S.part_a + (size_t)K * pstride;
+  S.m_used = ibuf;
+  S.status = ibuf + K;
+  S.active = ibuf + 2 * K;
+  int* dlen = ibuf + 3 * K;
+  int* dpa = ibuf + 4 * K;
+  int* dpb = ibuf + 5 * K;
+  S.Pa = max_tiles;
+  S.Pb = ew_blocks(max_len);
+  S.pstride = pstride;
+  S.col_off = doff;
+  S.col_len = dlen;
+  S.col_pa = dpa;
+  S.col_pb = dpb;
+  S.col_geom = dgeom;
+  S.slot_stride = tot;
+  HIP_TRY(hipMemsetAsync(dbuf, 0, nd * sizeof(double), st));
+  HIP_TRY(hipMemsetAsync(ibuf, 0, 2 * K * sizeof(int), st));
+  HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)S.active, 1, K, st));
+  HIP_TRY(hipMemcpyAsync(doff, off.data(), K * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(dlen, len.data(), K * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(dpa, pa.data(), K * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(dpb, pb.data(), K * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(dgeom, geom.data(), K * sizeof(StencilGeom), hipMemcpyHostToDevice, st));
+  auto slot = [&](int t) { return V + (size_t)t * tot; };
+  launch_init_from_f64<T>(Z, 0, max_len, slot(0), S, st);
+  int* pbuf = poll_buffer(K);
+  if (!pbuf) return fail(GMRF_ENOMEM, "pinned host buffer allocation failed");
+  int poll = 8;
+  for (int j = 1; j <= m_max; ++j) {
+    launch_stencil_batch<T>(Q0->order, Q0->dim, max_tiles, slot(j - 1), Qb, j >= 2 ? slot(j - 2) : slot(0), S, j, st);
+    launch_update<T>(Qb, slot(j - 1), slot(j), max_len, j, 1, S, st);
+    if (j % poll == 0 && j < m_max) {
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(pbuf, S.active, K * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      bool any = false;
+      for (int r = 0; r < K; ++r) any |= pbuf[r] != 0;
+      if (!any) break;
+      poll = std::min(poll * 2, 32);
+    }
+  }
+  launch_finalize(S, st);
+  double *y, *scr;
+  if ((s = ws.alloc((size_t)K * m_max, &y)) != GMRF_OK) return s;
+  if ((s = ws.alloc(tri_scratch_doubles(K, m_max), &scr)) != GMRF_OK) return s;
+  launch_tri_invsqrt(S.alpha, m_max + 1, 1, S.beta, m_max + 2, 1, S.m_used, 0, S.status, y, m_max, S.status, scr,
+                     m_max, K, st);
+  launch_combine<T, double>(V, max_len, y, m_max, X, 0, S, st);
+  HIP_TRY(hipGetLastError());
+  std::vector<int> mu(K), stt(K);
+  std::vector<double> rho((size_t)K * (m_max + 1));
+  HIP_TRY(hipMemcpyAsync(mu.data(), S.m_used, K * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(stt.data(), S.status, K * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(rho.data(), S.rho, rho.size() * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  gmrf_status ret = GMRF_OK;
+  for (int r = 0; r < K; ++r) {
+    const gmrf_op* Q = ops[field[r]];
+    double lam_lb = NAN;
+    if (Q->kappa2 > 0.0) lam_lb = Q->order == 1 ? Q->tau * Q->kappa2 : Q->tau * Q->kappa2 * Q->kappa2;
+    const int m = mu[r];
+    const double rr = rho[(size_t)r * (m_max + 1) + std::max(m, 0)];
+    if (info) {
+      info[r].m_used = m;
+      info[r].status = stt[r];
+      info[r].rel_residual = m > 0 ? rr : 0.0;
+      info[r].err_bound = (m > 0 && std::isfinite(lam_lb)) ? rr / std::sqrt(lam_lb) : NAN;
+    }
+    if (stt[r] == kENOTSPD) ret = GMRF_ENOTSPD;
+    if (stt[r] == kEINVAL && ret == GMRF_OK) ret = GMRF_EINVAL;
+  }
+  if (ret != GMRF_OK) fail(ret, "at least one column is not positive definite or not finite (see info)");
+  return ret;
+}
+
+extern "C" gmrf_status gmrf_sample_batch(int32_t n_fields, const gmrf_op* const* ops, const int64_t* k,
+                                         const double* Z, double tol, int32_t m_max, double* X, gmrf_info* info,
+                                         void* stream) {
+  if (n_fields < 1 || !ops || !k || !Z || !X) return fail(GMRF_EINVAL, "bad arguments");
+  if (m_max < 1 || m_max > tri_max_m()) return fail(GMRF_EINVAL, "m_max must be in 1..%d", tri_max_m());
+  if (!std::isfinite(tol)) return fail(GMRF_EINVAL, "tol must be finite");
+  int64_t K = 0;
+  for (int f = 0; f < n_fields; ++f) {
+    const gmrf_op* Q = ops[f];
+    if (!Q) return fail(GMRF_EINVAL, "field %d: NULL operator", f);
+    if (Q->kind != 0 || Q->precond) return fail(GMRF_EUNSUPPORTED, "field %d: batches take lattice operators without preconditioning", f);
+    if (Q->ndim != ops[0]->ndim || Q->order != ops[0]->order || Q->storage != ops[0]->storage)
+      return fail(GMRF_EINVAL, "field %d: all fields must share ndim, order and storage", f);
+    if (k[f] < 1) return fail(GMRF_EINVAL, "field %d: k must be >= 1", f);
+    K += k[f];
+  }
+  if (K > 65535) return fail(GMRF_EINVAL, "at most 65535 columns per batch");
+  hipStream_t st = (hipStream_t)stream;
+  if (ops[0]->storage == GMRF_F64) return sample_batch_impl<double>(n_fields, ops, k, Z, tol, m_max, X, info, st);
+  return sample_batch_impl<float>(n_fields, ops, k, Z, tol, m_max, X, info, st);
 }

@@ -8,14 +8,6 @@
 
 namespace gmrf {
 
-// Lattice geometry as a 3D box (n0, n1, n2), n2 contiguous; 1D/2D lattices have leading 1s.
-struct StencilGeom {
-  int n0, n1, n2;
-  int periodic;
-  double kappa2, tau;
-  int tiles_x, tiles_y, tiles_z;
-};
-
 // lanczos_kernels.hip
 int ew_blocks(long L);
 int rademacher_blocks(long n);
@@ -34,6 +26,7 @@ template <typename T, typename OutT> void launch_combine(const T* V, long L, con
 void stencil_geom_tiles(StencilGeom& g, int dim);
 int stencil_blocks(const StencilGeom& g);
 template <typename T> void launch_stencil(const StencilGeom& g, int order, int dim, bool lz, const T* X, long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k, hipStream_t st);
+template <typename T> void launch_stencil_batch(int order, int dim, int max_tiles, const T* X, T* Y, const T* Xprev, const LzState& S, int j, hipStream_t st);
 int csr_blocks(long n);
 template <typename T> void launch_csr(long n, const int64_t* rp, const int32_t* ci, const T* va, bool lz, const T* X, long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k, hipStream_t st);
 

@@ -15,13 +15,15 @@ __global__ __launch_bounds__(kEwThreads) void k_init_from_f64(const double* __re
                                                               long L, T* __restrict__ V0, LzState S) {
   __shared__ double lds[kEwThreads / kWave];
   const int r = blockIdx.y;
+  const long len = lz_len(S, r, L);
+  if ((long)blockIdx.x * kEwChunk >= len) return;
   const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
-  const double* z = Z + (size_t)r * zld;
-  T* v = V0 + (size_t)r * L;
+  const double* z = Z + (S.col_off ? (size_t)S.col_off[r] : (size_t)r * zld);
+  T* v = V0 + lz_off(S, r, L);
   double acc = 0.0;
   EW_LOOP(q) {
     const long e = base + (long)q * kEwThreads;
-    if (e < L) {
+    if (e < len) {
       const T t = (T)z[e];
       v[e] = t;
       acc += ip_weight(S, e) * (double)t * (double)t;
@@ -127,18 +129,21 @@ __global__ __launch_bounds__(kEwThreads) void k_update(const T* __restrict__ Qb,
   __shared__ double lds[kEwThreads / kWave];
   __shared__ int flag[1];
   const int r = blockIdx.y;
+  const long len = lz_len(S, r, L);
+  if ((long)blockIdx.x * kEwChunk >= len) return;
   if (!block_active(S, r, flag)) return;
-  const double a = sum_partials<kEwThreads>(S.part_a + (size_t)r * S.pstride, S.Pa, lds);
+  const double a = sum_partials<kEwThreads>(S.part_a + (size_t)r * S.pstride, lz_pa(S, r), lds);
   if (blockIdx.x == 0 && threadIdx.x == 0) S.alpha[lz_ia(S, r, j)] = a;
   const double sc = 1.0 / S.beta[lz_ib(S, r, j - 1)];
-  const T* vj = Vj + (size_t)r * L;
-  T* w = W + (size_t)r * L;
-  const T* q = Qb + (size_t)r * L;
+  const size_t off = lz_off(S, r, L);
+  const T* vj = Vj + off;
+  T* w = W + off;
+  const T* q = Qb + off;
   const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
   double acc = 0.0;
   EW_LOOP(qq) {
     const long e = base + (long)qq * kEwThreads;
-    if (e < L) {
+    if (e < len) {
       const double v = (double)(T)((double)vj[e] * sc);
       const T t = (T)((double)q[e] - a * v);
       w[e] = t;
@@ -189,7 +194,7 @@ __global__ __launch_bounds__(kEwThreads) void k_reorth_dot(const T* __restrict__
   __shared__ int flag[1];
   const int r = blockIdx.y;
   if (!block_active(S, r, flag)) return;
-  const size_t vs = (size_t)S.k * L;
+  const size_t vs = lz_slot(S, L);
   const long base = (long)blockIdx.x * kEwChunk;
   const T* w = V + (size_t)j * vs + (size_t)r * L;
   for (int i = threadIdx.x; i < kEwChunk; i += kEwThreads) {
@@ -235,7 +240,7 @@ __global__ __launch_bounds__(kEwThreads) void k_reorth_update(T* __restrict__ V,
   __shared__ int flag[1];
   const int r = blockIdx.y;
   if (!block_active(S, r, flag)) return;
-  const size_t vs = (size_t)S.k * L;
+  const size_t vs = lz_slot(S, L);
   T* w = V + (size_t)j * vs + (size_t)r * L;
   const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
   double acc[kEwPerThread];
@@ -282,10 +287,14 @@ __global__ __launch_bounds__(kEwThreads) void k_combine(const T* __restrict__ V,
                                                         OutT* __restrict__ out, long old, LzState S) {
   __shared__ double cl[1024];
   const int r = blockIdx.y;
+  const long len = lz_len(S, r, L);
+  if ((long)blockIdx.x * kEwChunk >= len) return;
   const int m = S.m_used[r];
   const int st = S.status[r];
   const double beta0 = S.beta[lz_ib(S, r, 0)];
-  const size_t vs = (size_t)S.k * L;
+  const size_t vs = lz_slot(S, L);
+  const size_t voff = lz_off(S, r, L);
+  const size_t ooff = S.col_off ? (size_t)S.col_off[r] : (size_t)r * old;
   const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
   double acc[kEwPerThread];
   EW_LOOP(q) acc[q] = 0.0;
@@ -298,11 +307,11 @@ __global__ __launch_bounds__(kEwThreads) void k_combine(const T* __restrict__ V,
         cl[t] = beta0 * y[(size_t)r * ldy + t0 + t] / S.beta[lz_ib(S, r, t0 + t)];
       __syncthreads();
       for (int t = 0; t < tn; ++t) {
-        const T* vt = V + (size_t)(t0 + t) * vs + (size_t)r * L;
+        const T* vt = V + (size_t)(t0 + t) * vs + voff;
         const double ct = cl[t];
         EW_LOOP(q) {
           const long e = base + (long)q * kEwThreads;
-          if (e < L) acc[q] += ct * (double)vt[e];
+          if (e < len) acc[q] += ct * (double)vt[e];
         }
       }
     }
@@ -310,7 +319,7 @@ __global__ __launch_bounds__(kEwThreads) void k_combine(const T* __restrict__ V,
   const double nanv = __longlong_as_double(0x7ff8000000000000ll);
   EW_LOOP(q) {
     const long e = base + (long)q * kEwThreads;
-    if (e < L) out[(size_t)r * old + e] = (OutT)(bad ? nanv : acc[q]);
+    if (e < len) out[ooff + e] = (OutT)(bad ? nanv : acc[q]);
   }
 }
 
@@ -347,6 +356,7 @@ void launch_hutchinson_aggregate(const double* g, const double* beta, int ldb, i
 
 // ---- host launchers ---------------------------------------------------------------------------
 static inline dim3 ew_grid(long L, int k) { return dim3((unsigned)((L + kEwChunk - 1) / kEwChunk), (unsigned)k); }
+// in batch mode L is the longest column; shorter columns' surplus blocks return at once
 int ew_blocks(long L) { return (int)((L + kEwChunk - 1) / kEwChunk); }
 
 template <typename T>

@@ -48,7 +48,7 @@ __device__ __forceinline__ T apply_K(const T* A, int AY, int AX, int lz, int ly,
 }
 
 template <typename T, int ORDER, int DIM, bool LZ>
-__global__ __launch_bounds__(256) void k_stencil(StencilGeom g, const T* __restrict__ X, long xld,
+__global__ __launch_bounds__(256) void k_stencil(StencilGeom g0, const T* __restrict__ X, long xld,
                                                  T* __restrict__ Y, long yld,
                                                  const T* __restrict__ Xprev, LzState S, int j,
                                                  const int* __restrict__ active) {
@@ -63,6 +63,9 @@ __global__ __launch_bounds__(256) void k_stencil(StencilGeom g, const T* __restr
   __shared__ int flag[1];
 
   const int r = blockIdx.y;
+  // uneven batches: each column has its own lattice and offset; surplus tiles return
+  const StencilGeom g = (LZ && S.col_geom) ? S.col_geom[r] : g0;
+  if ((int)blockIdx.x >= g.tiles_x * g.tiles_y * g.tiles_z) return;
   double s_cur = 1.0, s_prev = 0.0, bprev = 0.0;
   if (LZ) {
     if (!lz_open<256>(S, r, j, blockIdx.x == 0, red, flag, s_cur, s_prev, bprev)) return;
@@ -72,7 +75,8 @@ __global__ __launch_bounds__(256) void k_stencil(StencilGeom g, const T* __restr
   const int bid = blockIdx.x;
   const int tx = bid % g.tiles_x, ty = (bid / g.tiles_x) % g.tiles_y, tz = bid / (g.tiles_x * g.tiles_y);
   const int x0 = tx * TS::TX, y0 = ty * TS::TY, z0 = tz * TS::TZ;
-  const T* src = X + (size_t)r * xld;
+  const size_t roff = (LZ && S.col_off) ? (size_t)S.col_off[r] : (size_t)r * xld;
+  const T* src = X + roff;
   const bool per = g.periodic != 0;
 
   for (int idx = threadIdx.x; idx < RZ * RY * RX; idx += 256) {
@@ -116,8 +120,8 @@ __global__ __launch_bounds__(256) void k_stencil(StencilGeom g, const T* __restr
     ox = 1;
   }
   const T tau = (T)g.tau;
-  T* dst = Y + (size_t)r * yld;
-  const T* prv = LZ ? Xprev + (size_t)r * xld : nullptr;
+  T* dst = Y + ((LZ && S.col_off) ? roff : (size_t)r * yld);
+  const T* prv = LZ ? Xprev + roff : nullptr;
   double acc = 0.0;
   constexpr int TP = TS::TZ * TS::TY * TS::TX;
   for (int idx = threadIdx.x; idx < TP; idx += 256) {
@@ -215,6 +219,26 @@ void launch_stencil(const StencilGeom& g, int order, int dim, bool lz, const T* 
   CASE(1, 1) CASE(1, 2) CASE(1, 3) CASE(2, 1) CASE(2, 2) CASE(2, 3)
 #undef CASE
 }
+
+// Uneven batch: S.col_geom / S.col_off describe each column's lattice; the grid covers the
+// largest field's tiles.
+template <typename T>
+void launch_stencil_batch(int order, int dim, int max_tiles, const T* X, T* Y, const T* Xprev, const LzState& S,
+                          int j, hipStream_t st) {
+  StencilGeom g{};
+#define CASEB(O, D)                                                                                          \
+  if (order == O && dim == D) {                                                                               \
+    hipLaunchKernelGGL((k_stencil<T, O, D, true>), dim3(max_tiles, S.k), dim3(256), 0, st, g, X, 0L, Y, 0L, \
+                       Xprev, S, j, (const int*)nullptr);                                                    \
+    return;                                                                                                   \
+  }
+  CASEB(1, 1) CASEB(1, 2) CASEB(1, 3) CASEB(2, 1) CASEB(2, 2) CASEB(2, 3)
+#undef CASEB
+}
+template void launch_stencil_batch<double>(int, int, int, const double*, double*, const double*, const LzState&,
+                                           int, hipStream_t);
+template void launch_stencil_batch<float>(int, int, int, const float*, float*, const float*, const LzState&, int,
+                                          hipStream_t);
 
 int csr_blocks(long n) { return (int)((n + 255) / 256); }
 

@@ -1,0 +1,110 @@
+"""Serving (continuous batching) over the C ABI: each result is identical alone and in a mix,
+admission never exceeds the HBM budget, admitted work overlaps, oversize requests are
+rejected, and a served sample matches the oracle."""
+import numpy as np
+import pytest
+
+from oracle import lanczos, lattice
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import os
+    import torch
+    from paper_1312_1476_amd import build as b
+    if not os.path.exists(b.LIB):
+        b.build()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1312_1476_amd as gm
+    from paper_1312_1476_amd import serve
+    ops = [gm.Operator.lattice((96, 80), 1, 0.05, 1.0, "free", "f32"),
+           gm.Operator.lattice((24, 20, 28), 1, 0.2, 1.0, "free", "f64"),
+           gm.Operator.lattice((128, 128), 2, 0.05, 1.0, "free", "f64").set_circulant_precond(),
+           gm.Operator.lattice((150, 150), 1, 0.01, 1.0, "free", "f64")]
+    return gm, serve, ops
+
+
+def _same_info(a, b):
+    def norm(d):
+        return {k: ("nan" if isinstance(v, float) and v != v else v) for k, v in d.items()}
+    return [norm(x) for x in a] == [norm(x) for x in b]
+
+
+def _mix(serve):
+    R = serve.ServeRequest
+    return [R(1, "sample", 0, 4, 7, tol=1e-6, m_max=300), R(2, "logdet", 1, 8, 11, m_max=40),
+            R(3, "sample", 2, 3, 5, tol=1e-8, m_max=400), R(4, "sample", 3, 8, 9, tol=1e-6, m_max=400),
+            R(5, "logdet", 2, 6, 13, m_max=60), R(6, "sample", 1, 16, 3, tol=1e-6, m_max=200),
+            R(7, "sample", 0, 32, 21, tol=1e-6, m_max=300), R(8, "logdet", 3, 4, 17, m_max=80)]
+
+
+def test_alone_equals_mix(env):
+    import torch
+    gm, serve, ops = env
+    mix = _mix(serve)
+    alone = {}
+    srv = serve.Server(ops, hbm_budget=64 << 30, workers=1).start()
+    for req in _mix(serve):
+        srv.submit(req)
+        req.done.wait()
+        assert not req.error, req.error
+        alone[req.rid] = req.result
+    srv.stop()
+    srv = serve.Server(ops, hbm_budget=64 << 30, workers=4).start()
+    for req in mix:
+        srv.submit(req)
+    for req in mix:
+        req.done.wait()
+    srv.stop()
+    assert srv.peak_busy >= 2          # requests really overlapped on the device
+    for req in mix:
+        assert not req.error, req.error
+        a = alone[req.rid]
+        if req.kind == "sample":
+            assert torch.equal(a["X"], req.result["X"]), req.rid
+            assert _same_info(a["info"], req.result["info"])
+        else:
+            assert a["logdet"] == req.result["logdet"]
+            assert np.array_equal(a["per_probe"], req.result["per_probe"])
+
+
+def test_budget_admission_and_rejection(env):
+    gm, serve, ops = env
+    probe = serve.Server(ops, hbm_budget=1 << 40)
+    reqs = _mix(serve)
+    sizes = [probe.request_bytes(r) for r in reqs]
+    budget = int(max(sizes) * 1.3)
+    srv = serve.Server(ops, hbm_budget=budget, workers=4, keep_results=False).start()
+    for req in reqs:
+        srv.submit(req)
+    big = serve.ServeRequest(99, "sample", 3, 2000, 1, m_max=1000)
+    srv.submit(big)
+    for req in reqs + [big]:
+        req.done.wait()
+    srv.stop()
+    assert all(not r.error for r in reqs)
+    assert big.error and "budget" in big.error
+    assert srv.peak_bytes <= budget
+    st = serve.stats(reqs + [big], 1.0)
+    assert st["completed"] == len(reqs) and st["rejected"] == 1
+
+
+def test_served_sample_matches_oracle(env):
+    import torch
+    gm, serve, ops = env
+    srv = serve.Server(ops, hbm_budget=64 << 30, workers=2).start()
+    req = srv.submit(serve.ServeRequest(1, "sample", 3, 2, 42, tol=1e-8, m_max=500))
+    req.done.wait()
+    srv.stop()
+    assert not req.error
+    g = torch.Generator(device="cuda")
+    g.manual_seed(42)
+    Z = torch.randn((2, ops[3].n), dtype=torch.float64, device="cuda", generator=g).cpu().numpy()
+    Q = lattice.lattice_precision((150, 150), 1, 0.01, 1.0, "free")
+    X = req.result["X"].cpu().numpy()
+    for r in range(2):
+        m = req.result["info"][r]["m_used"]
+        ref = lanczos.sample_csr(Q, Z[r], m, tol=0.0)
+        assert np.linalg.norm(X[r] - ref.x) / np.linalg.norm(ref.x) <= 1e-8
