@@ -54,17 +54,17 @@ void fft_forward_init_probes(const FftPlan& p, uint64_t seed, const int8_t* prob
 // forming Q u of a smooth u = M^{-1/2} v costs in FP32):
 //   q_hat = v_hat_j - Lambda^{-1/2} F D F^H Lambda^{-1/2} v_hat_j - beta_{j-1} v_hat_{j-1},
 // plus the alpha partials.
-// scratch: k * 10 * N2 storage elements (edge rows of the band pass).
+// scratch: fft_band_bytes(p, storage, k) bytes (band hand-off between the two column passes).
 template <typename T>
 void fft_lanczos_operator(const FftPlan& p, const StencilGeom& g, int order, const void* mult, const T* Xj,
-                          const T* Xprev, T* Qb, T* F1, T* F2, T* scratch, const LzState& S, int j, int k,
-                          hipStream_t st);
+                          const T* Xprev, T* Qb, void* scratch, const LzState& S, int j, int k, hipStream_t st);
+size_t fft_band_bytes(const FftPlan& p, int storage, int k);
 
 // One column pass on its own (kernel timing): forward = 1 is the operator's second half with
 // the Lanczos epilogue, forward = 0 the first half that opens iteration j.
 template <typename T>
-void fft_col_pass_lz(const FftPlan& p, int forward, const void* mult, const T* in, T* out, const T* Xj,
-                     const T* Xprev, const LzState& S, int j, int k, hipStream_t st);
+void fft_col_pass_lz(const FftPlan& p, int forward, const void* mult, const T* Xj, const T* Xprev, T* Qb,
+                     void* scratch, const LzState& S, int j, int k, hipStream_t st);
 
 // X (FP64, real, n x k) = F^H Lambda^{-1/2} U_hat for the combined spectral vectors U_hat.
 template <typename T>

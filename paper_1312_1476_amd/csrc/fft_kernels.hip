@@ -244,14 +244,41 @@ __device__ void apply_mult(C2<T>* buf, int nf, int c0, int N1, int H, const T* _
   __syncthreads();
 }
 
+// Band-pass hand-off between the two column passes of the preconditioned operator.
+//   pband[((rhs * N1 + row) * ntiles + tile) * 4 + t]: per column tile, the partial sums of
+//     u(row, {0, 1, N2-2, N2-1}[t]) over the tile's packed columns (written by the opener);
+//   edge_in[(rhs * 6 + q) * H + c]: packed row spectra of u for rows {0,1,2,N1-3,N1-2,N1-1};
+//   bcoef[(rhs * N1 + row) * 2 + {0,1}]: (d0, d1) of interior rows (written by the band pass);
+//   edge_out[(rhs * 4 + q) * H + c]: packed row spectra of D u for rows {0,1,N1-2,N1-1}.
+template <typename T>
+struct BandIO {
+  const C2<T>* tw2;        // N2-point twiddles
+  double* pband;
+  C2<T>* edge_in;
+  double* bcoef;
+  C2<T>* edge_out;
+};
+
+__device__ __forceinline__ int edge_in_slot(int row, int N1) {
+  return row <= 2 ? row : (row >= N1 - 3 ? row - (N1 - 6) : -1);
+}
+__device__ __forceinline__ int edge_out_slot(int row, int N1) {
+  return row <= 1 ? row : (row >= N1 - 2 ? row - (N1 - 4) : -1);
+}
+
 template <typename T, int MODE>
 __global__ __launch_bounds__(kFftThreads) void k_cols(const C2<T>* __restrict__ in, C2<T>* __restrict__ out,
                                                       int N1, int H, int nf, const C2<T>* __restrict__ tw,
                                                       const T* __restrict__ mult, T scale, LzState S, int j,
-                                                      const C2<T>* __restrict__ Xj, const C2<T>* __restrict__ Xprev) {
+                                                      const C2<T>* __restrict__ Xj, const C2<T>* __restrict__ Xprev,
+                                                      BandIO<T> bio) {
   __shared__ C2<T> buf[FftCfg<T>::ELEMS];
   __shared__ double red[kFftThreads / kWave];
   __shared__ int flag[1];
+  // per-column coefficients of the band hand-off (tiles of at most kCoefCols columns use them)
+  constexpr int kCoefCols = 64;
+  __shared__ C2<T> coefA[(MODE == kColFwdLz) ? kCoefCols : 1], coefB[(MODE == kColFwdLz) ? kCoefCols : 1];
+  __shared__ double coefW[(MODE == kColInvLz) ? 8 * kCoefCols : 1];
   const int r = blockIdx.y;
   const int c0 = blockIdx.x * nf;
   const size_t fsz = (size_t)N1 * H;   // complex values per field
@@ -267,11 +294,51 @@ __global__ __launch_bounds__(kFftThreads) void k_cols(const C2<T>* __restrict__ 
     }
   }
   const C2<T>* src = in + (size_t)r * fsz;
-  for (int idx = threadIdx.x; idx < nf * N1; idx += kFftThreads) {
-    const int k1 = idx / nf, c = idx % nf;
-    C2<T> v = src[(size_t)k1 * H + c0 + c];
-    if (MODE == kColInvLz) v = {(T)((double)v.x * s_cur), (T)((double)v.y * s_cur)};
-    buf[idx] = v;
+  const bool use_coef = nf <= kCoefCols;
+  if (MODE == kColFwdLz && bio.bcoef) {
+    // row spectra of D u: closed form X_c = d0 A_c + d1 B_c on interior rows, with
+    // A_c = 1 - conj w^c, B_c = w^c - conj w^{2c} (A_0 = 2i, B_0 = -2i covers X_{N2/2} = 2(d0 - d1));
+    // stored spectra on the edge rows
+    auto coef = [&](int cg, C2<T>& A, C2<T>& Bc) {
+      if (cg == 0) {
+        A = {(T)0, (T)2};
+        Bc = {(T)0, (T)-2};
+      } else {
+        const C2<T> w1 = bio.tw2[cg], w2 = bio.tw2[2 * cg];
+        A = {(T)1 - w1.x, w1.y};
+        Bc = {w1.x - w2.x, w1.y + w2.y};
+      }
+    };
+    if (use_coef) {
+      for (int c = threadIdx.x; c < nf; c += kFftThreads) coef(c0 + c, coefA[c], coefB[c]);
+      __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < nf * N1; idx += kFftThreads) {
+      const int k1 = idx / nf, c = idx % nf, cg = c0 + c;
+      const int q = edge_out_slot(k1, N1);
+      C2<T> v;
+      if (q >= 0) {
+        v = bio.edge_out[((size_t)r * 4 + q) * H + cg];
+      } else {
+        const double d0 = bio.bcoef[((size_t)r * N1 + k1) * 2], d1 = bio.bcoef[((size_t)r * N1 + k1) * 2 + 1];
+        C2<T> A, Bc;
+        if (use_coef) {
+          A = coefA[c];
+          Bc = coefB[c];
+        } else {
+          coef(cg, A, Bc);
+        }
+        v = {(T)(d0 * (double)A.x + d1 * (double)Bc.x), (T)(d0 * (double)A.y + d1 * (double)Bc.y)};
+      }
+      buf[idx] = v;
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < nf * N1; idx += kFftThreads) {
+      const int k1 = idx / nf, c = idx % nf;
+      C2<T> v = src[(size_t)k1 * H + c0 + c];
+      if (MODE == kColInvLz) v = {(T)((double)v.x * s_cur), (T)((double)v.y * s_cur)};
+      buf[idx] = v;
+    }
   }
   if (MODE == kColInvLz || MODE == kColInvOut) apply_mult(buf, nf, c0, N1, H, mult, scale);
   else __syncthreads();
@@ -282,6 +349,53 @@ __global__ __launch_bounds__(kFftThreads) void k_cols(const C2<T>* __restrict__ 
     lds_fft<T, true>(buf, N1, nf, 1, nf, tw, true);
   }
   if (MODE == kColFwdLz) apply_mult(buf, nf, c0, N1, H, mult, (T)1);
+  if (MODE == kColInvLz && bio.pband) {
+    // u at columns {0, 1, N2-2, N2-1} from this tile's packed columns:
+    //   X_0 + (-1)^t X_{N2/2} (column 0), 2 Re(X_c e^{+2 pi i c t / N2}) (columns c >= 1)
+    const int ntiles = gridDim.x;
+    // contribution of column cg to u(., t) is a px + b py with (a, b) = weight(cg, t)
+    auto weight = [&](int cg, int t, double& a, double& b) {
+      if (cg == 0) {
+        a = 1.0;
+        b = (t & 1) ? -1.0 : 1.0;
+      } else {
+        const C2<T> w1 = bio.tw2[cg], w2 = bio.tw2[2 * cg];
+        if (t == 0) { a = 2.0; b = 0.0; }
+        else if (t == 1) { a = 2.0 * (double)w1.x; b = 2.0 * (double)w1.y; }
+        else if (t == 2) { a = 2.0 * (double)w2.x; b = -2.0 * (double)w2.y; }
+        else { a = 2.0 * (double)w1.x; b = -2.0 * (double)w1.y; }
+      }
+    };
+    if (use_coef) {
+      for (int item = threadIdx.x; item < 4 * nf; item += kFftThreads) {
+        const int t = item / nf, c = item % nf;
+        weight(c0 + c, t, coefW[2 * item], coefW[2 * item + 1]);
+      }
+      __syncthreads();
+    }
+    for (int item = threadIdx.x; item < N1 * 4; item += kFftThreads) {
+      const int k1 = item >> 2, t = item & 3;
+      double acc = 0.0;
+      for (int c = 0; c < nf; ++c) {
+        const C2<T> x = buf[k1 * nf + c];
+        double a, b;
+        if (use_coef) {
+          a = coefW[2 * (t * nf + c)];
+          b = coefW[2 * (t * nf + c) + 1];
+        } else {
+          weight(c0 + c, t, a, b);
+        }
+        acc += a * (double)x.x + b * (double)x.y;
+      }
+      bio.pband[(((size_t)r * N1 + k1) * ntiles + blockIdx.x) * 4 + t] = acc;
+    }
+    for (int idx = threadIdx.x; idx < 6 * nf; idx += kFftThreads) {
+      const int q = idx / nf, c = idx % nf;
+      const int k1 = q < 3 ? q : N1 - 6 + q;
+      bio.edge_in[((size_t)r * 6 + q) * H + c0 + c] = buf[k1 * nf + c];
+    }
+    return;
+  }
   C2<T>* dst = out + (size_t)r * fsz;
   if (MODE == kColFwdLz) {
     const C2<T>* vj = Xj + (size_t)r * fsz;
@@ -391,235 +505,235 @@ static void rows_c2r(const FftPlan& p, const T* in, long ild_complex, Tout* out,
 }
 template <typename T, int MODE>
 static void cols(const FftPlan& p, const T* in, T* out, const T* mult, T scale, const LzState& S, int j,
-                 const T* Xj, const T* Xprev, int k, hipStream_t st) {
+                 const T* Xj, const T* Xprev, int k, hipStream_t st, BandIO<T> bio = BandIO<T>{}) {
   const int nf = col_nf<T>(p);
   hipLaunchKernelGGL((k_cols<T, MODE>), dim3(p.H / nf, k), dim3(kFftThreads), 0, st, (const C2<T>*)in,
                      (C2<T>*)out, p.N1, p.H, nf, tw1<T>(p), mult, scale, S, j, (const C2<T>*)Xj,
-                     (const C2<T>*)Xprev);
+                     (const C2<T>*)Xprev, bio);
 }
 
 
-// ---- band pass: packed row spectra of u -> packed row spectra of D u --------------------------------
-// Replaces inverse row FFT + boundary correction + forward row FFT.  D = M - Q (M the periodic
-// version of Q) is nonzero only within one point of the boundary, so for interior rows
-// r = 2..N1-3 the row of D u is supported on columns {0, 1, N2-2, N2-1} and, with
+// ---- band pass of the preconditioned operator --------------------------------------------------------
+// D = M - Q (M the periodic version of Q) is nonzero only within one point of the boundary, so for
+// interior rows r = 2..N1-3 the row of D u is supported on columns {0, 1, N2-2, N2-1} and, with
 // e_r = u(r,0) - u(r,N2-1),
 //   order 1:  d0 = tau e_r,  d1 = 0
 //   order 2:  d0 = tau [K_f(Eu)(r,0) + K_p u(r,0) - K_p u(r,N2-1)],  d1 = -tau e_r,
-// with D u(r, N2-2) = -d1 and D u(r, N2-1) = -d0.  Such a row needs u only at those 4 columns
-// of rows r-1..r+1, evaluated straight from the half spectrum
-//   u[t] = X0 + (-1)^t X_{N2/2} + 2 sum_{c=1}^{N2/2-1} Re(X_c e^{+2 pi i c t / N2}),
-// and its forward transform is closed form: X_0 = 0, X_{N2/2} = 2 d0 - 2 d1,
-//   X_c = d0 (1 - conj w^c) + d1 (w^c - conj w^{2c}),  w = e^{-2 pi i / N2}.
-// Block 0 of each field handles the edge rows {0, 1, N1-2, N1-1} (full rows, y-wrap terms):
-// inverse FFTs of rows {0, 1, 2, N1-3, N1-2, N1-1} into global scratch, D u there by its
-// definition D u = tau [K_f (E u) + E (K_p u)] (order 2; tau E u for order 1), forward FFTs.
-constexpr int kBandRows = 14;   // interior rows per block (16 waves: 14 rows + 2 halo rows)
+// D u(r, N2-2) = -d1 and D u(r, N2-1) = -d0.  Such a row needs u only at those four columns of
+// rows r-1..r+1: the opening column pass leaves their partial sums per column tile, here summed in
+// tile order.  Its forward row transform is closed form (X_0 = 0, X_{N2/2} = 2 (d0 - d1),
+// X_c = d0 (1 - conj w^c) + d1 (w^c - conj w^{2c}), w = e^{-2 pi i / N2}) and is evaluated by the
+// closing column pass.  Blocks 0 and 1 of each field handle the edge rows {0, 1} and {N1-2, N1-1}
+// (full rows, y-wrap terms): each takes the inverse FFTs of rows {0, 1, 2, N1-3, N1-2, N1-1}
+// (batched in LDS), tabulates E u and K_p u, forms D u = tau [K_f (E u) + E (K_p u)] (order 2;
+// tau E u for order 1) on its two rows and takes their forward FFT.
 
-template <typename T>
-__device__ __forceinline__ T band_u(const T* U, int N1, int N2, int r, int c) {
-  // scratch rows: 0, 1, 2, N1-3, N1-2, N1-1 -> slots 0..5
-  const int s = r <= 2 ? r : r - (N1 - 6);
-  return U[(size_t)s * N2 + ((c % N2) + N2) % N2];
+constexpr int kBandRowsPerBlock = 64;   // interior rows per band block
+
+// u(row, band column t) from the opener's per-tile partial sums, in tile order
+__device__ __forceinline__ double band_sum(const double* pb, int row, int ntiles, int t) {
+  const double* p = pb + (size_t)row * ntiles * 4 + t;
+  double s = 0.0;
+  for (int i = 0; i < ntiles; ++i) s += p[4 * i];
+  return s;
 }
 
-template <typename T>
-__device__ T edge_Kp(const T* U, int N1, int N2, int r, int c, T k2) {
-  const T v = band_u(U, N1, N2, r, c);
-  const int rm = (r - 1 + N1) % N1, rp = (r + 1) % N1;
-  return k2 * v + (v - band_u(U, N1, N2, r, c - 1)) + (v - band_u(U, N1, N2, r, c + 1)) +
-         (v - band_u(U, N1, N2, rm, c)) + (v - band_u(U, N1, N2, rp, c));
-}
-
-template <typename T>
-__device__ T edge_Eu(const T* U, int N1, int N2, int r, int c) {
-  const T v = band_u(U, N1, N2, r, c);
-  T acc = (T)0;
-  if (c == 0) acc += v - band_u(U, N1, N2, r, N2 - 1);
-  if (c == N2 - 1) acc += v - band_u(U, N1, N2, r, 0);
-  if (r == 0) acc += v - band_u(U, N1, N2, N1 - 1, c);
-  if (r == N1 - 1) acc += v - band_u(U, N1, N2, 0, c);
-  return acc;
-}
-
-template <typename T>
-__device__ T edge_EKp(const T* U, int N1, int N2, int r, int c, T k2) {
-  const T v = edge_Kp(U, N1, N2, r, c, k2);
-  T acc = (T)0;
-  if (c == 0) acc += v - edge_Kp(U, N1, N2, r, N2 - 1, k2);
-  if (c == N2 - 1) acc += v - edge_Kp(U, N1, N2, r, 0, k2);
-  if (r == 0) acc += v - edge_Kp(U, N1, N2, N1 - 1, c, k2);
-  if (r == N1 - 1) acc += v - edge_Kp(U, N1, N2, 0, c, k2);
-  return acc;
-}
-
-template <typename T>
-__device__ T edge_KfEu(const T* U, int N1, int N2, int r, int c, T k2) {
-  const T e = edge_Eu(U, N1, N2, r, c);
-  T acc = k2 * e;
-  if (c > 0) acc += e - edge_Eu(U, N1, N2, r, c - 1);
-  if (c < N2 - 1) acc += e - edge_Eu(U, N1, N2, r, c + 1);
-  if (r > 0) acc += e - edge_Eu(U, N1, N2, r - 1, c);
-  if (r < N1 - 1) acc += e - edge_Eu(U, N1, N2, r + 1, c);
-  return acc;
-}
+// Edge rows.  Slots 0..5 hold rows {0, 1, 2, N1-3, N1-2, N1-1}; the output slots 0..3 rows
+// {0, 1, N1-2, N1-1}.  E u is needed on all six rows, K_p u on the four output rows.
+__device__ __forceinline__ int slot_row(int s, int N1) { return s < 3 ? s : N1 - 6 + s; }
+__device__ __forceinline__ int row_slot(int r, int N1) { return r <= 2 ? r : r - (N1 - 6); }
 
 template <typename T, int ORDER>
-__global__ __launch_bounds__(kFftThreads) void k_band(const C2<T>* __restrict__ in, C2<T>* __restrict__ out,
-                                                      int N1, int N2, const C2<T>* __restrict__ tw, T k2, T tau,
-                                                      T* __restrict__ scratch, const int* __restrict__ active,
-                                                      int periodic) {
+__global__ __launch_bounds__(kFftThreads) void k_band(int N1, int N2, int ntiles, const C2<T>* __restrict__ tw,
+                                                      T k2, T tau, BandIO<T> bio, T* __restrict__ scratch,
+                                                      const int* __restrict__ active, int periodic) {
   __shared__ C2<T> buf[FftCfg<T>::ELEMS];
   const int r = blockIdx.y;
   if (active && !active[r]) return;
   const int H = N2 / 2;
-  const size_t fsz = (size_t)N1 * H;
-  const C2<T>* src = in + (size_t)r * fsz;
-  C2<T>* dst = out + (size_t)r * fsz;
+  C2<T>* E = bio.edge_out + (size_t)r * 4 * H;
+  double* B = bio.bcoef + (size_t)r * N1 * 2;
+  const int half = blockIdx.x < 2 ? (int)blockIdx.x : -1;   // edge block: 0 top, 1 bottom
   if (periodic) {
     // a periodic Q is its own preconditioner: D = 0
-    const int ra = blockIdx.x == 0 ? 0 : 2 + (blockIdx.x - 1) * kBandRows;
-    const int rb = blockIdx.x == 0 ? 2 : min(N1 - 2, ra + kBandRows);
-    for (int idx = threadIdx.x; idx < (rb - ra) * H; idx += kFftThreads) {
-      dst[(size_t)ra * H + idx] = {(T)0, (T)0};
-      if (blockIdx.x == 0) dst[(size_t)(N1 - 2) * H + idx] = {(T)0, (T)0};
+    if (half >= 0) {
+      for (int i = threadIdx.x; i < 2 * H; i += kFftThreads) E[(size_t)half * 2 * H + i] = {(T)0, (T)0};
+    } else {
+      const int r0 = 2 + (blockIdx.x - 2) * kBandRowsPerBlock, r1 = min(N1 - 2, r0 + kBandRowsPerBlock);
+      for (int i = threadIdx.x; i < 2 * (r1 - r0); i += kFftThreads) B[2 * r0 + i] = 0.0;
     }
     return;
   }
-  if (blockIdx.x == 0) {
-    // ---- edge rows ----
-    T* U = scratch + (size_t)r * 10 * N2;     // 6 rows of u
-    T* Dr = U + (size_t)6 * N2;               // 4 rows of D u: 0, 1, N1-2, N1-1
-    const int rows_in[6] = {0, 1, 2, N1 - 3, N1 - 2, N1 - 1};
-    for (int pr = 0; pr < 3; ++pr) {
-      const C2<T>* PA = src + (size_t)rows_in[2 * pr] * H;
-      const C2<T>* PB = src + (size_t)rows_in[2 * pr + 1] * H;
-      for (int k = threadIdx.x; k < N2; k += kFftThreads) {
-        C2<T> a, b;
-        if (k == 0) { a = {PA[0].x, (T)0}; b = {PB[0].x, (T)0}; }
-        else if (k == H) { a = {PA[0].y, (T)0}; b = {PB[0].y, (T)0}; }
-        else if (k < H) { a = PA[k]; b = PB[k]; }
-        else { a = {PA[N2 - k].x, -PA[N2 - k].y}; b = {PB[N2 - k].x, -PB[N2 - k].y}; }
-        buf[k] = {a.x - b.y, a.y + b.x};
-      }
-      __syncthreads();
-      lds_fft<T, false>(buf, N2, 1, N2, 1, tw, true);
-      for (int t = threadIdx.x; t < N2; t += kFftThreads) {
-        U[(size_t)(2 * pr) * N2 + t] = buf[t].x;
-        U[(size_t)(2 * pr + 1) * N2 + t] = buf[t].y;
-      }
-      __syncthreads();
-    }
-    const int rows_out[4] = {0, 1, N1 - 2, N1 - 1};
-    for (int idx = threadIdx.x; idx < 4 * N2; idx += kFftThreads) {
-      const int q = idx / N2, c = idx % N2;
-      const int rr = rows_out[q];
-      T d;
-      if (ORDER == 1) d = tau * edge_Eu(U, N1, N2, rr, c);
-      else d = tau * (edge_KfEu(U, N1, N2, rr, c, k2) + edge_EKp(U, N1, N2, rr, c, k2));
-      Dr[(size_t)q * N2 + c] = d;
+  if (half < 0) {
+    // ---- interior rows r0..r1-1: (d0, d1) ----
+    const int r0 = 2 + (blockIdx.x - 2) * kBandRowsPerBlock, r1 = min(N1 - 2, r0 + kBandRowsPerBlock);
+    double* ub = (double*)buf;   // [(r1 - r0 + 2) rows][4]
+    const double* pb = bio.pband + (size_t)r * N1 * ntiles * 4;
+    const int nq = r1 - r0 + 2;
+    for (int item = threadIdx.x; item < nq * 4; item += kFftThreads) {
+      const int q = item >> 2, t = item & 3;
+      ub[item] = band_sum(pb, r0 - 1 + q, ntiles, t);
     }
     __syncthreads();
-    for (int pr = 0; pr < 2; ++pr) {
-      for (int t = threadIdx.x; t < N2; t += kFftThreads)
-        buf[t] = {Dr[(size_t)(2 * pr) * N2 + t], Dr[(size_t)(2 * pr + 1) * N2 + t]};
-      __syncthreads();
-      lds_fft<T, false>(buf, N2, 1, N2, 1, tw, false);
-      C2<T>* PA = dst + (size_t)rows_out[2 * pr] * H;
-      C2<T>* PB = dst + (size_t)rows_out[2 * pr + 1] * H;
-      const T h = (T)0.5;
-      for (int c = threadIdx.x; c < H; c += kFftThreads) {
-        if (c == 0) {
-          PA[0] = {buf[0].x, buf[H].x};
-          PB[0] = {buf[0].y, buf[H].y};
-        } else {
-          const C2<T> zk = buf[c], zm = buf[N2 - c];
-          PA[c] = {(zk.x + zm.x) * h, (zk.y - zm.y) * h};
-          PB[c] = {(zk.y + zm.y) * h, (zm.x - zk.x) * h};
-        }
+    const double kk = (double)k2, tt = (double)tau;
+    for (int row = r0 + threadIdx.x; row < r1; row += kFftThreads) {
+      const double* cu = ub + 4 * (row - r0 + 1);
+      const double u0 = cu[0], u1 = cu[1], um2 = cu[2], um1 = cu[3];
+      const double e = u0 - um1;
+      double d0, d1;
+      if (ORDER == 1) {
+        d0 = tt * e;
+        d1 = 0.0;
+      } else {
+        const double a0 = cu[-4], a3 = cu[-1], b0 = cu[4], b3 = cu[7];
+        const double em = a0 - a3, ep = b0 - b3;
+        const double kfe0 = kk * e + e + (e - em) + (e - ep);
+        const double kp0 = kk * u0 + (u0 - u1) + (u0 - um1) + (u0 - a0) + (u0 - b0);
+        const double kpm1 = kk * um1 + (um1 - um2) + (um1 - u0) + (um1 - a3) + (um1 - b3);
+        d0 = tt * (kfe0 + kp0 - kpm1);
+        d1 = -tt * e;
       }
-      __syncthreads();
+      B[2 * row] = d0;
+      B[2 * row + 1] = d1;
     }
     return;
   }
-  // ---- interior rows r0 .. r1-1 ----
-  T* ub = (T*)buf;   // [kBandRows + 2][4]: u at columns 0, 1, N2-2, N2-1
-  const int r0 = 2 + (blockIdx.x - 1) * kBandRows;
-  const int r1 = min(N1 - 2, r0 + kBandRows);
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  constexpr int NW = kFftThreads / kWave;
-  for (int q = wv; q < r1 - r0 + 2; q += NW) {
-    const int rr = r0 - 1 + q;
-    const C2<T>* P = src + (size_t)rr * H;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    for (int c = lane; c < H; c += kWave) {
-      const C2<T> x = P[c];
-      if (c == 0) {
-        const double x0 = (double)x.x, xn = (double)x.y;
-        s0 += x0 + xn;          // t = 0
-        s1 += x0 - xn;          // t = 1
-        s2 += x0 + xn;          // t = N2 - 2
-        s3 += x0 - xn;          // t = N2 - 1
-      } else {
-        const C2<T> w1 = tw[c], w2 = tw[2 * c];
-        const double px = (double)x.x, py = (double)x.y;
-        s0 += 2.0 * px;
-        s1 += 2.0 * (px * (double)w1.x + py * (double)w1.y);   // Re(X conj w^c)
-        s2 += 2.0 * (px * (double)w2.x - py * (double)w2.y);   // Re(X w^{2c})
-        s3 += 2.0 * (px * (double)w1.x - py * (double)w1.y);   // Re(X w^c)
-      }
+  // ---- edge rows: block `half` produces output slots 2 half, 2 half + 1 ----
+  T* U = scratch + ((size_t)r * 2 + half) * 20 * N2;   // 6 rows u, 6 rows E u, 4 rows K_p u, 4 rows D u
+  T* EU = U + (size_t)6 * N2;
+  T* KP = EU + (size_t)6 * N2;
+  T* DU = KP + (size_t)4 * N2;
+  const C2<T>* Cin = bio.edge_in + (size_t)r * 6 * H;
+  const int np = min(3, FftCfg<T>::ELEMS / N2);   // row pairs per LDS pass
+  for (int p0 = 0; p0 < 3; p0 += np) {
+    const int npp = min(np, 3 - p0);
+    for (int idx = threadIdx.x; idx < npp * N2; idx += kFftThreads) {
+      const int pr = p0 + idx / N2, k = idx % N2;
+      const C2<T>* PA = Cin + (size_t)(2 * pr) * H;
+      const C2<T>* PB = PA + H;
+      C2<T> a, b;
+      if (k == 0) { a = {PA[0].x, (T)0}; b = {PB[0].x, (T)0}; }
+      else if (k == H) { a = {PA[0].y, (T)0}; b = {PB[0].y, (T)0}; }
+      else if (k < H) { a = PA[k]; b = PB[k]; }
+      else { a = {PA[N2 - k].x, -PA[N2 - k].y}; b = {PB[N2 - k].x, -PB[N2 - k].y}; }
+      buf[idx] = {a.x - b.y, a.y + b.x};
     }
-    s0 = wave_sum(s0);
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    s3 = wave_sum(s3);
-    if (lane == 0) {
-      ub[4 * q + 0] = (T)s0;
-      ub[4 * q + 1] = (T)s1;
-      ub[4 * q + 2] = (T)s2;
-      ub[4 * q + 3] = (T)s3;
+    __syncthreads();
+    lds_fft<T, false>(buf, N2, npp, N2, 1, tw, true);
+    for (int idx = threadIdx.x; idx < npp * N2; idx += kFftThreads) {
+      const int pr = p0 + idx / N2, t = idx % N2;
+      U[(size_t)(2 * pr) * N2 + t] = buf[idx].x;
+      U[(size_t)(2 * pr + 1) * N2 + t] = buf[idx].y;
+    }
+    __syncthreads();
+  }
+  // E u on the six rows, K_p u on the four output rows (wrap in both directions)
+  for (int idx = threadIdx.x; idx < 10 * N2; idx += kFftThreads) {
+    const int q = idx / N2, c = idx % N2;
+    const int cm = c == 0 ? N2 - 1 : c - 1, cp = c == N2 - 1 ? 0 : c + 1;
+    if (q < 6) {
+      const int row = slot_row(q, N1);
+      const T v = U[(size_t)q * N2 + c];
+      T acc = (T)0;
+      if (c == 0) acc += v - U[(size_t)q * N2 + N2 - 1];
+      if (c == N2 - 1) acc += v - U[(size_t)q * N2];
+      if (row == 0) acc += v - U[(size_t)5 * N2 + c];
+      if (row == N1 - 1) acc += v - U[c];
+      EU[(size_t)q * N2 + c] = acc;
+    } else {
+      const int o = q - 6;                         // output slot 0..3 -> rows 0, 1, N1-2, N1-1
+      const int row = o < 2 ? o : N1 - 4 + o;
+      const int s = row_slot(row, N1);
+      const int sm = row_slot(row == 0 ? N1 - 1 : row - 1, N1), sp = row_slot(row == N1 - 1 ? 0 : row + 1, N1);
+      const T v = U[(size_t)s * N2 + c];
+      KP[(size_t)o * N2 + c] = k2 * v + (v - U[(size_t)s * N2 + cm]) + (v - U[(size_t)s * N2 + cp]) +
+                               (v - U[(size_t)sm * N2 + c]) + (v - U[(size_t)sp * N2 + c]);
     }
   }
   __syncthreads();
-  const int nr = r1 - r0;
-  for (int idx = threadIdx.x; idx < nr * H; idx += kFftThreads) {
-    const int q = idx / H + 1, c = idx % H;   // q indexes ub (row r0 - 1 + q)
-    const T u0 = ub[4 * q], u1 = ub[4 * q + 1], um2 = ub[4 * q + 2], um1 = ub[4 * q + 3];
-    const T e = u0 - um1;
-    T d0, d1;
+  // D u = tau [K_f (E u) + E (K_p u)] (order 2), tau E u (order 1), on this block's two rows
+  for (int idx = threadIdx.x; idx < 2 * N2; idx += kFftThreads) {
+    const int o = 2 * half + idx / N2, c = idx % N2;
+    const int row = o < 2 ? o : N1 - 4 + o;
+    const int s = row_slot(row, N1);
+    T d;
     if (ORDER == 1) {
-      d0 = tau * e;
-      d1 = (T)0;
+      d = tau * EU[(size_t)s * N2 + c];
     } else {
-      const T em = ub[4 * (q - 1)] - ub[4 * (q - 1) + 3], ep = ub[4 * (q + 1)] - ub[4 * (q + 1) + 3];
-      const T kfe0 = k2 * e + e + (e - em) + (e - ep);
-      const T kp0 = k2 * u0 + (u0 - u1) + (u0 - um1) + (u0 - ub[4 * (q - 1)]) + (u0 - ub[4 * (q + 1)]);
-      const T kpm1 = k2 * um1 + (um1 - um2) + (um1 - u0) + (um1 - ub[4 * (q - 1) + 3]) + (um1 - ub[4 * (q + 1) + 3]);
-      d0 = tau * (kfe0 + kp0 - kpm1);
-      d1 = -tau * e;
+      const T e = EU[(size_t)s * N2 + c];
+      T kfe = k2 * e;
+      if (c > 0) kfe += e - EU[(size_t)s * N2 + c - 1];
+      if (c < N2 - 1) kfe += e - EU[(size_t)s * N2 + c + 1];
+      if (row > 0) kfe += e - EU[(size_t)row_slot(row - 1, N1) * N2 + c];
+      if (row < N1 - 1) kfe += e - EU[(size_t)row_slot(row + 1, N1) * N2 + c];
+      const T kp = KP[(size_t)o * N2 + c];
+      T ekp = (T)0;
+      if (c == 0) ekp += kp - KP[(size_t)o * N2 + N2 - 1];
+      if (c == N2 - 1) ekp += kp - KP[(size_t)o * N2];
+      if (row == 0) ekp += kp - KP[(size_t)3 * N2 + c];
+      if (row == N1 - 1) ekp += kp - KP[c];
+      d = tau * (kfe + ekp);
     }
-    C2<T> X;
+    DU[(size_t)(idx / N2) * N2 + c] = d;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < N2; t += kFftThreads) buf[t] = {DU[t], DU[(size_t)N2 + t]};
+  __syncthreads();
+  lds_fft<T, false>(buf, N2, 1, N2, 1, tw, false);
+  C2<T>* PA = E + (size_t)(2 * half) * H;
+  C2<T>* PB = PA + H;
+  const T h = (T)0.5;
+  for (int c = threadIdx.x; c < H; c += kFftThreads) {
     if (c == 0) {
-      X = {(T)0, (T)2 * (d0 - d1)};
+      PA[0] = {buf[0].x, buf[H].x};
+      PB[0] = {buf[0].y, buf[H].y};
     } else {
-      const C2<T> w1 = tw[c], w2 = tw[2 * c];
-      // d0 (1 - conj w1) + d1 (w1 - conj w2)
-      X = {d0 * ((T)1 - w1.x) + d1 * (w1.x - w2.x), d0 * w1.y + d1 * (w1.y + w2.y)};
+      const C2<T> zk = buf[c], zm = buf[N2 - c];
+      PA[c] = {(zk.x + zm.x) * h, (zk.y - zm.y) * h};
+      PB[c] = {(zk.y + zm.y) * h, (zm.x - zk.x) * h};
     }
-    dst[(size_t)(r0 - 1 + q) * H + c] = X;
   }
 }
 
 template <typename T>
-static void band(const FftPlan& p, const StencilGeom& g, int order, const T* in, T* out, T* scratch,
-                 const int* active, int k, hipStream_t st) {
-  const dim3 grid(1 + (p.N1 - 4 + kBandRows - 1) / kBandRows, k);
+static void band(const FftPlan& p, const StencilGeom& g, int order, BandIO<T> bio, T* scratch, const int* active,
+                 int k, hipStream_t st) {
+  const int ntiles = p.H / col_nf<T>(p);
+  const dim3 grid(2 + (p.N1 - 4 + kBandRowsPerBlock - 1) / kBandRowsPerBlock, k);
   if (order == 1)
-    hipLaunchKernelGGL((k_band<T, 1>), grid, dim3(kFftThreads), 0, st, (const C2<T>*)in, (C2<T>*)out, p.N1, p.N2,
-                       tw2<T>(p), (T)g.kappa2, (T)g.tau, scratch, active, g.periodic);
+    hipLaunchKernelGGL((k_band<T, 1>), grid, dim3(kFftThreads), 0, st, p.N1, p.N2, ntiles, tw2<T>(p),
+                       (T)g.kappa2, (T)g.tau, bio, scratch, active, g.periodic);
   else
-    hipLaunchKernelGGL((k_band<T, 2>), grid, dim3(kFftThreads), 0, st, (const C2<T>*)in, (C2<T>*)out, p.N1, p.N2,
-                       tw2<T>(p), (T)g.kappa2, (T)g.tau, scratch, active, g.periodic);
+    hipLaunchKernelGGL((k_band<T, 2>), grid, dim3(kFftThreads), 0, st, p.N1, p.N2, ntiles, tw2<T>(p),
+                       (T)g.kappa2, (T)g.tau, bio, scratch, active, g.periodic);
+}
+
+// device bytes of the band hand-off buffers for k fields
+template <typename T>
+static size_t band_bytes(const FftPlan& p, int k) {
+  const size_t ntiles = p.H / col_nf<T>(p);
+  return (size_t)k * ((size_t)p.N1 * ntiles * 4 * 8 + (size_t)6 * p.H * sizeof(C2<T>) + (size_t)p.N1 * 2 * 8 +
+                      (size_t)4 * p.H * sizeof(C2<T>) + (size_t)40 * p.N2 * sizeof(T));
+}
+
+template <typename T>
+static BandIO<T> band_io(const FftPlan& p, void* base, int k) {
+  const size_t ntiles = p.H / col_nf<T>(p);
+  char* b = (char*)base;
+  BandIO<T> io{};
+  io.tw2 = tw2<T>(p);
+  io.pband = (double*)b;
+  b += (size_t)k * p.N1 * ntiles * 4 * 8;
+  io.bcoef = (double*)b;
+  b += (size_t)k * p.N1 * 2 * 8;
+  io.edge_in = (C2<T>*)b;
+  b += (size_t)k * 6 * p.H * sizeof(C2<T>);
+  io.edge_out = (C2<T>*)b;
+  return io;
+}
+
+size_t fft_band_bytes(const FftPlan& p, int storage, int k) {
+  return storage == GMRF_F64 ? band_bytes<double>(p, k) : band_bytes<float>(p, k);
 }
 
 template <typename T>
@@ -652,14 +766,16 @@ void fft_forward_init_probes(const FftPlan& p, uint64_t seed, const int8_t* prob
 
 template <typename T>
 void fft_lanczos_operator(const FftPlan& p, const StencilGeom& g, int order, const void* mult, const T* Xj,
-                          const T* Xprev, T* Qb, T* F1, T* F2, T* scratch, const LzState& S, int j, int k,
-                          hipStream_t st) {
+                          const T* Xprev, T* Qb, void* scratch, const LzState& S, int j, int k, hipStream_t st) {
   const long n = (long)p.N1 * p.N2;
   const T* m = (const T*)mult;
   // A = M^{-1/2} Q M^{-1/2} = I - M^{-1/2} D M^{-1/2} with D = M - Q supported near the boundary
-  cols<T, kColInvLz>(p, Xj, F1, m, (T)(1.0 / (double)n), S, j, nullptr, nullptr, k, st);
-  band<T>(p, g, order, F1, F2, scratch, S.active, k, st);
-  cols<T, kColFwdLz>(p, F2, Qb, m, (T)1, S, j, Xj, Xprev, k, st);
+  // scratch: band hand-off buffers followed by the edge-row work rows (40 N2 per field)
+  const BandIO<T> bio = band_io<T>(p, scratch, k);
+  T* edge_rows = (T*)((char*)scratch + band_bytes<T>(p, k) - (size_t)k * 40 * p.N2 * sizeof(T));
+  cols<T, kColInvLz>(p, Xj, nullptr, m, (T)(1.0 / (double)n), S, j, nullptr, nullptr, k, st, bio);
+  band<T>(p, g, order, bio, edge_rows, S.active, k, st);
+  cols<T, kColFwdLz>(p, nullptr, Qb, m, (T)1, S, j, Xj, Xprev, k, st, bio);
 }
 
 template <typename T>
@@ -671,16 +787,17 @@ void fft_backward_output(const FftPlan& p, const void* mult, const T* U, double*
 }
 
 template <typename T>
-void fft_col_pass_lz(const FftPlan& p, int forward, const void* mult, const T* in, T* out, const T* Xj,
-                     const T* Xprev, const LzState& S, int j, int k, hipStream_t st) {
+void fft_col_pass_lz(const FftPlan& p, int forward, const void* mult, const T* Xj, const T* Xprev, T* Qb,
+                     void* scratch, const LzState& S, int j, int k, hipStream_t st) {
   const long n = (long)p.N1 * p.N2;
-  if (forward) cols<T, kColFwdLz>(p, in, out, (const T*)mult, (T)1, S, j, Xj, Xprev, k, st);
-  else cols<T, kColInvLz>(p, in, out, (const T*)mult, (T)(1.0 / (double)n), S, j, nullptr, nullptr, k, st);
+  const BandIO<T> bio = band_io<T>(p, scratch, k);
+  if (forward) cols<T, kColFwdLz>(p, nullptr, Qb, (const T*)mult, (T)1, S, j, Xj, Xprev, k, st, bio);
+  else cols<T, kColInvLz>(p, Xj, nullptr, (const T*)mult, (T)(1.0 / (double)n), S, j, nullptr, nullptr, k, st, bio);
 }
-template void fft_col_pass_lz<double>(const FftPlan&, int, const void*, const double*, double*, const double*,
-                                      const double*, const LzState&, int, int, hipStream_t);
-template void fft_col_pass_lz<float>(const FftPlan&, int, const void*, const float*, float*, const float*,
-                                     const float*, const LzState&, int, int, hipStream_t);
+template void fft_col_pass_lz<double>(const FftPlan&, int, const void*, const double*, const double*, double*,
+                                      void*, const LzState&, int, int, hipStream_t);
+template void fft_col_pass_lz<float>(const FftPlan&, int, const void*, const float*, const float*, float*,
+                                     void*, const LzState&, int, int, hipStream_t);
 
 int fft_col_blocks_for(const FftPlan& p, int storage) {
   return storage == GMRF_F64 ? col_blocks_t<double>(p) : col_blocks_t<float>(p);
@@ -690,7 +807,7 @@ int fft_col_blocks_for(const FftPlan& p, int storage) {
   template void fft_apply_inv_sqrt_M<T>(const FftPlan&, const T*, const T*, T*, T*, int, hipStream_t);     \
   template void fft_forward_init<T>(const FftPlan&, const double*, T*, T*, const LzState&, int, hipStream_t); \
   template void fft_forward_init_probes<T>(const FftPlan&, uint64_t, const int8_t*, T*, T*, T*, const LzState&, int, hipStream_t); \
-  template void fft_lanczos_operator<T>(const FftPlan&, const StencilGeom&, int, const void*, const T*, const T*, T*, T*, T*, T*, const LzState&, int, int, hipStream_t); \
+  template void fft_lanczos_operator<T>(const FftPlan&, const StencilGeom&, int, const void*, const T*, const T*, T*, void*, const LzState&, int, int, hipStream_t); \
   template void fft_backward_output<T>(const FftPlan&, const void*, const T*, double*, T*, const LzState&, int, hipStream_t);
 INST(double)
 INST(float)

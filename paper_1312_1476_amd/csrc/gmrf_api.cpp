@@ -388,7 +388,7 @@ size_t call_bytes(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3
   Sizes z = sizes_for(Q, k, m_max, reorth, ring3);
   size_t b = (size_t)z.slots * k * z.vec_bytes;       // Krylov basis
   b += (size_t)k * z.vec_bytes;                       // q
-  if (Q->precond) b += 2 * (size_t)k * z.vec_bytes + (size_t)k * 10 * Q->shape[2] * 8;   // FFT intermediates
+  if (Q->precond) b += (size_t)k * z.vec_bytes + fft_band_bytes(Q->plan, Q->storage, (int)k);   // FFT scratch
   b += (size_t)k * (m_max + 2) * 8 * 4 + (size_t)k * 16;  // scalars
   b += 2 * (size_t)k * z.pstride * 8;                 // partials
   if (reorth) b += (size_t)k * (m_max + 1) * (z.Pb + 1) * 8;
@@ -471,8 +471,7 @@ struct Run {
   T* V = nullptr;        // slots x k x L
   T* Qb = nullptr;       // k x L
   T* F1 = nullptr;       // FFT intermediates (preconditioned)
-  T* F2 = nullptr;
-  T* F3 = nullptr;       // edge-row scratch of the band pass
+  void* band = nullptr;  // band hand-off buffers of the preconditioned operator
   double* part_h = nullptr;
   double* h = nullptr;
   bool ring3 = false;
@@ -493,8 +492,9 @@ gmrf_status setup(Run<T>& R, Workspace& ws) {
   if ((s = ws.alloc((size_t)k * R.z.L, &R.Qb)) != GMRF_OK) return s;
   if (Q->precond) {
     if ((s = ws.alloc((size_t)k * R.z.L, &R.F1)) != GMRF_OK) return s;
-    if ((s = ws.alloc((size_t)k * R.z.L, &R.F2)) != GMRF_OK) return s;
-    if ((s = ws.alloc((size_t)k * 10 * Q->shape[2], &R.F3)) != GMRF_OK) return s;
+    char* band;
+    if ((s = ws.alloc(fft_band_bytes(Q->plan, Q->storage, k), &band)) != GMRF_OK) return s;
+    R.band = band;
   }
   double* dbuf;
   const size_t nd = (size_t)k * (m + 1) * 3 + (size_t)k * (m + 2) + 2 * (size_t)k * R.z.pstride;
@@ -551,7 +551,7 @@ void iterate(Run<T>& R, int j) {
   T* xp = j >= 2 ? R.slot(j - 2) : R.slot(0);
   if (Q->precond) {
     fft_lanczos_operator<T>(Q->plan, Q->geom, Q->order, Q->storage == GMRF_F64 ? (const void*)Q->mult64 : (const void*)Q->mult32,
-                            xj, xp, R.Qb, R.F1, R.F2, R.F3, R.S, j, R.k, R.st);
+                            xj, xp, R.Qb, R.band, R.S, j, R.k, R.st);
   } else {
     op_apply_lz<T>(Q, xj, R.Qb, xp, R.S, j, R.k, R.st);
   }
@@ -821,11 +821,11 @@ static gmrf_status kernel_bench_impl(const gmrf_op* Q, int which, int k, int rep
   } else if (which == 1 || which == 2) {
     if (!Q->precond) return fail(GMRF_EINVAL, "kernel %d needs circulant preconditioning", which);
     if (which == 1) {
-      launch = [&]() { fft_col_pass_lz<T>(Q->plan, 1, mult, R.F2, R.Qb, R.slot(1), R.slot(0), R.S, 2, k, st); };
-      b = 4.0 * vb;   // read F2, v_j, v_{j-1}; write q
+      launch = [&]() { fft_col_pass_lz<T>(Q->plan, 1, mult, R.slot(1), R.slot(0), R.Qb, R.band, R.S, 2, k, st); };
+      b = 3.0 * vb;   // read v_j, v_{j-1}; write q (the D u row spectra are synthesised on chip)
     } else {
-      launch = [&]() { fft_col_pass_lz<T>(Q->plan, 0, mult, R.slot(0), R.F1, nullptr, nullptr, R.S, 1, k, st); };
-      b = 2.0 * vb;   // read v_j; write C1
+      launch = [&]() { fft_col_pass_lz<T>(Q->plan, 0, mult, R.slot(0), nullptr, nullptr, R.band, R.S, 1, k, st); };
+      b = 1.0 * vb;   // read v_j (writes only band partial sums and six edge rows)
     }
   } else if (which == 3) {
     launch = [&]() { launch_update<T>(R.Qb, R.slot(0), R.slot(1), R.z.L, 1, 1, R.S, st); };
