@@ -182,11 +182,14 @@ gmrf_status gmrf_tridiag_log_e1(const double* alpha, const double* beta, const i
 
 /* Times one kernel of the sampling path on its own: `reps` launches between two HIP events
  * recorded on `stream`, on scratch buffers of the handle's shape with k columns.
- *   which 0: Y = Q X (the operator's SpMV/SpMM kernel),  1: spectral column pass of the
- *   preconditioned operator with the Lanczos epilogue,  2: spectral column pass that opens
- *   an iteration,  3: the update w = q - alpha v.
- * Outputs (host): *avg_us = mean duration of one launch, *bytes = algorithmic bytes of one
- * launch (inputs read once, outputs written once).  EINVAL for 1/2 without preconditioning. */
+ *   which 0: Y = Q X (the operator's SpMV/SpMM kernel),  1: closing pass of the
+ *   preconditioned step (writes w_j from v_j, v_{j-1} and the boundary tables),  2: opening
+ *   pass of the preconditioned step (one read of v_j),  3: the update w = q - alpha v of the
+ *   unpreconditioned step,  4: band kernel of the preconditioned step.
+ * Buffers are zero-filled first.  Outputs (host): *avg_us = mean duration of one launch,
+ * *bytes = algorithmic bytes of one launch (inputs read once, outputs written once; 0 for the
+ * band kernel, whose traffic is the small boundary tables).  EINVAL for 1, 2, 4 without
+ * preconditioning.                                                                           */
 gmrf_status gmrf_kernel_bench(const gmrf_op* Q, int which, int64_t k, int32_t reps, double* avg_us,
                               double* bytes, void* stream);
 

@@ -43,6 +43,7 @@ struct LzState {
   int* active;
   double* part_a;       // [k][pstride] partial sums of v_j^T q (op kernels)
   double* part_b;       // [k][pstride] partial sums of ||w||^2 (elementwise kernels)
+  double* part_c;       // [k][pstride] partial sums of <w, v_j> (preconditioned closing pass)
   int Pa;               // number of partials the op kernel writes per RHS
   int Pb;               // number of partials the elementwise kernels write per RHS
   int pstride;

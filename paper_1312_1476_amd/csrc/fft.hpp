@@ -33,8 +33,6 @@ struct FftPlan {
 
 gmrf_status fft_plan_create(FftPlan& p, int N1, int N2);
 void fft_plan_destroy(FftPlan& p);
-int fft_col_blocks(const FftPlan& p);
-int fft_col_blocks_for(const FftPlan& p, int storage);   // alpha partials per field
 
 // Y = M^{-1/2} X for k real fields (storage T); tmp holds k packed spectra.
 template <typename T>
@@ -49,22 +47,23 @@ template <typename T>
 void fft_forward_init_probes(const FftPlan& p, uint64_t seed, const int8_t* probes, T* real_tmp, T* V0, T* tmp,
                              const LzState& S, int k, hipStream_t st);
 
-// Opener + operator of iteration j in the spectral basis, with A = I - M^{-1/2} D M^{-1/2}
-// (D = M - Q, nonzero only next to the boundary; the same A without the cancellation that
-// forming Q u of a smooth u = M^{-1/2} v costs in FP32):
-//   q_hat = v_hat_j - Lambda^{-1/2} F D F^H Lambda^{-1/2} v_hat_j - beta_{j-1} v_hat_{j-1},
-// plus the alpha partials.
-// scratch: fft_band_bytes(p, storage, k) bytes (band hand-off between the two column passes).
+// One preconditioned Lanczos step (precond_step.hip): opens iteration j, applies
+// A_hat = I - Lambda^{-1/2} F D F^H Lambda^{-1/2} to v_j = Xj / beta_{j-1} and writes
+// w_j = A_hat v_j - alpha_j v_j - beta_{j-1} v_{j-1} to W with its partial sums.  use_c = 0 when
+// w_{j-1} was reorthogonalised after the previous step (its <w, v> partials are then stale).
+// scratch: precond_step_bytes(p, storage, k) bytes.  only = -1 runs the three kernels, 0, 1, 2 one
+// of them (opening pass, band kernel, closing pass) for timing.
+struct PrecondStepCounts {
+  int Pband;   // <u, D u> partials per field (part_a[0..Pband))
+  int Po;      // opening blocks per field: ||v_j||^2 partials at part_a[Pband..Pband+Po), then <w, v>
+  int Pc;      // closing blocks per field: ||w_j||^2 and <w_j, v_j> partials (part_b, part_c)
+};
+PrecondStepCounts precond_step_counts(const FftPlan& p);
+size_t precond_step_bytes(const FftPlan& p, int storage, int k);
 template <typename T>
-void fft_lanczos_operator(const FftPlan& p, const StencilGeom& g, int order, const void* mult, const T* Xj,
-                          const T* Xprev, T* Qb, void* scratch, const LzState& S, int j, int k, hipStream_t st);
-size_t fft_band_bytes(const FftPlan& p, int storage, int k);
-
-// One column pass on its own (kernel timing): forward = 1 is the operator's second half with
-// the Lanczos epilogue, forward = 0 the first half that opens iteration j.
-template <typename T>
-void fft_col_pass_lz(const FftPlan& p, int forward, const void* mult, const T* Xj, const T* Xprev, T* Qb,
-                     void* scratch, const LzState& S, int j, int k, hipStream_t st);
+void precond_lanczos_step(const FftPlan& p, const StencilGeom& g, int order, const void* mult, const T* Xj,
+                          const T* Xprev, T* W, void* scratch, const LzState& S, int j, int use_c, int k,
+                          hipStream_t st, int only = -1);
 
 // X (FP64, real, n x k) = F^H Lambda^{-1/2} U_hat for the combined spectral vectors U_hat.
 template <typename T>

@@ -1,0 +1,119 @@
+// LDS FFT shared by the transform kernels and the preconditioned Lanczos step: Stockham
+// autosort (radix-4 stages, one radix-2 stage when log2 N is odd), after Govindaraju et al.,
+// "High performance discrete Fourier transforms on graphics processors" (SC'08).  Stage with
+// span Ns: item j gathers v_r = x[j + r N/R], multiplies by w^{r (j mod Ns) N/(Ns R)}
+// (w = e^{-2 pi i / N}), takes an R-point DFT and scatters y_r to
+// x[(j / Ns) Ns R + (j mod Ns) + r Ns].  Each thread stages its items in registers between two
+// barriers, so one LDS buffer suffices.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace gmrf {
+
+template <typename T> struct C2 { T x, y; };
+
+template <typename T>
+__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+constexpr int kFftThreads = 1024;
+template <typename T> struct FftCfg {
+  static constexpr int ELEMS = 65536 / (int)sizeof(C2<T>);          // complex values per block
+  static constexpr int MAXIT = ELEMS / (4 * kFftThreads);            // radix-4 items per thread
+};
+
+__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
+
+// nf sequences of length N in LDS: element e of sequence f at buf[f * fs + e * es].
+// INTER: items enumerate f fastest (interleaved sequences, es = nf, fs = 1), else e fastest.
+template <typename T, bool INTER>
+__device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* __restrict__ tw, bool inv) {
+  constexpr int MAXIT = FftCfg<T>::MAXIT;
+  const int logN = ilog2(N);
+  int Ns = 1;
+  const int n4 = N >> 2;
+  for (int s = 0; s < logN / 2; ++s) {
+    const int items = nf * n4;
+    C2<T> v[MAXIT][4];
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+      const int item = threadIdx.x + it * kFftThreads;
+      if (item < items) {
+        const int f = INTER ? item % nf : item / n4;
+        const int j = INTER ? item / nf : item % n4;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[it][r] = buf[f * fs + (j + r * n4) * es];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+      const int item = threadIdx.x + it * kFftThreads;
+      if (item < items) {
+        const int f = INTER ? item % nf : item / n4;
+        const int j = INTER ? item / nf : item % n4;
+        const int k = j & (Ns - 1);
+        const int step = N / (Ns * 4);
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+          C2<T> w = tw[r * k * step];
+          if (inv) w.y = -w.y;
+          v[it][r] = cmul(v[it][r], w);
+        }
+        const C2<T> a0 = v[it][0], a1 = v[it][1], a2 = v[it][2], a3 = v[it][3];
+        const C2<T> s02 = {a0.x + a2.x, a0.y + a2.y}, d02 = {a0.x - a2.x, a0.y - a2.y};
+        const C2<T> s13 = {a1.x + a3.x, a1.y + a3.y}, d13 = {a1.x - a3.x, a1.y - a3.y};
+        // forward: y1 = d02 - i d13, y3 = d02 + i d13; inverse swaps them
+        const C2<T> mi = {d13.y, -d13.x};   // -i * d13
+        C2<T> y[4];
+        y[0] = {s02.x + s13.x, s02.y + s13.y};
+        y[2] = {s02.x - s13.x, s02.y - s13.y};
+        const C2<T> p = {d02.x + mi.x, d02.y + mi.y}, q = {d02.x - mi.x, d02.y - mi.y};
+        y[1] = inv ? q : p;
+        y[3] = inv ? p : q;
+        const int idxD = (j / Ns) * Ns * 4 + k;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) buf[f * fs + (idxD + r * Ns) * es] = y[r];
+      }
+    }
+    __syncthreads();
+    Ns *= 4;
+  }
+  if (logN & 1) {
+    const int n2 = N >> 1;
+    const int items = nf * n2;
+    C2<T> v[2 * MAXIT][2];
+#pragma unroll
+    for (int it = 0; it < 2 * MAXIT; ++it) {
+      const int item = threadIdx.x + it * kFftThreads;
+      if (item < items) {
+        const int f = INTER ? item % nf : item / n2;
+        const int j = INTER ? item / nf : item % n2;
+        v[it][0] = buf[f * fs + j * es];
+        v[it][1] = buf[f * fs + (j + n2) * es];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 2 * MAXIT; ++it) {
+      const int item = threadIdx.x + it * kFftThreads;
+      if (item < items) {
+        const int f = INTER ? item % nf : item / n2;
+        const int j = INTER ? item / nf : item % n2;
+        const int k = j & (Ns - 1);
+        C2<T> w = tw[k * (N / (Ns * 2))];
+        if (inv) w.y = -w.y;
+        const C2<T> b = cmul(v[it][1], w), a = v[it][0];
+        const int idxD = (j / Ns) * Ns * 2 + k;
+        buf[f * fs + idxD * es] = {a.x + b.x, a.y + b.y};
+        buf[f * fs + (idxD + Ns) * es] = {a.x - b.x, a.y - b.y};
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace gmrf

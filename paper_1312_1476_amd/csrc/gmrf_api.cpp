@@ -367,6 +367,7 @@ struct Sizes {
   long L;          // storage elements per vector
   int slots;       // Krylov slots kept
   int Pa, Pb, pstride;
+  int Pb_first;    // ||w||^2 partials written by the init kernel (read by the opener of iteration 1)
   size_t vec_bytes;
 };
 
@@ -374,13 +375,19 @@ Sizes sizes_for(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3) 
   Sizes z{};
   z.L = (long)Q->n;  // packed half spectrum has exactly n reals too
   z.slots = ring3 ? 3 : m_max + 1;
-  if (Q->precond) z.Pa = fft_col_blocks_for(Q->plan, Q->storage);
-  else z.Pa = Q->kind == 0 ? stencil_blocks(Q->geom) : csr_blocks((long)Q->n);
-  z.Pb = ew_blocks(z.L);
-  z.pstride = std::max(z.Pa, z.Pb);
+  z.Pb_first = ew_blocks(z.L);
+  if (Q->precond) {
+    const PrecondStepCounts c = precond_step_counts(Q->plan);
+    z.Pa = c.Pband + c.Po + 1;                    // <u, D u>, ||v_j||^2, <w_{j-1}, v_{j-1}>
+    z.Pb = reorth ? ew_blocks(z.L) : c.Pc;        // the reorthogonalisation rewrites the norm partials
+  } else {
+    z.Pa = Q->kind == 0 ? stencil_blocks(Q->geom) : csr_blocks((long)Q->n);
+    z.Pb = ew_blocks(z.L);
+  }
+  z.pstride = std::max(std::max(z.Pa, z.Pb), z.Pb_first);
+  if (Q->precond) z.pstride = std::max(z.pstride, precond_step_counts(Q->plan).Pc);   // closing-pass partials
   z.vec_bytes = (size_t)z.L * (Q->storage == GMRF_F64 ? 8 : 4);
   (void)k;
-  (void)reorth;
   return z;
 }
 
@@ -388,9 +395,9 @@ size_t call_bytes(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3
   Sizes z = sizes_for(Q, k, m_max, reorth, ring3);
   size_t b = (size_t)z.slots * k * z.vec_bytes;       // Krylov basis
   b += (size_t)k * z.vec_bytes;                       // q
-  if (Q->precond) b += (size_t)k * z.vec_bytes + fft_band_bytes(Q->plan, Q->storage, (int)k);   // FFT scratch
+  if (Q->precond) b += (size_t)k * z.vec_bytes + precond_step_bytes(Q->plan, Q->storage, (int)k);   // FFT scratch
   b += (size_t)k * (m_max + 2) * 8 * 4 + (size_t)k * 16;  // scalars
-  b += 2 * (size_t)k * z.pstride * 8;                 // partials
+  b += 3 * (size_t)k * z.pstride * 8;                 // partials
   if (reorth) b += (size_t)k * (m_max + 1) * (z.Pb + 1) * 8;
   if (!ring3) b += (size_t)k * m_max * 8 + tri_scratch_doubles((int)k, m_max) * 8;
   return b;
@@ -471,7 +478,8 @@ struct Run {
   T* V = nullptr;        // slots x k x L
   T* Qb = nullptr;       // k x L
   T* F1 = nullptr;       // FFT intermediates (preconditioned)
-  void* band = nullptr;  // band hand-off buffers of the preconditioned operator
+  void* band = nullptr;  // hand-off buffers between the kernels of a preconditioned step
+  int pb_first = 0;      // partial count of the init kernel (iteration 1's opener)
   double* part_h = nullptr;
   double* h = nullptr;
   bool ring3 = false;
@@ -493,11 +501,11 @@ gmrf_status setup(Run<T>& R, Workspace& ws) {
   if (Q->precond) {
     if ((s = ws.alloc((size_t)k * R.z.L, &R.F1)) != GMRF_OK) return s;
     char* band;
-    if ((s = ws.alloc(fft_band_bytes(Q->plan, Q->storage, k), &band)) != GMRF_OK) return s;
+    if ((s = ws.alloc(precond_step_bytes(Q->plan, Q->storage, k), &band)) != GMRF_OK) return s;
     R.band = band;
   }
   double* dbuf;
-  const size_t nd = (size_t)k * (m + 1) * 3 + (size_t)k * (m + 2) + 2 * (size_t)k * R.z.pstride;
+  const size_t nd = (size_t)k * (m + 1) * 3 + (size_t)k * (m + 2) + 3 * (size_t)k * R.z.pstride;
   if ((s = ws.alloc(nd, &dbuf)) != GMRF_OK) return s;
   int* ibuf;
   if ((s = ws.alloc((size_t)3 * k, &ibuf)) != GMRF_OK) return s;
@@ -511,12 +519,14 @@ gmrf_status setup(Run<T>& R, Workspace& ws) {
   S.beta = S.rho + (size_t)k * (m + 1);
   S.part_a = S.beta + (size_t)k * (m + 2);
   S.part_b = S.part_a + (size_t)k * R.z.pstride;
+  S.part_c = S.part_b + (size_t)k * R.z.pstride;
   S.m_used = ibuf;
   S.status = ibuf + k;
   S.active = ibuf + 2 * k;
   S.Pa = R.z.Pa;
   S.Pb = R.z.Pb;
   S.pstride = R.z.pstride;
+  R.pb_first = R.z.Pb_first;
   S.weighted = Q->precond ? 1 : 0;
   S.H = Q->precond ? (int)(Q->shape[2] / 2) : 1;
   HIP_TRY(hipMemsetAsync(dbuf, 0, nd * sizeof(double), R.st));
@@ -543,20 +553,24 @@ int* poll_buffer(int k) {
   return buf;
 }
 
-// One iteration j: operator (opener) + update (+ reorth).
+// One iteration j: operator (opener) + update (+ reorth).  The opener of iteration 1 reduces the
+// partial sums of the init kernel, later openers those of the previous iteration.
 template <typename T>
 void iterate(Run<T>& R, int j) {
   const gmrf_op* Q = R.Q;
   T* xj = R.slot(j - 1);
   T* xp = j >= 2 ? R.slot(j - 2) : R.slot(0);
+  R.S.Pb = (j == 1) ? R.pb_first : R.z.Pb;
   if (Q->precond) {
-    fft_lanczos_operator<T>(Q->plan, Q->geom, Q->order, Q->storage == GMRF_F64 ? (const void*)Q->mult64 : (const void*)Q->mult32,
-                            xj, xp, R.Qb, R.band, R.S, j, R.k, R.st);
+    precond_lanczos_step<T>(Q->plan, Q->geom, Q->order,
+                            Q->storage == GMRF_F64 ? (const void*)Q->mult64 : (const void*)Q->mult32, xj, xp,
+                            R.slot(j), R.band, R.S, j, R.reorth ? 0 : 1, R.k, R.st);
   } else {
     op_apply_lz<T>(Q, xj, R.Qb, xp, R.S, j, R.k, R.st);
+    launch_update<T>(R.Qb, xj, R.slot(j), R.z.L, j, R.reorth ? 0 : 1, R.S, R.st);
   }
-  launch_update<T>(R.Qb, xj, R.slot(j), R.z.L, j, R.reorth ? 0 : 1, R.S, R.st);
   if (R.reorth) launch_reorth<T>(R.V, R.z.L, j, R.part_h, R.h, R.m_max + 1, R.S, R.st);
+  R.S.Pb = R.z.Pb;
 }
 
 // Runs iterations until every column stopped or m_max; returns the last j launched.
@@ -699,22 +713,10 @@ static gmrf_status logdet_impl(const gmrf_op* Q, int np, int m, uint64_t seed, c
     LzState S2 = R.S;
     S2.Pb = rademacher_blocks(R.z.L);
     launch_init_rademacher<T>(seed, R.z.L, R.slot(0), S2, st);
-    R.S.Pb = S2.Pb;  // opener of iteration 1 reduces the probe partials
+    R.pb_first = S2.Pb;  // opener of iteration 1 reduces the probe partials
   }
-  // the opener of iteration 1 reads Pb partials written by the init kernel; from then on
-  // the elementwise kernels write ew_blocks(L) partials
-  {
-    const int pb_init = R.S.Pb;
-    // iteration 1 with the init partial count, the rest with the elementwise count
-    int* pb = poll_buffer(np);
-    if (!pb) return fail(GMRF_ENOMEM, "pinned host buffer allocation failed");
-    for (int j = 1; j <= m; ++j) {
-      R.S.Pb = (j == 1) ? pb_init : R.z.Pb;
-      iterate<T>(R, j);
-    }
-    R.S.Pb = R.z.Pb;
-    launch_finalize(R.S, st);
-  }
+  for (int j = 1; j <= m; ++j) iterate<T>(R, j);
+  launch_finalize(R.S, st);
   double* g;
   if ((s = ws.alloc((size_t)np * 4, &g)) != GMRF_OK) return s;
   launch_tri_log(R.S.alpha, m + 1, 1, R.S.beta, m + 2, 1, R.S.m_used, 0, R.S.status, g, 1, R.S.status, np, st);
@@ -783,12 +785,13 @@ extern "C" gmrf_status gmrf_tridiag_log_e1(const double* alpha, const double* be
 
 // ---- single-kernel timing (for the roofline of the step's dominant kernels) ----------------------------
 // which: 0 = lattice/CSR operator Y = Q X (SpMM over k columns, storage dtype)
-//        1 = spectral column pass, forward, with the Lanczos epilogue (preconditioned step)
-//        2 = spectral column pass, inverse, opening the iteration (preconditioned step)
-//        3 = update w = q - alpha v (any path)
-// Buffers are allocated before the first event; `reps` launches run between two HIP events
-// recorded on `stream`.  bytes = algorithmic bytes of one launch (each input read once, each
-// output written once).
+//        1 = closing pass of the preconditioned step (writes w_j)
+//        2 = opening pass of the preconditioned step (reads v_j)
+//        3 = update w = q - alpha v (unpreconditioned path)
+//        4 = band kernel of the preconditioned step
+// Buffers are allocated and zero-filled before the first event; `reps` launches run between two HIP
+// events recorded on `stream`.  bytes = algorithmic bytes of one launch (each input read once, each
+// output written once; the small hand-off tables between the kernels of a step are not counted).
 template <typename T>
 static gmrf_status kernel_bench_impl(const gmrf_op* Q, int which, int k, int reps, double* avg_us, double* bytes,
                                      hipStream_t st) {
@@ -802,15 +805,18 @@ static gmrf_status kernel_bench_impl(const gmrf_op* Q, int which, int k, int rep
   R.st = st;
   gmrf_status s = setup<T>(R, ws);
   if (s != GMRF_OK) return s;
-  // beta_j = 1, partial sums = 1: every column active, no stop decision triggers
+  // beta_j = 1, partial sums = 1, zero vectors: every column active, no stop decision triggers
   {
     std::vector<double> ones((size_t)k * (R.m_max + 2), 1.0);
     HIP_TRY(hipMemcpyAsync(R.S.beta, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, st));
     std::vector<double> pones((size_t)k * R.z.pstride, 1.0);
     HIP_TRY(hipMemcpyAsync(R.S.part_b, pones.data(), pones.size() * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(R.S.part_a, pones.data(), pones.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(R.V, 0, (size_t)R.z.slots * k * R.z.vec_bytes, st));
+    if (R.band) HIP_TRY(hipMemsetAsync(R.band, 0, precond_step_bytes(Q->plan, Q->storage, k), st));
     HIP_TRY(hipStreamSynchronize(st));
   }
+  R.S.Pb = R.pb_first;
   const size_t vb = (size_t)k * R.z.vec_bytes;
   std::function<void()> launch;
   double b = 0.0;
@@ -818,14 +824,26 @@ static gmrf_status kernel_bench_impl(const gmrf_op* Q, int which, int k, int rep
   if (which == 0) {
     launch = [&]() { op_apply_plain<T>(Q, R.slot(0), R.Qb, k, st); };
     b = 2.0 * vb + (Q->kind == 1 ? (double)Q->resident_bytes : 0.0);
-  } else if (which == 1 || which == 2) {
+  } else if (which == 1 || which == 2 || which == 4) {
     if (!Q->precond) return fail(GMRF_EINVAL, "kernel %d needs circulant preconditioning", which);
     if (which == 1) {
-      launch = [&]() { fft_col_pass_lz<T>(Q->plan, 1, mult, R.slot(1), R.slot(0), R.Qb, R.band, R.S, 2, k, st); };
-      b = 3.0 * vb;   // read v_j, v_{j-1}; write q (the D u row spectra are synthesised on chip)
+      launch = [&]() {
+        precond_lanczos_step<T>(Q->plan, Q->geom, Q->order, mult, R.slot(1), R.slot(0), R.slot(2), R.band, R.S, 2, 1,
+                                k, st, 2);
+      };
+      b = 3.0 * vb;   // read v_j, v_{j-1}; write w_j
+    } else if (which == 2) {
+      launch = [&]() {
+        precond_lanczos_step<T>(Q->plan, Q->geom, Q->order, mult, R.slot(0), R.slot(0), R.slot(1), R.band, R.S, 1, 1,
+                                k, st, 0);
+      };
+      b = 1.0 * vb;   // read v_j (writes only the dot partial sums)
     } else {
-      launch = [&]() { fft_col_pass_lz<T>(Q->plan, 0, mult, R.slot(0), nullptr, nullptr, R.band, R.S, 1, k, st); };
-      b = 1.0 * vb;   // read v_j (writes only band partial sums and six edge rows)
+      launch = [&]() {
+        precond_lanczos_step<T>(Q->plan, Q->geom, Q->order, mult, R.slot(0), R.slot(0), R.slot(1), R.band, R.S, 1, 1,
+                                k, st, 1);
+      };
+      b = 0.0;
     }
   } else if (which == 3) {
     launch = [&]() { launch_update<T>(R.Qb, R.slot(0), R.slot(1), R.z.L, 1, 1, R.S, st); };
