@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-DOMINANT_KERNEL = "lz_close"     # largest share of the step in the committed rocprofv3 summary
+DOMINANT_KERNEL = "lz_step"      # largest share of the step in the committed rocprofv3 summary
 TRAFFIC_GB = None                # FETCH_SIZE/WRITE_SIZE per launch, once counters are taken
 TOL_HEADLINE = 1e-5
 M_MAX_HEADLINE = 600
@@ -153,7 +153,7 @@ def main():
                           "traffic": TRAFFIC_GB, "kernel": roof["kernel"], "avg_us": round(roof["avg_us"], 2),
                           "bytes_per_launch": roof["bytes"]}
     kern = {}
-    for name in ("lz_open", "lz_band"):
+    for name in ("lz_band", "lz_dots"):
         r = gm.kernel_bench(op64, name, k, reps=50, stream=stream)
         kern[name] = {"avg_us": round(r["avg_us"], 2), "gbs": round(r["achieved_gbs"], 1)}
     result["other_kernels"] = kern

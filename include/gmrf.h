@@ -182,10 +182,11 @@ gmrf_status gmrf_tridiag_log_e1(const double* alpha, const double* beta, const i
 
 /* Times one kernel of the sampling path on its own: `reps` launches between two HIP events
  * recorded on `stream`, on scratch buffers of the handle's shape with k columns.
- *   which 0: Y = Q X (the operator's SpMV/SpMM kernel),  1: closing pass of the
- *   preconditioned step (writes w_j from v_j, v_{j-1} and the boundary tables),  2: opening
- *   pass of the preconditioned step (one read of v_j),  3: the update w = q - alpha v of the
- *   unpreconditioned step,  4: band kernel of the preconditioned step.
+ *   which 0: Y = Q X (the operator's SpMV/SpMM kernel),  1: step kernel of the
+ *   preconditioned step (writes w_j from v_j, v_{j-1} and the boundary tables, with the dot
+ *   products the next step needs),  2: dot-product kernel of the preconditioned step (one read
+ *   of a vector),  3: the update w = q - alpha v of the unpreconditioned step,  4: band kernel
+ *   of the preconditioned step.
  * Buffers are zero-filled first.  Outputs (host): *avg_us = mean duration of one launch,
  * *bytes = algorithmic bytes of one launch (inputs read once, outputs written once; 0 for the
  * band kernel, whose traffic is the small boundary tables).  EINVAL for 1, 2, 4 without

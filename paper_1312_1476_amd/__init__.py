@@ -237,7 +237,7 @@ def tridiag_log_e1(alpha, beta, m, stream=None):
     return out, status
 
 
-KERNELS = {"spmv": 0, "lz_close": 1, "lz_open": 2, "update": 3, "lz_band": 4}
+KERNELS = {"spmv": 0, "lz_step": 1, "lz_dots": 2, "update": 3, "lz_band": 4}
 
 
 def kernel_bench(op, kernel, k, reps=50, stream=None):

@@ -31,6 +31,10 @@ struct FftPlan {
   float* tw32_2 = nullptr;
 };
 
+// lambda_M^{-1/2} table, [N1][mult_stride(H)]: entries 0..H-1 for packed columns (column 0 -> k2 = 0),
+// entry H -> k2 = N2/2, entry H+1 padding so that every row starts on a 16-byte boundary.
+__host__ __device__ constexpr int mult_stride(int H) { return H + 2; }
+
 gmrf_status fft_plan_create(FftPlan& p, int N1, int N2);
 void fft_plan_destroy(FftPlan& p);
 
@@ -47,23 +51,27 @@ template <typename T>
 void fft_forward_init_probes(const FftPlan& p, uint64_t seed, const int8_t* probes, T* real_tmp, T* V0, T* tmp,
                              const LzState& S, int k, hipStream_t st);
 
-// One preconditioned Lanczos step (precond_step.hip): opens iteration j, applies
-// A_hat = I - Lambda^{-1/2} F D F^H Lambda^{-1/2} to v_j = Xj / beta_{j-1} and writes
-// w_j = A_hat v_j - alpha_j v_j - beta_{j-1} v_{j-1} to W with its partial sums.  use_c = 0 when
-// w_{j-1} was reorthogonalised after the previous step (its <w, v> partials are then stale).
-// scratch: precond_step_bytes(p, storage, k) bytes.  only = -1 runs the three kernels, 0, 1, 2 one
-// of them (opening pass, band kernel, closing pass) for timing.
+// Preconditioned Lanczos step (precond_step.hip).  Opens iteration j (beta_{j-1} from the partial
+// sums, stopping rule), applies A_hat = I - Lambda^{-1/2} F D F^H Lambda^{-1/2} to v_j = Xj / beta_{j-1}
+// and writes w_j = A_hat v_j - alpha_j v_j - beta_{j-1} v_{j-1} to W with its partial sums.  The
+// boundary values of u = F^H Lambda^{-1/2} v_j come from dot products of v_j left in scratch by the
+// previous step (dots = 1) or by precond_dots (slot 0; a w_j changed by reorthogonalisation, after
+// which use_c = 0 because its <w, v> partials are stale).
+// scratch: precond_step_bytes(p, storage, k) bytes.  only = -1 runs the band and the step kernels;
+// 1 the band kernel, 2 the step kernel, 0 the dots kernel on Xj (timing).
 struct PrecondStepCounts {
-  int Pband;   // <u, D u> partials per field (part_a[0..Pband))
-  int Po;      // opening blocks per field: ||v_j||^2 partials at part_a[Pband..Pband+Po), then <w, v>
-  int Pc;      // closing blocks per field: ||w_j||^2 and <w_j, v_j> partials (part_b, part_c)
+  int Pband;   // <u, D u> partials per field (part_a[0..Pband)), then <w_{j-1}, v_{j-1}> at part_a[Pband]
+  int Ps;      // step blocks per field: ||w_j||^2 and <w_j, v_j> partials (part_b, part_c)
 };
 PrecondStepCounts precond_step_counts(const FftPlan& p);
 size_t precond_step_bytes(const FftPlan& p, int storage, int k);
 template <typename T>
 void precond_lanczos_step(const FftPlan& p, const StencilGeom& g, int order, const void* mult, const T* Xj,
-                          const T* Xprev, T* W, void* scratch, const LzState& S, int j, int use_c, int k,
+                          const T* Xprev, T* W, void* scratch, const LzState& S, int j, int use_c, int dots, int k,
                           hipStream_t st, int only = -1);
+template <typename T>
+void precond_dots(const FftPlan& p, const void* mult, const T* X, void* scratch, const LzState& S, int k,
+                  hipStream_t st);
 
 // X (FP64, real, n x k) = F^H Lambda^{-1/2} U_hat for the combined spectral vectors U_hat.
 template <typename T>

@@ -117,13 +117,13 @@ __device__ void apply_mult(C2<T>* buf, int nf, int c0, int N1, int H, const T* _
   for (int idx = threadIdx.x; idx < nf * N1; idx += kFftThreads) {
     const int k1 = idx / nf, c = idx % nf, cg = c0 + c;
     if (cg == 0) continue;
-    const T m = mult[(size_t)k1 * (H + 1) + cg] * scale;
+    const T m = mult[(size_t)k1 * mult_stride(H) + cg] * scale;
     buf[idx] = {buf[idx].x * m, buf[idx].y * m};
   }
   if (c0 == 0) {
     for (int k1 = threadIdx.x; k1 <= N1 / 2; k1 += kFftThreads) {
       const int kb = (N1 - k1) & (N1 - 1);
-      const T m0 = mult[(size_t)k1 * (H + 1)] * scale, mN = mult[(size_t)k1 * (H + 1) + H] * scale;
+      const T m0 = mult[(size_t)k1 * mult_stride(H)] * scale, mN = mult[(size_t)k1 * mult_stride(H) + H] * scale;
       const T p = (m0 + mN) * (T)0.5, q = (m0 - mN) * (T)0.5;
       const C2<T> a = buf[k1 * nf], b = buf[kb * nf];
       buf[k1 * nf] = {p * a.x + q * b.x, p * a.y - q * b.y};

@@ -317,12 +317,13 @@ static gmrf_status build_precond(gmrf_op* Q) {
     const double b = Q->kappa2 + mu1[k1] + mu2[k2];
     return Q->order == 1 ? Q->tau * b : Q->tau * b * b;
   };
-  // table layout: [k1][H + 1]: entries 0..H-1 for columns (col 0 -> k2 = 0), entry H -> k2 = N2/2
-  std::vector<double> t((size_t)N1 * (H + 1));
+  // table layout: [k1][mult_stride(H)]: entries 0..H-1 for columns (col 0 -> k2 = 0), entry H -> k2 = N2/2
+  const int ms = mult_stride(H);
+  std::vector<double> t((size_t)N1 * ms, 0.0);
   double ld = 0.0;
   for (int k1 = 0; k1 < N1; ++k1) {
-    for (int c = 0; c < H; ++c) t[(size_t)k1 * (H + 1) + c] = 1.0 / std::sqrt(lam(k1, c));
-    t[(size_t)k1 * (H + 1) + H] = 1.0 / std::sqrt(lam(k1, H));
+    for (int c = 0; c < H; ++c) t[(size_t)k1 * ms + c] = 1.0 / std::sqrt(lam(k1, c));
+    t[(size_t)k1 * ms + H] = 1.0 / std::sqrt(lam(k1, H));
     for (int k2 = 0; k2 < N2; ++k2) {
       const double l = lam(k1, k2);
       if (!(l > 0.0)) return fail(GMRF_ENOTSPD, "periodic preconditioner is singular (kappa2 <= 0)");
@@ -378,14 +379,14 @@ Sizes sizes_for(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3) 
   z.Pb_first = ew_blocks(z.L);
   if (Q->precond) {
     const PrecondStepCounts c = precond_step_counts(Q->plan);
-    z.Pa = c.Pband + c.Po + 1;                    // <u, D u>, ||v_j||^2, <w_{j-1}, v_{j-1}>
-    z.Pb = reorth ? ew_blocks(z.L) : c.Pc;        // the reorthogonalisation rewrites the norm partials
+    z.Pa = c.Pband + 1;                           // <u, D u> per band block, <w_{j-1}, v_{j-1}>
+    z.Pb = reorth ? ew_blocks(z.L) : c.Ps;        // the reorthogonalisation rewrites the norm partials
   } else {
     z.Pa = Q->kind == 0 ? stencil_blocks(Q->geom) : csr_blocks((long)Q->n);
     z.Pb = ew_blocks(z.L);
   }
   z.pstride = std::max(std::max(z.Pa, z.Pb), z.Pb_first);
-  if (Q->precond) z.pstride = std::max(z.pstride, precond_step_counts(Q->plan).Pc);   // closing-pass partials
+  if (Q->precond) z.pstride = std::max(z.pstride, precond_step_counts(Q->plan).Ps);   // step-kernel partials
   z.vec_bytes = (size_t)z.L * (Q->storage == GMRF_F64 ? 8 : 4);
   (void)k;
   return z;
@@ -460,6 +461,10 @@ extern "C" gmrf_status gmrf_precond_apply(const gmrf_op* Q, const void* X, void*
 
 // ---- the Lanczos driver --------------------------------------------------------------------------------
 namespace {
+
+const void* precond_mult(const gmrf_op* Q) {
+  return Q->storage == GMRF_F64 ? (const void*)Q->mult64 : (const void*)Q->mult32;
+}
 
 struct Scalars {
   double *alpha, *beta, *dpiv, *rho;
@@ -562,14 +567,16 @@ void iterate(Run<T>& R, int j) {
   T* xp = j >= 2 ? R.slot(j - 2) : R.slot(0);
   R.S.Pb = (j == 1) ? R.pb_first : R.z.Pb;
   if (Q->precond) {
-    precond_lanczos_step<T>(Q->plan, Q->geom, Q->order,
-                            Q->storage == GMRF_F64 ? (const void*)Q->mult64 : (const void*)Q->mult32, xj, xp,
-                            R.slot(j), R.band, R.S, j, R.reorth ? 0 : 1, R.k, R.st);
+    precond_lanczos_step<T>(Q->plan, Q->geom, Q->order, precond_mult(Q), xj, xp, R.slot(j), R.band, R.S, j,
+                            R.reorth ? 0 : 1, R.reorth ? 0 : 1, R.k, R.st);
   } else {
     op_apply_lz<T>(Q, xj, R.Qb, xp, R.S, j, R.k, R.st);
     launch_update<T>(R.Qb, xj, R.slot(j), R.z.L, j, R.reorth ? 0 : 1, R.S, R.st);
   }
-  if (R.reorth) launch_reorth<T>(R.V, R.z.L, j, R.part_h, R.h, R.m_max + 1, R.S, R.st);
+  if (R.reorth) {
+    launch_reorth<T>(R.V, R.z.L, j, R.part_h, R.h, R.m_max + 1, R.S, R.st);
+    if (Q->precond) precond_dots<T>(Q->plan, precond_mult(Q), R.slot(j), R.band, R.S, R.k, R.st);
+  }
   R.S.Pb = R.z.Pb;
 }
 
@@ -613,8 +620,12 @@ static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, dou
   gmrf_status s = setup<T>(R, ws);
   if (s != GMRF_OK) return s;
   // slot 0 <- z (preconditioned: z in the unitary spectral basis)
-  if (Q->precond) fft_forward_init<T>(Q->plan, Z, R.slot(0), R.F1, R.S, (int)k, st);
-  else launch_init_from_f64<T>(Z, Q->n, R.z.L, R.slot(0), R.S, st);
+  if (Q->precond) {
+    fft_forward_init<T>(Q->plan, Z, R.slot(0), R.F1, R.S, (int)k, st);
+    precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, (int)k, st);
+  } else {
+    launch_init_from_f64<T>(Z, Q->n, R.z.L, R.slot(0), R.S, st);
+  }
   if ((s = run_loop<T>(R)) != GMRF_OK) return s;
   // y = T_m^{-1/2} e_1, then x_m = ||z|| V_m y
   double *y, *scr;
@@ -707,6 +718,7 @@ static gmrf_status logdet_impl(const gmrf_op* Q, int np, int m, uint64_t seed, c
     T* pr;
     if ((s = ws.alloc((size_t)np * Q->n, &pr)) != GMRF_OK) return s;
     fft_forward_init_probes<T>(Q->plan, seed, probes, pr, R.slot(0), R.F1, R.S, np, st);
+    precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, np, st);
   } else if (probes) {
     launch_init_from_i8<T>(probes, R.z.L, R.slot(0), R.S, st);
   } else {
@@ -785,8 +797,8 @@ extern "C" gmrf_status gmrf_tridiag_log_e1(const double* alpha, const double* be
 
 // ---- single-kernel timing (for the roofline of the step's dominant kernels) ----------------------------
 // which: 0 = lattice/CSR operator Y = Q X (SpMM over k columns, storage dtype)
-//        1 = closing pass of the preconditioned step (writes w_j)
-//        2 = opening pass of the preconditioned step (reads v_j)
+//        1 = step kernel of the preconditioned step (writes w_j and its dot products)
+//        2 = dot-product kernel of the preconditioned step (reads one vector)
 //        3 = update w = q - alpha v (unpreconditioned path)
 //        4 = band kernel of the preconditioned step
 // Buffers are allocated and zero-filled before the first event; `reps` launches run between two HIP
@@ -829,19 +841,19 @@ static gmrf_status kernel_bench_impl(const gmrf_op* Q, int which, int k, int rep
     if (which == 1) {
       launch = [&]() {
         precond_lanczos_step<T>(Q->plan, Q->geom, Q->order, mult, R.slot(1), R.slot(0), R.slot(2), R.band, R.S, 2, 1,
-                                k, st, 2);
+                                1, k, st, 2);
       };
       b = 3.0 * vb;   // read v_j, v_{j-1}; write w_j
     } else if (which == 2) {
       launch = [&]() {
         precond_lanczos_step<T>(Q->plan, Q->geom, Q->order, mult, R.slot(0), R.slot(0), R.slot(1), R.band, R.S, 1, 1,
-                                k, st, 0);
+                                1, k, st, 0);
       };
-      b = 1.0 * vb;   // read v_j (writes only the dot partial sums)
+      b = 1.0 * vb;   // read one vector (writes only the dot partial sums)
     } else {
       launch = [&]() {
         precond_lanczos_step<T>(Q->plan, Q->geom, Q->order, mult, R.slot(0), R.slot(0), R.slot(1), R.band, R.S, 1, 1,
-                                k, st, 1);
+                                1, k, st, 1);
       };
       b = 0.0;
     }

@@ -109,6 +109,22 @@ def test_precond_sample_prefix_fp64(gm, m):
         assert _rel(X[:, r], ref.x) <= 1e-8
 
 
+@pytest.mark.parametrize("shape,storage,tol", [((16, 2048), "f64", 1e-8), ((2048, 16), "f64", 1e-8),
+                                               ((8, 4096), "f32", 1e-5)])
+def test_precond_wide_lattice_prefix(gm, shape, storage, tol):
+    """Sides beyond the on-chip band kernel (4 N > LDS FFT capacity: 1024 in FP64, 2048 in
+    FP32) take the band kernel that stages the boundary rows in global scratch."""
+    order, k2, m = 2, 0.05, 6
+    op = gm.Operator.lattice(shape, order, k2, 1.0, "free", storage).set_circulant_precond()
+    Q = lattice.lattice_precision(shape, order, k2, 1.0, "free")
+    Zh = workloads.gaussian_block(Q.shape[0], 2, 98, 0)
+    X, info, al, _ = _sample(gm, op, Zh, tol=0.0, m_max=m)
+    for r in range(2):
+        ref = precond.sample(Q, shape, order, k2, 1.0, Zh[:, r], m, tol=0.0)
+        assert info[r]["m_used"] == m
+        assert _rel(X[:, r], ref.x) <= tol, _rel(X[:, r], ref.x)
+
+
 def test_precond_sample_fp32(gm):
     shape, order, k2, k = (64, 64), 2, 0.05, 3
     op = gm.Operator.lattice(shape, order, k2, 1.0, "free", "f32").set_circulant_precond()
