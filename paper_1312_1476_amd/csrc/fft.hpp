@@ -17,6 +17,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+
 #include "../../include/gmrf.h"
 #include "common.hpp"
 #include "kernels.hpp"
@@ -29,7 +32,16 @@ struct FftPlan {
   double* tw64_2 = nullptr;   // e^{-2 pi i k / N2}, k < N2
   float* tw32_1 = nullptr;
   float* tw32_2 = nullptr;
+  double* mu1 = nullptr;      // 4 sin^2(pi min(k, N1-k) / N1), k < N1: eigenvalues of the periodic second difference
+  double* mu2 = nullptr;      // same for N2
 };
+
+// mu(k) of the periodic second difference on N points, evaluated at min(k, N - k) so that mu(k) = mu(N - k)
+// exactly (shared by the multiplier table and the kernels that evaluate the multiplier in registers).
+inline double periodic_mu(int k, int N) {
+  const double s = std::sin(M_PI * (double)std::min(k, N - k) / N);
+  return 4.0 * s * s;
+}
 
 // lambda_M^{-1/2} table, [N1][mult_stride(H)]: entries 0..H-1 for packed columns (column 0 -> k2 = 0),
 // entry H -> k2 = N2/2, entry H+1 padding so that every row starts on a 16-byte boundary.
@@ -46,10 +58,10 @@ void fft_apply_inv_sqrt_M(const FftPlan& p, const T* mult, const T* X, T* Y, T* 
 template <typename T>
 void fft_forward_init(const FftPlan& p, const double* Z, T* V0, T* tmp, const LzState& S, int k, hipStream_t st);
 
-// same for Rademacher probes (from seed, or from an int8 block when probes != nullptr).
+// same for Rademacher probes p0 .. p0 + k - 1 (from seed, or from an int8 block when probes != nullptr).
 template <typename T>
-void fft_forward_init_probes(const FftPlan& p, uint64_t seed, const int8_t* probes, T* real_tmp, T* V0, T* tmp,
-                             const LzState& S, int k, hipStream_t st);
+void fft_forward_init_probes(const FftPlan& p, uint64_t seed, int p0, const int8_t* probes, T* real_tmp, T* V0,
+                             T* tmp, const LzState& S, int k, hipStream_t st);
 
 // Preconditioned Lanczos step (precond_step.hip).  Opens iteration j (beta_{j-1} from the partial
 // sums, stopping rule), applies A_hat = I - Lambda^{-1/2} F D F^H Lambda^{-1/2} to v_j = Xj / beta_{j-1}

@@ -189,9 +189,16 @@ gmrf_status fft_plan_create(FftPlan& p, int N1, int N2) {
   table(N1, t1);
   table(N2, t2);
   std::vector<float> f1(t1.begin(), t1.end()), f2(t2.begin(), t2.end());
+  std::vector<double> m1(N1), m2(N2);
+  for (int k = 0; k < N1; ++k) m1[k] = periodic_mu(k, N1);
+  for (int k = 0; k < N2; ++k) m2[k] = periodic_mu(k, N2);
   if (hipMalloc(&p.tw64_1, t1.size() * 8) != hipSuccess || hipMalloc(&p.tw64_2, t2.size() * 8) != hipSuccess ||
-      hipMalloc(&p.tw32_1, f1.size() * 4) != hipSuccess || hipMalloc(&p.tw32_2, f2.size() * 4) != hipSuccess)
+      hipMalloc(&p.tw32_1, f1.size() * 4) != hipSuccess || hipMalloc(&p.tw32_2, f2.size() * 4) != hipSuccess ||
+      hipMalloc(&p.mu1, m1.size() * 8) != hipSuccess || hipMalloc(&p.mu2, m2.size() * 8) != hipSuccess)
     return GMRF_ENOMEM;
+  if (hipMemcpy(p.mu1, m1.data(), m1.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p.mu2, m2.data(), m2.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+    return GMRF_EDEVICE;
   if (hipMemcpy(p.tw64_1, t1.data(), t1.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p.tw64_2, t2.data(), t2.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p.tw32_1, f1.data(), f1.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
@@ -205,6 +212,8 @@ void fft_plan_destroy(FftPlan& p) {
   if (p.tw64_2) (void)hipFree(p.tw64_2);
   if (p.tw32_1) (void)hipFree(p.tw32_1);
   if (p.tw32_2) (void)hipFree(p.tw32_2);
+  if (p.mu1) (void)hipFree(p.mu1);
+  if (p.mu2) (void)hipFree(p.mu2);
   p = FftPlan{};
 }
 
@@ -253,11 +262,11 @@ void fft_forward_init(const FftPlan& p, const double* Z, T* V0, T* tmp, const Lz
 }
 
 template <typename T>
-void fft_forward_init_probes(const FftPlan& p, uint64_t seed, const int8_t* probes, T* real_tmp, T* V0, T* tmp,
-                             const LzState& S, int k, hipStream_t st) {
+void fft_forward_init_probes(const FftPlan& p, uint64_t seed, int p0, const int8_t* probes, T* real_tmp, T* V0,
+                             T* tmp, const LzState& S, int k, hipStream_t st) {
   const long n = (long)p.N1 * p.N2;
   if (probes) launch_init_from_i8<T>(probes, n, real_tmp, S, st);
-  else launch_init_rademacher<T>(seed, n, real_tmp, S, st);
+  else launch_init_rademacher<T>(seed, n, p0, real_tmp, S, st);
   rows_r2c<T, T>(p, real_tmp, n, tmp, n / 2, (T)1, nullptr, k, st);
   cols<T, kColFwdInit>(p, tmp, V0, nullptr, (T)(1.0 / std::sqrt((double)n)), k, st);
   launch_norm_partials<T>(V0, n, S, st);
@@ -274,7 +283,7 @@ void fft_backward_output(const FftPlan& p, const void* mult, const T* U, double*
 #define INST(T)                                                                                            \
   template void fft_apply_inv_sqrt_M<T>(const FftPlan&, const T*, const T*, T*, T*, int, hipStream_t);     \
   template void fft_forward_init<T>(const FftPlan&, const double*, T*, T*, const LzState&, int, hipStream_t); \
-  template void fft_forward_init_probes<T>(const FftPlan&, uint64_t, const int8_t*, T*, T*, T*, const LzState&, int, hipStream_t); \
+  template void fft_forward_init_probes<T>(const FftPlan&, uint64_t, int, const int8_t*, T*, T*, T*, const LzState&, int, hipStream_t); \
   template void fft_backward_output<T>(const FftPlan&, const void*, const T*, double*, T*, const LzState&, int, hipStream_t);
 INST(double)
 INST(float)

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -304,15 +305,8 @@ static gmrf_status build_precond(gmrf_op* Q) {
   const int N1 = (int)Q->shape[1], N2 = (int)Q->shape[2];
   const int H = N2 / 2;
   std::vector<double> mu1(N1), mu2(N2);
-  // mu(k) = mu(N - k) exactly: evaluate at min(k, N - k)
-  for (int k = 0; k < N1; ++k) {
-    const double s = std::sin(M_PI * (double)std::min(k, N1 - k) / N1);
-    mu1[k] = 4.0 * s * s;
-  }
-  for (int k = 0; k < N2; ++k) {
-    const double s = std::sin(M_PI * (double)std::min(k, N2 - k) / N2);
-    mu2[k] = 4.0 * s * s;
-  }
+  for (int k = 0; k < N1; ++k) mu1[k] = periodic_mu(k, N1);
+  for (int k = 0; k < N2; ++k) mu2[k] = periodic_mu(k, N2);
   auto lam = [&](int k1, int k2) {
     const double b = Q->kappa2 + mu1[k1] + mu2[k2];
     return Q->order == 1 ? Q->tau * b : Q->tau * b * b;
@@ -580,28 +574,104 @@ void iterate(Run<T>& R, int j) {
   R.S.Pb = R.z.Pb;
 }
 
-// Runs iterations until every column stopped or m_max; returns the last j launched.
+// Iteration j of all groups, launches interleaved across the groups' streams.
 template <typename T>
-gmrf_status run_loop(Run<T>& R) {
-  int* pb = poll_buffer(R.k);
+void iterate_all(std::vector<Run<T>>& Rs, int j, const std::vector<char>& live) {
+  for (size_t g = 0; g < Rs.size(); ++g)
+    if (live[g]) iterate<T>(Rs[g], j);
+}
+
+// Runs iterations of all groups (each on its own stream) until every column stopped or m_max, then closes
+// the columns that hit m_max.  Groups whose columns all stopped launch no more.
+template <typename T>
+gmrf_status run_loop(std::vector<Run<T>>& Rs) {
+  int ktot = 0;
+  for (auto& R : Rs) ktot += R.k;
+  int* pb = poll_buffer(ktot);
   if (!pb) return fail(GMRF_ENOMEM, "pinned host buffer allocation failed");
+  std::vector<char> live(Rs.size(), 1);
+  const int m_max = Rs[0].m_max;
   int poll = 8;
-  for (int j = 1; j <= R.m_max; ++j) {
-    iterate<T>(R, j);
-    if (j % poll == 0 && j < R.m_max) {
+  for (int j = 1; j <= m_max; ++j) {
+    iterate_all<T>(Rs, j, live);
+    if (j % poll == 0 && j < m_max) {
       HIP_TRY(hipGetLastError());
-      HIP_TRY(hipMemcpyAsync(pb, R.S.active, R.k * sizeof(int), hipMemcpyDeviceToHost, R.st));
-      HIP_TRY(hipStreamSynchronize(R.st));
+      int off = 0;
+      for (size_t g = 0; g < Rs.size(); ++g) {
+        if (live[g])
+          HIP_TRY(hipMemcpyAsync(pb + off, Rs[g].S.active, Rs[g].k * sizeof(int), hipMemcpyDeviceToHost, Rs[g].st));
+        off += Rs[g].k;
+      }
       bool any = false;
-      for (int r = 0; r < R.k; ++r) any |= pb[r] != 0;
+      off = 0;
+      for (size_t g = 0; g < Rs.size(); ++g) {
+        if (live[g]) {
+          HIP_TRY(hipStreamSynchronize(Rs[g].st));
+          bool a = false;
+          for (int r = 0; r < Rs[g].k; ++r) a |= pb[off + r] != 0;
+          live[g] = a;
+        }
+        any |= live[g] != 0;
+        off += Rs[g].k;
+      }
       if (!any) break;
       poll = std::min(poll * 2, 32);
     }
   }
-  launch_finalize(R.S, R.st);
+  for (auto& R : Rs) launch_finalize(R.S, R.st);
   HIP_TRY(hipGetLastError());
   return GMRF_OK;
 }
+
+// Independent column groups of one call run side by side: with the preconditioned step the band
+// kernel of one group (a few blocks, latency-bound) overlaps the streaming step kernel of the other.
+int groups_for(const gmrf_op* Q, int64_t k) { return (Q->precond && k >= 8) ? 2 : 1; }
+
+// Side streams of the calling host thread on the current device (default priority, created once).
+gmrf_status side_streams(hipStream_t* out, int count) {
+  static thread_local std::map<int, std::array<hipStream_t, 2>> cache;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  auto it = cache.find(dev);
+  if (it == cache.end()) {
+    std::array<hipStream_t, 2> a{};
+    for (auto& x : a) HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    it = cache.emplace(dev, a).first;
+  }
+  for (int i = 0; i < count; ++i) out[i] = it->second[i];
+  return GMRF_OK;
+}
+
+// Fork: the group streams start after the work already queued on `st`; join: `st` continues after
+// everything queued on the group streams.
+struct ForkJoin {
+  hipStream_t st;
+  std::vector<hipStream_t> gs;
+  gmrf_status fork(hipStream_t s, int G) {
+    st = s;
+    gs.assign(G, s);
+    if (G == 1) return GMRF_OK;
+    gmrf_status e = side_streams(gs.data(), G);
+    if (e != GMRF_OK) return e;
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ev, st));
+    for (auto g : gs) HIP_TRY(hipStreamWaitEvent(g, ev, 0));
+    HIP_TRY(hipEventDestroy(ev));
+    return GMRF_OK;
+  }
+  gmrf_status join() {
+    if (gs.size() <= 1) return GMRF_OK;
+    for (auto g : gs) {
+      hipEvent_t ev;
+      HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      HIP_TRY(hipEventRecord(ev, g));
+      HIP_TRY(hipStreamWaitEvent(st, ev, 0));
+      HIP_TRY(hipEventDestroy(ev));
+    }
+    return GMRF_OK;
+  }
+};
 
 }  // namespace
 
@@ -609,50 +679,71 @@ template <typename T>
 static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, double tol, int m_max, int reorth,
                                double* X, gmrf_info* info, double* alpha_out, double* beta_out,
                                hipStream_t st) {
-  Workspace ws(st);
-  Run<T> R;
-  R.Q = Q;
-  R.k = (int)k;
-  R.m_max = m_max;
-  R.reorth = reorth;
-  R.tol = tol;
-  R.st = st;
-  gmrf_status s = setup<T>(R, ws);
+  const int G = groups_for(Q, k);
+  ForkJoin fj;
+  gmrf_status s = fj.fork(st, G);
   if (s != GMRF_OK) return s;
-  // slot 0 <- z (preconditioned: z in the unitary spectral basis)
-  if (Q->precond) {
-    fft_forward_init<T>(Q->plan, Z, R.slot(0), R.F1, R.S, (int)k, st);
-    precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, (int)k, st);
-  } else {
-    launch_init_from_f64<T>(Z, Q->n, R.z.L, R.slot(0), R.S, st);
+  std::vector<int64_t> c0(G + 1);
+  for (int g = 0; g <= G; ++g) c0[g] = k * g / G;
+  std::vector<std::unique_ptr<Workspace>> ws;
+  std::vector<Run<T>> Rs(G);
+  std::vector<double*> ys(G);
+  for (int g = 0; g < G; ++g) {
+    ws.emplace_back(new Workspace(fj.gs[g]));
+    Run<T>& R = Rs[g];
+    R.Q = Q;
+    R.k = (int)(c0[g + 1] - c0[g]);
+    R.m_max = m_max;
+    R.reorth = reorth;
+    R.tol = tol;
+    R.st = fj.gs[g];
+    if ((s = setup<T>(R, *ws[g])) != GMRF_OK) return s;
+    // slot 0 <- z (preconditioned: z in the unitary spectral basis, with its dot products)
+    const double* Zg = Z + (size_t)c0[g] * Q->n;
+    if (Q->precond) {
+      fft_forward_init<T>(Q->plan, Zg, R.slot(0), R.F1, R.S, R.k, R.st);
+      precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, R.k, R.st);
+    } else {
+      launch_init_from_f64<T>(Zg, Q->n, R.z.L, R.slot(0), R.S, R.st);
+    }
   }
-  if ((s = run_loop<T>(R)) != GMRF_OK) return s;
+  if ((s = run_loop<T>(Rs)) != GMRF_OK) return s;
   // y = T_m^{-1/2} e_1, then x_m = ||z|| V_m y
-  double *y, *scr;
-  if ((s = ws.alloc((size_t)k * m_max, &y)) != GMRF_OK) return s;
-  if ((s = ws.alloc(tri_scratch_doubles((int)k, m_max), &scr)) != GMRF_OK) return s;
-  launch_tri_invsqrt(R.S.alpha, m_max + 1, 1, R.S.beta, m_max + 2, 1, R.S.m_used, 0, R.S.status, y, m_max,
-                     R.S.status, scr, m_max, (int)k, st);
-  if (Q->precond) {
-    launch_combine<T, T>(R.V, R.z.L, y, m_max, R.Qb, R.z.L, R.S, st);
-    fft_backward_output<T>(Q->plan, Q->storage == GMRF_F64 ? (const void*)Q->mult64 : (const void*)Q->mult32,
-                           R.Qb, X, R.F1, R.S, (int)k, st);
-  } else {
-    launch_combine<T, double>(R.V, R.z.L, y, m_max, X, Q->n, R.S, st);
+  for (int g = 0; g < G; ++g) {
+    Run<T>& R = Rs[g];
+    double* scr;
+    if ((s = ws[g]->alloc((size_t)R.k * m_max, &ys[g])) != GMRF_OK) return s;
+    if ((s = ws[g]->alloc(tri_scratch_doubles(R.k, m_max), &scr)) != GMRF_OK) return s;
+    launch_tri_invsqrt(R.S.alpha, m_max + 1, 1, R.S.beta, m_max + 2, 1, R.S.m_used, 0, R.S.status, ys[g], m_max,
+                       R.S.status, scr, m_max, R.k, R.st);
+    double* Xg = X + (size_t)c0[g] * Q->n;
+    if (Q->precond) {
+      launch_combine<T, T>(R.V, R.z.L, ys[g], m_max, R.Qb, R.z.L, R.S, R.st);
+      fft_backward_output<T>(Q->plan, precond_mult(Q), R.Qb, Xg, R.F1, R.S, R.k, R.st);
+    } else {
+      launch_combine<T, double>(R.V, R.z.L, ys[g], m_max, Xg, Q->n, R.S, R.st);
+    }
   }
   HIP_TRY(hipGetLastError());
   // results to host
   std::vector<int> mu(k), stt(k);
   std::vector<double> rho((size_t)k * (m_max + 1)), beta((size_t)k * (m_max + 2)), alpha;
-  HIP_TRY(hipMemcpyAsync(mu.data(), R.S.m_used, k * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(stt.data(), R.S.status, k * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(rho.data(), R.S.rho, rho.size() * 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(beta.data(), R.S.beta, beta.size() * 8, hipMemcpyDeviceToHost, st));
-  if (alpha_out) {
-    alpha.resize((size_t)k * (m_max + 1));
-    HIP_TRY(hipMemcpyAsync(alpha.data(), R.S.alpha, alpha.size() * 8, hipMemcpyDeviceToHost, st));
+  if (alpha_out) alpha.resize((size_t)k * (m_max + 1));
+  for (int g = 0; g < G; ++g) {
+    Run<T>& R = Rs[g];
+    const size_t o = (size_t)c0[g];
+    HIP_TRY(hipMemcpyAsync(mu.data() + o, R.S.m_used, R.k * sizeof(int), hipMemcpyDeviceToHost, R.st));
+    HIP_TRY(hipMemcpyAsync(stt.data() + o, R.S.status, R.k * sizeof(int), hipMemcpyDeviceToHost, R.st));
+    HIP_TRY(hipMemcpyAsync(rho.data() + o * (m_max + 1), R.S.rho, (size_t)R.k * (m_max + 1) * 8,
+                           hipMemcpyDeviceToHost, R.st));
+    HIP_TRY(hipMemcpyAsync(beta.data() + o * (m_max + 2), R.S.beta, (size_t)R.k * (m_max + 2) * 8,
+                           hipMemcpyDeviceToHost, R.st));
+    if (alpha_out)
+      HIP_TRY(hipMemcpyAsync(alpha.data() + o * (m_max + 1), R.S.alpha, (size_t)R.k * (m_max + 1) * 8,
+                             hipMemcpyDeviceToHost, R.st));
   }
-  HIP_TRY(hipStreamSynchronize(st));
+  if ((s = fj.join()) != GMRF_OK) return s;
+  for (int g = 0; g < G; ++g) HIP_TRY(hipStreamSynchronize(Rs[g].st));
   double lam_lb = NAN;
   if (Q->kind == 0 && !Q->precond && Q->kappa2 > 0.0)
     lam_lb = Q->order == 1 ? Q->tau * Q->kappa2 : Q->tau * Q->kappa2 * Q->kappa2;
@@ -702,44 +793,65 @@ extern "C" gmrf_status gmrf_sample(const gmrf_op* Q, const double* Z, int64_t k,
 template <typename T>
 static gmrf_status logdet_impl(const gmrf_op* Q, int np, int m, uint64_t seed, const int8_t* probes,
                                double* logdet, double* std_err, double* per_probe, hipStream_t st) {
-  Workspace ws(st);
-  Run<T> R;
-  R.Q = Q;
-  R.k = np;
-  R.m_max = m;
-  R.reorth = 0;
-  R.tol = 0.0;
-  R.st = st;
-  R.ring3 = true;
-  gmrf_status s = setup<T>(R, ws);
+  const int G = groups_for(Q, np);
+  ForkJoin fj;
+  gmrf_status s = fj.fork(st, G);
   if (s != GMRF_OK) return s;
-  if (Q->precond) {
-    // probes in real space, then into the spectral basis
-    T* pr;
-    if ((s = ws.alloc((size_t)np * Q->n, &pr)) != GMRF_OK) return s;
-    fft_forward_init_probes<T>(Q->plan, seed, probes, pr, R.slot(0), R.F1, R.S, np, st);
-    precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, np, st);
-  } else if (probes) {
-    launch_init_from_i8<T>(probes, R.z.L, R.slot(0), R.S, st);
-  } else {
-    LzState S2 = R.S;
-    S2.Pb = rademacher_blocks(R.z.L);
-    launch_init_rademacher<T>(seed, R.z.L, R.slot(0), S2, st);
-    R.pb_first = S2.Pb;  // opener of iteration 1 reduces the probe partials
+  std::vector<int> c0(G + 1);
+  for (int g = 0; g <= G; ++g) c0[g] = (int)((int64_t)np * g / G);
+  std::vector<std::unique_ptr<Workspace>> ws;
+  std::vector<Run<T>> Rs(G);
+  for (int g = 0; g < G; ++g) {
+    ws.emplace_back(new Workspace(fj.gs[g]));
+    Run<T>& R = Rs[g];
+    R.Q = Q;
+    R.k = c0[g + 1] - c0[g];
+    R.m_max = m;
+    R.reorth = 0;
+    R.tol = 0.0;
+    R.st = fj.gs[g];
+    R.ring3 = true;
+    if ((s = setup<T>(R, *ws[g])) != GMRF_OK) return s;
+    const int8_t* pg = probes ? probes + (size_t)c0[g] * Q->n : nullptr;
+    if (Q->precond) {
+      // probes in real space, then into the spectral basis
+      T* pr;
+      if ((s = ws[g]->alloc((size_t)R.k * Q->n, &pr)) != GMRF_OK) return s;
+      fft_forward_init_probes<T>(Q->plan, seed, c0[g], pg, pr, R.slot(0), R.F1, R.S, R.k, R.st);
+      precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, R.k, R.st);
+    } else if (pg) {
+      launch_init_from_i8<T>(pg, R.z.L, R.slot(0), R.S, R.st);
+    } else {
+      LzState S2 = R.S;
+      S2.Pb = rademacher_blocks(R.z.L);
+      launch_init_rademacher<T>(seed, R.z.L, c0[g], R.slot(0), S2, R.st);
+      R.pb_first = S2.Pb;  // opener of iteration 1 reduces the probe partials
+    }
   }
-  for (int j = 1; j <= m; ++j) iterate<T>(R, j);
-  launch_finalize(R.S, st);
-  double* g;
-  if ((s = ws.alloc((size_t)np * 4, &g)) != GMRF_OK) return s;
-  launch_tri_log(R.S.alpha, m + 1, 1, R.S.beta, m + 2, 1, R.S.m_used, 0, R.S.status, g, 1, R.S.status, np, st);
-  double* agg = g + np;
-  launch_hutchinson_aggregate(g, R.S.beta, m + 2, np, Q->precond ? Q->logdet_M : 0.0, agg, st);
+  const std::vector<char> live(G, 1);
+  for (int j = 1; j <= m; ++j) iterate_all<T>(Rs, j, live);
+  // per-probe quadrature e_1^T log(T_m) e_1 and ||v_p||^2 = beta_0^2, gathered for the aggregate
+  double *g_all, *b0_all;
+  if ((s = ws[0]->alloc((size_t)np * 4, &g_all)) != GMRF_OK) return s;
+  if ((s = ws[0]->alloc((size_t)np, &b0_all)) != GMRF_OK) return s;
+  for (int g = 0; g < G; ++g) {
+    Run<T>& R = Rs[g];
+    launch_finalize(R.S, R.st);
+    launch_tri_log(R.S.alpha, m + 1, 1, R.S.beta, m + 2, 1, R.S.m_used, 0, R.S.status, g_all + c0[g], 1,
+                   R.S.status, R.k, R.st);
+    HIP_TRY(hipMemcpy2DAsync(b0_all + c0[g], sizeof(double), R.S.beta, (size_t)(m + 2) * sizeof(double),
+                             sizeof(double), R.k, hipMemcpyDeviceToDevice, R.st));
+  }
+  if ((s = fj.join()) != GMRF_OK) return s;
+  double* agg = g_all + np;
+  launch_hutchinson_aggregate(g_all, b0_all, 1, np, Q->precond ? Q->logdet_M : 0.0, agg, st);
   HIP_TRY(hipGetLastError());
   std::vector<double> gam(np), out(2);
   std::vector<int> stt(np);
   HIP_TRY(hipMemcpyAsync(gam.data(), agg + 2, np * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(out.data(), agg, 16, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(stt.data(), R.S.status, np * sizeof(int), hipMemcpyDeviceToHost, st));
+  for (int g = 0; g < G; ++g)
+    HIP_TRY(hipMemcpyAsync(stt.data() + c0[g], Rs[g].S.status, Rs[g].k * sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   for (int p = 0; p < np; ++p)
     if (stt[p] == kENOTSPD) return fail(GMRF_ENOTSPD, "probe %d: operator is not positive definite", p);

@@ -13,7 +13,7 @@ int ew_blocks(long L);
 int rademacher_blocks(long n);
 template <typename T> void launch_init_from_f64(const double* Z, long zld, long L, T* V0, const LzState& S, hipStream_t st);
 template <typename T> void launch_init_from_i8(const int8_t* P, long L, T* V0, const LzState& S, hipStream_t st);
-template <typename T> void launch_init_rademacher(uint64_t seed, long n, T* V0, const LzState& S, hipStream_t st);
+template <typename T> void launch_init_rademacher(uint64_t seed, long n, int p0, T* V0, const LzState& S, hipStream_t st);
 void launch_rademacher_i8(uint64_t seed, long n, int nprobes, int8_t* out, hipStream_t st);
 template <typename T> void launch_update(const T* Qb, const T* Vj, T* W, long L, int j, int with_norm, const LzState& S, hipStream_t st);
 void launch_hutchinson_aggregate(const double* g, const double* beta, int ldb, int np, double shift, double* out, hipStream_t st);

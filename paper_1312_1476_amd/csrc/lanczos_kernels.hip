@@ -89,15 +89,16 @@ __global__ __launch_bounds__(256) void k_rademacher_i8(uint64_t seed, long n, in
   rademacher_wave<int8_t>(seed, p, n, wave_block0, out + (size_t)p * n, acc);
 }
 
-// Probes straight into Krylov slot 0 (storage type); ||v||^2 partials per block.
+// Probes p0, p0 + 1, ... straight into Krylov slot 0 (storage type, column p - p0); ||v||^2 partials
+// per block.
 template <typename T>
-__global__ __launch_bounds__(256) void k_init_rademacher(uint64_t seed, long n, T* __restrict__ V0,
+__global__ __launch_bounds__(256) void k_init_rademacher(uint64_t seed, long n, int p0, T* __restrict__ V0,
                                                          LzState S) {
   __shared__ double lds[256 / kWave];
   const int p = blockIdx.y;
   const long wave_block0 = ((long)blockIdx.x * (256 / kWave) + threadIdx.x / kWave) * kWave;
   double acc = 0.0;
-  if (wave_block0 * 256 < n) rademacher_wave<T>(seed, p, n, wave_block0, V0 + (size_t)p * n, acc);
+  if (wave_block0 * 256 < n) rademacher_wave<T>(seed, p0 + p, n, wave_block0, V0 + (size_t)p * n, acc);
   const double s = block_sum<256>(acc, lds);
   if (threadIdx.x == 0) S.part_b[(size_t)p * S.pstride + blockIdx.x] = s;
 }
@@ -373,8 +374,8 @@ int rademacher_blocks(long n) {
   return (int)((waves + 3) / 4);
 }
 template <typename T>
-void launch_init_rademacher(uint64_t seed, long n, T* V0, const LzState& S, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_rademacher<T>, dim3(rademacher_blocks(n), S.k), dim3(256), 0, st, seed, n, V0, S);
+void launch_init_rademacher(uint64_t seed, long n, int p0, T* V0, const LzState& S, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_rademacher<T>, dim3(rademacher_blocks(n), S.k), dim3(256), 0, st, seed, n, p0, V0, S);
 }
 void launch_rademacher_i8(uint64_t seed, long n, int nprobes, int8_t* out, hipStream_t st) {
   hipLaunchKernelGGL(k_rademacher_i8, dim3(rademacher_blocks(n), nprobes), dim3(256), 0, st, seed, n, out);
@@ -410,7 +411,7 @@ void launch_combine(const T* V, long L, const double* y, int ldy, OutT* out, lon
 #define INST(T)                                                                                  \
   template void launch_init_from_f64<T>(const double*, long, long, T*, const LzState&, hipStream_t); \
   template void launch_init_from_i8<T>(const int8_t*, long, T*, const LzState&, hipStream_t);      \
-  template void launch_init_rademacher<T>(uint64_t, long, T*, const LzState&, hipStream_t);        \
+  template void launch_init_rademacher<T>(uint64_t, long, int, T*, const LzState&, hipStream_t);        \
   template void launch_update<T>(const T*, const T*, T*, long, int, int, const LzState&, hipStream_t); \
   template void launch_norm_partials<T>(const T*, long, const LzState&, hipStream_t);              \
   template void launch_reorth<T>(T*, long, int, double*, double*, int, const LzState&, hipStream_t); \

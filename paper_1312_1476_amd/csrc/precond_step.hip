@@ -56,6 +56,12 @@ namespace gmrf {
 #ifndef GMRF_STEP_WAVES
 #define GMRF_STEP_WAVES 4
 #endif
+#ifndef GMRF_STEP_PREFETCH
+#define GMRF_STEP_PREFETCH 0
+#endif
+#ifndef GMRF_STREAM_NT
+#define GMRF_STREAM_NT 0     // 1: non-temporal loads of the Krylov vectors, 2: loads and stores
+#endif
 constexpr int kStepThreads = 512;              // threads per streaming block
 constexpr int kStepWaves = GMRF_STEP_WAVES;    // waves per SIMD asked of the compiler
 constexpr int kStepRows = GMRF_STEP_ROWS;      // spectral rows per block (column dots are partial per block)
@@ -93,6 +99,32 @@ struct StepIO {
 
 template <typename T>
 __device__ __forceinline__ double rnd(double v) { return (double)(T)v; }
+
+// Krylov vectors stream through once per step; optionally with non-temporal loads and stores, which keep
+// them from evicting the tables every block re-reads (multipliers, boundary spectra) from L2.
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct Vec2<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <typename T>
+__device__ __forceinline__ C2<T> stream_load(const C2<T>* p) {
+  if constexpr (GMRF_STREAM_NT >= 1) {
+    const typename Vec2<T>::type v = __builtin_nontemporal_load((const typename Vec2<T>::type*)p);
+    return {v.x, v.y};
+  } else {
+    return *p;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void stream_store(C2<T>* p, C2<T> a) {
+  if constexpr (GMRF_STREAM_NT >= 2) {
+    typename Vec2<T>::type v;
+    v.x = a.x;
+    v.y = a.y;
+    __builtin_nontemporal_store(v, (typename Vec2<T>::type*)p);
+  } else {
+    *p = a;
+  }
+}
 
 // Row index that is the same on every lane of a row segment: with full-wave segments it is read
 // from the first lane, so row-indexed tables come through scalar loads.
@@ -711,15 +743,20 @@ __global__ __launch_bounds__(kFftThreads) void k_band_lds(int N1, int N2, const 
                                                           int j, int use_c, int periodic, StepIO<T> io) {
   constexpr int NT = kFftThreads;
   constexpr int EX = FftCfg<T>::ELEMS;
+  constexpr int TWL = 3 * EX / 16;   // twiddles an N-point stage reads: indices below 3N/4, N <= EX/4
   __shared__ C2<T> buf[EX];
   __shared__ C2<T> aux[EX];
+  __shared__ C2<T> tl1[TWL], tl2[TWL];
   __shared__ double red[NT / kWave];
   __shared__ int flag[1];
   const int r = blockIdx.y;
+  const int tid = threadIdx.x;
+  // FFT twiddles staged in LDS (every stage reads them)
+  for (int i = tid; i < 3 * N1 / 4; i += NT) tl1[i] = tw1[i];
+  for (int i = tid; i < 3 * N2 / 4; i += NT) tl2[i] = tw2[i];
   double s_cur;
   if (!band_open<NT>(S, r, j, use_c, red, flag, s_cur)) return;
   const int H = N2 / 2;
-  const int tid = threadIdx.x;
   double* pa = S.part_a + (size_t)r * S.pstride;
   C2<T>* E = io.etab + (size_t)r * 4 * H;
   C2<double>* Dt = io.dtab + (size_t)r * N1 * 2;
@@ -736,14 +773,22 @@ __global__ __launch_bounds__(kFftThreads) void k_band_lds(int N1, int N2, const 
     // ---- interior ----
     const int RH = io.CT + 1;
     const double* gp = io.gpart + (size_t)r * N1 * RH * 8;
-    for (int idx = tid; idx < 4 * N1; idx += NT) {
-      const int t = idx / N1, k1 = idx % N1;
-      double gx, gy;
-      band_row_dot(gp, k1, RH, t, s_cur, gx, gy);
-      buf[idx] = {(T)gx, (T)gy};
+    for (int k1 = tid; k1 < N1; k1 += NT) {
+      // the row's segments are contiguous: G_0, A, B, G_2 summed in segment order
+      const double* g = gp + (size_t)k1 * RH * 8;
+      double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 4
+      for (int sg = 0; sg < RH; ++sg) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a[i] += g[sg * 8 + i];
+      }
+      buf[k1] = {(T)(a[0] * s_cur), (T)(a[1] * s_cur)};
+      buf[N1 + k1] = {(T)((a[2] + a[5]) * s_cur), (T)((a[3] - a[4]) * s_cur)};   // A - i B
+      buf[2 * N1 + k1] = {(T)(a[6] * s_cur), (T)(a[7] * s_cur)};
+      buf[3 * N1 + k1] = {(T)((a[2] - a[5]) * s_cur), (T)((a[3] + a[4]) * s_cur)};   // A + i B
     }
     __syncthreads();
-    lds_fft<T, false>(buf, N1, 4, N1, 1, tw1, true);
+    lds_fft<T, false>(buf, N1, 4, N1, 1, tl1, true);
     // u(row, col_t) = Re buf[t N1 + row]
     auto ub = [&](int row, int t) { return (double)buf[t * N1 + row].x; };
     const double kk = (double)k2, tt = (double)tau;
@@ -770,7 +815,7 @@ __global__ __launch_bounds__(kFftThreads) void k_band_lds(int N1, int N2, const 
     }
     const double uDu = block_sum<NT>(acc, red);
     if (tid == 0) pa[2] = uDu;
-    lds_fft<T, false>(aux, N1, 1, N1, 1, tw1, false);
+    lds_fft<T, false>(aux, N1, 1, N1, 1, tl1, false);
     for (int k = tid; k < N1; k += NT) {
       const C2<T> zk = aux[k], zm = aux[(N1 - k) & (N1 - 1)];
       Dt[2 * k] = {0.5 * ((double)zk.x + (double)zm.x), 0.5 * ((double)zk.y - (double)zm.y)};
@@ -819,7 +864,7 @@ __global__ __launch_bounds__(kFftThreads) void k_band_lds(int N1, int N2, const 
     buf[idx] = {a.x - b.y, a.y + b.x};
   }
   __syncthreads();
-  lds_fft<T, false>(buf, N2, 3, N2, 1, tw2, true);
+  lds_fft<T, false>(buf, N2, 3, N2, 1, tl2, true);
   const BoundaryRows<T, ORDER> br{buf, N1, N2, k2};
   double acc = 0.0;
   for (int idx = tid; idx < 2 * N2; idx += NT) {
@@ -834,7 +879,7 @@ __global__ __launch_bounds__(kFftThreads) void k_band_lds(int N1, int N2, const 
   if (tid == 0) pa[half] = uDu;
   for (int t = tid; t < N2; t += NT) buf[t] = {du[t], du[N2 + t]};
   __syncthreads();
-  lds_fft<T, false>(buf, N2, 1, N2, 1, tw2, false);
+  lds_fft<T, false>(buf, N2, 1, N2, 1, tl2, false);
   C2<T>* PA = E + (size_t)(2 * half) * H;
   C2<T>* PB = PA + H;
   const T hh = (T)0.5;
@@ -882,23 +927,29 @@ struct CloseCoef {
 
 // Scalars of iteration j and alpha_j = ||v_j||^2 - <w_{j-1}, v_{j-1}> - n <u, D u> from the fixed-order
 // partial sums (||v_j|| = 1 by construction); block 0 stores alpha_j.
-__device__ __forceinline__ bool step_prologue(const LzState& S, int r, int j, double n, int* flag, double* alpha_sh,
+__device__ __forceinline__ bool step_prologue(const LzState& S, int r, int j, double n, int* flag, double* sh,
                                               double& s_cur, double& s_prev, double& bprev, double& alpha) {
-  if (!block_active(S, r, flag)) return false;
-  const double bj = S.beta[lz_ib(S, r, j - 1)];
-  s_cur = 1.0 / bj;
-  s_prev = j > 1 ? 1.0 / S.beta[lz_ib(S, r, j - 2)] : 0.0;
-  bprev = j > 1 ? bj : 0.0;
   if (threadIdx.x == 0) {
+    // one thread gathers the scalars in one round trip and shares them through LDS
     const double* pa = S.part_a + (size_t)r * S.pstride;
+    const int act = S.active[r];
+    const double bj = S.beta[lz_ib(S, r, j - 1)];
+    const double bp = j > 1 ? S.beta[lz_ib(S, r, j - 2)] : 1.0;
     double band = 0.0;
     for (int i = 0; i < kBandBlocks; ++i) band += pa[i];
     const double a = 1.0 - pa[kBandBlocks] - n * band;
-    alpha_sh[0] = a;
-    if (blockIdx.x == 0) S.alpha[lz_ia(S, r, j)] = a;
+    flag[0] = act;
+    sh[0] = a;
+    sh[1] = bj;
+    sh[2] = bp;
+    if (act && blockIdx.x == 0) S.alpha[lz_ia(S, r, j)] = a;
   }
   __syncthreads();
-  alpha = alpha_sh[0];
+  if (!flag[0]) return false;
+  alpha = sh[0];
+  s_cur = 1.0 / sh[1];
+  s_prev = j > 1 ? 1.0 / sh[2] : 0.0;
+  bprev = j > 1 ? sh[1] : 0.0;
   return true;
 }
 
@@ -952,18 +1003,42 @@ __device__ void step_col0(const C2<T>* __restrict__ vj, const C2<T>* __restrict_
 
 // One Lanczos step in the spectral basis (grid: NB * CT + 1 blocks per field).  DOTS: also the dots of
 // lambda^{-1/2} w_j / n for the next band kernel.
+// lambda_M^{-1/2} of packed column c >= 1 at row k1, in registers: b = kappa2 + mu1(k1) + mu2(c),
+// order 1: (tau b)^{-1/2}, order 2: tau^{-1/2} / b (hardware reciprocal and reciprocal square root, two
+// Newton steps each).
+struct MultEval {
+  const double* mu1;
+  double kappa2, tau, rtau;   // rtau = tau^{-1/2}
+  int order;
+  __device__ __forceinline__ double operator()(double mu2c, int k1) const {
+    const double b = kappa2 + mu1[k1] + mu2c;
+    if (order == 2) {
+      double y = __builtin_amdgcn_rcp(b);
+      y = y * (2.0 - b * y);
+      y = y * (2.0 - b * y);
+      return rtau * y;
+    }
+    const double x = tau * b;
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y;
+  }
+};
+
 template <typename T, int LG, bool DOTS>
 __global__ __launch_bounds__(kStepThreads, kStepWaves) void k_step(const C2<T>* __restrict__ Xj,
                                                                    const C2<T>* __restrict__ Xprev,
                                                                    C2<T>* __restrict__ W, int N1, int H,
-                                                                   const T* __restrict__ mult,
+                                                                   const T* __restrict__ mult, MultEval me,
+                                                                   const double* __restrict__ mu2,
                                                                    const C2<double>* __restrict__ tw1,
                                                                    const C2<double>* __restrict__ tw2, LzState S,
                                                                    int j, double n, StepIO<T> io) {
   constexpr int NT = kStepThreads;
   __shared__ double red[NT / kWave];
   __shared__ int flag[1];
-  __shared__ double alpha_sh[1];
+  __shared__ double alpha_sh[3];
   __shared__ double xch[DOTS ? NT * 4 : 1];
   const int r = blockIdx.y;
   double s_cur, s_prev, bprev, alpha;
@@ -992,20 +1067,42 @@ __global__ __launch_bounds__(kStepThreads, kStepWaves) void k_step(const C2<T>* 
   const int cc = live ? c : 1;
   CloseCoef g;
   g.init<T>(tw2, E, H, cc);
+  // band-column weights from the same twiddles: w^c = 1 - conj A_c, w^{2c} = w^c - conj(B_c - w^c)
   DotCoef dg;
-  if (DOTS) dg.init(tw2, cc);
-  const int ms = mult_stride(H);
+  dg.ga = 2.0 * (1.0 - g.Ax);
+  dg.gb = 2.0 * g.Ay;
+  dg.g2x = 2.0 * (1.0 - g.Ax - g.Bx);
+  dg.g2y = 2.0 * (g.By - g.Ay);
+  const double mu2c = mu2[cc];
   const double inv_n = live ? 1.0 / n : 0.0;
   double ca[12];
 #pragma unroll
   for (int i = 0; i < 12; ++i) ca[i] = 0.0;
   const int nsteps = ro < tl.R ? (tl.R - ro + tl.RPS - 1) / tl.RPS : 0;
+  // rows stream one ahead: the loads of row s + 1 are issued before row s is computed
+  auto row_of = [&](int s) { return seg_uniform<LG>(rb * tl.R + ro + s * tl.RPS); };
+  const C2<T> zero = {(T)0, (T)0};
+  C2<T> xn = zero, xpn = zero;
+  if (GMRF_STEP_PREFETCH != 0 && nsteps > 0) {
+    const size_t gi = (size_t)row_of(0) * H + cc;
+    xn = stream_load(vj + gi);
+    if (j > 1) xpn = stream_load(vp + gi);
+  }
   for (int s = 0; s < nsteps; ++s) {
-    const int k1 = seg_uniform<LG>(rb * tl.R + ro + s * tl.RPS);
+    const int k1 = row_of(s);
+    C2<T> x = xn, xp = xpn;
+    if (GMRF_STEP_PREFETCH == 0) {
+      const size_t g0 = (size_t)k1 * H + cc;
+      x = stream_load(vj + g0);
+      if (j > 1) xp = stream_load(vp + g0);
+    } else if (s + 1 < nsteps) {
+      const int k1n = row_of(s + 1);
+      const size_t gn = (size_t)k1n * H + cc;
+      xn = stream_load(vj + gn);
+      if (j > 1) xpn = stream_load(vp + gn);
+    }
+    const double m = me(mu2c, k1);
     const size_t gi = (size_t)k1 * H + cc;
-    const C2<T> x = vj[gi];
-    const C2<T> xp = j > 1 ? vp[gi] : C2<T>{(T)0, (T)0};
-    const double m = (double)mult[(size_t)k1 * ms + cc];
     const C2<double> t1 = tw1[k1], t2 = tw1[(2 * k1) & (N1 - 1)];
     double zx, zy;
     g.z(Dt[2 * k1], Dt[2 * k1 + 1], t1.x, -t1.y, t2.x, -t2.y, zx, zy);
@@ -1013,7 +1110,7 @@ __global__ __launch_bounds__(kStepThreads, kStepWaves) void k_step(const C2<T>* 
     const double ux = rnd<T>((double)xp.x * s_prev), uy = rnd<T>((double)xp.y * s_prev);
     const C2<T> out = {(T)(vx - m * zx - bprev * ux - alpha * vx), (T)(vy - m * zy - bprev * uy - alpha * vy)};
     if (live) {
-      wo[gi] = out;
+      stream_store(wo + gi, out);
       nb += 2.0 * ((double)out.x * (double)out.x + (double)out.y * (double)out.y);
       nc += 2.0 * ((double)out.x * vx + (double)out.y * vy);
     }
@@ -1081,9 +1178,10 @@ template <> const C2<float>* twT1<float>(const FftPlan& p) { return (const C2<fl
 template <> const C2<float>* twT2<float>(const FftPlan& p) { return (const C2<float>*)p.tw32_2; }
 
 template <typename T, int LG>
-static void launch_stream(const FftPlan& p, const T* m, const T* X, const T* Xprev, T* W, const StepIO<T>& io,
-                          const LzState& S, int j, int k, hipStream_t st, int kind) {
+static void launch_stream(const FftPlan& p, const StencilGeom& g, int order, const T* m, const T* X, const T* Xprev,
+                          T* W, const StepIO<T>& io, const LzState& S, int j, int k, hipStream_t st, int kind) {
   const double n = (double)p.N1 * (double)p.N2;
+  MultEval me{p.mu1, g.kappa2, g.tau, 1.0 / std::sqrt(g.tau), order};
   const C2<double>* t1 = (const C2<double>*)p.tw64_1;
   const C2<double>* t2 = (const C2<double>*)p.tw64_2;
   const dim3 grid(precond_step_counts(p).Ps, k);
@@ -1092,22 +1190,22 @@ static void launch_stream(const FftPlan& p, const T* m, const T* X, const T* Xpr
                        t2, S, io);
   else if (kind == 1)
     hipLaunchKernelGGL((k_step<T, LG, true>), grid, dim3(kStepThreads), 0, st, (const C2<T>*)X, (const C2<T>*)Xprev,
-                       (C2<T>*)W, p.N1, p.H, m, t1, t2, S, j, n, io);
+                       (C2<T>*)W, p.N1, p.H, m, me, (const double*)p.mu2, t1, t2, S, j, n, io);
   else
     hipLaunchKernelGGL((k_step<T, LG, false>), grid, dim3(kStepThreads), 0, st, (const C2<T>*)X, (const C2<T>*)Xprev,
-                       (C2<T>*)W, p.N1, p.H, m, t1, t2, S, j, n, io);
+                       (C2<T>*)W, p.N1, p.H, m, me, (const double*)p.mu2, t1, t2, S, j, n, io);
 }
 
 // kind 0: dots of X; 1: step with dots; 2: step without dots
 template <typename T>
-static void stream(const FftPlan& p, const T* m, const T* X, const T* Xprev, T* W, const StepIO<T>& io,
-                   const LzState& S, int j, int k, hipStream_t st, int kind) {
+static void stream(const FftPlan& p, const StencilGeom& g, int order, const T* m, const T* X, const T* Xprev, T* W,
+                   const StepIO<T>& io, const LzState& S, int j, int k, hipStream_t st, int kind) {
   switch (spec_tile(p.N1, p.H, kStepThreads, 1).LG) {
-    case 4: launch_stream<T, 4>(p, m, X, Xprev, W, io, S, j, k, st, kind); break;
-    case 8: launch_stream<T, 8>(p, m, X, Xprev, W, io, S, j, k, st, kind); break;
-    case 16: launch_stream<T, 16>(p, m, X, Xprev, W, io, S, j, k, st, kind); break;
-    case 32: launch_stream<T, 32>(p, m, X, Xprev, W, io, S, j, k, st, kind); break;
-    default: launch_stream<T, 64>(p, m, X, Xprev, W, io, S, j, k, st, kind); break;
+    case 4: launch_stream<T, 4>(p, g, order, m, X, Xprev, W, io, S, j, k, st, kind); break;
+    case 8: launch_stream<T, 8>(p, g, order, m, X, Xprev, W, io, S, j, k, st, kind); break;
+    case 16: launch_stream<T, 16>(p, g, order, m, X, Xprev, W, io, S, j, k, st, kind); break;
+    case 32: launch_stream<T, 32>(p, g, order, m, X, Xprev, W, io, S, j, k, st, kind); break;
+    default: launch_stream<T, 64>(p, g, order, m, X, Xprev, W, io, S, j, k, st, kind); break;
   }
 }
 
@@ -1115,7 +1213,7 @@ template <typename T>
 void precond_dots(const FftPlan& p, const void* mult, const T* X, void* scratch, const LzState& S, int k,
                   hipStream_t st) {
   const StepIO<T> io = step_io<T>(p, scratch, k, nullptr);
-  stream<T>(p, (const T*)mult, X, nullptr, nullptr, io, S, 0, k, st, 0);
+  stream<T>(p, StencilGeom{}, 0, (const T*)mult, X, nullptr, nullptr, io, S, 0, k, st, 0);
 }
 
 template <typename T>
@@ -1142,8 +1240,8 @@ void precond_lanczos_step(const FftPlan& p, const StencilGeom& g, int order, con
       hipLaunchKernelGGL((k_band_global<T, 2>), grid, dim3(kFftThreads), 0, st, p.N1, p.N2, twT1<T>(p), twT2<T>(p),
                          k2, tau, S, j, use_c, g.periodic, io);
   }
-  if (only < 0 || only == 2) stream<T>(p, m, Xj, Xprev, W, io, S, j, k, st, dots ? 1 : 2);
-  if (only == 0) stream<T>(p, m, Xj, nullptr, nullptr, io, S, 0, k, st, 0);
+  if (only < 0 || only == 2) stream<T>(p, g, order, m, Xj, Xprev, W, io, S, j, k, st, dots ? 1 : 2);
+  if (only == 0) stream<T>(p, g, order, m, Xj, nullptr, nullptr, io, S, 0, k, st, 0);
 }
 
 #define INST(T)                                                                                                  \
