@@ -31,7 +31,10 @@ import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 DOMINANT_KERNEL = "lz_step"      # largest share of the step in the committed rocprofv3 summary
-TRAFFIC_GB = None                # FETCH_SIZE/WRITE_SIZE per launch, once counters are taken
+COPY_BYTES = 512 << 20           # reference copy of the counter runs (--only counters)
+# HBM bytes per launch of the dominant kernel from the committed counter summary: FETCH_SIZE x 2 +
+# WRITE_SIZE x 1 (KiB per dispatch, scaled by the reference copy's readings); None if the kernel changed
+TRAFFIC_BYTES = None
 TOL_HEADLINE = 1e-5
 M_MAX_HEADLINE = 600
 
@@ -48,7 +51,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
-    ap.add_argument("--only", default="", help="profiling: run only this leg (headline|kernel)")
+    ap.add_argument("--only", default="", help="profiling: run only this leg (headline|counters)")
     return ap.parse_args()
 
 
@@ -73,6 +76,18 @@ def main():
         return gm.Operator.lattice(sp.shape, sp.order, sp.kappa2, sp.tau, sp.boundary, storage).set_circulant_precond()
 
     op64 = make("f64")
+
+    if args.only == "counters":
+        # workload of the hardware-counter runs: the dominant kernel alone, then a plain device copy of
+        # known size whose FETCH_SIZE / WRITE_SIZE readings scale the counters to bytes
+        r = gm.kernel_bench(op64, DOMINANT_KERNEL, k, reps=50, stream=stream)
+        a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel": DOMINANT_KERNEL, "avg_us": r["avg_us"], "copy_bytes": COPY_BYTES}))
+        return
 
     def step(op, tol, m_max):
         return op.sample(Z, tol=tol, m_max=m_max, reorth=False)
@@ -150,7 +165,7 @@ def main():
     roof = gm.kernel_bench(op64, DOMINANT_KERNEL, k, reps=50, stream=stream)
     result["roofline"] = {"bound": "hbm", "achieved": round(roof["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": round(roof["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                          "traffic": TRAFFIC_GB, "kernel": roof["kernel"], "avg_us": round(roof["avg_us"], 2),
+                          "traffic": TRAFFIC_BYTES, "kernel": roof["kernel"], "avg_us": round(roof["avg_us"], 2),
                           "bytes_per_launch": roof["bytes"]}
     kern = {}
     for name in ("lz_band", "lz_dots"):

@@ -913,8 +913,8 @@ extern "C" gmrf_status gmrf_tridiag_log_e1(const double* alpha, const double* be
 //        2 = dot-product kernel of the preconditioned step (reads one vector)
 //        3 = update w = q - alpha v (unpreconditioned path)
 //        4 = band kernel of the preconditioned step
-// Buffers are allocated and zero-filled before the first event; `reps` launches run between two HIP
-// events recorded on `stream`.  bytes = algorithmic bytes of one launch (each input read once, each
+// Buffers are allocated and filled (Krylov slots with seeded +-1 values, scratch with zeros) before the
+// first event; `reps` launches run between two HIP events recorded on `stream`.  bytes = algorithmic bytes of one launch (each input read once, each
 // output written once; the small hand-off tables between the kernels of a step are not counted).
 template <typename T>
 static gmrf_status kernel_bench_impl(const gmrf_op* Q, int which, int k, int reps, double* avg_us, double* bytes,
@@ -929,14 +929,18 @@ static gmrf_status kernel_bench_impl(const gmrf_op* Q, int which, int k, int rep
   R.st = st;
   gmrf_status s = setup<T>(R, ws);
   if (s != GMRF_OK) return s;
-  // beta_j = 1, partial sums = 1, zero vectors: every column active, no stop decision triggers
+  // seeded +-1 vectors in every slot (representative bit patterns, unlike zero fill); then beta_j = 1 and
+  // partial sums = 1: every column active, no stop decision triggers
   {
+    LzState S2 = R.S;
+    S2.Pb = rademacher_blocks(R.z.L);
+    if (S2.Pb > R.z.pstride) return fail(GMRF_EDEVICE, "kernel bench: partial-sum stride too small");
+    for (int s = 0; s < R.z.slots; ++s) launch_init_rademacher<T>(0x5eed + s, R.z.L, 0, R.slot(s), S2, st);
     std::vector<double> ones((size_t)k * (R.m_max + 2), 1.0);
     HIP_TRY(hipMemcpyAsync(R.S.beta, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, st));
     std::vector<double> pones((size_t)k * R.z.pstride, 1.0);
     HIP_TRY(hipMemcpyAsync(R.S.part_b, pones.data(), pones.size() * 8, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(R.S.part_a, pones.data(), pones.size() * 8, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemsetAsync(R.V, 0, (size_t)R.z.slots * k * R.z.vec_bytes, st));
     if (R.band) HIP_TRY(hipMemsetAsync(R.band, 0, precond_step_bytes(Q->plan, Q->storage, k), st));
     HIP_TRY(hipStreamSynchronize(st));
   }

@@ -926,31 +926,51 @@ struct CloseCoef {
 };
 
 // Scalars of iteration j and alpha_j = ||v_j||^2 - <w_{j-1}, v_{j-1}> - n <u, D u> from the fixed-order
-// partial sums (||v_j|| = 1 by construction); block 0 stores alpha_j.
-__device__ __forceinline__ bool step_prologue(const LzState& S, int r, int j, double n, int* flag, double* sh,
-                                              double& s_cur, double& s_prev, double& bprev, double& alpha) {
-  if (threadIdx.x == 0) {
-    // one thread gathers the scalars in one round trip and shares them through LDS
-    const double* pa = S.part_a + (size_t)r * S.pstride;
-    const int act = S.active[r];
-    const double bj = S.beta[lz_ib(S, r, j - 1)];
-    const double bp = j > 1 ? S.beta[lz_ib(S, r, j - 2)] : 1.0;
-    double band = 0.0;
-    for (int i = 0; i < kBandBlocks; ++i) band += pa[i];
-    const double a = 1.0 - pa[kBandBlocks] - n * band;
-    flag[0] = act;
-    sh[0] = a;
-    sh[1] = bj;
-    sh[2] = bp;
-    if (act && blockIdx.x == 0) S.alpha[lz_ia(S, r, j)] = a;
-  }
-  __syncthreads();
-  if (!flag[0]) return false;
-  alpha = sh[0];
-  s_cur = 1.0 / sh[1];
-  s_prev = j > 1 ? 1.0 / sh[2] : 0.0;
-  bprev = j > 1 ? sh[1] : 0.0;
-  return true;
+// partial sums (||v_j|| = 1 by construction), gathered by thread 0 into LDS (flag, sh[0..2]) in one round
+// trip; block 0 stores alpha_j.  The caller issues its own loads before the barrier that publishes them.
+__device__ __forceinline__ void step_scalars(const LzState& S, int r, int j, double n, int* flag, double* sh) {
+  const double* pa = S.part_a + (size_t)r * S.pstride;
+  const int act = S.active[r];
+  const double bj = S.beta[lz_ib(S, r, j - 1)];
+  const double bp = j > 1 ? S.beta[lz_ib(S, r, j - 2)] : 1.0;
+  double band = 0.0;
+  for (int i = 0; i < kBandBlocks; ++i) band += pa[i];
+  const double a = 1.0 - pa[kBandBlocks] - n * band;
+  flag[0] = act;
+  sh[0] = a;
+  sh[1] = bj;
+  sh[2] = bp;
+  if (act && blockIdx.x == 0) S.alpha[lz_ia(S, r, j)] = a;
+}
+// A value known to be the same on every lane, kept in scalar registers.
+__device__ __forceinline__ double uniform_d(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ void step_read_scalars(int j, const double* sh, double& s_cur, double& s_prev,
+                                                  double& bprev, double& alpha) {
+  alpha = uniform_d(sh[0]);
+  const double b1 = uniform_d(sh[1]), b2 = uniform_d(sh[2]);
+  s_cur = 1.0 / b1;
+  s_prev = j > 1 ? 1.0 / b2 : 0.0;
+  bprev = j > 1 ? b1 : 0.0;
+}
+
+// Sum over the wave of two values: afterwards lanes 0..31 hold the total of a, lanes 32..63 that of b
+// (v_permlane32_swap pairs the halves, v_permlane16_swap the rows, then a row mirror, a half-row
+// mirror and two quad permutes; no LDS traffic).
+__device__ __forceinline__ double wave_sum2(double a, double b) {
+  swap32(a, b);
+  double v = a + b;
+  double u = v;
+  swap16(v, u);
+  v += u;
+  v += dpp<kDppRowMirror>(v);
+  v += dpp<kDppRowHalfMirror>(v);
+  v += dpp<kDppQuadXor2>(v);
+  v += dpp<kDppQuadXor1>(v);
+  return v;
 }
 
 template <int NT>
@@ -1010,8 +1030,8 @@ struct MultEval {
   const double* mu1;
   double kappa2, tau, rtau;   // rtau = tau^{-1/2}
   int order;
-  __device__ __forceinline__ double operator()(double mu2c, int k1) const {
-    const double b = kappa2 + mu1[k1] + mu2c;
+  __device__ __forceinline__ double operator()(double mu2c, int k1) const { return eval(kappa2 + mu1[k1] + mu2c); }
+  __device__ __forceinline__ double eval(double b) const {
     if (order == 2) {
       double y = __builtin_amdgcn_rcp(b);
       y = y * (2.0 - b * y);
@@ -1026,6 +1046,13 @@ struct MultEval {
   }
 };
 
+// Per-row values of a block's rows, staged in LDS once per block: cos/sin of theta, 2 theta, e^{-3 i theta}
+// (theta = 2 pi k1 / N1), D0(k1), D1(k1) and mu1(k1).
+constexpr int kRowTab = 12;
+// s_waitcnt operand: vector memory count 0, export and LDS/scalar counts left at their maxima
+constexpr int kWaitVm0 = (7 << 4) | (15 << 8);
+enum { RT_C1 = 0, RT_S1, RT_C2, RT_S2, RT_T3X, RT_T3Y, RT_D0X, RT_D0Y, RT_D1X, RT_D1Y, RT_MU1 };
+
 template <typename T, int LG, bool DOTS>
 __global__ __launch_bounds__(kStepThreads, kStepWaves) void k_step(const C2<T>* __restrict__ Xj,
                                                                    const C2<T>* __restrict__ Xprev,
@@ -1036,13 +1063,13 @@ __global__ __launch_bounds__(kStepThreads, kStepWaves) void k_step(const C2<T>* 
                                                                    const C2<double>* __restrict__ tw2, LzState S,
                                                                    int j, double n, StepIO<T> io) {
   constexpr int NT = kStepThreads;
-  __shared__ double red[NT / kWave];
+  constexpr int NW = NT / kWave;
+  __shared__ double red[2 * NW];
   __shared__ int flag[1];
-  __shared__ double alpha_sh[3];
-  __shared__ double xch[DOTS ? NT * 4 : 1];
+  __shared__ double sh[3];
+  __shared__ __align__(16) double rowtab[kStepRows * kRowTab];
+  __shared__ double xch[DOTS ? 12 * NT : 1];
   const int r = blockIdx.y;
-  double s_cur, s_prev, bprev, alpha;
-  if (!step_prologue(S, r, j, n, flag, alpha_sh, s_cur, s_prev, bprev, alpha)) return;
   const SpecTile tl = spec_tile(N1, H, NT, kStepRows);
   const size_t fsz = (size_t)N1 * H;
   const C2<T>* vj = Xj + (size_t)r * fsz;
@@ -1051,8 +1078,14 @@ __global__ __launch_bounds__(kStepThreads, kStepWaves) void k_step(const C2<T>* 
   const C2<T>* E = io.etab + (size_t)r * 4 * H;
   const C2<double>* Dt = io.dtab + (size_t)r * N1 * 2;
   double* gpart = io.gpart + (size_t)r * N1 * (tl.CT + 1) * 8;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  double s_cur, s_prev, bprev, alpha;
   double nb = 0.0, nc = 0.0;
   if ((int)blockIdx.x == tl.NB * tl.CT) {
+    if (tid == 0) step_scalars(S, r, j, n, flag, sh);
+    __syncthreads();
+    if (!flag[0]) return;
+    step_read_scalars(j, sh, s_cur, s_prev, bprev, alpha);
     step_col0<T, NT>(vj, vp, wo, N1, H, mult, tw1, E, Dt, j, s_cur, s_prev, bprev, alpha, nb, nc);
     __threadfence_block();   // column 0 of w_j is read back by other threads of this block
     step_norms<NT>(S, r, nb, nc, red);
@@ -1060,72 +1093,150 @@ __global__ __launch_bounds__(kStepThreads, kStepWaves) void k_step(const C2<T>* 
     return;
   }
   const int rb = blockIdx.x / tl.CT, ct = blockIdx.x - rb * tl.CT;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int row0 = rb * tl.R;
   const int tlane = tid % LG, ro = tid / LG;
   const int c = ct * LG + tlane;
   const bool live = c != 0;   // column 0 belongs to the extra block
   const int cc = live ? c : 1;
+  const int nsteps = ro < tl.R ? (tl.R - ro + tl.RPS - 1) / tl.RPS : 0;
+  auto row_of = [&](int s) { return seg_uniform<LG>(row0 + ro + s * tl.RPS); };
+  // Everything the block needs before its first row is requested at once, ahead of the one barrier:
+  // the iteration scalars (thread 0), the per-row table (one thread per row), the per-column
+  // coefficients and the first row of v_j and v_{j-1}.
+  const C2<T> zero = {(T)0, (T)0};
+  C2<T> xa = zero, xpa = zero, xb = zero, xpb = zero;
+  if (nsteps > 0) {
+    const int g0 = row_of(0) * H + cc;
+    xa = stream_load(vj + g0);
+    xpa = stream_load(vp + g0);
+  }
+  if (tid == 0) step_scalars(S, r, j, n, flag, sh);
+  for (int i = tid - (NT - kWave); i >= 0 && i < tl.R; i += kWave) {
+    // the last wave fills the table (thread 0's scalar gather runs in the first)
+    const int k1 = row0 + i;
+    const C2<double> t1 = tw1[k1], t2 = tw1[(2 * k1) & (N1 - 1)], t3 = tw1[(3 * k1) & (N1 - 1)];
+    const C2<double> d0 = Dt[2 * k1], d1 = Dt[2 * k1 + 1];
+    double* rt = rowtab + i * kRowTab;
+    rt[RT_C1] = t1.x;
+    rt[RT_S1] = -t1.y;
+    rt[RT_C2] = t2.x;
+    rt[RT_S2] = -t2.y;
+    rt[RT_T3X] = t3.x;
+    rt[RT_T3Y] = t3.y;
+    rt[RT_D0X] = d0.x;
+    rt[RT_D0Y] = d0.y;
+    rt[RT_D1X] = d1.x;
+    rt[RT_D1Y] = d1.y;
+    rt[RT_MU1] = me.mu1[k1];
+  }
   CloseCoef g;
   g.init<T>(tw2, E, H, cc);
-  // band-column weights from the same twiddles: w^c = 1 - conj A_c, w^{2c} = w^c - conj(B_c - w^c)
-  DotCoef dg;
-  dg.ga = 2.0 * (1.0 - g.Ax);
-  dg.gb = 2.0 * g.Ay;
-  dg.g2x = 2.0 * (1.0 - g.Ax - g.Bx);
-  dg.g2y = 2.0 * (g.By - g.Ay);
   const double mu2c = mu2[cc];
-  const double inv_n = live ? 1.0 / n : 0.0;
+  __syncthreads();
+  if (!flag[0]) return;
+  step_read_scalars(j, sh, s_cur, s_prev, bprev, alpha);
+  const double inv_n = 1.0 / n;
+  const double b0 = me.kappa2 + mu2c;   // kappa2 + mu2(c), per lane, formed before the loop
   double ca[12];
 #pragma unroll
   for (int i = 0; i < 12; ++i) ca[i] = 0.0;
-  const int nsteps = ro < tl.R ? (tl.R - ro + tl.RPS - 1) / tl.RPS : 0;
-  // rows stream one ahead: the loads of row s + 1 are issued before row s is computed
-  auto row_of = [&](int s) { return seg_uniform<LG>(rb * tl.R + ro + s * tl.RPS); };
-  const C2<T> zero = {(T)0, (T)0};
-  C2<T> xn = zero, xpn = zero;
-  if (GMRF_STEP_PREFETCH != 0 && nsteps > 0) {
-    const size_t gi = (size_t)row_of(0) * H + cc;
-    xn = stream_load(vj + gi);
-    if (j > 1) xpn = stream_load(vp + gi);
-  }
-  for (int s = 0; s < nsteps; ++s) {
+  // Loads are issued unconditionally (row index clamped; at j = 1 Xprev is a valid vector whose value is
+  // not used): the hardware wait counter is in order, and a load that some paths skip would make the
+  // compiler wait for every load in flight.
+  auto load_row = [&](int s, C2<T>& a, C2<T>& ap) {
+    const int gi = row_of(min(s, nsteps - 1)) * H + cc;
+    a = stream_load(vj + gi);
+    ap = stream_load(vp + gi);
+  };
+  auto do_row = [&](int s, C2<T> x, C2<T> xp) {
     const int k1 = row_of(s);
-    C2<T> x = xn, xp = xpn;
-    if (GMRF_STEP_PREFETCH == 0) {
-      const size_t g0 = (size_t)k1 * H + cc;
-      x = stream_load(vj + g0);
-      if (j > 1) xp = stream_load(vp + g0);
-    } else if (s + 1 < nsteps) {
-      const int k1n = row_of(s + 1);
-      const size_t gn = (size_t)k1n * H + cc;
-      xn = stream_load(vj + gn);
-      if (j > 1) xpn = stream_load(vp + gn);
-    }
-    const double m = me(mu2c, k1);
-    const size_t gi = (size_t)k1 * H + cc;
-    const C2<double> t1 = tw1[k1], t2 = tw1[(2 * k1) & (N1 - 1)];
+    const double* rt = rowtab + (k1 - row0) * kRowTab;
+    const C2<double> t1 = {rt[RT_C1], rt[RT_S1]}, t2 = {rt[RT_C2], rt[RT_S2]};
+    const C2<double> D0 = {rt[RT_D0X], rt[RT_D0Y]}, D1 = {rt[RT_D1X], rt[RT_D1Y]};
+    const double m = me.eval(b0 + rt[RT_MU1]);
     double zx, zy;
-    g.z(Dt[2 * k1], Dt[2 * k1 + 1], t1.x, -t1.y, t2.x, -t2.y, zx, zy);
+    g.z(D0, D1, t1.x, t1.y, t2.x, t2.y, zx, zy);
     const double vx = rnd<T>((double)x.x * s_cur), vy = rnd<T>((double)x.y * s_cur);
-    const double ux = rnd<T>((double)xp.x * s_prev), uy = rnd<T>((double)xp.y * s_prev);
+    const double ux = j > 1 ? rnd<T>((double)xp.x * s_prev) : 0.0;
+    const double uy = j > 1 ? rnd<T>((double)xp.y * s_prev) : 0.0;
     const C2<T> out = {(T)(vx - m * zx - bprev * ux - alpha * vx), (T)(vy - m * zy - bprev * uy - alpha * vy)};
     if (live) {
-      stream_store(wo + gi, out);
+      stream_store(wo + (k1 * H + cc), out);
       nb += 2.0 * ((double)out.x * (double)out.x + (double)out.y * (double)out.y);
       nc += 2.0 * ((double)out.x * vx + (double)out.y * vy);
     }
     if (DOTS) {
-      const double f = m * inv_n;
-      double r0, r1, r2, r3, r4, r5, r6, r7;
-      dot_elem(dg, f * (double)out.x, f * (double)out.y, t1, t2, tw1[(3 * k1) & (N1 - 1)], ca, r0, r1, r2, r3, r4,
-               r5, r6, r7);
-      store_row_dots<LG>(gpart + ((size_t)k1 * (tl.CT + 1) + ct) * 8, lane, r0, r1, r2, r3, r4, r5, r6, r7);
+      const double f = live ? m * inv_n : 0.0;
+      const double yx = f * (double)out.x, yy = f * (double)out.y;
+      // band-column weights through the closed-form coefficients (w^c = 1 - conj A_c,
+      // w^{2c} = w^c - conj(B_c - w^c)): with r0 = 2 y,
+      //   2 Re w^c y = r0 - A_x r0,  2 Im w^c y = A_y r0,  2 w^{2c} y = (1 - A_x - B_x) r0 - i (B_y - A_y) r0
+      const double r0 = 2.0 * yx, r1 = 2.0 * yy;
+      const double r2 = r0 - g.Ax * r0, r3 = r1 - g.Ax * r1;
+      const double r4 = g.Ay * r0, r5 = g.Ay * r1;
+      const double r6 = r2 + r5 - g.Bx * r0 - g.By * r1;
+      const double r7 = r3 - r4 - g.Bx * r1 + g.By * r0;
+      ca[0] += yx;
+      ca[1] += yy;
+      ca[2] += t1.x * yx;
+      ca[3] += t1.x * yy;
+      ca[4] += t1.y * yx;
+      ca[5] += t1.y * yy;
+      ca[6] += t2.x * yx;
+      ca[7] += t2.x * yy;
+      ca[8] += t2.y * yx;
+      ca[9] += t2.y * yy;
+      const double t3x = rt[RT_T3X], t3y = rt[RT_T3Y];
+      ca[10] += t3x * yx - t3y * yy;
+      ca[11] += t3x * yy + t3y * yx;
+      store_row_dots<LG>(gpart + ((k1 * (tl.CT + 1) + ct) * 8), lane, r0, r1, r2, r3, r4, r5, r6, r7);
+    }
+  };
+  // Two register sets take turns (no copies between them), so that one row's loads are in flight while
+  // the other row is computed.  The loads issued before the loop are drained first: the wait counter
+  // is in order, and a wait for them inside the loop would also wait for the row in flight.
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
+  for (int s = 0; s < nsteps; s += 2) {
+    load_row(s + 1, xb, xpb);
+    do_row(s, xa, xpa);
+    load_row(s + 2, xa, xpa);
+    if (s + 1 < nsteps) do_row(s + 1, xb, xpb);
+  }
+  // Epilogue, one barrier: per-wave sums of ||w||^2 and <w, v_j>, and the column dots of every
+  // (value, column) pair, combined below in fixed order.
+  const double ws = wave_sum2(nb, nc);
+  const int w = tid / kWave;
+  if (lane == 0) red[2 * w] = ws;
+  if (lane == 32) red[2 * w + 1] = ws;
+  if (DOTS) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) xch[i * NT + tid] = ca[i];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double sb = 0.0, sc = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      sb += red[2 * i];
+      sc += red[2 * i + 1];
+    }
+    S.part_b[(size_t)r * S.pstride + blockIdx.x] = sb;
+    S.part_c[(size_t)r * S.pstride + blockIdx.x] = sc;
+  }
+  if (DOTS) {
+    // slot q (P0, P1, R1, P2, R2, H3) of column ct * LG + t: values 2q and 2q + 1 summed over the row groups
+    const int nro = min(tl.RPS, tl.R);
+    C2<double>* cp = io.cpart + ((size_t)r * tl.NB + rb) * 6 * H;
+    for (int pq = tid; pq < 6 * LG; pq += NT) {
+      const int q = pq / LG, t = pq - q * LG;
+      double sx = 0.0, sy = 0.0;
+      for (int o = 0; o < nro; ++o) {
+        sx += xch[(2 * q) * NT + o * LG + t];
+        sy += xch[(2 * q + 1) * NT + o * LG + t];
+      }
+      cp[(size_t)q * H + ct * LG + t] = {sx, sy};
     }
   }
-  step_norms<NT>(S, r, nb, nc, red);
-  if (DOTS)
-    store_col_dots<NT>(ca, xch, tid, ro, tlane, LG, min(tl.RPS, tl.R), io.cpart + ((size_t)r * tl.NB + rb) * 6 * H,
-                       H, c);
 }
 
 // ---- host side -----------------------------------------------------------------------------------------
