@@ -34,7 +34,7 @@ DOMINANT_KERNEL = "lz_step"      # largest share of the step in the committed ro
 COPY_BYTES = 512 << 20           # reference copy of the counter runs (--only counters)
 # HBM bytes per launch of the dominant kernel from the committed counter summary: FETCH_SIZE x 2 +
 # WRITE_SIZE x 1 (KiB per dispatch, scaled by the reference copy's readings); None if the kernel changed
-TRAFFIC_BYTES = None
+TRAFFIC_BYTES = 225601472      # k_step<double, 64, true>, 512x512, 32 fields (profiles/k_step_precond_512x512_32rhs_fp64.md)
 TOL_HEADLINE = 1e-5
 M_MAX_HEADLINE = 600
 
