@@ -231,7 +231,7 @@ gmrf_status gmrf_op_create_lattice(int ndim, const int64_t* shape, int order, do
   op->geom.periodic = bc == GMRF_PERIODIC;
   op->geom.kappa2 = kappa2;
   op->geom.tau = tau;
-  stencil_geom_tiles(op->geom, ndim);
+  stencil_geom_tiles(op->geom, ndim, order);
   *out = op;
   return GMRF_OK;
 }

@@ -148,6 +148,170 @@ __global__ __launch_bounds__(256) void k_stencil(StencilGeom g0, const T* __rest
   }
 }
 
+// ---- 2D lattices: row-streaming waves ---------------------------------------------------------
+// One wave per 64-column strip (kWave - 2 ORDER output columns, the strips overlap by ORDER columns
+// on each side) walks down a band of kS2Band rows.  Vertical neighbours stay in registers; each row
+// of v (and, for order 2, of K v) passes through a small per-wave LDS row buffer for its left and
+// right neighbours, so the row loop has no block barrier.  Rows are requested S2Ahead rows ahead,
+// unconditionally (row index clamped or wrapped), so that several rows are in flight per wave.
+// Free boundary: a missing neighbour is replaced by the point itself, so its difference is exactly 0
+// (same terms in the same order as k_stencil).
+constexpr int kS2Waves = 4;     // waves per block (bands stacked vertically)
+constexpr int kS2Band = 32;     // output rows per wave
+// rows requested ahead per wave: a row is 64 elements, so FP32 rows carry half the bytes of FP64 rows
+#ifndef GMRF_S2_AHEAD64
+#define GMRF_S2_AHEAD64 4
+#endif
+#ifndef GMRF_S2_AHEAD32
+#define GMRF_S2_AHEAD32 8
+#endif
+template <typename T> struct S2Ahead;
+template <> struct S2Ahead<double> { static constexpr int value = GMRF_S2_AHEAD64; };
+template <> struct S2Ahead<float> { static constexpr int value = GMRF_S2_AHEAD32; };
+
+template <typename T, int ORDER, bool LZ>
+__global__ __launch_bounds__(256) void k_stencil2d(StencilGeom g0, const T* __restrict__ X, long xld,
+                                                   T* __restrict__ Y, long yld, const T* __restrict__ Xprev,
+                                                   LzState S, int j, const int* __restrict__ active) {
+  constexpr int OX = kWave - 2 * ORDER;
+  __shared__ T vrow[kS2Waves][2][kWave];
+  __shared__ T trow[kS2Waves][2][kWave];
+  __shared__ double red[256 / kWave];
+  __shared__ int flag[1];
+  const int r = blockIdx.y;
+  const StencilGeom g = (LZ && S.col_geom) ? S.col_geom[r] : g0;
+  if ((int)blockIdx.x >= g.tiles_x * g.tiles_y) return;
+  double s_cur = 1.0, s_prev = 0.0, bprev = 0.0;
+  if (LZ) {
+    if (!lz_open<256>(S, r, j, blockIdx.x == 0, red, flag, s_cur, s_prev, bprev)) return;
+  } else if (active && !active[r]) {
+    return;
+  }
+  const int n1 = g.n1, n2 = g.n2;
+  const bool per = g.periodic != 0;
+  const int tx = blockIdx.x % g.tiles_x, ty = blockIdx.x / g.tiles_x;
+  // wave index read as a scalar: the row loop's bounds are then uniform and its branches scalar
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
+  const int x = tx * OX - ORDER + lane;                       // this lane's column
+  const int gx = per ? ((x % n2) + n2) % n2 : min(max(x, 0), n2 - 1);
+  const bool hl = per || x > 0, hr = per || x < n2 - 1;       // left / right neighbour inside
+  const bool olane = lane >= ORDER && lane < kWave - ORDER && x < n2;
+  const int lm = (lane - 1) & (kWave - 1), lp = (lane + 1) & (kWave - 1);
+  const int y_lo = (ty * kS2Waves + w) * kS2Band;
+  const int y_hi = min(y_lo + kS2Band, n1);
+  const int count = y_hi > y_lo ? y_hi - y_lo + 2 * ORDER : 0;   // input rows y_lo - ORDER .. y_hi + ORDER - 1
+  const int ys = y_lo - ORDER;
+  const size_t roff = (LZ && S.col_off) ? (size_t)S.col_off[r] : (size_t)r * xld;
+  const T* src = X + roff + gx;
+  T* dst = Y + ((LZ && S.col_off) ? roff : (size_t)r * yld);
+  const T* prv = LZ ? Xprev + roff + min(max(x, 0), n2 - 1) : nullptr;
+  // rows requested lie in [-ORDER, n1 + ORDER): one wrap suffices unless the lattice is tiny
+  const bool tiny = n1 <= 2 * ORDER;
+  auto rowi = [&](int y) {
+    if (!per) return min(max(y, 0), n1 - 1);
+    if (tiny) return ((y % n1) + n1) % n1;
+    return y < 0 ? y + n1 : (y >= n1 ? y - n1 : y);
+  };
+  auto ld = [&](int i) { return src[(size_t)rowi(ys + min(i, count - 1)) * n2]; };
+  // v_{j-1} at output row ys + i - ORDER (LZ): requested with the row, row and column clamped so that
+  // every lane loads (a load some lanes skip would make the compiler wait for all rows in flight)
+  auto ldp = [&](int i) {
+    const int yo = min(max(ys + min(i, count - 1) - ORDER, 0), n1 - 1);
+    return prv[(size_t)yo * n2];
+  };
+  const T k2 = (T)g.kappa2, tau = (T)g.tau;
+  // K at row yc of a value v with vertical neighbours u (yc - 1), d (yc + 1), horizontal from buffer b
+  auto kop = [&](T v, T u, T d, const T* b, int yc) {
+    const T bl = b[lm], br = b[lp];   // read by every lane, then selected (no masked LDS reads)
+    const T l = hl ? bl : v, rr = hr ? br : v;
+    const T uu = (per || yc > 0) ? u : v, dd = (per || yc < n1 - 1) ? d : v;
+    T acc = k2 * v;
+    acc += v - l;
+    acc += v - rr;
+    acc += v - uu;
+    acc += v - dd;
+    return acc;
+  };
+  T v0 = (T)0, v1 = (T)0, t0 = (T)0, t1 = (T)0;
+  double acc = 0.0;
+  // Input row i (row ys + i).  The LDS row slots alternate with i; par = i & 1 is a constant once the
+  // loops below are unrolled.  OUT: the row produces an output (i >= LEAD); T2: it forms K v (i >= 2).
+  constexpr int LEAD = 2 * ORDER;   // input rows consumed before the first output
+  auto step = [&](int i, int par, bool T2, bool OUT, T raw, T rawp) {
+    const T v2 = LZ ? (T)((double)raw * s_cur) : raw;
+    vrow[w][par][lane] = v2;
+    const int yi = ys + i;
+    T oc = (T)0, vc = v1;                      // output value and v at the output row
+    int yo;
+    if (ORDER == 1) {
+      yo = yi - 1;
+      if (OUT) oc = tau * kop(v1, v0, v2, vrow[w][par ^ 1], yo);
+    } else {
+      T t2 = (T)0;
+      if (T2) {
+        t2 = kop(v1, v0, v2, vrow[w][par ^ 1], yi - 1);
+        trow[w][par ^ 1][lane] = t2;
+      }
+      yo = yi - 2;
+      vc = v0;
+      if (OUT) oc = tau * kop(t1, t0, t2, trow[w][par], yo);
+      t0 = t1;
+      t1 = t2;
+    }
+    if (OUT && olane) {
+      const size_t o = (size_t)yo * n2 + x;
+      if (LZ) {
+        double q = (double)oc;
+        if (j > 1) q -= bprev * (double)(T)((double)rawp * s_prev);
+        const T qt = (T)q;
+        dst[o] = qt;
+        acc += (double)vc * (double)qt;
+      } else {
+        dst[o] = oc;
+      }
+    }
+    v0 = v1;
+    v1 = v2;
+  };
+  if (count > 0) {
+    // AHEAD register sets take turns (unrolled, no copies between them): row i lives in set i % AHEAD
+    // and is computed while rows i + 1 .. i + AHEAD - 1 are in flight
+    constexpr int AHEAD = S2Ahead<T>::value;
+    static_assert(AHEAD >= LEAD && AHEAD % 2 == 0, "prefetch depth");
+    T q[AHEAD], p[AHEAD];
+#pragma unroll
+    for (int d = 0; d < AHEAD; ++d) {
+      q[d] = ld(d);
+      p[d] = LZ ? ldp(d) : (T)0;
+    }
+#pragma unroll
+    for (int d = 0; d < LEAD; ++d) {   // warm-up rows: no output
+      step(d, d & 1, d >= 2, false, q[d], p[d]);
+      q[d] = ld(d + AHEAD);
+      if (LZ) p[d] = ldp(d + AHEAD);
+    }
+    int i = LEAD;
+    for (; i + AHEAD <= count; i += AHEAD) {
+#pragma unroll
+      for (int d = 0; d < AHEAD; ++d) {
+        const int c = (LEAD + d) % AHEAD;
+        step(i + d, (LEAD + d) & 1, true, true, q[c], p[c]);
+        q[c] = ld(i + d + AHEAD);
+        if (LZ) p[c] = ldp(i + d + AHEAD);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < AHEAD; ++d) {   // tail: the rows left, already requested
+      const int c = (LEAD + d) % AHEAD;
+      if (i + d < count) step(i + d, (LEAD + d) & 1, true, true, q[c], p[c]);
+    }
+  }
+  if (LZ) {
+    const double bs = block_sum<256>(acc, red);
+    if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + blockIdx.x] = bs;
+  }
+}
+
 // ---- CSR: one thread per row ----------------------------------------------------------------
 template <typename T, bool LZ>
 __global__ __launch_bounds__(256) void k_csr(long n, const int64_t* __restrict__ rp,
@@ -187,10 +351,10 @@ __global__ __launch_bounds__(256) void k_csr(long n, const int64_t* __restrict__
 }
 
 // ---- host side --------------------------------------------------------------------------------
-void stencil_geom_tiles(StencilGeom& g, int dim) {
+void stencil_geom_tiles(StencilGeom& g, int dim, int order) {
   int TZ, TY, TX;
   if (dim == 1) { TZ = TileShape<1>::TZ; TY = TileShape<1>::TY; TX = TileShape<1>::TX; }
-  else if (dim == 2) { TZ = TileShape<2>::TZ; TY = TileShape<2>::TY; TX = TileShape<2>::TX; }
+  else if (dim == 2) { TZ = 1; TY = kS2Waves * kS2Band; TX = kWave - 2 * order; }   // k_stencil2d
   else { TZ = TileShape<3>::TZ; TY = TileShape<3>::TY; TX = TileShape<3>::TX; }
   g.tiles_x = (g.n2 + TX - 1) / TX;
   g.tiles_y = (g.n1 + TY - 1) / TY;
@@ -203,8 +367,12 @@ template <typename T, int ORDER, int DIM, bool LZ>
 static void launch_stencil_t(const StencilGeom& g, const T* X, long xld, T* Y, long yld,
                              const T* Xprev, const LzState& S, int j, int k, hipStream_t st,
                              const int* active = nullptr) {
-  hipLaunchKernelGGL((k_stencil<T, ORDER, DIM, LZ>), dim3(stencil_blocks(g), k), dim3(256), 0, st, g,
-                     X, xld, Y, yld, Xprev, S, j, active);
+  if constexpr (DIM == 2)
+    hipLaunchKernelGGL((k_stencil2d<T, ORDER, LZ>), dim3(stencil_blocks(g), k), dim3(256), 0, st, g, X, xld, Y,
+                       yld, Xprev, S, j, active);
+  else
+    hipLaunchKernelGGL((k_stencil<T, ORDER, DIM, LZ>), dim3(stencil_blocks(g), k), dim3(256), 0, st, g,
+                       X, xld, Y, yld, Xprev, S, j, active);
 }
 
 template <typename T>
@@ -232,8 +400,15 @@ void launch_stencil_batch(int order, int dim, int max_tiles, const T* X, T* Y, c
                        Xprev, S, j, (const int*)nullptr);                                                    \
     return;                                                                                                   \
   }
-  CASEB(1, 1) CASEB(1, 2) CASEB(1, 3) CASEB(2, 1) CASEB(2, 2) CASEB(2, 3)
+#define CASEB2(O)                                                                                            \
+  if (order == O && dim == 2) {                                                                               \
+    hipLaunchKernelGGL((k_stencil2d<T, O, true>), dim3(max_tiles, S.k), dim3(256), 0, st, g, X, 0L, Y, 0L,  \
+                       Xprev, S, j, (const int*)nullptr);                                                    \
+    return;                                                                                                   \
+  }
+  CASEB(1, 1) CASEB2(1) CASEB(1, 3) CASEB(2, 1) CASEB2(2) CASEB(2, 3)
 #undef CASEB
+#undef CASEB2
 }
 template void launch_stencil_batch<double>(int, int, int, const double*, double*, const double*, const LzState&,
                                            int, hipStream_t);
