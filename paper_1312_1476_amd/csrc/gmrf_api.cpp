@@ -625,16 +625,25 @@ gmrf_status run_loop(std::vector<Run<T>>& Rs) {
 
 // Independent column groups of one call run side by side: with the preconditioned step the band
 // kernel of one group (a few blocks, latency-bound) overlaps the streaming step kernel of the other.
-int groups_for(const gmrf_op* Q, int64_t k) { return (Q->precond && k >= 8) ? 2 : 1; }
+// Column groups of a preconditioned call, each on its own stream (at least 4 columns per group).
+#ifndef GMRF_PRECOND_GROUPS
+#define GMRF_PRECOND_GROUPS 2
+#endif
+constexpr int kMaxGroups = 4;
+static_assert(GMRF_PRECOND_GROUPS >= 1 && GMRF_PRECOND_GROUPS <= kMaxGroups, "column groups");
+int groups_for(const gmrf_op* Q, int64_t k) {
+  if (!Q->precond) return 1;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(GMRF_PRECOND_GROUPS, k / 4));
+}
 
 // Side streams of the calling host thread on the current device (default priority, created once).
 gmrf_status side_streams(hipStream_t* out, int count) {
-  static thread_local std::map<int, std::array<hipStream_t, 2>> cache;
+  static thread_local std::map<int, std::array<hipStream_t, kMaxGroups>> cache;
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   auto it = cache.find(dev);
   if (it == cache.end()) {
-    std::array<hipStream_t, 2> a{};
+    std::array<hipStream_t, kMaxGroups> a{};
     for (auto& x : a) HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
     it = cache.emplace(dev, a).first;
   }
