@@ -36,6 +36,7 @@ COPY_BYTES = 512 << 20           # reference copy of the counter runs (--only co
 # WRITE_SIZE x 1 (KiB per dispatch, scaled by the reference copy's readings); None if the kernel changed
 TRAFFIC_BYTES = 225601472      # k_step<double, 64, true>, 512x512, 32 fields (profiles/k_step_precond_512x512_32rhs_fp64.md)
 TOL_HEADLINE = 1e-5
+SERVE_RATES = (2, 4, 8)          # requests/s of the serving leg (the queue saturates near 8-16)
 M_MAX_HEADLINE = 600
 
 
@@ -52,6 +53,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
     ap.add_argument("--only", default="", help="profiling: run only this leg (headline|counters)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-seconds", type=float, default=4.0, help="arrival window per serving rate")
     return ap.parse_args()
 
 
@@ -180,6 +183,10 @@ def main():
                       "avg_us": round(r["avg_us"], 2), "bytes_per_launch": r["bytes"]}
     result["spmv_13pt_32rhs"] = spmv
 
+    # ---- serving: Poisson request stream over a pool of 64 resident operators ---------------------------
+    if not args.no_serve:
+        result["serving"] = serving_leg(gm, torch, args.serve_seconds)
+
     # ---- oracle legs ----------------------------------------------------------------------------------
     if not args.no_cpu:
         from oracle import lattice as olat, precond as opre
@@ -206,6 +213,37 @@ def main():
     result["at_m_max_300"] = {"f64": extra["f64"], "f32": extra["f32"]}
     result["fp32_storage_at_tol"] = extra["f32_tol"]
     print(json.dumps(result))
+
+
+def serving_leg(gm, torch, seconds):
+    """Continuous batching (serve.Server, 4 worker streams, HBM budget = 80% of free memory) of the
+    seeded request stream: samples (tol 1e-5, m_max 300) and log-det estimates (m = 80) on 2D
+    first-order lattices (side log-uniform on [64, 2048]) and 3D 7-point lattices (side 16..128),
+    k uniform on 1..32.  The request sizes are heavy-tailed (up to 2048^2 x 32 right-hand sides x 300
+    steps), and one GPU saturates between 8 and 16 requests/s, so the rates stay at or below that;
+    latency = arrival to result."""
+    from paper_1312_1476_amd import serve
+    pool = workloads.serving_pool()
+    ops = [gm.Operator.lattice(p.shape, p.order, p.kappa2, p.tau, "free", "f64") for p in pool]
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    out = {"pool": "64 operators: 2D 5-point (80%), 3D 7-point (20%)", "workers": 4,
+           "hbm_budget_gb": round(budget / 1e9, 1), "arrival_window_s": seconds, "rates": {}}
+    for rate in SERVE_RATES:
+        trace = workloads.serving_trace(rate=rate, duration=seconds)
+        reqs = [serve.ServeRequest(i, r.kind, r.op_index, r.k, r.seed, m_max=(300 if r.kind == "sample" else 80),
+                                   t_arrival=r.t_arrival) for i, r in enumerate(trace)]
+        srv = serve.Server(ops, budget, workers=4, keep_results=False).start()
+        st = srv.run_trace(reqs)
+        srv.stop()
+        out["rates"][f"{rate}_req_per_s"] = {
+            "requests": st["requests"], "completed": st["completed"], "rejected": st["rejected"],
+            "wall_s": round(st["wall_s"], 2), "p50_latency_s": round(st["p50_latency_s"], 4),
+            "p99_latency_s": round(st["p99_latency_s"], 4), "samples_per_s": round(st["samples_per_s"], 2),
+            "probes_per_s": round(st["probes_per_s"], 2)}
+    for op in ops:
+        op.close()
+    return out
 
 
 if __name__ == "__main__":
