@@ -25,6 +25,7 @@ struct StencilGeom {
   int periodic;
   double kappa2, tau;
   int tiles_x, tiles_y, tiles_z;
+  int epl;                 // 2D kernel: elements per lane (1 or 2)
 };
 
 // Per-call Lanczos state, all device memory.  Index conventions (1-based j as in
@@ -51,6 +52,7 @@ struct LzState {
   int H;                // packed columns per spectral row (weighted mode)
   // Uneven batches (many fields in one launch): per-column tables, all nullptr otherwise.
   const int64_t* col_off;         // offset of column r inside a slot (default r * L)
+  const int64_t* col_ext;         // offset of column r in the caller's Z and X (default col_off)
   const int* col_len;             // length of column r (default L)
   const int* col_pa;              // op-kernel partials of column r (default Pa)
   const int* col_pb;              // elementwise partials of column r (default Pb)

@@ -418,10 +418,14 @@ static void op_apply_lz(const gmrf_op* Q, const T* X, T* Y, const T* Xprev, cons
 template <typename T>
 static void op_apply_plain(const gmrf_op* Q, const T* X, T* Y, int k, hipStream_t st) {
   LzState S{};
-  if (Q->kind == 0)
-    launch_stencil<T>(Q->geom, Q->order, Q->dim, false, X, Q->n, Y, Q->n, nullptr, S, 0, k, st);
-  else
-    launch_csr<T>((long)Q->n, Q->rp, Q->ci, (const T*)Q->va, false, X, Q->n, Y, Q->n, nullptr, S, 0, k, st);
+  if (Q->kind == 0) {
+    // caller buffers may not be aligned for the 2D kernel's element pairs: then one element per lane
+    StencilGeom g = Q->geom;
+    if (g.epl == 2 && (((uintptr_t)X | (uintptr_t)Y) % (2 * sizeof(T))) != 0) stencil_geom_tiles(g, Q->dim, Q->order, 1);
+    launch_stencil<T>(g, Q->order, Q->dim, false, X, Q->n, Y, Q->n, nullptr, S, 0, k, st);
+    return;
+  }
+  launch_csr<T>((long)Q->n, Q->rp, Q->ci, (const T*)Q->va, false, X, Q->n, Y, Q->n, nullptr, S, 0, k, st);
 }
 
 extern "C" gmrf_status gmrf_op_apply(const gmrf_op* Q, const void* X, void* Y, int64_t k, void* stream) {
@@ -1019,25 +1023,30 @@ template <typename T>
 static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const int64_t* kf, const double* Z, double tol,
                                      int m_max, double* X, gmrf_info* info, hipStream_t st) {
   const gmrf_op* Q0 = ops[0];
-  std::vector<int64_t> off;
+  std::vector<int64_t> off, ext;   // column offsets inside a Krylov slot, and in the caller's Z and X
   std::vector<int> len, pa, pb, field;
   std::vector<StencilGeom> geom;
-  int64_t tot = 0;
+  int64_t tot = 0, tot_ext = 0;
   int max_tiles = 1;
   long max_len = 1;
   for (int f = 0; f < nf; ++f) {
     const gmrf_op* Q = ops[f];
-    const int tiles = stencil_blocks(Q->geom);
+    // inside the Krylov slots every column starts at an even offset, so that the 2D kernel's element
+    // pairs (even row length) stay aligned: each field is then tiled as it is when sampled alone
+    const StencilGeom gf = Q->geom;
+    const int tiles = stencil_blocks(gf);
     max_tiles = std::max(max_tiles, tiles);
     max_len = std::max<long>(max_len, (long)Q->n);
     for (int64_t r = 0; r < kf[f]; ++r) {
       off.push_back(tot);
+      ext.push_back(tot_ext);
       len.push_back((int)Q->n);
       pa.push_back(tiles);
       pb.push_back(ew_blocks((long)Q->n));
-      geom.push_back(Q->geom);
+      geom.push_back(gf);
       field.push_back(f);
-      tot += Q->n;
+      tot += (Q->n + 1) & ~(int64_t)1;
+      tot_ext += Q->n;
     }
   }
   const int K = (int)off.size();
@@ -1053,7 +1062,8 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
   int* ibuf;
   if ((s = ws.alloc((size_t)6 * K, &ibuf)) != GMRF_OK) return s;
   int64_t* doff;
-  if ((s = ws.alloc((size_t)K, &doff)) != GMRF_OK) return s;
+  if ((s = ws.alloc((size_t)2 * K, &doff)) != GMRF_OK) return s;
+  int64_t* dext = doff + K;
   StencilGeom* dgeom;
   if ((s = ws.alloc((size_t)K, &dgeom)) != GMRF_OK) return s;
   LzState S{};
@@ -1076,6 +1086,7 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
   S.Pb = ew_blocks(max_len);
   S.pstride = pstride;
   S.col_off = doff;
+  S.col_ext = dext;
   S.col_len = dlen;
   S.col_pa = dpa;
   S.col_pb = dpb;
@@ -1085,6 +1096,7 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
   HIP_TRY(hipMemsetAsync(ibuf, 0, 2 * K * sizeof(int), st));
   HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)S.active, 1, K, st));
   HIP_TRY(hipMemcpyAsync(doff, off.data(), K * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(dext, ext.data(), K * sizeof(int64_t), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(dlen, len.data(), K * sizeof(int), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(dpa, pa.data(), K * sizeof(int), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(dpb, pb.data(), K * sizeof(int), hipMemcpyHostToDevice, st));

@@ -23,7 +23,9 @@ template <typename T> void launch_reorth(T* V, long L, int j, double* part_h, do
 template <typename T, typename OutT> void launch_combine(const T* V, long L, const double* y, int ldy, OutT* out, long old, const LzState& S, hipStream_t st);
 
 // operator_kernels.hip
-void stencil_geom_tiles(StencilGeom& g, int dim, int order);
+// epl: elements per lane of the 2D kernel (0: 2 when the row length is even; 1 for fields packed at
+// arbitrary offsets)
+void stencil_geom_tiles(StencilGeom& g, int dim, int order, int epl = 0);
 int stencil_blocks(const StencilGeom& g);
 template <typename T> void launch_stencil(const StencilGeom& g, int order, int dim, bool lz, const T* X, long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k, hipStream_t st);
 template <typename T> void launch_stencil_batch(int order, int dim, int max_tiles, const T* X, T* Y, const T* Xprev, const LzState& S, int j, hipStream_t st);

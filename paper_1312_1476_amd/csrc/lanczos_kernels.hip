@@ -18,7 +18,8 @@ __global__ __launch_bounds__(kEwThreads) void k_init_from_f64(const double* __re
   const long len = lz_len(S, r, L);
   if ((long)blockIdx.x * kEwChunk >= len) return;
   const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
-  const double* z = Z + (S.col_off ? (size_t)S.col_off[r] : (size_t)r * zld);
+  const int64_t* ext = S.col_ext ? S.col_ext : S.col_off;
+  const double* z = Z + (ext ? (size_t)ext[r] : (size_t)r * zld);
   T* v = V0 + lz_off(S, r, L);
   double acc = 0.0;
   EW_LOOP(q) {
@@ -295,7 +296,8 @@ __global__ __launch_bounds__(kEwThreads) void k_combine(const T* __restrict__ V,
   const double beta0 = S.beta[lz_ib(S, r, 0)];
   const size_t vs = lz_slot(S, L);
   const size_t voff = lz_off(S, r, L);
-  const size_t ooff = S.col_off ? (size_t)S.col_off[r] : (size_t)r * old;
+  const int64_t* ext = S.col_ext ? S.col_ext : S.col_off;
+  const size_t ooff = ext ? (size_t)ext[r] : (size_t)r * old;
   const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
   double acc[kEwPerThread];
   EW_LOOP(q) acc[q] = 0.0;

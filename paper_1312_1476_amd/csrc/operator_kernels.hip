@@ -169,13 +169,205 @@ template <typename T> struct S2Ahead;
 template <> struct S2Ahead<double> { static constexpr int value = GMRF_S2_AHEAD64; };
 template <> struct S2Ahead<float> { static constexpr int value = GMRF_S2_AHEAD32; };
 
+// Elements of a lane: EPL = 2 adjacent columns (one vector load) when the geometry allows it (even row
+// length and even field offsets), else 1.  With EPL = 2 the strips start 2 columns left of their first
+// output, so lanes hold aligned pairs and a pair never straddles the lattice edge.
+template <typename T, int EPL> struct VecE;
+template <typename T> struct VecE<T, 1> {
+  typedef T type;
+  __device__ static T get(const type& v, int) { return v; }
+};
+template <> struct VecE<double, 2> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  __device__ static double get(const type& v, int e) { return v[e]; }
+};
+template <> struct VecE<float, 2> {
+  typedef float type __attribute__((ext_vector_type(2)));
+  __device__ static float get(const type& v, int e) { return v[e]; }
+};
+__host__ __device__ inline int s2_halo(int order, int epl) { return epl == 2 ? 2 : order; }
+__host__ __device__ inline int s2_out(int order, int epl) { return kWave * epl - 2 * s2_halo(order, epl); }
+
+template <typename T, int ORDER, bool LZ, int EPL>
+__device__ __forceinline__ void s2_strip(const StencilGeom& g, int tx, int ty, int w, int lane,
+                                         const T* __restrict__ src, T* __restrict__ dst,
+                                         const T* __restrict__ prv, int j, double s_cur, double s_prev,
+                                         double bprev, T* vbuf, T* tbuf, double& acc) {
+  using VE = VecE<T, EPL>;
+  using VT = typename VE::type;
+  constexpr int HX = EPL == 2 ? 2 : ORDER;
+  constexpr int OX = kWave * EPL - 2 * HX;
+  constexpr int RW = kWave * EPL;                               // row-slot width
+  const int n1 = g.n1, n2 = g.n2;
+  const bool per = g.periodic != 0;
+  const int xb = tx * OX - HX + lane * EPL;                     // first column of this lane
+  // column of the lane's load: clamped (free) or wrapped (periodic), pair-aligned when EPL = 2
+  const int xl = per ? ((xb % n2) + n2) % n2 : min(max(xb, 0), n2 - EPL);
+  bool hl[EPL], hr[EPL];
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    hl[e] = per || xb + e > 0;
+    hr[e] = per || xb + e < n2 - 1;
+  }
+  const bool olane = lane * EPL >= HX && lane * EPL < RW - HX && xb >= 0 && xb < n2;
+  const int lm = (lane * EPL - 1) & (RW - 1), lp = (lane * EPL + EPL) & (RW - 1);
+  const int y_lo = (ty * kS2Waves + w) * kS2Band;
+  const int y_hi = min(y_lo + kS2Band, n1);
+  const int count = y_hi > y_lo ? y_hi - y_lo + 2 * ORDER : 0;   // input rows y_lo - ORDER .. y_hi + ORDER - 1
+  if (count == 0) return;
+  const int ys = y_lo - ORDER;
+  const int xp = min(max(xb, 0), n2 - EPL);                       // v_{j-1} column (clamped, aligned)
+  const bool tiny = n1 <= 2 * ORDER;
+  auto rowi = [&](int y) {
+    if (!per) return min(max(y, 0), n1 - 1);
+    if (tiny) return ((y % n1) + n1) % n1;
+    return y < 0 ? y + n1 : (y >= n1 ? y - n1 : y);
+  };
+  auto ld = [&](int i) { return *(const VT*)(src + (size_t)rowi(ys + min(i, count - 1)) * n2 + xl); };
+  auto ldp = [&](int i) {
+    const int yo = min(max(ys + min(i, count - 1) - ORDER, 0), n1 - 1);
+    return *(const VT*)(prv + (size_t)yo * n2 + xp);
+  };
+  const T k2 = (T)g.kappa2, tau = (T)g.tau;
+  // K at row yc of element e: centre c[e], vertical u[e], d[e]; horizontal from the row slot b and the
+  // lane's own neighbouring element
+  auto kop = [&](const T (&c)[EPL], const T (&u)[EPL], const T (&d)[EPL], const T* b, int yc, T (&out)[EPL]) {
+    const T bl = b[lm], br = b[lp];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const T v = c[e];
+      const T ln = e > 0 ? c[e > 0 ? e - 1 : 0] : bl;
+      const T rn = e < EPL - 1 ? c[e < EPL - 1 ? e + 1 : 0] : br;
+      const T l = hl[e] ? ln : v, rr = hr[e] ? rn : v;
+      const T uu = (per || yc > 0) ? u[e] : v, dd = (per || yc < n1 - 1) ? d[e] : v;
+      T a = k2 * v;
+      a += v - l;
+      a += v - rr;
+      a += v - uu;
+      a += v - dd;
+      out[e] = a;
+    }
+  };
+  T v0[EPL], v1[EPL], t0[EPL], t1[EPL];
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) v0[e] = v1[e] = t0[e] = t1[e] = (T)0;
+  constexpr int LEAD = 2 * ORDER;   // input rows consumed before the first output
+  auto store_row = [&](T* buf, int par, const T (&val)[EPL]) {
+    VT vv;
+    if constexpr (EPL == 1) {
+      vv = val[0];
+    } else {
+      vv[0] = val[0];
+      vv[1] = val[1];
+    }
+    *(VT*)(buf + par * RW + lane * EPL) = vv;
+  };
+  auto step = [&](int i, int par, bool T2, bool OUT, const VT& raw, const VT& rawp) {
+    T v2[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) v2[e] = LZ ? (T)((double)VE::get(raw, e) * s_cur) : VE::get(raw, e);
+    store_row(vbuf, par, v2);
+    const int yi = ys + i;
+    T oc[EPL], vc[EPL];
+    int yo;
+    if (ORDER == 1) {
+      yo = yi - 1;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) vc[e] = v1[e];
+      if (OUT) {
+        kop(v1, v0, v2, vbuf + (par ^ 1) * RW, yo, oc);
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) oc[e] = tau * oc[e];
+      }
+    } else {
+      T t2[EPL];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) t2[e] = (T)0;
+      if (T2) {
+        kop(v1, v0, v2, vbuf + (par ^ 1) * RW, yi - 1, t2);
+        store_row(tbuf, par ^ 1, t2);
+      }
+      yo = yi - 2;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) vc[e] = v0[e];
+      if (OUT) {
+        kop(t1, t0, t2, tbuf + par * RW, yo, oc);
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) oc[e] = tau * oc[e];
+      }
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        t0[e] = t1[e];
+        t1[e] = t2[e];
+      }
+    }
+    if (OUT && olane) {
+      T res[EPL];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        if (LZ) {
+          double q = (double)oc[e];
+          if (j > 1) q -= bprev * (double)(T)((double)VE::get(rawp, e) * s_prev);
+          res[e] = (T)q;
+          acc += (double)vc[e] * (double)res[e];
+        } else {
+          res[e] = oc[e];
+        }
+      }
+      VT vv;
+      if constexpr (EPL == 1) {
+        vv = res[0];
+      } else {
+        vv[0] = res[0];
+        vv[1] = res[1];
+      }
+      *(VT*)(dst + (size_t)yo * n2 + xb) = vv;
+    }
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      v0[e] = v1[e];
+      v1[e] = v2[e];
+    }
+  };
+  // AHEAD register sets take turns (unrolled, no copies between them): row i lives in set i % AHEAD and
+  // is computed while rows i + 1 .. i + AHEAD - 1 are in flight
+  constexpr int AHEAD = S2Ahead<T>::value;
+  static_assert(AHEAD >= LEAD && AHEAD % 2 == 0, "prefetch depth");
+  VT q[AHEAD], p[AHEAD];
+#pragma unroll
+  for (int d = 0; d < AHEAD; ++d) {
+    q[d] = ld(d);
+    p[d] = LZ ? ldp(d) : q[d];
+  }
+#pragma unroll
+  for (int d = 0; d < LEAD; ++d) {   // warm-up rows: no output
+    step(d, d & 1, d >= 2, false, q[d], p[d]);
+    q[d] = ld(d + AHEAD);
+    if (LZ) p[d] = ldp(d + AHEAD);
+  }
+  int i = LEAD;
+  for (; i + AHEAD <= count; i += AHEAD) {
+#pragma unroll
+    for (int d = 0; d < AHEAD; ++d) {
+      const int c = (LEAD + d) % AHEAD;
+      step(i + d, (LEAD + d) & 1, true, true, q[c], p[c]);
+      q[c] = ld(i + d + AHEAD);
+      if (LZ) p[c] = ldp(i + d + AHEAD);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < AHEAD; ++d) {   // tail: the rows left, already requested
+    const int c = (LEAD + d) % AHEAD;
+    if (i + d < count) step(i + d, (LEAD + d) & 1, true, true, q[c], p[c]);
+  }
+}
+
 template <typename T, int ORDER, bool LZ>
 __global__ __launch_bounds__(256) void k_stencil2d(StencilGeom g0, const T* __restrict__ X, long xld,
                                                    T* __restrict__ Y, long yld, const T* __restrict__ Xprev,
                                                    LzState S, int j, const int* __restrict__ active) {
-  constexpr int OX = kWave - 2 * ORDER;
-  __shared__ T vrow[kS2Waves][2][kWave];
-  __shared__ T trow[kS2Waves][2][kWave];
+  __shared__ __align__(16) T vrow[kS2Waves][2][2 * kWave];
+  __shared__ __align__(16) T trow[kS2Waves][2][2 * kWave];
   __shared__ double red[256 / kWave];
   __shared__ int flag[1];
   const int r = blockIdx.y;
@@ -187,125 +379,20 @@ __global__ __launch_bounds__(256) void k_stencil2d(StencilGeom g0, const T* __re
   } else if (active && !active[r]) {
     return;
   }
-  const int n1 = g.n1, n2 = g.n2;
-  const bool per = g.periodic != 0;
   const int tx = blockIdx.x % g.tiles_x, ty = blockIdx.x / g.tiles_x;
   // wave index read as a scalar: the row loop's bounds are then uniform and its branches scalar
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
-  const int x = tx * OX - ORDER + lane;                       // this lane's column
-  const int gx = per ? ((x % n2) + n2) % n2 : min(max(x, 0), n2 - 1);
-  const bool hl = per || x > 0, hr = per || x < n2 - 1;       // left / right neighbour inside
-  const bool olane = lane >= ORDER && lane < kWave - ORDER && x < n2;
-  const int lm = (lane - 1) & (kWave - 1), lp = (lane + 1) & (kWave - 1);
-  const int y_lo = (ty * kS2Waves + w) * kS2Band;
-  const int y_hi = min(y_lo + kS2Band, n1);
-  const int count = y_hi > y_lo ? y_hi - y_lo + 2 * ORDER : 0;   // input rows y_lo - ORDER .. y_hi + ORDER - 1
-  const int ys = y_lo - ORDER;
   const size_t roff = (LZ && S.col_off) ? (size_t)S.col_off[r] : (size_t)r * xld;
-  const T* src = X + roff + gx;
+  const T* src = X + roff;
   T* dst = Y + ((LZ && S.col_off) ? roff : (size_t)r * yld);
-  const T* prv = LZ ? Xprev + roff + min(max(x, 0), n2 - 1) : nullptr;
-  // rows requested lie in [-ORDER, n1 + ORDER): one wrap suffices unless the lattice is tiny
-  const bool tiny = n1 <= 2 * ORDER;
-  auto rowi = [&](int y) {
-    if (!per) return min(max(y, 0), n1 - 1);
-    if (tiny) return ((y % n1) + n1) % n1;
-    return y < 0 ? y + n1 : (y >= n1 ? y - n1 : y);
-  };
-  auto ld = [&](int i) { return src[(size_t)rowi(ys + min(i, count - 1)) * n2]; };
-  // v_{j-1} at output row ys + i - ORDER (LZ): requested with the row, row and column clamped so that
-  // every lane loads (a load some lanes skip would make the compiler wait for all rows in flight)
-  auto ldp = [&](int i) {
-    const int yo = min(max(ys + min(i, count - 1) - ORDER, 0), n1 - 1);
-    return prv[(size_t)yo * n2];
-  };
-  const T k2 = (T)g.kappa2, tau = (T)g.tau;
-  // K at row yc of a value v with vertical neighbours u (yc - 1), d (yc + 1), horizontal from buffer b
-  auto kop = [&](T v, T u, T d, const T* b, int yc) {
-    const T bl = b[lm], br = b[lp];   // read by every lane, then selected (no masked LDS reads)
-    const T l = hl ? bl : v, rr = hr ? br : v;
-    const T uu = (per || yc > 0) ? u : v, dd = (per || yc < n1 - 1) ? d : v;
-    T acc = k2 * v;
-    acc += v - l;
-    acc += v - rr;
-    acc += v - uu;
-    acc += v - dd;
-    return acc;
-  };
-  T v0 = (T)0, v1 = (T)0, t0 = (T)0, t1 = (T)0;
+  const T* prv = LZ ? Xprev + roff : nullptr;
   double acc = 0.0;
-  // Input row i (row ys + i).  The LDS row slots alternate with i; par = i & 1 is a constant once the
-  // loops below are unrolled.  OUT: the row produces an output (i >= LEAD); T2: it forms K v (i >= 2).
-  constexpr int LEAD = 2 * ORDER;   // input rows consumed before the first output
-  auto step = [&](int i, int par, bool T2, bool OUT, T raw, T rawp) {
-    const T v2 = LZ ? (T)((double)raw * s_cur) : raw;
-    vrow[w][par][lane] = v2;
-    const int yi = ys + i;
-    T oc = (T)0, vc = v1;                      // output value and v at the output row
-    int yo;
-    if (ORDER == 1) {
-      yo = yi - 1;
-      if (OUT) oc = tau * kop(v1, v0, v2, vrow[w][par ^ 1], yo);
-    } else {
-      T t2 = (T)0;
-      if (T2) {
-        t2 = kop(v1, v0, v2, vrow[w][par ^ 1], yi - 1);
-        trow[w][par ^ 1][lane] = t2;
-      }
-      yo = yi - 2;
-      vc = v0;
-      if (OUT) oc = tau * kop(t1, t0, t2, trow[w][par], yo);
-      t0 = t1;
-      t1 = t2;
-    }
-    if (OUT && olane) {
-      const size_t o = (size_t)yo * n2 + x;
-      if (LZ) {
-        double q = (double)oc;
-        if (j > 1) q -= bprev * (double)(T)((double)rawp * s_prev);
-        const T qt = (T)q;
-        dst[o] = qt;
-        acc += (double)vc * (double)qt;
-      } else {
-        dst[o] = oc;
-      }
-    }
-    v0 = v1;
-    v1 = v2;
-  };
-  if (count > 0) {
-    // AHEAD register sets take turns (unrolled, no copies between them): row i lives in set i % AHEAD
-    // and is computed while rows i + 1 .. i + AHEAD - 1 are in flight
-    constexpr int AHEAD = S2Ahead<T>::value;
-    static_assert(AHEAD >= LEAD && AHEAD % 2 == 0, "prefetch depth");
-    T q[AHEAD], p[AHEAD];
-#pragma unroll
-    for (int d = 0; d < AHEAD; ++d) {
-      q[d] = ld(d);
-      p[d] = LZ ? ldp(d) : (T)0;
-    }
-#pragma unroll
-    for (int d = 0; d < LEAD; ++d) {   // warm-up rows: no output
-      step(d, d & 1, d >= 2, false, q[d], p[d]);
-      q[d] = ld(d + AHEAD);
-      if (LZ) p[d] = ldp(d + AHEAD);
-    }
-    int i = LEAD;
-    for (; i + AHEAD <= count; i += AHEAD) {
-#pragma unroll
-      for (int d = 0; d < AHEAD; ++d) {
-        const int c = (LEAD + d) % AHEAD;
-        step(i + d, (LEAD + d) & 1, true, true, q[c], p[c]);
-        q[c] = ld(i + d + AHEAD);
-        if (LZ) p[c] = ldp(i + d + AHEAD);
-      }
-    }
-#pragma unroll
-    for (int d = 0; d < AHEAD; ++d) {   // tail: the rows left, already requested
-      const int c = (LEAD + d) % AHEAD;
-      if (i + d < count) step(i + d, (LEAD + d) & 1, true, true, q[c], p[c]);
-    }
-  }
+  if (g.epl == 2)
+    s2_strip<T, ORDER, LZ, 2>(g, tx, ty, w, lane, src, dst, prv, j, s_cur, s_prev, bprev, &vrow[w][0][0],
+                              &trow[w][0][0], acc);
+  else
+    s2_strip<T, ORDER, LZ, 1>(g, tx, ty, w, lane, src, dst, prv, j, s_cur, s_prev, bprev, &vrow[w][0][0],
+                              &trow[w][0][0], acc);
   if (LZ) {
     const double bs = block_sum<256>(acc, red);
     if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + blockIdx.x] = bs;
@@ -351,10 +438,12 @@ __global__ __launch_bounds__(256) void k_csr(long n, const int64_t* __restrict__
 }
 
 // ---- host side --------------------------------------------------------------------------------
-void stencil_geom_tiles(StencilGeom& g, int dim, int order) {
+void stencil_geom_tiles(StencilGeom& g, int dim, int order, int epl) {
   int TZ, TY, TX;
+  g.epl = 1;
+  if (dim == 2) g.epl = epl > 0 ? epl : (g.n2 % 2 == 0 ? 2 : 1);   // pairs need an even row length
   if (dim == 1) { TZ = TileShape<1>::TZ; TY = TileShape<1>::TY; TX = TileShape<1>::TX; }
-  else if (dim == 2) { TZ = 1; TY = kS2Waves * kS2Band; TX = kWave - 2 * order; }   // k_stencil2d
+  else if (dim == 2) { TZ = 1; TY = kS2Waves * kS2Band; TX = s2_out(order, g.epl); }   // k_stencil2d
   else { TZ = TileShape<3>::TZ; TY = TileShape<3>::TY; TX = TileShape<3>::TX; }
   g.tiles_x = (g.n2 + TX - 1) / TX;
   g.tiles_y = (g.n1 + TY - 1) / TY;
