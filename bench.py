@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
     ap.add_argument("--only", default="", help="profiling: run only this leg (headline|counters)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--kernel", default="", help="counters leg: kernel to run (default: the dominant one)")
+    ap.add_argument("--storage", default="f64", help="counters leg: storage dtype (f64|f32)")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="arrival window per serving rate")
     return ap.parse_args()
 
@@ -81,15 +83,20 @@ def main():
     op64 = make("f64")
 
     if args.only == "counters":
-        # workload of the hardware-counter runs: the dominant kernel alone, then a plain device copy of
-        # known size whose FETCH_SIZE / WRITE_SIZE readings scale the counters to bytes
-        r = gm.kernel_bench(op64, DOMINANT_KERNEL, k, reps=50, stream=stream)
+        # workload of the hardware-counter runs: one kernel alone (the dominant one unless --kernel names
+        # another: spmv = the 13-point operator alone), then a plain device copy of known size whose
+        # FETCH_SIZE / WRITE_SIZE readings scale the counters to bytes
+        name = args.kernel or DOMINANT_KERNEL
+        op = make(args.storage) if name != "spmv" else gm.Operator.lattice(sp.shape, sp.order, sp.kappa2, sp.tau,
+                                                                            sp.boundary, args.storage)
+        r = gm.kernel_bench(op, name, k, reps=50, stream=stream)
         a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"kernel": DOMINANT_KERNEL, "avg_us": r["avg_us"], "copy_bytes": COPY_BYTES}))
+        print(json.dumps({"kernel": name, "storage": args.storage, "avg_us": r["avg_us"], "bytes": r["bytes"],
+                          "copy_bytes": COPY_BYTES}))
         return
 
     def step(op, tol, m_max):
