@@ -26,6 +26,7 @@ struct StencilGeom {
   double kappa2, tau;
   int tiles_x, tiles_y, tiles_z;
   int epl;                 // 2D kernel: elements per lane (1 or 2)
+  int ftiles_x;            // 2D one-pass Lanczos kernel: strips per row
 };
 
 // Per-call Lanczos state, all device memory.  Index conventions (1-based j as in

@@ -358,6 +358,10 @@ extern "C" gmrf_status gmrf_op_set_circulant_precond(gmrf_op* Q, int enable) {
 
 // ---- sizes ------------------------------------------------------------------------------------------
 namespace {
+// 2D lattice operators without preconditioning or reorthogonalisation run one pass per Lanczos step
+// (k_lanczos2d: alpha_j from the quadratic form the previous pass formed).
+bool fused_path(const gmrf_op* Q, int reorth) { return !Q->precond && Q->kind == 0 && Q->dim == 2 && !reorth; }
+
 struct Sizes {
   long L;          // storage elements per vector
   int slots;       // Krylov slots kept
@@ -375,6 +379,9 @@ Sizes sizes_for(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3) 
     const PrecondStepCounts c = precond_step_counts(Q->plan);
     z.Pa = c.Pband + 1;                           // <u, D u> per band block, <w_{j-1}, v_{j-1}>
     z.Pb = reorth ? ew_blocks(z.L) : c.Ps;        // the reorthogonalisation rewrites the norm partials
+  } else if (fused_path(Q, reorth)) {
+    z.Pa = lanczos2d_blocks(Q->geom);             // the one-pass kernel's partial sums
+    z.Pb = z.Pa;
   } else {
     z.Pa = Q->kind == 0 ? stencil_blocks(Q->geom) : csr_blocks((long)Q->n);
     z.Pb = ew_blocks(z.L);
@@ -392,7 +399,7 @@ size_t call_bytes(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3
   b += (size_t)k * z.vec_bytes;                       // q
   if (Q->precond) b += (size_t)k * z.vec_bytes + precond_step_bytes(Q->plan, Q->storage, (int)k);   // FFT scratch
   b += (size_t)k * (m_max + 2) * 8 * 4 + (size_t)k * 16;  // scalars
-  b += 3 * (size_t)k * z.pstride * 8;                 // partials
+  b += (fused_path(Q, reorth) ? 6 : 3) * (size_t)k * z.pstride * 8;   // partials (two sets when fused)
   if (reorth) b += (size_t)k * (m_max + 1) * (z.Pb + 1) * 8;
   if (!ring3) b += (size_t)k * m_max * 8 + tri_scratch_doubles((int)k, m_max) * 8;
   return b;
@@ -486,6 +493,8 @@ struct Run {
   double* part_h = nullptr;
   double* h = nullptr;
   bool ring3 = false;
+  bool fused = false;             // one pass per step (k_lanczos2d); partial sums alternate between ps[0], ps[1]
+  double* ps[2][3] = {};          // {quadratic form, ||w||^2, <w, v>} partial sums
 
   T* slot(int t) const {
     const int s = ring3 ? (t % 3) : t;
@@ -507,8 +516,10 @@ gmrf_status setup(Run<T>& R, Workspace& ws) {
     if ((s = ws.alloc(precond_step_bytes(Q->plan, Q->storage, k), &band)) != GMRF_OK) return s;
     R.band = band;
   }
+  R.fused = fused_path(Q, R.reorth);
   double* dbuf;
-  const size_t nd = (size_t)k * (m + 1) * 3 + (size_t)k * (m + 2) + 3 * (size_t)k * R.z.pstride;
+  const int nsets = R.fused ? 6 : 3;
+  const size_t nd = (size_t)k * (m + 1) * 3 + (size_t)k * (m + 2) + nsets * (size_t)k * R.z.pstride;
   if ((s = ws.alloc(nd, &dbuf)) != GMRF_OK) return s;
   int* ibuf;
   if ((s = ws.alloc((size_t)3 * k, &ibuf)) != GMRF_OK) return s;
@@ -523,6 +534,9 @@ gmrf_status setup(Run<T>& R, Workspace& ws) {
   S.part_a = S.beta + (size_t)k * (m + 2);
   S.part_b = S.part_a + (size_t)k * R.z.pstride;
   S.part_c = S.part_b + (size_t)k * R.z.pstride;
+  if (R.fused) {
+    for (int q = 0; q < 6; ++q) R.ps[q / 3][q % 3] = S.part_a + (size_t)q * k * R.z.pstride;
+  }
   S.m_used = ibuf;
   S.status = ibuf + k;
   S.active = ibuf + 2 * k;
@@ -540,6 +554,15 @@ gmrf_status setup(Run<T>& R, Workspace& ws) {
     if ((s = ws.alloc((size_t)k * (m + 1), &R.h)) != GMRF_OK) return s;
   }
   return GMRF_OK;
+}
+
+// After slot 0 and its norm partial sums are in place: the quadratic form of slot 0 (set 0) for the
+// one-pass kernel's alpha_1.
+template <typename T>
+void fused_init(Run<T>& R) {
+  if (!R.fused) return;
+  launch_lanczos2d<T>(R.Q->geom, R.Q->order, 1, 0, R.slot(0), R.z.L, nullptr, nullptr, R.S, 0, R.k, R.ps[0][0],
+                      nullptr, nullptr, R.st);
 }
 
 // pinned polling buffer per host thread
@@ -564,7 +587,16 @@ void iterate(Run<T>& R, int j) {
   T* xj = R.slot(j - 1);
   T* xp = j >= 2 ? R.slot(j - 2) : R.slot(0);
   R.S.Pb = (j == 1) ? R.pb_first : R.z.Pb;
-  if (Q->precond) {
+  if (R.fused) {
+    // reads the partial sums in R.S (pass j - 1's; iteration 1: the init kernels' set 0) and writes the other
+    // set, which R.S then points to (the next pass and k_finalize read it)
+    const int wset = j & 1;
+    launch_lanczos2d<T>(Q->geom, Q->order, 0, 0, xj, R.z.L, R.slot(j), xp, R.S, j, R.k, R.ps[wset][0],
+                        R.ps[wset][1], R.ps[wset][2], R.st);
+    R.S.part_a = R.ps[wset][0];
+    R.S.part_b = R.ps[wset][1];
+    R.S.part_c = R.ps[wset][2];
+  } else if (Q->precond) {
     precond_lanczos_step<T>(Q->plan, Q->geom, Q->order, precond_mult(Q), xj, xp, R.slot(j), R.band, R.S, j,
                             R.reorth ? 0 : 1, R.reorth ? 0 : 1, R.k, R.st);
   } else {
@@ -718,6 +750,7 @@ static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, dou
       precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, R.k, R.st);
     } else {
       launch_init_from_f64<T>(Zg, Q->n, R.z.L, R.slot(0), R.S, R.st);
+      fused_init<T>(R);
     }
   }
   if ((s = run_loop<T>(Rs)) != GMRF_OK) return s;
@@ -840,6 +873,7 @@ static gmrf_status logdet_impl(const gmrf_op* Q, int np, int m, uint64_t seed, c
       launch_init_rademacher<T>(seed, R.z.L, c0[g], R.slot(0), S2, R.st);
       R.pb_first = S2.Pb;  // opener of iteration 1 reduces the probe partials
     }
+    if (!Q->precond) fused_init<T>(R);
   }
   const std::vector<char> live(G, 1);
   for (int j = 1; j <= m; ++j) iterate_all<T>(Rs, j, live);
@@ -1024,7 +1058,8 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
                                      int m_max, double* X, gmrf_info* info, hipStream_t st) {
   const gmrf_op* Q0 = ops[0];
   std::vector<int64_t> off, ext;   // column offsets inside a Krylov slot, and in the caller's Z and X
-  std::vector<int> len, pa, pb, field;
+  std::vector<int> len, pa, pb, pbf, field;
+  const bool fused = Q0->kind == 0 && Q0->dim == 2;   // one pass per step (k_lanczos2d)
   std::vector<StencilGeom> geom;
   int64_t tot = 0, tot_ext = 0;
   int max_tiles = 1;
@@ -1034,7 +1069,7 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
     // inside the Krylov slots every column starts at an even offset, so that the 2D kernel's element
     // pairs (even row length) stay aligned: each field is then tiled as it is when sampled alone
     const StencilGeom gf = Q->geom;
-    const int tiles = stencil_blocks(gf);
+    const int tiles = fused ? lanczos2d_blocks(gf) : stencil_blocks(gf);
     max_tiles = std::max(max_tiles, tiles);
     max_len = std::max<long>(max_len, (long)Q->n);
     for (int64_t r = 0; r < kf[f]; ++r) {
@@ -1042,7 +1077,8 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
       ext.push_back(tot_ext);
       len.push_back((int)Q->n);
       pa.push_back(tiles);
-      pb.push_back(ew_blocks((long)Q->n));
+      pb.push_back(ew_blocks((long)Q->n));     // the init kernel's (and the update kernel's) norm partials
+      pbf.push_back(tiles);                    // the one-pass kernel's norm partials
       geom.push_back(gf);
       field.push_back(f);
       tot += (Q->n + 1) & ~(int64_t)1;
@@ -1057,10 +1093,10 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
   if ((s = ws.alloc((size_t)tot, &Qb)) != GMRF_OK) return s;
   const int pstride = std::max(max_tiles, ew_blocks(max_len));
   double* dbuf;
-  const size_t nd = (size_t)K * (m_max + 1) * 3 + (size_t)K * (m_max + 2) + 2 * (size_t)K * pstride;
+  const size_t nd = (size_t)K * (m_max + 1) * 3 + (size_t)K * (m_max + 2) + 6 * (size_t)K * pstride;
   if ((s = ws.alloc(nd, &dbuf)) != GMRF_OK) return s;
   int* ibuf;
-  if ((s = ws.alloc((size_t)6 * K, &ibuf)) != GMRF_OK) return s;
+  if ((s = ws.alloc((size_t)7 * K, &ibuf)) != GMRF_OK) return s;
   int64_t* doff;
   if ((s = ws.alloc((size_t)2 * K, &doff)) != GMRF_OK) return s;
   int64_t* dext = doff + K;
@@ -1076,12 +1112,16 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
   S.beta = S.rho + (size_t)K * (m_max + 1);
   S.part_a = S.beta + (size_t)K * (m_max + 2);
   S.part_b = S.part_a + (size_t)K * pstride;
+  S.part_c = S.part_b + (size_t)K * pstride;
+  double* ps[2][3];
+  for (int q = 0; q < 6; ++q) ps[q / 3][q % 3] = S.part_a + (size_t)q * K * pstride;
   S.m_used = ibuf;
   S.status = ibuf + K;
   S.active = ibuf + 2 * K;
   int* dlen = ibuf + 3 * K;
   int* dpa = ibuf + 4 * K;
   int* dpb = ibuf + 5 * K;
+  int* dpbf = ibuf + 6 * K;
   S.Pa = max_tiles;
   S.Pb = ew_blocks(max_len);
   S.pstride = pstride;
@@ -1100,15 +1140,31 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
   HIP_TRY(hipMemcpyAsync(dlen, len.data(), K * sizeof(int), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(dpa, pa.data(), K * sizeof(int), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(dpb, pb.data(), K * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(dpbf, pbf.data(), K * sizeof(int), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(dgeom, geom.data(), K * sizeof(StencilGeom), hipMemcpyHostToDevice, st));
   auto slot = [&](int t) { return V + (size_t)t * tot; };
   launch_init_from_f64<T>(Z, 0, max_len, slot(0), S, st);
+  if (fused)
+    launch_lanczos2d<T>(Q0->geom, Q0->order, 1, max_tiles, slot(0), 0, nullptr, nullptr, S, 0, K, ps[0][0], nullptr,
+                        nullptr, st);
   int* pbuf = poll_buffer(K);
   if (!pbuf) return fail(GMRF_ENOMEM, "pinned host buffer allocation failed");
   int poll = 8;
   for (int j = 1; j <= m_max; ++j) {
-    launch_stencil_batch<T>(Q0->order, Q0->dim, max_tiles, slot(j - 1), Qb, j >= 2 ? slot(j - 2) : slot(0), S, j, st);
-    launch_update<T>(Qb, slot(j - 1), slot(j), max_len, j, 1, S, st);
+    if (fused) {
+      // S holds pass j - 1's partial sums (iteration 1: the init kernels' set 0); this pass writes the other set
+      const int wset = j & 1;
+      launch_lanczos2d<T>(Q0->geom, Q0->order, 0, max_tiles, slot(j - 1), 0, slot(j), j >= 2 ? slot(j - 2) : slot(0),
+                          S, j, K, ps[wset][0], ps[wset][1], ps[wset][2], st);
+      S.part_a = ps[wset][0];
+      S.part_b = ps[wset][1];
+      S.part_c = ps[wset][2];
+      S.col_pb = dpbf;
+    } else {
+      launch_stencil_batch<T>(Q0->order, Q0->dim, max_tiles, slot(j - 1), Qb, j >= 2 ? slot(j - 2) : slot(0), S, j,
+                              st);
+      launch_update<T>(Qb, slot(j - 1), slot(j), max_len, j, 1, S, st);
+    }
     if (j % poll == 0 && j < m_max) {
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipMemcpyAsync(pbuf, S.active, K * sizeof(int), hipMemcpyDeviceToHost, st));

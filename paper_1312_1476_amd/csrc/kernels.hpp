@@ -26,6 +26,14 @@ template <typename T, typename OutT> void launch_combine(const T* V, long L, con
 // epl: elements per lane of the 2D kernel (0: 2 when the row length is even; 1 for fields packed at
 // arbitrary offsets)
 void stencil_geom_tiles(StencilGeom& g, int dim, int order, int epl = 0);
+// One-pass Lanczos step on a 2D lattice (k_lanczos2d): mode 0 reads v_j = X / beta_{j-1} and v_{j-1} = Xprev
+// (S holds the previous pass's partial sums), writes w_j to W and this pass's partial sums to out_*; mode 1
+// writes the partial sums of X^T Q X to out_a.  grid_x = 0: the lattice's own block count.
+int lanczos2d_blocks(const StencilGeom& g);
+template <typename T>
+void launch_lanczos2d(const StencilGeom& g, int order, int mode, int grid_x, const T* X, long xld, T* W,
+                      const T* Xprev, const LzState& S, int j, int k, double* out_a, double* out_b, double* out_c,
+                      hipStream_t st);
 int stencil_blocks(const StencilGeom& g);
 template <typename T> void launch_stencil(const StencilGeom& g, int order, int dim, bool lz, const T* X, long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k, hipStream_t st);
 template <typename T> void launch_stencil_batch(int order, int dim, int max_tiles, const T* X, T* Y, const T* Xprev, const LzState& S, int j, hipStream_t st);

@@ -399,6 +399,267 @@ __global__ __launch_bounds__(256) void k_stencil2d(StencilGeom g0, const T* __re
   }
 }
 
+// ---- 2D lattices: one pass per Lanczos step ----------------------------------------------------
+// alpha_j is known before the pass (Algorithm 1's alpha_j = v_j^T (Q v_j - beta_{j-1} v_{j-1})):
+//   v_j^T Q v_j = w_{j-1}^T Q w_{j-1} / beta_{j-1}^2,   beta_{j-1} v_j^T v_{j-1} = <w_{j-1}, v_{j-1}>,
+// with w^T Q w = tau ||K w||^2 (order 2, Q = tau K^2) or tau (kappa2 ||w||^2 + sum over the lattice's
+// edges of (w_a - w_b)^2) (order 1) -- sums of squares, formed by the previous pass while it wrote
+// w_{j-1}.  One pass therefore reads v_j (= slot j-1 / beta_{j-1}) and v_{j-1} and writes
+//   w_j = Q v_j - alpha_j v_j - beta_{j-1} v_{j-1}
+// with the partial sums of ||w_j||^2, <w_j, v_j> and w_j^T Q w_j for the next pass: 3 s E bytes per step
+// instead of 6 s E for an operator pass plus an update pass.  K w needs w around each output point, so
+// each strip forms w on a one-point halo: v is read with a halo of ORDER + 1 points.
+// MODE 1: the quadratic form of the input alone (slot 0 before iteration 1), into out_a.
+__host__ __device__ inline int s2f_halo(int order, int epl) { return epl == 2 ? (order == 2 ? 4 : 2) : order + 1; }
+__host__ __device__ inline int s2f_out(int order, int epl) { return kWave * epl - 2 * s2f_halo(order, epl); }
+
+template <typename T, int ORDER, int MODE, int EPL>
+__device__ __forceinline__ void s2f_strip(const StencilGeom& g, int tx, int ty, int w, int lane,
+                                          const T* __restrict__ src, T* __restrict__ dst,
+                                          const T* __restrict__ prv, int j, double s_cur, double s_prev,
+                                          double bprev, double alpha, T* vbuf, T* tbuf, T* wbuf, double& acc_b,
+                                          double& acc_c, double& acc_a) {
+  using VE = VecE<T, EPL>;
+  using VT = typename VE::type;
+  constexpr int HX = EPL == 2 ? (ORDER == 2 ? 4 : 2) : ORDER + 1;
+  constexpr int OX = kWave * EPL - 2 * HX;
+  constexpr int RW = kWave * EPL;
+  constexpr int HV = ORDER + 1;                                 // rows of v above and below the band
+  const int n1 = g.n1, n2 = g.n2;
+  const bool per = g.periodic != 0;
+  const int xb = tx * OX - HX + lane * EPL;
+  const int xl = per ? ((xb % n2) + n2) % n2 : min(max(xb, 0), n2 - EPL);
+  bool hl[EPL], hr[EPL];
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) {
+    hl[e] = per || xb + e > 0;
+    hr[e] = per || xb + e < n2 - 1;
+  }
+  const bool olane = lane * EPL >= HX && lane * EPL < RW - HX && xb >= 0 && xb < n2;
+  const int lm = (lane * EPL - 1) & (RW - 1), lp = (lane * EPL + EPL) & (RW - 1);
+  const int y_lo = (ty * kS2Waves + w) * kS2Band;
+  const int y_hi = min(y_lo + kS2Band, n1);
+  const int count = y_hi > y_lo ? y_hi - y_lo + 2 * HV : 0;
+  if (count == 0) return;
+  const int ys = y_lo - HV;
+  const bool tiny = n1 <= 2 * HV;
+  auto rowi = [&](int y) {
+    if (!per) return min(max(y, 0), n1 - 1);
+    if (tiny) return ((y % n1) + n1) % n1;
+    return y < 0 ? y + n1 : (y >= n1 ? y - n1 : y);
+  };
+  auto ld = [&](int i) { return *(const VT*)(src + (size_t)rowi(ys + min(i, count - 1)) * n2 + xl); };
+  // v_{j-1} at the row of w formed at input row i (ys + i - ORDER), wrapped or clamped like v: w is also
+  // formed on the halo, where a periodic lattice needs the wrapped values
+  auto ldp = [&](int i) { return *(const VT*)(prv + (size_t)rowi(ys + min(i, count - 1) - ORDER) * n2 + xl); };
+  const T k2 = (T)g.kappa2, tau = (T)g.tau;
+  const double dk2 = g.kappa2, dtau = g.tau;
+  auto kop = [&](const T (&c)[EPL], const T (&u)[EPL], const T (&d)[EPL], const T* b, int yc, T (&out)[EPL]) {
+    const T bl = b[lm], br = b[lp];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      const T v = c[e];
+      const T ln = e > 0 ? c[e > 0 ? e - 1 : 0] : bl;
+      const T rn = e < EPL - 1 ? c[e < EPL - 1 ? e + 1 : 0] : br;
+      const T l = hl[e] ? ln : v, rr = hr[e] ? rn : v;
+      const T uu = (per || yc > 0) ? u[e] : v, dd = (per || yc < n1 - 1) ? d[e] : v;
+      T a = k2 * v;
+      a += v - l;
+      a += v - rr;
+      a += v - uu;
+      a += v - dd;
+      out[e] = a;
+    }
+  };
+  // quadratic-form terms of the points of row yc held in c (row yc + 1 in d, right neighbours from b)
+  auto qform = [&](const T (&c)[EPL], const T (&u)[EPL], const T (&d)[EPL], const T* b, int yc) {
+    if (ORDER == 2) {
+      T kw[EPL];
+      kop(c, u, d, b, yc, kw);
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) acc_a += dtau * ((double)kw[e] * (double)kw[e]);
+    } else {
+      const T br = b[lp];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const double v = (double)c[e];
+        const double rn = (double)(e < EPL - 1 ? c[e < EPL - 1 ? e + 1 : 0] : br);
+        double q = dk2 * v * v;
+        if (hr[e]) q += (v - rn) * (v - rn);
+        if (per || yc < n1 - 1) q += (v - (double)d[e]) * (v - (double)d[e]);
+        acc_a += dtau * q;
+      }
+    }
+  };
+  auto store_row = [&](T* buf, int par, const T (&val)[EPL]) {
+    VT vv;
+    if constexpr (EPL == 1) {
+      vv = val[0];
+    } else {
+      vv[0] = val[0];
+      vv[1] = val[1];
+    }
+    *(VT*)(buf + par * RW + lane * EPL) = vv;
+  };
+  T v0[EPL], v1[EPL], t0[EPL], t1[EPL], wa[EPL], wb[EPL];
+#pragma unroll
+  for (int e = 0; e < EPL; ++e) v0[e] = v1[e] = t0[e] = t1[e] = wa[e] = wb[e] = (T)0;
+  // Input row i (row ys + i).  par = i & 1 picks the LDS row slots; the stages run from i >= 2 (K v, order
+  // 2), i >= 2 ORDER (w at row ys + i - ORDER) and i >= 2 ORDER + 2 (K w at row ys + i - ORDER - 1).
+  auto step = [&](int i, int par, const VT& raw, const VT& rawp) {
+    T v2[EPL];
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) v2[e] = MODE == 0 ? (T)((double)VE::get(raw, e) * s_cur) : VE::get(raw, e);
+    store_row(vbuf, par, v2);
+    const int yi = ys + i;
+    if (MODE == 1) {
+      // quadratic form of the input itself: row yi - 1
+      const int yc = yi - 1;
+      if (i >= 2 && olane && yc >= y_lo && yc < y_hi) qform(v1, v0, v2, vbuf + (par ^ 1) * RW, yc);
+    } else {
+      T q[EPL], vw[EPL];
+      bool haw = false;
+      const int yw = yi - ORDER;
+      if (ORDER == 1) {
+        if (i >= 2) {
+          kop(v1, v0, v2, vbuf + (par ^ 1) * RW, yw, q);
+          haw = true;
+        }
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) vw[e] = v1[e];
+      } else {
+        T t2[EPL];
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) t2[e] = (T)0;
+        if (i >= 2) {
+          kop(v1, v0, v2, vbuf + (par ^ 1) * RW, yi - 1, t2);
+          store_row(tbuf, par ^ 1, t2);
+        }
+        if (i >= 4) {
+          kop(t1, t0, t2, tbuf + par * RW, yw, q);
+          haw = true;
+        }
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          vw[e] = v0[e];
+          t0[e] = t1[e];
+          t1[e] = t2[e];
+        }
+      }
+      if (haw) {
+        T wn[EPL];
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          double qq = (double)(tau * q[e]);
+          if (j > 1) qq -= bprev * (double)(T)((double)VE::get(rawp, e) * s_prev);
+          const T qt = (T)qq;
+          wn[e] = (T)((double)qt - alpha * (double)vw[e]);
+        }
+        const int wpar = (ORDER == 1) ? (par ^ 1) : par;   // slot of index i - ORDER
+        store_row(wbuf, wpar, wn);
+        if (olane && yw >= y_lo && yw < y_hi) {
+          VT vv;
+          if constexpr (EPL == 1) {
+            vv = wn[0];
+          } else {
+            vv[0] = wn[0];
+            vv[1] = wn[1];
+          }
+          *(VT*)(dst + (size_t)yw * n2 + xb) = vv;
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) {
+            acc_b += (double)wn[e] * (double)wn[e];
+            acc_c += (double)wn[e] * (double)vw[e];
+          }
+        }
+        // K w at the row above (its lower neighbour wn just formed)
+        const int yk = yw - 1;
+        if (i >= 2 * ORDER + 2 && olane && yk >= y_lo && yk < y_hi) qform(wb, wa, wn, wbuf + (wpar ^ 1) * RW, yk);
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          wa[e] = wb[e];
+          wb[e] = wn[e];
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EPL; ++e) {
+      v0[e] = v1[e];
+      v1[e] = v2[e];
+    }
+  };
+  constexpr int AHEAD = S2Ahead<T>::value;
+  VT qv[AHEAD], pv[AHEAD];
+#pragma unroll
+  for (int d = 0; d < AHEAD; ++d) {
+    qv[d] = ld(d);
+    pv[d] = MODE == 0 ? ldp(d) : qv[d];
+  }
+  int i = 0;
+  for (; i + AHEAD <= count; i += AHEAD) {
+#pragma unroll
+    for (int d = 0; d < AHEAD; ++d) {
+      step(i + d, d & 1, qv[d], pv[d]);
+      qv[d] = ld(i + d + AHEAD);
+      if (MODE == 0) pv[d] = ldp(i + d + AHEAD);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < AHEAD; ++d)
+    if (i + d < count) step(i + d, d & 1, qv[d], pv[d]);
+}
+
+#ifndef GMRF_L2D_WAVES
+#define GMRF_L2D_WAVES 2       // lower bound on waves per SIMD given to the compiler; 4 caps registers at
+                               // 128 and spills in the FP64 13-point case (measured 14% slower)
+#endif
+template <typename T, int ORDER, int MODE>
+__global__ __launch_bounds__(256, GMRF_L2D_WAVES) void k_lanczos2d(StencilGeom g0, const T* __restrict__ X, long xld,
+                                                   T* __restrict__ W, const T* __restrict__ Xprev, LzState S,
+                                                   int j, double* __restrict__ out_a, double* __restrict__ out_b,
+                                                   double* __restrict__ out_c) {
+  constexpr int NW = 256 / kWave;
+  __shared__ __align__(16) T vrow[kS2Waves][2][2 * kWave];
+  __shared__ __align__(16) T trow[kS2Waves][2][2 * kWave];
+  __shared__ __align__(16) T wrow[kS2Waves][2][2 * kWave];
+  __shared__ double red[3 * NW];
+  __shared__ int flag[1];
+  const int r = blockIdx.y;
+  const StencilGeom g = S.col_geom ? S.col_geom[r] : g0;
+  if ((int)blockIdx.x >= g.ftiles_x * g.tiles_y) return;
+  double s_cur = 1.0, s_prev = 0.0, bprev = 0.0, alpha = 0.0;
+  if (MODE == 0) {
+    if (!lz_open<256>(S, r, j, blockIdx.x == 0, red, flag, s_cur, s_prev, bprev)) return;
+    // alpha_j from the previous pass's partial sums (fixed order; the same in every block)
+    const double qf = sum_partials<256>(S.part_a + (size_t)r * S.pstride, lz_pa(S, r), red);
+    const double cc = j > 1 ? sum_partials<256>(S.part_c + (size_t)r * S.pstride, lz_pa(S, r), red) : 0.0;
+    alpha = qf * s_cur * s_cur - cc;
+    if (blockIdx.x == 0 && threadIdx.x == 0) S.alpha[lz_ia(S, r, j)] = alpha;
+  }
+  const int tx = blockIdx.x % g.ftiles_x, ty = blockIdx.x / g.ftiles_x;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
+  const size_t roff = S.col_off ? (size_t)S.col_off[r] : (size_t)r * xld;
+  double acc_b = 0.0, acc_c = 0.0, acc_a = 0.0;
+  const T* prv = MODE == 0 ? Xprev + roff : nullptr;
+  if (g.epl == 2)
+    s2f_strip<T, ORDER, MODE, 2>(g, tx, ty, w, lane, X + roff, W + roff, prv, j, s_cur, s_prev, bprev, alpha,
+                                 &vrow[w][0][0], &trow[w][0][0], &wrow[w][0][0], acc_b, acc_c, acc_a);
+  else
+    s2f_strip<T, ORDER, MODE, 1>(g, tx, ty, w, lane, X + roff, W + roff, prv, j, s_cur, s_prev, bprev, alpha,
+                                 &vrow[w][0][0], &trow[w][0][0], &wrow[w][0][0], acc_b, acc_c, acc_a);
+  // block sums in fixed order
+  const double sa = block_sum<256>(acc_a, red);
+  if (MODE == 0) {
+    const double sb = block_sum<256>(acc_b, red);
+    const double sc = block_sum<256>(acc_c, red);
+    if (threadIdx.x == 0) {
+      out_b[(size_t)r * S.pstride + blockIdx.x] = sb;
+      out_c[(size_t)r * S.pstride + blockIdx.x] = sc;
+    }
+  }
+  if (threadIdx.x == 0) out_a[(size_t)r * S.pstride + blockIdx.x] = sa;
+}
+
 // ---- CSR: one thread per row ----------------------------------------------------------------
 template <typename T, bool LZ>
 __global__ __launch_bounds__(256) void k_csr(long n, const int64_t* __restrict__ rp,
@@ -446,6 +707,7 @@ void stencil_geom_tiles(StencilGeom& g, int dim, int order, int epl) {
   else if (dim == 2) { TZ = 1; TY = kS2Waves * kS2Band; TX = s2_out(order, g.epl); }   // k_stencil2d
   else { TZ = TileShape<3>::TZ; TY = TileShape<3>::TY; TX = TileShape<3>::TX; }
   g.tiles_x = (g.n2 + TX - 1) / TX;
+  g.ftiles_x = dim == 2 ? (g.n2 + s2f_out(order, g.epl) - 1) / s2f_out(order, g.epl) : 0;   // k_lanczos2d
   g.tiles_y = (g.n1 + TY - 1) / TY;
   g.tiles_z = (g.n0 + TZ - 1) / TZ;
 }
@@ -503,6 +765,28 @@ template void launch_stencil_batch<double>(int, int, int, const double*, double*
                                            int, hipStream_t);
 template void launch_stencil_batch<float>(int, int, int, const float*, float*, const float*, const LzState&, int,
                                           hipStream_t);
+
+int lanczos2d_blocks(const StencilGeom& g) { return g.ftiles_x * g.tiles_y; }
+
+template <typename T>
+void launch_lanczos2d(const StencilGeom& g, int order, int mode, int grid_x, const T* X, long xld, T* W,
+                      const T* Xprev, const LzState& S, int j, int k, double* out_a, double* out_b, double* out_c,
+                      hipStream_t st) {
+  const dim3 grid(grid_x > 0 ? grid_x : lanczos2d_blocks(g), k);
+#define CASEL(O, M)                                                                                            \
+  if (order == O && mode == M) {                                                                                \
+    hipLaunchKernelGGL((k_lanczos2d<T, O, M>), grid, dim3(256), 0, st, g, X, xld, W, Xprev, S, j, out_a, out_b, \
+                       out_c);                                                                                  \
+    return;                                                                                                     \
+  }
+  CASEL(1, 0) CASEL(2, 0) CASEL(1, 1) CASEL(2, 1)
+#undef CASEL
+}
+template void launch_lanczos2d<double>(const StencilGeom&, int, int, int, const double*, long, double*,
+                                       const double*, const LzState&, int, int, double*, double*, double*,
+                                       hipStream_t);
+template void launch_lanczos2d<float>(const StencilGeom&, int, int, int, const float*, long, float*, const float*,
+                                      const LzState&, int, int, double*, double*, double*, hipStream_t);
 
 int csr_blocks(long n) { return (int)((n + 255) / 256); }
 
