@@ -15,6 +15,12 @@ Workloads (synthetic lattices standing in for the paper's unspecified LGCP latti
       m = 80 (probe seed SEED + 3)
   C4  serving mix: Poisson arrivals (mean 200 req/s), sample and log-det requests on 2D
       lattices of side 64..2048 and 3D 7-point lattices up to 128^3
+  C5  log-Gaussian Cox process proposal (Sections 3 and 5.1, Table 1): N x N lattice on the
+      unit torus (h = 1/N), prior Q = tau (kappa2 I + L)^2 with tau = N^2, kappa2 = kc^2 / N^2
+      (kc = 10: the same continuum field at every N), and the diagonal Fisher information
+      H = h^2 exp(x) of Poisson cell counts at a smooth log-intensity x (mean log 500, unit
+      variance, a fixed sum of low-frequency cosines, so every N sees the same surface).  The
+      paper does not give its covariance, point pattern or intensity; this stands in for them.
 """
 from dataclasses import dataclass, field
 
@@ -121,3 +127,38 @@ def serving_trace(rate=200.0, duration=30.0, n_ops=64, frac_logdet=0.25, k_max=3
         out.append(Request(t, kind, int(g.integers(0, n_ops)), int(g.integers(1, k_max + 1)),
                            int(g.integers(0, 2 ** 62))))
     return out
+
+
+# ---- C5: log-Gaussian Cox process proposal ---------------------------------------------------------
+LGCP_KC = 10.0                 # prior inverse range on the unit torus
+LGCP_MEAN = float(np.log(500.0))
+LGCP_MODES = 24                # cosine modes of the log-intensity surface
+LGCP_KMAX = 4                  # largest wave number per axis
+
+
+def lgcp_prior(N, kc=LGCP_KC):
+    """Second-order periodic lattice on the unit torus at spacing h = 1/N."""
+    return LatticeSpec((N, N), 2, kc * kc / float(N * N), float(N * N), "periodic")
+
+
+def lgcp_log_intensity(N, stream=0):
+    """x at the cell centres s = ((i + 1/2) / N, (j + 1/2) / N), row-major: LGCP_MEAN plus
+    sum_k a_k g_k cos(2 pi (k . s) + phi_k) with integer wave vectors |k_i| <= LGCP_KMAX,
+    a_k proportional to (1 + |k|^2)^{-1/2} and g_k ~ N(0, 1), scaled to unit variance."""
+    g = rng(5, stream)
+    kv = g.integers(-LGCP_KMAX, LGCP_KMAX + 1, size=(LGCP_MODES, 2))
+    phase = g.uniform(0.0, 2.0 * np.pi, size=LGCP_MODES)
+    gain = g.standard_normal(LGCP_MODES)
+    amp = 1.0 / np.sqrt(1.0 + (kv.astype(np.float64) ** 2).sum(axis=1))
+    amp *= np.sqrt(2.0 / (amp ** 2).sum())
+    s = (np.arange(N, dtype=np.float64) + 0.5) / N
+    x = np.full((N, N), LGCP_MEAN)
+    for (k1, k2), ph, gk, ak in zip(kv, phase, gain, amp):
+        x += ak * gk * np.cos(2.0 * np.pi * (k1 * s[:, None] + k2 * s[None, :]) + ph)
+    return x.ravel()
+
+
+def lgcp_diagonal(N, stream=0):
+    """H = h^2 exp(x): the Fisher information of the cell counts y_ij ~ Po(h^2 exp(x_ij))
+    at the log-intensity above (the input of the sMMALA proposal; diagonal, length N^2)."""
+    return np.exp(lgcp_log_intensity(N, stream)) / float(N * N)
