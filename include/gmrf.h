@@ -91,6 +91,17 @@ gmrf_status gmrf_op_create_csr(int64_t n, const int64_t* row_ptr, const int32_t*
  * EUNSUPPORTED: not a 2D lattice, or a side that is not a power of two in [8, 4096].      */
 gmrf_status gmrf_op_set_circulant_precond(gmrf_op* Q, int enable);
 
+/* Q <- Q + diag(d) for a lattice operator: d is a host array of n finite values (copied; NULL
+ * removes the term).  The log-Gaussian Cox process proposal of Section 3 samples
+ * N(0, (Q + H)^{-1}) with Q the periodic prior and H the diagonal Fisher information; Section 5.1
+ * (Theorem 2, alpha_n = 0) preconditions it with M = Q.  With circulant preconditioning enabled
+ * the operator must be periodic, M stays the lattice part, and sampling runs Algorithm 1 on
+ * A = I + M^{-1/2} H M^{-1/2} (two 2D FFTs per step); log det adds log det M.  Sampling or log det
+ * of Q + diag(d) without preconditioning returns EUNSUPPORTED (pass such a Q as CSR);
+ * gmrf_op_apply includes the term.  EINVAL: non-finite value.  EUNSUPPORTED: CSR operator, or
+ * preconditioning on a free-boundary lattice.                                                 */
+gmrf_status gmrf_op_set_diagonal(gmrf_op* Q, const double* d);
+
 /* Device bytes one gmrf_sample call needs for k right-hand sides and m_max steps (Krylov
  * basis, work vectors, partial sums, FFT scratch), plus what the handle keeps resident.    */
 gmrf_status gmrf_op_bytes(const gmrf_op* Q, int64_t k, int32_t m_max, int reorth, size_t* bytes);
@@ -186,11 +197,12 @@ gmrf_status gmrf_tridiag_log_e1(const double* alpha, const double* beta, const i
  *   preconditioned step (writes w_j from v_j, v_{j-1} and the boundary tables, with the dot
  *   products the next step needs),  2: dot-product kernel of the preconditioned step (one read
  *   of a vector),  3: the update w = q - alpha v of the unpreconditioned step,  4: band kernel
- *   of the preconditioned step.
+ *   of the preconditioned step,  5: row pass and 6: column pass of the preconditioned step of
+ *   Q + diag(d) (gmrf_op_set_diagonal).
  * Buffers are zero-filled first.  Outputs (host): *avg_us = mean duration of one launch,
  * *bytes = algorithmic bytes of one launch (inputs read once, outputs written once; 0 for the
  * band kernel, whose traffic is the small boundary tables).  EINVAL for 1, 2, 4 without
- * preconditioning.                                                                           */
+ * preconditioning or with a diagonal term, for 5, 6 without both.                            */
 gmrf_status gmrf_kernel_bench(const gmrf_op* Q, int which, int64_t k, int32_t reps, double* avg_us,
                               double* bytes, void* stream);
 

@@ -78,6 +78,18 @@ class Operator:
                                        va.ctypes.data_as(C.c_void_p), sc, C.byref(h)), "gmrf_op_create_csr")
         return cls(h, n, sc)
 
+    def set_diagonal(self, d):
+        """Q <- Q + diag(d) (host array of n values; None removes the term).  With circulant
+        preconditioning on a periodic 2D lattice the preconditioner stays M = Q."""
+        if d is None:
+            check(lib().gmrf_op_set_diagonal(self._h, None), "gmrf_op_set_diagonal")
+            return self
+        arr = np.ascontiguousarray(d, dtype=np.float64)
+        if arr.shape != (self.n,):
+            raise ValueError(f"diagonal must have shape ({self.n},)")
+        check(lib().gmrf_op_set_diagonal(self._h, arr.ctypes.data_as(C.c_void_p)), "gmrf_op_set_diagonal")
+        return self
+
     def set_circulant_precond(self, enable=True):
         check(lib().gmrf_op_set_circulant_precond(self._h, 1 if enable else 0), "gmrf_op_set_circulant_precond")
         return self
@@ -237,7 +249,7 @@ def tridiag_log_e1(alpha, beta, m, stream=None):
     return out, status
 
 
-KERNELS = {"spmv": 0, "lz_step": 1, "lz_dots": 2, "update": 3, "lz_band": 4}
+KERNELS = {"spmv": 0, "lz_step": 1, "lz_dots": 2, "update": 3, "lz_band": 4, "lgcp_rows": 5, "lgcp_cols": 6}
 
 
 def kernel_bench(op, kernel, k, reps=50, stream=None):

@@ -85,6 +85,23 @@ template <typename T>
 void precond_dots(const FftPlan& p, const void* mult, const T* X, void* scratch, const LzState& S, int k,
                   hipStream_t st);
 
+// Preconditioned step for Q + diag(H) with M = Q on a periodic lattice (lgcp_step.hip): a row pass
+// (opens iteration j; y = F^H Lambda^{-1/2} v_j, y^T H y partial sums in part_a[0..Pr), <w_{j-1}, v_{j-1}>
+// at part_a[Pr]; row transforms of H y into T2) and a column pass (w_j into W with its ||w||^2 and
+// <w, v_j> partials over Pc blocks; T1 <- column-inverse transform of Lambda^{-1/2} w_j).  T1 must hold
+// that transform of slot j - 1 on entry (lgcp_col_init for slot 0 and after a reorthogonalisation, which
+// also sets use_c = 0).  d: the diagonal H (n values, storage dtype).  only = 1: row pass, 2: column pass.
+struct LgcpCounts {
+  int Pr;   // row-pass blocks per field
+  int Pc;   // column-pass blocks per field
+};
+LgcpCounts lgcp_counts(const FftPlan& p, int storage);
+template <typename T>
+void lgcp_col_init(const FftPlan& p, const void* mult, const T* X, T* T1, int k, hipStream_t st);
+template <typename T>
+void lgcp_lanczos_step(const FftPlan& p, const void* mult, const T* d, T* T1, T* T2, const T* Xj, const T* Xprev,
+                       T* W, const LzState& S, int j, int use_c, int k, hipStream_t st, int only = 0);
+
 // X (FP64, real, n x k) = F^H Lambda^{-1/2} U_hat for the combined spectral vectors U_hat.
 template <typename T>
 void fft_backward_output(const FftPlan& p, const void* mult, const T* U, double* X, T* tmp, const LzState& S,

@@ -108,31 +108,6 @@ enum ColMode : int {
   kColApply = 4      // FFT, times lambda^{-1/2} scale, inverse FFT         (M^{-1/2} on its own)
 };
 
-// Multiply the LDS tile (columns c0.., row-major [k1][c]) by lambda^{-1/2} * scale.  Column 0 holds
-// X[k1, 0] + i X[k1, N2/2]: with m0 = mult(k1, 0), mN = mult(k1, N2/2) and k1' = -k1 mod N1,
-//   S'[k1] = (m0 + mN)/2 S[k1] + (m0 - mN)/2 conj(S[k1']).
-template <typename T>
-__device__ void apply_mult(C2<T>* buf, int nf, int c0, int N1, int H, const T* __restrict__ mult, T scale) {
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < nf * N1; idx += kFftThreads) {
-    const int k1 = idx / nf, c = idx % nf, cg = c0 + c;
-    if (cg == 0) continue;
-    const T m = mult[(size_t)k1 * mult_stride(H) + cg] * scale;
-    buf[idx] = {buf[idx].x * m, buf[idx].y * m};
-  }
-  if (c0 == 0) {
-    for (int k1 = threadIdx.x; k1 <= N1 / 2; k1 += kFftThreads) {
-      const int kb = (N1 - k1) & (N1 - 1);
-      const T m0 = mult[(size_t)k1 * mult_stride(H)] * scale, mN = mult[(size_t)k1 * mult_stride(H) + H] * scale;
-      const T p = (m0 + mN) * (T)0.5, q = (m0 - mN) * (T)0.5;
-      const C2<T> a = buf[k1 * nf], b = buf[kb * nf];
-      buf[k1 * nf] = {p * a.x + q * b.x, p * a.y - q * b.y};
-      if (kb != k1) buf[kb * nf] = {p * b.x + q * a.x, p * b.y - q * a.y};
-    }
-  }
-  __syncthreads();
-}
-
 template <typename T, int MODE>
 __global__ __launch_bounds__(kFftThreads) void k_cols(const C2<T>* __restrict__ in, C2<T>* __restrict__ out,
                                                       int N1, int H, int nf, const C2<T>* __restrict__ tw,

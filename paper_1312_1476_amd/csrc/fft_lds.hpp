@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
+#include "fft.hpp"
 
 namespace gmrf {
 
@@ -114,6 +115,31 @@ __device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* 
     }
     __syncthreads();
   }
+}
+
+// Multiply the LDS tile (columns c0.., row-major [k1][c]) by lambda^{-1/2} * scale.  Column 0 holds
+// X[k1, 0] + i X[k1, N2/2]: with m0 = mult(k1, 0), mN = mult(k1, N2/2) and k1' = -k1 mod N1,
+//   S'[k1] = (m0 + mN)/2 S[k1] + (m0 - mN)/2 conj(S[k1']).
+template <typename T>
+__device__ void apply_mult(C2<T>* buf, int nf, int c0, int N1, int H, const T* __restrict__ mult, T scale) {
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nf * N1; idx += kFftThreads) {
+    const int k1 = idx / nf, c = idx % nf, cg = c0 + c;
+    if (cg == 0) continue;
+    const T m = mult[(size_t)k1 * mult_stride(H) + cg] * scale;
+    buf[idx] = {buf[idx].x * m, buf[idx].y * m};
+  }
+  if (c0 == 0) {
+    for (int k1 = threadIdx.x; k1 <= N1 / 2; k1 += kFftThreads) {
+      const int kb = (N1 - k1) & (N1 - 1);
+      const T m0 = mult[(size_t)k1 * mult_stride(H)] * scale, mN = mult[(size_t)k1 * mult_stride(H) + H] * scale;
+      const T p = (m0 + mN) * (T)0.5, q = (m0 - mN) * (T)0.5;
+      const C2<T> a = buf[k1 * nf], b = buf[kb * nf];
+      buf[k1 * nf] = {p * a.x + q * b.x, p * a.y - q * b.y};
+      if (kb != k1) buf[kb * nf] = {p * b.x + q * a.x, p * b.y - q * a.y};
+    }
+  }
+  __syncthreads();
 }
 
 }  // namespace gmrf

@@ -164,6 +164,10 @@ struct gmrf_op {
   double logdet_M = 0.0;
   double* mult64 = nullptr;  // lambda_M^{-1/2} tables (device)
   float* mult32 = nullptr;
+  // diagonal term: Q + diag(d) (device, both storage dtypes)
+  int has_diag = 0;
+  double* diag64 = nullptr;
+  float* diag32 = nullptr;
   size_t resident_bytes = 0;
 };
 
@@ -285,6 +289,8 @@ void gmrf_op_destroy(gmrf_op* Q) {
   if (Q->va) (void)hipFree(Q->va);
   if (Q->mult64) (void)hipFree(Q->mult64);
   if (Q->mult32) (void)hipFree(Q->mult32);
+  if (Q->diag64) (void)hipFree(Q->diag64);
+  if (Q->diag32) (void)hipFree(Q->diag32);
   fft_plan_destroy(Q->plan);
   delete Q;
 }
@@ -344,6 +350,8 @@ extern "C" gmrf_status gmrf_op_set_circulant_precond(gmrf_op* Q, int enable) {
   }
   if (Q->kind != 0 || Q->ndim != 2)
     return fail(GMRF_EUNSUPPORTED, "circulant preconditioning needs a 2D lattice operator");
+  if (Q->has_diag && Q->bc != GMRF_PERIODIC)
+    return fail(GMRF_EUNSUPPORTED, "with a diagonal term the preconditioner M = Q needs a periodic lattice");
   if (!pow2_in(Q->shape[1], 8, 4096) || !pow2_in(Q->shape[2], 8, 4096))
     return fail(GMRF_EUNSUPPORTED, "circulant preconditioning needs power-of-two sides in [8, 4096]");
   if (!Q->mult64) {
@@ -356,11 +364,43 @@ extern "C" gmrf_status gmrf_op_set_circulant_precond(gmrf_op* Q, int enable) {
   return GMRF_OK;
 }
 
+extern "C" gmrf_status gmrf_op_set_diagonal(gmrf_op* Q, const double* d) {
+  if (!Q) return fail(GMRF_EINVAL, "NULL operator");
+  if (!d) {
+    Q->has_diag = 0;
+    return GMRF_OK;
+  }
+  if (Q->kind != 0) return fail(GMRF_EUNSUPPORTED, "a diagonal term needs a lattice operator");
+  if (Q->precond && Q->bc != GMRF_PERIODIC)
+    return fail(GMRF_EUNSUPPORTED, "with circulant preconditioning a diagonal term needs a periodic lattice");
+  const size_t n = (size_t)Q->n;
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(d[i])) return fail(GMRF_EINVAL, "non-finite diagonal value at %zu", i);
+  if (!Q->diag64) {
+    HIP_TRY(hipMalloc(&Q->diag64, n * sizeof(double)));
+    HIP_TRY(hipMalloc(&Q->diag32, n * sizeof(float)));
+    Q->resident_bytes += n * 12;
+  }
+  std::vector<float> d32(d, d + n);
+  HIP_TRY(hipMemcpy(Q->diag64, d, n * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(Q->diag32, d32.data(), n * sizeof(float), hipMemcpyHostToDevice));
+  Q->has_diag = 1;
+  return GMRF_OK;
+}
+
 // ---- sizes ------------------------------------------------------------------------------------------
 namespace {
+// Q + diag(d) preconditioned by its periodic lattice part: two FFT passes per step (lgcp_step.hip).
+bool lgcp_path(const gmrf_op* Q) { return Q->precond && Q->has_diag; }
+const void* diag_of(const gmrf_op* Q) {
+  return Q->storage == GMRF_F64 ? (const void*)Q->diag64 : (const void*)Q->diag32;
+}
+
 // 2D lattice operators without preconditioning or reorthogonalisation run one pass per Lanczos step
 // (k_lanczos2d: alpha_j from the quadratic form the previous pass formed).
-bool fused_path(const gmrf_op* Q, int reorth) { return !Q->precond && Q->kind == 0 && Q->dim == 2 && !reorth; }
+bool fused_path(const gmrf_op* Q, int reorth) {
+  return !Q->precond && !Q->has_diag && Q->kind == 0 && Q->dim == 2 && !reorth;
+}
 
 struct Sizes {
   long L;          // storage elements per vector
@@ -375,7 +415,12 @@ Sizes sizes_for(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3) 
   z.L = (long)Q->n;  // packed half spectrum has exactly n reals too
   z.slots = ring3 ? 3 : m_max + 1;
   z.Pb_first = ew_blocks(z.L);
-  if (Q->precond) {
+  if (lgcp_path(Q)) {
+    const LgcpCounts c = lgcp_counts(Q->plan, Q->storage);
+    z.Pa = c.Pr + 1;                              // y^T H y per row block, <w_{j-1}, v_{j-1}>
+    z.Pb = reorth ? ew_blocks(z.L) : c.Pc;
+    z.pstride = std::max(std::max(z.Pa, z.Pb), std::max(z.Pb_first, c.Pc));
+  } else if (Q->precond) {
     const PrecondStepCounts c = precond_step_counts(Q->plan);
     z.Pa = c.Pband + 1;                           // <u, D u> per band block, <w_{j-1}, v_{j-1}>
     z.Pb = reorth ? ew_blocks(z.L) : c.Ps;        // the reorthogonalisation rewrites the norm partials
@@ -386,8 +431,8 @@ Sizes sizes_for(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3) 
     z.Pa = Q->kind == 0 ? stencil_blocks(Q->geom) : csr_blocks((long)Q->n);
     z.Pb = ew_blocks(z.L);
   }
-  z.pstride = std::max(std::max(z.Pa, z.Pb), z.Pb_first);
-  if (Q->precond) z.pstride = std::max(z.pstride, precond_step_counts(Q->plan).Ps);   // step-kernel partials
+  z.pstride = std::max(std::max(std::max(z.Pa, z.Pb), z.Pb_first), z.pstride);
+  if (Q->precond && !lgcp_path(Q)) z.pstride = std::max(z.pstride, precond_step_counts(Q->plan).Ps);   // step kernel
   z.vec_bytes = (size_t)z.L * (Q->storage == GMRF_F64 ? 8 : 4);
   (void)k;
   return z;
@@ -397,7 +442,8 @@ size_t call_bytes(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3
   Sizes z = sizes_for(Q, k, m_max, reorth, ring3);
   size_t b = (size_t)z.slots * k * z.vec_bytes;       // Krylov basis
   b += (size_t)k * z.vec_bytes;                       // q
-  if (Q->precond) b += (size_t)k * z.vec_bytes + precond_step_bytes(Q->plan, Q->storage, (int)k);   // FFT scratch
+  if (Q->precond) b += (size_t)k * z.vec_bytes;                                        // FFT scratch
+  if (Q->precond && !lgcp_path(Q)) b += precond_step_bytes(Q->plan, Q->storage, (int)k);   // band tables
   b += (size_t)k * (m_max + 2) * 8 * 4 + (size_t)k * 16;  // scalars
   b += (fused_path(Q, reorth) ? 6 : 3) * (size_t)k * z.pstride * 8;   // partials (two sets when fused)
   if (reorth) b += (size_t)k * (m_max + 1) * (z.Pb + 1) * 8;
@@ -430,6 +476,7 @@ static void op_apply_plain(const gmrf_op* Q, const T* X, T* Y, int k, hipStream_
     StencilGeom g = Q->geom;
     if (g.epl == 2 && (((uintptr_t)X | (uintptr_t)Y) % (2 * sizeof(T))) != 0) stencil_geom_tiles(g, Q->dim, Q->order, 1);
     launch_stencil<T>(g, Q->order, Q->dim, false, X, Q->n, Y, Q->n, nullptr, S, 0, k, st);
+    if (Q->has_diag) launch_add_diag<T>((const T*)diag_of(Q), X, Y, (long)Q->n, k, st);
     return;
   }
   launch_csr<T>((long)Q->n, Q->rp, Q->ci, (const T*)Q->va, false, X, Q->n, Y, Q->n, nullptr, S, 0, k, st);
@@ -512,6 +559,8 @@ gmrf_status setup(Run<T>& R, Workspace& ws) {
   if ((s = ws.alloc((size_t)k * R.z.L, &R.Qb)) != GMRF_OK) return s;
   if (Q->precond) {
     if ((s = ws.alloc((size_t)k * R.z.L, &R.F1)) != GMRF_OK) return s;
+  }
+  if (Q->precond && !lgcp_path(Q)) {
     char* band;
     if ((s = ws.alloc(precond_step_bytes(Q->plan, Q->storage, k), &band)) != GMRF_OK) return s;
     R.band = band;
@@ -596,6 +645,10 @@ void iterate(Run<T>& R, int j) {
     R.S.part_a = R.ps[wset][0];
     R.S.part_b = R.ps[wset][1];
     R.S.part_c = R.ps[wset][2];
+  } else if (lgcp_path(Q)) {
+    // T1 = R.F1 holds the column-inverse transform of Lambda^{-1/2} slot j-1; T2 = R.Qb
+    lgcp_lanczos_step<T>(Q->plan, precond_mult(Q), (const T*)diag_of(Q), R.F1, R.Qb, xj, xp, R.slot(j), R.S, j,
+                         R.reorth ? 0 : 1, R.k, R.st);
   } else if (Q->precond) {
     precond_lanczos_step<T>(Q->plan, Q->geom, Q->order, precond_mult(Q), xj, xp, R.slot(j), R.band, R.S, j,
                             R.reorth ? 0 : 1, R.reorth ? 0 : 1, R.k, R.st);
@@ -605,7 +658,8 @@ void iterate(Run<T>& R, int j) {
   }
   if (R.reorth) {
     launch_reorth<T>(R.V, R.z.L, j, R.part_h, R.h, R.m_max + 1, R.S, R.st);
-    if (Q->precond) precond_dots<T>(Q->plan, precond_mult(Q), R.slot(j), R.band, R.S, R.k, R.st);
+    if (lgcp_path(Q)) lgcp_col_init<T>(Q->plan, precond_mult(Q), R.slot(j), R.F1, R.k, R.st);
+    else if (Q->precond) precond_dots<T>(Q->plan, precond_mult(Q), R.slot(j), R.band, R.S, R.k, R.st);
   }
   R.S.Pb = R.z.Pb;
 }
@@ -668,7 +722,7 @@ gmrf_status run_loop(std::vector<Run<T>>& Rs) {
 constexpr int kMaxGroups = 4;
 static_assert(GMRF_PRECOND_GROUPS >= 1 && GMRF_PRECOND_GROUPS <= kMaxGroups, "column groups");
 int groups_for(const gmrf_op* Q, int64_t k) {
-  if (!Q->precond) return 1;
+  if (!Q->precond || lgcp_path(Q)) return 1;
   return (int)std::max<int64_t>(1, std::min<int64_t>(GMRF_PRECOND_GROUPS, k / 4));
 }
 
@@ -747,7 +801,8 @@ static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, dou
     const double* Zg = Z + (size_t)c0[g] * Q->n;
     if (Q->precond) {
       fft_forward_init<T>(Q->plan, Zg, R.slot(0), R.F1, R.S, R.k, R.st);
-      precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, R.k, R.st);
+      if (lgcp_path(Q)) lgcp_col_init<T>(Q->plan, precond_mult(Q), R.slot(0), R.F1, R.k, R.st);
+      else precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, R.k, R.st);
     } else {
       launch_init_from_f64<T>(Zg, Q->n, R.z.L, R.slot(0), R.S, R.st);
       fused_init<T>(R);
@@ -825,6 +880,8 @@ extern "C" gmrf_status gmrf_sample_ex(const gmrf_op* Q, const double* Z, int64_t
   if (m_max < 1 || m_max > tri_max_m()) return fail(GMRF_EINVAL, "m_max must be in 1..%d", tri_max_m());
   if (!std::isfinite(tol)) return fail(GMRF_EINVAL, "tol must be finite");
   if (reorth != 0 && reorth != 1) return fail(GMRF_EINVAL, "reorth must be 0 or 1");
+  if (Q->has_diag && !Q->precond)
+    return fail(GMRF_EUNSUPPORTED, "Q + diag(d) is sampled with circulant preconditioning only (else pass it as CSR)");
   hipStream_t st = (hipStream_t)stream;
   if (Q->storage == GMRF_F64) return sample_impl<double>(Q, Z, k, tol, m_max, reorth, X, info, alpha, beta, st);
   return sample_impl<float>(Q, Z, k, tol, m_max, reorth, X, info, alpha, beta, st);
@@ -864,7 +921,8 @@ static gmrf_status logdet_impl(const gmrf_op* Q, int np, int m, uint64_t seed, c
       T* pr;
       if ((s = ws[g]->alloc((size_t)R.k * Q->n, &pr)) != GMRF_OK) return s;
       fft_forward_init_probes<T>(Q->plan, seed, c0[g], pg, pr, R.slot(0), R.F1, R.S, R.k, R.st);
-      precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, R.k, R.st);
+      if (lgcp_path(Q)) lgcp_col_init<T>(Q->plan, precond_mult(Q), R.slot(0), R.F1, R.k, R.st);
+      else precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, R.k, R.st);
     } else if (pg) {
       launch_init_from_i8<T>(pg, R.z.L, R.slot(0), R.S, R.st);
     } else {
@@ -914,6 +972,8 @@ extern "C" gmrf_status gmrf_logdet(const gmrf_op* Q, int32_t n_probes, int32_t m
   if (!Q) return fail(GMRF_EINVAL, "NULL operator");
   if (n_probes < 1 || n_probes > 65535) return fail(GMRF_EINVAL, "n_probes must be in 1..65535");
   if (m < 1 || m > tri_max_m()) return fail(GMRF_EINVAL, "m must be in 1..%d", tri_max_m());
+  if (Q->has_diag && !Q->precond)
+    return fail(GMRF_EUNSUPPORTED, "Q + diag(d) is handled with circulant preconditioning only (else pass it as CSR)");
   hipStream_t st = (hipStream_t)stream;
   if (Q->storage == GMRF_F64) return logdet_impl<double>(Q, n_probes, m, seed, probes, logdet, std_err, per_probe, st);
   return logdet_impl<float>(Q, n_probes, m, seed, probes, logdet, std_err, per_probe, st);
@@ -1000,7 +1060,8 @@ static gmrf_status kernel_bench_impl(const gmrf_op* Q, int which, int k, int rep
     launch = [&]() { op_apply_plain<T>(Q, R.slot(0), R.Qb, k, st); };
     b = 2.0 * vb + (Q->kind == 1 ? (double)Q->resident_bytes : 0.0);
   } else if (which == 1 || which == 2 || which == 4) {
-    if (!Q->precond) return fail(GMRF_EINVAL, "kernel %d needs circulant preconditioning", which);
+    if (!Q->precond || lgcp_path(Q))
+      return fail(GMRF_EINVAL, "kernel %d needs circulant preconditioning without a diagonal term", which);
     if (which == 1) {
       launch = [&]() {
         precond_lanczos_step<T>(Q->plan, Q->geom, Q->order, mult, R.slot(1), R.slot(0), R.slot(2), R.band, R.S, 2, 1,
@@ -1023,6 +1084,19 @@ static gmrf_status kernel_bench_impl(const gmrf_op* Q, int which, int k, int rep
   } else if (which == 3) {
     launch = [&]() { launch_update<T>(R.Qb, R.slot(0), R.slot(1), R.z.L, 1, 1, R.S, st); };
     b = 3.0 * vb;
+  } else if (which == 5 || which == 6) {
+    if (!lgcp_path(Q)) return fail(GMRF_EINVAL, "kernel %d needs a diagonal term and circulant preconditioning", which);
+    // the row pass opens iteration 1 (no stop decision on the seeded sums); the column pass runs as step 2 so
+    // that it reads v_{j-1}
+    const int only = which == 5 ? 1 : 2, jj = which == 5 ? 1 : 2;
+    HIP_TRY(hipMemsetAsync(R.F1, 0, vb, st));
+    HIP_TRY(hipMemsetAsync(R.Qb, 0, vb, st));
+    launch = [&, only, jj]() {
+      lgcp_lanczos_step<T>(Q->plan, mult, (const T*)diag_of(Q), R.F1, R.Qb, R.slot(1), R.slot(0), R.slot(2), R.S,
+                           jj, 1, k, st, only);
+    };
+    // row pass: read T1, write T2, read the diagonal once; column pass: read T2, v_j, v_{j-1}, write w_j, T1
+    b = which == 5 ? 2.0 * vb + (double)R.z.vec_bytes : 5.0 * vb;
   } else {
     return fail(GMRF_EINVAL, "unknown kernel id %d", which);
   }
@@ -1219,7 +1293,8 @@ extern "C" gmrf_status gmrf_sample_batch(int32_t n_fields, const gmrf_op* const*
   for (int f = 0; f < n_fields; ++f) {
     const gmrf_op* Q = ops[f];
     if (!Q) return fail(GMRF_EINVAL, "field %d: NULL operator", f);
-    if (Q->kind != 0 || Q->precond) return fail(GMRF_EUNSUPPORTED, "field %d: batches take lattice operators without preconditioning", f);
+    if (Q->kind != 0 || Q->precond || Q->has_diag)
+      return fail(GMRF_EUNSUPPORTED, "field %d: batches take lattice operators without preconditioning or diagonal", f);
     if (Q->ndim != ops[0]->ndim || Q->order != ops[0]->order || Q->storage != ops[0]->storage)
       return fail(GMRF_EINVAL, "field %d: all fields must share ndim, order and storage", f);
     if (k[f] < 1) return fail(GMRF_EINVAL, "field %d: k must be >= 1", f);

@@ -40,6 +40,9 @@ template <typename T> void launch_stencil_batch(int order, int dim, int max_tile
 int csr_blocks(long n);
 template <typename T> void launch_csr(long n, const int64_t* rp, const int32_t* ci, const T* va, bool lz, const T* X, long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k, hipStream_t st);
 
+// lgcp_step.hip: Y += diag(d) X for k columns of length n (the diagonal term of Q + diag(d))
+template <typename T> void launch_add_diag(const T* d, const T* X, T* Y, long n, int k, hipStream_t st);
+
 // tridiag_kernels.hip
 int tri_max_m();
 size_t tri_scratch_doubles(int k, int m_cap);

@@ -1,0 +1,235 @@
+"""GPU parity of the log-Gaussian Cox process proposal (Section 3): Q + H with the periodic prior
+Q as preconditioner (Section 5.1, Theorem 2 with alpha_n = 0), through the C ABI, against the
+FP64 oracle.
+
+The GPU runs Algorithm 1 on I + Lambda^{-1/2} F H F^H Lambda^{-1/2} in the packed spectral basis
+(two 2D FFTs per step, split over a row pass and a column pass); the oracle runs it on
+A = M^{-1/2} (Q + H) M^{-1/2} in real space (four FFTs per step).  A is a bounded perturbation
+of the identity (spectrum in [1, 1 + max H / lambda_min(M)]), so the process is well conditioned
+and parity is asserted tightly: relative 2-norm 1e-8 (FP64) / 1e-5 (FP32) at the oracle's m,
+identical iteration counts at the tolerance, and the Lanczos coefficients of the first steps.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import closed_form, dense, lattice, lgcp, logdet
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gm():
+    import os
+    import torch
+    from paper_1312_1476_amd import build as b
+    if not os.path.exists(b.LIB):
+        b.build()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1312_1476_amd as gm
+    return gm
+
+
+def _t(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _diag(n, seed, lo=0.05, hi=3.0):
+    return np.random.default_rng(seed).uniform(lo, hi, n)
+
+
+def _op(gm, shape, order, k2, tau, d, storage="f64"):
+    op = gm.Operator.lattice(shape, order, k2, tau, "periodic", storage)
+    op.set_diagonal(d)
+    return op.set_circulant_precond()
+
+
+def _sample(op, Zh, **kw):
+    X, info, al, be = op.sample(_t(Zh.T), coeffs=True, **kw)
+    return X.cpu().numpy().T, info, al, be
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (16, 32), (64, 8), (32, 4096)])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_apply_with_diagonal(gm, shape, storage):
+    import torch
+    n = shape[0] * shape[1]
+    d = _diag(n, 1)
+    op = gm.Operator.lattice(shape, 2, 0.2, 1.5, "periodic", storage)
+    op.set_diagonal(d)
+    X = np.random.default_rng(2).standard_normal((2, n))
+    dt = torch.float64 if storage == "f64" else torch.float32
+    Y = op.apply(_t(X, dt)).double().cpu().numpy()
+    P = lgcp.posterior_precision(shape, 2, 0.2, 1.5, d)
+    for r in range(2):
+        assert _rel(Y[r], P @ X[r]) <= (1e-14 if storage == "f64" else 1e-6)
+
+
+CASES = [((8, 8), 2, 0.3, 2.0, 1), ((16, 32), 2, 0.1, 4.0, 2), ((64, 8), 1, 0.2, 1.0, 3),
+         ((128, 64), 2, 0.02, 16.0, 2), ((8, 256), 1, 0.5, 1.0, 1)]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-o{c[1]}")
+@pytest.mark.parametrize("reorth", [False, True])
+def test_lgcp_sample_fp64(gm, case, reorth):
+    shape, order, k2, tau, k = case
+    n = shape[0] * shape[1]
+    # H between 0.1 and 10 times lambda_min(M): cond(A) <= 11, the LGCP regime of a bounded
+    # perturbation of the identity (the strong case below takes reorthogonalisation)
+    d = (tau * k2 ** order) * _diag(n, 3, 0.1, 10.0)
+    op = _op(gm, shape, order, k2, tau, d)
+    Zh = workloads.gaussian_block(n, k, 51, 0)
+    _, info_tol, _, _ = _sample(op, Zh, tol=1e-10, m_max=100, reorth=reorth)
+    refs = [lgcp.sample(shape, order, k2, tau, d, Zh[:, r], 100, tol=1e-10, reorth=reorth) for r in range(k)]
+    for r in range(k):
+        # with the plain recurrence rho_m is not monotone once orthogonality is lost, and the step
+        # that first crosses the tolerance can follow rounding
+        assert info_tol[r]["status"] == "OK"
+        assert abs(info_tol[r]["m_used"] - refs[r].m) <= (0 if reorth else 1)
+    # parity at the oracle's m (forced)
+    mf = max(ref.m for ref in refs)
+    X, info, al, be = _sample(op, Zh, tol=0.0, m_max=mf, reorth=reorth)
+    for r in range(k):
+        ref = lgcp.sample(shape, order, k2, tau, d, Zh[:, r], mf, tol=0.0, reorth=reorth)
+        assert info[r]["m_used"] == ref.m == mf
+        # coefficients: the first steps (before the plain recurrence loses orthogonality, after which
+        # they follow rounding); the sample at convergence is bounded by rho_m on both sides
+        p = min(ref.m, 8)
+        assert np.allclose(al[r, :p], ref.alpha[:p], rtol=1e-11, atol=0)
+        assert np.allclose(be[r, 1:p + 1], ref.beta[:p], rtol=1e-9, atol=0)
+        assert _rel(X[:, r], ref.x) <= 1e-8, _rel(X[:, r], ref.x)
+
+
+def test_lgcp_strong_diagonal_reorth(gm):
+    """cond(A) ~ 470 (H up to 3, lambda_min(M) = 0.0064): with CGS2 the iteration count at the
+    tolerance and the sample match the oracle's."""
+    shape, order, k2, tau, k = (128, 64), 2, 0.02, 16.0, 2
+    n = shape[0] * shape[1]
+    d = _diag(n, 3)
+    op = _op(gm, shape, order, k2, tau, d)
+    Zh = workloads.gaussian_block(n, k, 51, 1)
+    X, info, al, _ = _sample(op, Zh, tol=1e-10, m_max=200, reorth=True)
+    for r in range(k):
+        ref = lgcp.sample(shape, order, k2, tau, d, Zh[:, r], 200, tol=1e-10, reorth=True)
+        assert info[r]["status"] == "OK" and info[r]["m_used"] == ref.m
+        assert np.allclose(al[r, :8], ref.alpha[:8], rtol=1e-11, atol=0)
+        assert _rel(X[:, r], ref.x) <= 1e-8, _rel(X[:, r], ref.x)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 5])
+def test_lgcp_sample_prefix(gm, m):
+    shape, order, k2, tau = (32, 64), 2, 0.05, 8.0
+    n = shape[0] * shape[1]
+    d = _diag(n, 4, 0.5, 20.0)
+    op = _op(gm, shape, order, k2, tau, d)
+    Zh = workloads.gaussian_block(n, 2, 52, 0)
+    X, info, _, _ = _sample(op, Zh, tol=0.0, m_max=m)
+    for r in range(2):
+        ref = lgcp.sample(shape, order, k2, tau, d, Zh[:, r], m, tol=0.0)
+        assert info[r]["m_used"] == m
+        assert _rel(X[:, r], ref.x) <= 1e-8
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (8, 2048), (4096, 8)])
+def test_lgcp_sample_fp32(gm, shape):
+    order, k2, tau, k = 2, 0.05, 4.0, 2
+    n = shape[0] * shape[1]
+    d = _diag(n, 5)
+    op = _op(gm, shape, order, k2, tau, d, "f32")
+    Zh = workloads.gaussian_block(n, k, 53, 0)
+    X, info, _, _ = _sample(op, Zh, tol=1e-7, m_max=60)
+    for r in range(k):
+        ref = lgcp.sample(shape, order, k2, tau, d, Zh[:, r], info[r]["m_used"], tol=0.0)
+        assert _rel(X[:, r], ref.x) <= 1e-5, _rel(X[:, r], ref.x)
+
+
+def test_zero_diagonal_is_the_direct_sample(gm):
+    shape, k2, tau = (32, 64), 0.2, 3.0
+    n = shape[0] * shape[1]
+    op = _op(gm, shape, 2, k2, tau, np.zeros(n))
+    Zh = workloads.gaussian_block(n, 2, 54, 0)
+    X, info, _, _ = _sample(op, Zh, tol=1e-10, m_max=10)
+    assert [i["m_used"] for i in info] == [1, 1]
+    for r in range(2):
+        ex = closed_form.exact_sample_periodic(shape, 2, k2, tau, Zh[:, r])
+        assert _rel(X[:, r], ex) <= 1e-13
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_lgcp_logdet(gm, storage, tol):
+    shape, order, k2, tau, npb, m, seed = (32, 32), 2, 0.1, 4.0, 6, 30, 4242
+    n = shape[0] * shape[1]
+    d = _diag(n, 6)
+    op = _op(gm, shape, order, k2, tau, d, storage)
+    mean, se, per = op.logdet(npb, m, seed=seed)
+    P = lgcp.posterior_precision(shape, order, k2, tau, d)
+    ref = logdet.hutchinson_preconditioned(P, shape, order, k2, tau, npb, m, seed=seed)
+    assert np.all(np.abs(per - ref.per_probe) <= tol * np.abs(ref.per_probe))
+    assert abs(mean - ref.logdet) <= tol * abs(ref.logdet)
+    exact = dense.cholesky_logdet(P)
+    assert abs(mean - exact) < 5 * se + 1e-6 * abs(exact)
+
+
+def test_table1_iterations_flat_in_n(gm):
+    """Table 1's preconditioned row, on the synthetic LGCP workload: the Krylov dimension for the
+    a posteriori bound to fall below 1e-8 (rho_m, since lambda_min(A) >= 1) is the same from
+    16 x 16 to 4096 x 4096, and equal to the oracle's where the oracle runs in seconds."""
+    ms = {}
+    for N in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096):
+        spec = workloads.lgcp_prior(N)
+        d = workloads.lgcp_diagonal(N)
+        op = _op(gm, spec.shape, 2, spec.kappa2, spec.tau, d)
+        Zh = workloads.gaussian_block(N * N, 1, 5, 1)
+        X, info, _, _ = _sample(op, Zh, tol=1e-8, m_max=40)
+        assert info[0]["status"] == "OK"
+        ms[N] = info[0]["m_used"]
+        if N <= 128:
+            ref = lgcp.sample(spec.shape, 2, spec.kappa2, spec.tau, d, Zh[:, 0], 40, tol=1e-8)
+            assert ref.m == ms[N]
+            assert _rel(X[:, 0], ref.x) <= 1e-8
+        op.close()
+    assert max(ms.values()) - min(ms.values()) <= 1, ms
+
+
+def test_lgcp_full_size_batch(gm):
+    """512 x 512 LGCP proposal, 32 right-hand sides, FP64: columns 0 and 31 against the oracle."""
+    N, k = 512, 32
+    spec = workloads.lgcp_prior(N)
+    d = workloads.lgcp_diagonal(N)
+    op = _op(gm, spec.shape, 2, spec.kappa2, spec.tau, d)
+    Zh = workloads.gaussian_block(N * N, k, 5, 2)
+    X, info, _, _ = _sample(op, Zh, tol=1e-8, m_max=40)
+    for r in (0, 31):
+        ref = lgcp.sample(spec.shape, 2, spec.kappa2, spec.tau, d, Zh[:, r], 40, tol=1e-8)
+        assert info[r]["m_used"] == ref.m
+        assert _rel(X[:, r], ref.x) <= 1e-8
+
+
+def test_diagonal_unsupported_combinations(gm):
+    n = 16 * 16
+    d = _diag(n, 7)
+    op = gm.Operator.lattice((16, 16), 2, 0.1, 1.0, "periodic")
+    op.set_diagonal(d)
+    Z = _t(np.random.default_rng(0).standard_normal((1, n)))
+    with pytest.raises(gm.GmrfError):
+        op.sample(Z, tol=1e-8, m_max=10)            # no preconditioning: pass Q + H as CSR
+    with pytest.raises(gm.GmrfError):
+        op.logdet(2, 10)
+    free = gm.Operator.lattice((16, 16), 2, 0.1, 1.0, "free")
+    free.set_diagonal(d)
+    with pytest.raises(gm.GmrfError):
+        free.set_circulant_precond()                # M = Q needs the periodic lattice
+    Q = lattice.lattice_precision((4, 4), 1, 0.5, 1.0, "free")
+    csr = gm.Operator.csr(16, Q.indptr, Q.indices, Q.data)
+    with pytest.raises(gm.GmrfError):
+        csr.set_diagonal(np.ones(16))
+    with pytest.raises(gm.GmrfError):
+        op.set_diagonal(np.full(n, np.nan))
