@@ -52,8 +52,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
-    ap.add_argument("--only", default="", help="profiling: run only this leg (headline|counters)")
+    ap.add_argument("--only", default="", help="profiling: run only this leg (headline|counters|lgcp)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-lgcp", action="store_true", help="skip the log-Gaussian Cox process leg")
     ap.add_argument("--kernel", default="", help="counters leg: kernel to run (default: the dominant one)")
     ap.add_argument("--storage", default="f64", help="counters leg: storage dtype (f64|f32)")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="arrival window per serving rate")
@@ -101,6 +102,10 @@ def main():
 
     def step(op, tol, m_max):
         return op.sample(Z, tol=tol, m_max=m_max, reorth=False)
+
+    if args.only == "lgcp":
+        print(json.dumps({"lgcp": lgcp_leg(gm, torch, stream)}))
+        return
 
     # ---- headline: FP64 storage, stop at rho <= 1e-5 ---------------------------------------------
     for _ in range(args.warmup):
@@ -190,6 +195,10 @@ def main():
                       "avg_us": round(r["avg_us"], 2), "bytes_per_launch": r["bytes"]}
     result["spmv_13pt_32rhs"] = spmv
 
+    # ---- log-Gaussian Cox process proposal (Q + H, M = Q): Table 1 and throughput --------------------
+    if not args.no_lgcp:
+        result["lgcp"] = lgcp_leg(gm, torch, stream)
+
     # ---- serving: Poisson request stream over a pool of 64 resident operators ---------------------------
     if not args.no_serve:
         result["serving"] = serving_leg(gm, torch, args.serve_seconds)
@@ -220,6 +229,62 @@ def main():
     result["at_m_max_300"] = {"f64": extra["f64"], "f32": extra["f32"]}
     result["fp32_storage_at_tol"] = extra["f32_tol"]
     print(json.dumps(result))
+
+
+LGCP_TOL = 1e-8                  # Table 1's accuracy
+LGCP_TABLE_N = (16, 32, 64, 128, 256, 512, 1024, 2048, 4096)
+LGCP_BATCH = (512, 32)           # side, right-hand sides of the throughput line
+
+
+def lgcp_leg(gm, torch, stream):
+    """The sMMALA proposal of the log-Gaussian Cox process on the unit torus (workload C5): Q + H with
+    the periodic prior as preconditioner (two 2D FFTs per step).  Table 1's preconditioned row (Krylov
+    dimension at rho <= 1e-8, one right-hand side, FP64) from 16^2 to 4096^2, the time of one such
+    sample, the batch throughput at 512^2 x 32, and the two passes of the step timed alone."""
+    out = {"workload": "LGCP proposal: periodic 13-point prior tau = N^2, kappa2 = 100 / N^2 on the unit "
+                       "torus, H = h^2 exp(x) at a smooth synthetic log-intensity; M = prior; FP64",
+           "tol_rho": LGCP_TOL, "table1_preconditioned_m": {}, "ms_per_sample_k1": {}}
+    for N in LGCP_TABLE_N:
+        spec = workloads.lgcp_prior(N)
+        op = gm.Operator.lattice(spec.shape, 2, spec.kappa2, spec.tau, "periodic", "f64")
+        op.set_diagonal(workloads.lgcp_diagonal(N))
+        op.set_circulant_precond()
+        Z1 = torch.from_numpy(np.ascontiguousarray(workloads.gaussian_block(N * N, 1, 5, 1).T)).to("cuda:0")
+        op.sample(Z1, tol=LGCP_TOL, m_max=40)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            X, info = op.sample(Z1, tol=LGCP_TOL, m_max=40)
+        torch.cuda.synchronize()
+        out["table1_preconditioned_m"][str(N)] = info[0]["m_used"]
+        out["ms_per_sample_k1"][str(N)] = round(1000 * (time.perf_counter() - t0) / reps, 3)
+        op.close()
+        del X, Z1
+    N, k = LGCP_BATCH
+    spec = workloads.lgcp_prior(N)
+    op = gm.Operator.lattice(spec.shape, 2, spec.kappa2, spec.tau, "periodic", "f64")
+    op.set_diagonal(workloads.lgcp_diagonal(N))
+    op.set_circulant_precond()
+    Zb = torch.from_numpy(np.ascontiguousarray(workloads.gaussian_block(N * N, k, 5, 2).T)).to("cuda:0")
+    op.sample(Zb, tol=LGCP_TOL, m_max=40)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        X, info = op.sample(Zb, tol=LGCP_TOL, m_max=40)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    out["batch"] = {"side": N, "rhs": k, "samples_per_s": round(k / dt, 1), "ms_per_call": round(1000 * dt, 3),
+                    "m_used_max": max(i["m_used"] for i in info)}
+    kern = {}
+    for name in ("lgcp_rows", "lgcp_cols"):
+        r = gm.kernel_bench(op, name, k, reps=50, stream=stream)
+        kern[name] = {"avg_us": round(r["avg_us"], 2), "bytes_per_launch": r["bytes"],
+                      "achieved_gbs": round(r["achieved_gbs"], 1), "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4)}
+    out["kernels_512x512_32rhs"] = kern
+    op.close()
+    return out
 
 
 def serving_leg(gm, torch, seconds):

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kFftThreads) void k_cols(const C2<T>* __restrict__ 
                                                       const T* __restrict__ mult, T scale) {
   __shared__ C2<T> buf[FftCfg<T>::ELEMS];
   const int r = blockIdx.y;
-  const int c0 = blockIdx.x * nf;
+  const int c0 = xcd_col_block(blockIdx.x, gridDim.x) * nf;
   const size_t fsz = (size_t)N1 * H;   // complex values per field
   const C2<T>* src = in + (size_t)r * fsz;
   for (int idx = threadIdx.x; idx < nf * N1; idx += kFftThreads) {

@@ -30,7 +30,9 @@ __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
 // nf sequences of length N in LDS: element e of sequence f at buf[f * fs + e * es].
 // INTER: items enumerate f fastest (interleaved sequences, es = nf, fs = 1), else e fastest.
-template <typename T, bool INTER>
+// EARLY_TW: each stage requests its twiddles together with its LDS reads, before the barrier, so
+// that a twiddle table in global memory costs one latency per stage instead of two.
+template <typename T, bool INTER, bool EARLY_TW = false>
 __device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* __restrict__ tw, bool inv) {
   constexpr int MAXIT = FftCfg<T>::MAXIT;
   const int logN = ilog2(N);
@@ -39,6 +41,7 @@ __device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* 
   for (int s = 0; s < logN / 2; ++s) {
     const int items = nf * n4;
     C2<T> v[MAXIT][4];
+    C2<T> wv[EARLY_TW ? MAXIT : 1][3];
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
       const int item = threadIdx.x + it * kFftThreads;
@@ -47,6 +50,12 @@ __device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* 
         const int j = INTER ? item / nf : item % n4;
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[it][r] = buf[f * fs + (j + r * n4) * es];
+        if (EARLY_TW) {
+          const int k = j & (Ns - 1);
+          const int step = N / (Ns * 4);
+#pragma unroll
+          for (int r = 1; r < 4; ++r) wv[EARLY_TW ? it : 0][r - 1] = tw[r * k * step];
+        }
       }
     }
     __syncthreads();
@@ -60,7 +69,7 @@ __device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* 
         const int step = N / (Ns * 4);
 #pragma unroll
         for (int r = 1; r < 4; ++r) {
-          C2<T> w = tw[r * k * step];
+          C2<T> w = EARLY_TW ? wv[EARLY_TW ? it : 0][r - 1] : tw[r * k * step];
           if (inv) w.y = -w.y;
           v[it][r] = cmul(v[it][r], w);
         }
@@ -87,6 +96,7 @@ __device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* 
     const int n2 = N >> 1;
     const int items = nf * n2;
     C2<T> v[2 * MAXIT][2];
+    C2<T> wv[EARLY_TW ? 2 * MAXIT : 1];
 #pragma unroll
     for (int it = 0; it < 2 * MAXIT; ++it) {
       const int item = threadIdx.x + it * kFftThreads;
@@ -95,6 +105,7 @@ __device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* 
         const int j = INTER ? item / nf : item % n2;
         v[it][0] = buf[f * fs + j * es];
         v[it][1] = buf[f * fs + (j + n2) * es];
+        if (EARLY_TW) wv[EARLY_TW ? it : 0] = tw[(j & (Ns - 1)) * (N / (Ns * 2))];
       }
     }
     __syncthreads();
@@ -105,7 +116,7 @@ __device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* 
         const int f = INTER ? item % nf : item / n2;
         const int j = INTER ? item / nf : item % n2;
         const int k = j & (Ns - 1);
-        C2<T> w = tw[k * (N / (Ns * 2))];
+        C2<T> w = EARLY_TW ? wv[EARLY_TW ? it : 0] : tw[k * (N / (Ns * 2))];
         if (inv) w.y = -w.y;
         const C2<T> b = cmul(v[it][1], w), a = v[it][0];
         const int idxD = (j / Ns) * Ns * 2 + k;
@@ -115,6 +126,18 @@ __device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* 
     }
     __syncthreads();
   }
+}
+
+#ifndef GMRF_XCD_COLS
+#define GMRF_XCD_COLS 1        // column blocks of one XCD take adjacent columns
+#endif
+// Column block of launch block b (of nb) in the column passes.  Blocks are dispatched to the 8 XCDs
+// round robin (b mod 8); giving the blocks of one XCD consecutive column groups keeps the rows'
+// shared 128-byte lines in that XCD's L2 when a block covers fewer columns than a line holds (FP64
+// sides of 1024 and more: LGCP column pass 869 -> 565 us at 4096^2, 1208 -> 712 us at 2048^2 x 8).
+__device__ __forceinline__ int xcd_col_block(int b, int nb) {
+  if (!GMRF_XCD_COLS || (nb & 7) != 0) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
 // Multiply the LDS tile (columns c0.., row-major [k1][c]) by lambda^{-1/2} * scale.  Column 0 holds
