@@ -164,6 +164,25 @@ gmrf_status gmrf_logdet(const gmrf_op* Q, int32_t n_probes, int32_t m, uint64_t 
                         const int8_t* probes, double* logdet, double* std_err,
                         double* per_probe, void* stream);
 
+/* Coloured Hutchinson (Section 6.1): colour (host, n entries in 0..n_colours-1) partitions the
+ * lattice points; probe p is the Rademacher probe of gmrf_logdet's rule split by class, and each
+ * class runs its own quadrature: Gamma_p = sum_c ||v_pc||^2 e_1^T log(T_m,c) e_1 (+ log det M when
+ * preconditioned).  Unbiased for any partition; a colouring of the graph of Q^p
+ * (gmrf_distance_colouring) keeps nodes within p steps in different classes and so removes the
+ * largest off-diagonal terms of log(Q) from the variance.  Runs n_probes * n_colours Lanczos columns
+ * (at most 65535).  Outputs as for gmrf_logdet (per_probe[p] = Gamma_p).  EINVAL: a colour out of
+ * range.                                                                                      */
+gmrf_status gmrf_logdet_coloured(const gmrf_op* Q, int32_t n_probes, int32_t m, uint64_t seed,
+                                 const int32_t* colour, int32_t n_colours, double* logdet,
+                                 double* std_err, double* per_probe, void* stream);
+
+/* Distance-p colouring for the coloured estimator (Section 6.1): first fit in lattice-point order,
+ * each point taking the smallest colour not used by an already coloured point within p steps of
+ * it in the graph of Q (i.e. adjacent in the graph of Q^p).  Lattice handles: points within L1
+ * distance p * order (wrapped on periodic lattices); CSR handles: breadth-first search on the
+ * pattern.  colour: host array of n entries; *n_colours: number of classes.  p = 0: one class.  */
+gmrf_status gmrf_distance_colouring(const gmrf_op* Q, int32_t p, int32_t* colour, int32_t* n_colours);
+
 /* Rademacher probes (Section 6) into a device int8 n x n_probes block:
  *   v_p[i] = +1 if bit (i mod 256) mod 64 of word (i mod 256) / 64 of
  *            Philox4x64-10(counter = (i / 256, p, 0, 0), key = (seed, 0)) is 0, else -1.

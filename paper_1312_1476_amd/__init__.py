@@ -178,6 +178,29 @@ class Operator:
               "gmrf_logdet")
         return mean.value, se.value, per
 
+    def logdet_coloured(self, n_probes, m, colour, seed=0, stream=None):
+        """Coloured Hutchinson estimate (Section 6.1) for a partition `colour` (n integers in
+        0..K-1): (mean, standard error, per-probe values as numpy)."""
+        col = np.ascontiguousarray(colour, dtype=np.int32)
+        if col.shape != (self.n,):
+            raise ValueError(f"colour must have shape ({self.n},)")
+        K = int(col.max()) + 1 if col.size else 1
+        mean, se = C.c_double(), C.c_double()
+        per = np.zeros(n_probes)
+        check(lib().gmrf_logdet_coloured(self._h, int(n_probes), int(m), C.c_uint64(seed & (2 ** 64 - 1)),
+                                         col.ctypes.data_as(C.c_void_p), K, C.byref(mean), C.byref(se),
+                                         per.ctypes.data_as(C.c_void_p), _stream_ptr(stream)),
+              "gmrf_logdet_coloured")
+        return mean.value, se.value, per
+
+    def distance_colouring(self, p):
+        """Distance-p colouring of the lattice points (graph of Q^p, first fit): int32 numpy array."""
+        col = np.zeros(self.n, dtype=np.int32)
+        K = C.c_int32()
+        check(lib().gmrf_distance_colouring(self._h, int(p), col.ctypes.data_as(C.c_void_p), C.byref(K)),
+              "gmrf_distance_colouring")
+        return col
+
 
 def sample_batch(ops, Zs, tol=1e-8, m_max=300, stream=None):
     """Uneven batch: field f is ops[f] with right-hand sides Zs[f] ((k_f, n_f) FP64 CUDA

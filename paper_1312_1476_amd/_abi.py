@@ -42,6 +42,9 @@ SIGNATURES = {
                                     C.c_void_p, C.POINTER(Info), C.c_void_p]),
     "gmrf_logdet": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p,
                               C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
+    "gmrf_logdet_coloured": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p, C.c_int32,
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
+    "gmrf_distance_colouring": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
     "gmrf_rademacher": (C.c_int, [C.c_uint64, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p]),
     "gmrf_tridiag_invsqrt_e1": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                           C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -58,10 +58,12 @@ void fft_apply_inv_sqrt_M(const FftPlan& p, const T* mult, const T* X, T* Y, T* 
 template <typename T>
 void fft_forward_init(const FftPlan& p, const double* Z, T* V0, T* tmp, const LzState& S, int k, hipStream_t st);
 
-// same for Rademacher probes p0 .. p0 + k - 1 (from seed, or from an int8 block when probes != nullptr).
+// same for Rademacher probe columns p0 .. p0 + k - 1 (from seed, or from an int8 block when probes != nullptr;
+// with a colouring, column q is probe q / K restricted to class q mod K).
 template <typename T>
 void fft_forward_init_probes(const FftPlan& p, uint64_t seed, int p0, const int8_t* probes, T* real_tmp, T* V0,
-                             T* tmp, const LzState& S, int k, hipStream_t st);
+                             T* tmp, const LzState& S, int k, hipStream_t st, const int32_t* colour = nullptr,
+                             int K = 1);
 
 // Preconditioned Lanczos step (precond_step.hip).  Opens iteration j (beta_{j-1} from the partial
 // sums, stopping rule), applies A_hat = I - Lambda^{-1/2} F D F^H Lambda^{-1/2} to v_j = Xj / beta_{j-1}

@@ -238,10 +238,10 @@ void fft_forward_init(const FftPlan& p, const double* Z, T* V0, T* tmp, const Lz
 
 template <typename T>
 void fft_forward_init_probes(const FftPlan& p, uint64_t seed, int p0, const int8_t* probes, T* real_tmp, T* V0,
-                             T* tmp, const LzState& S, int k, hipStream_t st) {
+                             T* tmp, const LzState& S, int k, hipStream_t st, const int32_t* colour, int K) {
   const long n = (long)p.N1 * p.N2;
   if (probes) launch_init_from_i8<T>(probes, n, real_tmp, S, st);
-  else launch_init_rademacher<T>(seed, n, p0, real_tmp, S, st);
+  else launch_init_rademacher<T>(seed, n, p0, real_tmp, S, st, colour, K);
   rows_r2c<T, T>(p, real_tmp, n, tmp, n / 2, (T)1, nullptr, k, st);
   cols<T, kColFwdInit>(p, tmp, V0, nullptr, (T)(1.0 / std::sqrt((double)n)), k, st);
   launch_norm_partials<T>(V0, n, S, st);
@@ -258,7 +258,7 @@ void fft_backward_output(const FftPlan& p, const void* mult, const T* U, double*
 #define INST(T)                                                                                            \
   template void fft_apply_inv_sqrt_M<T>(const FftPlan&, const T*, const T*, T*, T*, int, hipStream_t);     \
   template void fft_forward_init<T>(const FftPlan&, const double*, T*, T*, const LzState&, int, hipStream_t); \
-  template void fft_forward_init_probes<T>(const FftPlan&, uint64_t, int, const int8_t*, T*, T*, T*, const LzState&, int, hipStream_t); \
+  template void fft_forward_init_probes<T>(const FftPlan&, uint64_t, int, const int8_t*, T*, T*, T*, const LzState&, int, hipStream_t, const int32_t*, int); \
   template void fft_backward_output<T>(const FftPlan&, const void*, const T*, double*, T*, const LzState&, int, hipStream_t);
 INST(double)
 INST(float)

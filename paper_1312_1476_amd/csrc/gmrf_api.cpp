@@ -153,7 +153,9 @@ struct gmrf_op {
   int64_t n = 0;
   StencilGeom geom{};
   int dim = 1;
-  // CSR (device)
+  // CSR (device; the pattern is also kept on the host for the distance colouring)
+  std::vector<int64_t> h_rp;
+  std::vector<int32_t> h_ci;
   int64_t* rp = nullptr;
   int32_t* ci = nullptr;
   void* va = nullptr;
@@ -278,6 +280,8 @@ gmrf_status gmrf_op_create_csr(int64_t n, const int64_t* row_ptr, const int32_t*
     }
   }
   op->resident_bytes = (n + 1) * 8 + nnz * (4 + vb);
+  op->h_rp.assign(row_ptr, row_ptr + n + 1);
+  op->h_ci.assign(col_idx, col_idx + nnz);
   *out = op.release();
   return GMRF_OK;
 }
@@ -893,15 +897,19 @@ extern "C" gmrf_status gmrf_sample(const gmrf_op* Q, const double* Z, int64_t k,
 }
 
 // ---- log-determinant ------------------------------------------------------------------------------------
+// np probes; with a colouring (device, K classes) every probe runs as K columns, one per class
+// (Section 6.1), and the aggregate sums each probe's K quadratures.
 template <typename T>
 static gmrf_status logdet_impl(const gmrf_op* Q, int np, int m, uint64_t seed, const int8_t* probes,
-                               double* logdet, double* std_err, double* per_probe, hipStream_t st) {
-  const int G = groups_for(Q, np);
+                               const int32_t* colour, int K, double* logdet, double* std_err, double* per_probe,
+                               hipStream_t st) {
+  const int ncol = np * K;
+  const int G = groups_for(Q, ncol);
   ForkJoin fj;
   gmrf_status s = fj.fork(st, G);
   if (s != GMRF_OK) return s;
   std::vector<int> c0(G + 1);
-  for (int g = 0; g <= G; ++g) c0[g] = (int)((int64_t)np * g / G);
+  for (int g = 0; g <= G; ++g) c0[g] = (int)((int64_t)ncol * g / G);
   std::vector<std::unique_ptr<Workspace>> ws;
   std::vector<Run<T>> Rs(G);
   for (int g = 0; g < G; ++g) {
@@ -920,7 +928,7 @@ static gmrf_status logdet_impl(const gmrf_op* Q, int np, int m, uint64_t seed, c
       // probes in real space, then into the spectral basis
       T* pr;
       if ((s = ws[g]->alloc((size_t)R.k * Q->n, &pr)) != GMRF_OK) return s;
-      fft_forward_init_probes<T>(Q->plan, seed, c0[g], pg, pr, R.slot(0), R.F1, R.S, R.k, R.st);
+      fft_forward_init_probes<T>(Q->plan, seed, c0[g], pg, pr, R.slot(0), R.F1, R.S, R.k, R.st, colour, K);
       if (lgcp_path(Q)) lgcp_col_init<T>(Q->plan, precond_mult(Q), R.slot(0), R.F1, R.k, R.st);
       else precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, R.k, R.st);
     } else if (pg) {
@@ -928,17 +936,17 @@ static gmrf_status logdet_impl(const gmrf_op* Q, int np, int m, uint64_t seed, c
     } else {
       LzState S2 = R.S;
       S2.Pb = rademacher_blocks(R.z.L);
-      launch_init_rademacher<T>(seed, R.z.L, c0[g], R.slot(0), S2, R.st);
+      launch_init_rademacher<T>(seed, R.z.L, c0[g], R.slot(0), S2, R.st, colour, K);
       R.pb_first = S2.Pb;  // opener of iteration 1 reduces the probe partials
     }
     if (!Q->precond) fused_init<T>(R);
   }
   const std::vector<char> live(G, 1);
   for (int j = 1; j <= m; ++j) iterate_all<T>(Rs, j, live);
-  // per-probe quadrature e_1^T log(T_m) e_1 and ||v_p||^2 = beta_0^2, gathered for the aggregate
+  // per-column quadrature e_1^T log(T_m) e_1 and ||v||^2 = beta_0^2, gathered for the aggregate
   double *g_all, *b0_all;
-  if ((s = ws[0]->alloc((size_t)np * 4, &g_all)) != GMRF_OK) return s;
-  if ((s = ws[0]->alloc((size_t)np, &b0_all)) != GMRF_OK) return s;
+  if ((s = ws[0]->alloc((size_t)ncol + 2 + np, &g_all)) != GMRF_OK) return s;
+  if ((s = ws[0]->alloc((size_t)ncol, &b0_all)) != GMRF_OK) return s;
   for (int g = 0; g < G; ++g) {
     Run<T>& R = Rs[g];
     launch_finalize(R.S, R.st);
@@ -948,18 +956,18 @@ static gmrf_status logdet_impl(const gmrf_op* Q, int np, int m, uint64_t seed, c
                              sizeof(double), R.k, hipMemcpyDeviceToDevice, R.st));
   }
   if ((s = fj.join()) != GMRF_OK) return s;
-  double* agg = g_all + np;
-  launch_hutchinson_aggregate(g_all, b0_all, 1, np, Q->precond ? Q->logdet_M : 0.0, agg, st);
+  double* agg = g_all + ncol;
+  launch_hutchinson_aggregate(g_all, b0_all, 1, np, K, Q->precond ? Q->logdet_M : 0.0, agg, st);
   HIP_TRY(hipGetLastError());
   std::vector<double> gam(np), out(2);
-  std::vector<int> stt(np);
+  std::vector<int> stt(ncol);
   HIP_TRY(hipMemcpyAsync(gam.data(), agg + 2, np * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(out.data(), agg, 16, hipMemcpyDeviceToHost, st));
   for (int g = 0; g < G; ++g)
     HIP_TRY(hipMemcpyAsync(stt.data() + c0[g], Rs[g].S.status, Rs[g].k * sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  for (int p = 0; p < np; ++p)
-    if (stt[p] == kENOTSPD) return fail(GMRF_ENOTSPD, "probe %d: operator is not positive definite", p);
+  for (int q = 0; q < ncol; ++q)
+    if (stt[q] == kENOTSPD) return fail(GMRF_ENOTSPD, "probe %d: operator is not positive definite", q / K);
   if (logdet) *logdet = out[0];
   if (std_err) *std_err = out[1];
   if (per_probe) std::memcpy(per_probe, gam.data(), np * sizeof(double));
@@ -975,8 +983,113 @@ extern "C" gmrf_status gmrf_logdet(const gmrf_op* Q, int32_t n_probes, int32_t m
   if (Q->has_diag && !Q->precond)
     return fail(GMRF_EUNSUPPORTED, "Q + diag(d) is handled with circulant preconditioning only (else pass it as CSR)");
   hipStream_t st = (hipStream_t)stream;
-  if (Q->storage == GMRF_F64) return logdet_impl<double>(Q, n_probes, m, seed, probes, logdet, std_err, per_probe, st);
-  return logdet_impl<float>(Q, n_probes, m, seed, probes, logdet, std_err, per_probe, st);
+  if (Q->storage == GMRF_F64)
+    return logdet_impl<double>(Q, n_probes, m, seed, probes, nullptr, 1, logdet, std_err, per_probe, st);
+  return logdet_impl<float>(Q, n_probes, m, seed, probes, nullptr, 1, logdet, std_err, per_probe, st);
+}
+
+extern "C" gmrf_status gmrf_logdet_coloured(const gmrf_op* Q, int32_t n_probes, int32_t m, uint64_t seed,
+                                            const int32_t* colour, int32_t n_colours, double* logdet,
+                                            double* std_err, double* per_probe, void* stream) {
+  if (!Q || !colour) return fail(GMRF_EINVAL, "NULL argument");
+  if (n_probes < 1 || n_colours < 1 || (int64_t)n_probes * n_colours > 65535)
+    return fail(GMRF_EINVAL, "need n_probes >= 1, n_colours >= 1 and n_probes * n_colours <= 65535");
+  if (m < 1 || m > tri_max_m()) return fail(GMRF_EINVAL, "m must be in 1..%d", tri_max_m());
+  if (Q->has_diag && !Q->precond)
+    return fail(GMRF_EUNSUPPORTED, "Q + diag(d) is handled with circulant preconditioning only (else pass it as CSR)");
+  for (int64_t i = 0; i < Q->n; ++i)
+    if (colour[i] < 0 || colour[i] >= n_colours)
+      return fail(GMRF_EINVAL, "colour[%lld] = %d is outside 0..%d", (long long)i, colour[i], n_colours - 1);
+  hipStream_t st = (hipStream_t)stream;
+  Workspace ws(st);
+  int32_t* dcol;
+  gmrf_status s = ws.alloc((size_t)Q->n, &dcol);
+  if (s != GMRF_OK) return s;
+  HIP_TRY(hipMemcpyAsync(dcol, colour, (size_t)Q->n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  if (Q->storage == GMRF_F64)
+    return logdet_impl<double>(Q, n_probes, m, seed, nullptr, dcol, n_colours, logdet, std_err, per_probe, st);
+  return logdet_impl<float>(Q, n_probes, m, seed, nullptr, dcol, n_colours, logdet, std_err, per_probe, st);
+}
+
+// Distance-p colouring (Section 6.1): first fit in node order, a node taking the smallest colour not
+// used by an already coloured node within p steps of it in the graph of Q (the graph of Q^p).  Lattice
+// handles: Q couples nodes within lattice (L1) distance `order`, so the neighbours are the nodes within
+// L1 distance p * order (wrapped on periodic axes); CSR handles: breadth-first search to depth p.
+extern "C" gmrf_status gmrf_distance_colouring(const gmrf_op* Q, int32_t p, int32_t* colour, int32_t* n_colours) {
+  if (!Q || !colour || !n_colours || p < 0) return fail(GMRF_EINVAL, "bad arguments");
+  const int64_t n = Q->n;
+  std::vector<int32_t> col((size_t)n, -1);
+  std::vector<uint8_t> used;
+  int32_t K = 1;
+  auto first_fit = [&](int64_t i, const std::vector<int64_t>& nb) {
+    used.assign((size_t)K + 1, 0);
+    for (int64_t j : nb)
+      if (col[(size_t)j] >= 0) used[(size_t)col[(size_t)j]] = 1;
+    int32_t c = 0;
+    while (used[(size_t)c]) ++c;
+    col[(size_t)i] = c;
+    K = std::max(K, c + 1);
+  };
+  std::vector<int64_t> nb;
+  if (p == 0) {
+    std::fill(col.begin(), col.end(), 0);
+  } else if (Q->kind == 0) {
+    const int D = p * Q->order;
+    const int64_t N0 = Q->shape[0], N1 = Q->shape[1], N2 = Q->shape[2];
+    const bool per = Q->bc == GMRF_PERIODIC;
+    // offsets of the L1 ball of radius D, per axis clipped to the lattice (a periodic axis reaches at
+    // most its whole cycle)
+    std::vector<std::array<int, 3>> off;
+    for (int a = -D; a <= D; ++a)
+      for (int b = -(D - std::abs(a)); b <= D - std::abs(a); ++b)
+        for (int c = -(D - std::abs(a) - std::abs(b)); c <= D - std::abs(a) - std::abs(b); ++c)
+          if (a || b || c) off.push_back({a, b, c});
+    std::vector<int64_t> stamp((size_t)n, -1);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t i0 = i / (N1 * N2), i1 = (i / N2) % N1, i2 = i % N2;
+      nb.clear();
+      for (const auto& o : off) {
+        int64_t j0 = i0 + o[0], j1 = i1 + o[1], j2 = i2 + o[2];
+        if (per) {
+          j0 = ((j0 % N0) + N0) % N0;
+          j1 = ((j1 % N1) + N1) % N1;
+          j2 = ((j2 % N2) + N2) % N2;
+        } else if (j0 < 0 || j0 >= N0 || j1 < 0 || j1 >= N1 || j2 < 0 || j2 >= N2) {
+          continue;
+        }
+        const int64_t j = (j0 * N1 + j1) * N2 + j2;
+        if (j != i && stamp[(size_t)j] != i) {
+          stamp[(size_t)j] = i;
+          nb.push_back(j);
+        }
+      }
+      first_fit(i, nb);
+    }
+  } else {
+    std::vector<int64_t> stamp((size_t)n, -1), frontier, next;
+    for (int64_t i = 0; i < n; ++i) {
+      nb.clear();
+      frontier.assign(1, i);
+      stamp[(size_t)i] = i;
+      for (int d = 0; d < p && !frontier.empty(); ++d) {
+        next.clear();
+        for (int64_t u : frontier)
+          for (int64_t e = Q->h_rp[(size_t)u]; e < Q->h_rp[(size_t)u + 1]; ++e) {
+            const int64_t v = Q->h_ci[(size_t)e];
+            if (stamp[(size_t)v] != i) {
+              stamp[(size_t)v] = i;
+              next.push_back(v);
+              nb.push_back(v);
+            }
+          }
+        frontier.swap(next);
+      }
+      first_fit(i, nb);
+    }
+  }
+  std::memcpy(colour, col.data(), (size_t)n * sizeof(int32_t));
+  *n_colours = K;
+  return GMRF_OK;
 }
 
 extern "C" gmrf_status gmrf_rademacher(uint64_t seed, int64_t n, int32_t n_probes, int8_t* out, void* stream) {

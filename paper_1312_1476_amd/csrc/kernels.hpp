@@ -13,10 +13,12 @@ int ew_blocks(long L);
 int rademacher_blocks(long n);
 template <typename T> void launch_init_from_f64(const double* Z, long zld, long L, T* V0, const LzState& S, hipStream_t st);
 template <typename T> void launch_init_from_i8(const int8_t* P, long L, T* V0, const LzState& S, hipStream_t st);
-template <typename T> void launch_init_rademacher(uint64_t seed, long n, int p0, T* V0, const LzState& S, hipStream_t st);
+// column q = p0 + r of V0 <- probe q / K restricted to colour class q mod K (colour NULL, K = 1: probe q)
+template <typename T> void launch_init_rademacher(uint64_t seed, long n, int p0, T* V0, const LzState& S, hipStream_t st,
+                                                  const int32_t* colour = nullptr, int K = 1);
 void launch_rademacher_i8(uint64_t seed, long n, int nprobes, int8_t* out, hipStream_t st);
 template <typename T> void launch_update(const T* Qb, const T* Vj, T* W, long L, int j, int with_norm, const LzState& S, hipStream_t st);
-void launch_hutchinson_aggregate(const double* g, const double* beta, int ldb, int np, double shift, double* out, hipStream_t st);
+void launch_hutchinson_aggregate(const double* g, const double* beta, int ldb, int np, int K, double shift, double* out, hipStream_t st);
 void launch_finalize(const LzState& S, hipStream_t st);
 template <typename T> void launch_norm_partials(const T* V0, long L, const LzState& S, hipStream_t st);
 template <typename T> void launch_reorth(T* V, long L, int j, double* part_h, double* h, int hstride, const LzState& S, hipStream_t st);

@@ -57,10 +57,12 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
 
 // Rademacher probe entries: lane l of a wave generates the four Philox words of block
 // (wave_base + l) (256 entries); the wave then writes its 64 x 256 entries with coalesced
-// stores, reading each word from its owner lane.
+// stores, reading each word from its owner lane.  With a colouring (Section 6.1) entries whose
+// node is not of class `cls` are zero: the probe restricted to one colour class.
 template <typename OutT>
 __device__ __forceinline__ void rademacher_wave(uint64_t seed, int p, long n, long wave_block0,
-                                                OutT* out, double& acc) {
+                                                OutT* out, double& acc, const int32_t* colour = nullptr,
+                                                int cls = 0) {
   const int lane = threadIdx.x & (kWave - 1);
   uint64_t c[4] = {(uint64_t)(wave_block0 + lane), (uint64_t)p, 0ull, 0ull};
   philox4x64_10(c, seed, 0ull);
@@ -75,9 +77,10 @@ __device__ __forceinline__ void rademacher_wave(uint64_t seed, int p, long n, lo
     const long e = e0 + 64L * q + lane;
     if (e < n) {
       const int bit = (int)((word >> lane) & 1ull);
-      const OutT v = bit ? (OutT)-1 : (OutT)1;
+      const bool on = colour == nullptr || colour[e] == cls;
+      const OutT v = !on ? (OutT)0 : bit ? (OutT)-1 : (OutT)1;
       out[e] = v;
-      acc += 1.0;
+      acc += on ? 1.0 : 0.0;
     }
   }
 }
@@ -90,16 +93,19 @@ __global__ __launch_bounds__(256) void k_rademacher_i8(uint64_t seed, long n, in
   rademacher_wave<int8_t>(seed, p, n, wave_block0, out + (size_t)p * n, acc);
 }
 
-// Probes p0, p0 + 1, ... straight into Krylov slot 0 (storage type, column p - p0); ||v||^2 partials
-// per block.
+// Probe columns q = p0, p0 + 1, ... straight into Krylov slot 0 (storage type, column q - p0); ||v||^2
+// partials per block.  Column q is probe q / K restricted to colour class q mod K (K = 1, colour = NULL:
+// the plain probe q).
 template <typename T>
 __global__ __launch_bounds__(256) void k_init_rademacher(uint64_t seed, long n, int p0, T* __restrict__ V0,
-                                                         LzState S) {
+                                                         LzState S, const int32_t* __restrict__ colour, int K) {
   __shared__ double lds[256 / kWave];
   const int p = blockIdx.y;
+  const int q = p0 + p;
   const long wave_block0 = ((long)blockIdx.x * (256 / kWave) + threadIdx.x / kWave) * kWave;
   double acc = 0.0;
-  if (wave_block0 * 256 < n) rademacher_wave<T>(seed, p0 + p, n, wave_block0, V0 + (size_t)p * n, acc);
+  if (wave_block0 * 256 < n)
+    rademacher_wave<T>(seed, q / K, n, wave_block0, V0 + (size_t)p * n, acc, colour, q % K);
   const double s = block_sum<256>(acc, lds);
   if (threadIdx.x == 0) S.part_b[(size_t)p * S.pstride + blockIdx.x] = s;
 }
@@ -326,23 +332,34 @@ __global__ __launch_bounds__(kEwThreads) void k_combine(const T* __restrict__ V,
   }
 }
 
-// ---- Hutchinson aggregate (Section 6): Gamma_p = ||v_p||^2 e_1^T log(T_m) e_1 + shift,
-// out[0] = mean, out[1] = sd / sqrt(N) (NaN for N = 1), out[2 + p] = Gamma_p.
+// ---- Hutchinson aggregate (Section 6): Gamma_p = sum_{c < K} ||v_pc||^2 e_1^T log(T_m) e_1 + shift over
+// the K colour classes of probe p (columns p K .. p K + K - 1; K = 1 without a colouring, Section 6.1);
+// an empty class (||v_pc|| = 0) adds nothing.  out[0] = mean, out[1] = sd / sqrt(N) (NaN for N = 1),
+// out[2 + p] = Gamma_p.
+__device__ __forceinline__ double probe_gamma(const double* g, const double* beta, int ldb, int p, int K,
+                                              double shift) {
+  double gam = shift;
+  for (int c = 0; c < K; ++c) {
+    const int q = p * K + c;
+    const double b0 = beta[(size_t)q * ldb];
+    if (b0 != 0.0) gam += b0 * b0 * g[q];
+  }
+  return gam;
+}
+
 __global__ __launch_bounds__(256) void k_hutchinson(const double* __restrict__ g, const double* __restrict__ beta,
-                                                    int ldb, int np, double shift, double* __restrict__ out) {
+                                                    int ldb, int np, int K, double shift, double* __restrict__ out) {
   __shared__ double lds[256 / kWave];
   double s = 0.0;
   for (int p = threadIdx.x; p < np; p += 256) {
-    const double b0 = beta[(size_t)p * ldb];
-    const double gam = b0 * b0 * g[p] + shift;
+    const double gam = probe_gamma(g, beta, ldb, p, K, shift);
     out[2 + p] = gam;
     s += gam;
   }
   const double mean = block_sum<256>(s, lds) / np;
   double v = 0.0;
   for (int p = threadIdx.x; p < np; p += 256) {
-    const double b0 = beta[(size_t)p * ldb];
-    const double d = (b0 * b0 * g[p] + shift) - mean;
+    const double d = probe_gamma(g, beta, ldb, p, K, shift) - mean;
     v += d * d;
   }
   const double ss = block_sum<256>(v, lds);
@@ -352,9 +369,9 @@ __global__ __launch_bounds__(256) void k_hutchinson(const double* __restrict__ g
   }
 }
 
-void launch_hutchinson_aggregate(const double* g, const double* beta, int ldb, int np, double shift, double* out,
-                                 hipStream_t st) {
-  hipLaunchKernelGGL(k_hutchinson, dim3(1), dim3(256), 0, st, g, beta, ldb, np, shift, out);
+void launch_hutchinson_aggregate(const double* g, const double* beta, int ldb, int np, int K, double shift,
+                                 double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_hutchinson, dim3(1), dim3(256), 0, st, g, beta, ldb, np, K, shift, out);
 }
 
 // ---- host launchers ---------------------------------------------------------------------------
@@ -376,8 +393,10 @@ int rademacher_blocks(long n) {
   return (int)((waves + 3) / 4);
 }
 template <typename T>
-void launch_init_rademacher(uint64_t seed, long n, int p0, T* V0, const LzState& S, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_rademacher<T>, dim3(rademacher_blocks(n), S.k), dim3(256), 0, st, seed, n, p0, V0, S);
+void launch_init_rademacher(uint64_t seed, long n, int p0, T* V0, const LzState& S, hipStream_t st,
+                            const int32_t* colour, int K) {
+  hipLaunchKernelGGL(k_init_rademacher<T>, dim3(rademacher_blocks(n), S.k), dim3(256), 0, st, seed, n, p0, V0, S,
+                     colour, K);
 }
 void launch_rademacher_i8(uint64_t seed, long n, int nprobes, int8_t* out, hipStream_t st) {
   hipLaunchKernelGGL(k_rademacher_i8, dim3(rademacher_blocks(n), nprobes), dim3(256), 0, st, seed, n, out);
@@ -413,7 +432,7 @@ void launch_combine(const T* V, long L, const double* y, int ldy, OutT* out, lon
 #define INST(T)                                                                                  \
   template void launch_init_from_f64<T>(const double*, long, long, T*, const LzState&, hipStream_t); \
   template void launch_init_from_i8<T>(const int8_t*, long, T*, const LzState&, hipStream_t);      \
-  template void launch_init_rademacher<T>(uint64_t, long, int, T*, const LzState&, hipStream_t);        \
+  template void launch_init_rademacher<T>(uint64_t, long, int, T*, const LzState&, hipStream_t, const int32_t*, int);        \
   template void launch_update<T>(const T*, const T*, T*, long, int, int, const LzState&, hipStream_t); \
   template void launch_norm_partials<T>(const T*, long, const LzState&, hipStream_t);              \
   template void launch_reorth<T>(T*, long, int, double*, double*, int, const LzState&, hipStream_t); \
