@@ -52,9 +52,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
-    ap.add_argument("--only", default="", help="profiling: run only this leg (headline|counters|lgcp)")
+    ap.add_argument("--only", default="", help="profiling: run only this leg (headline|counters|lgcp|logdet)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-lgcp", action="store_true", help="skip the log-Gaussian Cox process leg")
+    ap.add_argument("--no-logdet", action="store_true", help="skip the log-determinant leg")
     ap.add_argument("--kernel", default="", help="counters leg: kernel to run (default: the dominant one)")
     ap.add_argument("--storage", default="f64", help="counters leg: storage dtype (f64|f32)")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="arrival window per serving rate")
@@ -105,6 +106,9 @@ def main():
 
     if args.only == "lgcp":
         print(json.dumps({"lgcp": lgcp_leg(gm, torch, stream)}))
+        return
+    if args.only == "logdet":
+        print(json.dumps({"logdet": logdet_leg(gm, torch)}))
         return
 
     # ---- headline: FP64 storage, stop at rho <= 1e-5 ---------------------------------------------
@@ -199,6 +203,10 @@ def main():
     if not args.no_lgcp:
         result["lgcp"] = lgcp_leg(gm, torch, stream)
 
+    # ---- Hutchinson log det (workload C3), plain and coloured ------------------------------------------
+    if not args.no_logdet:
+        result["logdet"] = logdet_leg(gm, torch)
+
     # ---- serving: Poisson request stream over a pool of 64 resident operators ---------------------------
     if not args.no_serve:
         result["serving"] = serving_leg(gm, torch, args.serve_seconds)
@@ -283,6 +291,38 @@ def lgcp_leg(gm, torch, stream):
         kern[name] = {"avg_us": round(r["avg_us"], 2), "bytes_per_launch": r["bytes"],
                       "achieved_gbs": round(r["achieved_gbs"], 1), "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4)}
     out["kernels_512x512_32rhs"] = kern
+    op.close()
+    return out
+
+
+LOGDET_COLUMNS = 64             # Lanczos columns per estimate (probes x colour classes), all variants
+
+
+def logdet_leg(gm, torch):
+    """Section 6 on workload C3 (1024^2, 13-point, kappa2 = 0.05, m = 80, FP32 storage): the plain
+    Hutchinson estimate with 64 probes, and the coloured estimate of Section 6.1 for distance-p
+    colourings (p = 1, 2) at the same number of Lanczos columns (probes = 64 / classes).  The
+    variance per column (SE^2 x columns) compares the estimators at equal cost."""
+    sp = workloads.C3_LATTICE
+    seed = workloads.c3_probe_seed()
+    op = gm.Operator.lattice(sp.shape, sp.order, sp.kappa2, sp.tau, sp.boundary, "f32")
+    out = {"workload": "1024x1024 13-point lattice, kappa2 = 0.05, free boundary, m = 80, FP32 storage",
+           "columns": LOGDET_COLUMNS, "m": workloads.C3_M, "variants": {}}
+    for p in (0, 1, 2):
+        col = op.distance_colouring(p)
+        K = int(col.max()) + 1
+        npb = max(2, LOGDET_COLUMNS // K)
+        run = (lambda: op.logdet(npb, workloads.C3_M, seed=seed)) if p == 0 else \
+              (lambda: op.logdet_coloured(npb, workloads.C3_M, col, seed=seed))
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mean, se, per = run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["variants"][f"p{p}"] = {"classes": K, "probes": npb, "columns": npb * K, "estimate": mean,
+                                    "std_err": se, "var_per_column": se * se * npb * K,
+                                    "ms": round(1000 * dt, 2), "columns_per_s": round(npb * K / dt, 1)}
     op.close()
     return out
 
