@@ -139,6 +139,17 @@ gmrf_status gmrf_sample_ex(const gmrf_op* Q, const double* Z, int64_t k, double 
                            int32_t m_max, int reorth, double* X, gmrf_info* info,
                            double* alpha, double* beta, void* stream);
 
+/* As gmrf_sample without reorthogonalisation, in O(n k) device memory instead of O(n k m_max):
+ * the sampler keeps three Krylov vectors (the O(n) storage Section 1 claims for the method).
+ * Pass 1 runs the recurrence with the stopping rule and keeps only alpha_j, beta_j; after
+ * y = T_m^{-1/2} e_1 pass 2 runs the same recurrence from z again and adds beta_0 y_t v_{t+1}
+ * into X as each vector appears (x_m = ||z|| V_m y, Algorithm 1).  Every reduction has a fixed
+ * order, so pass 2 reproduces pass 1's vectors bit for bit.  Twice the recurrence's traffic; no
+ * reorthogonalisation (it needs the basis).  Arguments, info and return as for gmrf_sample
+ * (err_bound NaN).                                                                             */
+gmrf_status gmrf_sample_two_pass(const gmrf_op* Q, const double* Z, int64_t k, double tol,
+                                 int32_t m_max, double* X, gmrf_info* info, void* stream);
+
 /* Uneven batch: Algorithm 1 for many independent lattice fields in one set of launches per
  * Lanczos step (every kernel of the iteration covers all fields' columns).  Field f is
  * ops[f] with k[f] right-hand sides; all fields share ndim, order and storage (shape, kappa2,

@@ -163,6 +163,22 @@ class Operator:
             return X, infos, alpha, beta
         return X, infos
 
+    def sample_two_pass(self, Z, tol=1e-8, m_max=200, out=None, stream=None):
+        """As sample(), in O(n) device memory: the recurrence runs twice and no Krylov basis is kept
+        (no reorthogonalisation).  Returns (X, info)."""
+        torch = _torch()
+        self._check_block(Z, torch.float64, "Z")
+        k = Z.shape[0]
+        X = out if out is not None else torch.empty_like(Z)
+        info = (Info * k)()
+        st = lib().gmrf_sample_two_pass(self._h, _dptr(Z), k, float(tol), int(m_max), _dptr(X), info,
+                                        _stream_ptr(stream))
+        if st not in (_abi.GMRF_OK, _abi.GMRF_ENOTSPD, _abi.GMRF_EINVAL) or (
+                st == _abi.GMRF_EINVAL and not any(i.status == _abi.GMRF_EINVAL for i in info)):
+            raise GmrfError(st, "gmrf_sample_two_pass")
+        return X, [dict(m_used=i.m_used, status=STATUS[i.status], rel_residual=i.rel_residual,
+                        err_bound=i.err_bound) for i in info]
+
     def logdet(self, n_probes, m, seed=0, probes=None, stream=None):
         """Hutchinson estimate (mean, standard error, per-probe values as numpy)."""
         torch = _torch()

@@ -554,6 +554,9 @@ struct Run {
 };
 
 template <typename T>
+gmrf_status setup_state(Run<T>& R, Workspace& ws);
+
+template <typename T>
 gmrf_status setup(Run<T>& R, Workspace& ws) {
   const gmrf_op* Q = R.Q;
   R.z = sizes_for(Q, R.k, R.m_max, R.reorth, R.ring3);
@@ -570,6 +573,16 @@ gmrf_status setup(Run<T>& R, Workspace& ws) {
     R.band = band;
   }
   R.fused = fused_path(Q, R.reorth);
+  return setup_state<T>(R, ws);
+}
+
+// The scalar state of a run (coefficients, pivots, partial sums, flags), zeroed and active: a second
+// pass over the same vector buffers takes a fresh one.
+template <typename T>
+gmrf_status setup_state(Run<T>& R, Workspace& ws) {
+  const gmrf_op* Q = R.Q;
+  const int k = R.k, m = R.m_max;
+  gmrf_status s;
   double* dbuf;
   const int nsets = R.fused ? 6 : 3;
   const size_t nd = (size_t)k * (m + 1) * 3 + (size_t)k * (m + 2) + nsets * (size_t)k * R.z.pstride;
@@ -778,6 +791,20 @@ struct ForkJoin {
 
 }  // namespace
 
+// slot 0 <- z (preconditioned: z in the unitary spectral basis, with what the first step needs)
+template <typename T>
+static void init_from_z(Run<T>& R, const double* Zg) {
+  const gmrf_op* Q = R.Q;
+  if (Q->precond) {
+    fft_forward_init<T>(Q->plan, Zg, R.slot(0), R.F1, R.S, R.k, R.st);
+    if (lgcp_path(Q)) lgcp_col_init<T>(Q->plan, precond_mult(Q), R.slot(0), R.F1, R.k, R.st);
+    else precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, R.k, R.st);
+  } else {
+    launch_init_from_f64<T>(Zg, Q->n, R.z.L, R.slot(0), R.S, R.st);
+    fused_init<T>(R);
+  }
+}
+
 template <typename T>
 static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, double tol, int m_max, int reorth,
                                double* X, gmrf_info* info, double* alpha_out, double* beta_out,
@@ -801,16 +828,7 @@ static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, dou
     R.tol = tol;
     R.st = fj.gs[g];
     if ((s = setup<T>(R, *ws[g])) != GMRF_OK) return s;
-    // slot 0 <- z (preconditioned: z in the unitary spectral basis, with its dot products)
-    const double* Zg = Z + (size_t)c0[g] * Q->n;
-    if (Q->precond) {
-      fft_forward_init<T>(Q->plan, Zg, R.slot(0), R.F1, R.S, R.k, R.st);
-      if (lgcp_path(Q)) lgcp_col_init<T>(Q->plan, precond_mult(Q), R.slot(0), R.F1, R.k, R.st);
-      else precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, R.k, R.st);
-    } else {
-      launch_init_from_f64<T>(Zg, Q->n, R.z.L, R.slot(0), R.S, R.st);
-      fused_init<T>(R);
-    }
+    init_from_z<T>(R, Z + (size_t)c0[g] * Q->n);
   }
   if ((s = run_loop<T>(Rs)) != GMRF_OK) return s;
   // y = T_m^{-1/2} e_1, then x_m = ||z|| V_m y
@@ -874,6 +892,111 @@ static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, dou
   if (ret == GMRF_ENOTSPD) fail(ret, "at least one column is not positive definite (see info)");
   if (ret == GMRF_EINVAL) fail(ret, "at least one column of Z is not finite (see info)");
   return ret;
+}
+
+// Two passes over the recurrence, three Krylov slots (Section 1's O(n) storage): pass 1 runs the
+// stopping rule and keeps only the coefficients; y = T_m^{-1/2} e_1; pass 2 runs the same launches from z
+// again (bitwise the same vectors: every reduction has a fixed order) and adds beta_0 y_t v_{t+1} into
+// the output as each vector appears.
+template <typename T>
+static gmrf_status sample_two_pass_impl(const gmrf_op* Q, const double* Z, int64_t k, double tol, int m_max,
+                                        double* X, gmrf_info* info, hipStream_t st) {
+  const int G = groups_for(Q, k);
+  ForkJoin fj;
+  gmrf_status s = fj.fork(st, G);
+  if (s != GMRF_OK) return s;
+  std::vector<int64_t> c0(G + 1);
+  for (int g = 0; g <= G; ++g) c0[g] = k * g / G;
+  std::vector<std::unique_ptr<Workspace>> ws;
+  std::vector<Run<T>> Rs(G), R2s(G);
+  std::vector<double*> ys(G);
+  std::vector<T*> U(G, nullptr);
+  for (int g = 0; g < G; ++g) {
+    ws.emplace_back(new Workspace(fj.gs[g]));
+    Run<T>& R = Rs[g];
+    R.Q = Q;
+    R.k = (int)(c0[g + 1] - c0[g]);
+    R.m_max = m_max;
+    R.reorth = 0;
+    R.tol = tol;
+    R.st = fj.gs[g];
+    R.ring3 = true;
+    if ((s = setup<T>(R, *ws[g])) != GMRF_OK) return s;
+    init_from_z<T>(R, Z + (size_t)c0[g] * Q->n);
+  }
+  if ((s = run_loop<T>(Rs)) != GMRF_OK) return s;
+  for (int g = 0; g < G; ++g) {
+    Run<T>& R = Rs[g];
+    double* scr;
+    if ((s = ws[g]->alloc((size_t)R.k * m_max, &ys[g])) != GMRF_OK) return s;
+    if ((s = ws[g]->alloc(tri_scratch_doubles(R.k, m_max), &scr)) != GMRF_OK) return s;
+    launch_tri_invsqrt(R.S.alpha, m_max + 1, 1, R.S.beta, m_max + 2, 1, R.S.m_used, 0, R.S.status, ys[g], m_max,
+                       R.S.status, scr, m_max, R.k, R.st);
+  }
+  std::vector<int> mu(k), stt(k);
+  std::vector<double> rho((size_t)k * (m_max + 1));
+  for (int g = 0; g < G; ++g) {
+    Run<T>& R = Rs[g];
+    const size_t o = (size_t)c0[g];
+    HIP_TRY(hipMemcpyAsync(mu.data() + o, R.S.m_used, R.k * sizeof(int), hipMemcpyDeviceToHost, R.st));
+    HIP_TRY(hipMemcpyAsync(stt.data() + o, R.S.status, R.k * sizeof(int), hipMemcpyDeviceToHost, R.st));
+    HIP_TRY(hipMemcpyAsync(rho.data() + o * (m_max + 1), R.S.rho, (size_t)R.k * (m_max + 1) * 8,
+                           hipMemcpyDeviceToHost, R.st));
+  }
+  for (int g = 0; g < G; ++g) HIP_TRY(hipStreamSynchronize(Rs[g].st));
+  // pass 2: the same vector buffers, fresh scalars
+  for (int g = 0; g < G; ++g) {
+    Run<T>& R1 = Rs[g];
+    Run<T>& R = R2s[g];
+    R = R1;
+    if ((s = setup_state<T>(R, *ws[g])) != GMRF_OK) return s;
+    if (Q->precond && (s = ws[g]->alloc((size_t)R.k * R.z.L, &U[g])) != GMRF_OK) return s;
+    int mg = 0;
+    for (int r = 0; r < R.k; ++r) mg = std::max(mg, mu[(size_t)c0[g] + r]);
+    double* Xg = X + (size_t)c0[g] * Q->n;
+    init_from_z<T>(R, Z + (size_t)c0[g] * Q->n);
+    auto acc = [&](int t) {
+      if (Q->precond) launch_accumulate<T, T>(R.slot(t), R.z.L, ys[g], m_max, R1.S, t, U[g], R.z.L, R.st);
+      else launch_accumulate<T, double>(R.slot(t), R.z.L, ys[g], m_max, R1.S, t, Xg, Q->n, R.st);
+    };
+    acc(0);
+    for (int j = 1; j < mg; ++j) {
+      iterate<T>(R, j);
+      acc(j);
+    }
+    if (Q->precond) fft_backward_output<T>(Q->plan, precond_mult(Q), U[g], Xg, R.F1, R1.S, R.k, R.st);
+  }
+  HIP_TRY(hipGetLastError());
+  if ((s = fj.join()) != GMRF_OK) return s;
+  for (int g = 0; g < G; ++g) HIP_TRY(hipStreamSynchronize(R2s[g].st));
+  gmrf_status ret = GMRF_OK;
+  for (int r = 0; r < k; ++r) {
+    const int m = mu[r];
+    if (info) {
+      info[r].m_used = m;
+      info[r].status = stt[r];
+      info[r].rel_residual = m > 0 ? rho[(size_t)r * (m_max + 1) + m] : 0.0;
+      info[r].err_bound = NAN;
+    }
+    if (stt[r] == kENOTSPD) ret = GMRF_ENOTSPD;
+    if (stt[r] == kEINVAL && ret == GMRF_OK) ret = GMRF_EINVAL;
+  }
+  if (ret == GMRF_ENOTSPD) fail(ret, "at least one column is not positive definite (see info)");
+  if (ret == GMRF_EINVAL) fail(ret, "at least one column of Z is not finite (see info)");
+  return ret;
+}
+
+extern "C" gmrf_status gmrf_sample_two_pass(const gmrf_op* Q, const double* Z, int64_t k, double tol, int32_t m_max,
+                                            double* X, gmrf_info* info, void* stream) {
+  if (!Q || !Z || !X) return fail(GMRF_EINVAL, "NULL argument");
+  if (k < 1 || k > 65535) return fail(GMRF_EINVAL, "k must be in 1..65535");
+  if (m_max < 1 || m_max > tri_max_m()) return fail(GMRF_EINVAL, "m_max must be in 1..%d", tri_max_m());
+  if (!std::isfinite(tol)) return fail(GMRF_EINVAL, "tol must be finite");
+  if (Q->has_diag && !Q->precond)
+    return fail(GMRF_EUNSUPPORTED, "Q + diag(d) is sampled with circulant preconditioning only (else pass it as CSR)");
+  hipStream_t st = (hipStream_t)stream;
+  if (Q->storage == GMRF_F64) return sample_two_pass_impl<double>(Q, Z, k, tol, m_max, X, info, st);
+  return sample_two_pass_impl<float>(Q, Z, k, tol, m_max, X, info, st);
 }
 
 extern "C" gmrf_status gmrf_sample_ex(const gmrf_op* Q, const double* Z, int64_t k, double tol, int32_t m_max,

@@ -332,6 +332,32 @@ __global__ __launch_bounds__(kEwThreads) void k_combine(const T* __restrict__ V,
   }
 }
 
+// The combine one basis vector at a time (the second pass of the two-pass sampler): with slot t holding
+// w_t = beta_t v_{t+1}, out[r] = beta_0 y_0 v_1 for t = 0 and out[r] += beta_0 y_t v_{t+1} for 0 < t < m_used.
+// NaN for a column whose status is ENOTSPD or EINVAL, zero for m_used = 0.
+template <typename T, typename OutT>
+__global__ __launch_bounds__(kEwThreads) void k_accumulate(const T* __restrict__ Vt, long L,
+                                                           const double* __restrict__ y, int ldy, LzState S, int t,
+                                                           OutT* __restrict__ out, long old) {
+  const int r = blockIdx.y;
+  const int m = S.m_used[r];
+  const int st = S.status[r];
+  const bool bad = (st == kENOTSPD || st == kEINVAL);
+  if (t > 0 && (bad || t >= m)) return;
+  const double c = (bad || t >= m) ? 0.0 : S.beta[lz_ib(S, r, 0)] * y[(size_t)r * ldy + t] / S.beta[lz_ib(S, r, t)];
+  const double nanv = __longlong_as_double(0x7ff8000000000000ll);
+  const T* v = Vt + (size_t)r * L;
+  OutT* o = out + (size_t)r * old;
+  const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
+  EW_LOOP(q) {
+    const long e = base + (long)q * kEwThreads;
+    if (e < L) {
+      const double cv = c * (double)v[e];
+      o[e] = t == 0 ? (OutT)(bad ? nanv : cv) : (OutT)((double)o[e] + cv);
+    }
+  }
+}
+
 // ---- Hutchinson aggregate (Section 6): Gamma_p = sum_{c < K} ||v_pc||^2 e_1^T log(T_m) e_1 + shift over
 // the K colour classes of probe p (columns p K .. p K + K - 1; K = 1 without a colouring, Section 6.1);
 // an empty class (||v_pc|| = 0) adds nothing.  out[0] = mean, out[1] = sd / sqrt(N) (NaN for N = 1),
@@ -424,6 +450,12 @@ void launch_reorth(T* V, long L, int j, double* part_h, double* h, int hstride, 
   }
 }
 template <typename T, typename OutT>
+void launch_accumulate(const T* Vt, long L, const double* y, int ldy, const LzState& S, int t, OutT* out, long old,
+                       hipStream_t st) {
+  hipLaunchKernelGGL((k_accumulate<T, OutT>), ew_grid(L, S.k), dim3(kEwThreads), 0, st, Vt, L, y, ldy, S, t, out, old);
+}
+
+template <typename T, typename OutT>
 void launch_combine(const T* V, long L, const double* y, int ldy, OutT* out, long old, const LzState& S,
                     hipStream_t st) {
   hipLaunchKernelGGL((k_combine<T, OutT>), ew_grid(L, S.k), dim3(kEwThreads), 0, st, V, L, y, ldy, out, old, S);
@@ -437,10 +469,14 @@ void launch_combine(const T* V, long L, const double* y, int ldy, OutT* out, lon
   template void launch_norm_partials<T>(const T*, long, const LzState&, hipStream_t);              \
   template void launch_reorth<T>(T*, long, int, double*, double*, int, const LzState&, hipStream_t); \
   template void launch_combine<T, double>(const T*, long, const double*, int, double*, long,       \
-                                          const LzState&, hipStream_t);
+                                          const LzState&, hipStream_t);                           \
+  template void launch_accumulate<T, double>(const T*, long, const double*, int, const LzState&, int, double*, \
+                                             long, hipStream_t);
 INST(double)
 INST(float)
 #undef INST
+template void launch_accumulate<float, float>(const float*, long, const double*, int, const LzState&, int, float*,
+                                              long, hipStream_t);
 template void launch_combine<float, float>(const float*, long, const double*, int, float*, long,
                                            const LzState&, hipStream_t);
 
