@@ -170,6 +170,18 @@ def main():
     dtp = (time.perf_counter() - t0) / nplain
     result["plain_single_sample_fp64"] = {"samples_per_s": round(1.0 / dtp, 2), "ms_per_sample": round(1000 * dtp, 3),
                                           "batched_speedup": round((k / dt) * dtp, 2)}
+    # two-pass sampler (no stored basis: three Krylov slots instead of m_max + 1) on the same batch and rule
+    op64.sample_two_pass(Z, tol=TOL_HEADLINE, m_max=M_MAX_HEADLINE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X2p, i2p = op64.sample_two_pass(Z, tol=TOL_HEADLINE, m_max=M_MAX_HEADLINE)
+    torch.cuda.synchronize()
+    dt2 = time.perf_counter() - t0
+    vec = k * sp.n * 8
+    result["two_pass_fp64"] = {"samples_per_s": round(k / dt2, 2), "ms_per_step": round(1000 * dt2, 3),
+                               "m_used_max": max(i["m_used"] for i in i2p),
+                               "basis_bytes_one_pass": (M_MAX_HEADLINE + 1) * vec, "basis_bytes_two_pass": 3 * vec,
+                               "max_abs_diff_vs_one_pass": float((X2p - X).abs().max())}
     # FP32 storage with the headline stopping rule (reaches its accuracy floor)
     step(op32, TOL_HEADLINE, M_MAX_HEADLINE)
     torch.cuda.synchronize()
