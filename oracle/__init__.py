@@ -18,6 +18,7 @@ Modules
   lanczos      -- Algorithm 1 (Section 4) with the Theorem 1 stopping quantity
   precond      -- Proposition 1 with the block-circulant preconditioner (Section 5)
   lgcp         -- the log-Gaussian Cox process proposal Q + H with M = Q (Sections 3, 5.1)
+  ichol        -- incomplete-Cholesky preconditioning of a general sparse Q (Section 5.2)
   logdet       -- Hutchinson estimator with Lanczos (Gauss) quadrature (Section 6)
   philox       -- Philox4x64-10 counter-based generator for Rademacher probes
 
