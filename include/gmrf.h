@@ -102,6 +102,24 @@ gmrf_status gmrf_op_set_circulant_precond(gmrf_op* Q, int enable);
  * preconditioning on a free-boundary lattice.                                                 */
 gmrf_status gmrf_op_set_diagonal(gmrf_op* Q, const double* d);
 
+/* Proposition 1 with M = L L^T from an incomplete Cholesky factorisation of a CSR operator and
+ * F = L (Section 5.2, Figure 3): sampling runs Algorithm 1 on A = L^{-1} Q L^{-T} and returns
+ * x = L^{-T} u_m; log det adds 2 sum log l_ii.  The factorisation runs on the host when the
+ * preconditioner is set (left looking on C = Q + shift diag(Q)):
+ *   droptol >= 0: an off-diagonal entry is dropped when its numerator c_ij - sum_k l_ik l_jk is
+ *                 below droptol * ||Q[:, j]||_2 in magnitude (droptol = 0: complete Cholesky);
+ *   droptol <  0: zero fill, IC(0) (entries only where Q_ij != 0).
+ * A non-positive pivot restarts with the next shift of 0, 1e-3, 2e-3, 4e-3, ...; *shift_used (may
+ * be NULL) receives the shift.  Each step then costs two level-scheduled triangular solves (one
+ * block per column, a barrier between levels; the number of levels bounds the speed).
+ * enable = 0 removes the preconditioner.  EUNSUPPORTED: not a CSR operator.  ENOTSPD: breakdown
+ * at every shift.  EINVAL: NaN droptol.                                                         */
+gmrf_status gmrf_op_set_ichol_precond(gmrf_op* Q, int enable, double droptol, double* shift_used);
+
+/* Size of the incomplete-Cholesky factor of a handle: nonzeros of L (with the diagonal), number
+ * of levels of the forward solve, the diagonal shift used.  EINVAL without the preconditioner.  */
+gmrf_status gmrf_ichol_info(const gmrf_op* Q, int64_t* nnz_L, int32_t* levels, double* shift);
+
 /* Device bytes one gmrf_sample call needs for k right-hand sides and m_max steps (Krylov
  * basis, work vectors, partial sums, FFT scratch), plus what the handle keeps resident.    */
 gmrf_status gmrf_op_bytes(const gmrf_op* Q, int64_t k, int32_t m_max, int reorth, size_t* bytes);

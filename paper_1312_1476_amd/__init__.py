@@ -90,6 +90,20 @@ class Operator:
         check(lib().gmrf_op_set_diagonal(self._h, arr.ctypes.data_as(C.c_void_p)), "gmrf_op_set_diagonal")
         return self
 
+    def set_ichol_precond(self, droptol=-1.0, enable=True):
+        """Incomplete-Cholesky preconditioning of a CSR operator (droptol < 0: IC(0)); returns the
+        diagonal shift the factorisation needed."""
+        sh = C.c_double()
+        check(lib().gmrf_op_set_ichol_precond(self._h, 1 if enable else 0, float(droptol), C.byref(sh)),
+              "gmrf_op_set_ichol_precond")
+        return sh.value
+
+    def ichol_info(self):
+        """(nonzeros of L, forward-solve levels, diagonal shift) of the incomplete-Cholesky factor."""
+        nnz, lev, sh = C.c_int64(), C.c_int32(), C.c_double()
+        check(lib().gmrf_ichol_info(self._h, C.byref(nnz), C.byref(lev), C.byref(sh)), "gmrf_ichol_info")
+        return nnz.value, lev.value, sh.value
+
     def set_circulant_precond(self, enable=True):
         check(lib().gmrf_op_set_circulant_precond(self._h, 1 if enable else 0), "gmrf_op_set_circulant_precond")
         return self

@@ -29,6 +29,8 @@ SIGNATURES = {
                                      C.POINTER(C.c_void_p)]),
     "gmrf_op_set_circulant_precond": (C.c_int, [C.c_void_p, C.c_int]),
     "gmrf_op_set_diagonal": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "gmrf_op_set_ichol_precond": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.POINTER(C.c_double)]),
+    "gmrf_ichol_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "gmrf_op_bytes": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int, C.POINTER(C.c_size_t)]),
     "gmrf_op_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "gmrf_op_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),

@@ -23,6 +23,7 @@
 
 #include "../../include/gmrf.h"
 #include "fft.hpp"
+#include "ichol.hpp"
 #include "kernels.hpp"
 
 using namespace gmrf;
@@ -156,6 +157,13 @@ struct gmrf_op {
   // CSR (device; the pattern is also kept on the host for the distance colouring)
   std::vector<int64_t> h_rp;
   std::vector<int32_t> h_ci;
+  std::vector<double> h_va;
+  // incomplete-Cholesky preconditioner (CSR handles)
+  int ic = 0;
+  IcholDev icd{};
+  double ic_logdet = 0.0;     // log det (L L^T)
+  double ic_shift = 0.0;
+  int64_t ic_nnz = 0;
   int64_t* rp = nullptr;
   int32_t* ci = nullptr;
   void* va = nullptr;
@@ -282,6 +290,7 @@ gmrf_status gmrf_op_create_csr(int64_t n, const int64_t* row_ptr, const int32_t*
   op->resident_bytes = (n + 1) * 8 + nnz * (4 + vb);
   op->h_rp.assign(row_ptr, row_ptr + n + 1);
   op->h_ci.assign(col_idx, col_idx + nnz);
+  op->h_va.assign(values, values + nnz);
   *out = op.release();
   return GMRF_OK;
 }
@@ -295,6 +304,10 @@ void gmrf_op_destroy(gmrf_op* Q) {
   if (Q->mult32) (void)hipFree(Q->mult32);
   if (Q->diag64) (void)hipFree(Q->diag64);
   if (Q->diag32) (void)hipFree(Q->diag32);
+  for (void* p : {(void*)Q->icd.lrp, (void*)Q->icd.lci, Q->icd.lva, (void*)Q->icd.urp, (void*)Q->icd.uci, Q->icd.uva,
+                  Q->icd.dinv, (void*)Q->icd.flev_ptr, (void*)Q->icd.flev_rows, (void*)Q->icd.blev_ptr,
+                  (void*)Q->icd.blev_rows})
+    if (p) (void)hipFree(p);
   fft_plan_destroy(Q->plan);
   delete Q;
 }
@@ -392,6 +405,65 @@ extern "C" gmrf_status gmrf_op_set_diagonal(gmrf_op* Q, const double* d) {
   return GMRF_OK;
 }
 
+// ---- incomplete-Cholesky preconditioner (Section 5.2) -----------------------------------------------
+namespace {
+template <typename V>
+gmrf_status upload(const std::vector<V>& h, V** d) {
+  HIP_TRY(hipMalloc(d, std::max<size_t>(h.size(), 1) * sizeof(V)));
+  if (!h.empty()) HIP_TRY(hipMemcpy(*d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice));
+  return GMRF_OK;
+}
+gmrf_status upload_vals(const std::vector<double>& h, int storage, void** d) {
+  if (storage == GMRF_F64) return upload(h, (double**)d);
+  std::vector<float> f(h.begin(), h.end());
+  return upload(f, (float**)d);
+}
+}  // namespace
+
+extern "C" gmrf_status gmrf_op_set_ichol_precond(gmrf_op* Q, int enable, double droptol, double* shift_used) {
+  if (!Q) return fail(GMRF_EINVAL, "NULL operator");
+  if (!enable) {
+    Q->ic = 0;
+    return GMRF_OK;
+  }
+  if (Q->kind != 1) return fail(GMRF_EUNSUPPORTED, "incomplete-Cholesky preconditioning needs a CSR operator");
+  if (std::isnan(droptol)) return fail(GMRF_EINVAL, "droptol is NaN");
+  IcholHost h;
+  if (!ichol_factor(Q->n, Q->h_rp.data(), Q->h_ci.data(), Q->h_va.data(), droptol, h))
+    return fail(GMRF_ENOTSPD, "incomplete Cholesky broke down for every diagonal shift up to 2^30 * 1e-3");
+  IcholDev& d = Q->icd;
+  for (void* p : {(void*)d.lrp, (void*)d.lci, d.lva, (void*)d.urp, (void*)d.uci, d.uva, d.dinv, (void*)d.flev_ptr,
+                  (void*)d.flev_rows, (void*)d.blev_ptr, (void*)d.blev_rows})
+    if (p) (void)hipFree(p);
+  d = IcholDev{};
+  std::vector<double> dinv(h.diag.size());
+  for (size_t i = 0; i < dinv.size(); ++i) dinv[i] = 1.0 / h.diag[i];
+  gmrf_status s;
+  if ((s = upload(h.lrp, &d.lrp)) != GMRF_OK || (s = upload(h.lci, &d.lci)) != GMRF_OK ||
+      (s = upload_vals(h.lva, Q->storage, &d.lva)) != GMRF_OK || (s = upload(h.urp, &d.urp)) != GMRF_OK ||
+      (s = upload(h.uci, &d.uci)) != GMRF_OK || (s = upload_vals(h.uva, Q->storage, &d.uva)) != GMRF_OK ||
+      (s = upload_vals(dinv, Q->storage, &d.dinv)) != GMRF_OK || (s = upload(h.flev_ptr, &d.flev_ptr)) != GMRF_OK ||
+      (s = upload(h.flev_rows, &d.flev_rows)) != GMRF_OK || (s = upload(h.blev_ptr, &d.blev_ptr)) != GMRF_OK ||
+      (s = upload(h.blev_rows, &d.blev_rows)) != GMRF_OK)
+    return s;
+  d.nflev = (int)h.flev_ptr.size() - 1;
+  d.nblev = (int)h.blev_ptr.size() - 1;
+  Q->ic_logdet = h.logdet_M;
+  Q->ic_shift = h.shift;
+  Q->ic_nnz = (int64_t)h.lva.size() + Q->n;
+  Q->ic = 1;
+  if (shift_used) *shift_used = h.shift;
+  return GMRF_OK;
+}
+
+extern "C" gmrf_status gmrf_ichol_info(const gmrf_op* Q, int64_t* nnz_L, int32_t* levels, double* shift) {
+  if (!Q || !Q->ic) return fail(GMRF_EINVAL, "no incomplete-Cholesky preconditioner on this operator");
+  if (nnz_L) *nnz_L = Q->ic_nnz;
+  if (levels) *levels = Q->icd.nflev;
+  if (shift) *shift = Q->ic_shift;
+  return GMRF_OK;
+}
+
 // ---- sizes ------------------------------------------------------------------------------------------
 namespace {
 // Q + diag(d) preconditioned by its periodic lattice part: two FFT passes per step (lgcp_step.hip).
@@ -431,6 +503,9 @@ Sizes sizes_for(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3) 
   } else if (fused_path(Q, reorth)) {
     z.Pa = lanczos2d_blocks(Q->geom);             // the one-pass kernel's partial sums
     z.Pb = z.Pa;
+  } else if (Q->ic) {
+    z.Pa = ew_blocks(z.L);                        // the opener's v_j^T q partials (elementwise tiling)
+    z.Pb = ew_blocks(z.L);
   } else {
     z.Pa = Q->kind == 0 ? stencil_blocks(Q->geom) : csr_blocks((long)Q->n);
     z.Pb = ew_blocks(z.L);
@@ -446,7 +521,7 @@ size_t call_bytes(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3
   Sizes z = sizes_for(Q, k, m_max, reorth, ring3);
   size_t b = (size_t)z.slots * k * z.vec_bytes;       // Krylov basis
   b += (size_t)k * z.vec_bytes;                       // q
-  if (Q->precond) b += (size_t)k * z.vec_bytes;                                        // FFT scratch
+  if (Q->precond || Q->ic) b += (size_t)k * z.vec_bytes;                               // FFT / solve scratch
   if (Q->precond && !lgcp_path(Q)) b += precond_step_bytes(Q->plan, Q->storage, (int)k);   // band tables
   b += (size_t)k * (m_max + 2) * 8 * 4 + (size_t)k * 16;  // scalars
   b += (fused_path(Q, reorth) ? 6 : 3) * (size_t)k * z.pstride * 8;   // partials (two sets when fused)
@@ -564,7 +639,7 @@ gmrf_status setup(Run<T>& R, Workspace& ws) {
   gmrf_status s;
   if ((s = ws.alloc((size_t)R.z.slots * k * R.z.L, &R.V)) != GMRF_OK) return s;
   if ((s = ws.alloc((size_t)k * R.z.L, &R.Qb)) != GMRF_OK) return s;
-  if (Q->precond) {
+  if (Q->precond || Q->ic) {
     if ((s = ws.alloc((size_t)k * R.z.L, &R.F1)) != GMRF_OK) return s;
   }
   if (Q->precond && !lgcp_path(Q)) {
@@ -669,6 +744,13 @@ void iterate(Run<T>& R, int j) {
   } else if (Q->precond) {
     precond_lanczos_step<T>(Q->plan, Q->geom, Q->order, precond_mult(Q), xj, xp, R.slot(j), R.band, R.S, j,
                             R.reorth ? 0 : 1, R.reorth ? 0 : 1, R.k, R.st);
+  } else if (Q->ic) {
+    // A slot_{j-1} = L^{-1} Q L^{-T} slot_{j-1} (F1 <- L^{-T} slot, Qb <- Q F1, F1 <- L^{-1} Qb), then the opener
+    launch_trsv<T, T>(Q->icd, true, xj, R.z.L, R.F1, R.z.L, R.S.active, R.k, R.st);
+    launch_csr<T>((long)Q->n, Q->rp, Q->ci, (const T*)Q->va, false, R.F1, Q->n, R.Qb, Q->n, nullptr, R.S, 0, R.k, R.st);
+    launch_trsv<T, T>(Q->icd, false, R.Qb, R.z.L, R.F1, R.z.L, R.S.active, R.k, R.st);
+    launch_pre_lz<T>(R.F1, xj, xp, R.Qb, R.z.L, R.S, j, R.st);
+    launch_update<T>(R.Qb, xj, R.slot(j), R.z.L, j, R.reorth ? 0 : 1, R.S, R.st);
   } else {
     op_apply_lz<T>(Q, xj, R.Qb, xp, R.S, j, R.k, R.st);
     launch_update<T>(R.Qb, xj, R.slot(j), R.z.L, j, R.reorth ? 0 : 1, R.S, R.st);
@@ -843,6 +925,10 @@ static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, dou
     if (Q->precond) {
       launch_combine<T, T>(R.V, R.z.L, ys[g], m_max, R.Qb, R.z.L, R.S, R.st);
       fft_backward_output<T>(Q->plan, precond_mult(Q), R.Qb, Xg, R.F1, R.S, R.k, R.st);
+    } else if (Q->ic) {
+      // x = L^{-T} u_m
+      launch_combine<T, T>(R.V, R.z.L, ys[g], m_max, R.Qb, R.z.L, R.S, R.st);
+      launch_trsv<T, double>(Q->icd, true, R.Qb, R.z.L, Xg, Q->n, nullptr, R.k, R.st);
     } else {
       launch_combine<T, double>(R.V, R.z.L, ys[g], m_max, Xg, Q->n, R.S, R.st);
     }
@@ -950,13 +1036,14 @@ static gmrf_status sample_two_pass_impl(const gmrf_op* Q, const double* Z, int64
     Run<T>& R = R2s[g];
     R = R1;
     if ((s = setup_state<T>(R, *ws[g])) != GMRF_OK) return s;
-    if (Q->precond && (s = ws[g]->alloc((size_t)R.k * R.z.L, &U[g])) != GMRF_OK) return s;
+    const bool via_u = Q->precond || Q->ic;   // accumulate u_m, then map it to x
+    if (via_u && (s = ws[g]->alloc((size_t)R.k * R.z.L, &U[g])) != GMRF_OK) return s;
     int mg = 0;
     for (int r = 0; r < R.k; ++r) mg = std::max(mg, mu[(size_t)c0[g] + r]);
     double* Xg = X + (size_t)c0[g] * Q->n;
     init_from_z<T>(R, Z + (size_t)c0[g] * Q->n);
     auto acc = [&](int t) {
-      if (Q->precond) launch_accumulate<T, T>(R.slot(t), R.z.L, ys[g], m_max, R1.S, t, U[g], R.z.L, R.st);
+      if (via_u) launch_accumulate<T, T>(R.slot(t), R.z.L, ys[g], m_max, R1.S, t, U[g], R.z.L, R.st);
       else launch_accumulate<T, double>(R.slot(t), R.z.L, ys[g], m_max, R1.S, t, Xg, Q->n, R.st);
     };
     acc(0);
@@ -965,6 +1052,7 @@ static gmrf_status sample_two_pass_impl(const gmrf_op* Q, const double* Z, int64
       acc(j);
     }
     if (Q->precond) fft_backward_output<T>(Q->plan, precond_mult(Q), U[g], Xg, R.F1, R1.S, R.k, R.st);
+    if (Q->ic) launch_trsv<T, double>(Q->icd, true, U[g], R.z.L, Xg, Q->n, nullptr, R.k, R.st);
   }
   HIP_TRY(hipGetLastError());
   if ((s = fj.join()) != GMRF_OK) return s;
@@ -1080,7 +1168,8 @@ static gmrf_status logdet_impl(const gmrf_op* Q, int np, int m, uint64_t seed, c
   }
   if ((s = fj.join()) != GMRF_OK) return s;
   double* agg = g_all + ncol;
-  launch_hutchinson_aggregate(g_all, b0_all, 1, np, K, Q->precond ? Q->logdet_M : 0.0, agg, st);
+  const double shift = Q->precond ? Q->logdet_M : Q->ic ? Q->ic_logdet : 0.0;   // log det M (Section 6.2)
+  launch_hutchinson_aggregate(g_all, b0_all, 1, np, K, shift, agg, st);
   HIP_TRY(hipGetLastError());
   std::vector<double> gam(np), out(2);
   std::vector<int> stt(ncol);

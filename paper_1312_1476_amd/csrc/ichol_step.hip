@@ -1,0 +1,94 @@
+// Incomplete-Cholesky preconditioned Lanczos step (Section 5.2, Proposition 1 with F = L):
+// A v = L^{-1} Q L^{-T} v as a backward solve, the operator, a forward solve; then the opener below and
+// the update kernel finish Algorithm 1's step.  The triangular solves are sequential by nature: rows run
+// level by level (a level holds rows whose dependencies all lie in earlier levels), one block per
+// right-hand side with a barrier between levels, so no block ever waits on another.
+#include "ichol.hpp"
+#include "kernels.hpp"
+
+namespace gmrf {
+
+constexpr int kTrsvThreads = 1024;
+
+// x = T^{-1} b, T = D + N with N strictly triangular by rows (rp, ci, va) and dinv = 1 / diag.
+template <typename T, typename OutT>
+__global__ __launch_bounds__(kTrsvThreads) void k_trsv_levels(const int64_t* __restrict__ rp,
+                                                              const int32_t* __restrict__ ci,
+                                                              const T* __restrict__ va, const T* __restrict__ dinv,
+                                                              const int32_t* __restrict__ lvl_ptr,
+                                                              const int32_t* __restrict__ lvl_rows, int nlev,
+                                                              const T* __restrict__ B, long bld, OutT* X, long xld,
+                                                              const int* __restrict__ active) {
+  const int r = blockIdx.x;
+  if (active && !active[r]) return;   // one value per block: the whole block returns or none does
+  const T* b = B + (size_t)r * bld;
+  OutT* x = X + (size_t)r * xld;
+  for (int lev = 0; lev < nlev; ++lev) {
+    const int e0 = lvl_ptr[lev], e1 = lvl_ptr[lev + 1];
+    for (int idx = e0 + (int)threadIdx.x; idx < e1; idx += kTrsvThreads) {
+      const int i = lvl_rows[idx];
+      double s = (double)b[i];
+      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) s -= (double)va[e] * (double)x[ci[e]];
+      x[i] = (OutT)(s * (double)dinv[i]);
+    }
+    __syncthreads();   // this level's x are visible to the block before the next level reads them
+  }
+}
+
+// Opener of iteration j plus q = AX / beta_{j-1} - beta_{j-1} v_{j-1} and partial sums of v_j^T q.
+template <typename T>
+__global__ __launch_bounds__(kEwThreads) void k_pre_lz(const T* __restrict__ AX, const T* __restrict__ Xj,
+                                                       const T* __restrict__ Xprev, T* __restrict__ Qb, long L,
+                                                       LzState S, int j) {
+  __shared__ double lds[kEwThreads / kWave];
+  __shared__ int flag;
+  const int r = blockIdx.y;
+  double s_cur, s_prev, bprev;
+  if (!lz_open<kEwThreads>(S, r, j, blockIdx.x == 0, lds, &flag, s_cur, s_prev, bprev)) return;
+  const size_t off = (size_t)r * L;
+  const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
+  double acc = 0.0;
+  for (int q = 0; q < kEwPerThread; ++q) {
+    const long e = base + (long)q * kEwThreads;
+    if (e < L) {
+      const double v = (double)(T)((double)Xj[off + e] * s_cur);
+      double qv = (double)AX[off + e] * s_cur;
+      if (j > 1) qv -= bprev * (double)(T)((double)Xprev[off + e] * s_prev);
+      const T qt = (T)qv;
+      Qb[off + e] = qt;
+      acc += v * (double)qt;
+    }
+  }
+  const double s = block_sum<kEwThreads>(acc, lds);
+  if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + blockIdx.x] = s;
+}
+
+template <typename T, typename OutT>
+void launch_trsv(const IcholDev& f, bool upper, const T* B, long bld, OutT* X, long xld, const int* active, int k,
+                 hipStream_t st) {
+  if (upper)
+    hipLaunchKernelGGL((k_trsv_levels<T, OutT>), dim3(k), dim3(kTrsvThreads), 0, st, f.urp, f.uci, (const T*)f.uva,
+                       (const T*)f.dinv, f.blev_ptr, f.blev_rows, f.nblev, B, bld, X, xld, active);
+  else
+    hipLaunchKernelGGL((k_trsv_levels<T, OutT>), dim3(k), dim3(kTrsvThreads), 0, st, f.lrp, f.lci, (const T*)f.lva,
+                       (const T*)f.dinv, f.flev_ptr, f.flev_rows, f.nflev, B, bld, X, xld, active);
+}
+
+template <typename T>
+void launch_pre_lz(const T* AX, const T* Xj, const T* Xprev, T* Qb, long L, const LzState& S, int j, hipStream_t st) {
+  hipLaunchKernelGGL(k_pre_lz<T>, dim3((unsigned)ew_blocks(L), S.k), dim3(kEwThreads), 0, st, AX, Xj, Xprev, Qb, L,
+                     S, j);
+}
+
+template void launch_trsv<double, double>(const IcholDev&, bool, const double*, long, double*, long, const int*, int,
+                                          hipStream_t);
+template void launch_trsv<float, float>(const IcholDev&, bool, const float*, long, float*, long, const int*, int,
+                                        hipStream_t);
+template void launch_trsv<float, double>(const IcholDev&, bool, const float*, long, double*, long, const int*, int,
+                                         hipStream_t);
+template void launch_pre_lz<double>(const double*, const double*, const double*, double*, long, const LzState&, int,
+                                    hipStream_t);
+template void launch_pre_lz<float>(const float*, const float*, const float*, float*, long, const LzState&, int,
+                                   hipStream_t);
+
+}  // namespace gmrf
