@@ -52,10 +52,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
-    ap.add_argument("--only", default="", help="profiling: run only this leg (headline|counters|lgcp|logdet)")
+    ap.add_argument("--only", default="", help="profiling: run only this leg (headline|counters|lgcp|logdet|ichol)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-lgcp", action="store_true", help="skip the log-Gaussian Cox process leg")
     ap.add_argument("--no-logdet", action="store_true", help="skip the log-determinant leg")
+    ap.add_argument("--no-ichol", action="store_true", help="skip the incomplete-Cholesky leg")
     ap.add_argument("--kernel", default="", help="counters leg: kernel to run (default: the dominant one)")
     ap.add_argument("--storage", default="f64", help="counters leg: storage dtype (f64|f32)")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="arrival window per serving rate")
@@ -109,6 +110,9 @@ def main():
         return
     if args.only == "logdet":
         print(json.dumps({"logdet": logdet_leg(gm, torch)}))
+        return
+    if args.only == "ichol":
+        print(json.dumps({"ichol": ichol_leg(gm, torch)}))
         return
 
     # ---- headline: FP64 storage, stop at rho <= 1e-5 ---------------------------------------------
@@ -218,6 +222,10 @@ def main():
     # ---- Hutchinson log det (workload C3), plain and coloured ------------------------------------------
     if not args.no_logdet:
         result["logdet"] = logdet_leg(gm, torch)
+
+    # ---- incomplete-Cholesky preconditioning (Section 5.2, Figure 3) ------------------------------------
+    if not args.no_ichol:
+        result["ichol"] = ichol_leg(gm, torch)
 
     # ---- serving: Poisson request stream over a pool of 64 resident operators ---------------------------
     if not args.no_serve:
@@ -336,6 +344,47 @@ def logdet_leg(gm, torch):
                                     "std_err": se, "var_per_column": se * se * npb * K,
                                     "ms": round(1000 * dt, 2), "columns_per_s": round(npb * K / dt, 1)}
     op.close()
+    return out
+
+
+ICHOL_DROPTOLS = (None, -1.0, 1e-2, 1e-3, 1e-4, 1e-5)   # None: no preconditioner; -1: IC(0)
+
+
+def section52_matrix():
+    """Q = (31^2 P_30)^2, P_30 the 5-point Dirichlet Laplacian on a 30 x 30 grid (n = 900), CSR."""
+    import scipy.sparse as sps
+    T = sps.diags([-np.ones(29), 2 * np.ones(30), -np.ones(29)], [-1, 0, 1])
+    P = 31.0 ** 2 * (sps.kron(T, sps.identity(30)) + sps.kron(sps.identity(30), T))
+    return sps.csr_matrix(P @ P)
+
+
+def ichol_leg(gm, torch):
+    """Figure 3's experiment on the GPU: Section 5.2's 900-point matrix, sampled with incomplete-Cholesky
+    preconditioners (IC(0) and drop thresholds 1e-2 .. 1e-5) and without: Krylov dimension at
+    rho <= 1e-8 (one right-hand side, CGS2, FP64), factor size and solve levels, and the time of a
+    32-sample batch at that tolerance without reorthogonalisation."""
+    Q = section52_matrix()
+    n = Q.shape[0]
+    z1 = torch.from_numpy(np.ascontiguousarray(workloads.gaussian_block(n, 1, 8, 0).T)).to("cuda:0")
+    zb = torch.from_numpy(np.ascontiguousarray(workloads.gaussian_block(n, 32, 8, 1).T)).to("cuda:0")
+    out = {"matrix": "(31^2 P_30)^2, n = 900 (Section 5.2)", "tol_rho": 1e-8, "variants": {}}
+    for dt in ICHOL_DROPTOLS:
+        op = gm.Operator.csr(n, Q.indptr, Q.indices, Q.data, "f64")
+        rec = {}
+        if dt is not None:
+            rec["shift"] = op.set_ichol_precond(dt)
+            rec["nnz_L"], rec["levels"], _ = op.ichol_info()
+        _, info = op.sample(z1, tol=1e-8, m_max=900, reorth=True)
+        rec["m_cgs2"] = info[0]["m_used"]
+        op.sample(zb, tol=1e-8, m_max=900)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, ib = op.sample(zb, tol=1e-8, m_max=900)
+        torch.cuda.synchronize()
+        rec["batch32_ms"] = round(1000 * (time.perf_counter() - t0), 2)
+        rec["batch32_m_max"] = max(i["m_used"] for i in ib)
+        out["variants"]["none" if dt is None else ("ic0" if dt < 0 else f"{dt:g}")] = rec
+        op.close()
     return out
 
 
