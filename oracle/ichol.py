@@ -85,3 +85,11 @@ def hutchinson(Q, L, n_probes, m, seed=0):
     """Section 6.2 with F = L: Hutchinson on A plus 2 sum log L_ii."""
     shift = 2.0 * float(np.sum(np.log(np.diag(L))))
     return logdet.hutchinson(operator(Q, L), Q.shape[0], n_probes, m, seed, shift=shift)
+
+
+def solve(Q, L, b, m_max, tol=0.0, reorth=False):
+    """Q^{-1} b = L^{-T} A^{-1} L^{-1} b (incomplete-Cholesky preconditioned conjugate gradients)."""
+    res = lanczos.solve(operator(Q, L), sla.solve_triangular(L, b, lower=True), m_max, tol, reorth)
+    if res.x is not None:
+        res.x = sla.solve_triangular(L, res.x, lower=True, trans="T")
+    return res

@@ -150,3 +150,22 @@ def cg_relative_residual(Q, z, V, alpha, beta, beta0, j):
     y = beta0 * np.linalg.solve(T, e1)
     r = z - Q @ (V[:, :j] @ y)
     return float(np.linalg.norm(r) / beta0)
+
+
+def tridiag_solve_e1(alpha, beta):
+    """y = T^{-1} e_1 (T = tridiag(beta[:m-1], alpha, beta[:m-1])) by a dense solve."""
+    m = len(alpha)
+    T = np.diag(alpha[:m]) + np.diag(beta[: m - 1], 1) + np.diag(beta[: m - 1], -1)
+    e1 = np.zeros(m)
+    e1[0] = 1.0
+    return np.linalg.solve(T, e1)
+
+
+def solve(matvec, b, m_max, tol=0.0, reorth=False):
+    """x_m = ||b|| V_m T_m^{-1} e_1: the Lanczos form of the conjugate-gradient iterate for Q x = b
+    (Theorem 1 ties the sampler's stopping quantity rho_m to this iterate's residual ||b - Q x_m||)."""
+    alpha, beta, beta0, rho, m, status, V = lanczos_tridiag(matvec, b, m_max, tol, reorth)
+    if status == ENOTSPD:
+        return LanczosResult(None, m, alpha, beta, beta0, rho, status)
+    y = tridiag_solve_e1(alpha[:m], beta[:m])
+    return LanczosResult(beta0 * (V[:, :m] @ y), m, alpha, beta, beta0, rho, status)

@@ -43,3 +43,9 @@ def sample_unpreconditioned(shape, order, kappa2, tau, d, z, m_max, tol=0.0, reo
 def logdet_split(shape, order, kappa2, tau):
     """log det M, added to the Hutchinson estimate of log det A (Section 6.2, sign corrected)."""
     return precond.logdet_M(shape, order, kappa2, tau)
+
+
+def proposal_mean_solve(shape, order, kappa2, tau, d, g, m_max, tol=0.0, reorth=False):
+    """(Q + H)^{-1} g with M = Q (the drift of the sMMALA proposal of Section 3)."""
+    P = posterior_precision(shape, order, kappa2, tau, d)
+    return precond.solve(P, shape, order, kappa2, tau, g, m_max, tol, reorth)

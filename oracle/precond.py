@@ -65,3 +65,13 @@ def sample_many(Q, shape, order, kappa2, tau, Z, m_max, tol=0.0, reorth=False, m
 def logdet_M(shape, order, kappa2, tau):
     """log det M = sum log lambda_M (closed form)."""
     return closed_form.exact_logdet(shape, order, kappa2, tau, "periodic")
+
+
+def solve(Q, shape, order, kappa2, tau, b, m_max, tol=0.0, reorth=False):
+    """Q^{-1} b = M^{-1/2} A^{-1} M^{-1/2} b with A^{-1} by the Lanczos iterate (Proposition 1's
+    factorisation used for a linear solve, i.e. preconditioned conjugate gradients)."""
+    mult = circulant_inv_sqrt_multiplier(shape, order, kappa2, tau)
+    res = lanczos.solve(preconditioned_operator(Q, shape, mult), apply_inv_sqrt_M(shape, mult, b), m_max, tol, reorth)
+    if res.x is not None:
+        res.x = apply_inv_sqrt_M(shape, mult, res.x)
+    return res
