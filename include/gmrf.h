@@ -157,6 +157,15 @@ gmrf_status gmrf_sample_ex(const gmrf_op* Q, const double* Z, int64_t k, double 
                            int32_t m_max, int reorth, double* X, gmrf_info* info,
                            double* alpha, double* beta, void* stream);
 
+/* X[:, r] = x_m ~= Q^{-1} B[:, r] by the same recurrence: x_m = ||b|| V_m T_m^{-1} e_1, the Lanczos
+ * form of the conjugate-gradient iterate, whose relative residual ||b - Q x_m|| / ||b|| is the
+ * rho_m of Theorem 1 (so tol is a residual tolerance).  With a preconditioner F (circulant,
+ * diagonal term, incomplete Cholesky) it solves A u = F^{-1} b and returns F^{-T} u: preconditioned
+ * conjugate gradients on the sampler's kernels, e.g. the sMMALA proposal mean (Q + H)^{-1} grad
+ * of Section 3 with M = Q.  Arguments, info and return as for gmrf_sample (B, X: device FP64).  */
+gmrf_status gmrf_solve(const gmrf_op* Q, const double* B, int64_t k, double tol, int32_t m_max,
+                       int reorth, double* X, gmrf_info* info, void* stream);
+
 /* As gmrf_sample without reorthogonalisation, in O(n k) device memory instead of O(n k m_max):
  * the sampler keeps three Krylov vectors (the O(n) storage Section 1 claims for the method).
  * Pass 1 runs the recurrence with the stopping rule and keeps only alpha_j, beta_j; after

@@ -40,6 +40,8 @@ SIGNATURES = {
                               C.c_void_p, C.POINTER(Info), C.c_void_p]),
     "gmrf_sample_ex": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.c_int,
                                  C.c_void_p, C.POINTER(Info), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "gmrf_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.c_int, C.c_void_p,
+                             C.POINTER(Info), C.c_void_p]),
     "gmrf_sample_two_pass": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.c_void_p,
                                        C.POINTER(Info), C.c_void_p]),
     "gmrf_sample_batch": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,

@@ -58,6 +58,11 @@ void fft_apply_inv_sqrt_M(const FftPlan& p, const T* mult, const T* X, T* Y, T* 
 template <typename T>
 void fft_forward_init(const FftPlan& p, const double* Z, T* V0, T* tmp, const LzState& S, int k, hipStream_t st);
 
+// slot 0 <- Lambda^{-1/2} F b (the spectral start vector of a preconditioned solve), with its norm partials.
+template <typename T>
+void fft_forward_init_mult(const FftPlan& p, const void* mult, const double* B, T* V0, T* tmp, const LzState& S, int k,
+                           hipStream_t st);
+
 // same for Rademacher probe columns p0 .. p0 + k - 1 (from seed, or from an int8 block when probes != nullptr;
 // with a colouring, column q is probe q / K restricted to class q mod K).
 template <typename T>

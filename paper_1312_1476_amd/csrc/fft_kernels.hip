@@ -104,6 +104,7 @@ __global__ __launch_bounds__(kFftThreads) void k_rows_c2r(const C2<T>* __restric
 // ---- column pass -------------------------------------------------------------------------------------
 enum ColMode : int {
   kColFwdInit = 0,   // FFT, times scale                                  (z_hat = F z)
+  kColFwdMult = 1,   // FFT, times lambda^{-1/2} scale                      (Lambda^{-1/2} F b)
   kColInvOut = 3,    // times lambda^{-1/2} scale, inverse FFT              (x = F^H Lambda^{-1/2} u)
   kColApply = 4      // FFT, times lambda^{-1/2} scale, inverse FFT         (M^{-1/2} on its own)
 };
@@ -124,6 +125,7 @@ __global__ __launch_bounds__(kFftThreads) void k_cols(const C2<T>* __restrict__ 
   if (MODE == kColInvOut) apply_mult(buf, nf, c0, N1, H, mult, scale);
   else __syncthreads();
   lds_fft<T, true>(buf, N1, nf, 1, nf, tw, MODE == kColInvOut);
+  if (MODE == kColFwdMult) apply_mult(buf, nf, c0, N1, H, mult, scale);
   if (MODE == kColApply) {
     apply_mult(buf, nf, c0, N1, H, mult, scale);
     lds_fft<T, true>(buf, N1, nf, 1, nf, tw, true);
@@ -237,6 +239,15 @@ void fft_forward_init(const FftPlan& p, const double* Z, T* V0, T* tmp, const Lz
 }
 
 template <typename T>
+void fft_forward_init_mult(const FftPlan& p, const void* mult, const double* B, T* V0, T* tmp, const LzState& S, int k,
+                           hipStream_t st) {
+  const long n = (long)p.N1 * p.N2;
+  rows_r2c<double, T>(p, B, n, tmp, n / 2, (T)1, nullptr, k, st);
+  cols<T, kColFwdMult>(p, tmp, V0, (const T*)mult, (T)(1.0 / std::sqrt((double)n)), k, st);
+  launch_norm_partials<T>(V0, n, S, st);
+}
+
+template <typename T>
 void fft_forward_init_probes(const FftPlan& p, uint64_t seed, int p0, const int8_t* probes, T* real_tmp, T* V0,
                              T* tmp, const LzState& S, int k, hipStream_t st, const int32_t* colour, int K) {
   const long n = (long)p.N1 * p.N2;
@@ -258,6 +269,7 @@ void fft_backward_output(const FftPlan& p, const void* mult, const T* U, double*
 #define INST(T)                                                                                            \
   template void fft_apply_inv_sqrt_M<T>(const FftPlan&, const T*, const T*, T*, T*, int, hipStream_t);     \
   template void fft_forward_init<T>(const FftPlan&, const double*, T*, T*, const LzState&, int, hipStream_t); \
+  template void fft_forward_init_mult<T>(const FftPlan&, const void*, const double*, T*, T*, const LzState&, int, hipStream_t); \
   template void fft_forward_init_probes<T>(const FftPlan&, uint64_t, int, const int8_t*, T*, T*, T*, const LzState&, int, hipStream_t, const int32_t*, int); \
   template void fft_backward_output<T>(const FftPlan&, const void*, const T*, double*, T*, const LzState&, int, hipStream_t);
 INST(double)

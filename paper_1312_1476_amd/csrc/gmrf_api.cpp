@@ -887,10 +887,30 @@ static void init_from_z(Run<T>& R, const double* Zg) {
   }
 }
 
+// slot 0 <- the start vector of the preconditioned solve: Lambda^{-1/2} F b (circulant, LGCP), L^{-1} b
+// (incomplete Cholesky), b otherwise; the iterate is mapped back by the same output step as a sample.
+template <typename T>
+static void init_for_solve(Run<T>& R, const double* Bg) {
+  const gmrf_op* Q = R.Q;
+  if (Q->precond) {
+    fft_forward_init_mult<T>(Q->plan, precond_mult(Q), Bg, R.slot(0), R.F1, R.S, R.k, R.st);
+    if (lgcp_path(Q)) lgcp_col_init<T>(Q->plan, precond_mult(Q), R.slot(0), R.F1, R.k, R.st);
+    else precond_dots<T>(Q->plan, precond_mult(Q), R.slot(0), R.band, R.S, R.k, R.st);
+  } else if (Q->ic) {
+    launch_init_from_f64<T>(Bg, Q->n, R.z.L, R.F1, R.S, R.st);
+    launch_trsv<T, T>(Q->icd, false, R.F1, R.z.L, R.slot(0), R.z.L, nullptr, R.k, R.st);
+    launch_norm_partials<T>(R.slot(0), R.z.L, R.S, R.st);
+  } else {
+    init_from_z<T>(R, Bg);
+  }
+}
+
+// solve = false: samples x_m = ||z|| V_m T_m^{-1/2} e_1 (Algorithm 1); solve = true: the Lanczos form of the
+// conjugate-gradient iterate x_m = ||b|| V_m T_m^{-1} e_1 for Q x = b, preconditioned the same way.
 template <typename T>
 static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, double tol, int m_max, int reorth,
                                double* X, gmrf_info* info, double* alpha_out, double* beta_out,
-                               hipStream_t st) {
+                               hipStream_t st, bool solve = false) {
   const int G = groups_for(Q, k);
   ForkJoin fj;
   gmrf_status s = fj.fork(st, G);
@@ -910,17 +930,23 @@ static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, dou
     R.tol = tol;
     R.st = fj.gs[g];
     if ((s = setup<T>(R, *ws[g])) != GMRF_OK) return s;
-    init_from_z<T>(R, Z + (size_t)c0[g] * Q->n);
+    if (solve) init_for_solve<T>(R, Z + (size_t)c0[g] * Q->n);
+    else init_from_z<T>(R, Z + (size_t)c0[g] * Q->n);
   }
   if ((s = run_loop<T>(Rs)) != GMRF_OK) return s;
-  // y = T_m^{-1/2} e_1, then x_m = ||z|| V_m y
+  // y = T_m^{-1/2} e_1 (or T_m^{-1} e_1), then x_m = ||z|| V_m y
   for (int g = 0; g < G; ++g) {
     Run<T>& R = Rs[g];
     double* scr;
     if ((s = ws[g]->alloc((size_t)R.k * m_max, &ys[g])) != GMRF_OK) return s;
-    if ((s = ws[g]->alloc(tri_scratch_doubles(R.k, m_max), &scr)) != GMRF_OK) return s;
-    launch_tri_invsqrt(R.S.alpha, m_max + 1, 1, R.S.beta, m_max + 2, 1, R.S.m_used, 0, R.S.status, ys[g], m_max,
-                       R.S.status, scr, m_max, R.k, R.st);
+    if (solve) {
+      launch_tri_solve(R.S.alpha, m_max + 1, 1, R.S.beta, m_max + 2, 1, R.S.m_used, 0, R.S.status, ys[g], m_max,
+                       R.S.status, R.k, R.st);
+    } else {
+      if ((s = ws[g]->alloc(tri_scratch_doubles(R.k, m_max), &scr)) != GMRF_OK) return s;
+      launch_tri_invsqrt(R.S.alpha, m_max + 1, 1, R.S.beta, m_max + 2, 1, R.S.m_used, 0, R.S.status, ys[g], m_max,
+                         R.S.status, scr, m_max, R.k, R.st);
+    }
     double* Xg = X + (size_t)c0[g] * Q->n;
     if (Q->precond) {
       launch_combine<T, T>(R.V, R.z.L, ys[g], m_max, R.Qb, R.z.L, R.S, R.st);
@@ -964,7 +990,9 @@ static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, dou
       info[r].m_used = m;
       info[r].status = stt[r];
       info[r].rel_residual = m > 0 ? rr : 0.0;
-      info[r].err_bound = (m > 0 && std::isfinite(lam_lb)) ? rr / std::sqrt(lam_lb) : NAN;
+      // Theorem 1: ||x - x_m|| / ||z|| <= lambda_min^{-1/2} rho_m for a sample; ||x - x_m|| / ||b|| <= rho_m /
+      // lambda_min for a solve
+      info[r].err_bound = (m > 0 && std::isfinite(lam_lb)) ? (solve ? rr / lam_lb : rr / std::sqrt(lam_lb)) : NAN;
     }
     if (stt[r] == kENOTSPD) ret = GMRF_ENOTSPD;
     if (stt[r] == kEINVAL && ret == GMRF_OK) ret = GMRF_EINVAL;
@@ -1100,6 +1128,21 @@ extern "C" gmrf_status gmrf_sample_ex(const gmrf_op* Q, const double* Z, int64_t
   hipStream_t st = (hipStream_t)stream;
   if (Q->storage == GMRF_F64) return sample_impl<double>(Q, Z, k, tol, m_max, reorth, X, info, alpha, beta, st);
   return sample_impl<float>(Q, Z, k, tol, m_max, reorth, X, info, alpha, beta, st);
+}
+
+extern "C" gmrf_status gmrf_solve(const gmrf_op* Q, const double* B, int64_t k, double tol, int32_t m_max, int reorth,
+                                  double* X, gmrf_info* info, void* stream) {
+  if (!Q || !B || !X) return fail(GMRF_EINVAL, "NULL argument");
+  if (k < 1 || k > 65535) return fail(GMRF_EINVAL, "k must be in 1..65535");
+  if (m_max < 1 || m_max > tri_max_m()) return fail(GMRF_EINVAL, "m_max must be in 1..%d", tri_max_m());
+  if (!std::isfinite(tol)) return fail(GMRF_EINVAL, "tol must be finite");
+  if (reorth != 0 && reorth != 1) return fail(GMRF_EINVAL, "reorth must be 0 or 1");
+  if (Q->has_diag && !Q->precond)
+    return fail(GMRF_EUNSUPPORTED, "Q + diag(d) is solved with circulant preconditioning only (else pass it as CSR)");
+  hipStream_t st = (hipStream_t)stream;
+  if (Q->storage == GMRF_F64)
+    return sample_impl<double>(Q, B, k, tol, m_max, reorth, X, info, nullptr, nullptr, st, true);
+  return sample_impl<float>(Q, B, k, tol, m_max, reorth, X, info, nullptr, nullptr, st, true);
 }
 
 extern "C" gmrf_status gmrf_sample(const gmrf_op* Q, const double* Z, int64_t k, double tol, int32_t m_max,

@@ -53,6 +53,9 @@ size_t tri_scratch_doubles(int k, int m_cap);
 void launch_tri_invsqrt(const double* alpha, int lda, int a_off, const double* beta, int ldb, int b_off,
                         const int* m, int m_fixed, const int* status_in, double* y, int ldy,
                         int* status_out, double* scratch, int scr_m, int k, hipStream_t st);
+// y = T^{-1} e_1 (the linear solve's tridiagonal step); status_out[r] = ENOTSPD when T is not SPD
+void launch_tri_solve(const double* alpha, int lda, int a_off, const double* beta, int ldb, int b_off, const int* m,
+                      int m_fixed, const int* status_in, double* y, int ldy, int* status_out, int k, hipStream_t st);
 void launch_tri_log(const double* alpha, int lda, int a_off, const double* beta, int ldb, int b_off,
                     const int* m, int m_fixed, const int* status_in, double* out, int ldo,
                     int* status_out, int k, hipStream_t st);

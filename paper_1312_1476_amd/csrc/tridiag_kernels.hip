@@ -171,6 +171,45 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_log(TriArgs A) {
   if (threadIdx.x == 0) A.out[(size_t)r * A.ldy] = tot;
 }
 
+// y = T^{-1} e_1 for the linear solve x_m = ||b|| V_m T_m^{-1} e_1: backward pivots d_{m-1} = alpha_{m-1},
+// d_i = alpha_i - beta_i^2 / d_{i+1}, then y_0 = 1 / d_0, y_{i+1} = -(beta_i / d_{i+1}) y_i (the sigma = 0
+// case of the shifted solves above).  One thread per right-hand side; a non-positive pivot is ENOTSPD.
+__global__ __launch_bounds__(kTriThreads) void k_tri_solve(TriArgs A, int k) {
+  const int r = blockIdx.x * kTriThreads + threadIdx.x;
+  if (r >= k) return;
+  const int m = A.m ? A.m[r] : A.m_fixed;
+  double* y = A.out + (size_t)r * A.ldy;
+  if ((A.status_in && A.status_in[r] != kOK && A.status_in[r] != kENOCONV) || m <= 0) return;
+  const double* al = A.alpha + (size_t)r * A.lda + A.a_off;
+  const double* be = A.beta + (size_t)r * A.ldb + A.b_off;
+  // pass 1: backward pivots into y (reused as scratch), checking definiteness
+  double d = al[m - 1];
+  bool ok = d > 0.0;
+  y[m - 1] = d;
+  for (int i = m - 2; i >= 0; --i) {
+    d = al[i] - be[i] * be[i] / d;
+    ok = ok && d > 0.0;
+    y[i] = d;
+  }
+  if (!ok) {
+    if (A.status_out) A.status_out[r] = kENOTSPD;
+    return;
+  }
+  // pass 2: y_0 = 1 / d_0, y_{i+1} = -(beta_i / d_{i+1}) y_i
+  double yi = 1.0 / y[0];
+  y[0] = yi;
+  for (int i = 0; i + 1 < m; ++i) {
+    yi = -(be[i] / y[i + 1]) * yi;
+    y[i + 1] = yi;
+  }
+}
+
+void launch_tri_solve(const double* alpha, int lda, int a_off, const double* beta, int ldb, int b_off, const int* m,
+                      int m_fixed, const int* status_in, double* y, int ldy, int* status_out, int k, hipStream_t st) {
+  TriArgs A{alpha, lda, a_off, beta, ldb, b_off, m, m_fixed, status_in, y, ldy, status_out, nullptr, 0};
+  hipLaunchKernelGGL(k_tri_solve, dim3((k + kTriThreads - 1) / kTriThreads), dim3(kTriThreads), 0, st, A, k);
+}
+
 int tri_max_m() { return kTriMaxM; }
 size_t tri_scratch_doubles(int k, int m_cap) { return (size_t)k * m_cap * kTriThreads; }
 
