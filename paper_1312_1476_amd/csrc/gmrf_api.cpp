@@ -142,6 +142,8 @@ struct Workspace {
 };
 }  // namespace
 
+void free_ichol(gmrf::IcholDev& f);
+
 // ---- operator handle -------------------------------------------------------------------------------
 struct gmrf_op {
   int kind = 0;           // 0 lattice, 1 csr
@@ -304,10 +306,7 @@ void gmrf_op_destroy(gmrf_op* Q) {
   if (Q->mult32) (void)hipFree(Q->mult32);
   if (Q->diag64) (void)hipFree(Q->diag64);
   if (Q->diag32) (void)hipFree(Q->diag32);
-  for (void* p : {(void*)Q->icd.lrp, (void*)Q->icd.lci, Q->icd.lva, (void*)Q->icd.urp, (void*)Q->icd.uci, Q->icd.uva,
-                  Q->icd.dinv, (void*)Q->icd.flev_ptr, (void*)Q->icd.flev_rows, (void*)Q->icd.blev_ptr,
-                  (void*)Q->icd.blev_rows})
-    if (p) (void)hipFree(p);
+  free_ichol(Q->icd);
   fft_plan_destroy(Q->plan);
   delete Q;
 }
@@ -407,6 +406,17 @@ extern "C" gmrf_status gmrf_op_set_diagonal(gmrf_op* Q, const double* d) {
 
 // ---- incomplete-Cholesky preconditioner (Section 5.2) -----------------------------------------------
 namespace {
+void free_trsv(TrsvDev& d) {
+  for (void* p : {(void*)d.lvl_ptr, (void*)d.rows, (void*)d.rp, (void*)d.ci, d.va, d.dinv})
+    if (p) (void)hipFree(p);
+  d = TrsvDev{};
+}
+}  // namespace
+void free_ichol(IcholDev& f) {
+  free_trsv(f.fwd);
+  free_trsv(f.bwd);
+}
+namespace {
 template <typename V>
 gmrf_status upload(const std::vector<V>& h, V** d) {
   HIP_TRY(hipMalloc(d, std::max<size_t>(h.size(), 1) * sizeof(V)));
@@ -417,6 +427,33 @@ gmrf_status upload_vals(const std::vector<double>& h, int storage, void** d) {
   if (storage == GMRF_F64) return upload(h, (double**)d);
   std::vector<float> f(h.begin(), h.end());
   return upload(f, (float**)d);
+}
+// One solve in level order: position p = row lvl_rows[p] of (rp, ci, va), 1 / diagonal alongside.
+gmrf_status upload_trsv(const std::vector<int64_t>& rp, const std::vector<int32_t>& ci, const std::vector<double>& va,
+                        const std::vector<double>& diag, const std::vector<int32_t>& lvl_ptr,
+                        const std::vector<int32_t>& lvl_rows, int storage, TrsvDev& d) {
+  const size_t n = lvl_rows.size();
+  std::vector<int64_t> prp(n + 1, 0);
+  std::vector<int32_t> pci;
+  std::vector<double> pva, pdinv(n);
+  pci.reserve(ci.size());
+  pva.reserve(va.size());
+  for (size_t p = 0; p < n; ++p) {
+    const int32_t i = lvl_rows[p];
+    for (int64_t e = rp[(size_t)i]; e < rp[(size_t)i + 1]; ++e) {
+      pci.push_back(ci[(size_t)e]);
+      pva.push_back(va[(size_t)e]);
+    }
+    prp[p + 1] = (int64_t)pci.size();
+    pdinv[p] = 1.0 / diag[(size_t)i];
+  }
+  gmrf_status s;
+  if ((s = upload(lvl_ptr, &d.lvl_ptr)) != GMRF_OK || (s = upload(lvl_rows, &d.rows)) != GMRF_OK ||
+      (s = upload(prp, &d.rp)) != GMRF_OK || (s = upload(pci, &d.ci)) != GMRF_OK ||
+      (s = upload_vals(pva, storage, &d.va)) != GMRF_OK || (s = upload_vals(pdinv, storage, &d.dinv)) != GMRF_OK)
+    return s;
+  d.nlev = (int)lvl_ptr.size() - 1;
+  return GMRF_OK;
 }
 }  // namespace
 
@@ -432,22 +469,12 @@ extern "C" gmrf_status gmrf_op_set_ichol_precond(gmrf_op* Q, int enable, double 
   if (!ichol_factor(Q->n, Q->h_rp.data(), Q->h_ci.data(), Q->h_va.data(), droptol, h))
     return fail(GMRF_ENOTSPD, "incomplete Cholesky broke down for every diagonal shift up to 2^30 * 1e-3");
   IcholDev& d = Q->icd;
-  for (void* p : {(void*)d.lrp, (void*)d.lci, d.lva, (void*)d.urp, (void*)d.uci, d.uva, d.dinv, (void*)d.flev_ptr,
-                  (void*)d.flev_rows, (void*)d.blev_ptr, (void*)d.blev_rows})
-    if (p) (void)hipFree(p);
-  d = IcholDev{};
-  std::vector<double> dinv(h.diag.size());
-  for (size_t i = 0; i < dinv.size(); ++i) dinv[i] = 1.0 / h.diag[i];
+  free_ichol(d);
+  d.n = Q->n;
   gmrf_status s;
-  if ((s = upload(h.lrp, &d.lrp)) != GMRF_OK || (s = upload(h.lci, &d.lci)) != GMRF_OK ||
-      (s = upload_vals(h.lva, Q->storage, &d.lva)) != GMRF_OK || (s = upload(h.urp, &d.urp)) != GMRF_OK ||
-      (s = upload(h.uci, &d.uci)) != GMRF_OK || (s = upload_vals(h.uva, Q->storage, &d.uva)) != GMRF_OK ||
-      (s = upload_vals(dinv, Q->storage, &d.dinv)) != GMRF_OK || (s = upload(h.flev_ptr, &d.flev_ptr)) != GMRF_OK ||
-      (s = upload(h.flev_rows, &d.flev_rows)) != GMRF_OK || (s = upload(h.blev_ptr, &d.blev_ptr)) != GMRF_OK ||
-      (s = upload(h.blev_rows, &d.blev_rows)) != GMRF_OK)
+  if ((s = upload_trsv(h.lrp, h.lci, h.lva, h.diag, h.flev_ptr, h.flev_rows, Q->storage, d.fwd)) != GMRF_OK ||
+      (s = upload_trsv(h.urp, h.uci, h.uva, h.diag, h.blev_ptr, h.blev_rows, Q->storage, d.bwd)) != GMRF_OK)
     return s;
-  d.nflev = (int)h.flev_ptr.size() - 1;
-  d.nblev = (int)h.blev_ptr.size() - 1;
   Q->ic_logdet = h.logdet_M;
   Q->ic_shift = h.shift;
   Q->ic_nnz = (int64_t)h.lva.size() + Q->n;
@@ -459,7 +486,7 @@ extern "C" gmrf_status gmrf_op_set_ichol_precond(gmrf_op* Q, int enable, double 
 extern "C" gmrf_status gmrf_ichol_info(const gmrf_op* Q, int64_t* nnz_L, int32_t* levels, double* shift) {
   if (!Q || !Q->ic) return fail(GMRF_EINVAL, "no incomplete-Cholesky preconditioner on this operator");
   if (nnz_L) *nnz_L = Q->ic_nnz;
-  if (levels) *levels = Q->icd.nflev;
+  if (levels) *levels = Q->icd.fwd.nlev;
   if (shift) *shift = Q->ic_shift;
   return GMRF_OK;
 }

@@ -26,20 +26,21 @@ struct IcholHost {
 // false: breakdown at every shift of the sequence.  Q: symmetric CSR (host).
 bool ichol_factor(int64_t n, const int64_t* rp, const int32_t* ci, const double* va, double droptol, IcholHost& out);
 
-// Device copy (storage dtype T for the factor values).
+// One triangular solve on the device, stored in level order: position p (levels are the ranges
+// lvl_ptr[l] .. lvl_ptr[l+1]) holds row rows[p], its strictly-triangular entries rp[p] .. rp[p+1] of
+// (ci, va) (column = original row index) and dinv[p] = 1 / l_ii; values in the storage dtype.
+struct TrsvDev {
+  int32_t* lvl_ptr = nullptr;
+  int32_t* rows = nullptr;
+  int64_t* rp = nullptr;
+  int32_t* ci = nullptr;
+  void* va = nullptr;
+  void* dinv = nullptr;
+  int nlev = 0;
+};
 struct IcholDev {
-  int64_t* lrp = nullptr;
-  int32_t* lci = nullptr;
-  void* lva = nullptr;
-  int64_t* urp = nullptr;
-  int32_t* uci = nullptr;
-  void* uva = nullptr;
-  void* dinv = nullptr;           // 1 / l_ii
-  int32_t* flev_ptr = nullptr;
-  int32_t* flev_rows = nullptr;
-  int32_t* blev_ptr = nullptr;
-  int32_t* blev_rows = nullptr;
-  int nflev = 0, nblev = 0;
+  TrsvDev fwd, bwd;     // L y = b, L^T x = y
+  int64_t n = 0;
 };
 
 // X[:, r] = L^{-1} B[:, r] (lower) or L^{-T} B[:, r] (upper) for the k columns with active[r] != 0

@@ -9,30 +9,39 @@
 namespace gmrf {
 
 constexpr int kTrsvThreads = 1024;
+constexpr int64_t kTrsvLdsRows = 8192;   // x of up to this many rows is kept in LDS (64 KB of FP64)
 
-// x = T^{-1} b, T = D + N with N strictly triangular by rows (rp, ci, va) and dinv = 1 / diag.
-template <typename T, typename OutT>
-__global__ __launch_bounds__(kTrsvThreads) void k_trsv_levels(const int64_t* __restrict__ rp,
+// x = T^{-1} b, T = D + N with N strictly triangular, stored in level order (TrsvDev).  Only the x
+// values carry the dependency between levels; every row's indices and values are known in advance.
+// XLDS: x lives in LDS (n <= kTrsvLdsRows) and is written out once at the end.
+template <typename T, typename OutT, bool XLDS>
+__global__ __launch_bounds__(kTrsvThreads) void k_trsv_levels(const int32_t* __restrict__ lvl_ptr,
+                                                              const int32_t* __restrict__ rows,
+                                                              const int64_t* __restrict__ rp,
                                                               const int32_t* __restrict__ ci,
                                                               const T* __restrict__ va, const T* __restrict__ dinv,
-                                                              const int32_t* __restrict__ lvl_ptr,
-                                                              const int32_t* __restrict__ lvl_rows, int nlev,
-                                                              const T* __restrict__ B, long bld, OutT* X, long xld,
-                                                              const int* __restrict__ active) {
+                                                              int nlev, long n, const T* __restrict__ B, long bld,
+                                                              OutT* X, long xld, const int* __restrict__ active) {
+  extern __shared__ double xs[];
   const int r = blockIdx.x;
   if (active && !active[r]) return;   // one value per block: the whole block returns or none does
   const T* b = B + (size_t)r * bld;
   OutT* x = X + (size_t)r * xld;
   for (int lev = 0; lev < nlev; ++lev) {
     const int e0 = lvl_ptr[lev], e1 = lvl_ptr[lev + 1];
-    for (int idx = e0 + (int)threadIdx.x; idx < e1; idx += kTrsvThreads) {
-      const int i = lvl_rows[idx];
+    for (int p = e0 + (int)threadIdx.x; p < e1; p += kTrsvThreads) {
+      const int i = rows[p];
       double s = (double)b[i];
-      for (int64_t e = rp[i]; e < rp[i + 1]; ++e) s -= (double)va[e] * (double)x[ci[e]];
-      x[i] = (OutT)(s * (double)dinv[i]);
+      const int64_t q1 = rp[p + 1];
+      for (int64_t e = rp[p]; e < q1; ++e) s -= (double)va[e] * (XLDS ? xs[ci[e]] : (double)x[ci[e]]);
+      s *= (double)dinv[p];
+      if (XLDS) xs[i] = s;
+      else x[i] = (OutT)s;
     }
     __syncthreads();   // this level's x are visible to the block before the next level reads them
   }
+  if (XLDS)
+    for (long i = threadIdx.x; i < n; i += kTrsvThreads) x[i] = (OutT)xs[i];
 }
 
 // Opener of iteration j plus q = AX / beta_{j-1} - beta_{j-1} v_{j-1} and partial sums of v_j^T q.
@@ -66,12 +75,14 @@ __global__ __launch_bounds__(kEwThreads) void k_pre_lz(const T* __restrict__ AX,
 template <typename T, typename OutT>
 void launch_trsv(const IcholDev& f, bool upper, const T* B, long bld, OutT* X, long xld, const int* active, int k,
                  hipStream_t st) {
-  if (upper)
-    hipLaunchKernelGGL((k_trsv_levels<T, OutT>), dim3(k), dim3(kTrsvThreads), 0, st, f.urp, f.uci, (const T*)f.uva,
-                       (const T*)f.dinv, f.blev_ptr, f.blev_rows, f.nblev, B, bld, X, xld, active);
+  const TrsvDev& d = upper ? f.bwd : f.fwd;
+  if (f.n <= kTrsvLdsRows)
+    hipLaunchKernelGGL((k_trsv_levels<T, OutT, true>), dim3(k), dim3(kTrsvThreads), (size_t)f.n * sizeof(double), st,
+                       d.lvl_ptr, d.rows, d.rp, d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, B, bld,
+                       X, xld, active);
   else
-    hipLaunchKernelGGL((k_trsv_levels<T, OutT>), dim3(k), dim3(kTrsvThreads), 0, st, f.lrp, f.lci, (const T*)f.lva,
-                       (const T*)f.dinv, f.flev_ptr, f.flev_rows, f.nflev, B, bld, X, xld, active);
+    hipLaunchKernelGGL((k_trsv_levels<T, OutT, false>), dim3(k), dim3(kTrsvThreads), 0, st, d.lvl_ptr, d.rows, d.rp,
+                       d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, B, bld, X, xld, active);
 }
 
 template <typename T>
