@@ -25,7 +25,8 @@ struct StencilGeom {
   int periodic;
   double kappa2, tau;
   int tiles_x, tiles_y, tiles_z;
-  int epl;                 // 2D kernel: elements per lane (1 or 2)
+  int epl;                 // 2D operator kernel: elements per lane (1, 2, or 4 for FP32)
+  int fepl;                // 2D one-pass Lanczos kernel: elements per lane (1 or 2)
   int ftiles_x;            // 2D one-pass Lanczos kernel: strips per row
 };
 

@@ -247,7 +247,7 @@ gmrf_status gmrf_op_create_lattice(int ndim, const int64_t* shape, int order, do
   op->geom.periodic = bc == GMRF_PERIODIC;
   op->geom.kappa2 = kappa2;
   op->geom.tau = tau;
-  stencil_geom_tiles(op->geom, ndim, order);
+  stencil_geom_tiles(op->geom, ndim, order, 0, storage == GMRF_F64 ? 8 : 4);
   *out = op;
   return GMRF_OK;
 }
@@ -580,7 +580,7 @@ static void op_apply_plain(const gmrf_op* Q, const T* X, T* Y, int k, hipStream_
   if (Q->kind == 0) {
     // caller buffers may not be aligned for the 2D kernel's element pairs: then one element per lane
     StencilGeom g = Q->geom;
-    if (g.epl == 2 && (((uintptr_t)X | (uintptr_t)Y) % (2 * sizeof(T))) != 0) stencil_geom_tiles(g, Q->dim, Q->order, 1);
+    if (g.epl > 1 && (((uintptr_t)X | (uintptr_t)Y) % (g.epl * sizeof(T))) != 0) stencil_geom_tiles(g, Q->dim, Q->order, 1);
     launch_stencil<T>(g, Q->order, Q->dim, false, X, Q->n, Y, Q->n, nullptr, S, 0, k, st);
     if (Q->has_diag) launch_add_diag<T>((const T*)diag_of(Q), X, Y, (long)Q->n, k, st);
     return;

@@ -27,9 +27,10 @@ template <typename T, typename OutT> void launch_accumulate(const T* Vt, long L,
 template <typename T, typename OutT> void launch_combine(const T* V, long L, const double* y, int ldy, OutT* out, long old, const LzState& S, hipStream_t st);
 
 // operator_kernels.hip
-// epl: elements per lane of the 2D kernel (0: 2 when the row length is even; 1 for fields packed at
-// arbitrary offsets)
-void stencil_geom_tiles(StencilGeom& g, int dim, int order, int epl = 0);
+// epl: elements per lane of the 2D operator kernel (0: the widest the row length allows for vbytes-byte
+// storage, 4 for FP32 and 2 for FP64; 1 for fields at arbitrary offsets); the one-pass kernel takes at
+// most 2
+void stencil_geom_tiles(StencilGeom& g, int dim, int order, int epl = 0, int vbytes = 8);
 // One-pass Lanczos step on a 2D lattice (k_lanczos2d): mode 0 reads v_j = X / beta_{j-1} and v_{j-1} = Xprev
 // (S holds the previous pass's partial sums), writes w_j to W and this pass's partial sums to out_*; mode 1
 // writes the partial sums of X^T Q X to out_a.  grid_x = 0: the lattice's own block count.

@@ -169,9 +169,10 @@ template <typename T> struct S2Ahead;
 template <> struct S2Ahead<double> { static constexpr int value = GMRF_S2_AHEAD64; };
 template <> struct S2Ahead<float> { static constexpr int value = GMRF_S2_AHEAD32; };
 
-// Elements of a lane: EPL = 2 adjacent columns (one vector load) when the geometry allows it (even row
-// length and even field offsets), else 1.  With EPL = 2 the strips start 2 columns left of their first
-// output, so lanes hold aligned pairs and a pair never straddles the lattice edge.
+// Elements of a lane: EPL adjacent columns (one vector load) when the geometry allows it (row length and
+// field offsets multiples of EPL): 4 for FP32 storage (16-byte loads), 2 for FP64, else 1.  With EPL > 1
+// the strips start EPL columns left of their first output, so lanes hold aligned groups and a group never
+// straddles the lattice edge.
 template <typename T, int EPL> struct VecE;
 template <typename T> struct VecE<T, 1> {
   typedef T type;
@@ -185,7 +186,13 @@ template <> struct VecE<float, 2> {
   typedef float type __attribute__((ext_vector_type(2)));
   __device__ static float get(const type& v, int e) { return v[e]; }
 };
-__host__ __device__ inline int s2_halo(int order, int epl) { return epl == 2 ? 2 : order; }
+template <> struct VecE<float, 4> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  __device__ static float get(const type& v, int e) { return v[e]; }
+};
+// largest EPL of the 2D operator kernel per storage type (sizes its LDS row slots)
+template <typename T> constexpr int kS2MaxEpl = sizeof(T) == 4 ? 4 : 2;
+__host__ __device__ inline int s2_halo(int order, int epl) { return epl >= 2 ? epl : order; }
 __host__ __device__ inline int s2_out(int order, int epl) { return kWave * epl - 2 * s2_halo(order, epl); }
 
 template <typename T, int ORDER, bool LZ, int EPL>
@@ -195,13 +202,13 @@ __device__ __forceinline__ void s2_strip(const StencilGeom& g, int tx, int ty, i
                                          double bprev, T* vbuf, T* tbuf, double& acc) {
   using VE = VecE<T, EPL>;
   using VT = typename VE::type;
-  constexpr int HX = EPL == 2 ? 2 : ORDER;
+  constexpr int HX = EPL >= 2 ? EPL : ORDER;
   constexpr int OX = kWave * EPL - 2 * HX;
   constexpr int RW = kWave * EPL;                               // row-slot width
   const int n1 = g.n1, n2 = g.n2;
   const bool per = g.periodic != 0;
   const int xb = tx * OX - HX + lane * EPL;                     // first column of this lane
-  // column of the lane's load: clamped (free) or wrapped (periodic), pair-aligned when EPL = 2
+  // column of the lane's load: clamped (free) or wrapped (periodic), group-aligned when EPL > 1
   const int xl = per ? ((xb % n2) + n2) % n2 : min(max(xb, 0), n2 - EPL);
   bool hl[EPL], hr[EPL];
 #pragma unroll
@@ -257,8 +264,8 @@ __device__ __forceinline__ void s2_strip(const StencilGeom& g, int tx, int ty, i
     if constexpr (EPL == 1) {
       vv = val[0];
     } else {
-      vv[0] = val[0];
-      vv[1] = val[1];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) vv[e] = val[e];
     }
     *(VT*)(buf + par * RW + lane * EPL) = vv;
   };
@@ -318,8 +325,8 @@ __device__ __forceinline__ void s2_strip(const StencilGeom& g, int tx, int ty, i
       if constexpr (EPL == 1) {
         vv = res[0];
       } else {
-        vv[0] = res[0];
-        vv[1] = res[1];
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) vv[e] = res[e];
       }
       *(VT*)(dst + (size_t)yo * n2 + xb) = vv;
     }
@@ -330,8 +337,9 @@ __device__ __forceinline__ void s2_strip(const StencilGeom& g, int tx, int ty, i
     }
   };
   // AHEAD register sets take turns (unrolled, no copies between them): row i lives in set i % AHEAD and
-  // is computed while rows i + 1 .. i + AHEAD - 1 are in flight
-  constexpr int AHEAD = S2Ahead<T>::value;
+  // is computed while rows i + 1 .. i + AHEAD - 1 are in flight; 16-byte lanes (FP64 pairs, FP32 groups
+  // of four) take the FP64 depth
+  constexpr int AHEAD = EPL * sizeof(T) >= 16 ? GMRF_S2_AHEAD64 : S2Ahead<T>::value;
   static_assert(AHEAD >= LEAD && AHEAD % 2 == 0, "prefetch depth");
   VT q[AHEAD], p[AHEAD];
 #pragma unroll
@@ -366,8 +374,8 @@ template <typename T, int ORDER, bool LZ>
 __global__ __launch_bounds__(256) void k_stencil2d(StencilGeom g0, const T* __restrict__ X, long xld,
                                                    T* __restrict__ Y, long yld, const T* __restrict__ Xprev,
                                                    LzState S, int j, const int* __restrict__ active) {
-  __shared__ __align__(16) T vrow[kS2Waves][2][2 * kWave];
-  __shared__ __align__(16) T trow[kS2Waves][2][2 * kWave];
+  __shared__ __align__(16) T vrow[kS2Waves][2][kS2MaxEpl<T> * kWave];
+  __shared__ __align__(16) T trow[kS2Waves][2][kS2MaxEpl<T> * kWave];
   __shared__ double red[256 / kWave];
   __shared__ int flag[1];
   const int r = blockIdx.y;
@@ -387,12 +395,20 @@ __global__ __launch_bounds__(256) void k_stencil2d(StencilGeom g0, const T* __re
   T* dst = Y + ((LZ && S.col_off) ? roff : (size_t)r * yld);
   const T* prv = LZ ? Xprev + roff : nullptr;
   double acc = 0.0;
+  if constexpr (kS2MaxEpl<T> == 4) {
+    if (g.epl == 4) {
+      s2_strip<T, ORDER, LZ, 4>(g, tx, ty, w, lane, src, dst, prv, j, s_cur, s_prev, bprev, &vrow[w][0][0],
+                                &trow[w][0][0], acc);
+      goto done;
+    }
+  }
   if (g.epl == 2)
     s2_strip<T, ORDER, LZ, 2>(g, tx, ty, w, lane, src, dst, prv, j, s_cur, s_prev, bprev, &vrow[w][0][0],
                               &trow[w][0][0], acc);
   else
     s2_strip<T, ORDER, LZ, 1>(g, tx, ty, w, lane, src, dst, prv, j, s_cur, s_prev, bprev, &vrow[w][0][0],
                               &trow[w][0][0], acc);
+done:
   if (LZ) {
     const double bs = block_sum<256>(acc, red);
     if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + blockIdx.x] = bs;
@@ -641,7 +657,7 @@ __global__ __launch_bounds__(256, GMRF_L2D_WAVES) void k_lanczos2d(StencilGeom g
   const size_t roff = S.col_off ? (size_t)S.col_off[r] : (size_t)r * xld;
   double acc_b = 0.0, acc_c = 0.0, acc_a = 0.0;
   const T* prv = MODE == 0 ? Xprev + roff : nullptr;
-  if (g.epl == 2)
+  if (g.fepl == 2)
     s2f_strip<T, ORDER, MODE, 2>(g, tx, ty, w, lane, X + roff, W + roff, prv, j, s_cur, s_prev, bprev, alpha,
                                  &vrow[w][0][0], &trow[w][0][0], &wrow[w][0][0], acc_b, acc_c, acc_a);
   else
@@ -699,15 +715,28 @@ __global__ __launch_bounds__(256) void k_csr(long n, const int64_t* __restrict__
 }
 
 // ---- host side --------------------------------------------------------------------------------
-void stencil_geom_tiles(StencilGeom& g, int dim, int order, int epl) {
+void stencil_geom_tiles(StencilGeom& g, int dim, int order, int epl, int vbytes) {
   int TZ, TY, TX;
   g.epl = 1;
-  if (dim == 2) g.epl = epl > 0 ? epl : (g.n2 % 2 == 0 ? 2 : 1);   // pairs need an even row length
+  // groups need a row length that is a multiple of the group: 4 for FP32, 2 for FP64.  A strip of 4-column
+  // lanes covers 256 - 8 columns, so short rows leave much of the last strip idle: FP32 takes groups of
+  // four only while its strips cover at most 15% more columns than those of pairs (measured: 2048 columns
+  // 30.4 -> 26.1 us, 1024 columns 16.0 -> 15.0 us with fours; 512 columns 17.3 -> 19.5 us, so pairs)
+  auto cover = [&](int e) {
+    const int ox = s2_out(order, e);
+    return (double)((g.n2 + ox - 1) / ox) * (kWave * e);
+  };
+  if (dim == 2) {
+    if (epl > 0) g.epl = epl;
+    else if (g.n2 % 2 != 0) g.epl = 1;
+    else g.epl = (vbytes == 4 && g.n2 % 4 == 0 && cover(4) <= 1.15 * cover(2)) ? 4 : 2;
+  }
+  g.fepl = g.epl < 2 ? g.epl : 2;
   if (dim == 1) { TZ = TileShape<1>::TZ; TY = TileShape<1>::TY; TX = TileShape<1>::TX; }
   else if (dim == 2) { TZ = 1; TY = kS2Waves * kS2Band; TX = s2_out(order, g.epl); }   // k_stencil2d
   else { TZ = TileShape<3>::TZ; TY = TileShape<3>::TY; TX = TileShape<3>::TX; }
   g.tiles_x = (g.n2 + TX - 1) / TX;
-  g.ftiles_x = dim == 2 ? (g.n2 + s2f_out(order, g.epl) - 1) / s2f_out(order, g.epl) : 0;   // k_lanczos2d
+  g.ftiles_x = dim == 2 ? (g.n2 + s2f_out(order, g.fepl) - 1) / s2f_out(order, g.fepl) : 0;   // k_lanczos2d
   g.tiles_y = (g.n1 + TY - 1) / TY;
   g.tiles_z = (g.n0 + TZ - 1) / TZ;
 }
