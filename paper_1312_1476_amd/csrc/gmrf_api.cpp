@@ -1550,7 +1550,7 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
       pbf.push_back(tiles);                    // the one-pass kernel's norm partials
       geom.push_back(gf);
       field.push_back(f);
-      tot += (Q->n + 1) & ~(int64_t)1;
+      tot += (Q->n + 3) & ~(int64_t)3;         // column starts 16-byte aligned for the 2D kernels' vector loads
       tot_ext += Q->n;
     }
   }

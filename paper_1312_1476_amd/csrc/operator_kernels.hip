@@ -426,7 +426,10 @@ done:
 // instead of 6 s E for an operator pass plus an update pass.  K w needs w around each output point, so
 // each strip forms w on a one-point halo: v is read with a halo of ORDER + 1 points.
 // MODE 1: the quadratic form of the input alone (slot 0 before iteration 1), into out_a.
-__host__ __device__ inline int s2f_halo(int order, int epl) { return epl == 2 ? (order == 2 ? 4 : 2) : order + 1; }
+// halo: w needs v one point beyond K w's output, K one more for order 2; group-aligned for EPL > 1
+__host__ __device__ inline int s2f_halo(int order, int epl) {
+  return epl == 4 ? 4 : (epl == 2 ? (order == 2 ? 4 : 2) : order + 1);
+}
 __host__ __device__ inline int s2f_out(int order, int epl) { return kWave * epl - 2 * s2f_halo(order, epl); }
 
 template <typename T, int ORDER, int MODE, int EPL>
@@ -437,7 +440,7 @@ __device__ __forceinline__ void s2f_strip(const StencilGeom& g, int tx, int ty, 
                                           double& acc_c, double& acc_a) {
   using VE = VecE<T, EPL>;
   using VT = typename VE::type;
-  constexpr int HX = EPL == 2 ? (ORDER == 2 ? 4 : 2) : ORDER + 1;
+  constexpr int HX = EPL == 4 ? 4 : (EPL == 2 ? (ORDER == 2 ? 4 : 2) : ORDER + 1);
   constexpr int OX = kWave * EPL - 2 * HX;
   constexpr int RW = kWave * EPL;
   constexpr int HV = ORDER + 1;                                 // rows of v above and below the band
@@ -512,8 +515,8 @@ __device__ __forceinline__ void s2f_strip(const StencilGeom& g, int tx, int ty, 
     if constexpr (EPL == 1) {
       vv = val[0];
     } else {
-      vv[0] = val[0];
-      vv[1] = val[1];
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) vv[e] = val[e];
     }
     *(VT*)(buf + par * RW + lane * EPL) = vv;
   };
@@ -578,8 +581,8 @@ __device__ __forceinline__ void s2f_strip(const StencilGeom& g, int tx, int ty, 
           if constexpr (EPL == 1) {
             vv = wn[0];
           } else {
-            vv[0] = wn[0];
-            vv[1] = wn[1];
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) vv[e] = wn[e];
           }
           *(VT*)(dst + (size_t)yw * n2 + xb) = vv;
 #pragma unroll
@@ -604,7 +607,7 @@ __device__ __forceinline__ void s2f_strip(const StencilGeom& g, int tx, int ty, 
       v1[e] = v2[e];
     }
   };
-  constexpr int AHEAD = S2Ahead<T>::value;
+  constexpr int AHEAD = EPL * sizeof(T) >= 16 ? GMRF_S2_AHEAD64 : S2Ahead<T>::value;
   VT qv[AHEAD], pv[AHEAD];
 #pragma unroll
   for (int d = 0; d < AHEAD; ++d) {
@@ -635,9 +638,9 @@ __global__ __launch_bounds__(256, GMRF_L2D_WAVES) void k_lanczos2d(StencilGeom g
                                                    int j, double* __restrict__ out_a, double* __restrict__ out_b,
                                                    double* __restrict__ out_c) {
   constexpr int NW = 256 / kWave;
-  __shared__ __align__(16) T vrow[kS2Waves][2][2 * kWave];
-  __shared__ __align__(16) T trow[kS2Waves][2][2 * kWave];
-  __shared__ __align__(16) T wrow[kS2Waves][2][2 * kWave];
+  __shared__ __align__(16) T vrow[kS2Waves][2][kS2MaxEpl<T> * kWave];
+  __shared__ __align__(16) T trow[kS2Waves][2][kS2MaxEpl<T> * kWave];
+  __shared__ __align__(16) T wrow[kS2Waves][2][kS2MaxEpl<T> * kWave];
   __shared__ double red[3 * NW];
   __shared__ int flag[1];
   const int r = blockIdx.y;
@@ -657,12 +660,20 @@ __global__ __launch_bounds__(256, GMRF_L2D_WAVES) void k_lanczos2d(StencilGeom g
   const size_t roff = S.col_off ? (size_t)S.col_off[r] : (size_t)r * xld;
   double acc_b = 0.0, acc_c = 0.0, acc_a = 0.0;
   const T* prv = MODE == 0 ? Xprev + roff : nullptr;
+  if constexpr (kS2MaxEpl<T> == 4) {
+    if (g.fepl == 4) {
+      s2f_strip<T, ORDER, MODE, 4>(g, tx, ty, w, lane, X + roff, W + roff, prv, j, s_cur, s_prev, bprev, alpha,
+                                   &vrow[w][0][0], &trow[w][0][0], &wrow[w][0][0], acc_b, acc_c, acc_a);
+      goto sums;
+    }
+  }
   if (g.fepl == 2)
     s2f_strip<T, ORDER, MODE, 2>(g, tx, ty, w, lane, X + roff, W + roff, prv, j, s_cur, s_prev, bprev, alpha,
                                  &vrow[w][0][0], &trow[w][0][0], &wrow[w][0][0], acc_b, acc_c, acc_a);
   else
     s2f_strip<T, ORDER, MODE, 1>(g, tx, ty, w, lane, X + roff, W + roff, prv, j, s_cur, s_prev, bprev, alpha,
                                  &vrow[w][0][0], &trow[w][0][0], &wrow[w][0][0], acc_b, acc_c, acc_a);
+sums:
   // block sums in fixed order
   const double sa = block_sum<256>(acc_a, red);
   if (MODE == 0) {
@@ -726,12 +737,20 @@ void stencil_geom_tiles(StencilGeom& g, int dim, int order, int epl, int vbytes)
     const int ox = s2_out(order, e);
     return (double)((g.n2 + ox - 1) / ox) * (kWave * e);
   };
+  // the one-pass kernel by the same rule with its own strip width
+  auto fcover = [&](int e) {
+    const int ox = s2f_out(order, e);
+    return (double)((g.n2 + ox - 1) / ox) * (kWave * e);
+  };
+  g.fepl = 1;
   if (dim == 2) {
     if (epl > 0) g.epl = epl;
     else if (g.n2 % 2 != 0) g.epl = 1;
     else g.epl = (vbytes == 4 && g.n2 % 4 == 0 && cover(4) <= 1.15 * cover(2)) ? 4 : 2;
+    if (epl > 0) g.fepl = epl;
+    else if (g.n2 % 2 != 0) g.fepl = 1;
+    else g.fepl = (vbytes == 4 && g.n2 % 4 == 0 && fcover(4) <= 1.15 * fcover(2)) ? 4 : 2;
   }
-  g.fepl = g.epl < 2 ? g.epl : 2;
   if (dim == 1) { TZ = TileShape<1>::TZ; TY = TileShape<1>::TY; TX = TileShape<1>::TX; }
   else if (dim == 2) { TZ = 1; TY = kS2Waves * kS2Band; TX = s2_out(order, g.epl); }   // k_stencil2d
   else { TZ = TileShape<3>::TZ; TY = TileShape<3>::TY; TX = TileShape<3>::TX; }
