@@ -31,8 +31,10 @@ __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 // nf sequences of length N in LDS: element e of sequence f at buf[f * fs + e * es].
 // INTER: items enumerate f fastest (interleaved sequences, es = nf, fs = 1), else e fastest.
 // EARLY_TW: each stage requests its twiddles together with its LDS reads, before the barrier, so
-// that a twiddle table in global memory costs one latency per stage instead of two.
-template <typename T, bool INTER, bool EARLY_TW = false>
+// that a twiddle table in global memory costs one latency per stage instead of two.  NT threads; a
+// block of NT < kFftThreads threads transforms at most 4 MAXIT NT points (a proportionally smaller
+// buffer).
+template <typename T, bool INTER, bool EARLY_TW = false, int NT = kFftThreads>
 __device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* __restrict__ tw, bool inv) {
   constexpr int MAXIT = FftCfg<T>::MAXIT;
   const int logN = ilog2(N);
@@ -44,7 +46,7 @@ __device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* 
     C2<T> wv[EARLY_TW ? MAXIT : 1][3];
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
-      const int item = threadIdx.x + it * kFftThreads;
+      const int item = threadIdx.x + it * NT;
       if (item < items) {
         const int f = INTER ? item % nf : item / n4;
         const int j = INTER ? item / nf : item % n4;
@@ -61,7 +63,7 @@ __device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* 
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
-      const int item = threadIdx.x + it * kFftThreads;
+      const int item = threadIdx.x + it * NT;
       if (item < items) {
         const int f = INTER ? item % nf : item / n4;
         const int j = INTER ? item / nf : item % n4;
@@ -99,7 +101,7 @@ __device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* 
     C2<T> wv[EARLY_TW ? 2 * MAXIT : 1];
 #pragma unroll
     for (int it = 0; it < 2 * MAXIT; ++it) {
-      const int item = threadIdx.x + it * kFftThreads;
+      const int item = threadIdx.x + it * NT;
       if (item < items) {
         const int f = INTER ? item % nf : item / n2;
         const int j = INTER ? item / nf : item % n2;
@@ -111,7 +113,7 @@ __device__ void lds_fft(C2<T>* buf, int N, int nf, int fs, int es, const C2<T>* 
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < 2 * MAXIT; ++it) {
-      const int item = threadIdx.x + it * kFftThreads;
+      const int item = threadIdx.x + it * NT;
       if (item < items) {
         const int f = INTER ? item % nf : item / n2;
         const int j = INTER ? item / nf : item % n2;
@@ -143,17 +145,17 @@ __device__ __forceinline__ int xcd_col_block(int b, int nb) {
 // Multiply the LDS tile (columns c0.., row-major [k1][c]) by lambda^{-1/2} * scale.  Column 0 holds
 // X[k1, 0] + i X[k1, N2/2]: with m0 = mult(k1, 0), mN = mult(k1, N2/2) and k1' = -k1 mod N1,
 //   S'[k1] = (m0 + mN)/2 S[k1] + (m0 - mN)/2 conj(S[k1']).
-template <typename T>
+template <typename T, int NT = kFftThreads>
 __device__ void apply_mult(C2<T>* buf, int nf, int c0, int N1, int H, const T* __restrict__ mult, T scale) {
   __syncthreads();
-  for (int idx = threadIdx.x; idx < nf * N1; idx += kFftThreads) {
+  for (int idx = threadIdx.x; idx < nf * N1; idx += NT) {
     const int k1 = idx / nf, c = idx % nf, cg = c0 + c;
     if (cg == 0) continue;
     const T m = mult[(size_t)k1 * mult_stride(H) + cg] * scale;
     buf[idx] = {buf[idx].x * m, buf[idx].y * m};
   }
   if (c0 == 0) {
-    for (int k1 = threadIdx.x; k1 <= N1 / 2; k1 += kFftThreads) {
+    for (int k1 = threadIdx.x; k1 <= N1 / 2; k1 += NT) {
       const int kb = (N1 - k1) & (N1 - 1);
       const T m0 = mult[(size_t)k1 * mult_stride(H)] * scale, mN = mult[(size_t)k1 * mult_stride(H) + H] * scale;
       const T p = (m0 + mN) * (T)0.5, q = (m0 - mN) * (T)0.5;

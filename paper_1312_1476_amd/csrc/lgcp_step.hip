@@ -28,33 +28,51 @@ namespace gmrf {
 // (FP32 column pass 59 -> 84 us).
 template <typename T> constexpr bool kRowsEarlyTw = sizeof(T) == 8;
 
+// Threads per block of each pass: 512 (half the LDS of a 1024-thread block, four blocks per CU, so their
+// load, transform and store phases overlap more than two large blocks do) when the pass's tile still fits:
+// a row for the row pass, at least four columns (64 bytes of each row) for the column pass; else 1024.
+// Measured at 512^2 x 32 FP64: row pass 76.2 -> 66.8 us, column pass 127.8 -> 116.9 us; at 2048^2 the
+// one-column tiles of small column blocks were slower (711 -> 809 us), so that pass stays large there.
+#ifndef GMRF_LGCP_SMALL
+#define GMRF_LGCP_SMALL 1
+#endif
+template <typename T>
+static int lgcp_rows_nt(const FftPlan& p) {
+  return (GMRF_LGCP_SMALL && p.N2 <= FftCfg<T>::ELEMS / 2) ? kFftThreads / 2 : kFftThreads;
+}
+template <typename T>
+static int lgcp_cols_nt(const FftPlan& p) {
+  return (GMRF_LGCP_SMALL && 4 * p.N1 <= FftCfg<T>::ELEMS / 2) ? kFftThreads / 2 : kFftThreads;
+}
 template <typename T>
 static int lgcp_row_np(const FftPlan& p) {
-  return std::min(p.N1 / 2, FftCfg<T>::ELEMS / p.N2);
+  const int elems = FftCfg<T>::ELEMS / (kFftThreads / lgcp_rows_nt<T>(p));
+  return std::min(p.N1 / 2, elems / p.N2);
 }
 template <typename T>
 static int lgcp_col_nf(const FftPlan& p) {
-  return std::min(p.H, FftCfg<T>::ELEMS / p.N1);
+  const int elems = FftCfg<T>::ELEMS / (kFftThreads / lgcp_cols_nt<T>(p));
+  return std::min(p.H, elems / p.N1);
 }
 
 // ---- row pass ------------------------------------------------------------------------------------------
 // Grid (N1 / (2 np), k): np row pairs of field r per block.  Partial sums of y^T H y go to
 // part_a[r][blockIdx.x]; the opener block also stores <w_{j-1}, v_{j-1}> (the column pass's part_c
 // partials, Pc of them; 0 when use_c = 0 or j = 1) at part_a[r][gridDim.x].
-template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_lgcp_rows(const C2<T>* __restrict__ T1, C2<T>* __restrict__ T2,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_lgcp_rows(const C2<T>* __restrict__ T1, C2<T>* __restrict__ T2,
                                                            const T* __restrict__ d, int N1, int N2, int np,
                                                            const C2<T>* __restrict__ tw, LzState S, int j,
                                                            int use_c, int Pc, double inv_sqrt_n) {
-  __shared__ C2<T> buf[FftCfg<T>::ELEMS];
-  __shared__ double red[kFftThreads / kWave];
+  __shared__ C2<T> buf[FftCfg<T>::ELEMS * NT / kFftThreads];
+  __shared__ double red[NT / kWave];
   __shared__ int flag;
   const int r = blockIdx.y;
   const bool writer = blockIdx.x == 0;
   double s_cur, s_prev, bprev;
-  if (!lz_open<kFftThreads>(S, r, j, writer, red, &flag, s_cur, s_prev, bprev)) return;
+  if (!lz_open<NT>(S, r, j, writer, red, &flag, s_cur, s_prev, bprev)) return;
   if (writer) {
-    const double c = (use_c && j > 1) ? sum_partials<kFftThreads>(S.part_c + (size_t)r * S.pstride, Pc, red) : 0.0;
+    const double c = (use_c && j > 1) ? sum_partials<NT>(S.part_c + (size_t)r * S.pstride, Pc, red) : 0.0;
     if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + gridDim.x] = c;
   }
   const int H = N2 / 2;
@@ -62,7 +80,7 @@ __global__ __launch_bounds__(kFftThreads) void k_lgcp_rows(const C2<T>* __restri
   const size_t fsz = (size_t)N1 * H;
   const C2<T>* src = T1 + (size_t)r * fsz;
   // packed rows (A + i B of rows 2p, 2p+1) -> full-length sequence A + i B
-  for (int idx = threadIdx.x; idx < np * N2; idx += kFftThreads) {
+  for (int idx = threadIdx.x; idx < np * N2; idx += NT) {
     const int p = idx / N2, k = idx % N2;
     const C2<T>* PA = src + (size_t)(row0 + 2 * p) * H;
     const C2<T>* PB = PA + H;
@@ -83,11 +101,11 @@ __global__ __launch_bounds__(kFftThreads) void k_lgcp_rows(const C2<T>* __restri
     buf[p * N2 + k] = {a.x - b.y, a.y + b.x};
   }
   __syncthreads();
-  lds_fft<T, false, kRowsEarlyTw<T>>(buf, N2, np, N2, 1, tw, true);
+  lds_fft<T, false, kRowsEarlyTw<T>, NT>(buf, N2, np, N2, 1, tw, true);
   // y = (1 / (beta_{j-1} sqrt n)) * (real rows), u = H y, partial y^T H y
   const T sc = (T)(s_cur * inv_sqrt_n);
   double acc = 0.0;
-  for (int idx = threadIdx.x; idx < np * N2; idx += kFftThreads) {
+  for (int idx = threadIdx.x; idx < np * N2; idx += NT) {
     const int p = idx / N2, t = idx % N2;
     const size_t ra = (size_t)(row0 + 2 * p) * N2;
     const C2<T> z = buf[idx];
@@ -97,10 +115,10 @@ __global__ __launch_bounds__(kFftThreads) void k_lgcp_rows(const C2<T>* __restri
     buf[idx] = {ua, ub};
   }
   __syncthreads();
-  lds_fft<T, false, kRowsEarlyTw<T>>(buf, N2, np, N2, 1, tw, false);
+  lds_fft<T, false, kRowsEarlyTw<T>, NT>(buf, N2, np, N2, 1, tw, false);
   // unpack the two half spectra of rows 2p, 2p+1 into packed rows of T2
   C2<T>* dst = T2 + (size_t)r * fsz;
-  for (int idx = threadIdx.x; idx < np * H; idx += kFftThreads) {
+  for (int idx = threadIdx.x; idx < np * H; idx += NT) {
     const int p = idx / H, c = idx % H;
     const C2<T>* Z = buf + p * N2;
     C2<T> pa, pb;
@@ -116,7 +134,7 @@ __global__ __launch_bounds__(kFftThreads) void k_lgcp_rows(const C2<T>* __restri
     dst[(size_t)(row0 + 2 * p) * H + c] = pa;
     dst[(size_t)(row0 + 2 * p + 1) * H + c] = pb;
   }
-  const double tot = block_sum<kFftThreads>(acc, red);
+  const double tot = block_sum<NT>(acc, red);
   if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + blockIdx.x] = tot;
 }
 
@@ -124,14 +142,14 @@ __global__ __launch_bounds__(kFftThreads) void k_lgcp_rows(const C2<T>* __restri
 // MODE 0: T1 <- column-inverse transform of Lambda^{-1/2} X (X = slot 0, or a reorthogonalised w_j).
 // MODE 1: the column pass of step j (X = T2, Vj = slot j-1, Vp = slot j-2, W = slot j).
 // Grid (H / nf, k): nf packed columns of field r per block, all N1 rows.
-template <typename T, int MODE>
-__global__ __launch_bounds__(kFftThreads) void k_lgcp_cols(const C2<T>* __restrict__ X, const C2<T>* __restrict__ Vj,
+template <typename T, int MODE, int NT>
+__global__ __launch_bounds__(NT) void k_lgcp_cols(const C2<T>* __restrict__ X, const C2<T>* __restrict__ Vj,
                                                            const C2<T>* __restrict__ Vp, C2<T>* __restrict__ W,
                                                            C2<T>* __restrict__ T1, int N1, int H, int nf,
                                                            const C2<T>* __restrict__ tw, const T* __restrict__ mult,
                                                            LzState S, int j, int Pr, double inv_sqrt_n) {
-  __shared__ C2<T> buf[FftCfg<T>::ELEMS];
-  __shared__ double red[kFftThreads / kWave];
+  __shared__ C2<T> buf[FftCfg<T>::ELEMS * NT / kFftThreads];
+  __shared__ double red[NT / kWave];
   __shared__ double sh[4];
   __shared__ int flag;
   const int r = blockIdx.y;
@@ -141,7 +159,7 @@ __global__ __launch_bounds__(kFftThreads) void k_lgcp_cols(const C2<T>* __restri
   double alpha = 0.0, s_cur = 0.0, s_prev = 0.0, bprev = 0.0;
   if (MODE == 1) {
     if (!block_active(S, r, &flag)) return;
-    const double yhy = sum_partials<kFftThreads>(S.part_a + (size_t)r * S.pstride, Pr, red);
+    const double yhy = sum_partials<NT>(S.part_a + (size_t)r * S.pstride, Pr, red);
     if (threadIdx.x == 0) {
       const double a = 1.0 + yhy - S.part_a[(size_t)r * S.pstride + Pr];
       sh[0] = a;
@@ -155,17 +173,17 @@ __global__ __launch_bounds__(kFftThreads) void k_lgcp_cols(const C2<T>* __restri
     s_prev = j > 1 ? 1.0 / sh[2] : 0.0;
     bprev = j > 1 ? sh[1] : 0.0;
   }
-  for (int idx = threadIdx.x; idx < nf * N1; idx += kFftThreads) {
+  for (int idx = threadIdx.x; idx < nf * N1; idx += NT) {
     const int k1 = idx / nf, c = idx % nf;
     buf[idx] = X[foff + (size_t)k1 * H + c0 + c];
   }
   if (MODE == 1) {
     __syncthreads();
-    lds_fft<T, true>(buf, N1, nf, 1, nf, tw, false);
-    apply_mult(buf, nf, c0, N1, H, mult, (T)inv_sqrt_n);
+    lds_fft<T, true, false, NT>(buf, N1, nf, 1, nf, tw, false);
+    apply_mult<T, NT>(buf, nf, c0, N1, H, mult, (T)inv_sqrt_n);
     const T sc = (T)s_cur, sp = (T)s_prev, al = (T)alpha, bp = (T)bprev;
     double nb = 0.0, nc = 0.0;
-    for (int idx = threadIdx.x; idx < nf * N1; idx += kFftThreads) {
+    for (int idx = threadIdx.x; idx < nf * N1; idx += NT) {
       const int k1 = idx / nf, c = idx % nf;
       const size_t g = foff + (size_t)k1 * H + c0 + c;
       const C2<T> xv = Vj[g];
@@ -183,16 +201,16 @@ __global__ __launch_bounds__(kFftThreads) void k_lgcp_cols(const C2<T>* __restri
       W[g] = w;
       buf[idx] = w;
     }
-    const double sb = block_sum<kFftThreads>(nb, red);
-    const double scc = block_sum<kFftThreads>(nc, red);
+    const double sb = block_sum<NT>(nb, red);
+    const double scc = block_sum<NT>(nc, red);
     if (threadIdx.x == 0) {
       S.part_b[(size_t)r * S.pstride + blockIdx.x] = sb;
       S.part_c[(size_t)r * S.pstride + blockIdx.x] = scc;
     }
   }
-  apply_mult(buf, nf, c0, N1, H, mult, (T)1);
-  lds_fft<T, true>(buf, N1, nf, 1, nf, tw, true);
-  for (int idx = threadIdx.x; idx < nf * N1; idx += kFftThreads) {
+  apply_mult<T, NT>(buf, nf, c0, N1, H, mult, (T)1);
+  lds_fft<T, true, false, NT>(buf, N1, nf, 1, nf, tw, true);
+  for (int idx = threadIdx.x; idx < nf * N1; idx += NT) {
     const int k1 = idx / nf, c = idx % nf;
     T1[foff + (size_t)k1 * H + c0 + c] = buf[idx];
   }
@@ -231,8 +249,14 @@ template <typename T>
 void lgcp_col_init(const FftPlan& p, const void* mult, const T* X, T* T1, int k, hipStream_t st) {
   const int nf = lgcp_col_nf<T>(p);
   LzState S{};
-  hipLaunchKernelGGL((k_lgcp_cols<T, 0>), dim3(p.H / nf, k), dim3(kFftThreads), 0, st, (const C2<T>*)X, nullptr,
-                     nullptr, nullptr, (C2<T>*)T1, p.N1, p.H, nf, twid1<T>(p), (const T*)mult, S, 0, 0, 0.0);
+  if (lgcp_cols_nt<T>(p) == kFftThreads)
+    hipLaunchKernelGGL((k_lgcp_cols<T, 0, kFftThreads>), dim3(p.H / nf, k), dim3(kFftThreads), 0, st,
+                       (const C2<T>*)X, nullptr, nullptr, nullptr, (C2<T>*)T1, p.N1, p.H, nf, twid1<T>(p),
+                       (const T*)mult, S, 0, 0, 0.0);
+  else
+    hipLaunchKernelGGL((k_lgcp_cols<T, 0, kFftThreads / 2>), dim3(p.H / nf, k), dim3(kFftThreads / 2), 0, st,
+                       (const C2<T>*)X, nullptr, nullptr, nullptr, (C2<T>*)T1, p.N1, p.H, nf, twid1<T>(p),
+                       (const T*)mult, S, 0, 0, 0.0);
 }
 
 template <typename T>
@@ -242,14 +266,23 @@ void lgcp_lanczos_step(const FftPlan& p, const void* mult, const T* d, T* T1, T*
   const LgcpCounts c = lgcp_counts(p, sizeof(T) == 8 ? GMRF_F64 : GMRF_F32);
   if (only != 2) {
     const int np = lgcp_row_np<T>(p);
-    hipLaunchKernelGGL((k_lgcp_rows<T>), dim3(c.Pr, k), dim3(kFftThreads), 0, st, (const C2<T>*)T1, (C2<T>*)T2, d,
-                       p.N1, p.N2, np, twid2<T>(p), S, j, use_c, c.Pc, inv_sqrt_n);
+    if (lgcp_rows_nt<T>(p) == kFftThreads)
+      hipLaunchKernelGGL((k_lgcp_rows<T, kFftThreads>), dim3(c.Pr, k), dim3(kFftThreads), 0, st, (const C2<T>*)T1,
+                         (C2<T>*)T2, d, p.N1, p.N2, np, twid2<T>(p), S, j, use_c, c.Pc, inv_sqrt_n);
+    else
+      hipLaunchKernelGGL((k_lgcp_rows<T, kFftThreads / 2>), dim3(c.Pr, k), dim3(kFftThreads / 2), 0, st,
+                         (const C2<T>*)T1, (C2<T>*)T2, d, p.N1, p.N2, np, twid2<T>(p), S, j, use_c, c.Pc, inv_sqrt_n);
   }
   if (only != 1) {
     const int nf = lgcp_col_nf<T>(p);
-    hipLaunchKernelGGL((k_lgcp_cols<T, 1>), dim3(c.Pc, k), dim3(kFftThreads), 0, st, (const C2<T>*)T2,
-                       (const C2<T>*)Xj, (const C2<T>*)Xprev, (C2<T>*)W, (C2<T>*)T1, p.N1, p.H, nf, twid1<T>(p),
-                       (const T*)mult, S, j, c.Pr, inv_sqrt_n);
+    if (lgcp_cols_nt<T>(p) == kFftThreads)
+      hipLaunchKernelGGL((k_lgcp_cols<T, 1, kFftThreads>), dim3(c.Pc, k), dim3(kFftThreads), 0, st, (const C2<T>*)T2,
+                         (const C2<T>*)Xj, (const C2<T>*)Xprev, (C2<T>*)W, (C2<T>*)T1, p.N1, p.H, nf, twid1<T>(p),
+                         (const T*)mult, S, j, c.Pr, inv_sqrt_n);
+    else
+      hipLaunchKernelGGL((k_lgcp_cols<T, 1, kFftThreads / 2>), dim3(c.Pc, k), dim3(kFftThreads / 2), 0, st,
+                         (const C2<T>*)T2, (const C2<T>*)Xj, (const C2<T>*)Xprev, (C2<T>*)W, (C2<T>*)T1, p.N1, p.H,
+                         nf, twid1<T>(p), (const T*)mult, S, j, c.Pr, inv_sqrt_n);
   }
 }
 
