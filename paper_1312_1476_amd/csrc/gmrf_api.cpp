@@ -800,7 +800,7 @@ void iterate_all(std::vector<Run<T>>& Rs, int j, const std::vector<char>& live) 
 // Runs iterations of all groups (each on its own stream) until every column stopped or m_max, then closes
 // the columns that hit m_max.  Groups whose columns all stopped launch no more.
 template <typename T>
-gmrf_status run_loop(std::vector<Run<T>>& Rs) {
+gmrf_status run_loop(std::vector<Run<T>>& Rs, const std::function<gmrf_status(int)>& on_done = nullptr) {
   int ktot = 0;
   for (auto& R : Rs) ktot += R.k;
   int* pb = poll_buffer(ktot);
@@ -826,6 +826,14 @@ gmrf_status run_loop(std::vector<Run<T>>& Rs) {
           bool a = false;
           for (int r = 0; r < Rs[g].k; ++r) a |= pb[off + r] != 0;
           live[g] = a;
+          if (!a) {
+            // every column of this group has stopped: its closing work can overlap the other groups' steps
+            launch_finalize(Rs[g].S, Rs[g].st);
+            if (on_done) {
+              gmrf_status e = on_done((int)g);
+              if (e != GMRF_OK) return e;
+            }
+          }
         }
         any |= live[g] != 0;
         off += Rs[g].k;
@@ -834,7 +842,14 @@ gmrf_status run_loop(std::vector<Run<T>>& Rs) {
       poll = std::min(poll * 2, 32);
     }
   }
-  for (auto& R : Rs) launch_finalize(R.S, R.st);
+  for (size_t g = 0; g < Rs.size(); ++g) {
+    if (!live[g]) continue;   // closed above
+    launch_finalize(Rs[g].S, Rs[g].st);
+    if (on_done) {
+      gmrf_status e = on_done((int)g);
+      if (e != GMRF_OK) return e;
+    }
+  }
   HIP_TRY(hipGetLastError());
   return GMRF_OK;
 }
@@ -960,9 +975,8 @@ static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, dou
     if (solve) init_for_solve<T>(R, Z + (size_t)c0[g] * Q->n);
     else init_from_z<T>(R, Z + (size_t)c0[g] * Q->n);
   }
-  if ((s = run_loop<T>(Rs)) != GMRF_OK) return s;
-  // y = T_m^{-1/2} e_1 (or T_m^{-1} e_1), then x_m = ||z|| V_m y
-  for (int g = 0; g < G; ++g) {
+  // y = T_m^{-1/2} e_1 (or T_m^{-1} e_1), then x_m = ||z|| V_m y, enqueued as soon as the group's columns stop
+  auto close_group = [&](int g) -> gmrf_status {
     Run<T>& R = Rs[g];
     double* scr;
     if ((s = ws[g]->alloc((size_t)R.k * m_max, &ys[g])) != GMRF_OK) return s;
@@ -985,7 +999,9 @@ static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, dou
     } else {
       launch_combine<T, double>(R.V, R.z.L, ys[g], m_max, Xg, Q->n, R.S, R.st);
     }
-  }
+    return GMRF_OK;
+  };
+  if ((s = run_loop<T>(Rs, close_group)) != GMRF_OK) return s;
   HIP_TRY(hipGetLastError());
   // results to host
   std::vector<int> mu(k), stt(k);
