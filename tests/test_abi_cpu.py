@@ -47,6 +47,14 @@ def test_errors_without_device_or_with_bad_args():
     assert L.gmrf_op_create_lattice(2, shape, 1, 0.1, -1.0, 0, 0, C.byref(h)) == abi.GMRF_EINVAL
     assert b"order" in L.gmrf_last_error() or b"tau" in L.gmrf_last_error()
     assert L.gmrf_sample(None, None, 1, 1e-8, 10, 0, None, None, None) == abi.GMRF_EINVAL
+    # NULL handles of the later entry points: refused before any device call
+    assert L.gmrf_solve(None, None, 1, 1e-8, 10, 0, None, None, None) == abi.GMRF_EINVAL
+    assert L.gmrf_sample_two_pass(None, None, 1, 1e-8, 10, None, None, None) == abi.GMRF_EINVAL
+    assert L.gmrf_op_set_diagonal(None, None) == abi.GMRF_EINVAL
+    assert L.gmrf_op_set_ichol_precond(None, 1, -1.0, None) == abi.GMRF_EINVAL
+    assert L.gmrf_ichol_info(None, None, None, None) == abi.GMRF_EINVAL
+    assert L.gmrf_logdet_coloured(None, 2, 10, 0, None, 1, None, None, None, None) == abi.GMRF_EINVAL
+    assert L.gmrf_distance_colouring(None, 1, None, None) == abi.GMRF_EINVAL
     assert L.gmrf_strerror(abi.GMRF_ENOTSPD).startswith(b"operator is not")
     import torch
     if not torch.cuda.is_available():
