@@ -52,11 +52,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
-    ap.add_argument("--only", default="", help="profiling: run only this leg (headline|counters|lgcp|logdet|ichol)")
+    ap.add_argument("--only", default="", help="profiling: run only this leg (headline|counters|lgcp|logdet|ichol|plain|uneven)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-lgcp", action="store_true", help="skip the log-Gaussian Cox process leg")
     ap.add_argument("--no-logdet", action="store_true", help="skip the log-determinant leg")
     ap.add_argument("--no-ichol", action="store_true", help="skip the incomplete-Cholesky leg")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain 64x64 and uneven-batch legs")
     ap.add_argument("--kernel", default="", help="counters leg: kernel to run (default: the dominant one)")
     ap.add_argument("--storage", default="f64", help="counters leg: storage dtype (f64|f32)")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="arrival window per serving rate")
@@ -113,6 +114,12 @@ def main():
         return
     if args.only == "ichol":
         print(json.dumps({"ichol": ichol_leg(gm, torch)}))
+        return
+    if args.only == "plain":
+        print(json.dumps({"plain_64x64": plain_leg(gm, torch)}))
+        return
+    if args.only == "uneven":
+        print(json.dumps({"uneven_batch": uneven_leg(gm, torch)}))
         return
 
     # ---- headline: FP64 storage, stop at rho <= 1e-5 ---------------------------------------------
@@ -226,6 +233,11 @@ def main():
     # ---- incomplete-Cholesky preconditioning (Section 5.2, Figure 3) ------------------------------------
     if not args.no_ichol:
         result["ichol"] = ichol_leg(gm, torch)
+
+    # ---- plain FP64 single sample (64 x 64) and the uneven batch of 256 fields ---------------------------
+    if not args.no_plain:
+        result["plain_64x64"] = plain_leg(gm, torch)
+        result["uneven_batch"] = uneven_leg(gm, torch)
 
     # ---- serving: Poisson request stream over a pool of 64 resident operators ---------------------------
     if not args.no_serve:
@@ -384,6 +396,62 @@ def ichol_leg(gm, torch):
         rec["batch32_ms"] = round(1000 * (time.perf_counter() - t0), 2)
         rec["batch32_m_max"] = max(i["m_used"] for i in ib)
         out["variants"]["none" if dt is None else ("ic0" if dt < 0 else f"{dt:g}")] = rec
+        op.close()
+    return out
+
+
+def plain_leg(gm, torch, reps=20):
+    """Plain FP64 Lanczos, one sample (workload C0): 64 x 64 first-order lattice, kappa2 = 0.1, free
+    boundary, full reorthogonalisation (CGS2), m_max = 200, stop at rho <= 1e-8.  Launch-bound at this
+    size (n = 4096): the time is the latency of one request."""
+    c = workloads.C0
+    sp = c.lattice
+    op = gm.Operator.lattice(sp.shape, sp.order, sp.kappa2, sp.tau, sp.boundary, "f64")
+    Z = torch.from_numpy(np.ascontiguousarray(workloads.gaussian_block(sp.n, 1, 0, 0).T)).to("cuda:0")
+    op.sample(Z, tol=c.tol, m_max=c.m_max, reorth=c.reorth)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        X, info = op.sample(Z, tol=c.tol, m_max=c.m_max, reorth=c.reorth)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    out = {"samples_per_s": round(1.0 / dt, 2), "ms_per_sample": round(1000 * dt, 3), "m_used": info[0]["m_used"],
+           "rho": info[0]["rel_residual"], "status": info[0]["status"], "reorth": "CGS2"}
+    op.close()
+    return out
+
+
+UNEVEN_TOL, UNEVEN_M_MAX = 1e-5, 400
+
+
+def uneven_leg(gm, torch):
+    """Uneven batch (workload C2): 256 first-order fields, side uniform in 32..256, kappa2 log-uniform
+    in [1e-3, 1], 8 right-hand sides each, FP32 storage (FP64 scalars), all fields in one set of
+    launches per Lanczos step; against the same fields sampled one call each."""
+    fields = workloads.uneven_fields()
+    ops = [gm.Operator.lattice((s, s), 1, k2, 1.0, "free", "f32") for s, k2 in fields]
+    Zs = [torch.from_numpy(np.ascontiguousarray(workloads.uneven_field_rhs(f, s).T)).to("cuda:0")
+          for f, (s, _) in enumerate(fields)]
+    ncol = sum(int(Z.shape[0]) for Z in Zs)
+    gm.sample_batch(ops, Zs, tol=UNEVEN_TOL, m_max=UNEVEN_M_MAX)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Xs, info = gm.sample_batch(ops, Zs, tol=UNEVEN_TOL, m_max=UNEVEN_M_MAX)
+    torch.cuda.synchronize()
+    dtb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for op, Z in zip(ops, Zs):
+        op.sample(Z, tol=UNEVEN_TOL, m_max=UNEVEN_M_MAX)
+    torch.cuda.synchronize()
+    dts = time.perf_counter() - t0
+    ms = [i["m_used"] for i in info]
+    out = {"fields": len(fields), "columns": ncol, "unknowns": int(sum(s * s for s, _ in fields)), "storage": "f32",
+           "tol_rho": UNEVEN_TOL, "m_max": UNEVEN_M_MAX, "m_used_min": min(ms), "m_used_max": max(ms),
+           "not_converged": sum(i["status"] != "OK" for i in info),
+           "batched_samples_per_s": round(ncol / dtb, 1), "batched_s": round(dtb, 3),
+           "one_call_per_field_samples_per_s": round(ncol / dts, 1), "one_call_per_field_s": round(dts, 3),
+           "batch_speedup": round(dts / dtb, 2)}
+    for op in ops:
         op.close()
     return out
 
