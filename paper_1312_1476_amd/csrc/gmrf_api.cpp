@@ -521,21 +521,21 @@ Sizes sizes_for(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3) 
   if (lgcp_path(Q)) {
     const LgcpCounts c = lgcp_counts(Q->plan, Q->storage);
     z.Pa = c.Pr + 1;                              // y^T H y per row block, <w_{j-1}, v_{j-1}>
-    z.Pb = reorth ? ew_blocks(z.L) : c.Pc;
+    z.Pb = reorth ? reorth_blocks(z.L) : c.Pc;
     z.pstride = std::max(std::max(z.Pa, z.Pb), std::max(z.Pb_first, c.Pc));
   } else if (Q->precond) {
     const PrecondStepCounts c = precond_step_counts(Q->plan);
     z.Pa = c.Pband + 1;                           // <u, D u> per band block, <w_{j-1}, v_{j-1}>
-    z.Pb = reorth ? ew_blocks(z.L) : c.Ps;        // the reorthogonalisation rewrites the norm partials
+    z.Pb = reorth ? reorth_blocks(z.L) : c.Ps;    // the reorthogonalisation rewrites the norm partials
   } else if (fused_path(Q, reorth)) {
     z.Pa = lanczos2d_blocks(Q->geom);             // the one-pass kernel's partial sums
     z.Pb = z.Pa;
   } else if (Q->ic) {
     z.Pa = ew_blocks(z.L);                        // the opener's v_j^T q partials (elementwise tiling)
-    z.Pb = ew_blocks(z.L);
+    z.Pb = reorth ? reorth_blocks(z.L) : ew_blocks(z.L);
   } else {
     z.Pa = Q->kind == 0 ? stencil_blocks(Q->geom) : csr_blocks((long)Q->n);
-    z.Pb = ew_blocks(z.L);
+    z.Pb = reorth ? reorth_blocks(z.L) : ew_blocks(z.L);
   }
   z.pstride = std::max(std::max(std::max(z.Pa, z.Pb), z.Pb_first), z.pstride);
   if (Q->precond && !lgcp_path(Q)) z.pstride = std::max(z.pstride, precond_step_counts(Q->plan).Ps);   // step kernel

@@ -21,6 +21,8 @@ template <typename T> void launch_update(const T* Qb, const T* Vj, T* W, long L,
 void launch_hutchinson_aggregate(const double* g, const double* beta, int ldb, int np, int K, double shift, double* out, hipStream_t st);
 void launch_finalize(const LzState& S, hipStream_t st);
 template <typename T> void launch_norm_partials(const T* V0, long L, const LzState& S, hipStream_t st);
+// norm partials per column the reorthogonalisation's last pass writes (vectors of L elements)
+int reorth_blocks(long L);
 template <typename T> void launch_reorth(T* V, long L, int j, double* part_h, double* h, int hstride, const LzState& S, hipStream_t st);
 // out (+)= beta_0 y_t v_{t+1} from slot t (t = 0 writes); S: the state of the pass that produced y
 template <typename T, typename OutT> void launch_accumulate(const T* Vt, long L, const double* y, int ldy, const LzState& S, int t, OutT* out, long old, hipStream_t st);

@@ -2,6 +2,8 @@
 // reorthogonalisation, the final combination x_m = ||z|| V_m y and the Rademacher probes
 // of the Hutchinson estimator (Section 6).  All memory-bound: coalesced strided loops, FP64
 // arithmetic on values loaded from the storage type T, deterministic partial sums.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace gmrf {
@@ -194,10 +196,13 @@ __global__ __launch_bounds__(256) void k_finalize(LzState S) {
 // pass: h_t = v_{t+1}^T w for t < j (partials per block), then w -= sum_t h_t v_{t+1}.
 // Dot kernel: the block's chunk of w is staged in LDS; wave g takes basis vectors
 // t = g, g + NW, ... and reduces each with wave shuffles only.
+// grid.z splits t < j into slices of tslice vectors (short vectors: the dot of every basis vector in
+// flight at once instead of a chain of j / NW per wave); each h_t is still formed by one wave alone, so
+// the result does not depend on the split.
 template <typename T>
 __global__ __launch_bounds__(kEwThreads) void k_reorth_dot(const T* __restrict__ V, long L, int j,
                                                            double* __restrict__ part_h, int hstride,
-                                                           LzState S) {
+                                                           int tslice, LzState S) {
   __shared__ double wl[kEwChunk];
   __shared__ int flag[1];
   const int r = blockIdx.y;
@@ -212,7 +217,8 @@ __global__ __launch_bounds__(kEwThreads) void k_reorth_dot(const T* __restrict__
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1), g = threadIdx.x / kWave;
   constexpr int NW = kEwThreads / kWave;
-  for (int t = g; t < j; t += NW) {
+  const int t1 = min(j, (int)(blockIdx.z + 1) * tslice);
+  for (int t = (int)blockIdx.z * tslice + g; t < t1; t += NW) {
     const T* vt = V + (size_t)t * vs + (size_t)r * L;
     const double sc = 1.0 / S.beta[lz_ib(S, r, t)];
     double acc = 0.0;
@@ -282,6 +288,62 @@ __global__ __launch_bounds__(kEwThreads) void k_reorth_update(T* __restrict__ V,
   }
   if (with_norm) {
     const double s = block_sum<kEwThreads>(nrm, lds);
+    if (threadIdx.x == 0) S.part_b[(size_t)r * S.pstride + blockIdx.x] = s;
+  }
+}
+
+// Short vectors (L <= kRoSmallL): w -= sum_t h_t v_{t+1} with the t sum split over the 16 waves of a
+// 1024-thread block (wave g takes t = g, g + 16, ...) over a 512-element chunk, the 16 partial sums
+// added in wave order through LDS, so every element's chain is j / 16 long instead of j.
+constexpr int kRoThreads = 1024;
+constexpr int kRoWaves = kRoThreads / kWave;
+constexpr int kRoChunk = 512;
+constexpr int kRoPer = kRoChunk / kWave;
+constexpr long kRoSmallL = 65536;
+
+template <typename T>
+__global__ __launch_bounds__(kRoThreads) void k_reorth_update_short(T* __restrict__ V, long L, int j,
+                                                                    const double* __restrict__ h, int hstride,
+                                                                    int with_norm, LzState S) {
+  __shared__ double red[kRoWaves][kRoChunk];
+  __shared__ double lds[kRoWaves];
+  __shared__ int flag[1];
+  const int r = blockIdx.y;
+  if (!block_active(S, r, flag)) return;
+  const size_t vs = lz_slot(S, L);
+  T* w = V + (size_t)j * vs + (size_t)r * L;
+  const long base = (long)blockIdx.x * kRoChunk;
+  const int lane = threadIdx.x & (kWave - 1), g = threadIdx.x / kWave;
+  double acc[kRoPer];
+#pragma unroll
+  for (int q = 0; q < kRoPer; ++q) acc[q] = 0.0;
+  for (int t = g; t < j; t += kRoWaves) {
+    const T* vt = V + (size_t)t * vs + (size_t)r * L;
+    const double sc = 1.0 / S.beta[lz_ib(S, r, t)];
+    const double ht = h[(size_t)r * hstride + t];
+#pragma unroll
+    for (int q = 0; q < kRoPer; ++q) {
+      const long e = base + lane + q * kWave;
+      if (e < L) acc[q] += ht * (double)(T)((double)vt[e] * sc);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kRoPer; ++q) red[g][lane + q * kWave] = acc[q];
+  __syncthreads();
+  double nrm = 0.0;
+  if (threadIdx.x < kRoChunk) {
+    const long e = base + threadIdx.x;
+    double s = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < kRoWaves; ++w2) s += red[w2][threadIdx.x];
+    if (e < L) {
+      const T t = (T)((double)w[e] - s);
+      w[e] = t;
+      nrm = ip_weight(S, e) * (double)t * (double)t;
+    }
+  }
+  if (with_norm) {
+    const double s = block_sum<kRoThreads>(nrm, lds);
     if (threadIdx.x == 0) S.part_b[(size_t)r * S.pstride + blockIdx.x] = s;
   }
 }
@@ -438,15 +500,31 @@ void launch_norm_partials(const T* V0, long L, const LzState& S, hipStream_t st)
 void launch_finalize(const LzState& S, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(S.k), dim3(256), 0, st, S);
 }
+int reorth_blocks(long L) { return L <= kRoSmallL ? (int)((L + kRoChunk - 1) / kRoChunk) : ew_blocks(L); }
+
 template <typename T>
 void launch_reorth(T* V, long L, int j, double* part_h, double* h, int hstride, const LzState& S,
                    hipStream_t st) {
   const dim3 g = ew_grid(L, S.k);
+  // t slices for the dot kernel: enough blocks for about two per compute unit, at least kEwThreads /
+  // kWave vectors per slice
+  constexpr int NW = kEwThreads / kWave;
+  const long blocks = (long)g.x * S.k;
+  int nz = (int)std::min<long>((j + NW - 1) / NW, std::max<long>(1, (512 + blocks - 1) / blocks));
+  const int tslice = ((j + nz - 1) / nz + NW - 1) / NW * NW;
+  nz = (j + tslice - 1) / tslice;
+  const dim3 gd(g.x, g.y, (unsigned)nz);
+  const bool short_v = L <= kRoSmallL;
+  const dim3 gu((unsigned)reorth_blocks(L), S.k);
   for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(k_reorth_dot<T>, g, dim3(kEwThreads), 0, st, V, L, j, part_h, hstride, S);
+    hipLaunchKernelGGL(k_reorth_dot<T>, gd, dim3(kEwThreads), 0, st, V, L, j, part_h, hstride, tslice, S);
     hipLaunchKernelGGL(k_reorth_reduce, dim3(S.k), dim3(256), 0, st, part_h, hstride, (int)g.x, j, h, S);
-    hipLaunchKernelGGL(k_reorth_update<T>, g, dim3(kEwThreads), 0, st, V, L, j, h, hstride,
-                       pass == 1 ? 1 : 0, S);
+    if (short_v)
+      hipLaunchKernelGGL(k_reorth_update_short<T>, gu, dim3(kRoThreads), 0, st, V, L, j, h, hstride,
+                         pass == 1 ? 1 : 0, S);
+    else
+      hipLaunchKernelGGL(k_reorth_update<T>, g, dim3(kEwThreads), 0, st, V, L, j, h, hstride,
+                         pass == 1 ? 1 : 0, S);
   }
 }
 template <typename T, typename OutT>
