@@ -421,7 +421,7 @@ def plain_leg(gm, torch, reps=20):
     return out
 
 
-UNEVEN_TOL, UNEVEN_M_MAX = 1e-5, 400
+UNEVEN_TOL, UNEVEN_M_MAX = 1e-5, 600
 
 
 def uneven_leg(gm, torch):
@@ -439,11 +439,12 @@ def uneven_leg(gm, torch):
     Xs, info = gm.sample_batch(ops, Zs, tol=UNEVEN_TOL, m_max=UNEVEN_M_MAX)
     torch.cuda.synchronize()
     dtb = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    for op, Z in zip(ops, Zs):
-        op.sample(Z, tol=UNEVEN_TOL, m_max=UNEVEN_M_MAX)
-    torch.cuda.synchronize()
-    dts = time.perf_counter() - t0
+    for _ in range(2):   # the first pass over the fields sizes the library's scratch pool, the second is timed
+        t0 = time.perf_counter()
+        for op, Z in zip(ops, Zs):
+            op.sample(Z, tol=UNEVEN_TOL, m_max=UNEVEN_M_MAX)
+        torch.cuda.synchronize()
+        dts = time.perf_counter() - t0
     ms = [i["m_used"] for i in info]
     out = {"fields": len(fields), "columns": ncol, "unknowns": int(sum(s * s for s, _ in fields)), "storage": "f32",
            "tol_rho": UNEVEN_TOL, "m_max": UNEVEN_M_MAX, "m_used_min": min(ms), "m_used_max": max(ms),

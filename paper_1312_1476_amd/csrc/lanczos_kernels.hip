@@ -292,9 +292,62 @@ __global__ __launch_bounds__(kEwThreads) void k_reorth_update(T* __restrict__ V,
   }
 }
 
+// Short vectors (L <= kRoSmallL), dot half: block (x, r, z) covers the kEwChunk elements of chunk x for
+// the basis vectors of slice z; wave g holds its 512 elements of w in registers (8 per lane) and
+// reduces each v_{t+1}^T w over them, the four wave sums added in wave order through LDS.  No load
+// waits on another: active[] is not written during the reorthogonalisation, so it is read directly.
+constexpr int kRoDotTs = 64;   // basis vectors per LDS round
+
+template <typename T>
+__global__ __launch_bounds__(kEwThreads) void k_reorth_dot_short(const T* __restrict__ V, long L, int j,
+                                                                 double* __restrict__ part_h, int hstride,
+                                                                 int tslice, LzState S) {
+  constexpr int NW = kEwThreads / kWave;
+  constexpr int PER = kEwChunk / kEwThreads;
+  __shared__ double red[NW][kRoDotTs];
+  const int r = blockIdx.y;
+  if (!S.active[r]) return;
+  const size_t vs = lz_slot(S, L);
+  const int lane = threadIdx.x & (kWave - 1), g = threadIdx.x / kWave;
+  const long base = (long)blockIdx.x * kEwChunk + (long)g * (kWave * PER) + lane;
+  const T* w = V + (size_t)j * vs + (size_t)r * L;
+  double wv[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const long e = base + (long)q * kWave;
+    wv[q] = (e < L) ? ip_weight(S, e) * (double)w[e] : 0.0;
+  }
+  const int t1 = min(j, (int)(blockIdx.z + 1) * tslice);
+  for (int t0 = (int)blockIdx.z * tslice; t0 < t1; t0 += kRoDotTs) {
+    const int tn = min(kRoDotTs, t1 - t0);
+    for (int u = 0; u < tn; ++u) {
+      const int t = t0 + u;
+      const T* vt = V + (size_t)t * vs + (size_t)r * L;
+      const double sc = 1.0 / S.beta[lz_ib(S, r, t)];
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const long e = base + (long)q * kWave;
+        if (e < L) acc += (double)(T)((double)vt[e] * sc) * wv[q];
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) red[g][u] = acc;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < tn) {
+      double s = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) s += red[w2][threadIdx.x];
+      part_h[((size_t)r * hstride + t0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+    }
+    __syncthreads();
+  }
+}
+
 // Short vectors (L <= kRoSmallL): w -= sum_t h_t v_{t+1} with the t sum split over the 16 waves of a
 // 1024-thread block (wave g takes t = g, g + 16, ...) over a 512-element chunk, the 16 partial sums
-// added in wave order through LDS, so every element's chain is j / 16 long instead of j.
+// added in wave order through LDS, so every element's chain is j / 16 long instead of j.  h_t is
+// summed here from the dot kernel's P block partials (in block order), with no reduce launch.
 constexpr int kRoThreads = 1024;
 constexpr int kRoWaves = kRoThreads / kWave;
 constexpr int kRoChunk = 512;
@@ -303,24 +356,27 @@ constexpr long kRoSmallL = 65536;
 
 template <typename T>
 __global__ __launch_bounds__(kRoThreads) void k_reorth_update_short(T* __restrict__ V, long L, int j,
-                                                                    const double* __restrict__ h, int hstride,
-                                                                    int with_norm, LzState S) {
+                                                                    const double* __restrict__ part_h,
+                                                                    int hstride, int P, int with_norm, LzState S) {
   __shared__ double red[kRoWaves][kRoChunk];
   __shared__ double lds[kRoWaves];
-  __shared__ int flag[1];
   const int r = blockIdx.y;
-  if (!block_active(S, r, flag)) return;
+  if (!S.active[r]) return;   // not written during the reorthogonalisation: every thread reads the same value
   const size_t vs = lz_slot(S, L);
   T* w = V + (size_t)j * vs + (size_t)r * L;
   const long base = (long)blockIdx.x * kRoChunk;
   const int lane = threadIdx.x & (kWave - 1), g = threadIdx.x / kWave;
+  const long ew = base + threadIdx.x;
+  const double w0 = ((int)threadIdx.x < kRoChunk && ew < L) ? (double)w[ew] : 0.0;   // in flight during the t loop
   double acc[kRoPer];
 #pragma unroll
   for (int q = 0; q < kRoPer; ++q) acc[q] = 0.0;
   for (int t = g; t < j; t += kRoWaves) {
     const T* vt = V + (size_t)t * vs + (size_t)r * L;
     const double sc = 1.0 / S.beta[lz_ib(S, r, t)];
-    const double ht = h[(size_t)r * hstride + t];
+    const double* ph = part_h + ((size_t)r * hstride + t) * P;
+    double ht = 0.0;
+    for (int b = 0; b < P; ++b) ht += ph[b];
 #pragma unroll
     for (int q = 0; q < kRoPer; ++q) {
       const long e = base + lane + q * kWave;
@@ -331,15 +387,14 @@ __global__ __launch_bounds__(kRoThreads) void k_reorth_update_short(T* __restric
   for (int q = 0; q < kRoPer; ++q) red[g][lane + q * kWave] = acc[q];
   __syncthreads();
   double nrm = 0.0;
-  if (threadIdx.x < kRoChunk) {
-    const long e = base + threadIdx.x;
+  if ((int)threadIdx.x < kRoChunk) {
     double s = 0.0;
 #pragma unroll
     for (int w2 = 0; w2 < kRoWaves; ++w2) s += red[w2][threadIdx.x];
-    if (e < L) {
-      const T t = (T)((double)w[e] - s);
-      w[e] = t;
-      nrm = ip_weight(S, e) * (double)t * (double)t;
+    if (ew < L) {
+      const T t = (T)(w0 - s);
+      w[ew] = t;
+      nrm = ip_weight(S, ew) * (double)t * (double)t;
     }
   }
   if (with_norm) {
@@ -506,25 +561,30 @@ template <typename T>
 void launch_reorth(T* V, long L, int j, double* part_h, double* h, int hstride, const LzState& S,
                    hipStream_t st) {
   const dim3 g = ew_grid(L, S.k);
-  // t slices for the dot kernel: enough blocks for about two per compute unit, at least kEwThreads /
-  // kWave vectors per slice
+  // t slices for the dot kernel: enough blocks for about two per compute unit, with at least
+  // kEwThreads / kWave vectors per slice (one per block for short vectors)
   constexpr int NW = kEwThreads / kWave;
+  const bool short_v = L <= kRoSmallL;
+  const int tmin = short_v ? 1 : NW;
   const long blocks = (long)g.x * S.k;
-  int nz = (int)std::min<long>((j + NW - 1) / NW, std::max<long>(1, (512 + blocks - 1) / blocks));
-  const int tslice = ((j + nz - 1) / nz + NW - 1) / NW * NW;
+  int nz = (int)std::min<long>((j + tmin - 1) / tmin, std::max<long>(1, (512 + blocks - 1) / blocks));
+  const int tslice = ((j + nz - 1) / nz + tmin - 1) / tmin * tmin;
   nz = (j + tslice - 1) / tslice;
   const dim3 gd(g.x, g.y, (unsigned)nz);
-  const bool short_v = L <= kRoSmallL;
   const dim3 gu((unsigned)reorth_blocks(L), S.k);
   for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(k_reorth_dot<T>, gd, dim3(kEwThreads), 0, st, V, L, j, part_h, hstride, tslice, S);
-    hipLaunchKernelGGL(k_reorth_reduce, dim3(S.k), dim3(256), 0, st, part_h, hstride, (int)g.x, j, h, S);
     if (short_v)
-      hipLaunchKernelGGL(k_reorth_update_short<T>, gu, dim3(kRoThreads), 0, st, V, L, j, h, hstride,
-                         pass == 1 ? 1 : 0, S);
+      hipLaunchKernelGGL(k_reorth_dot_short<T>, gd, dim3(kEwThreads), 0, st, V, L, j, part_h, hstride, tslice, S);
     else
+      hipLaunchKernelGGL(k_reorth_dot<T>, gd, dim3(kEwThreads), 0, st, V, L, j, part_h, hstride, tslice, S);
+    if (short_v) {
+      hipLaunchKernelGGL(k_reorth_update_short<T>, gu, dim3(kRoThreads), 0, st, V, L, j, part_h, hstride,
+                         (int)g.x, pass == 1 ? 1 : 0, S);
+    } else {
+      hipLaunchKernelGGL(k_reorth_reduce, dim3(S.k), dim3(256), 0, st, part_h, hstride, (int)g.x, j, h, S);
       hipLaunchKernelGGL(k_reorth_update<T>, g, dim3(kEwThreads), 0, st, V, L, j, h, hstride,
                          pass == 1 ? 1 : 0, S);
+    }
   }
 }
 template <typename T, typename OutT>
