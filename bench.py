@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
-    ap.add_argument("--only", default="", help="profiling: run only this leg (headline|counters|lgcp|logdet|ichol|plain|uneven)")
+    ap.add_argument("--only", default="", help="profiling: run only this leg (headline|counters|lgcp|logdet|ichol|plain|uneven|serve)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-lgcp", action="store_true", help="skip the log-Gaussian Cox process leg")
     ap.add_argument("--no-logdet", action="store_true", help="skip the log-determinant leg")
@@ -116,10 +116,13 @@ def main():
         print(json.dumps({"ichol": ichol_leg(gm, torch)}))
         return
     if args.only == "plain":
-        print(json.dumps({"plain_64x64": plain_leg(gm, torch)}))
+        print(json.dumps({"plain_64x64": _public(plain_leg(gm, torch))}))
+        return
+    if args.only == "serve":
+        print(json.dumps({"serving": serving_leg(gm, torch, args.serve_seconds)}))
         return
     if args.only == "uneven":
-        print(json.dumps({"uneven_batch": uneven_leg(gm, torch)}))
+        print(json.dumps({"uneven_batch": _public(uneven_leg(gm, torch))}))
         return
 
     # ---- headline: FP64 storage, stop at rho <= 1e-5 ---------------------------------------------
@@ -264,11 +267,37 @@ def main():
         }
         for key in ("f64", "f32", "f32_tol"):
             extra[key]["rel_err_col0"] = rel(extra[key]["x_col0"])
+        if "plain_64x64" in result:
+            from oracle import closed_form as ocf
+            c0 = workloads.C0
+            sp0 = c0.lattice
+            z0 = workloads.gaussian_block(sp0.n, 1, 0, 0)[:, 0]
+            ex = ocf.exact_sample_free(sp0.shape, sp0.order, sp0.kappa2, sp0.tau, z0)
+            result["plain_64x64"]["rel_err_vs_exact"] = float(np.linalg.norm(result["plain_64x64"]["_x"] - ex)
+                                                              / np.linalg.norm(ex))
+        if "uneven_batch" in result:
+            from oracle import closed_form as ocf
+            errs = []
+            for f, ((side, k2), Zf, Xf) in result["uneven_batch"]["_x"].items():
+                ex = ocf.exact_sample_free((side, side), 1, k2, 1.0, Zf.T)
+                errs += [float(np.linalg.norm(Xf[r] - ex[:, r]) / np.linalg.norm(ex[:, r])) for r in range(Zf.shape[0])]
+            result["uneven_batch"]["accuracy"] = {
+                "sample": "8 fields across the kappa2 range x 8 columns, vs the exact DCT sample",
+                "max_rel_err": max(errs), "median_rel_err": float(np.median(errs)),
+                "within_1e-5": sum(e <= 1e-5 for e in errs), "of": len(errs)}
     for key in extra:
         extra[key].pop("x_col0", None)
+    for key in ("plain_64x64", "uneven_batch"):
+        if key in result:
+            result[key] = _public(result[key])
     result["at_m_max_300"] = {"f64": extra["f64"], "f32": extra["f32"]}
     result["fp32_storage_at_tol"] = extra["f32_tol"]
     print(json.dumps(result))
+
+
+def _public(d):
+    """The leg's record without its private arrays (keys starting with an underscore)."""
+    return {k: v for k, v in d.items() if not k.startswith("_")}
 
 
 LGCP_TOL = 1e-8                  # Table 1's accuracy
@@ -416,7 +445,8 @@ def plain_leg(gm, torch, reps=20):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
     out = {"samples_per_s": round(1.0 / dt, 2), "ms_per_sample": round(1000 * dt, 3), "m_used": info[0]["m_used"],
-           "rho": info[0]["rel_residual"], "status": info[0]["status"], "reorth": "CGS2"}
+           "rho": info[0]["rel_residual"], "status": info[0]["status"], "reorth": "CGS2",
+           "_x": X[0].cpu().numpy()}   # for the accuracy check beside the oracle leg (removed before printing)
     op.close()
     return out
 
@@ -427,7 +457,8 @@ UNEVEN_TOL, UNEVEN_M_MAX = 1e-5, 600
 def uneven_leg(gm, torch):
     """Uneven batch (workload C2): 256 first-order fields, side uniform in 32..256, kappa2 log-uniform
     in [1e-3, 1], 8 right-hand sides each, FP32 storage (FP64 scalars), all fields in one set of
-    launches per Lanczos step; against the same fields sampled one call each."""
+    launches per Lanczos step; against the same fields sampled one call each, and against plain FP64
+    Lanczos one sample at a time (column 0 of every field, same stopping rule)."""
     fields = workloads.uneven_fields()
     ops = [gm.Operator.lattice((s, s), 1, k2, 1.0, "free", "f32") for s, k2 in fields]
     Zs = [torch.from_numpy(np.ascontiguousarray(workloads.uneven_field_rhs(f, s).T)).to("cuda:0")
@@ -445,13 +476,31 @@ def uneven_leg(gm, torch):
             op.sample(Z, tol=UNEVEN_TOL, m_max=UNEVEN_M_MAX)
         torch.cuda.synchronize()
         dts = time.perf_counter() - t0
+    # plain FP64, k = 1: column 0 of every field
+    ops64 = [gm.Operator.lattice((s, s), 1, k2, 1.0, "free", "f64") for s, k2 in fields]
+    Z1 = [Z[:1].contiguous() for Z in Zs]
+    for op, z in zip(ops64[:8], Z1[:8]):
+        op.sample(z, tol=UNEVEN_TOL, m_max=UNEVEN_M_MAX)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for op, z in zip(ops64, Z1):
+        op.sample(z, tol=UNEVEN_TOL, m_max=UNEVEN_M_MAX)
+    torch.cuda.synchronize()
+    dtp = time.perf_counter() - t0
+    for op in ops64:
+        op.close()
     ms = [i["m_used"] for i in info]
+    order = np.argsort([k2 for _, k2 in fields])
+    picks = [int(order[(len(order) - 1) * q // 7]) for q in range(8)]   # 8 fields across the kappa2 range
     out = {"fields": len(fields), "columns": ncol, "unknowns": int(sum(s * s for s, _ in fields)), "storage": "f32",
            "tol_rho": UNEVEN_TOL, "m_max": UNEVEN_M_MAX, "m_used_min": min(ms), "m_used_max": max(ms),
            "not_converged": sum(i["status"] != "OK" for i in info),
            "batched_samples_per_s": round(ncol / dtb, 1), "batched_s": round(dtb, 3),
            "one_call_per_field_samples_per_s": round(ncol / dts, 1), "one_call_per_field_s": round(dts, 3),
-           "batch_speedup": round(dts / dtb, 2)}
+           "batch_speedup": round(dts / dtb, 2),
+           "plain_fp64_k1_samples_per_s": round(len(fields) / dtp, 1),
+           "speedup_vs_plain_fp64_k1": round((ncol / dtb) / (len(fields) / dtp), 1),
+           "_x": {f: (fields[f], Zs[f].cpu().numpy(), Xs[f].cpu().numpy()) for f in picks}}
     for op in ops:
         op.close()
     return out
@@ -467,6 +516,8 @@ def serving_leg(gm, torch, seconds):
     from paper_1312_1476_amd import serve
     pool = workloads.serving_pool()
     ops = [gm.Operator.lattice(p.shape, p.order, p.kappa2, p.tau, "free", "f64") for p in pool]
+    gm.set_hbm_budget(0)           # returns the scratch the earlier legs left cached in the library's pool
+    torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
     out = {"pool": "64 operators: 2D 5-point (80%), 3D 7-point (20%)", "workers": 4,
@@ -480,6 +531,7 @@ def serving_leg(gm, torch, seconds):
         srv.stop()
         out["rates"][f"{rate}_req_per_s"] = {
             "requests": st["requests"], "completed": st["completed"], "rejected": st["rejected"],
+            "two_pass": st["two_pass"],
             "wall_s": round(st["wall_s"], 2), "p50_latency_s": round(st["p50_latency_s"], 4),
             "p99_latency_s": round(st["p99_latency_s"], 4), "samples_per_s": round(st["samples_per_s"], 2),
             "probes_per_s": round(st["probes_per_s"], 2)}

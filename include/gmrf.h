@@ -266,7 +266,8 @@ gmrf_status gmrf_kernel_bench(const gmrf_op* Q, int which, int64_t k, int32_t re
 /* ---- memory budget and errors ---------------------------------------------------------- */
 
 /* Cap on device bytes held by the library's scratch pool (0 = no cap).  Calls that would
- * exceed it return GMRF_ENOMEM without running.                                             */
+ * exceed it return GMRF_ENOMEM without running.  Every call also returns the pool's cached
+ * free blocks (scratch of finished calls kept for reuse) to the device.                     */
 gmrf_status gmrf_set_hbm_budget(size_t bytes);
 size_t gmrf_hbm_in_use(void);
 

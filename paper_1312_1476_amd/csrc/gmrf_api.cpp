@@ -203,6 +203,10 @@ const char* gmrf_strerror(gmrf_status s) {
 gmrf_status gmrf_set_hbm_budget(size_t bytes) {
   std::lock_guard<std::mutex> lk(pool().mu);
   pool().budget = bytes;
+  // cached free blocks go back to the device, so that what the caller sees free afterwards is free
+  for (auto& kv : pool().free_blocks) (void)hipFree(kv.second);
+  pool().free_blocks.clear();
+  pool().cached = 0;
   return GMRF_OK;
 }
 

@@ -3,7 +3,9 @@
 Operators stay resident on the device (their gmrf_op handles, with FFT spectra when
 preconditioned).  Requests queue in arrival order; the dispatcher admits the head request as
 soon as a worker slot is free and its device bytes fit the HBM budget next to everything
-already in flight, so requests that arrive while others run start as capacity frees up.  Each
+already in flight, so requests that arrive while others run start as capacity frees up.  A
+sample whose stored Krylov basis alone would exceed the budget runs the two-pass sampler (O(n)
+memory, the recurrence twice) instead of being turned away.  Each
 worker owns a HIP stream (default priority) and calls the blocking sample / log-det entry
 point, which releases the GIL: admitted requests overlap on the GPU.  Every call has its own
 scratch and the kernels' reductions are fixed-order, so a request's result does not depend on
@@ -33,6 +35,7 @@ class ServeRequest:
     t_start: float = 0.0
     t_done: float = 0.0
     bytes: int = 0
+    two_pass: bool = False    # sample whose stored Krylov basis does not fit the budget: O(n) two-pass mode
     result: object = None
     error: str = ""
     done: threading.Event = field(default_factory=threading.Event)
@@ -64,11 +67,16 @@ class Server:
 
     # -- sizing -------------------------------------------------------------------------------
     def request_bytes(self, req):
+        """Device bytes of the request; a sample whose stored basis would exceed the budget is
+        switched to the two-pass sampler (three Krylov slots instead of m_max + 1)."""
         op = self.ops[req.op_index]
         vec = op.n * req.k * 8
+        ring3 = op.bytes(req.k, 2, False) + req.k * (req.m_max + 2) * 64   # 3 Krylov slots + scalars
         if req.kind == "sample":
-            return op.bytes(req.k, req.m_max, False) + 2 * vec          # + Z and X (FP64)
-        return op.bytes(req.k, 2, False) + req.k * (req.m_max + 2) * 64   # 3 Krylov slots + scalars
+            stored = op.bytes(req.k, req.m_max, False) + 2 * vec          # + Z and X (FP64)
+            req.two_pass = stored > self.budget
+            return ring3 + 2 * vec if req.two_pass else stored
+        return ring3
 
     # -- lifecycle ----------------------------------------------------------------------------
     def start(self):
@@ -159,7 +167,10 @@ class Server:
             g = torch.Generator(device="cuda")
             g.manual_seed(req.seed)
             Z = torch.randn((req.k, op.n), dtype=torch.float64, device="cuda", generator=g)
-            X, info = op.sample(Z, tol=req.tol, m_max=req.m_max, reorth=False, stream=stream)
+            if req.two_pass:
+                X, info = op.sample_two_pass(Z, tol=req.tol, m_max=req.m_max, stream=stream)
+            else:
+                X, info = op.sample(Z, tol=req.tol, m_max=req.m_max, reorth=False, stream=stream)
             return {"X": X, "info": info}
         mean, se, per = op.logdet(req.k, req.m_max, seed=req.seed, stream=stream)
         return {"logdet": mean, "std_err": se, "per_probe": per}
@@ -193,6 +204,7 @@ def stats(requests, wall):
     samples = sum(r.k for r in ok if r.kind == "sample")
     probes = sum(r.k for r in ok if r.kind == "logdet")
     return {"requests": len(requests), "completed": len(ok), "rejected": len(requests) - len(ok),
+            "two_pass": sum(1 for r in ok if r.two_pass),
             "wall_s": wall, "p50_latency_s": pct(50), "p99_latency_s": pct(99),
             "samples_per_s": samples / wall if wall > 0 else 0.0,
             "probes_per_s": probes / wall if wall > 0 else 0.0}

@@ -1,6 +1,7 @@
 """Serving (continuous batching) over the C ABI: each result is identical alone and in a mix,
-admission never exceeds the HBM budget, admitted work overlaps, oversize requests are
-rejected, and a served sample matches the oracle."""
+admission never exceeds the HBM budget, admitted work overlaps, a sample whose stored basis
+does not fit runs the two-pass sampler, requests too large even for that are rejected, and a
+served sample matches the oracle."""
 import numpy as np
 import pytest
 
@@ -108,3 +109,28 @@ def test_served_sample_matches_oracle(env):
         m = req.result["info"][r]["m_used"]
         ref = lanczos.sample_csr(Q, Z[r], m, tol=0.0)
         assert np.linalg.norm(X[r] - ref.x) / np.linalg.norm(ref.x) <= 1e-8
+
+
+def test_two_pass_fallback(env):
+    """A budget below the stored basis but above three Krylov slots: the sample is admitted in
+    two-pass mode and equals the one-pass sample (same m, 1e-12)."""
+    import torch
+    gm, serve, ops = env
+    probe = serve.Server(ops, hbm_budget=1 << 40)
+    req = serve.ServeRequest(1, "sample", 3, 4, 23, tol=1e-8, m_max=500)
+    stored = probe.request_bytes(req)
+    assert not req.two_pass
+    budget = stored // 4
+    srv = serve.Server(ops, hbm_budget=budget, workers=2).start()
+    req2 = srv.submit(serve.ServeRequest(1, "sample", 3, 4, 23, tol=1e-8, m_max=500))
+    req2.done.wait()
+    srv.stop()
+    assert not req2.error, req2.error
+    assert req2.two_pass and req2.bytes <= budget and srv.peak_bytes <= budget
+    g = torch.Generator(device="cuda")
+    g.manual_seed(23)
+    Z = torch.randn((4, ops[3].n), dtype=torch.float64, device="cuda", generator=g)
+    X1, i1 = ops[3].sample(Z, tol=1e-8, m_max=500)
+    assert [i["m_used"] for i in i1] == [i["m_used"] for i in req2.result["info"]]
+    assert float((req2.result["X"] - X1).norm() / X1.norm()) <= 1e-12
+    assert serve.stats([req2], 1.0)["two_pass"] == 1
