@@ -490,6 +490,7 @@ def uneven_leg(gm, torch):
     for op in ops64:
         op.close()
     ms = [i["m_used"] for i in info]
+    col_n = [int(Z.shape[1]) for Z in Zs for _ in range(int(Z.shape[0]))]
     order = np.argsort([k2 for _, k2 in fields])
     picks = [int(order[(len(order) - 1) * q // 7]) for q in range(8)]   # 8 fields across the kappa2 range
     out = {"fields": len(fields), "columns": ncol, "unknowns": int(sum(s * s for s, _ in fields)), "storage": "f32",
@@ -498,6 +499,10 @@ def uneven_leg(gm, torch):
            "batched_samples_per_s": round(ncol / dtb, 1), "batched_s": round(dtb, 3),
            "one_call_per_field_samples_per_s": round(ncol / dts, 1), "one_call_per_field_s": round(dts, 3),
            "batch_speedup": round(dts / dtb, 2),
+           # algorithmic bytes: the one-pass step reads v_j, v_{j-1} and writes w_j (3 s n per column and
+           # step); the final combination reads each column's m basis vectors once (s n m)
+           "step_bytes": 3 * 4 * sum(i["m_used"] * n for i, n in zip(info, col_n)),
+           "combine_bytes": 4 * sum(i["m_used"] * n for i, n in zip(info, col_n)),
            "plain_fp64_k1_samples_per_s": round(len(fields) / dtp, 1),
            "speedup_vs_plain_fp64_k1": round((ncol / dtb) / (len(fields) / dtp), 1),
            "_x": {f: (fields[f], Zs[f].cpu().numpy(), Xs[f].cpu().numpy()) for f in picks}}

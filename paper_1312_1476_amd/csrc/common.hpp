@@ -60,6 +60,9 @@ struct LzState {
   const int* col_pb;              // elementwise partials of column r (default Pb)
   const StencilGeom* col_geom;    // lattice of column r (default: the kernel's geometry)
   int64_t slot_stride;            // elements per Krylov slot (default k * L)
+  // One-pass 2D step over an uneven batch: block b works on column work[b].x, tile work[b].y (the
+  // tiles of the columns still running; nullptr: column blockIdx.y, tile blockIdx.x).
+  const int2* work;
 };
 
 __device__ __forceinline__ size_t lz_off(const LzState& S, int r, long L) {

@@ -1638,13 +1638,36 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
                         nullptr, st);
   int* pbuf = poll_buffer(K);
   if (!pbuf) return fail(GMRF_ENOMEM, "pinned host buffer allocation failed");
+  // one-pass step: a flat list of (column, tile) over the columns still running, rebuilt at every poll,
+  // so that the grid shrinks as columns stop instead of launching max_tiles blocks for every column
+  std::vector<int2> work;
+  int2* dwork = nullptr;
+  int nwork = 0;
+  auto build_work = [&](const int* act) -> gmrf_status {
+    work.clear();
+    for (int r = 0; r < K; ++r) {
+      if (act && !act[r]) continue;
+      for (int t = 0; t < pa[r]; ++t) work.push_back(make_int2(r, t));
+    }
+    nwork = (int)work.size();
+    if (nwork) HIP_TRY(hipMemcpyAsync(dwork, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    return GMRF_OK;
+  };
+  if (fused) {
+    size_t cap = 0;
+    for (int r = 0; r < K; ++r) cap += (size_t)pa[r];
+    if ((s = ws.alloc(cap, &dwork)) != GMRF_OK) return s;
+    if ((s = build_work(nullptr)) != GMRF_OK) return s;
+    S.work = dwork;
+  }
   int poll = 8;
   for (int j = 1; j <= m_max; ++j) {
     if (fused) {
       // S holds pass j - 1's partial sums (iteration 1: the init kernels' set 0); this pass writes the other set
       const int wset = j & 1;
-      launch_lanczos2d<T>(Q0->geom, Q0->order, 0, max_tiles, slot(j - 1), 0, slot(j), j >= 2 ? slot(j - 2) : slot(0),
-                          S, j, K, ps[wset][0], ps[wset][1], ps[wset][2], st);
+      if (nwork)
+        launch_lanczos2d<T>(Q0->geom, Q0->order, 0, nwork, slot(j - 1), 0, slot(j), j >= 2 ? slot(j - 2) : slot(0),
+                            S, j, 1, ps[wset][0], ps[wset][1], ps[wset][2], st);
       S.part_a = ps[wset][0];
       S.part_b = ps[wset][1];
       S.part_c = ps[wset][2];
@@ -1661,9 +1684,11 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
       bool any = false;
       for (int r = 0; r < K; ++r) any |= pbuf[r] != 0;
       if (!any) break;
+      if (fused && (s = build_work(pbuf)) != GMRF_OK) return s;
       poll = std::min(poll * 2, 32);
     }
   }
+  S.work = nullptr;
   launch_finalize(S, st);
   double *y, *scr;
   if ((s = ws.alloc((size_t)K * m_max, &y)) != GMRF_OK) return s;

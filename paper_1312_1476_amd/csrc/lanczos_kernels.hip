@@ -2,6 +2,8 @@
 // reorthogonalisation, the final combination x_m = ||z|| V_m y and the Rademacher probes
 // of the Hutchinson estimator (Section 6).  All memory-bound: coalesced strided loops, FP64
 // arithmetic on values loaded from the storage type T, deterministic partial sums.
+#include <stdint.h>
+
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -449,6 +451,90 @@ __global__ __launch_bounds__(kEwThreads) void k_combine(const T* __restrict__ V,
   }
 }
 
+// FP32 storage with 16-byte aligned columns: the same sums with float4 loads, 4096 elements per block
+// (16 KB of each basis vector) and two basis vectors in flight.  Each element still accumulates
+// beta_0 y_t / beta_t v_{t+1}[e] in t order, as k_combine does.
+constexpr int kCbVec = 4;                                // float4 loads per thread and basis vector
+constexpr int kCbChunk = kEwThreads * kCbVec * 4;        // elements per block
+
+template <typename OutT>
+__global__ __launch_bounds__(kEwThreads) void k_combine_f32v(const float* __restrict__ V, long L,
+                                                             const double* __restrict__ y, int ldy,
+                                                             OutT* __restrict__ out, long old, LzState S) {
+  __shared__ double cl[1024];
+  const int r = blockIdx.y;
+  const long len = lz_len(S, r, L);
+  if ((long)blockIdx.x * kCbChunk >= len) return;
+  const int m = S.m_used[r];
+  const int st = S.status[r];
+  const double beta0 = S.beta[lz_ib(S, r, 0)];
+  const size_t vs = lz_slot(S, L);
+  const size_t voff = lz_off(S, r, L);
+  const int64_t* ext = S.col_ext ? S.col_ext : S.col_off;
+  const size_t ooff = ext ? (size_t)ext[r] : (size_t)r * old;
+  const long base = (long)blockIdx.x * kCbChunk + (long)threadIdx.x * 4;
+  double acc[kCbVec][4];
+#pragma unroll
+  for (int q = 0; q < kCbVec; ++q)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[q][i] = 0.0;
+  auto load = [&](const float* v, long e) {
+    if (e + 3 < len) return *(const float4*)(v + e);
+    float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (e < len) x.x = v[e];
+    if (e + 1 < len) x.y = v[e + 1];
+    if (e + 2 < len) x.z = v[e + 2];
+    return x;
+  };
+  auto add = [&](double c, const float4* x) {
+#pragma unroll
+    for (int q = 0; q < kCbVec; ++q) {
+      acc[q][0] += c * (double)x[q].x;
+      acc[q][1] += c * (double)x[q].y;
+      acc[q][2] += c * (double)x[q].z;
+      acc[q][3] += c * (double)x[q].w;
+    }
+  };
+  const bool bad = (st == kENOTSPD || st == kEINVAL);
+  if (!bad) {
+    for (int t0 = 0; t0 < m; t0 += 1024) {
+      const int tn = min(1024, m - t0);
+      __syncthreads();
+      for (int t = threadIdx.x; t < tn; t += kEwThreads)
+        cl[t] = beta0 * y[(size_t)r * ldy + t0 + t] / S.beta[lz_ib(S, r, t0 + t)];
+      __syncthreads();
+      int t = 0;
+      for (; t + 1 < tn; t += 2) {
+        const float* va = V + (size_t)(t0 + t) * vs + voff;
+        const float* vb = va + vs;
+        float4 xa[kCbVec], xb[kCbVec];
+#pragma unroll
+        for (int q = 0; q < kCbVec; ++q) {
+          xa[q] = load(va, base + (long)q * kEwThreads * 4);
+          xb[q] = load(vb, base + (long)q * kEwThreads * 4);
+        }
+        add(cl[t], xa);
+        add(cl[t + 1], xb);
+      }
+      if (t < tn) {
+        const float* va = V + (size_t)(t0 + t) * vs + voff;
+        float4 xa[kCbVec];
+#pragma unroll
+        for (int q = 0; q < kCbVec; ++q) xa[q] = load(va, base + (long)q * kEwThreads * 4);
+        add(cl[t], xa);
+      }
+    }
+  }
+  const double nanv = __longlong_as_double(0x7ff8000000000000ll);
+#pragma unroll
+  for (int q = 0; q < kCbVec; ++q)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const long e = base + (long)q * kEwThreads * 4 + i;
+      if (e < len) out[ooff + e] = (OutT)(bad ? nanv : acc[q][i]);
+    }
+}
+
 // The combine one basis vector at a time (the second pass of the two-pass sampler): with slot t holding
 // w_t = beta_t v_{t+1}, out[r] = beta_0 y_0 v_1 for t = 0 and out[r] += beta_0 y_t v_{t+1} for 0 < t < m_used.
 // NaN for a column whose status is ENOTSPD or EINVAL, zero for m_used = 0.
@@ -596,6 +682,15 @@ void launch_accumulate(const T* Vt, long L, const double* y, int ldy, const LzSt
 template <typename T, typename OutT>
 void launch_combine(const T* V, long L, const double* y, int ldy, OutT* out, long old, const LzState& S,
                     hipStream_t st) {
+  // float4 loads need every column to start on a 16-byte boundary: batch offsets are padded to four
+  // elements, plain columns start at r * L
+  if constexpr (sizeof(T) == 4) {
+    if ((S.col_off != nullptr || L % 4 == 0) && ((uintptr_t)V & 15) == 0 && ((S.slot_stride ? (size_t)S.slot_stride : (size_t)S.k * (size_t)L) % 4) == 0) {
+      const dim3 g((unsigned)((L + kCbChunk - 1) / kCbChunk), S.k);
+      hipLaunchKernelGGL((k_combine_f32v<OutT>), g, dim3(kEwThreads), 0, st, (const float*)V, L, y, ldy, out, old, S);
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_combine<T, OutT>), ew_grid(L, S.k), dim3(kEwThreads), 0, st, V, L, y, ldy, out, old, S);
 }
 

@@ -643,19 +643,24 @@ __global__ __launch_bounds__(256, GMRF_L2D_WAVES) void k_lanczos2d(StencilGeom g
   __shared__ __align__(16) T wrow[kS2Waves][2][kS2MaxEpl<T> * kWave];
   __shared__ double red[3 * NW];
   __shared__ int flag[1];
-  const int r = blockIdx.y;
+  int r = blockIdx.y, tile = blockIdx.x;
+  if (S.work) {
+    const int2 wt = S.work[blockIdx.x];
+    r = wt.x;
+    tile = wt.y;
+  }
   const StencilGeom g = S.col_geom ? S.col_geom[r] : g0;
-  if ((int)blockIdx.x >= g.ftiles_x * g.tiles_y) return;
+  if (tile >= g.ftiles_x * g.tiles_y) return;
   double s_cur = 1.0, s_prev = 0.0, bprev = 0.0, alpha = 0.0;
   if (MODE == 0) {
-    if (!lz_open<256>(S, r, j, blockIdx.x == 0, red, flag, s_cur, s_prev, bprev)) return;
+    if (!lz_open<256>(S, r, j, tile == 0, red, flag, s_cur, s_prev, bprev)) return;
     // alpha_j from the previous pass's partial sums (fixed order; the same in every block)
     const double qf = sum_partials<256>(S.part_a + (size_t)r * S.pstride, lz_pa(S, r), red);
     const double cc = j > 1 ? sum_partials<256>(S.part_c + (size_t)r * S.pstride, lz_pa(S, r), red) : 0.0;
     alpha = qf * s_cur * s_cur - cc;
-    if (blockIdx.x == 0 && threadIdx.x == 0) S.alpha[lz_ia(S, r, j)] = alpha;
+    if (tile == 0 && threadIdx.x == 0) S.alpha[lz_ia(S, r, j)] = alpha;
   }
-  const int tx = blockIdx.x % g.ftiles_x, ty = blockIdx.x / g.ftiles_x;
+  const int tx = tile % g.ftiles_x, ty = tile / g.ftiles_x;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   const size_t roff = S.col_off ? (size_t)S.col_off[r] : (size_t)r * xld;
   double acc_b = 0.0, acc_c = 0.0, acc_a = 0.0;
@@ -680,11 +685,11 @@ sums:
     const double sb = block_sum<256>(acc_b, red);
     const double sc = block_sum<256>(acc_c, red);
     if (threadIdx.x == 0) {
-      out_b[(size_t)r * S.pstride + blockIdx.x] = sb;
-      out_c[(size_t)r * S.pstride + blockIdx.x] = sc;
+      out_b[(size_t)r * S.pstride + tile] = sb;
+      out_c[(size_t)r * S.pstride + tile] = sc;
     }
   }
-  if (threadIdx.x == 0) out_a[(size_t)r * S.pstride + blockIdx.x] = sa;
+  if (threadIdx.x == 0) out_a[(size_t)r * S.pstride + tile] = sa;
 }
 
 // ---- CSR: one thread per row ----------------------------------------------------------------
