@@ -195,6 +195,25 @@ def test_sample_fp32_storage(gm, reorth):
         assert _rel(X[:, r], ref.x) <= 1e-5
 
 
+@pytest.mark.parametrize("shape,k,m,storage", [((300, 300), 2, 30, "f64"), ((300, 300), 2, 20, "f32"),
+                                               ((256, 256), 2, 25, "f64"), ((65537,), 1, 20, "f64"),
+                                               ((64, 64), 24, 40, "f64"), ((33, 31), 3, 45, "f32")],
+                         ids=["long-f64", "long-f32", "at-limit", "limit+1", "many-columns", "odd-f32"])
+def test_reorth_tilings(gm, shape, k, m, storage):
+    """Both reorthogonalisation tilings (vectors of up to 65536 elements, and longer), the slices of
+    basis vectors the dot kernels take on small grids, and the FP32 combine with and without float4
+    loads, at a forced m against the oracle with CGS2."""
+    op = gm.Operator.lattice(shape, 1, 0.05, 1.0, "free", storage)
+    Q = lattice.lattice_precision(shape, 1, 0.05, 1.0, "free")
+    Zh = workloads.gaussian_block(Q.shape[0], k, 97, 0)
+    X, info, _, _ = _gpu_sample(gm, op, Zh, tol=0.0, m_max=m, reorth=True)
+    tol = 1e-8 if storage == "f64" else 1e-5
+    for r in range(k):
+        assert info[r]["m_used"] == m
+        ref = lanczos.sample_csr(Q, Zh[:, r], m, tol=0.0, reorth=True)
+        assert _rel(X[:, r], ref.x) <= tol, (r, _rel(X[:, r], ref.x))
+
+
 def test_edge_cases(gm):
     shape = (20, 20)
     op = gm.Operator.lattice(shape, 1, 0.3, 1.0, "free", "f64")
