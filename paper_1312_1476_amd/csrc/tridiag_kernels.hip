@@ -14,7 +14,7 @@
 // Each node needs (T + sigma I)^{-1} e_1: with the backward pivots
 //   d_{m-1} = alpha_{m-1} + sigma,  d_i = alpha_i + sigma - beta_i^2 / d_{i+1},
 // its entries are y_0 = 1/d_0, y_{i+1} = -(beta_i / d_{i+1}) y_i, and (T+sigma)^{-1}_{00} = 1/d_0.
-// Sums over nodes are wave butterflies then a fixed-order sum over waves: deterministic.
+// Sums over nodes are fixed-order (lanes, wave butterflies, node blocks in order): deterministic.
 #include "kernels.hpp"
 
 namespace gmrf {
@@ -78,9 +78,13 @@ __device__ void tri_load(const TriArgs& A, int r, int m, double* a, double* b) {
   __syncthreads();
 }
 
+// Per node (one thread each): the backward pivots leave q_i = beta_i / d_{i+1} in the scratch rows, the
+// forward recurrence overwrites row i with w y_i (loads taken eight rows ahead, no cross-lane work in the
+// chain); then each wave sums whole rows over the block's nodes, and an LDS accumulator adds the
+// node blocks in order.
 __global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
   __shared__ double a[kTriMaxM], b[kTriMaxM];
-  __shared__ double yw[kTriThreads / kWave][kTriMaxM / 2];
+  __shared__ double acc[kTriMaxM];
   __shared__ double red[kTriThreads / kWave];
   __shared__ int ired[kTriThreads / kWave];
   const int r = blockIdx.x;
@@ -100,42 +104,51 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
   const double s_lo = 0.5 * log(lo) - kPad, s_hi = 0.5 * log(hi) + kPad;
   const int nq = (int)ceil((s_hi - s_lo) / h) + 1;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  // the LDS accumulator holds half of kTriMaxM per wave; longer T uses two sweeps over i
-  for (int i0 = 0; i0 < m; i0 += kTriMaxM / 2) {
-    const int iend = min(m, i0 + kTriMaxM / 2);
-    for (int i = lane; i < iend - i0; i += kWave) yw[wv][i] = 0.0;
-    for (int base = 0; base < nq; base += kTriThreads) {
-      const int l = base + threadIdx.x;
-      const bool act = l < nq;
-      const double s = s_lo + h * (double)l;
-      const double es = exp(s);
-      const double sigma = es * es;
-      const double wgt = act ? (2.0 / M_PI) * h * es : 0.0;
-      double* rs = A.scratch + (size_t)r * A.scr_m * kTriThreads;
-      // backward pivots; rs[i][t] = beta_i / d_{i+1}
-      double d = a[m - 1] + sigma;
-      for (int i = m - 2; i >= 0; --i) {
-        const double q = b[i] / d;
-        rs[(size_t)i * kTriThreads + threadIdx.x] = q;
-        d = a[i] + sigma - b[i] * q;
-      }
-      double yi = 1.0 / d;
-      for (int i = 0; i < iend; ++i) {
-        if (i > 0) yi = -rs[(size_t)(i - 1) * kTriThreads + threadIdx.x] * yi;
-        if (i >= i0) {
-          const double c = wave_sum(act ? wgt * yi : 0.0);
-          if (lane == 0) yw[wv][i - i0] += c;
+  constexpr int NW = kTriThreads / kWave;
+  constexpr int AH = 8;   // rows loaded ahead in the forward recurrence
+  for (int i = threadIdx.x; i < m; i += kTriThreads) acc[i] = 0.0;
+  double* rs = A.scratch + (size_t)r * A.scr_m * kTriThreads;
+  for (int base = 0; base < nq; base += kTriThreads) {
+    const int l = base + threadIdx.x;
+    const double s = s_lo + h * (double)l;
+    const double es = exp(s);
+    const double sigma = es * es;
+    const double wgt = l < nq ? (2.0 / M_PI) * h * es : 0.0;
+    // backward pivots; row i holds q_i = beta_i / d_{i+1}
+    double d = a[m - 1] + sigma;
+    for (int i = m - 2; i >= 0; --i) {
+      const double q = b[i] / d;
+      rs[(size_t)i * kTriThreads + threadIdx.x] = q;
+      d = a[i] + sigma - b[i] * q;
+    }
+    // forward: y_0 = 1 / d_0, y_i = -q_{i-1} y_{i-1}; row i-1 then receives w y_{i-1}
+    double yi = 1.0 / d;
+    for (int i0 = 1; i0 < m; i0 += AH) {
+      double qv[AH];
+#pragma unroll
+      for (int u = 0; u < AH; ++u) qv[u] = i0 + u < m ? rs[(size_t)(i0 + u - 1) * kTriThreads + threadIdx.x] : 0.0;
+#pragma unroll
+      for (int u = 0; u < AH; ++u) {
+        if (i0 + u < m) {
+          rs[(size_t)(i0 + u - 1) * kTriThreads + threadIdx.x] = wgt * yi;
+          yi = -qv[u] * yi;
         }
       }
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < iend - i0; i += kTriThreads) {
-      double s = 0.0;
-      for (int w = 0; w < kTriThreads / kWave; ++w) s += yw[w][i];
-      y[i0 + i] = s;
+    rs[(size_t)(m - 1) * kTriThreads + threadIdx.x] = wgt * yi;
+    __syncthreads();   // the block's rows are complete in memory
+    // row sums: wave wv takes rows wv, wv + NW, ...; a lane adds four nodes, then the wave butterfly
+    for (int i = wv; i < m; i += NW) {
+      const double* row = rs + (size_t)i * kTriThreads;
+      double v = 0.0;
+#pragma unroll
+      for (int c = 0; c < kTriThreads / kWave; ++c) v += row[lane + c * kWave];
+      v = wave_sum(v);
+      if (lane == 0) acc[i] += v;
     }
-    __syncthreads();
+    __syncthreads();   // the rows are rewritten by the next node block
   }
+  for (int i = threadIdx.x; i < m; i += kTriThreads) y[i] = acc[i];
 }
 
 __global__ __launch_bounds__(kTriThreads) void k_tri_log(TriArgs A) {
