@@ -554,7 +554,7 @@ size_t call_bytes(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3
   b += (size_t)k * z.vec_bytes;                       // q
   if (Q->precond || Q->ic) b += (size_t)k * z.vec_bytes;                               // FFT / solve scratch
   if (Q->precond && !lgcp_path(Q)) b += precond_step_bytes(Q->plan, Q->storage, (int)k);   // band tables
-  b += (size_t)k * (m_max + 2) * 8 * 4 + (size_t)k * 16;  // scalars
+  b += (size_t)k * (m_max + 2) * 8 * 4 + (size_t)k * 32;  // scalars, flags, poll values
   b += (fused_path(Q, reorth) ? 6 : 3) * (size_t)k * z.pstride * 8;   // partials (two sets when fused)
   if (reorth) b += (size_t)k * (m_max + 1) * (z.Pb + 1) * 8;
   if (!ring3) b += (size_t)k * m_max * 8 + tri_scratch_doubles((int)k, m_max) * 8;
@@ -649,6 +649,7 @@ struct Run {
   int pb_first = 0;      // partial count of the init kernel (iteration 1's opener)
   double* part_h = nullptr;
   double* h = nullptr;
+  double* pollv = nullptr;        // 2 k doubles: active flags and rho_{j-1}, gathered for a stop poll
   bool ring3 = false;
   bool fused = false;             // one pass per step (k_lanczos2d); partial sums alternate between ps[0], ps[1]
   double* ps[2][3] = {};          // {quadratic form, ||w||^2, <w, v>} partial sums
@@ -693,6 +694,7 @@ gmrf_status setup_state(Run<T>& R, Workspace& ws) {
   const int nsets = R.fused ? 6 : 3;
   const size_t nd = (size_t)k * (m + 1) * 3 + (size_t)k * (m + 2) + nsets * (size_t)k * R.z.pstride;
   if ((s = ws.alloc(nd, &dbuf)) != GMRF_OK) return s;
+  if ((s = ws.alloc((size_t)2 * k, &R.pollv)) != GMRF_OK) return s;
   int* ibuf;
   if ((s = ws.alloc((size_t)3 * k, &ibuf)) != GMRF_OK) return s;
   LzState& S = R.S;
@@ -745,6 +747,20 @@ int* poll_buffer(int k) {
     if (buf) (void)hipHostFree(buf);
     buf = nullptr;
     if (hipHostMalloc((void**)&buf, (size_t)std::max(k, 64) * sizeof(int), hipHostMallocDefault) != hipSuccess)
+      return nullptr;
+    cap = std::max(k, 64);
+  }
+  return buf;
+}
+
+// pinned buffer for the residuals read at a poll, per host thread
+double* poll_rho_buffer(int k) {
+  static thread_local double* buf = nullptr;
+  static thread_local int cap = 0;
+  if (cap < k) {
+    if (buf) (void)hipHostFree(buf);
+    buf = nullptr;
+    if (hipHostMalloc((void**)&buf, (size_t)std::max(k, 64) * sizeof(double), hipHostMallocDefault) != hipSuccess)
       return nullptr;
     cap = std::max(k, 64);
   }
@@ -807,28 +823,54 @@ template <typename T>
 gmrf_status run_loop(std::vector<Run<T>>& Rs, const std::function<gmrf_status(int)>& on_done = nullptr) {
   int ktot = 0;
   for (auto& R : Rs) ktot += R.k;
-  int* pb = poll_buffer(ktot);
-  if (!pb) return fail(GMRF_ENOMEM, "pinned host buffer allocation failed");
+  double* ph = poll_rho_buffer(2 * ktot);   // per group: k active flags, then k residuals
+  if (!ph) return fail(GMRF_ENOMEM, "pinned host buffer allocation failed");
   std::vector<char> live(Rs.size(), 1);
   const int m_max = Rs[0].m_max;
-  int poll = 8;
+  const bool predict = Rs[0].S.tol > 0.0;
+  // Stop polls: every 8, 16, then 32 steps, or sooner where the residuals predict the last column's
+  // stop.  rho_{j-1} of every column is read with the active flags; its geometric rate since the previous
+  // poll (rho_0 = 1 before the first) gives each running column's remaining steps.  Polls only decide
+  // when the host stops launching steps that every column would skip; results do not depend on them.
+  std::vector<double> rho_prev((size_t)ktot, 1.0);
+  int j_prev = 1, interval = 8, next_poll = 8;
   for (int j = 1; j <= m_max; ++j) {
     iterate_all<T>(Rs, j, live);
-    if (j % poll == 0 && j < m_max) {
+    if (j == next_poll && j < m_max) {
       HIP_TRY(hipGetLastError());
       int off = 0;
       for (size_t g = 0; g < Rs.size(); ++g) {
-        if (live[g])
-          HIP_TRY(hipMemcpyAsync(pb + off, Rs[g].S.active, Rs[g].k * sizeof(int), hipMemcpyDeviceToHost, Rs[g].st));
+        if (live[g]) {
+          launch_poll_gather(Rs[g].S, j, Rs[g].pollv, Rs[g].st);
+          HIP_TRY(hipMemcpyAsync(ph + 2 * off, Rs[g].pollv, 2 * (size_t)Rs[g].k * sizeof(double),
+                                 hipMemcpyDeviceToHost, Rs[g].st));
+        }
         off += Rs[g].k;
       }
       bool any = false;
+      double need = 0.0;   // steps until the slowest running column is predicted to stop (0: unknown)
+      bool known = predict;
       off = 0;
       for (size_t g = 0; g < Rs.size(); ++g) {
         if (live[g]) {
           HIP_TRY(hipStreamSynchronize(Rs[g].st));
           bool a = false;
-          for (int r = 0; r < Rs[g].k; ++r) a |= pb[off + r] != 0;
+          const double* act = ph + 2 * off;
+          const double* rh = act + Rs[g].k;
+          for (int r = 0; r < Rs[g].k; ++r) {
+            if (act[r] == 0.0) continue;
+            a = true;
+            if (!known) continue;
+            const double rn = rh[r], rp = rho_prev[(size_t)(off + r)];
+            if (!(rn > 0.0) || !(rp > rn) || !std::isfinite(rn)) {
+              known = false;
+              continue;
+            }
+            const double rate = std::log(rn / rp) / (double)(j - j_prev);
+            need = std::max(need, std::log(Rs[g].S.tol / rn) / rate);
+          }
+          if (predict)
+            for (int r = 0; r < Rs[g].k; ++r) rho_prev[(size_t)(off + r)] = rh[r];
           live[g] = a;
           if (!a) {
             // every column of this group has stopped: its closing work can overlap the other groups' steps
@@ -843,7 +885,11 @@ gmrf_status run_loop(std::vector<Run<T>>& Rs, const std::function<gmrf_status(in
         off += Rs[g].k;
       }
       if (!any) break;
-      poll = std::min(poll * 2, 32);
+      j_prev = j;
+      interval = std::min(interval * 2, 32);
+      int step = interval;
+      if (known && need > 0.0) step = std::max(1, std::min(step, (int)std::ceil(need)));
+      next_poll = j + step;
     }
   }
   for (size_t g = 0; g < Rs.size(); ++g) {

@@ -20,6 +20,8 @@ void launch_rademacher_i8(uint64_t seed, long n, int nprobes, int8_t* out, hipSt
 template <typename T> void launch_update(const T* Qb, const T* Vj, T* W, long L, int j, int with_norm, const LzState& S, hipStream_t st);
 void launch_hutchinson_aggregate(const double* g, const double* beta, int ldb, int np, int K, double shift, double* out, hipStream_t st);
 void launch_finalize(const LzState& S, hipStream_t st);
+// out[r] = active[r], out[k + r] = rho_{j-1} of column r (2 k doubles, device)
+void launch_poll_gather(const LzState& S, int j, double* out, hipStream_t st);
 template <typename T> void launch_norm_partials(const T* V0, long L, const LzState& S, hipStream_t st);
 // norm partials per column the reorthogonalisation's last pass writes (vectors of L elements)
 int reorth_blocks(long L);

@@ -606,6 +606,18 @@ void launch_hutchinson_aggregate(const double* g, const double* beta, int ldb, i
 // ---- host launchers ---------------------------------------------------------------------------
 static inline dim3 ew_grid(long L, int k) { return dim3((unsigned)((L + kEwChunk - 1) / kEwChunk), (unsigned)k); }
 // in batch mode L is the longest column; shorter columns' surplus blocks return at once
+// Stop poll: out[r] = active[r], out[k + r] = rho_{j-1} of column r, one contiguous block for a single copy.
+__global__ __launch_bounds__(256) void k_poll_gather(LzState S, int j, double* __restrict__ out) {
+  for (int r = blockIdx.x * 256 + threadIdx.x; r < S.k; r += gridDim.x * 256) {
+    out[r] = (double)S.active[r];
+    out[S.k + r] = S.rho[lz_ia(S, r, j - 1)];
+  }
+}
+
+void launch_poll_gather(const LzState& S, int j, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_poll_gather, dim3((unsigned)std::min(64, (S.k + 255) / 256)), dim3(256), 0, st, S, j, out);
+}
+
 int ew_blocks(long L) { return (int)((L + kEwChunk - 1) / kEwChunk); }
 
 template <typename T>
