@@ -918,17 +918,20 @@ int groups_for(const gmrf_op* Q, int64_t k) {
 }
 
 // Side streams of the calling host thread on the current device (default priority, created once).
+// Created on first use only: the process has few hardware queues, and streams beyond them share one, where
+// work on one stream waits behind work on the other.
 gmrf_status side_streams(hipStream_t* out, int count) {
-  static thread_local std::map<int, std::array<hipStream_t, kMaxGroups>> cache;
+  static thread_local std::map<int, std::vector<hipStream_t>> cache;
+  if (count > kMaxGroups) return fail(GMRF_EINVAL, "at most %d side streams", kMaxGroups);
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
-  auto it = cache.find(dev);
-  if (it == cache.end()) {
-    std::array<hipStream_t, kMaxGroups> a{};
-    for (auto& x : a) HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-    it = cache.emplace(dev, a).first;
+  std::vector<hipStream_t>& v = cache[dev];
+  while ((int)v.size() < count) {
+    hipStream_t x;
+    HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    v.push_back(x);
   }
-  for (int i = 0; i < count; ++i) out[i] = it->second[i];
+  for (int i = 0; i < count; ++i) out[i] = v[(size_t)i];
   return GMRF_OK;
 }
 

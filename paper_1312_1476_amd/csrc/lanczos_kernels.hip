@@ -434,7 +434,24 @@ __global__ __launch_bounds__(kEwThreads) void k_combine(const T* __restrict__ V,
       for (int t = threadIdx.x; t < tn; t += kEwThreads)
         cl[t] = beta0 * y[(size_t)r * ldy + t0 + t] / S.beta[lz_ib(S, r, t0 + t)];
       __syncthreads();
-      for (int t = 0; t < tn; ++t) {
+      // four basis vectors' loads in flight, then the sums in t order
+      int t = 0;
+      for (; t + 3 < tn; t += 4) {
+        const T* v0 = V + (size_t)(t0 + t) * vs + voff;
+        double x[4][kEwPerThread];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          EW_LOOP(q) {
+            const long e = base + (long)q * kEwThreads;
+            x[u][q] = (e < len) ? (double)v0[(size_t)u * vs + e] : 0.0;
+          }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double ct = cl[t + u];
+          EW_LOOP(q) acc[q] += ct * x[u][q];
+        }
+      }
+      for (; t < tn; ++t) {
         const T* vt = V + (size_t)(t0 + t) * vs + voff;
         const double ct = cl[t];
         EW_LOOP(q) {
