@@ -8,13 +8,14 @@ Workload (one "step" = one pass of the whole sampling path over one batch):
 
 Headline value: samples/s at <= 1e-5 relative error.  With this preconditioner the operator
 keeps cond(A) ~ 1.7e4, so 1e-5 needs m ~ 480 steps (rho <= 1e-5) in FP64 storage; FP32
-storage floors near 5e-5 on this operator and m_max = 300 stops near 3e-4.  Those runs are
+storage floors near 8e-5 on this operator and m_max = 300 stops near 3e-4.  Those runs are
 reported beside the headline ("at_m_max_300", "fp32").  The relative error of column 0 is
 measured against the CPU oracle's converged sample (full reorthogonalisation, rho <= 1e-10).
 
-Roofline: the dominant kernel of the step is timed alone with HIP events on the stream it
-runs on; algorithmic bytes per launch are stated in the design doc.  cpu_baseline: the oracle
-(NumPy/SciPy FP64) on one column of the same workload with the same stopping rule.
+Roofline: the dominant kernel of the step (the preconditioned step kernel) is timed alone with
+HIP events on the stream it runs on; its algorithmic bytes per launch are 3 s n k (read v_j and
+v_{j-1}, write w_j; s = 8 bytes, n = 512^2, k = 32).  cpu_baseline: the oracle (NumPy/SciPy FP64)
+on one column of the same workload with the same stopping rule.
 """
 import argparse
 import json
@@ -68,7 +69,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (samples, probes and "
-              "fields shard across GPUs without communication; see DESIGN.md)", file=sys.stderr)
+              "fields shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
     _ensure_built()
     import torch

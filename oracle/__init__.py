@@ -27,7 +27,7 @@ linear algebra, closed forms, published invariants or an independent library rou
 except the items listed in ``PARITY_UNPINNED`` below.
 """
 
-# Functions for which no independent pin exists (the judge caps parity at "partial").
+# Functions for which no independent pin exists (their parity is partial).
 PARITY_UNPINNED = (
     # Table 1 iteration counts: the paper's LGCP inputs (covariance, point pattern,
     # intensity) are never given, so its printed counts cannot be reproduced.
