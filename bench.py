@@ -197,6 +197,19 @@ def main():
                                "m_used_max": max(i["m_used"] for i in i2p),
                                "basis_bytes_one_pass": (M_MAX_HEADLINE + 1) * vec, "basis_bytes_two_pass": 3 * vec,
                                "max_abs_diff_vs_one_pass": float((X2p - X).abs().max())}
+    # the same batch without the preconditioner at the workload's m_max = 300: it stops at m_max far from
+    # 1e-5, which is what the preconditioner is for
+    opq = gm.Operator.lattice(sp.shape, sp.order, sp.kappa2, sp.tau, sp.boundary, "f64")
+    step(opq, TOL_HEADLINE, c.m_max)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Xu, iu = step(opq, TOL_HEADLINE, c.m_max)
+    torch.cuda.synchronize()
+    dtu = time.perf_counter() - t0
+    extra["unprec"] = {"samples_per_s": round(k / dtu, 2), "ms_per_step": round(1000 * dtu, 3),
+                       "m_used": iu[0]["m_used"], "status": iu[0]["status"], "rho": iu[0]["rel_residual"],
+                       "x_col0": Xu[0].cpu().numpy()}
+    opq.close()
     # FP32 storage with the headline stopping rule (reaches its accuracy floor)
     step(op32, TOL_HEADLINE, M_MAX_HEADLINE)
     torch.cuda.synchronize()
@@ -266,7 +279,7 @@ def main():
             "headline_rel_err_col0": rel(x0),
             "parity_vs_oracle_same_rule_col0": float(np.linalg.norm(x0 - ro.x) / np.linalg.norm(ro.x)),
         }
-        for key in ("f64", "f32", "f32_tol"):
+        for key in ("f64", "f32", "f32_tol", "unprec"):
             extra[key]["rel_err_col0"] = rel(extra[key]["x_col0"])
         if "plain_64x64" in result:
             from oracle import closed_form as ocf
@@ -293,6 +306,7 @@ def main():
             result[key] = _public(result[key])
     result["at_m_max_300"] = {"f64": extra["f64"], "f32": extra["f32"]}
     result["fp32_storage_at_tol"] = extra["f32_tol"]
+    result["unpreconditioned_at_m_max_300"] = extra["unprec"]
     print(json.dumps(result))
 
 
