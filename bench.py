@@ -289,6 +289,13 @@ def main():
             ex = ocf.exact_sample_free(sp0.shape, sp0.order, sp0.kappa2, sp0.tau, z0)
             result["plain_64x64"]["rel_err_vs_exact"] = float(np.linalg.norm(result["plain_64x64"]["_x"] - ex)
                                                               / np.linalg.norm(ex))
+        if "logdet" in result:
+            from oracle import closed_form as ocf
+            sp3 = workloads.C3_LATTICE
+            ex = ocf.exact_logdet(sp3.shape, sp3.order, sp3.kappa2, sp3.tau, sp3.boundary)
+            result["logdet"]["exact"] = ex
+            for v in result["logdet"]["variants"].values():
+                v["z_score"] = (v["estimate"] - ex) / v["std_err"]
         if "uneven_batch" in result:
             from oracle import closed_form as ocf
             errs = []
@@ -399,6 +406,12 @@ def logdet_leg(gm, torch):
         out["variants"][f"p{p}"] = {"classes": K, "probes": npb, "columns": npb * K, "estimate": mean,
                                     "std_err": se, "var_per_column": se * se * npb * K,
                                     "ms": round(1000 * dt, 2), "columns_per_s": round(npb * K / dt, 1)}
+        if p == 2:
+            # the same probes with twice the quadrature steps: the change is the m = 80 quadrature's bias,
+            # which the standard error (probe variance only) does not see
+            mean2, se2, _ = op.logdet_coloured(npb, 2 * workloads.C3_M, col, seed=seed)
+            out["variants"]["p2_m160"] = {"classes": K, "probes": npb, "m": 2 * workloads.C3_M, "estimate": mean2,
+                                          "std_err": se2}
     op.close()
     return out
 
@@ -459,7 +472,8 @@ def plain_leg(gm, torch, reps=20):
         X, info = op.sample(Z, tol=c.tol, m_max=c.m_max, reorth=c.reorth)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
-    out = {"samples_per_s": round(1.0 / dt, 2), "ms_per_sample": round(1000 * dt, 3), "m_used": info[0]["m_used"],
+    out = {"samples_per_s": round(1.0 / dt, 2), "ms_per_sample": round(1000 * dt, 3),
+           "us_per_iteration": round(1e6 * dt / max(1, info[0]["m_used"]), 1), "m_used": info[0]["m_used"],
            "rho": info[0]["rel_residual"], "status": info[0]["status"], "reorth": "CGS2",
            "_x": X[0].cpu().numpy()}   # for the accuracy check beside the oracle leg (removed before printing)
     op.close()
