@@ -457,6 +457,7 @@ gmrf_status upload_trsv(const std::vector<int64_t>& rp, const std::vector<int32_
       (s = upload_vals(pva, storage, &d.va)) != GMRF_OK || (s = upload_vals(pdinv, storage, &d.dinv)) != GMRF_OK)
     return s;
   d.nlev = (int)lvl_ptr.size() - 1;
+  d.nnz = (int64_t)pci.size();
   return GMRF_OK;
 }
 }  // namespace

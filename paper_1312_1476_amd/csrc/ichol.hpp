@@ -37,6 +37,7 @@ struct TrsvDev {
   void* va = nullptr;
   void* dinv = nullptr;
   int nlev = 0;
+  int64_t nnz = 0;      // strictly-triangular entries
 };
 struct IcholDev {
   TrsvDev fwd, bwd;     // L y = b, L^T x = y

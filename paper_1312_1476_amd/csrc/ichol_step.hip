@@ -10,6 +10,7 @@ namespace gmrf {
 
 constexpr int kTrsvThreads = 1024;
 constexpr int64_t kTrsvLdsRows = 8192;   // x of up to this many rows is kept in LDS (64 KB of FP64)
+constexpr size_t kTrsvLdsMaxBytes = 160 * 1024;   // whole solve in LDS up to the CU's LDS size
 
 // x = T^{-1} b, T = D + N with N strictly triangular, stored in level order (TrsvDev).  Only the x
 // values carry the dependency between levels; every row's indices and values are known in advance.
@@ -33,7 +34,21 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_levels(const int32_t* __r
       const int i = rows[p];
       double s = (double)b[i];
       const int64_t q1 = rp[p + 1];
-      for (int64_t e = rp[p]; e < q1; ++e) s -= (double)va[e] * (XLDS ? xs[ci[e]] : (double)x[ci[e]]);
+      int64_t e = rp[p];
+      for (; e + 3 < q1; e += 4) {   // four entries' loads issued before the sums (same order)
+        int c[4];
+        double xv[4], lv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          c[u] = ci[e + u];
+          lv[u] = (double)va[e + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = XLDS ? xs[c[u]] : (double)x[c[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s -= lv[u] * xv[u];
+      }
+      for (; e < q1; ++e) s -= (double)va[e] * (XLDS ? xs[ci[e]] : (double)x[ci[e]]);
       s *= (double)dinv[p];
       if (XLDS) xs[i] = s;
       else x[i] = (OutT)s;
@@ -42,6 +57,78 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_levels(const int32_t* __r
   }
   if (XLDS)
     for (long i = threadIdx.x; i < n; i += kTrsvThreads) x[i] = (OutT)xs[i];
+}
+
+// The same solve with the whole factor in LDS as well (values, column indices, row starts, level
+// pointers and 1 / l_ii), staged once per block: every level's loads are then LDS loads, not two
+// dependent L2 round trips.  x starts as b in LDS (a row's own entry is read only by itself).  Same
+// arithmetic in the same order as k_trsv_levels.
+template <typename T, typename OutT>
+__global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __restrict__ lvl_ptr,
+                                                           const int32_t* __restrict__ rows,
+                                                           const int64_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ ci,
+                                                           const T* __restrict__ va, const T* __restrict__ dinv,
+                                                           int nlev, long n, long nnz, const T* __restrict__ B,
+                                                           long bld, OutT* X, long xld,
+                                                           const int* __restrict__ active) {
+  extern __shared__ double smem[];
+  const int r = blockIdx.x;
+  if (active && !active[r]) return;   // one value per block: the whole block returns or none does
+  double* xs = smem;
+  T* sd = (T*)(xs + n);
+  T* sv = sd + n;
+  int32_t* srp = (int32_t*)(sv + nnz);
+  int32_t* sci = srp + n + 1;
+  int32_t* srow = sci + nnz;
+  int32_t* slv = srow + n;
+  const T* b = B + (size_t)r * bld;
+  for (long i = threadIdx.x; i < n; i += kTrsvThreads) {
+    xs[i] = (double)b[i];
+    sd[i] = dinv[i];
+    srow[i] = rows[i];
+  }
+  for (long i = threadIdx.x; i <= n; i += kTrsvThreads) srp[i] = (int32_t)rp[i];
+  for (long e = threadIdx.x; e < nnz; e += kTrsvThreads) {
+    sv[e] = va[e];
+    sci[e] = ci[e];
+  }
+  for (int l = threadIdx.x; l <= nlev; l += kTrsvThreads) slv[l] = lvl_ptr[l];
+  __syncthreads();
+  for (int lev = 0; lev < nlev; ++lev) {
+    const int e0 = slv[lev], e1 = slv[lev + 1];
+    for (int p = e0 + (int)threadIdx.x; p < e1; p += kTrsvThreads) {
+      const int i = srow[p];
+      double s = xs[i];
+      const int q1 = srp[p + 1];
+      int e = srp[p];
+      for (; e + 3 < q1; e += 4) {   // four entries' index and x loads issued before the sums (same order)
+        int c[4];
+        double xv[4], lv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = sci[e + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          xv[u] = xs[c[u]];
+          lv[u] = (double)sv[e + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s -= lv[u] * xv[u];
+      }
+      for (; e < q1; ++e) s -= (double)sv[e] * xs[sci[e]];
+      xs[i] = s * (double)sd[p];
+    }
+    __syncthreads();   // this level's x are visible to the block before the next level reads them
+  }
+  OutT* x = X + (size_t)r * xld;
+  for (long i = threadIdx.x; i < n; i += kTrsvThreads) x[i] = (OutT)xs[i];
+}
+
+// LDS bytes of k_trsv_lds for a solve (0: does not fit)
+template <typename T>
+static size_t trsv_lds_bytes(const TrsvDev& d, int64_t n) {
+  const size_t b = (size_t)n * 8 + (size_t)(n + d.nnz) * sizeof(T) + (size_t)(2 * n + 1 + d.nnz + d.nlev + 1) * 4;
+  return b <= kTrsvLdsMaxBytes ? b : 0;
 }
 
 // Opener of iteration j plus q = AX / beta_{j-1} - beta_{j-1} v_{j-1} and partial sums of v_j^T q.
@@ -76,6 +163,20 @@ template <typename T, typename OutT>
 void launch_trsv(const IcholDev& f, bool upper, const T* B, long bld, OutT* X, long xld, const int* active, int k,
                  hipStream_t st) {
   const TrsvDev& d = upper ? f.bwd : f.fwd;
+  const size_t lb = trsv_lds_bytes<T>(d, f.n);
+  if (lb) {
+    static bool attr_set = false;   // the launch needs more than the default dynamic LDS
+    if (!attr_set) {
+      attr_set = hipFuncSetAttribute((const void*)k_trsv_lds<T, OutT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kTrsvLdsMaxBytes) == hipSuccess;
+      (void)hipGetLastError();
+    }
+    if (attr_set || lb <= 65536) {
+      hipLaunchKernelGGL((k_trsv_lds<T, OutT>), dim3(k), dim3(kTrsvThreads), lb, st, d.lvl_ptr, d.rows, d.rp, d.ci,
+                         (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, (long)d.nnz, B, bld, X, xld, active);
+      return;
+    }
+  }
   if (f.n <= kTrsvLdsRows)
     hipLaunchKernelGGL((k_trsv_levels<T, OutT, true>), dim3(k), dim3(kTrsvThreads), (size_t)f.n * sizeof(double), st,
                        d.lvl_ptr, d.rows, d.rp, d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, B, bld,
