@@ -710,9 +710,24 @@ __global__ __launch_bounds__(256) void k_csr(long n, const int64_t* __restrict__
   double acc = 0.0;
   if (row < n) {
     T s = (T)0;
-    for (int64_t e = rp[row]; e < rp[row + 1]; ++e) {
-      const T raw = src[ci[e]];
-      s += va[e] * (LZ ? (T)((double)raw * s_cur) : raw);
+    const int64_t e1 = rp[row + 1];
+    int64_t e = rp[row];
+    for (; e + 3 < e1; e += 4) {   // four entries' loads issued before the sums (same order)
+      int32_t c[4];
+      T a[4], raw[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        c[u] = ci[e + u];
+        a[u] = va[e + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) raw[u] = src[c[u]];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s += a[u] * (LZ ? (T)((double)raw[u] * s_cur) : raw[u]);
+    }
+    for (; e < e1; ++e) {
+      const T raw1 = src[ci[e]];
+      s += va[e] * (LZ ? (T)((double)raw1 * s_cur) : raw1);
     }
     if (LZ) {
       double q = (double)s;
