@@ -468,10 +468,18 @@ __global__ __launch_bounds__(kEwThreads) void k_combine(const T* __restrict__ V,
   }
 }
 
-// FP32 storage with 16-byte aligned columns: the same sums with float4 loads, 4096 elements per block
-// (16 KB of each basis vector) and two basis vectors in flight.  Each element still accumulates
-// beta_0 y_t / beta_t v_{t+1}[e] in t order, as k_combine does.
-constexpr int kCbVec = 4;                                // float4 loads per thread and basis vector
+// FP32 storage with 16-byte aligned columns: the same sums with one float4 load per thread and basis
+// vector (1024 elements per block, so short columns of an uneven batch leave few lanes idle) and four
+// basis vectors in flight.  Each element still accumulates beta_0 y_t / beta_t v_{t+1}[e] in t order,
+// as k_combine does.
+#ifndef GMRF_CB_VEC
+#define GMRF_CB_VEC 1
+#endif
+#ifndef GMRF_CB_T
+#define GMRF_CB_T 4
+#endif
+constexpr int kCbVec = GMRF_CB_VEC;                      // float4 loads per thread and basis vector
+constexpr int kCbT = GMRF_CB_T;                          // basis vectors in flight
 constexpr int kCbChunk = kEwThreads * kCbVec * 4;        // elements per block
 
 template <typename OutT>
@@ -521,19 +529,17 @@ __global__ __launch_bounds__(kEwThreads) void k_combine_f32v(const float* __rest
         cl[t] = beta0 * y[(size_t)r * ldy + t0 + t] / S.beta[lz_ib(S, r, t0 + t)];
       __syncthreads();
       int t = 0;
-      for (; t + 1 < tn; t += 2) {
+      for (; t + kCbT - 1 < tn; t += kCbT) {
         const float* va = V + (size_t)(t0 + t) * vs + voff;
-        const float* vb = va + vs;
-        float4 xa[kCbVec], xb[kCbVec];
+        float4 xa[kCbT][kCbVec];
 #pragma unroll
-        for (int q = 0; q < kCbVec; ++q) {
-          xa[q] = load(va, base + (long)q * kEwThreads * 4);
-          xb[q] = load(vb, base + (long)q * kEwThreads * 4);
-        }
-        add(cl[t], xa);
-        add(cl[t + 1], xb);
+        for (int u = 0; u < kCbT; ++u)
+#pragma unroll
+          for (int q = 0; q < kCbVec; ++q) xa[u][q] = load(va + (size_t)u * vs, base + (long)q * kEwThreads * 4);
+#pragma unroll
+        for (int u = 0; u < kCbT; ++u) add(cl[t + u], xa[u]);
       }
-      if (t < tn) {
+      for (; t < tn; ++t) {
         const float* va = V + (size_t)(t0 + t) * vs + voff;
         float4 xa[kCbVec];
 #pragma unroll
