@@ -95,3 +95,27 @@ def test_uneven_batch_workload_full_size(gm):
             ref = lanczos.sample_csr(Q, Zs[f][:, r], i["m_used"], tol=0.0)
             tol = 1e-8 if i["status"] == "OK" else 10 * ref.rho[-1]
             assert _rel(X[r], ref.x) <= tol, (f, r, _rel(X[r], ref.x), i)
+
+
+def test_batch_edge_columns(gm):
+    """Columns that stop at the first step inside a batch: a zero right-hand side (m = 0, x = 0) and a
+    non-finite one (EINVAL, NaN). The other columns keep running on the shrinking (column, tile) list and
+    equal the same fields sampled on their own, bit for bit."""
+    import torch
+    specs = [((20, 20), 0.3), ((33, 17), 0.05), ((64, 64), 0.01)]
+    ops = [gm.Operator.lattice(sh, 1, k2, 1.0, "free", "f64") for sh, k2 in specs]
+    Zs = [workloads.gaussian_block(sh[0] * sh[1], 2, 95, f) for f, (sh, _) in enumerate(specs)]
+    Zs[1][:, 0] = 0.0
+    Zs[2][7, 1] = np.nan
+    Xs, info = gm.sample_batch(ops, [_t(Z.T) for Z in Zs], tol=1e-8, m_max=400)
+    assert info[2]["status"] == "OK" and info[2]["m_used"] == 0
+    assert torch.all(Xs[1][0] == 0)
+    assert info[5]["status"] == "EINVAL" and torch.all(torch.isnan(Xs[2][1]))
+    for f, (op, Z) in enumerate(zip(ops, Zs)):
+        Xa, ia = op.sample(_t(Z.T), tol=1e-8, m_max=400)
+        for r in range(2):
+            c = 2 * f + r
+            if c in (2, 5):
+                continue
+            assert info[c]["status"] == "OK" and info[c]["m_used"] == ia[r]["m_used"]
+            assert torch.equal(Xs[f][r], Xa[r]), (f, r)
