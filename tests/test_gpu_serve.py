@@ -134,3 +134,22 @@ def test_two_pass_fallback(env):
     assert [i["m_used"] for i in i1] == [i["m_used"] for i in req2.result["info"]]
     assert float((req2.result["X"] - X1).norm() / X1.norm()) <= 1e-12
     assert serve.stats([req2], 1.0)["two_pass"] == 1
+
+
+def test_budget_call_returns_cached_scratch(env):
+    """Scratch of finished calls stays cached in the library's pool for reuse; setting the HBM budget
+    hands it back to the device, so the memory the caller then sees free includes it."""
+    import torch
+    gm, serve, ops = env
+    op = gm.Operator.lattice((256, 256), 1, 0.05, 1.0, "free", "f64")
+    Z = torch.randn((8, op.n), dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+    need = op.bytes(8, 600, False)
+    assert need > (256 << 20)
+    op.sample(Z, tol=0.0, m_max=600)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free_cached, _ = torch.cuda.mem_get_info()
+    gm.set_hbm_budget(0)
+    free_after, _ = torch.cuda.mem_get_info()
+    assert free_after - free_cached >= need // 2, (free_cached, free_after, need)
+    op.close()
