@@ -37,6 +37,7 @@ COPY_BYTES = 512 << 20           # reference copy of the counter runs (--only co
 # WRITE_SIZE x 1 (KiB per dispatch, scaled by the reference copy's readings); None if the kernel changed
 TRAFFIC_BYTES = 225601472      # k_step<double, 64, true>, 512x512, 32 fields (profiles/k_step_precond_512x512_32rhs_fp64.md)
 TOL_HEADLINE = 1e-5
+INFINITY_CACHE_BYTES = 256 << 20
 SERVE_RATES = (2, 4, 8)          # requests/s of the serving leg (the queue saturates near 8-16)
 M_MAX_HEADLINE = 600
 
@@ -225,7 +226,10 @@ def main():
     result["roofline"] = {"bound": "hbm", "achieved": round(roof["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": round(roof["achieved_gbs"] / HBM_PEAK_GBS, 4),
                           "traffic": TRAFFIC_BYTES, "kernel": roof["kernel"], "avg_us": round(roof["avg_us"], 2),
-                          "bytes_per_launch": roof["bytes"]}
+                          "bytes_per_launch": roof["bytes"],
+                          # the launch's vectors fit the 256 MB Infinity Cache (as they do in the sampling loop,
+                          # where v_j and v_{j-1} were written one and two steps before)
+                          "cache_resident": roof["bytes"] < INFINITY_CACHE_BYTES}
     kern = {}
     for name in ("lz_band", "lz_dots"):
         r = gm.kernel_bench(op64, name, k, reps=50, stream=stream)
