@@ -242,6 +242,17 @@ def main():
         spmv[name] = {"achieved_gbs": round(r["achieved_gbs"], 1), "frac_of_peak": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
                       "avg_us": round(r["avg_us"], 2), "bytes_per_launch": r["bytes"]}
     result["spmv_13pt_32rhs"] = spmv
+    # the same operator on 1024 x 1024 (537 MB per FP64 launch, beyond the 256 MB Infinity Cache): HBM-resident
+    spmv_big = {}
+    for storage in ("f64", "f32"):
+        opb = gm.Operator.lattice((1024, 1024), sp.order, sp.kappa2, sp.tau, sp.boundary, storage)
+        r = gm.kernel_bench(opb, "spmv", k, reps=20, stream=stream)
+        spmv_big[storage] = {"achieved_gbs": round(r["achieved_gbs"], 1),
+                             "frac_of_peak": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                             "avg_us": round(r["avg_us"], 2), "bytes_per_launch": r["bytes"],
+                             "cache_resident": r["bytes"] < INFINITY_CACHE_BYTES}
+        opb.close()
+    result["spmv_13pt_1024x1024_32rhs"] = spmv_big
 
     # ---- log-Gaussian Cox process proposal (Q + H, M = Q): Table 1 and throughput --------------------
     if not args.no_lgcp:
