@@ -153,3 +153,40 @@ def test_budget_call_returns_cached_scratch(env):
     free_after, _ = torch.cuda.mem_get_info()
     assert free_after - free_cached >= need // 2, (free_cached, free_after, need)
     op.close()
+
+
+def test_alone_equals_mix_with_two_pass(env):
+    """A budget that sends the larger samples to the two-pass sampler: each result is still the same
+    alone and in the mix (the mode depends only on the request and the budget)."""
+    import torch
+    gm, serve, ops = env
+    probe = serve.Server(ops, hbm_budget=1 << 40)
+    sizes = [probe.request_bytes(r) for r in _mix(serve)]
+    budget = int(sorted(sizes)[len(sizes) // 2])        # about half the samples do not fit stored
+    alone = {}
+    srv = serve.Server(ops, hbm_budget=budget, workers=1).start()
+    reqs = [r for r in _mix(serve)]
+    for req in reqs:
+        srv.submit(req)
+        req.done.wait()
+        alone[req.rid] = (req.error, req.two_pass, req.result)
+    srv.stop()
+    assert any(tp for e, tp, _ in alone.values() if not e)
+    mix = _mix(serve)
+    srv = serve.Server(ops, hbm_budget=budget, workers=4).start()
+    for req in mix:
+        srv.submit(req)
+    for req in mix:
+        req.done.wait()
+    srv.stop()
+    assert srv.peak_bytes <= budget
+    for req in mix:
+        err, tp, res = alone[req.rid]
+        assert bool(req.error) == bool(err) and req.two_pass == tp, req.rid
+        if err:
+            continue
+        if req.kind == "sample":
+            assert torch.equal(res["X"], req.result["X"]), req.rid
+            assert _same_info(res["info"], req.result["info"])
+        else:
+            assert res["logdet"] == req.result["logdet"]
