@@ -776,6 +776,9 @@ void iterate(Run<T>& R, int j) {
   T* xj = R.slot(j - 1);
   T* xp = j >= 2 ? R.slot(j - 2) : R.slot(0);
   R.S.Pb = (j == 1) ? R.pb_first : R.z.Pb;
+  // plain and incomplete-Cholesky steps with short vectors: the first reorthogonalisation launch also does
+  // the update step
+  const bool upd_in_reorth = R.reorth && !Q->precond && !R.fused && reorth_takes_update(R.z.L);
   if (R.fused) {
     // reads the partial sums in R.S (pass j - 1's; iteration 1: the init kernels' set 0) and writes the other
     // set, which R.S then points to (the next pass and k_finalize read it)
@@ -798,13 +801,13 @@ void iterate(Run<T>& R, int j) {
     launch_csr<T>((long)Q->n, Q->rp, Q->ci, (const T*)Q->va, false, R.F1, Q->n, R.Qb, Q->n, nullptr, R.S, 0, R.k, R.st);
     launch_trsv<T, T>(Q->icd, false, R.Qb, R.z.L, R.F1, R.z.L, R.S.active, R.k, R.st);
     launch_pre_lz<T>(R.F1, xj, xp, R.Qb, R.z.L, R.S, j, R.st);
-    launch_update<T>(R.Qb, xj, R.slot(j), R.z.L, j, R.reorth ? 0 : 1, R.S, R.st);
+    if (!upd_in_reorth) launch_update<T>(R.Qb, xj, R.slot(j), R.z.L, j, R.reorth ? 0 : 1, R.S, R.st);
   } else {
     op_apply_lz<T>(Q, xj, R.Qb, xp, R.S, j, R.k, R.st);
-    launch_update<T>(R.Qb, xj, R.slot(j), R.z.L, j, R.reorth ? 0 : 1, R.S, R.st);
+    if (!upd_in_reorth) launch_update<T>(R.Qb, xj, R.slot(j), R.z.L, j, R.reorth ? 0 : 1, R.S, R.st);
   }
   if (R.reorth) {
-    launch_reorth<T>(R.V, R.z.L, j, R.part_h, R.h, R.m_max + 1, R.S, R.st);
+    launch_reorth<T>(R.V, R.z.L, j, R.part_h, R.h, R.m_max + 1, R.S, R.st, upd_in_reorth ? R.Qb : nullptr);
     if (lgcp_path(Q)) lgcp_col_init<T>(Q->plan, precond_mult(Q), R.slot(j), R.F1, R.k, R.st);
     else if (Q->precond) precond_dots<T>(Q->plan, precond_mult(Q), R.slot(j), R.band, R.S, R.k, R.st);
   }

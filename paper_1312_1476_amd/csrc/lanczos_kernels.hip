@@ -300,13 +300,18 @@ __global__ __launch_bounds__(kEwThreads) void k_reorth_update(T* __restrict__ V,
 // waits on another: active[] is not written during the reorthogonalisation, so it is read directly.
 constexpr int kRoDotTs = 64;   // basis vectors per LDS round
 
+// Qb != nullptr (first pass only): the kernel also does the update step that precedes the
+// reorthogonalisation.  Every block forms alpha_j from the operator's partial sums and
+// w_j = q - alpha_j v_j for its elements (the update kernel's arithmetic); the blocks of slice 0 store w_j
+// and alpha_j, so no block reads slot j in this launch.
 template <typename T>
-__global__ __launch_bounds__(kEwThreads) void k_reorth_dot_short(const T* __restrict__ V, long L, int j,
-                                                                 double* __restrict__ part_h, int hstride,
+__global__ __launch_bounds__(kEwThreads) void k_reorth_dot_short(const T* V, T* Wj, const T* __restrict__ Qb, long L,
+                                                                 int j, double* __restrict__ part_h, int hstride,
                                                                  int tslice, LzState S) {
   constexpr int NW = kEwThreads / kWave;
   constexpr int PER = kEwChunk / kEwThreads;
   __shared__ double red[NW][kRoDotTs];
+  __shared__ double lds[NW];
   const int r = blockIdx.y;
   if (!S.active[r]) return;
   const size_t vs = lz_slot(S, L);
@@ -314,10 +319,30 @@ __global__ __launch_bounds__(kEwThreads) void k_reorth_dot_short(const T* __rest
   const long base = (long)blockIdx.x * kEwChunk + (long)g * (kWave * PER) + lane;
   const T* w = V + (size_t)j * vs + (size_t)r * L;
   double wv[PER];
+  if (Qb) {
+    const double a = sum_partials<kEwThreads>(S.part_a + (size_t)r * S.pstride, lz_pa(S, r), lds);
+    if (blockIdx.x == 0 && blockIdx.z == 0 && threadIdx.x == 0) S.alpha[lz_ia(S, r, j)] = a;
+    const double sc = 1.0 / S.beta[lz_ib(S, r, j - 1)];
+    const T* vj = V + (size_t)(j - 1) * vs + (size_t)r * L;
+    const T* q = Qb + (size_t)r * L;
+    T* wr = Wj + (size_t)r * L;
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const long e = base + (long)q * kWave;
-    wv[q] = (e < L) ? ip_weight(S, e) * (double)w[e] : 0.0;
+    for (int qq = 0; qq < PER; ++qq) {
+      const long e = base + (long)qq * kWave;
+      wv[qq] = 0.0;
+      if (e < L) {
+        const double v = (double)(T)((double)vj[e] * sc);
+        const T t = (T)((double)q[e] - a * v);
+        if (blockIdx.z == 0) wr[e] = t;
+        wv[qq] = ip_weight(S, e) * (double)t;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const long e = base + (long)q * kWave;
+      wv[q] = (e < L) ? ip_weight(S, e) * (double)w[e] : 0.0;
+    }
   }
   const int t1 = min(j, (int)(blockIdx.z + 1) * tslice);
   for (int t0 = (int)blockIdx.z * tslice; t0 < t1; t0 += kRoDotTs) {
@@ -678,9 +703,13 @@ void launch_finalize(const LzState& S, hipStream_t st) {
 }
 int reorth_blocks(long L) { return L <= kRoSmallL ? (int)((L + kRoChunk - 1) / kRoChunk) : ew_blocks(L); }
 
+bool reorth_takes_update(long L) { return L <= kRoSmallL; }
+
+static size_t lz_slot_h(const LzState& S, long L) { return S.slot_stride ? (size_t)S.slot_stride : (size_t)S.k * L; }
+
 template <typename T>
 void launch_reorth(T* V, long L, int j, double* part_h, double* h, int hstride, const LzState& S,
-                   hipStream_t st) {
+                   hipStream_t st, const T* Qb) {
   const dim3 g = ew_grid(L, S.k);
   // t slices for the dot kernel: enough blocks for about two per compute unit, with at least
   // kEwThreads / kWave vectors per slice (one per block for short vectors)
@@ -695,7 +724,8 @@ void launch_reorth(T* V, long L, int j, double* part_h, double* h, int hstride, 
   const dim3 gu((unsigned)reorth_blocks(L), S.k);
   for (int pass = 0; pass < 2; ++pass) {
     if (short_v)
-      hipLaunchKernelGGL(k_reorth_dot_short<T>, gd, dim3(kEwThreads), 0, st, V, L, j, part_h, hstride, tslice, S);
+      hipLaunchKernelGGL(k_reorth_dot_short<T>, gd, dim3(kEwThreads), 0, st, (const T*)V, V + (size_t)j * lz_slot_h(S, L),
+                         pass == 0 ? Qb : (const T*)nullptr, L, j, part_h, hstride, tslice, S);
     else
       hipLaunchKernelGGL(k_reorth_dot<T>, gd, dim3(kEwThreads), 0, st, V, L, j, part_h, hstride, tslice, S);
     if (short_v) {
@@ -735,7 +765,7 @@ void launch_combine(const T* V, long L, const double* y, int ldy, OutT* out, lon
   template void launch_init_rademacher<T>(uint64_t, long, int, T*, const LzState&, hipStream_t, const int32_t*, int);        \
   template void launch_update<T>(const T*, const T*, T*, long, int, int, const LzState&, hipStream_t); \
   template void launch_norm_partials<T>(const T*, long, const LzState&, hipStream_t);              \
-  template void launch_reorth<T>(T*, long, int, double*, double*, int, const LzState&, hipStream_t); \
+  template void launch_reorth<T>(T*, long, int, double*, double*, int, const LzState&, hipStream_t, const T*); \
   template void launch_combine<T, double>(const T*, long, const double*, int, double*, long,       \
                                           const LzState&, hipStream_t);                           \
   template void launch_accumulate<T, double>(const T*, long, const double*, int, const LzState&, int, double*, \
