@@ -28,6 +28,8 @@ struct StencilGeom {
   int epl;                 // 2D operator kernel: elements per lane (1, 2, or 4 for FP32)
   int fepl;                // 2D one-pass Lanczos kernel: elements per lane (1 or 2)
   int ftiles_x;            // 2D one-pass Lanczos kernel: strips per row
+  int band;                // 2D operator kernel: output rows per wave (0: kS2Band)
+  int ftiles_y;            // 2D one-pass Lanczos kernel: bands of kS2Waves x kS2Band rows
 };
 
 // Per-call Lanczos state, all device memory.  Index conventions (1-based j as in

@@ -218,8 +218,9 @@ __device__ __forceinline__ void s2_strip(const StencilGeom& g, int tx, int ty, i
   }
   const bool olane = lane * EPL >= HX && lane * EPL < RW - HX && xb >= 0 && xb < n2;
   const int lm = (lane * EPL - 1) & (RW - 1), lp = (lane * EPL + EPL) & (RW - 1);
-  const int y_lo = (ty * kS2Waves + w) * kS2Band;
-  const int y_hi = min(y_lo + kS2Band, n1);
+  const int band = g.band > 0 ? g.band : kS2Band;
+  const int y_lo = (ty * kS2Waves + w) * band;
+  const int y_hi = min(y_lo + band, n1);
   const int count = y_hi > y_lo ? y_hi - y_lo + 2 * ORDER : 0;   // input rows y_lo - ORDER .. y_hi + ORDER - 1
   if (count == 0) return;
   const int ys = y_lo - ORDER;
@@ -456,7 +457,7 @@ __device__ __forceinline__ void s2f_strip(const StencilGeom& g, int tx, int ty, 
   }
   const bool olane = lane * EPL >= HX && lane * EPL < RW - HX && xb >= 0 && xb < n2;
   const int lm = (lane * EPL - 1) & (RW - 1), lp = (lane * EPL + EPL) & (RW - 1);
-  const int y_lo = (ty * kS2Waves + w) * kS2Band;
+  const int y_lo = (ty * kS2Waves + w) * kS2Band;   // the one-pass kernel keeps full bands (ftiles_y)
   const int y_hi = min(y_lo + kS2Band, n1);
   const int count = y_hi > y_lo ? y_hi - y_lo + 2 * HV : 0;
   if (count == 0) return;
@@ -650,7 +651,7 @@ __global__ __launch_bounds__(256, GMRF_L2D_WAVES) void k_lanczos2d(StencilGeom g
     tile = wt.y;
   }
   const StencilGeom g = S.col_geom ? S.col_geom[r] : g0;
-  if (tile >= g.ftiles_x * g.tiles_y) return;
+  if (tile >= g.ftiles_x * g.ftiles_y) return;
   double s_cur = 1.0, s_prev = 0.0, bprev = 0.0, alpha = 0.0;
   if (MODE == 0) {
     if (!lz_open<256>(S, r, j, tile == 0, red, flag, s_cur, s_prev, bprev)) return;
@@ -763,6 +764,12 @@ void stencil_geom_tiles(StencilGeom& g, int dim, int order, int epl, int vbytes)
     return (double)((g.n2 + ox - 1) / ox) * (kWave * e);
   };
   g.fepl = 1;
+  // band of the operator kernel: 32 rows per wave from 256 rows up; shorter lattices take 16 or 8, so that
+  // their few tiles still spread over more waves with shorter row chains (the one-pass kernel keeps 32:
+  // with many columns in flight its halo rows cost more than the shorter chains save)
+  g.band = kS2Band;
+  if (dim == 2)
+    while (g.band > 8 && g.n1 < 8 * g.band) g.band >>= 1;
   if (dim == 2) {
     if (epl > 0) g.epl = epl;
     else if (g.n2 % 2 != 0) g.epl = 1;
@@ -772,10 +779,11 @@ void stencil_geom_tiles(StencilGeom& g, int dim, int order, int epl, int vbytes)
     else g.fepl = (vbytes == 4 && g.n2 % 4 == 0 && fcover(4) <= 1.15 * fcover(2)) ? 4 : 2;
   }
   if (dim == 1) { TZ = TileShape<1>::TZ; TY = TileShape<1>::TY; TX = TileShape<1>::TX; }
-  else if (dim == 2) { TZ = 1; TY = kS2Waves * kS2Band; TX = s2_out(order, g.epl); }   // k_stencil2d
+  else if (dim == 2) { TZ = 1; TY = kS2Waves * g.band; TX = s2_out(order, g.epl); }   // k_stencil2d
   else { TZ = TileShape<3>::TZ; TY = TileShape<3>::TY; TX = TileShape<3>::TX; }
   g.tiles_x = (g.n2 + TX - 1) / TX;
   g.ftiles_x = dim == 2 ? (g.n2 + s2f_out(order, g.fepl) - 1) / s2f_out(order, g.fepl) : 0;   // k_lanczos2d
+  g.ftiles_y = dim == 2 ? (g.n1 + kS2Waves * kS2Band - 1) / (kS2Waves * kS2Band) : 0;
   g.tiles_y = (g.n1 + TY - 1) / TY;
   g.tiles_z = (g.n0 + TZ - 1) / TZ;
 }
@@ -834,7 +842,7 @@ template void launch_stencil_batch<double>(int, int, int, const double*, double*
 template void launch_stencil_batch<float>(int, int, int, const float*, float*, const float*, const LzState&, int,
                                           hipStream_t);
 
-int lanczos2d_blocks(const StencilGeom& g) { return g.ftiles_x * g.tiles_y; }
+int lanczos2d_blocks(const StencilGeom& g) { return g.ftiles_x * g.ftiles_y; }
 
 template <typename T>
 void launch_lanczos2d(const StencilGeom& g, int order, int mode, int grid_x, const T* X, long xld, T* W,
