@@ -165,12 +165,13 @@ void launch_trsv(const IcholDev& f, bool upper, const T* B, long bld, OutT* X, l
   const TrsvDev& d = upper ? f.bwd : f.fwd;
   const size_t lb = trsv_lds_bytes<T>(d, f.n);
   if (lb) {
-    static bool attr_set = false;   // the launch needs more than the default dynamic LDS
-    if (!attr_set) {
-      attr_set = hipFuncSetAttribute((const void*)k_trsv_lds<T, OutT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)kTrsvLdsMaxBytes) == hipSuccess;
+    // the launch needs more than the default dynamic LDS; set once (thread-safe static initialisation)
+    static const bool attr_set = [] {
+      const bool ok = hipFuncSetAttribute((const void*)k_trsv_lds<T, OutT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)kTrsvLdsMaxBytes) == hipSuccess;
       (void)hipGetLastError();
-    }
+      return ok;
+    }();
     if (attr_set || lb <= 65536) {
       hipLaunchKernelGGL((k_trsv_lds<T, OutT>), dim3(k), dim3(kTrsvThreads), lb, st, d.lvl_ptr, d.rows, d.rp, d.ci,
                          (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, (long)d.nnz, B, bld, X, xld, active);
