@@ -36,7 +36,9 @@ COPY_BYTES = 512 << 20           # reference copy of the counter runs (--only co
 # HBM bytes per launch of the dominant kernel from the committed counter summary: FETCH_SIZE x 2 +
 # WRITE_SIZE x 1 (KiB per dispatch, scaled by the reference copy's readings); None if the kernel changed
 TRAFFIC_BYTES = 225601472      # k_step<double, 64, true>, 512x512, 32 fields (profiles/k_step_precond_512x512_32rhs_fp64.md)
-TOL_HEADLINE = 1e-5
+TOL_HEADLINE = 1e-5              # stopping rule of the headline (rho_m <= tol)
+ERR_HEADLINE = 1e-5              # a headline sample counts when its relative error is within this
+REF_TOL, REF_M_MAX = 1e-10, 1024 # converged FP64 reference of the headline columns
 INFINITY_CACHE_BYTES = 256 << 20
 SERVE_RATES = (2, 4, 8)          # requests/s of the serving leg (the queue saturates near 8-16)
 M_MAX_HEADLINE = 600
@@ -138,9 +140,16 @@ def main():
     dt = (time.perf_counter() - t0) / args.steps
     m_used = [i["m_used"] for i in info]
     x0 = X[0].cpu().numpy()
+    # every column against the same columns run to convergence (FP64, rho <= 1e-10, m_max = 1024; the
+    # full-size parity test pins this run to the oracle at 1e-8): only samples within 1e-5 count
+    Xref, iref = step(op64, REF_TOL, REF_M_MAX)
+    torch.cuda.synchronize()
+    errs = ((X - Xref).norm(dim=1) / Xref.norm(dim=1)).cpu().numpy()
+    n_ok = int(np.sum(errs <= ERR_HEADLINE))
+    xref0 = Xref[0].cpu().numpy()
     result = {
         "metric": "samples/s at 1e-5 rel err, batched/served vs plain; SpMV HBM GB/s; p99 latency",
-        "value": round(k / dt, 2),
+        "value": round(n_ok / dt, 2),
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -156,6 +165,12 @@ def main():
                    "n": sp.n, "rhs": k, "storage": "f64", "tol_rho": TOL_HEADLINE, "m_max": M_MAX_HEADLINE,
                    "m_used_max": max(m_used), "m_used_min": min(m_used), "reorth": False,
                    "parallelism": "single GPU, RHS-batched"},
+        "headline_accuracy": {
+            "reference": f"the same 32 columns, FP64, rho <= {REF_TOL:g} (m = {min(i['m_used'] for i in iref)}-"
+                         f"{max(i['m_used'] for i in iref)}), all converged: "
+                         f"{all(i['status'] == 'OK' for i in iref)}",
+            "within_1e-5": n_ok, "of": k, "max_rel_err": float(errs.max()),
+            "median_rel_err": float(np.median(errs))},
     }
     if args.only == "headline":
         print(json.dumps(result))
@@ -292,6 +307,11 @@ def main():
         result["accuracy"] = {
             "reference": f"oracle, full reorthogonalisation, rho = {ref.rho[-1]:.1e} (m = {ref.m})",
             "headline_rel_err_col0": rel(x0),
+            # the GPU's converged reference (no reorthogonalisation) against the oracle's (CGS2): both
+            # converged, so they differ by truncation only
+            "gpu_reference_col0_vs_oracle_reference": rel(xref0),
+            # both sides stop at rho <= 1e-5, before convergence, where the iterate moves by far more than
+            # rounding under a rounding-level change of the operator; tight parity is taken at convergence
             "parity_vs_oracle_same_rule_col0": float(np.linalg.norm(x0 - ro.x) / np.linalg.norm(ro.x)),
         }
         for key in ("f64", "f32", "f32_tol", "unprec"):

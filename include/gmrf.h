@@ -256,7 +256,9 @@ gmrf_status gmrf_tridiag_log_e1(const double* alpha, const double* beta, const i
  *   of a vector),  3: the update w = q - alpha v of the unpreconditioned step,  4: band kernel
  *   of the preconditioned step,  5: row pass and 6: column pass of the preconditioned step of
  *   Q + diag(d) (gmrf_op_set_diagonal).
- * Buffers are zero-filled first.  Outputs (host): *avg_us = mean duration of one launch,
+ * Krylov slots are filled with seeded +-1 values and the scalar state with ones (every column
+ * active, no stop decision triggers), other scratch with zeros, before the first event.
+ * Outputs (host): *avg_us = mean duration of one launch,
  * *bytes = algorithmic bytes of one launch (inputs read once, outputs written once; 0 for the
  * band kernel, whose traffic is the small boundary tables).  EINVAL for 1, 2, 4 without
  * preconditioning or with a diagonal term, for 5, 6 without both.                            */

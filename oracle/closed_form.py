@@ -93,3 +93,17 @@ def exact_logdet(shape, order, kappa2, tau, boundary):
 def exact_lambda_min_max(shape, order, kappa2, tau, boundary):
     lam = lattice_spectrum(shape, order, kappa2, tau, boundary)
     return float(lam.min()), float(lam.max())
+
+
+def exact_log_quadratic_form(shape, order, kappa2, tau, boundary, v):
+    """v^T log(Q) v for a lattice precision: the quantity that Section 6's Lanczos quadrature
+    approximates for one probe v.  log Q = U diag(log lambda) U^T with U the DCT-II (free) or the
+    unitary DFT (periodic) eigenvectors, so v^T log(Q) v = sum_k log(lambda_k) |(U^T v)_k|^2."""
+    shape = tuple(int(s) for s in shape)
+    lam = lattice_spectrum(shape, order, kappa2, tau, boundary)
+    V = np.asarray(v, dtype=np.float64).reshape(shape)
+    if boundary == "periodic":
+        c2 = np.abs(np.fft.fftn(V)) ** 2 / V.size
+    else:
+        c2 = _apply_axes(V, [dct2_matrix(N).T for N in shape]) ** 2
+    return float(np.sum(np.log(lam) * c2))

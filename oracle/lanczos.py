@@ -22,7 +22,9 @@ Readings where the paper is silent (each also listed in the design notes):
     status ENOTSPD and no sample.
   * T_m^{-1/2} e_1 is taken from the exact eigendecomposition of T_m (LAPACK stemr via
     scipy.linalg.eigh_tridiagonal): T_m = U diag(theta) U^T,
-    y = U (theta^{-1/2} * U^T e_1).
+    y = U (theta^{-1/2} * U^T e_1).  stemr (relatively robust representations) can fail to
+    converge on the tight Ritz-value clusters of long runs without reorthogonalisation; the
+    implicit QL/QR driver stev, which always converges, then computes the same decomposition.
 """
 from dataclasses import dataclass, field
 
@@ -87,12 +89,20 @@ def lanczos_tridiag(matvec, z, m_max, tol=0.0, reorth=False, keep_basis=False):
     return np.array(alpha), np.array(beta), beta0, np.array(rho), m, status, V[:, :m]
 
 
+def _eigh_tridiag(alpha, beta_off):
+    """Eigendecomposition of the symmetric tridiagonal T (LAPACK stemr; stev if stemr fails)."""
+    try:
+        return sla.eigh_tridiagonal(alpha, beta_off)
+    except np.linalg.LinAlgError:
+        return sla.eigh_tridiagonal(alpha, beta_off, lapack_driver="stev")
+
+
 def tridiag_inv_sqrt_e1(alpha, beta):
     """y = T^{-1/2} e_1 with T = tridiag(beta[:m-1], alpha, beta[:m-1]) via eigh."""
     m = len(alpha)
     if m == 1:
         return np.array([alpha[0] ** -0.5])
-    theta, U = sla.eigh_tridiagonal(alpha, beta[: m - 1])
+    theta, U = _eigh_tridiag(alpha, beta[: m - 1])
     if theta.min() <= 0:
         raise ValueError("T_m is not positive definite")
     return U @ (theta ** -0.5 * U[0, :])
@@ -103,7 +113,7 @@ def tridiag_log_e1(alpha, beta):
     m = len(alpha)
     if m == 1:
         return float(np.log(alpha[0]))
-    theta, U = sla.eigh_tridiagonal(alpha, beta[: m - 1])
+    theta, U = _eigh_tridiag(alpha, beta[: m - 1])
     if theta.min() <= 0:
         raise ValueError("T_m is not positive definite")
     return float(np.sum(U[0, :] ** 2 * np.log(theta)))

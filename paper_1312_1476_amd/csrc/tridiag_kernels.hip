@@ -8,7 +8,8 @@
 //   log(lambda)   = int_R e^s ( 1/(1 + e^s) - 1/(lambda + e^s) ) ds,
 // discretised by the trapezoidal rule in s.  The integrands are analytic in the strips
 // |Im s| < pi/2 and |Im s| < pi, so steps h = 1/4 and h = 1/2 give errors near 1e-16; the
-// truncation points sit 37 e-folds beyond the spectrum [lo, hi] of T, whose upper end is a
+// truncation points sit 37 e-folds beyond the spectrum [lo, hi] of T (for the log, beyond
+// [min(lo, 1), max(hi, 1)], where its integrand's tails begin), whose upper end is a
 // Gershgorin bound and whose lower end comes from Sturm counts (LDL^T inertia of T - x I)
 // at x = hi * 2^{-t/2}, t = 0..255, which also certifies that T is positive definite.
 // Each node needs (T + sigma I)^{-1} e_1: with the backward pivots
@@ -169,8 +170,10 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_log(TriArgs A) {
     }
     return;
   }
+  // the integrand decays like e^s below min(log lo, 0) and like e^{-s} above max(log hi, 0): the window
+  // covers both ends of the spectrum and the switch of 1/(1 + e^s) at s = 0
   const double h = 0.5;
-  const double s_lo = log(lo) - kPad, s_hi = log(hi) + kPad;
+  const double s_lo = fmin(log(lo), 0.0) - kPad, s_hi = fmax(log(hi), 0.0) + kPad;
   const int nq = (int)ceil((s_hi - s_lo) / h) + 1;
   double acc = 0.0;
   for (int l = threadIdx.x; l < nq; l += kTriThreads) {

@@ -134,8 +134,7 @@ class Server:
                 self._work_cv.notify()
 
     def _worker(self, w):
-        torch = self.torch
-        stream = torch.cuda.Stream()
+        stream = None
         while True:
             with self._work_cv:
                 while not self._work and not self._stop:
@@ -145,20 +144,31 @@ class Server:
                 req = self._work.popleft()
             req.t_start = time.perf_counter()
             try:
-                with torch.cuda.stream(stream):
-                    req.result = self._run(req, stream)
-            except GmrfError as e:
-                req.error = str(e)
-            stream.synchronize()
-            req.t_done = time.perf_counter()
-            if not self.keep_results:
+                if stream is None:
+                    stream = self._new_stream()
+                req.result = self._execute(req, stream)
+            except Exception as e:      # any failure ends this request only, never the worker
+                req.error = f"{type(e).__name__}: {e}" if not isinstance(e, GmrfError) else str(e)
                 req.result = None
-            with self.cv:
-                self.in_flight_bytes -= req.bytes
-                self.busy -= 1
-                self.completed.append(req)
-                self.cv.notify_all()
-            req.done.set()
+            finally:
+                req.t_done = time.perf_counter()
+                if not self.keep_results:
+                    req.result = None
+                with self.cv:
+                    self.in_flight_bytes -= req.bytes
+                    self.busy -= 1
+                    self.completed.append(req)
+                    self.cv.notify_all()
+                req.done.set()
+
+    def _new_stream(self):
+        return self.torch.cuda.Stream()
+
+    def _execute(self, req, stream):
+        with self.torch.cuda.stream(stream):
+            out = self._run(req, stream)
+        stream.synchronize()
+        return out
 
     def _run(self, req, stream):
         torch = self.torch

@@ -119,3 +119,31 @@ def test_batch_edge_columns(gm):
                 continue
             assert info[c]["status"] == "OK" and info[c]["m_used"] == ia[r]["m_used"]
             assert torch.equal(Xs[f][r], Xa[r]), (f, r)
+
+
+@pytest.mark.timeout(600)
+def test_uneven_batch_workload_fp32_as_benchmarked(gm):
+    """The uneven batch exactly as the benchmark runs it: 256 fields, 8 right-hand sides each, FP32
+    storage with FP64 scalars, stop at rho <= 1e-5, m_max = 600.  Every column converges.  Eight fields
+    across the kappa2 range (the smallest kappa2 = 1e-3 end included, cond(Q) ~ 8e3) x columns 0 and 7
+    equal the FP64 oracle at the same m within the FP32 tolerance 1e-5."""
+    fields = workloads.uneven_fields()
+    ops = [gm.Operator.lattice((s, s), 1, k2, 1.0, "free", "f32") for s, k2 in fields]
+    Zs = [workloads.uneven_field_rhs(f, s) for f, (s, _) in enumerate(fields)]
+    Xs, info = gm.sample_batch(ops, [_t(Z.T) for Z in Zs], tol=1e-5, m_max=600)
+    assert all(i["status"] == "OK" for i in info), [i for i in info if i["status"] != "OK"][:4]
+    order = np.argsort([k2 for _, k2 in fields])
+    picks = [int(order[(len(order) - 1) * q // 7]) for q in range(8)]
+    worst = 0.0
+    for f in picks:
+        s, k2 = fields[f]
+        Q = lattice.lattice_precision((s, s), 1, k2, 1.0, "free")
+        X = Xs[f].cpu().numpy()
+        for r in (0, 7):
+            ref = lanczos.sample_csr(Q, Zs[f][:, r], info[8 * f + r]["m_used"], tol=0.0)
+            e = _rel(X[r].astype(np.float64), ref.x)
+            worst = max(worst, e)
+            assert e <= 1e-5, (f, s, k2, r, info[8 * f + r], e)
+    print(f"uneven batch FP32 vs oracle: worst rel err {worst:.2e} over {2 * len(picks)} columns")
+    for op in ops:
+        op.close()

@@ -116,6 +116,27 @@ def test_tridiag_vs_eigh(gm, m, cond):
         assert abs(lg[r] - lref) <= 1e-13 * max(1.0, abs(lref)) + 20 * kap * 2.2e-16
 
 
+@pytest.mark.parametrize("scale", [1e-8, 1e-4, 1e4, 1e10])
+def test_tridiag_log_scaled_spectrum(gm, scale):
+    """e_1^T log(T) e_1 for T scaled far from 1 (tau-scaled operators): the quadrature window must cover
+    both the spectrum and s = 0, where the log integrand's tails begin."""
+    import torch
+    rng = np.random.default_rng(int(np.log10(scale)) + 50)
+    m, k = 60, 2
+    A = np.zeros((k, m))
+    B = np.zeros((k, m))
+    for r in range(k):
+        a, b = _rand_tridiag(rng, m, 1e3)
+        A[r], B[r] = scale * a, scale * b
+    mm = torch.full((k,), m, dtype=torch.int32, device="cuda:0")
+    lg, st = gm.tridiag_log_e1(_t(A), _t(B), mm)
+    lg = lg.cpu().numpy()
+    assert (st.cpu().numpy() == 0).all()
+    for r in range(k):
+        lref = lanczos.tridiag_log_e1(A[r], B[r])
+        assert abs(lg[r] - lref) <= 1e-12 * max(1.0, abs(lref)), (scale, lg[r], lref)
+
+
 def test_tridiag_flags_indefinite(gm):
     import torch
     A = np.array([[1.0, -2.0, 1.0, 0.0]])

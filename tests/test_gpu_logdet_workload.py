@@ -2,10 +2,16 @@
 second-order Q with kappa2 = 0.05, 64 Rademacher probes, m = 80 Lanczos steps, FP32 storage
 with FP64 scalars.  Checked against
   * the oracle per probe (two probes at full size, same probe rule), FP32 tolerance 1e-5;
-  * the closed-form log det of the periodic (block-circulant) version (DFT eigenvalues),
-    statistically: |mean - exact| < 5 standard errors;
-  * the free-boundary closed form (DCT eigenvalues), statistically;
-  * the oracle on the 128 x 128 subgrid, every probe, FP32 1e-5 and FP64 1e-10.
+  * the exact quadratic form v_p^T log(Q) v_p of every probe, from the closed-form DCT (free)
+    or DFT (periodic) eigendecomposition.  Gauss quadrature of log over-estimates each form
+    (log has negative even derivatives), and at m = 80 the rule has not converged on this
+    operator (cond(Q) ~ 2.6e4): each probe's value lies above its exact form by a relative
+    quadrature bias of a few 1e-4.  Comparing the estimate with the exact log det at m = 80
+    would mix that bias with the probe noise, so the exact log det is used only where the
+    quadrature has converged:
+  * the oracle on the 128 x 128 subgrid, every probe, FP32 1e-5 and FP64 1e-10 at m = 80, and
+    FP64 at m = 640, where each probe matches its exact form to 1e-8 and the estimate lies
+    within 5 standard errors of the exact log det.
 """
 import numpy as np
 import pytest
@@ -32,8 +38,7 @@ def test_logdet_full_size_free(gm):
     sp, npb, m, seed = workloads.C3_LATTICE, workloads.C3_PROBES, workloads.C3_M, workloads.c3_probe_seed()
     op = gm.Operator.lattice(sp.shape, sp.order, sp.kappa2, sp.tau, sp.boundary, "f32")
     mean, se, per = op.logdet(npb, m, seed=seed)
-    exact = closed_form.exact_logdet(sp.shape, sp.order, sp.kappa2, sp.tau, sp.boundary)
-    assert abs(mean - exact) < 5 * se, (mean, exact, se)
+    _check_bias_per_probe(sp.shape, sp, sp.boundary, seed, per)
     Q = lattice.lattice_precision(sp.shape, sp.order, sp.kappa2, sp.tau, sp.boundary)
     from oracle import philox
     for p in (0, npb - 1):
@@ -46,8 +51,7 @@ def test_logdet_full_size_periodic_closed_form(gm):
     sp, npb, m, seed = workloads.C3_LATTICE, workloads.C3_PROBES, workloads.C3_M, workloads.c3_probe_seed()
     op = gm.Operator.lattice(sp.shape, sp.order, sp.kappa2, sp.tau, "periodic", "f32")
     mean, se, per = op.logdet(npb, m, seed=seed)
-    exact = closed_form.exact_logdet(sp.shape, sp.order, sp.kappa2, sp.tau, "periodic")
-    assert abs(mean - exact) < 5 * se, (mean, exact, se)
+    _check_bias_per_probe(sp.shape, sp, "periodic", seed, per)
 
 
 @pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f64", 1e-10)])
@@ -60,8 +64,35 @@ def test_logdet_subgrid_128(gm, storage, tol):
     ref = logdet.hutchinson_csr(Q, npb, m, seed=seed)
     assert np.all(np.abs(per - ref.per_probe) <= tol * np.abs(ref.per_probe))
     assert abs(mean - ref.logdet) <= tol * abs(ref.logdet)
+
+
+def test_logdet_subgrid_128_converged(gm):
+    """m = 640 on the 128 x 128 subgrid (FP64): the quadrature has converged, every probe equals its
+    exact quadratic form to 1e-8, and only the probe noise is left between the estimate and the exact
+    log det (dense-checked closed form)."""
+    sp, npb, seed = workloads.C3_LATTICE, workloads.C3_PROBES, workloads.c3_probe_seed()
+    shape = (128, 128)
+    op = gm.Operator.lattice(shape, sp.order, sp.kappa2, sp.tau, sp.boundary, "f64")
+    mean, se, per = op.logdet(npb, 640, seed=seed)
+    from oracle import philox
+    n = shape[0] * shape[1]
+    for p in range(npb):
+        q = closed_form.exact_log_quadratic_form(shape, sp.order, sp.kappa2, sp.tau, sp.boundary,
+                                                 philox.rademacher_probe(seed, p, n))
+        assert abs(per[p] - q) <= 1e-8 * abs(q), (p, per[p], q)
     exact = closed_form.exact_logdet(shape, sp.order, sp.kappa2, sp.tau, sp.boundary)
-    assert abs(mean - exact) < 5 * se
+    assert abs(mean - exact) < 5 * se, (mean, exact, se)
+
+
+def _check_bias_per_probe(shape, sp, boundary, seed, per):
+    """Every probe's m = 80 value against its exact quadratic form: above it (the Gauss rule of log
+    over-estimates; 1e-5 of FP32 slack) by at most 1e-3 relative (the measured bias is ~4e-4)."""
+    from oracle import philox
+    n = shape[0] * shape[1]
+    for p in range(len(per)):
+        q = closed_form.exact_log_quadratic_form(shape, sp.order, sp.kappa2, sp.tau, boundary,
+                                                 philox.rademacher_probe(seed, p, n))
+        assert -1e-5 * abs(q) <= per[p] - q <= 1e-3 * abs(q), (p, per[p], q)
 
 
 def test_logdet_full_size_preconditioned(gm):

@@ -182,3 +182,21 @@ def test_preconditioned_batch_full_size(gm, storage):
     assert all(i["m_used"] == c.m_max and i["status"] == "ENOCONV" for i in info)
     ref = precond.sample(Q, sp.shape, sp.order, sp.kappa2, sp.tau, Zh[:, 0], c.m_max, tol=0.0)
     assert _rel(X[:, 0], ref.x) <= 10 * ref.rho[-1], (_rel(X[:, 0], ref.x), ref.rho[-1])
+
+
+@pytest.mark.timeout(900)
+def test_preconditioned_batch_full_size_converged(gm):
+    """The benchmark's configuration run to convergence: 512 x 512, 13-point, 32 right-hand sides in
+    the launch configuration of the benchmark (two column groups of 16 on two streams), FP64 storage,
+    no reorthogonalisation, stop at rho <= 1e-10 (m ~ 970-990, under m_max = 1024).  Every column
+    converges; columns 0 (first group) and 31 (second group) equal the oracle at the same m to 1e-8."""
+    c = workloads.C1
+    sp = c.lattice
+    op = gm.Operator.lattice(sp.shape, sp.order, sp.kappa2, sp.tau, sp.boundary, "f64").set_circulant_precond()
+    Zh = workloads.gaussian_block(sp.n, c.k, 1, 0)
+    X, info, _, _ = _sample(gm, op, Zh, tol=1e-10, m_max=1024, reorth=False)
+    assert all(i["status"] == "OK" and i["rel_residual"] <= 1e-10 for i in info), info
+    Q = lattice.lattice_precision(sp.shape, sp.order, sp.kappa2, sp.tau, sp.boundary)
+    for r in (0, 31):
+        ref = precond.sample(Q, sp.shape, sp.order, sp.kappa2, sp.tau, Zh[:, r], info[r]["m_used"], tol=0.0)
+        assert _rel(X[:, r], ref.x) <= 1e-8, (r, info[r]["m_used"], _rel(X[:, r], ref.x))

@@ -60,3 +60,27 @@ def test_principal_root_is_symmetric_and_squares_to_inverse():
     assert np.allclose(S, S.T, atol=1e-13)
     assert np.allclose(S @ S @ Q.toarray(), np.eye(30), atol=1e-10)
     assert np.all(np.linalg.eigvalsh(S) > 0)
+
+
+@pytest.mark.parametrize("shape,order", CASES)
+@pytest.mark.parametrize("boundary", ["free", "periodic"])
+def test_exact_log_quadratic_form_vs_dense_logm(shape, order, boundary):
+    Q = lattice.lattice_precision(shape, order, 0.05, 0.7, boundary)
+    v = np.where(np.random.default_rng(3).uniform(size=Q.shape[0]) < 0.5, -1.0, 1.0)
+    q = closed_form.exact_log_quadratic_form(shape, order, 0.05, 0.7, boundary, v)
+    ref = float(v @ dense.log_matrix(Q) @ v)
+    assert abs(q - ref) <= 1e-11 * abs(ref)
+
+
+def test_gauss_quadrature_of_log_decreases_to_the_quadratic_form():
+    """Section 6's quadrature is the m-node Gauss rule for the spectral measure of v; log has negative
+    even derivatives, so the rule over-estimates v^T log(Q) v and the error shrinks as m grows."""
+    from oracle import logdet
+    shape, order, k2 = (16, 16), 2, 0.05
+    Q = lattice.lattice_precision(shape, order, k2, 1.0, "free")
+    v = np.where(np.random.default_rng(4).uniform(size=Q.shape[0]) < 0.5, -1.0, 1.0)
+    q = closed_form.exact_log_quadratic_form(shape, order, k2, 1.0, "free", v)
+    g = [logdet.quadrature(lambda x: Q @ x, v, m)[0] for m in (5, 10, 20, 40, 256)]   # m = n: exact
+    assert all(a > b for a, b in zip(g, g[1:])), g
+    assert all(x > q for x in g[:-1]), (g, q)
+    assert abs(g[-1] - q) <= 1e-10 * abs(q), (g[-1], q)

@@ -40,3 +40,29 @@ def test_logdet_is_never_two_pass_and_oversize_is_rejected():
     assert not r.two_pass
     big = srv.submit(_req(k=32))     # not started: submit rejects before queueing
     assert big.error and "budget" in big.error and big.done.is_set()
+
+
+class _FailingServer(serve.Server):
+    """Requests with an odd id raise a non-library exception inside the worker."""
+
+    def _new_stream(self):
+        return object()
+
+    def _execute(self, req, stream):
+        if req.rid % 2:
+            raise RuntimeError("out of memory while drawing Z")
+        return {"ok": req.rid}
+
+
+def test_worker_survives_any_exception_and_releases_its_slot():
+    srv = _FailingServer([_Op(1000)], hbm_budget=1 << 40, workers=2).start()
+    reqs = [serve.ServeRequest(i, "sample", 0, 2, 7, m_max=50) for i in range(8)]
+    for r in reqs:
+        srv.submit(r)
+    for r in reqs:
+        assert r.done.wait(timeout=30)
+    srv.stop()
+    assert [bool(r.error) for r in reqs] == [bool(i % 2) for i in range(8)]
+    assert all("RuntimeError" in r.error for r in reqs if r.rid % 2)
+    assert all(r.result == {"ok": r.rid} for r in reqs if not r.rid % 2)
+    assert srv.busy == 0 and srv.in_flight_bytes == 0 and len(srv.completed) == 8
