@@ -166,6 +166,23 @@ gmrf_status gmrf_sample_ex(const gmrf_op* Q, const double* Z, int64_t k, double 
 gmrf_status gmrf_solve(const gmrf_op* Q, const double* B, int64_t k, double tol, int32_t m_max,
                        int reorth, double* X, gmrf_info* info, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): gmrf_sample with every scratch buffer (Krylov basis,
+ * work vectors, Lanczos scalars, partial sums, tridiagonal scratch) carved from one static device
+ * array of 128 MiB that the library holds on each GPU it runs on until the process ends.  The call
+ * makes no hipMalloc, hipFree or other allocating call; the caller still owns Z, X and info.
+ * The columns run as one group on `stream` (results equal gmrf_sample's, whose preconditioned
+ * calls split the columns over two streams).  Arguments, info and return as for gmrf_sample, with
+ * k <= 256.  ENOMEM (before any kernel runs) when the call's scratch exceeds 128 MiB, e.g.
+ * (m_max + 2) k n s bytes of Krylov basis with s = 8 (FP64) or 4 (FP32) must fit.  Every call on
+ * a GPU shares that GPU's array and leaves its contents behind (each call clears what must start
+ * at zero).  Overlapping calls on one GPU would race on it, so the library serialises the calls of
+ * a process (each returns after its work on the device has finished); each process has its own
+ * copy of the array.                                                                             */
+gmrf_status gmrf_sample_noalloc(const gmrf_op* Q, const double* Z, int64_t k, double tol,
+                                int32_t m_max, int reorth, double* X, gmrf_info* info,
+                                void* stream);
+
 /* As gmrf_sample without reorthogonalisation, in O(n k) device memory instead of O(n k m_max):
  * the sampler keeps three Krylov vectors (the O(n) storage Section 1 claims for the method).
  * Pass 1 runs the recurrence with the stopping rule and keeps only alpha_j, beta_j; after

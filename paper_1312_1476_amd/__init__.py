@@ -177,6 +177,24 @@ class Operator:
             return X, infos, alpha, beta
         return X, infos
 
+    def sample_noalloc(self, Z, tol=1e-8, m_max=200, reorth=False, out=None, stream=None):
+        """As sample(), through gmrf_sample_noalloc: the library allocates nothing, its scratch being a
+        static 128 MiB device array (the caller passes the output block `out`, else one is made here).
+        Returns (X, info)."""
+        torch = _torch()
+        self._check_block(Z, torch.float64, "Z")
+        k = Z.shape[0]
+        X = out if out is not None else torch.empty_like(Z)
+        self._check_block(X, torch.float64, "out")
+        info = (Info * k)()
+        st = lib().gmrf_sample_noalloc(self._h, _dptr(Z), k, float(tol), int(m_max), int(bool(reorth)), _dptr(X),
+                                       info, _stream_ptr(stream))
+        if st not in (_abi.GMRF_OK, _abi.GMRF_ENOTSPD, _abi.GMRF_EINVAL) or (
+                st == _abi.GMRF_EINVAL and not any(i.status == _abi.GMRF_EINVAL for i in info)):
+            raise GmrfError(st, "gmrf_sample_noalloc")
+        return X, [dict(m_used=i.m_used, status=STATUS[i.status], rel_residual=i.rel_residual,
+                        err_bound=i.err_bound) for i in info]
+
     def solve(self, B, tol=1e-8, m_max=200, reorth=False, out=None, stream=None):
         """X[r] ~= Q^{-1} B[r] (FP64 CUDA tensors of shape (k, n)) by the Lanczos form of (preconditioned)
         conjugate gradients; rel_residual in info is ||b - Q x|| / ||b||.  Returns (X, info)."""

@@ -38,6 +38,8 @@ SIGNATURES = {
     "gmrf_op_destroy": (None, [C.c_void_p]),
     "gmrf_sample": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.c_int,
                               C.c_void_p, C.POINTER(Info), C.c_void_p]),
+    "gmrf_sample_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.c_int,
+                                      C.c_void_p, C.POINTER(Info), C.c_void_p]),
     "gmrf_sample_ex": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.c_int,
                                  C.c_void_p, C.POINTER(Info), C.c_void_p, C.c_void_p, C.c_void_p]),
     "gmrf_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int32, C.c_int, C.c_void_p,

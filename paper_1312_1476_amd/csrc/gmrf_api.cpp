@@ -120,17 +120,31 @@ Pool& pool() {
   return *p;
 }
 
-// Scratch of one call; returned to the pool (after the stream has drained) on destruction.
+// Scratch of one call; returned to the pool (after the stream has drained) on destruction.  With an arena
+// (a caller-provided device range) the call's buffers are carved from it in order instead, 256-byte
+// aligned, and nothing is allocated or returned.
 struct Workspace {
   hipStream_t stream;
   std::vector<std::pair<void*, size_t>> blocks;
+  char* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
   explicit Workspace(hipStream_t s) : stream(s) {}
+  Workspace(hipStream_t s, void* base, size_t cap) : stream(s), arena(static_cast<char*>(base)), arena_cap(cap) {}
   ~Workspace() {
     if (!blocks.empty()) (void)hipStreamSynchronize(stream);
     for (auto& b : blocks) pool().put(b.first, b.second);
   }
   template <typename T>
   gmrf_status alloc(size_t count, T** out) {
+    if (arena) {
+      const size_t b = (std::max<size_t>(count * sizeof(T), 256) + 255) & ~(size_t)255;
+      if (b > arena_cap - arena_used)
+        return fail(GMRF_ENOMEM, "the call needs more than the %zu B of static scratch (%zu B used, %zu B more asked)",
+                    arena_cap, arena_used, b);
+      *out = reinterpret_cast<T*>(arena + arena_used);
+      arena_used += b;
+      return GMRF_OK;
+    }
     void* p = nullptr;
     size_t actual = 0;
     gmrf_status s = pool().get(std::max<size_t>(count * sizeof(T), 256), &p, &actual);
@@ -823,11 +837,13 @@ void iterate_all(std::vector<Run<T>>& Rs, int j, const std::vector<char>& live) 
 
 // Runs iterations of all groups (each on its own stream) until every column stopped or m_max, then closes
 // the columns that hit m_max.  Groups whose columns all stopped launch no more.
+// host_poll: host buffer of 2 x (columns) doubles for the stop polls (nullptr: the thread's pinned buffer).
 template <typename T>
-gmrf_status run_loop(std::vector<Run<T>>& Rs, const std::function<gmrf_status(int)>& on_done = nullptr) {
+gmrf_status run_loop(std::vector<Run<T>>& Rs, const std::function<gmrf_status(int)>& on_done = nullptr,
+                     double* host_poll = nullptr) {
   int ktot = 0;
   for (auto& R : Rs) ktot += R.k;
-  double* ph = poll_rho_buffer(2 * ktot);   // per group: k active flags, then k residuals
+  double* ph = host_poll ? host_poll : poll_rho_buffer(2 * ktot);   // per group: k active flags, then k residuals
   if (!ph) return fail(GMRF_ENOMEM, "pinned host buffer allocation failed");
   std::vector<char> live(Rs.size(), 1);
   const int m_max = Rs[0].m_max;
@@ -1006,11 +1022,14 @@ static void init_for_solve(Run<T>& R, const double* Bg) {
 
 // solve = false: samples x_m = ||z|| V_m T_m^{-1/2} e_1 (Algorithm 1); solve = true: the Lanczos form of the
 // conjugate-gradient iterate x_m = ||b|| V_m T_m^{-1} e_1 for Q x = b, preconditioned the same way.
+// arena (device, arena_cap bytes) non-null: every scratch buffer of the call is carved from it, the columns run
+// as one group on the caller's stream and the stop polls read into host_poll (2 k doubles); nothing is allocated.
 template <typename T>
 static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, double tol, int m_max, int reorth,
                                double* X, gmrf_info* info, double* alpha_out, double* beta_out,
-                               hipStream_t st, bool solve = false) {
-  const int G = groups_for(Q, k);
+                               hipStream_t st, bool solve = false, void* arena = nullptr, size_t arena_cap = 0,
+                               double* host_poll = nullptr) {
+  const int G = arena ? 1 : groups_for(Q, k);
   ForkJoin fj;
   gmrf_status s = fj.fork(st, G);
   if (s != GMRF_OK) return s;
@@ -1018,9 +1037,9 @@ static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, dou
   for (int g = 0; g <= G; ++g) c0[g] = k * g / G;
   std::vector<std::unique_ptr<Workspace>> ws;
   std::vector<Run<T>> Rs(G);
-  std::vector<double*> ys(G);
+  std::vector<double*> ys(G, nullptr), scrs(G, nullptr);
   for (int g = 0; g < G; ++g) {
-    ws.emplace_back(new Workspace(fj.gs[g]));
+    ws.emplace_back(arena ? new Workspace(fj.gs[g], arena, arena_cap) : new Workspace(fj.gs[g]));
     Run<T>& R = Rs[g];
     R.Q = Q;
     R.k = (int)(c0[g + 1] - c0[g]);
@@ -1029,21 +1048,25 @@ static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, dou
     R.tol = tol;
     R.st = fj.gs[g];
     if ((s = setup<T>(R, *ws[g])) != GMRF_OK) return s;
+    if (arena) {
+      // the closing buffers too, so that a call too large for the arena is refused before any kernel runs
+      if ((s = ws[g]->alloc((size_t)R.k * m_max, &ys[g])) != GMRF_OK) return s;
+      if (!solve && (s = ws[g]->alloc(tri_scratch_doubles(R.k, m_max), &scrs[g])) != GMRF_OK) return s;
+    }
     if (solve) init_for_solve<T>(R, Z + (size_t)c0[g] * Q->n);
     else init_from_z<T>(R, Z + (size_t)c0[g] * Q->n);
   }
   // y = T_m^{-1/2} e_1 (or T_m^{-1} e_1), then x_m = ||z|| V_m y, enqueued as soon as the group's columns stop
   auto close_group = [&](int g) -> gmrf_status {
     Run<T>& R = Rs[g];
-    double* scr;
-    if ((s = ws[g]->alloc((size_t)R.k * m_max, &ys[g])) != GMRF_OK) return s;
+    if (!ys[g] && (s = ws[g]->alloc((size_t)R.k * m_max, &ys[g])) != GMRF_OK) return s;
     if (solve) {
       launch_tri_solve(R.S.alpha, m_max + 1, 1, R.S.beta, m_max + 2, 1, R.S.m_used, 0, R.S.status, ys[g], m_max,
                        R.S.status, R.k, R.st);
     } else {
-      if ((s = ws[g]->alloc(tri_scratch_doubles(R.k, m_max), &scr)) != GMRF_OK) return s;
+      if (!scrs[g] && (s = ws[g]->alloc(tri_scratch_doubles(R.k, m_max), &scrs[g])) != GMRF_OK) return s;
       launch_tri_invsqrt(R.S.alpha, m_max + 1, 1, R.S.beta, m_max + 2, 1, R.S.m_used, 0, R.S.status, ys[g], m_max,
-                         R.S.status, scr, m_max, R.k, R.st);
+                         R.S.status, scrs[g], m_max, R.k, R.st);
     }
     double* Xg = X + (size_t)c0[g] * Q->n;
     if (Q->precond) {
@@ -1058,7 +1081,7 @@ static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, dou
     }
     return GMRF_OK;
   };
-  if ((s = run_loop<T>(Rs, close_group)) != GMRF_OK) return s;
+  if ((s = run_loop<T>(Rs, close_group, host_poll)) != GMRF_OK) return s;
   HIP_TRY(hipGetLastError());
   // results to host
   std::vector<int> mu(k), stt(k);
@@ -1248,6 +1271,63 @@ extern "C" gmrf_status gmrf_solve(const gmrf_op* Q, const double* B, int64_t k, 
 extern "C" gmrf_status gmrf_sample(const gmrf_op* Q, const double* Z, int64_t k, double tol, int32_t m_max,
                                    int reorth, double* X, gmrf_info* info, void* stream) {
   return gmrf_sample_ex(Q, Z, k, tol, m_max, reorth, X, info, nullptr, nullptr, stream);
+}
+
+// ---- allocation-free sampling -----------------------------------------------------------------------------------
+// Every scratch buffer of gmrf_sample_noalloc lives in one static device array per GPU.  In host code the name
+// `scratch` is only a host-side stand-in for the symbol: its device address (its own on every GPU) is taken once
+// per device with hipGetSymbolAddress, and only that address reaches kernels, memsets and copies.
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+constexpr int kNoAllocMaxK = 256;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;                   // guards the address table and serialises the calls of the process
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first call there); caller holds g_scratch_mu.
+gmrf_status static_scratch(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(GMRF_EDEVICE, "device ordinal %d out of range", dev);
+  if (!g_scratch_addr[dev]) {
+    gmrf_status ds = check_device();
+    if (ds != GMRF_OK) return ds;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(GMRF_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return GMRF_OK;
+}
+}  // namespace
+
+extern "C" gmrf_status gmrf_sample_noalloc(const gmrf_op* Q, const double* Z, int64_t k, double tol, int32_t m_max,
+                                           int reorth, double* X, gmrf_info* info, void* stream) {
+  if (!Q || !Z || !X) return fail(GMRF_EINVAL, "NULL argument");
+  if (k < 1 || k > kNoAllocMaxK) return fail(GMRF_EINVAL, "k must be in 1..%d", kNoAllocMaxK);
+  if (m_max < 1 || m_max > tri_max_m()) return fail(GMRF_EINVAL, "m_max must be in 1..%d", tri_max_m());
+  if (!std::isfinite(tol)) return fail(GMRF_EINVAL, "tol must be finite");
+  if (reorth != 0 && reorth != 1) return fail(GMRF_EINVAL, "reorth must be 0 or 1");
+  if (Q->has_diag && !Q->precond)
+    return fail(GMRF_EUNSUPPORTED, "Q + diag(d) is sampled with circulant preconditioning only (else pass it as CSR)");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  void* base = nullptr;
+  gmrf_status s = static_scratch(&base);
+  if (s != GMRF_OK) return s;
+  double poll[2 * kNoAllocMaxK];
+  hipStream_t st = (hipStream_t)stream;
+  s = Q->storage == GMRF_F64
+          ? sample_impl<double>(Q, Z, k, tol, m_max, reorth, X, info, nullptr, nullptr, st, false, base,
+                                kStaticScratchBytes, poll)
+          : sample_impl<float>(Q, Z, k, tol, m_max, reorth, X, info, nullptr, nullptr, st, false, base,
+                               kStaticScratchBytes, poll);
+  // a refused or failed call may have queued memsets into the array: let them finish before the next caller
+  if (s != GMRF_OK && s != GMRF_ENOTSPD && s != GMRF_EINVAL) (void)hipStreamSynchronize(st);
+  return s;
 }
 
 // ---- log-determinant ------------------------------------------------------------------------------------

@@ -50,6 +50,7 @@ def test_errors_without_device_or_with_bad_args():
     # NULL handles of the later entry points: refused before any device call
     assert L.gmrf_solve(None, None, 1, 1e-8, 10, 0, None, None, None) == abi.GMRF_EINVAL
     assert L.gmrf_sample_two_pass(None, None, 1, 1e-8, 10, None, None, None) == abi.GMRF_EINVAL
+    assert L.gmrf_sample_noalloc(None, None, 1, 1e-8, 10, 0, None, None, None) == abi.GMRF_EINVAL
     assert L.gmrf_op_set_diagonal(None, None) == abi.GMRF_EINVAL
     assert L.gmrf_op_set_ichol_precond(None, 1, -1.0, None) == abi.GMRF_EINVAL
     assert L.gmrf_ichol_info(None, None, None, None) == abi.GMRF_EINVAL
