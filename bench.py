@@ -32,7 +32,7 @@ import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 DOMINANT_KERNEL = "lz_step"      # largest share of the step in the committed rocprofv3 summary
-COPY_BYTES = 512 << 20           # reference copy of the counter runs (--only counters)
+COPY_BYTES = 512 << 20           # reference read / copy of the counter runs (--only counters)
 # HBM bytes per launch of the dominant kernel from the committed counter summary: FETCH_SIZE x 2 +
 # WRITE_SIZE x 1 (KiB per dispatch, scaled by the reference copy's readings); None if the kernel changed
 TRAFFIC_BYTES = 225601472      # k_step<double, 64, true>, 512x512, 32 fields (profiles/k_step_precond_512x512_32rhs_fp64.md)
@@ -40,6 +40,7 @@ TOL_HEADLINE = 1e-5              # stopping rule of the headline (rho_m <= tol)
 ERR_HEADLINE = 1e-5              # a headline sample counts when its relative error is within this
 REF_TOL, REF_M_MAX = 1e-10, 1024 # converged FP64 reference of the headline columns
 INFINITY_CACHE_BYTES = 256 << 20
+BW_BYTES = 1 << 30               # array size of the achievable-bandwidth kernels (beyond the Infinity Cache)
 SERVE_RATES = (2, 4, 8)          # requests/s of the serving leg (the queue saturates near 8-16)
 M_MAX_HEADLINE = 600
 
@@ -57,6 +58,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
     ap.add_argument("--only", default="", help="profiling: run only this leg (headline|counters|lgcp|logdet|ichol|plain|uneven|serve)")
+    ap.add_argument("--no-ref", action="store_true",
+                    help="profiling: skip the converged reference run of the headline (value is then null)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-lgcp", action="store_true", help="skip the log-Gaussian Cox process leg")
     ap.add_argument("--no-logdet", action="store_true", help="skip the log-determinant leg")
@@ -64,6 +67,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain 64x64 and uneven-batch legs")
     ap.add_argument("--kernel", default="", help="counters leg: kernel to run (default: the dominant one)")
     ap.add_argument("--storage", default="f64", help="counters leg: storage dtype (f64|f32)")
+    ap.add_argument("--side", type=int, default=512, help="counters leg: lattice side of the operator (spmv)")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="arrival window per serving rate")
     return ap.parse_args()
 
@@ -95,16 +99,18 @@ def main():
         # another: spmv = the 13-point operator alone), then a plain device copy of known size whose
         # FETCH_SIZE / WRITE_SIZE readings scale the counters to bytes
         name = args.kernel or DOMINANT_KERNEL
-        op = make(args.storage) if name != "spmv" else gm.Operator.lattice(sp.shape, sp.order, sp.kappa2, sp.tau,
-                                                                            sp.boundary, args.storage)
+        op = make(args.storage) if name != "spmv" else gm.Operator.lattice((args.side, args.side), sp.order, sp.kappa2,
+                                                                            sp.tau, sp.boundary, args.storage)
+        if name in ("spmv", "lz2d"):
+            gm.autotune(op, k, reps=20, stream=stream)     # count the kernel with the launch options it runs with
         r = gm.kernel_bench(op, name, k, reps=50, stream=stream)
-        a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
+        # references of known size: the library's read kernel (FETCH_SIZE) and copy kernel (WRITE_SIZE) over
+        # arrays of COPY_BYTES, 5 + 2 launches each
+        gm.bandwidth_bench("read", COPY_BYTES, reps=5, stream=stream)
+        gm.bandwidth_bench("copy", COPY_BYTES, reps=5, stream=stream)
         torch.cuda.synchronize()
         print(json.dumps({"kernel": name, "storage": args.storage, "avg_us": r["avg_us"], "bytes": r["bytes"],
-                          "copy_bytes": COPY_BYTES}))
+                          "reference_bytes": COPY_BYTES}))
         return
 
     def step(op, tol, m_max):
@@ -142,14 +148,17 @@ def main():
     x0 = X[0].cpu().numpy()
     # every column against the same columns run to convergence (FP64, rho <= 1e-10, m_max = 1024; the
     # full-size parity test pins this run to the oracle at 1e-8): only samples within 1e-5 count
-    Xref, iref = step(op64, REF_TOL, REF_M_MAX)
+    if args.no_ref:
+        Xref, iref = X, info
+    else:
+        Xref, iref = step(op64, REF_TOL, REF_M_MAX)
     torch.cuda.synchronize()
     errs = ((X - Xref).norm(dim=1) / Xref.norm(dim=1)).cpu().numpy()
     n_ok = int(np.sum(errs <= ERR_HEADLINE))
     xref0 = Xref[0].cpu().numpy()
     result = {
         "metric": "samples/s at 1e-5 rel err, batched/served vs plain; SpMV HBM GB/s; p99 latency",
-        "value": round(n_ok / dt, 2),
+        "value": None if args.no_ref else round(n_ok / dt, 2),
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -245,14 +254,21 @@ def main():
                           # the launch's vectors fit the 256 MB Infinity Cache (as they do in the sampling loop,
                           # where v_j and v_{j-1} were written one and two steps before)
                           "cache_resident": roof["bytes"] < INFINITY_CACHE_BYTES}
+    # achievable HBM bandwidth on this part (hand-written read / copy / triad kernels over 1 GiB arrays)
+    ach = {kind: round(gm.bandwidth_bench(kind, BW_BYTES, reps=10, stream=stream)["gbs"], 1)
+           for kind in ("read", "copy", "triad")}
+    result["roofline"]["achievable_gbs"] = ach
+    result["roofline"]["frac_of_achievable_copy"] = round(roof["achieved_gbs"] / ach["copy"], 4)
     kern = {}
     for name in ("lz_band", "lz_dots"):
         r = gm.kernel_bench(op64, name, k, reps=50, stream=stream)
         kern[name] = {"avg_us": round(r["avg_us"], 2), "gbs": round(r["achieved_gbs"], 1)}
     result["other_kernels"] = kern
-    # the SpMV/SpMM metric: the 13-point stencil over 32 columns, FP64 and FP32 storage
+    # the SpMV/SpMM metric: the 13-point stencil over 32 columns, FP64 and FP32 storage, with the launch options
+    # the autotuner picks (tile order, store policy; no option changes a result bit)
     spmv = {}
     for name, op in (("f64", op64), ("f32", op32)):
+        gm.autotune(op, k, reps=20, stream=stream)
         r = gm.kernel_bench(op, "spmv", k, reps=50, stream=stream)
         spmv[name] = {"achieved_gbs": round(r["achieved_gbs"], 1), "frac_of_peak": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
                       "avg_us": round(r["avg_us"], 2), "bytes_per_launch": r["bytes"]}
@@ -261,6 +277,7 @@ def main():
     spmv_big = {}
     for storage in ("f64", "f32"):
         opb = gm.Operator.lattice((1024, 1024), sp.order, sp.kappa2, sp.tau, sp.boundary, storage)
+        gm.autotune(opb, k, reps=10, stream=stream)
         r = gm.kernel_bench(opb, "spmv", k, reps=20, stream=stream)
         spmv_big[storage] = {"achieved_gbs": round(r["achieved_gbs"], 1),
                              "frac_of_peak": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
@@ -289,6 +306,10 @@ def main():
     # ---- serving: Poisson request stream over a pool of 64 resident operators ---------------------------
     if not args.no_serve:
         result["serving"] = serving_leg(gm, torch, args.serve_seconds)
+
+    # the launch options the autotuner chose (kernel, lattice class, columns class -> options)
+    result["autotune"] = [f"{r['kernel']} order {r['order']} {r['storage']} 2^{r['log2_n1']}x2^{r['log2_n2']} "
+                          f"k<=2^{r['log2_k']}: {'+'.join(r['options']) or 'none'}" for r in gm.tune_table()]
 
     # ---- oracle legs ----------------------------------------------------------------------------------
     if not args.no_cpu:
@@ -424,6 +445,7 @@ def logdet_leg(gm, torch):
     sp = workloads.C3_LATTICE
     seed = workloads.c3_probe_seed()
     op = gm.Operator.lattice(sp.shape, sp.order, sp.kappa2, sp.tau, sp.boundary, "f32")
+    gm.autotune(op, LOGDET_COLUMNS, reps=5)   # the variants' 64, 63 and 54 columns share one columns class
     out = {"workload": "1024x1024 13-point lattice, kappa2 = 0.05, free boundary, m = 80, FP32 storage",
            "columns": LOGDET_COLUMNS, "m": workloads.C3_M, "variants": {}}
     for p in (0, 1, 2):
@@ -528,6 +550,12 @@ def uneven_leg(gm, torch):
     Zs = [torch.from_numpy(np.ascontiguousarray(workloads.uneven_field_rhs(f, s).T)).to("cuda:0")
           for f, (s, _) in enumerate(fields)]
     ncol = sum(int(Z.shape[0]) for Z in Zs)
+    tuned = set()
+    for op, (s, _) in zip(ops, fields):      # one field per lattice class (ceil(log2) of the side)
+        c = int(np.ceil(np.log2(s)))
+        if c not in tuned:
+            gm.autotune(op, 8, reps=5)
+            tuned.add(c)
     gm.sample_batch(ops, Zs, tol=UNEVEN_TOL, m_max=UNEVEN_M_MAX)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

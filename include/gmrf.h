@@ -272,15 +272,49 @@ gmrf_status gmrf_tridiag_log_e1(const double* alpha, const double* beta, const i
  *   products the next step needs),  2: dot-product kernel of the preconditioned step (one read
  *   of a vector),  3: the update w = q - alpha v of the unpreconditioned step,  4: band kernel
  *   of the preconditioned step,  5: row pass and 6: column pass of the preconditioned step of
- *   Q + diag(d) (gmrf_op_set_diagonal).
+ *   Q + diag(d) (gmrf_op_set_diagonal),  7: one-pass Lanczos step of a 2D lattice without
+ *   preconditioning (w_j from v_j and v_{j-1} with the sums the next step needs).
  * Krylov slots are filled with seeded +-1 values and the scalar state with ones (every column
  * active, no stop decision triggers), other scratch with zeros, before the first event.
  * Outputs (host): *avg_us = mean duration of one launch,
  * *bytes = algorithmic bytes of one launch (inputs read once, outputs written once; 0 for the
  * band kernel, whose traffic is the small boundary tables).  EINVAL for 1, 2, 4 without
- * preconditioning or with a diagonal term, for 5, 6 without both.                            */
+ * preconditioning or with a diagonal term, for 5, 6 without both, for 7 on other operators.                            */
 gmrf_status gmrf_kernel_bench(const gmrf_op* Q, int which, int64_t k, int32_t reps, double* avg_us,
                               double* bytes, void* stream);
+
+/* Autotuner (for the batching and sampling paths): times, with `reps` launches between HIP events
+ * on scratch data of Q's shape with k columns, every candidate set of launch options of the
+ * kernels such calls launch on a 2D lattice -- the operator's SpMM (gmrf_op_apply) and, without
+ * preconditioning or diagonal term, the one-pass Lanczos step -- and records the fastest in a
+ * process-wide table keyed by (kernel, order, storage, ceil(log2) of each side, ceil(log2 k)).
+ * The options are the tile order (linear, or XCD-contiguous so that each of the 8 XCDs, each with
+ * its own L2, works through one range of neighbouring tiles) and the store policy of the output
+ * (ordinary or non-temporal).  No option changes what is computed or the order of any sum, so
+ * results are bitwise the same under every table state.  chosen (host, may be NULL): [2] chosen
+ * option bits (1 = XCD-contiguous, 2 = non-temporal stores; -1 = kernel not used by Q).  Other
+ * operators are left untuned (GMRF_OK, chosen = -1).                                           */
+gmrf_status gmrf_autotune(const gmrf_op* Q, int64_t k, int32_t reps, int32_t* chosen, void* stream);
+
+/* The tuning table as `count` entries of 7 int32 (kernel 0 = SpMM, 1 = one-pass step; order;
+ * storage; ceil(log2 N1); ceil(log2 N2); ceil(log2 k); option bits); at most `cap` are written
+ * to entries (host), *count receives the table size.  gmrf_tune_import adds or replaces entries
+ * in the same format (EINVAL for an invalid entry, the table then unchanged); gmrf_tune_clear
+ * empties the table (every launch then takes no options).                                       */
+gmrf_status gmrf_tune_export(int32_t* entries, int32_t cap, int32_t* count);
+gmrf_status gmrf_tune_import(const int32_t* entries, int32_t count);
+gmrf_status gmrf_tune_clear(void);
+
+/* Achievable HBM bandwidth of the device (the roofline denominator beside the published peak):
+ * `reps` launches of a streaming kernel over freshly allocated arrays of `bytes` bytes each
+ * (a multiple of 16, at least 1 MiB; use 1 GiB or more to stay beyond the 256 MB Infinity
+ * Cache), non-temporal 16-byte accesses, `blocks` workgroups of 256 threads (0: 32 per compute
+ * unit), each streaming one contiguous chunk of the arrays.
+ *   which 0: read (sum of a),  1: copy (b = a),  2: triad (a = b + q c).
+ * Outputs (host): *avg_us = mean launch duration, *gbs = bytes moved (1, 2 or 3 arrays) per
+ * launch / *avg_us, in GB/s.  The arrays are freed before returning.                          */
+gmrf_status gmrf_bandwidth_bench(int which, size_t bytes, int32_t blocks, int32_t reps, double* gbs,
+                                 double* avg_us, void* stream);
 
 /* ---- memory budget and errors ---------------------------------------------------------- */
 

@@ -18,7 +18,8 @@ from . import _abi
 from ._abi import GMRF_F32, GMRF_F64, GMRF_FREE, GMRF_PERIODIC, GmrfError, Info, check, lib
 
 __all__ = ["Operator", "rademacher", "tridiag_invsqrt_e1", "tridiag_log_e1", "set_hbm_budget",
-           "hbm_in_use", "kernel_bench", "sample_batch", "GmrfError", "STATUS"]
+           "hbm_in_use", "kernel_bench", "bandwidth_bench", "autotune", "tune_table", "save_tune", "load_tune",
+           "clear_tune", "sample_batch", "GmrfError", "STATUS"]
 
 STATUS = _abi.STATUS_NAMES
 
@@ -266,6 +267,75 @@ class Operator:
         return col
 
 
+TUNE_KERNELS = ("spmv", "lz2d")
+TUNE_OPTIONS = {1: "xcd_order", 2: "nt_store"}
+
+
+def _options(bits):
+    return None if bits < 0 else [name for b, name in TUNE_OPTIONS.items() if bits & b]
+
+
+def autotune(op, k, reps=20, stream=None):
+    """Time the candidate launch options of the operator's tunable kernels for k columns and record the
+    fastest in the library's table (results are bitwise the same under every choice).  Returns
+    {kernel: [options]} (None: kernel not used by this operator)."""
+    chosen = (C.c_int32 * 2)()
+    check(lib().gmrf_autotune(op._h, int(k), int(reps), chosen, _stream_ptr(stream)), "gmrf_autotune")
+    return {name: _options(chosen[i]) for i, name in enumerate(TUNE_KERNELS)}
+
+
+def tune_table():
+    """The library's tuning table: a list of dicts (kernel, order, storage, side classes, columns class,
+    options)."""
+    n = C.c_int32()
+    check(lib().gmrf_tune_export(None, 0, C.byref(n)), "gmrf_tune_export")
+    buf = (C.c_int32 * (7 * max(1, n.value)))()
+    check(lib().gmrf_tune_export(buf, n.value, C.byref(n)), "gmrf_tune_export")
+    out = []
+    for i in range(n.value):
+        e = list(buf[7 * i:7 * i + 7])
+        out.append({"kernel": TUNE_KERNELS[e[0]], "order": e[1], "storage": "f64" if e[2] == GMRF_F64 else "f32",
+                    "log2_n1": e[3], "log2_n2": e[4], "log2_k": e[5], "options": _options(e[6]), "bits": e[6]})
+    return out
+
+
+def save_tune(path):
+    """Persist the tuning table as JSON."""
+    import json
+    with open(path, "w") as f:
+        json.dump(tune_table(), f, indent=1)
+
+
+def load_tune(path):
+    """Add the entries of a JSON tuning table written by save_tune."""
+    import json
+    with open(path) as f:
+        rows = json.load(f)
+    flat = []
+    for r in rows:
+        flat += [TUNE_KERNELS.index(r["kernel"]), int(r["order"]), GMRF_F64 if r["storage"] == "f64" else GMRF_F32,
+                 int(r["log2_n1"]), int(r["log2_n2"]), int(r["log2_k"]), int(r["bits"])]
+    arr = (C.c_int32 * max(1, len(flat)))(*flat)
+    check(lib().gmrf_tune_import(arr, len(rows)), "gmrf_tune_import")
+
+
+def clear_tune():
+    check(lib().gmrf_tune_clear(), "gmrf_tune_clear")
+
+
+BANDWIDTH_KERNELS = {"read": 0, "copy": 1, "triad": 2}
+
+
+def bandwidth_bench(kind, nbytes=1 << 30, blocks=0, reps=20, stream=None):
+    """Achievable HBM bandwidth: `kind` in read / copy / triad over arrays of `nbytes` bytes each.
+    Returns {"gbs", "avg_us", "bytes_per_launch"}."""
+    which = BANDWIDTH_KERNELS[kind]
+    gbs, us = C.c_double(), C.c_double()
+    check(lib().gmrf_bandwidth_bench(which, C.c_size_t(int(nbytes)), int(blocks), int(reps), C.byref(gbs), C.byref(us),
+                                     _stream_ptr(stream)), "gmrf_bandwidth_bench")
+    return {"gbs": gbs.value, "avg_us": us.value, "bytes_per_launch": (which + 1) * int(nbytes)}
+
+
 def sample_batch(ops, Zs, tol=1e-8, m_max=300, stream=None):
     """Uneven batch: field f is ops[f] with right-hand sides Zs[f] ((k_f, n_f) FP64 CUDA
     tensors).  All fields run in one set of launches per Lanczos step.  Returns ([X_f], info)
@@ -336,7 +406,8 @@ def tridiag_log_e1(alpha, beta, m, stream=None):
     return out, status
 
 
-KERNELS = {"spmv": 0, "lz_step": 1, "lz_dots": 2, "update": 3, "lz_band": 4, "lgcp_rows": 5, "lgcp_cols": 6}
+KERNELS = {"spmv": 0, "lz_step": 1, "lz_dots": 2, "update": 3, "lz_band": 4, "lgcp_rows": 5, "lgcp_cols": 6,
+           "lz2d": 7}
 
 
 def kernel_bench(op, kernel, k, reps=50, stream=None):

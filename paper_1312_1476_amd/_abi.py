@@ -60,6 +60,12 @@ SIGNATURES = {
                                       C.c_void_p, C.c_void_p, C.c_void_p]),
     "gmrf_kernel_bench": (C.c_int, [C.c_void_p, C.c_int, C.c_int64, C.c_int32, C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), C.c_void_p]),
+    "gmrf_autotune": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p]),
+    "gmrf_tune_export": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "gmrf_tune_import": (C.c_int, [C.c_void_p, C.c_int32]),
+    "gmrf_tune_clear": (C.c_int, []),
+    "gmrf_bandwidth_bench": (C.c_int, [C.c_int, C.c_size_t, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.c_void_p]),
     "gmrf_set_hbm_budget": (C.c_int, [C.c_size_t]),
     "gmrf_hbm_in_use": (C.c_size_t, []),
     "gmrf_strerror": (C.c_char_p, [C.c_int]),

@@ -30,6 +30,14 @@ struct StencilGeom {
   int ftiles_x;            // 2D one-pass Lanczos kernel: strips per row
   int band;                // 2D operator kernel: output rows per wave (0: kS2Band)
   int ftiles_y;            // 2D one-pass Lanczos kernel: bands of kS2Waves x kS2Band rows
+  int tune;                // launch options that leave every result bit unchanged (kTune* bits)
+};
+
+// Launch options chosen by the autotuner.  None of them changes what a thread computes or the order of
+// any sum (partial sums are indexed by logical tile), so results are bitwise the same under every choice.
+enum : int {
+  kTuneXcd = 1,   // XCD-contiguous tile order: workgroup i runs on XCD i mod 8, each XCD takes one range
+  kTuneNtStore = 2,   // non-temporal stores of the kernel's output vector (selects a kernel instantiation)
 };
 
 // Per-call Lanczos state, all device memory.  Index conventions (1-based j as in

@@ -19,6 +19,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/gmrf.h"
@@ -583,6 +584,50 @@ extern "C" gmrf_status gmrf_op_bytes(const gmrf_op* Q, int64_t k, int32_t m_max,
   return GMRF_OK;
 }
 
+// ---- autotuner table: launch options that leave every result bit unchanged --------------------------------
+// The table maps (kernel, order, storage, shape class, columns class) to kTune* bits (common.hpp); shape class =
+// ceil(log2) of each lattice side, columns class = ceil(log2 k).  Entries come from gmrf_autotune, which times every
+// candidate with HIP events on scratch data of the call's shape and keeps the fastest, or from gmrf_tune_import.
+// A key without an entry launches with no options (linear tile order, ordinary stores).  Since no option changes a
+// result bit, results never depend on the table's state: a field gets identical bits alone and in a batch whatever
+// was tuned.
+namespace {
+enum { kTuneKernelSpmm = 0, kTuneKernelLanczos2d = 1, kTuneKernels = 2 };
+constexpr int kTuneCandidates[4] = {0, kTuneXcd, kTuneNtStore, kTuneXcd | kTuneNtStore};
+struct TuneKey {
+  int kernel, order, storage, c1, c2, ck;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(kernel, order, storage, c1, c2, ck) < std::tie(o.kernel, o.order, o.storage, o.c1, o.c2, o.ck);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int>& tune_table() {
+  static std::map<TuneKey, int>* t = new std::map<TuneKey, int>();
+  return *t;
+}
+int clog2(int64_t v) {
+  int c = 0;
+  while (((int64_t)1 << c) < v) ++c;
+  return c;
+}
+TuneKey tune_key(int kernel, const gmrf_op* Q, int64_t k) {
+  return {kernel, Q->order, Q->storage, clog2(Q->shape[1]), clog2(Q->shape[2]), clog2(k)};
+}
+bool tunable(const gmrf_op* Q) { return Q->kind == 0 && Q->dim == 2; }
+int tune_lookup(int kernel, const gmrf_op* Q, int64_t k) {
+  if (!tunable(Q)) return 0;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = tune_table().find(tune_key(kernel, Q, k));
+  return it == tune_table().end() ? 0 : it->second;
+}
+// the operator's geometry with the launch options of `kernel` for k columns (tune >= 0: those options instead)
+StencilGeom tuned_geom(int kernel, const gmrf_op* Q, int64_t k, int tune = -1) {
+  StencilGeom g = Q->geom;
+  g.tune = tune >= 0 ? tune : tune_lookup(kernel, Q, k);
+  return g;
+}
+}  // namespace
+
 // ---- operator application --------------------------------------------------------------------------
 template <typename T>
 static void op_apply_lz(const gmrf_op* Q, const T* X, T* Y, const T* Xprev, const LzState& S, int j, int k,
@@ -594,11 +639,11 @@ static void op_apply_lz(const gmrf_op* Q, const T* X, T* Y, const T* Xprev, cons
 }
 
 template <typename T>
-static void op_apply_plain(const gmrf_op* Q, const T* X, T* Y, int k, hipStream_t st) {
+static void op_apply_plain(const gmrf_op* Q, const T* X, T* Y, int k, hipStream_t st, int tune = -1) {
   LzState S{};
   if (Q->kind == 0) {
     // caller buffers may not be aligned for the 2D kernel's element pairs: then one element per lane
-    StencilGeom g = Q->geom;
+    StencilGeom g = tuned_geom(kTuneKernelSpmm, Q, k, tune);
     if (g.epl > 1 && (((uintptr_t)X | (uintptr_t)Y) % (g.epl * sizeof(T))) != 0) stencil_geom_tiles(g, Q->dim, Q->order, 1);
     launch_stencil<T>(g, Q->order, Q->dim, false, X, Q->n, Y, Q->n, nullptr, S, 0, k, st);
     if (Q->has_diag) launch_add_diag<T>((const T*)diag_of(Q), X, Y, (long)Q->n, k, st);
@@ -668,6 +713,7 @@ struct Run {
   bool ring3 = false;
   bool fused = false;             // one pass per step (k_lanczos2d); partial sums alternate between ps[0], ps[1]
   double* ps[2][3] = {};          // {quadratic form, ||w||^2, <w, v>} partial sums
+  StencilGeom geom2d{};           // the operator's geometry with the one-pass kernel's tuned launch options
 
   T* slot(int t) const {
     const int s = ring3 ? (t % 3) : t;
@@ -695,6 +741,7 @@ gmrf_status setup(Run<T>& R, Workspace& ws) {
     R.band = band;
   }
   R.fused = fused_path(Q, R.reorth);
+  R.geom2d = tuned_geom(kTuneKernelLanczos2d, Q, k);
   return setup_state<T>(R, ws);
 }
 
@@ -750,7 +797,7 @@ gmrf_status setup_state(Run<T>& R, Workspace& ws) {
 template <typename T>
 void fused_init(Run<T>& R) {
   if (!R.fused) return;
-  launch_lanczos2d<T>(R.Q->geom, R.Q->order, 1, 0, R.slot(0), R.z.L, nullptr, nullptr, R.S, 0, R.k, R.ps[0][0],
+  launch_lanczos2d<T>(R.geom2d, R.Q->order, 1, 0, R.slot(0), R.z.L, nullptr, nullptr, R.S, 0, R.k, R.ps[0][0],
                       nullptr, nullptr, R.st);
 }
 
@@ -797,7 +844,7 @@ void iterate(Run<T>& R, int j) {
     // reads the partial sums in R.S (pass j - 1's; iteration 1: the init kernels' set 0) and writes the other
     // set, which R.S then points to (the next pass and k_finalize read it)
     const int wset = j & 1;
-    launch_lanczos2d<T>(Q->geom, Q->order, 0, 0, xj, R.z.L, R.slot(j), xp, R.S, j, R.k, R.ps[wset][0],
+    launch_lanczos2d<T>(R.geom2d, Q->order, 0, 0, xj, R.z.L, R.slot(j), xp, R.S, j, R.k, R.ps[wset][0],
                         R.ps[wset][1], R.ps[wset][2], R.st);
     R.S.part_a = R.ps[wset][0];
     R.S.part_b = R.ps[wset][1];
@@ -1573,7 +1620,7 @@ extern "C" gmrf_status gmrf_tridiag_log_e1(const double* alpha, const double* be
 // output written once; the small hand-off tables between the kernels of a step are not counted).
 template <typename T>
 static gmrf_status kernel_bench_impl(const gmrf_op* Q, int which, int k, int reps, double* avg_us, double* bytes,
-                                     hipStream_t st) {
+                                     hipStream_t st, int tune = -1) {
   Workspace ws(st);
   Run<T> R;
   R.Q = Q;
@@ -1600,13 +1647,28 @@ static gmrf_status kernel_bench_impl(const gmrf_op* Q, int which, int k, int rep
     HIP_TRY(hipStreamSynchronize(st));
   }
   R.S.Pb = R.pb_first;
+  if (which == 7) {
+    // the one-pass step at j = 2 closes iteration 1 first: alpha_1 = 1 keeps every column positive definite
+    std::vector<double> aones((size_t)k * (R.m_max + 1), 1.0);
+    HIP_TRY(hipMemcpyAsync(R.S.alpha, aones.data(), aones.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
   const size_t vb = (size_t)k * R.z.vec_bytes;
   std::function<void()> launch;
   double b = 0.0;
   const void* mult = Q->storage == GMRF_F64 ? (const void*)Q->mult64 : (const void*)Q->mult32;
   if (which == 0) {
-    launch = [&]() { op_apply_plain<T>(Q, R.slot(0), R.Qb, k, st); };
+    launch = [&]() { op_apply_plain<T>(Q, R.slot(0), R.Qb, k, st, tune); };
     b = 2.0 * vb + (Q->kind == 1 ? (double)Q->resident_bytes : 0.0);
+  } else if (which == 7) {
+    if (!R.fused) return fail(GMRF_EINVAL, "kernel 7 needs a 2D lattice without preconditioning or diagonal term");
+    // step 2 from slots 1 and 0 into slot 2, reading partial-sum set 0 (seeded) and writing set 1
+    const StencilGeom g = tuned_geom(kTuneKernelLanczos2d, Q, k, tune);
+    launch = [&, g]() {
+      launch_lanczos2d<T>(g, Q->order, 0, 0, R.slot(1), R.z.L, R.slot(2), R.slot(0), R.S, 2, k, R.ps[1][0],
+                          R.ps[1][1], R.ps[1][2], st);
+    };
+    b = 3.0 * vb;   // read v_j, v_{j-1}; write w_j
   } else if (which == 1 || which == 2 || which == 4) {
     if (!Q->precond || lgcp_path(Q))
       return fail(GMRF_EINVAL, "kernel %d needs circulant preconditioning without a diagonal term", which);
@@ -1674,6 +1736,140 @@ extern "C" gmrf_status gmrf_kernel_bench(const gmrf_op* Q, int which, int64_t k,
   return kernel_bench_impl<float>(Q, which, (int)k, reps, avg_us, bytes, st);
 }
 
+// ---- autotuner -----------------------------------------------------------------------------------------------
+// Times every candidate option set of the tunable kernels that calls on Q with k columns launch (the 2D operator's
+// SpMM; the one-pass Lanczos step where the operator takes it) with `reps` launches between HIP events on scratch
+// data of that shape, and records the fastest (ties: the earlier candidate) in the table.
+template <typename T>
+static gmrf_status autotune_impl(const gmrf_op* Q, int k, int reps, int32_t* chosen, hipStream_t st) {
+  const int kernels[kTuneKernels] = {kTuneKernelSpmm, kTuneKernelLanczos2d};
+  const int which[kTuneKernels] = {0, 7};
+  for (int t = 0; t < kTuneKernels; ++t) {
+    if (t == 1 && !fused_path(Q, 0)) {
+      if (chosen) chosen[t] = -1;
+      continue;
+    }
+    int best = 0;
+    double best_us = 0.0;
+    for (int c = 0; c < 4; ++c) {
+      double us = 0.0, b = 0.0;
+      gmrf_status s = kernel_bench_impl<T>(Q, which[t], k, reps, &us, &b, st, kTuneCandidates[c]);
+      if (s != GMRF_OK) return s;
+      if (c == 0 || us < best_us) {
+        best = kTuneCandidates[c];
+        best_us = us;
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      tune_table()[tune_key(kernels[t], Q, k)] = best;
+    }
+    if (chosen) chosen[t] = best;
+  }
+  return GMRF_OK;
+}
+
+extern "C" gmrf_status gmrf_autotune(const gmrf_op* Q, int64_t k, int32_t reps, int32_t* chosen, void* stream) {
+  if (!Q || k < 1 || k > 65535 || reps < 1) return fail(GMRF_EINVAL, "bad arguments");
+  if (!tunable(Q)) {
+    if (chosen) chosen[0] = chosen[1] = -1;
+    return GMRF_OK;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (Q->storage == GMRF_F64) return autotune_impl<double>(Q, (int)k, reps, chosen, st);
+  return autotune_impl<float>(Q, (int)k, reps, chosen, st);
+}
+
+extern "C" gmrf_status gmrf_tune_export(int32_t* entries, int32_t cap, int32_t* count) {
+  if (!count || cap < 0 || (cap > 0 && !entries)) return fail(GMRF_EINVAL, "bad arguments");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  *count = (int32_t)tune_table().size();
+  int i = 0;
+  for (const auto& kv : tune_table()) {
+    if (i >= cap) break;
+    const TuneKey& q = kv.first;
+    const int32_t e[7] = {q.kernel, q.order, q.storage, q.c1, q.c2, q.ck, kv.second};
+    std::memcpy(entries + 7 * i, e, sizeof(e));
+    ++i;
+  }
+  return GMRF_OK;
+}
+
+extern "C" gmrf_status gmrf_tune_import(const int32_t* entries, int32_t count) {
+  if (count < 0 || (count > 0 && !entries)) return fail(GMRF_EINVAL, "bad arguments");
+  for (int i = 0; i < count; ++i) {
+    const int32_t* e = entries + 7 * i;
+    if (e[0] < 0 || e[0] >= kTuneKernels || (e[1] != 1 && e[1] != 2) || (e[2] != GMRF_F64 && e[2] != GMRF_F32) ||
+        e[3] < 0 || e[3] > 31 || e[4] < 0 || e[4] > 31 || e[5] < 0 || e[5] > 31 ||
+        (e[6] & ~(kTuneXcd | kTuneNtStore)) != 0)
+      return fail(GMRF_EINVAL, "tuning entry %d is not valid", i);
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (int i = 0; i < count; ++i) {
+    const int32_t* e = entries + 7 * i;
+    tune_table()[TuneKey{e[0], e[1], e[2], e[3], e[4], e[5]}] = e[6];
+  }
+  return GMRF_OK;
+}
+
+extern "C" gmrf_status gmrf_tune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_table().clear();
+  return GMRF_OK;
+}
+
+// ---- achievable HBM bandwidth --------------------------------------------------------------------------------------
+extern "C" gmrf_status gmrf_bandwidth_bench(int which, size_t bytes, int32_t blocks, int32_t reps, double* gbs,
+                                            double* avg_us, void* stream) {
+  if (which < 0 || which > 2 || bytes < ((size_t)1 << 20) || bytes % 16 != 0 || blocks < 0 || reps < 1 || !gbs ||
+      !avg_us)
+    return fail(GMRF_EINVAL, "bad arguments");
+  gmrf_status ds = check_device();
+  if (ds != GMRF_OK) return ds;
+  hipStream_t st = (hipStream_t)stream;
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int nb = blocks > 0 ? blocks : 32 * cus;
+  void *a = nullptr, *b = nullptr, *c = nullptr;
+  float* out = nullptr;
+  gmrf_status s = GMRF_OK;
+  auto release = [&]() {
+    (void)hipStreamSynchronize(st);
+    for (void* p : {a, b, c, (void*)out})
+      if (p) (void)hipFree(p);
+  };
+  if (hipMalloc(&a, bytes) != hipSuccess || (which >= 1 && hipMalloc(&b, bytes) != hipSuccess) ||
+      (which == 2 && hipMalloc(&c, bytes) != hipSuccess) || hipMalloc(&out, (size_t)nb * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return fail(GMRF_ENOMEM, "bandwidth bench: hipMalloc of %zu B failed", bytes);
+  }
+  for (void* p : {a, b, c})
+    if (p && hipMemsetAsync(p, 0, bytes, st) != hipSuccess) s = fail(GMRF_EDEVICE, "hipMemsetAsync failed");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (s == GMRF_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    s = fail(GMRF_EDEVICE, "hipEventCreate failed");
+  float ms = 0.f;
+  if (s == GMRF_OK) {
+    const size_t n4 = bytes / 16;
+    for (int i = 0; i < 2; ++i) launch_bandwidth(which, nb, a, b, c, out, n4, st);
+    (void)hipEventRecord(e0, st);
+    for (int i = 0; i < reps; ++i) launch_bandwidth(which, nb, a, b, c, out, n4, st);
+    (void)hipEventRecord(e1, st);
+    if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
+        hipGetLastError() != hipSuccess)
+      s = fail(GMRF_EDEVICE, "bandwidth bench: launch or timing failed");
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  release();
+  if (s != GMRF_OK) return s;
+  *avg_us = 1000.0 * ms / reps;
+  *gbs = (double)(which + 1) * (double)bytes / (*avg_us * 1e3);
+  return GMRF_OK;
+}
+
 // ---- uneven batch: many fields, one set of launches per Lanczos step ----------------------------------
 template <typename T>
 static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const int64_t* kf, const double* Z, double tol,
@@ -1686,6 +1882,8 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
   int64_t tot = 0, tot_ext = 0;
   int max_tiles = 1;
   long max_len = 1;
+  int big = 0;                 // the field with the most elements: its tuned store policy serves the batch's launches
+  int64_t big_elems = 0;
   for (int f = 0; f < nf; ++f) {
     const gmrf_op* Q = ops[f];
     // inside the Krylov slots every column starts at an even offset, so that the 2D kernel's element
@@ -1694,6 +1892,10 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
     const int tiles = fused ? lanczos2d_blocks(gf) : stencil_blocks(gf);
     max_tiles = std::max(max_tiles, tiles);
     max_len = std::max<long>(max_len, (long)Q->n);
+    if (Q->n * kf[f] > big_elems) {
+      big_elems = Q->n * kf[f];
+      big = f;
+    }
     for (int64_t r = 0; r < kf[f]; ++r) {
       off.push_back(tot);
       ext.push_back(tot_ext);
@@ -1765,9 +1967,13 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
   HIP_TRY(hipMemcpyAsync(dpbf, pbf.data(), K * sizeof(int), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(dgeom, geom.data(), K * sizeof(StencilGeom), hipMemcpyHostToDevice, st));
   auto slot = [&](int t) { return V + (size_t)t * tot; };
+  // launch options of the batch's one-pass steps: the store policy tuned for its largest field (the work list
+  // fixes the tile order); no option changes a result bit
+  StencilGeom gbatch = Q0->geom;
+  gbatch.tune = tune_lookup(kTuneKernelLanczos2d, ops[big], kf[big]) & kTuneNtStore;
   launch_init_from_f64<T>(Z, 0, max_len, slot(0), S, st);
   if (fused)
-    launch_lanczos2d<T>(Q0->geom, Q0->order, 1, max_tiles, slot(0), 0, nullptr, nullptr, S, 0, K, ps[0][0], nullptr,
+    launch_lanczos2d<T>(gbatch, Q0->order, 1, max_tiles, slot(0), 0, nullptr, nullptr, S, 0, K, ps[0][0], nullptr,
                         nullptr, st);
   int* pbuf = poll_buffer(K);
   if (!pbuf) return fail(GMRF_ENOMEM, "pinned host buffer allocation failed");
@@ -1799,7 +2005,7 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
       // S holds pass j - 1's partial sums (iteration 1: the init kernels' set 0); this pass writes the other set
       const int wset = j & 1;
       if (nwork)
-        launch_lanczos2d<T>(Q0->geom, Q0->order, 0, nwork, slot(j - 1), 0, slot(j), j >= 2 ? slot(j - 2) : slot(0),
+        launch_lanczos2d<T>(gbatch, Q0->order, 0, nwork, slot(j - 1), 0, slot(j), j >= 2 ? slot(j - 2) : slot(0),
                             S, j, 1, ps[wset][0], ps[wset][1], ps[wset][2], st);
       S.part_a = ps[wset][0];
       S.part_b = ps[wset][1];

@@ -68,4 +68,7 @@ void launch_tri_log(const double* alpha, int lda, int a_off, const double* beta,
                     const int* m, int m_fixed, const int* status_in, double* out, int ldo,
                     int* status_out, int k, hipStream_t st);
 
+// bandwidth.hip: which 0 read of a, 1 copy a -> b, 2 triad a = b + q c; n4 = 16-byte elements per array
+void launch_bandwidth(int which, int blocks, void* a, void* b, void* c, float* out, size_t n4, hipStream_t st);
+
 }  // namespace gmrf

@@ -158,6 +158,25 @@ __global__ __launch_bounds__(256) void k_stencil(StencilGeom g0, const T* __rest
 // (same terms in the same order as k_stencil).
 constexpr int kS2Waves = 4;     // waves per block (bands stacked vertically)
 constexpr int kS2Band = 32;     // output rows per wave
+
+// XCD-aware tile order (kTuneXcd): the dispatcher hands workgroup i (linear over the grid) to XCD i mod 8,
+// each XCD with its own L2.  Logical (tile, column) ids are assigned so that every XCD works through one
+// contiguous range of them: neighbouring strips and bands, whose halo rows and columns overlap, then meet
+// in one L2.  The map is a bijection of the grid.
+constexpr int kXcds = 8;
+__device__ __forceinline__ void xcd_order(bool on, int& tile, int& col) {
+  if (!on) {
+    tile = blockIdx.x;
+    col = blockIdx.y;
+    return;
+  }
+  const int gx = gridDim.x, nb = gx * gridDim.y;
+  const int i = blockIdx.x + blockIdx.y * gx;
+  const int q = nb / kXcds, rm = nb % kXcds, x = i % kXcds, k = i / kXcds;
+  const int L = (x < rm ? x * (q + 1) : rm * (q + 1) + (x - rm) * q) + k;
+  tile = L % gx;
+  col = L / gx;
+}
 // rows requested ahead per wave: a row is 64 elements, so FP32 rows carry half the bytes of FP64 rows
 #ifndef GMRF_S2_AHEAD64
 #define GMRF_S2_AHEAD64 4
@@ -195,7 +214,7 @@ template <typename T> constexpr int kS2MaxEpl = sizeof(T) == 4 ? 4 : 2;
 __host__ __device__ inline int s2_halo(int order, int epl) { return epl >= 2 ? epl : order; }
 __host__ __device__ inline int s2_out(int order, int epl) { return kWave * epl - 2 * s2_halo(order, epl); }
 
-template <typename T, int ORDER, bool LZ, int EPL>
+template <typename T, int ORDER, bool LZ, int EPL, bool NTS>
 __device__ __forceinline__ void s2_strip(const StencilGeom& g, int tx, int ty, int w, int lane,
                                          const T* __restrict__ src, T* __restrict__ dst,
                                          const T* __restrict__ prv, int j, double s_cur, double s_prev,
@@ -329,7 +348,8 @@ __device__ __forceinline__ void s2_strip(const StencilGeom& g, int tx, int ty, i
 #pragma unroll
         for (int e = 0; e < EPL; ++e) vv[e] = res[e];
       }
-      *(VT*)(dst + (size_t)yo * n2 + xb) = vv;
+      if constexpr (NTS) __builtin_nontemporal_store(vv, (VT*)(dst + (size_t)yo * n2 + xb));
+      else *(VT*)(dst + (size_t)yo * n2 + xb) = vv;
     }
 #pragma unroll
     for (int e = 0; e < EPL; ++e) {
@@ -371,7 +391,8 @@ __device__ __forceinline__ void s2_strip(const StencilGeom& g, int tx, int ty, i
   }
 }
 
-template <typename T, int ORDER, bool LZ>
+// NTS: non-temporal stores of q (kTuneNtStore; a template parameter so that the store keeps its cache policy)
+template <typename T, int ORDER, bool LZ, bool NTS>
 __global__ __launch_bounds__(256) void k_stencil2d(StencilGeom g0, const T* __restrict__ X, long xld,
                                                    T* __restrict__ Y, long yld, const T* __restrict__ Xprev,
                                                    LzState S, int j, const int* __restrict__ active) {
@@ -379,16 +400,17 @@ __global__ __launch_bounds__(256) void k_stencil2d(StencilGeom g0, const T* __re
   __shared__ __align__(16) T trow[kS2Waves][2][kS2MaxEpl<T> * kWave];
   __shared__ double red[256 / kWave];
   __shared__ int flag[1];
-  const int r = blockIdx.y;
+  int tile, r;
+  xcd_order((g0.tune & kTuneXcd) != 0, tile, r);
   const StencilGeom g = (LZ && S.col_geom) ? S.col_geom[r] : g0;
-  if ((int)blockIdx.x >= g.tiles_x * g.tiles_y) return;
+  if (tile >= g.tiles_x * g.tiles_y) return;
   double s_cur = 1.0, s_prev = 0.0, bprev = 0.0;
   if (LZ) {
-    if (!lz_open<256>(S, r, j, blockIdx.x == 0, red, flag, s_cur, s_prev, bprev)) return;
+    if (!lz_open<256>(S, r, j, tile == 0, red, flag, s_cur, s_prev, bprev)) return;
   } else if (active && !active[r]) {
     return;
   }
-  const int tx = blockIdx.x % g.tiles_x, ty = blockIdx.x / g.tiles_x;
+  const int tx = tile % g.tiles_x, ty = tile / g.tiles_x;
   // wave index read as a scalar: the row loop's bounds are then uniform and its branches scalar
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   const size_t roff = (LZ && S.col_off) ? (size_t)S.col_off[r] : (size_t)r * xld;
@@ -398,21 +420,21 @@ __global__ __launch_bounds__(256) void k_stencil2d(StencilGeom g0, const T* __re
   double acc = 0.0;
   if constexpr (kS2MaxEpl<T> == 4) {
     if (g.epl == 4) {
-      s2_strip<T, ORDER, LZ, 4>(g, tx, ty, w, lane, src, dst, prv, j, s_cur, s_prev, bprev, &vrow[w][0][0],
+      s2_strip<T, ORDER, LZ, 4, NTS>(g, tx, ty, w, lane, src, dst, prv, j, s_cur, s_prev, bprev, &vrow[w][0][0],
                                 &trow[w][0][0], acc);
       goto done;
     }
   }
   if (g.epl == 2)
-    s2_strip<T, ORDER, LZ, 2>(g, tx, ty, w, lane, src, dst, prv, j, s_cur, s_prev, bprev, &vrow[w][0][0],
+    s2_strip<T, ORDER, LZ, 2, NTS>(g, tx, ty, w, lane, src, dst, prv, j, s_cur, s_prev, bprev, &vrow[w][0][0],
                               &trow[w][0][0], acc);
   else
-    s2_strip<T, ORDER, LZ, 1>(g, tx, ty, w, lane, src, dst, prv, j, s_cur, s_prev, bprev, &vrow[w][0][0],
+    s2_strip<T, ORDER, LZ, 1, NTS>(g, tx, ty, w, lane, src, dst, prv, j, s_cur, s_prev, bprev, &vrow[w][0][0],
                               &trow[w][0][0], acc);
 done:
   if (LZ) {
     const double bs = block_sum<256>(acc, red);
-    if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + blockIdx.x] = bs;
+    if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + tile] = bs;
   }
 }
 
@@ -433,7 +455,7 @@ __host__ __device__ inline int s2f_halo(int order, int epl) {
 }
 __host__ __device__ inline int s2f_out(int order, int epl) { return kWave * epl - 2 * s2f_halo(order, epl); }
 
-template <typename T, int ORDER, int MODE, int EPL>
+template <typename T, int ORDER, int MODE, int EPL, bool NTS>
 __device__ __forceinline__ void s2f_strip(const StencilGeom& g, int tx, int ty, int w, int lane,
                                           const T* __restrict__ src, T* __restrict__ dst,
                                           const T* __restrict__ prv, int j, double s_cur, double s_prev,
@@ -585,7 +607,8 @@ __device__ __forceinline__ void s2f_strip(const StencilGeom& g, int tx, int ty, 
 #pragma unroll
             for (int e = 0; e < EPL; ++e) vv[e] = wn[e];
           }
-          *(VT*)(dst + (size_t)yw * n2 + xb) = vv;
+          if constexpr (NTS) __builtin_nontemporal_store(vv, (VT*)(dst + (size_t)yw * n2 + xb));
+          else *(VT*)(dst + (size_t)yw * n2 + xb) = vv;
 #pragma unroll
           for (int e = 0; e < EPL; ++e) {
             acc_b += (double)wn[e] * (double)wn[e];
@@ -633,7 +656,7 @@ __device__ __forceinline__ void s2f_strip(const StencilGeom& g, int tx, int ty, 
 #define GMRF_L2D_WAVES 2       // lower bound on waves per SIMD given to the compiler; 4 caps registers at
                                // 128 and spills in the FP64 13-point case (measured 14% slower)
 #endif
-template <typename T, int ORDER, int MODE>
+template <typename T, int ORDER, int MODE, bool NTS>
 __global__ __launch_bounds__(256, GMRF_L2D_WAVES) void k_lanczos2d(StencilGeom g0, const T* __restrict__ X, long xld,
                                                    T* __restrict__ W, const T* __restrict__ Xprev, LzState S,
                                                    int j, double* __restrict__ out_a, double* __restrict__ out_b,
@@ -644,7 +667,8 @@ __global__ __launch_bounds__(256, GMRF_L2D_WAVES) void k_lanczos2d(StencilGeom g
   __shared__ __align__(16) T wrow[kS2Waves][2][kS2MaxEpl<T> * kWave];
   __shared__ double red[3 * NW];
   __shared__ int flag[1];
-  int r = blockIdx.y, tile = blockIdx.x;
+  int r, tile;
+  xcd_order(!S.work && (g0.tune & kTuneXcd), tile, r);
   if (S.work) {
     const int2 wt = S.work[blockIdx.x];
     r = wt.x;
@@ -668,16 +692,16 @@ __global__ __launch_bounds__(256, GMRF_L2D_WAVES) void k_lanczos2d(StencilGeom g
   const T* prv = MODE == 0 ? Xprev + roff : nullptr;
   if constexpr (kS2MaxEpl<T> == 4) {
     if (g.fepl == 4) {
-      s2f_strip<T, ORDER, MODE, 4>(g, tx, ty, w, lane, X + roff, W + roff, prv, j, s_cur, s_prev, bprev, alpha,
+      s2f_strip<T, ORDER, MODE, 4, NTS>(g, tx, ty, w, lane, X + roff, W + roff, prv, j, s_cur, s_prev, bprev, alpha,
                                    &vrow[w][0][0], &trow[w][0][0], &wrow[w][0][0], acc_b, acc_c, acc_a);
       goto sums;
     }
   }
   if (g.fepl == 2)
-    s2f_strip<T, ORDER, MODE, 2>(g, tx, ty, w, lane, X + roff, W + roff, prv, j, s_cur, s_prev, bprev, alpha,
+    s2f_strip<T, ORDER, MODE, 2, NTS>(g, tx, ty, w, lane, X + roff, W + roff, prv, j, s_cur, s_prev, bprev, alpha,
                                  &vrow[w][0][0], &trow[w][0][0], &wrow[w][0][0], acc_b, acc_c, acc_a);
   else
-    s2f_strip<T, ORDER, MODE, 1>(g, tx, ty, w, lane, X + roff, W + roff, prv, j, s_cur, s_prev, bprev, alpha,
+    s2f_strip<T, ORDER, MODE, 1, NTS>(g, tx, ty, w, lane, X + roff, W + roff, prv, j, s_cur, s_prev, bprev, alpha,
                                  &vrow[w][0][0], &trow[w][0][0], &wrow[w][0][0], acc_b, acc_c, acc_a);
 sums:
   // block sums in fixed order
@@ -794,9 +818,14 @@ template <typename T, int ORDER, int DIM, bool LZ>
 static void launch_stencil_t(const StencilGeom& g, const T* X, long xld, T* Y, long yld,
                              const T* Xprev, const LzState& S, int j, int k, hipStream_t st,
                              const int* active = nullptr) {
-  if constexpr (DIM == 2)
-    hipLaunchKernelGGL((k_stencil2d<T, ORDER, LZ>), dim3(stencil_blocks(g), k), dim3(256), 0, st, g, X, xld, Y,
-                       yld, Xprev, S, j, active);
+  if constexpr (DIM == 2) {
+    if (g.tune & kTuneNtStore)
+      hipLaunchKernelGGL((k_stencil2d<T, ORDER, LZ, true>), dim3(stencil_blocks(g), k), dim3(256), 0, st, g, X, xld,
+                         Y, yld, Xprev, S, j, active);
+    else
+      hipLaunchKernelGGL((k_stencil2d<T, ORDER, LZ, false>), dim3(stencil_blocks(g), k), dim3(256), 0, st, g, X, xld,
+                         Y, yld, Xprev, S, j, active);
+  }
   else
     hipLaunchKernelGGL((k_stencil<T, ORDER, DIM, LZ>), dim3(stencil_blocks(g), k), dim3(256), 0, st, g,
                        X, xld, Y, yld, Xprev, S, j, active);
@@ -829,7 +858,7 @@ void launch_stencil_batch(int order, int dim, int max_tiles, const T* X, T* Y, c
   }
 #define CASEB2(O)                                                                                            \
   if (order == O && dim == 2) {                                                                               \
-    hipLaunchKernelGGL((k_stencil2d<T, O, true>), dim3(max_tiles, S.k), dim3(256), 0, st, g, X, 0L, Y, 0L,  \
+    hipLaunchKernelGGL((k_stencil2d<T, O, true, false>), dim3(max_tiles, S.k), dim3(256), 0, st, g, X, 0L, Y, 0L, \
                        Xprev, S, j, (const int*)nullptr);                                                    \
     return;                                                                                                   \
   }
@@ -849,11 +878,15 @@ void launch_lanczos2d(const StencilGeom& g, int order, int mode, int grid_x, con
                       const T* Xprev, const LzState& S, int j, int k, double* out_a, double* out_b, double* out_c,
                       hipStream_t st) {
   const dim3 grid(grid_x > 0 ? grid_x : lanczos2d_blocks(g), k);
-#define CASEL(O, M)                                                                                            \
-  if (order == O && mode == M) {                                                                                \
-    hipLaunchKernelGGL((k_lanczos2d<T, O, M>), grid, dim3(256), 0, st, g, X, xld, W, Xprev, S, j, out_a, out_b, \
-                       out_c);                                                                                  \
-    return;                                                                                                     \
+#define CASEL(O, M)                                                                                             \
+  if (order == O && mode == M) {                                                                                 \
+    if (g.tune & kTuneNtStore)                                                                                   \
+      hipLaunchKernelGGL((k_lanczos2d<T, O, M, true>), grid, dim3(256), 0, st, g, X, xld, W, Xprev, S, j, out_a, \
+                         out_b, out_c);                                                                          \
+    else                                                                                                         \
+      hipLaunchKernelGGL((k_lanczos2d<T, O, M, false>), grid, dim3(256), 0, st, g, X, xld, W, Xprev, S, j, out_a,\
+                         out_b, out_c);                                                                          \
+    return;                                                                                                      \
   }
   CASEL(1, 0) CASEL(2, 0) CASEL(1, 1) CASEL(2, 1)
 #undef CASEL
