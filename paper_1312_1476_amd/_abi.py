@@ -81,6 +81,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run paper_1312_1476_amd.build.build()")
+        # torch brings its own HIP runtime: it must initialise the device before the library's first HIP call,
+        # or its own later initialisation finds no GPU
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
         handle = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(handle, name)
