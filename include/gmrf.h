@@ -121,8 +121,13 @@ gmrf_status gmrf_op_set_ichol_precond(gmrf_op* Q, int enable, double droptol, do
 gmrf_status gmrf_ichol_info(const gmrf_op* Q, int64_t* nnz_L, int32_t* levels, double* shift);
 
 /* Device bytes one gmrf_sample call needs for k right-hand sides and m_max steps (Krylov
- * basis, work vectors, partial sums, FFT scratch), plus what the handle keeps resident.    */
+ * basis, work vectors, partial sums, FFT scratch, the tridiagonal step; each allocation rounded
+ * up to the scratch pool's 2 MiB granularity), plus what the handle keeps resident.        */
 gmrf_status gmrf_op_bytes(const gmrf_op* Q, int64_t k, int32_t m_max, int reorth, size_t* bytes);
+
+/* The same for gmrf_sample_two_pass: three Krylov slots, both passes' scalars, the tridiagonal
+ * step and, when preconditioned, the accumulator of u_m.                                    */
+gmrf_status gmrf_op_bytes_two_pass(const gmrf_op* Q, int64_t k, int32_t m_max, size_t* bytes);
 
 /* Lattice size n of the operator. */
 gmrf_status gmrf_op_size(const gmrf_op* Q, int64_t* n);
@@ -323,6 +328,31 @@ gmrf_status gmrf_bandwidth_bench(int which, size_t bytes, int32_t blocks, int32_
  * free blocks (scratch of finished calls kept for reuse) to the device.                     */
 gmrf_status gmrf_set_hbm_budget(size_t bytes);
 size_t gmrf_hbm_in_use(void);
+
+/* Reserve one device region of `bytes` (rounded up to 2 MiB) for the scratch pool: from then on
+ * every call's scratch is carved from it (best fit over free ranges, merged when blocks return)
+ * and the pool makes no further device allocations or releases, whose cost on this part is
+ * irregular (up to seconds for 100 GB, and a release waits for the whole device).  For servers
+ * whose request sizes vary.  A call whose scratch finds no free range large enough returns
+ * GMRF_ENOMEM without running (it may succeed once running calls have returned theirs).
+ * bytes = 0 releases the region.  Reserving or releasing while calls hold scratch from the
+ * region returns GMRF_EINVAL; cached blocks outside the region are returned to the device
+ * first.  The budget (gmrf_set_hbm_budget) still applies to what calls hold.                 */
+gmrf_status gmrf_pool_reserve(size_t bytes);
+
+typedef struct {
+  size_t reserved_bytes;       /* size of the reserved region (0: none)                      */
+  size_t largest_free_range;   /* largest free range in the region                           */
+  size_t in_use;               /* scratch bytes held by running calls                        */
+  size_t cached;               /* freed blocks kept for reuse outside the region             */
+  uint64_t device_allocs;      /* hipMalloc calls made by the pool since load                */
+  uint64_t device_frees;       /* hipFree calls made by the pool since load                  */
+  double alloc_seconds;        /* wall time spent in them                                    */
+  double free_seconds;
+} gmrf_pool_info;
+
+/* The pool's state and its device-allocator counters (host struct, filled in).               */
+gmrf_status gmrf_pool_query(gmrf_pool_info* info);
 
 const char* gmrf_strerror(gmrf_status s);
 const char* gmrf_last_error(void);

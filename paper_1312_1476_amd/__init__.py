@@ -50,11 +50,14 @@ def _storage_code(storage):
 class Operator:
     """A device-resident precision operator (gmrf_op handle)."""
 
-    def __init__(self, handle, n, storage, shape=None):
+    def __init__(self, handle, n, storage, shape=None, order=None):
         self._h = handle
         self.n = int(n)
         self.storage = storage
-        self.shape = shape
+        self.shape = shape          # lattice shape (None for CSR)
+        self.order = order          # lattice order 1 or 2 (None for CSR)
+        self.precond = False        # circulant or incomplete-Cholesky preconditioning enabled
+        self.has_diag = False       # Q + diag(d)
 
     # -- construction ---------------------------------------------------------------------
     @classmethod
@@ -66,7 +69,7 @@ class Operator:
         sc = _storage_code(storage)
         check(lib().gmrf_op_create_lattice(len(shape), arr, int(order), float(kappa2), float(tau), bc, sc,
                                            C.byref(h)), "gmrf_op_create_lattice")
-        return cls(h, int(np.prod(shape)), sc, shape)
+        return cls(h, int(np.prod(shape)), sc, shape, int(order))
 
     @classmethod
     def csr(cls, n, indptr, indices, data, storage="f64"):
@@ -84,11 +87,13 @@ class Operator:
         preconditioning on a periodic 2D lattice the preconditioner stays M = Q."""
         if d is None:
             check(lib().gmrf_op_set_diagonal(self._h, None), "gmrf_op_set_diagonal")
+            self.has_diag = False
             return self
         arr = np.ascontiguousarray(d, dtype=np.float64)
         if arr.shape != (self.n,):
             raise ValueError(f"diagonal must have shape ({self.n},)")
         check(lib().gmrf_op_set_diagonal(self._h, arr.ctypes.data_as(C.c_void_p)), "gmrf_op_set_diagonal")
+        self.has_diag = True
         return self
 
     def set_ichol_precond(self, droptol=-1.0, enable=True):
@@ -97,6 +102,7 @@ class Operator:
         sh = C.c_double()
         check(lib().gmrf_op_set_ichol_precond(self._h, 1 if enable else 0, float(droptol), C.byref(sh)),
               "gmrf_op_set_ichol_precond")
+        self.precond = bool(enable)
         return sh.value
 
     def ichol_info(self):
@@ -107,6 +113,7 @@ class Operator:
 
     def set_circulant_precond(self, enable=True):
         check(lib().gmrf_op_set_circulant_precond(self._h, 1 if enable else 0), "gmrf_op_set_circulant_precond")
+        self.precond = bool(enable)
         return self
 
     def close(self):
@@ -126,8 +133,15 @@ class Operator:
         return torch.float64 if self.storage == GMRF_F64 else torch.float32
 
     def bytes(self, k, m_max, reorth=False):
+        """Device bytes of one sample call with a stored Krylov basis (and of the handle)."""
         out = C.c_size_t()
         check(lib().gmrf_op_bytes(self._h, int(k), int(m_max), int(bool(reorth)), C.byref(out)), "gmrf_op_bytes")
+        return out.value
+
+    def bytes_two_pass(self, k, m_max):
+        """Device bytes of one two-pass sample call (three Krylov slots) and of the handle."""
+        out = C.c_size_t()
+        check(lib().gmrf_op_bytes_two_pass(self._h, int(k), int(m_max), C.byref(out)), "gmrf_op_bytes_two_pass")
         return out.value
 
     # -- kernels -----------------------------------------------------------------------------
@@ -426,3 +440,16 @@ def set_hbm_budget(nbytes):
 
 def hbm_in_use():
     return int(lib().gmrf_hbm_in_use())
+
+
+def pool_reserve(nbytes):
+    """Reserve one device region of nbytes for the library's scratch (0 releases it); calls then
+    allocate nothing from the device."""
+    check(lib().gmrf_pool_reserve(int(nbytes)), "gmrf_pool_reserve")
+
+
+def pool_info():
+    """The scratch pool's state and device-allocator counters, as a dict."""
+    info = _abi.PoolInfo()
+    check(lib().gmrf_pool_query(C.byref(info)), "gmrf_pool_query")
+    return {f: getattr(info, f) for f, _ in _abi.PoolInfo._fields_}

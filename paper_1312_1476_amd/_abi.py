@@ -21,6 +21,12 @@ class Info(C.Structure):
                 ("rel_residual", C.c_double), ("err_bound", C.c_double)]
 
 
+class PoolInfo(C.Structure):
+    _fields_ = [("reserved_bytes", C.c_size_t), ("largest_free_range", C.c_size_t), ("in_use", C.c_size_t),
+                ("cached", C.c_size_t), ("device_allocs", C.c_uint64), ("device_frees", C.c_uint64),
+                ("alloc_seconds", C.c_double), ("free_seconds", C.c_double)]
+
+
 # name -> (restype, argtypes); mirrors include/gmrf.h one to one
 SIGNATURES = {
     "gmrf_op_create_lattice": (C.c_int, [C.c_int, C.POINTER(C.c_int64), C.c_int, C.c_double, C.c_double,
@@ -32,6 +38,7 @@ SIGNATURES = {
     "gmrf_op_set_ichol_precond": (C.c_int, [C.c_void_p, C.c_int, C.c_double, C.POINTER(C.c_double)]),
     "gmrf_ichol_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "gmrf_op_bytes": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int, C.POINTER(C.c_size_t)]),
+    "gmrf_op_bytes_two_pass": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]),
     "gmrf_op_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "gmrf_op_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "gmrf_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
@@ -68,6 +75,8 @@ SIGNATURES = {
                                        C.POINTER(C.c_double), C.c_void_p]),
     "gmrf_set_hbm_budget": (C.c_int, [C.c_size_t]),
     "gmrf_hbm_in_use": (C.c_size_t, []),
+    "gmrf_pool_reserve": (C.c_int, [C.c_size_t]),
+    "gmrf_pool_query": (C.c_int, [C.POINTER(PoolInfo)]),
     "gmrf_strerror": (C.c_char_p, [C.c_int]),
     "gmrf_last_error": (C.c_char_p, []),
 }

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <array>
 #include <cmath>
 #include <cstdarg>
@@ -63,19 +64,73 @@ static gmrf_status check_device() {
 }
 
 // ---- scratch pool ---------------------------------------------------------------------------------
+// Calls take their scratch from here in blocks rounded to 2 MiB.  By default a block comes from a cache of
+// freed blocks (a cached block at most 25% larger than asked is reused) or from hipMalloc.  Device
+// allocation and release are slow and irregular on this part when memory has been used before (seconds
+// for some 100 GB requests, and hipFree waits for the whole device), so a server with a varied mix of
+// request sizes reserves one region up front (gmrf_pool_reserve): blocks are then carved from it, best
+// fit in an address-ordered list of free ranges that merges neighbours when a block comes back, and the
+// pool calls into the device allocator no more.
 namespace {
+using Clock = std::chrono::steady_clock;
+
 struct Pool {
   std::mutex mu;
   std::multimap<size_t, void*> free_blocks;
   size_t in_use = 0;
   size_t cached = 0;
   size_t budget = 0;
+  char* region = nullptr;
+  size_t region_size = 0;
+  std::map<size_t, size_t> holes;     // free ranges of the region: offset -> length
+  uint64_t n_alloc = 0, n_free = 0;
+  double t_alloc = 0.0, t_free = 0.0;
+
+  hipError_t dev_alloc(void** p, size_t bytes) {
+    const auto t0 = Clock::now();
+    const hipError_t e = hipMalloc(p, bytes);
+    t_alloc += std::chrono::duration<double>(Clock::now() - t0).count();
+    ++n_alloc;
+    return e;
+  }
+  void dev_free(void* p) {
+    const auto t0 = Clock::now();
+    (void)hipFree(p);
+    t_free += std::chrono::duration<double>(Clock::now() - t0).count();
+    ++n_free;
+  }
+  void drop_cache() {
+    for (auto& kv : free_blocks) dev_free(kv.second);
+    free_blocks.clear();
+    cached = 0;
+  }
+  size_t largest_hole() const {
+    size_t b = 0;
+    for (auto& h : holes) b = std::max(b, h.second);
+    return b;
+  }
+  bool region_idle() const { return holes.size() == 1 && holes.begin()->second == region_size; }
 
   gmrf_status get(size_t bytes, void** out, size_t* actual) {
     bytes = rounded(bytes);
     std::lock_guard<std::mutex> lk(mu);
     if (budget && in_use + bytes > budget)
       return fail(GMRF_ENOMEM, "HBM budget %zu B exceeded (in use %zu B, request %zu B)", budget, in_use, bytes);
+    if (region) {
+      auto best = holes.end();
+      for (auto it = holes.begin(); it != holes.end(); ++it)
+        if (it->second >= bytes && (best == holes.end() || it->second < best->second)) best = it;
+      if (best == holes.end())
+        return fail(GMRF_ENOMEM, "reserved region of %zu B has no free range of %zu B (largest %zu B)", region_size,
+                    bytes, largest_hole());
+      const size_t off = best->first, len = best->second;
+      holes.erase(best);
+      if (len > bytes) holes.emplace(off + bytes, len - bytes);
+      *out = region + off;
+      *actual = bytes;
+      in_use += bytes;
+      return GMRF_OK;
+    }
     auto it = free_blocks.lower_bound(bytes);
     if (it != free_blocks.end() && it->first <= bytes + bytes / 4) {
       *out = it->second;
@@ -86,18 +141,12 @@ struct Pool {
       return GMRF_OK;
     }
     // cached blocks count against the budget: release them before allocating fresh memory
-    if (budget && in_use + cached + bytes > budget) {
-      for (auto& kv : free_blocks) (void)hipFree(kv.second);
-      free_blocks.clear();
-      cached = 0;
-    }
+    if (budget && in_use + cached + bytes > budget) drop_cache();
     void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    if (dev_alloc(&p, bytes) != hipSuccess) {
       (void)hipGetLastError();
-      for (auto& kv : free_blocks) (void)hipFree(kv.second);
-      free_blocks.clear();
-      cached = 0;
-      if (hipMalloc(&p, bytes) != hipSuccess) {
+      drop_cache();
+      if (dev_alloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return fail(GMRF_ENOMEM, "hipMalloc of %zu B failed", bytes);
       }
@@ -108,12 +157,30 @@ struct Pool {
     return GMRF_OK;
   }
   static size_t rounded(size_t bytes) { return (bytes + (2u << 20) - 1) & ~((size_t)(2u << 20) - 1); }
-  // `bytes` is the size the block was handed out with (its cached size)
+  // `bytes` is the size the block was handed out with
   void put(void* p, size_t bytes) {
     std::lock_guard<std::mutex> lk(mu);
+    in_use -= std::min(in_use, bytes);
+    char* c = static_cast<char*>(p);
+    if (region && c >= region && c < region + region_size) {
+      size_t off = (size_t)(c - region), len = bytes;
+      auto nx = holes.lower_bound(off);
+      if (nx != holes.end() && off + len == nx->first) {
+        len += nx->second;
+        nx = holes.erase(nx);
+      }
+      if (nx != holes.begin()) {
+        auto pv = std::prev(nx);
+        if (pv->first + pv->second == off) {
+          pv->second += len;
+          return;
+        }
+      }
+      holes.emplace(off, len);
+      return;
+    }
     free_blocks.emplace(bytes, p);
     cached += bytes;
-    in_use -= std::min(in_use, bytes);
   }
 };
 Pool& pool() {
@@ -219,9 +286,51 @@ gmrf_status gmrf_set_hbm_budget(size_t bytes) {
   std::lock_guard<std::mutex> lk(pool().mu);
   pool().budget = bytes;
   // cached free blocks go back to the device, so that what the caller sees free afterwards is free
-  for (auto& kv : pool().free_blocks) (void)hipFree(kv.second);
-  pool().free_blocks.clear();
-  pool().cached = 0;
+  pool().drop_cache();
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_pool_reserve(size_t bytes) {
+  if (bytes) {
+    gmrf_status ds = check_device();
+    if (ds != GMRF_OK) return ds;
+  }
+  Pool& P = pool();
+  std::lock_guard<std::mutex> lk(P.mu);
+  if (P.region && !P.region_idle())
+    return fail(GMRF_EINVAL, "the reserved region still holds scratch of running calls");
+  P.drop_cache();
+  if (P.region) {
+    P.dev_free(P.region);
+    P.region = nullptr;
+    P.region_size = 0;
+    P.holes.clear();
+  }
+  if (bytes == 0) return GMRF_OK;
+  bytes = Pool::rounded(bytes);
+  void* p = nullptr;
+  if (P.dev_alloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GMRF_ENOMEM, "hipMalloc of the %zu B region failed", bytes);
+  }
+  P.region = static_cast<char*>(p);
+  P.region_size = bytes;
+  P.holes.emplace(0, bytes);
+  return GMRF_OK;
+}
+
+gmrf_status gmrf_pool_query(gmrf_pool_info* info) {
+  if (!info) return fail(GMRF_EINVAL, "info is null");
+  Pool& P = pool();
+  std::lock_guard<std::mutex> lk(P.mu);
+  info->reserved_bytes = P.region_size;
+  info->largest_free_range = P.largest_hole();
+  info->in_use = P.in_use;
+  info->cached = P.cached;
+  info->device_allocs = P.n_alloc;
+  info->device_frees = P.n_free;
+  info->alloc_seconds = P.t_alloc;
+  info->free_seconds = P.t_free;
   return GMRF_OK;
 }
 
@@ -564,6 +673,8 @@ Sizes sizes_for(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3) 
   return z;
 }
 
+int groups_for(const gmrf_op* Q, int64_t k);
+
 size_t call_bytes(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3) {
   Sizes z = sizes_for(Q, k, m_max, reorth, ring3);
   size_t b = (size_t)z.slots * k * z.vec_bytes;       // Krylov basis
@@ -578,9 +689,38 @@ size_t call_bytes(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3
 }
 }  // namespace
 
+// Allocations of one call are rounded up to the pool's granularity; kPoolAllocs bounds the number of blocks a
+// column group's call takes (basis, work vectors, FFT or solve scratch, band tables, scalars, poll values, flags,
+// reorthogonalisation partials, tridiagonal output and scratch, two-pass accumulator).
+constexpr size_t kPoolGranule = (size_t)2 << 20;
+constexpr int kPoolAllocs = 12;
+
 extern "C" gmrf_status gmrf_op_bytes(const gmrf_op* Q, int64_t k, int32_t m_max, int reorth, size_t* bytes) {
   if (!Q || !bytes || k < 1 || m_max < 1) return fail(GMRF_EINVAL, "bad arguments");
-  *bytes = call_bytes(Q, k, m_max, reorth, false) + Q->resident_bytes;
+  const int G = groups_for(Q, k);
+  size_t b = 0;
+  for (int g = 0; g < G; ++g) {
+    const int64_t kg = k * (g + 1) / G - k * g / G;
+    b += call_bytes(Q, kg, m_max, reorth, false) + kPoolAllocs * kPoolGranule;
+  }
+  *bytes = b + Q->resident_bytes;
+  return GMRF_OK;
+}
+
+extern "C" gmrf_status gmrf_op_bytes_two_pass(const gmrf_op* Q, int64_t k, int32_t m_max, size_t* bytes) {
+  if (!Q || !bytes || k < 1 || m_max < 1) return fail(GMRF_EINVAL, "bad arguments");
+  const int G = groups_for(Q, k);
+  size_t b = 0;
+  for (int g = 0; g < G; ++g) {
+    const int64_t kg = k * (g + 1) / G - k * g / G;
+    const Sizes z = sizes_for(Q, kg, m_max, 0, true);
+    b += call_bytes(Q, kg, m_max, 0, true);                                  // pass 1: three slots, scalars
+    b += (size_t)kg * (m_max + 2) * 8 * 4 + (size_t)kg * 32 + 3 * (size_t)kg * z.pstride * 8;   // pass 2 scalars
+    b += (size_t)kg * m_max * 8 + tri_scratch_doubles((int)kg, m_max) * 8;    // y and its scratch
+    if (Q->precond || Q->ic) b += (size_t)kg * z.vec_bytes;                  // the u_m accumulator
+    b += kPoolAllocs * kPoolGranule;
+  }
+  *bytes = b + Q->resident_bytes;
   return GMRF_OK;
 }
 
@@ -1095,23 +1235,22 @@ static gmrf_status sample_impl(const gmrf_op* Q, const double* Z, int64_t k, dou
     R.tol = tol;
     R.st = fj.gs[g];
     if ((s = setup<T>(R, *ws[g])) != GMRF_OK) return s;
-    if (arena) {
-      // the closing buffers too, so that a call too large for the arena is refused before any kernel runs
-      if ((s = ws[g]->alloc((size_t)R.k * m_max, &ys[g])) != GMRF_OK) return s;
-      if (!solve && (s = ws[g]->alloc(tri_scratch_doubles(R.k, m_max), &scrs[g])) != GMRF_OK) return s;
-    }
-    if (solve) init_for_solve<T>(R, Z + (size_t)c0[g] * Q->n);
-    else init_from_z<T>(R, Z + (size_t)c0[g] * Q->n);
+    // the closing buffers too: every buffer of the call is taken before its first kernel, so that a call
+    // whose scratch does not fit (budget, reserved region, arena) is refused without running
+    if ((s = ws[g]->alloc((size_t)R.k * m_max, &ys[g])) != GMRF_OK) return s;
+    if (!solve && (s = ws[g]->alloc(tri_scratch_doubles(R.k, m_max), &scrs[g])) != GMRF_OK) return s;
+  }
+  for (int g = 0; g < G; ++g) {
+    if (solve) init_for_solve<T>(Rs[g], Z + (size_t)c0[g] * Q->n);
+    else init_from_z<T>(Rs[g], Z + (size_t)c0[g] * Q->n);
   }
   // y = T_m^{-1/2} e_1 (or T_m^{-1} e_1), then x_m = ||z|| V_m y, enqueued as soon as the group's columns stop
   auto close_group = [&](int g) -> gmrf_status {
     Run<T>& R = Rs[g];
-    if (!ys[g] && (s = ws[g]->alloc((size_t)R.k * m_max, &ys[g])) != GMRF_OK) return s;
     if (solve) {
       launch_tri_solve(R.S.alpha, m_max + 1, 1, R.S.beta, m_max + 2, 1, R.S.m_used, 0, R.S.status, ys[g], m_max,
                        R.S.status, R.k, R.st);
     } else {
-      if (!scrs[g] && (s = ws[g]->alloc(tri_scratch_doubles(R.k, m_max), &scrs[g])) != GMRF_OK) return s;
       launch_tri_invsqrt(R.S.alpha, m_max + 1, 1, R.S.beta, m_max + 2, 1, R.S.m_used, 0, R.S.status, ys[g], m_max,
                          R.S.status, scrs[g], m_max, R.k, R.st);
     }

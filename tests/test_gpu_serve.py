@@ -1,7 +1,7 @@
-"""Serving (continuous batching) over the C ABI: each result is identical alone and in a mix,
-admission never exceeds the HBM budget, admitted work overlaps, a sample whose stored basis
-does not fit runs the two-pass sampler, requests too large even for that are rejected, and a
-served sample matches the oracle."""
+"""Serving (continuous batching) over the C ABI: each result is identical alone, in a mix of
+overlapping jobs and coalesced into a batched job; admission never exceeds the HBM budget; a sample
+whose stored basis does not fit runs the two-pass sampler; requests too large even for that are
+rejected; and served samples (FP64 alone, FP32 storage in a batch) match the oracle."""
 import numpy as np
 import pytest
 
@@ -38,29 +38,14 @@ def _mix(serve):
     return [R(1, "sample", 0, 4, 7, tol=1e-6, m_max=300), R(2, "logdet", 1, 8, 11, m_max=40),
             R(3, "sample", 2, 3, 5, tol=1e-8, m_max=400), R(4, "sample", 3, 8, 9, tol=1e-6, m_max=400),
             R(5, "logdet", 2, 6, 13, m_max=60), R(6, "sample", 1, 16, 3, tol=1e-6, m_max=200),
-            R(7, "sample", 0, 32, 21, tol=1e-6, m_max=300), R(8, "logdet", 3, 4, 17, m_max=80)]
+            R(7, "sample", 0, 32, 21, tol=1e-6, m_max=300), R(8, "logdet", 3, 4, 17, m_max=80),
+            R(9, "logdet", 1, 8, 19, m_max=40), R(10, "sample", 0, 2, 29, tol=1e-6, m_max=300),
+            R(11, "sample", 3, 3, 31, tol=1e-6, m_max=400)]
 
 
-def test_alone_equals_mix(env):
+def _check_same(alone, reqs):
     import torch
-    gm, serve, ops = env
-    mix = _mix(serve)
-    alone = {}
-    srv = serve.Server(ops, hbm_budget=64 << 30, workers=1).start()
-    for req in _mix(serve):
-        srv.submit(req)
-        req.done.wait()
-        assert not req.error, req.error
-        alone[req.rid] = req.result
-    srv.stop()
-    srv = serve.Server(ops, hbm_budget=64 << 30, workers=4).start()
-    for req in mix:
-        srv.submit(req)
-    for req in mix:
-        req.done.wait()
-    srv.stop()
-    assert srv.peak_busy >= 2          # requests really overlapped on the device
-    for req in mix:
+    for req in reqs:
         assert not req.error, req.error
         a = alone[req.rid]
         if req.kind == "sample":
@@ -69,6 +54,40 @@ def test_alone_equals_mix(env):
         else:
             assert a["logdet"] == req.result["logdet"]
             assert np.array_equal(a["per_probe"], req.result["per_probe"])
+
+
+def test_alone_equals_mix(env):
+    gm, serve, ops = env
+    alone = {}
+    srv = serve.Server(ops, hbm_budget=64 << 30, workers=1).start()
+    for req in _mix(serve):
+        srv.submit(req)
+        req.done.wait()
+        assert not req.error, req.error
+        assert req.batched_with == 0
+        alone[req.rid] = req.result
+    srv.stop()
+    # four workers: jobs overlap on the device
+    mix = _mix(serve)
+    srv = serve.Server(ops, hbm_budget=64 << 30, workers=4).start()
+    for req in mix:
+        srv.submit(req)
+    for req in mix:
+        req.done.wait()
+    srv.stop()
+    assert srv.peak_busy >= 2
+    _check_same(alone, mix)
+    # one worker busy on the first request: the rest queue up and compatible ones are coalesced
+    # (samples on the 96x80 lattice into one uneven batch, log-dets on the 3D lattice into one call)
+    mix = _mix(serve)
+    srv = serve.Server(ops, hbm_budget=64 << 30, workers=1).start()
+    for req in mix:
+        srv.submit(req)
+    for req in mix:
+        req.done.wait()
+    srv.stop()
+    assert serve.stats(mix, 1.0)["batched"] >= 2 and srv.jobs < len(mix)
+    _check_same(alone, mix)
 
 
 def test_budget_admission_and_rejection(env):
@@ -109,6 +128,31 @@ def test_served_sample_matches_oracle(env):
         m = req.result["info"][r]["m_used"]
         ref = lanczos.sample_csr(Q, Z[r], m, tol=0.0)
         assert np.linalg.norm(X[r] - ref.x) / np.linalg.norm(ref.x) <= 1e-8
+
+
+def test_served_fp32_batch_matches_oracle(env):
+    """Two requests on the FP32-storage lattice coalesced into one uneven batch at the serving tolerance
+    1e-5: every column reaches it, and each sample is within 1e-5 (relative) of the oracle's x_m at the
+    same m."""
+    import torch
+    gm, serve, ops = env
+    srv = serve.Server(ops, hbm_budget=64 << 30, workers=1)
+    reqs = [serve.ServeRequest(1, "sample", 0, 3, 71, tol=1e-5, m_max=600),
+            serve.ServeRequest(2, "sample", 0, 2, 73, tol=1e-5, m_max=600)]
+    for r in reqs:
+        r.bytes = srv.request_bytes(r)
+    assert srv._batch_key(reqs[0]) == srv._batch_key(reqs[1]) is not None
+    results = srv._execute(reqs, torch.cuda.Stream())
+    Q = lattice.lattice_precision((96, 80), 1, 0.05, 1.0, "free")
+    for r, res in zip(reqs, results):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(r.seed)
+        Z = torch.randn((r.k, ops[0].n), dtype=torch.float64, device="cuda", generator=g).cpu().numpy()
+        X = res["X"].cpu().numpy()
+        assert [i["status"] for i in res["info"]] == ["OK"] * r.k
+        for c in range(r.k):
+            ref = lanczos.sample_csr(Q, Z[c], res["info"][c]["m_used"], tol=0.0)
+            assert np.linalg.norm(X[c] - ref.x) / np.linalg.norm(ref.x) <= 1e-5, (r.rid, c)
 
 
 def test_two_pass_fallback(env):
