@@ -257,7 +257,9 @@ gmrf_status gmrf_rademacher(uint64_t seed, int64_t n, int32_t n_probes, int8_t* 
  * m[r] <= ld):  y[r * ld + i] = (T_r^{-1/2} e_1)_i.  Computed by a trapezoidal rule for
  * lambda^{-1/2} = (2/pi) int exp(s) / (exp(2s) + lambda) ds on the real line: the rational
  * approximation of T^{-1/2} that the caption of Algorithm 1 suggests.  status[r] (device)
- * = GMRF_OK or GMRF_ENOTSPD.                                                               */
+ * = GMRF_OK or GMRF_ENOTSPD.  ld <= 16384 (EINVAL otherwise); this is also the longest
+ * recurrence (m_max, quadrature m) the samplers and the log-det estimators accept.  Up to
+ * ld = 1024 T is staged on chip, beyond that read from device memory: the same bits.      */
 gmrf_status gmrf_tridiag_invsqrt_e1(const double* alpha, const double* beta, const int32_t* m,
                                     int32_t k, int32_t ld, double* y, int32_t* status,
                                     void* stream);

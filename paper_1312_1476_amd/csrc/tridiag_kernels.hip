@@ -16,12 +16,16 @@
 //   d_{m-1} = alpha_{m-1} + sigma,  d_i = alpha_i + sigma - beta_i^2 / d_{i+1},
 // its entries are y_0 = 1/d_0, y_{i+1} = -(beta_i / d_{i+1}) y_i, and (T+sigma)^{-1}_{00} = 1/d_0.
 // Sums over nodes are fixed-order (lanes, wave butterflies, node blocks in order): deterministic.
+// Up to kTriLdsM steps T and the output accumulator are staged in LDS; longer recurrences (unpreconditioned
+// runs on ill-conditioned fields take a few thousand steps) read T from global memory and accumulate in the
+// output row, with the same arithmetic in the same order, so both forms give the same bits.
 #include "kernels.hpp"
 
 namespace gmrf {
 
 constexpr int kTriThreads = 256;
-constexpr int kTriMaxM = 1024;
+constexpr int kTriLdsM = 1024;      // T in LDS up to this many steps
+constexpr int kTriMaxM = 16384;     // longest recurrence the tridiagonal step accepts
 constexpr double kPad = 37.0;
 
 struct TriArgs {
@@ -71,30 +75,44 @@ __device__ bool tri_bracket(const double* a, const double* b, int m, double* red
   return true;
 }
 
-__device__ void tri_load(const TriArgs& A, int r, int m, double* a, double* b) {
-  for (int i = threadIdx.x; i < m; i += kTriThreads) {
-    a[i] = A.alpha[(size_t)r * A.lda + A.a_off + i];
-    b[i] = (i + 1 < m) ? A.beta[(size_t)r * A.ldb + A.b_off + i] : 0.0;
+// T of column r: copied into the LDS arrays sa, sb (LDS form) or read in place (b[m-1] is never read)
+template <bool LDS>
+__device__ void tri_view(const TriArgs& A, int r, int m, double* sa, double* sb, const double*& a, const double*& b) {
+  const double* ga = A.alpha + (size_t)r * A.lda + A.a_off;
+  const double* gb = A.beta + (size_t)r * A.ldb + A.b_off;
+  if constexpr (LDS) {
+    for (int i = threadIdx.x; i < m; i += kTriThreads) {
+      sa[i] = ga[i];
+      sb[i] = (i + 1 < m) ? gb[i] : 0.0;
+    }
+    __syncthreads();
+    a = sa;
+    b = sb;
+  } else {
+    a = ga;
+    b = gb;
   }
-  __syncthreads();
 }
 
 // Per node (one thread each): the backward pivots leave q_i = beta_i / d_{i+1} in the scratch rows, the
 // forward recurrence overwrites row i with w y_i (loads taken eight rows ahead, no cross-lane work in the
 // chain); then each wave sums whole rows over the block's nodes, and an LDS accumulator adds the
 // node blocks in order.
+template <bool LDS>
 __global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
-  __shared__ double a[kTriMaxM], b[kTriMaxM];
-  __shared__ double acc[kTriMaxM];
+  constexpr int LM = LDS ? kTriLdsM : 1;
+  __shared__ double sa[LM], sb[LM], sacc[LM];
   __shared__ double red[kTriThreads / kWave];
   __shared__ int ired[kTriThreads / kWave];
   const int r = blockIdx.x;
   // m never exceeds the LDS copy, the scratch rows or the output row
-  const int m = min(min(A.m ? A.m[r] : A.m_fixed, kTriMaxM), min(A.scr_m, A.ldy));
+  const int m = min(min(A.m ? A.m[r] : A.m_fixed, LDS ? kTriLdsM : kTriMaxM), min(A.scr_m, A.ldy));
   double* y = A.out + (size_t)r * A.ldy;
   if (A.status_in && A.status_in[r] != kOK && A.status_in[r] != kENOCONV) return;
   if (m <= 0) return;
-  tri_load(A, r, m, a, b);
+  const double *a, *b;
+  tri_view<LDS>(A, r, m, sa, sb, a, b);
+  double* acc = LDS ? sacc : y;     // the node blocks' sums, in order
   double lo, hi;
   const bool spd = tri_bracket(a, b, m, red, ired, lo, hi);
   if (!spd) {
@@ -107,7 +125,9 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   constexpr int NW = kTriThreads / kWave;
   constexpr int AH = 8;   // rows loaded ahead in the forward recurrence
-  for (int i = threadIdx.x; i < m; i += kTriThreads) acc[i] = 0.0;
+  // each row's sum is kept by the lane that adds to it (lane 0 of wave i mod NW), which also clears it
+  if (lane == 0)
+    for (int i = wv; i < m; i += NW) acc[i] = 0.0;
   double* rs = A.scratch + (size_t)r * A.scr_m * kTriThreads;
   for (int base = 0; base < nq; base += kTriThreads) {
     const int l = base + threadIdx.x;
@@ -149,18 +169,22 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
     }
     __syncthreads();   // the rows are rewritten by the next node block
   }
-  for (int i = threadIdx.x; i < m; i += kTriThreads) y[i] = acc[i];
+  if constexpr (LDS)
+    for (int i = threadIdx.x; i < m; i += kTriThreads) y[i] = acc[i];
 }
 
+template <bool LDS>
 __global__ __launch_bounds__(kTriThreads) void k_tri_log(TriArgs A) {
-  __shared__ double a[kTriMaxM], b[kTriMaxM];
+  constexpr int LM = LDS ? kTriLdsM : 1;
+  __shared__ double sa[LM], sb[LM];
   __shared__ double red[kTriThreads / kWave];
   __shared__ int ired[kTriThreads / kWave];
   const int r = blockIdx.x;
-  const int m = min(A.m ? A.m[r] : A.m_fixed, min(kTriMaxM, A.lda));
+  const int m = min(A.m ? A.m[r] : A.m_fixed, min(LDS ? kTriLdsM : kTriMaxM, A.lda));
   if (A.status_in && A.status_in[r] != kOK && A.status_in[r] != kENOCONV) return;
   if (m <= 0) return;
-  tri_load(A, r, m, a, b);
+  const double *a, *b;
+  tri_view<LDS>(A, r, m, sa, sb, a, b);
   double lo, hi;
   const bool spd = tri_bracket(a, b, m, red, ired, lo, hi);
   if (!spd) {
@@ -233,14 +257,19 @@ void launch_tri_invsqrt(const double* alpha, int lda, int a_off, const double* b
                         const int* m, int m_fixed, const int* status_in, double* y, int ldy,
                         int* status_out, double* scratch, int scr_m, int k, hipStream_t st) {
   TriArgs A{alpha, lda, a_off, beta, ldb, b_off, m, m_fixed, status_in, y, ldy, status_out, scratch, scr_m};
-  hipLaunchKernelGGL(k_tri_invsqrt, dim3(k), dim3(kTriThreads), 0, st, A);
+  // the form follows the caller's capacity (scratch rows), never the data, so a column gets the same form
+  // whichever m it stopped at
+  if (scr_m <= kTriLdsM) hipLaunchKernelGGL(k_tri_invsqrt<true>, dim3(k), dim3(kTriThreads), 0, st, A);
+  else hipLaunchKernelGGL(k_tri_invsqrt<false>, dim3(k), dim3(kTriThreads), 0, st, A);
 }
 
 void launch_tri_log(const double* alpha, int lda, int a_off, const double* beta, int ldb, int b_off,
                     const int* m, int m_fixed, const int* status_in, double* out, int ldo,
                     int* status_out, int k, hipStream_t st) {
   TriArgs A{alpha, lda, a_off, beta, ldb, b_off, m, m_fixed, status_in, out, ldo, status_out, nullptr, 0};
-  hipLaunchKernelGGL(k_tri_log, dim3(k), dim3(kTriThreads), 0, st, A);
+  // the row holds lda - a_off steps: the form follows that capacity
+  if (lda - a_off <= kTriLdsM) hipLaunchKernelGGL(k_tri_log<true>, dim3(k), dim3(kTriThreads), 0, st, A);
+  else hipLaunchKernelGGL(k_tri_log<false>, dim3(k), dim3(kTriThreads), 0, st, A);
 }
 
 }  // namespace gmrf

@@ -92,7 +92,7 @@ def _rand_tridiag(rng, m, cond):
     return alpha, beta
 
 
-@pytest.mark.parametrize("m", [1, 2, 7, 80, 300, 700])
+@pytest.mark.parametrize("m", [1, 2, 7, 80, 300, 700, 1024, 1025, 3000])
 @pytest.mark.parametrize("cond", [1.0, 1e3, 1e6])
 def test_tridiag_vs_eigh(gm, m, cond):
     import torch
@@ -114,6 +114,30 @@ def test_tridiag_vs_eigh(gm, m, cond):
         assert _rel(y[r, :m], ref) <= max(1e-13, 20 * kap * 2.2e-16), (_rel(y[r, :m], ref), kap)
         lref = lanczos.tridiag_log_e1(A[r, :m], B[r, :m])
         assert abs(lg[r] - lref) <= 1e-13 * max(1.0, abs(lref)) + 20 * kap * 2.2e-16
+
+
+def test_tridiag_lds_and_global_forms_agree_bitwise(gm):
+    """Up to 1024 steps T is staged in LDS; a caller whose rows hold more steps gets the form that reads
+    T from global memory.  Same arithmetic in the same order: the same T gives the same bits in both."""
+    import torch
+    rng = np.random.default_rng(77)
+    k = 4
+    ms = [1, 64, 700, 1024]
+    A = np.zeros((k, 1024))
+    B = np.zeros((k, 1024))
+    for r, m in enumerate(ms):
+        A[r, :m], B[r, :m] = _rand_tridiag(rng, m, 1e4)
+    mm = torch.tensor(ms, dtype=torch.int32, device="cuda:0")
+    y1, _ = gm.tridiag_invsqrt_e1(_t(A), _t(B), mm)
+    l1, _ = gm.tridiag_log_e1(_t(A), _t(B), mm)
+    A2, B2 = np.zeros((k, 2000)), np.zeros((k, 2000))
+    A2[:, :1024], B2[:, :1024] = A, B
+    y2, _ = gm.tridiag_invsqrt_e1(_t(A2), _t(B2), mm)
+    l2, _ = gm.tridiag_log_e1(_t(A2), _t(B2), mm)
+    y1, y2 = y1.cpu().numpy(), y2.cpu().numpy()
+    for r, m in enumerate(ms):
+        assert np.array_equal(y1[r, :m], y2[r, :m]), m
+    assert torch.equal(l1, l2)
 
 
 @pytest.mark.parametrize("scale", [1e-8, 1e-4, 1e4, 1e10])
