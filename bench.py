@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--kernel", default="", help="counters leg: kernel to run (default: the dominant one)")
     ap.add_argument("--storage", default="f64", help="counters leg: storage dtype (f64|f32)")
     ap.add_argument("--side", type=int, default=512, help="counters leg: lattice side of the operator (spmv)")
+    ap.add_argument("--dim", type=int, default=2, help="counters leg: 2 (13-point) or 3 (7-point) lattice (spmv)")
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="arrival window per serving rate")
     return ap.parse_args()
 
@@ -101,8 +102,12 @@ def main():
         # another: spmv = the 13-point operator alone), then a plain device copy of known size whose
         # FETCH_SIZE / WRITE_SIZE readings scale the counters to bytes
         name = args.kernel or DOMINANT_KERNEL
-        op = make(args.storage) if name != "spmv" else gm.Operator.lattice((args.side, args.side), sp.order, sp.kappa2,
-                                                                            sp.tau, sp.boundary, args.storage)
+        if name != "spmv":
+            op = make(args.storage)
+        elif args.dim == 3:      # the 3D 7-point operator (first order) of the serving pool's 3D lattices
+            op = gm.Operator.lattice((args.side,) * 3, 1, 0.05, 1.0, "free", args.storage)
+        else:
+            op = gm.Operator.lattice((args.side, args.side), sp.order, sp.kappa2, sp.tau, sp.boundary, args.storage)
         if name in ("spmv", "lz2d"):
             gm.autotune(op, k, reps=20, stream=stream)     # count the kernel with the launch options it runs with
         r = gm.kernel_bench(op, name, k, reps=50, stream=stream)
@@ -384,6 +389,8 @@ def _public(d):
 LGCP_TOL = 1e-8                  # Table 1's accuracy
 LGCP_TABLE_N = (16, 32, 64, 128, 256, 512, 1024, 2048, 4096)
 LGCP_BATCH = (512, 32)           # side, right-hand sides of the throughput line
+LGCP_UNPRE_N = (16, 32, 64, 128)   # Table 1's unpreconditioned row (the Krylov dimension grows with N)
+LGCP_UNPRE_M_MAX = 16384
 
 
 def lgcp_leg(gm, torch, stream):
@@ -409,6 +416,21 @@ def lgcp_leg(gm, torch, stream):
         torch.cuda.synchronize()
         out["table1_preconditioned_m"][str(N)] = info[0]["m_used"]
         out["ms_per_sample_k1"][str(N)] = round(1000 * (time.perf_counter() - t0) / reps, 3)
+        op.close()
+        del X, Z1
+    # Table 1's unpreconditioned row: Algorithm 1 on Q + H itself (CSR operator), the same column and tolerance
+    out["table1_unpreconditioned_m"], out["ms_per_sample_k1_unpreconditioned"] = {}, {}
+    for N in LGCP_UNPRE_N:
+        spec = workloads.lgcp_prior(N)
+        P = lgcp_posterior_csr(N, spec, workloads.lgcp_diagonal(N))
+        op = gm.Operator.csr(P.shape[0], P.indptr, P.indices, P.data)
+        Z1 = torch.from_numpy(np.ascontiguousarray(workloads.gaussian_block(N * N, 1, 5, 1).T)).to("cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, info = op.sample(Z1, tol=LGCP_TOL, m_max=LGCP_UNPRE_M_MAX)
+        torch.cuda.synchronize()
+        out["table1_unpreconditioned_m"][str(N)] = info[0]["m_used"] if info[0]["status"] == "OK" else None
+        out["ms_per_sample_k1_unpreconditioned"][str(N)] = round(1000 * (time.perf_counter() - t0), 1)
         op.close()
         del X, Z1
     N, k = LGCP_BATCH
@@ -477,6 +499,19 @@ def logdet_leg(gm, torch):
 
 
 ICHOL_DROPTOLS = (None, -1.0, 1e-2, 1e-3, 1e-4, 1e-5)   # None: no preconditioner; -1: IC(0)
+
+
+def lgcp_posterior_csr(N, spec, d):
+    """Q + diag(d) as CSR: Q = tau (kappa2 I + L)^2, L the 5-point graph Laplacian of the N x N torus
+    (the LGCP prior of Section 3 with the Fisher information of the counts on the diagonal)."""
+    import scipy.sparse as sps
+    T = sps.diags([-np.ones(N - 1), 2 * np.ones(N), -np.ones(N - 1)], [-1, 0, 1]).tolil()
+    T[0, N - 1] = T[N - 1, 0] = -1.0
+    L = sps.kron(T, sps.identity(N)) + sps.kron(sps.identity(N), T)
+    K = spec.kappa2 * sps.identity(N * N) + L
+    P = sps.csr_matrix(spec.tau * (K @ K) + sps.diags(np.asarray(d, dtype=np.float64)))
+    P.sort_indices()
+    return P
 
 
 def section52_matrix():

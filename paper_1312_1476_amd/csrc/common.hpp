@@ -31,6 +31,7 @@ struct StencilGeom {
   int band;                // 2D operator kernel: output rows per wave (0: kS2Band)
   int ftiles_y;            // 2D one-pass Lanczos kernel: bands of kS2Waves x kS2Band rows
   int tune;                // launch options that leave every result bit unchanged (kTune* bits)
+  int zc;                  // 3D first-order lattices: planes per z-march block (0: box tiles)
 };
 
 // Launch options chosen by the autotuner.  None of them changes what a thread computes or the order of

@@ -2152,7 +2152,7 @@ static gmrf_status sample_batch_impl(int nf, const gmrf_op* const* ops, const in
       S.col_pb = dpbf;
     } else {
       launch_stencil_batch<T>(Q0->order, Q0->dim, max_tiles, slot(j - 1), Qb, j >= 2 ? slot(j - 2) : slot(0), S, j,
-                              st);
+                              st, Q0->geom.zc > 0);
       launch_update<T>(Qb, slot(j - 1), slot(j), max_len, j, 1, S, st);
     }
     if (j % poll == 0 && j < m_max) {
@@ -2215,6 +2215,9 @@ extern "C" gmrf_status gmrf_sample_batch(int32_t n_fields, const gmrf_op* const*
       return fail(GMRF_EUNSUPPORTED, "field %d: batches take lattice operators without preconditioning or diagonal", f);
     if (Q->ndim != ops[0]->ndim || Q->order != ops[0]->order || Q->storage != ops[0]->storage)
       return fail(GMRF_EINVAL, "field %d: all fields must share ndim, order and storage", f);
+    if ((Q->geom.zc > 0) != (ops[0]->geom.zc > 0))
+      return fail(GMRF_EUNSUPPORTED, "field %d: 3D first-order fields of one batch must all have their last "
+                  "(contiguous) side <= 512, or all > 512", f);
     if (k[f] < 1) return fail(GMRF_EINVAL, "field %d: k must be >= 1", f);
     K += k[f];
   }

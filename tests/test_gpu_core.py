@@ -38,8 +38,12 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+# 3D first-order lattices of 2^20 points and more march along z: several row segments with a ragged last
+# one and ragged runs of planes (37, 181, 157), rows of the maximum 512 points (5, 410, 512), a single
+# segment per plane (4100, 16, 16); rows of 513 points take the box tiles (3, 700, 513)
 LATTICES = [((300,), 1), ((300,), 2), ((64, 64), 1), ((45, 70), 2), ((17, 130), 1), ((130, 17), 2),
-            ((9, 10, 11), 1), ((16, 16, 16), 1), ((7, 9, 20), 2), ((1, 1), 1), ((2, 2), 2)]
+            ((9, 10, 11), 1), ((16, 16, 16), 1), ((7, 9, 20), 2), ((1, 1), 1), ((2, 2), 2),
+            ((37, 181, 157), 1), ((5, 410, 512), 1), ((4100, 16, 16), 1), ((3, 700, 513), 1)]
 
 
 @pytest.mark.parametrize("shape,order", LATTICES)
@@ -204,6 +208,8 @@ CASES = [
     ("lat", (33, 40), 1, 0.05, "periodic", 2, 60),
     ("lat", (500,), 2, 0.5, "free", 2, 30),
     ("lat", (7, 9, 20), 2, 0.4, "periodic", 1, 30),
+    ("lat", (37, 181, 157), 1, 0.2, "free", 2, 40),
+    ("lat", (4100, 16, 16), 1, 0.3, "periodic", 2, 30),
     ("csr", None, None, None, None, 2, 60),
 ]
 
