@@ -150,6 +150,25 @@ __global__ __launch_bounds__(256) void k_stencil(StencilGeom g0, const T* __rest
   }
 }
 
+// XCD-aware tile order (kTuneXcd): the dispatcher hands workgroup i (linear over the grid) to XCD i mod 8,
+// each XCD with its own L2.  Logical (tile, column) ids are assigned so that every XCD works through one
+// contiguous range of them: neighbouring strips and bands, whose halo rows and columns overlap, then meet
+// in one L2.  The map is a bijection of the grid.
+constexpr int kXcds = 8;
+__device__ __forceinline__ void xcd_order(bool on, int& tile, int& col) {
+  if (!on) {
+    tile = blockIdx.x;
+    col = blockIdx.y;
+    return;
+  }
+  const int gx = gridDim.x, nb = gx * gridDim.y;
+  const int i = blockIdx.x + blockIdx.y * gx;
+  const int q = nb / kXcds, rm = nb % kXcds, x = i % kXcds, k = i / kXcds;
+  const int L = (x < rm ? x * (q + 1) : rm * (q + 1) + (x - rm) * q) + k;
+  tile = L % gx;
+  col = L / gx;
+}
+
 // ---- 3D first-order lattices: z-march ----------------------------------------------------------
 // A block owns a segment of `band` whole rows of the plane (at most kZSeg points) and walks a run of `zc`
 // planes along z.  Each thread keeps its points of planes z - 1, z and z + 1 in registers (plane z + 1 and
@@ -170,17 +189,19 @@ __global__ __launch_bounds__(kZThreads) void k_stencil3z(StencilGeom g0, const T
   __shared__ T pl[kZSeg + 2 * kZMaxN2];       // halo row above, the segment, halo row below
   __shared__ double red[kZThreads / kWave];
   __shared__ int flag[1];
-  const int r = blockIdx.y;
+  // XCD-contiguous order: the segments and runs that share halo rows and planes meet in one L2
+  int tile, r;
+  xcd_order(true, tile, r);
   const StencilGeom g = (LZ && S.col_geom) ? S.col_geom[r] : g0;
-  if ((int)blockIdx.x >= g.tiles_x * g.tiles_z) return;
+  if (tile >= g.tiles_x * g.tiles_z) return;
   double s_cur = 1.0, s_prev = 0.0, bprev = 0.0;
   if (LZ) {
-    if (!lz_open<kZThreads>(S, r, j, blockIdx.x == 0, red, flag, s_cur, s_prev, bprev)) return;
+    if (!lz_open<kZThreads>(S, r, j, tile == 0, red, flag, s_cur, s_prev, bprev)) return;
   } else if (active && !active[r]) {
     return;
   }
   const int n0 = g.n0, n1 = g.n1, n2 = g.n2;
-  const int seg = (int)blockIdx.x % g.tiles_x, zi = (int)blockIdx.x / g.tiles_x;
+  const int seg = tile % g.tiles_x, zi = tile / g.tiles_x;
   const int y0 = seg * g.band, rows = min(g.band, n1 - y0), E = rows * n2;
   const int z0 = zi * g.zc, z1 = min(n0, z0 + g.zc);
   const bool per = g.periodic != 0;
@@ -286,7 +307,7 @@ __global__ __launch_bounds__(kZThreads) void k_stencil3z(StencilGeom g0, const T
   }
   if (LZ) {
     const double bs = block_sum<kZThreads>(acc, red);
-    if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + blockIdx.x] = bs;
+    if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + tile] = bs;
   }
 }
 
@@ -301,24 +322,6 @@ __global__ __launch_bounds__(kZThreads) void k_stencil3z(StencilGeom g0, const T
 constexpr int kS2Waves = 4;     // waves per block (bands stacked vertically)
 constexpr int kS2Band = 32;     // output rows per wave
 
-// XCD-aware tile order (kTuneXcd): the dispatcher hands workgroup i (linear over the grid) to XCD i mod 8,
-// each XCD with its own L2.  Logical (tile, column) ids are assigned so that every XCD works through one
-// contiguous range of them: neighbouring strips and bands, whose halo rows and columns overlap, then meet
-// in one L2.  The map is a bijection of the grid.
-constexpr int kXcds = 8;
-__device__ __forceinline__ void xcd_order(bool on, int& tile, int& col) {
-  if (!on) {
-    tile = blockIdx.x;
-    col = blockIdx.y;
-    return;
-  }
-  const int gx = gridDim.x, nb = gx * gridDim.y;
-  const int i = blockIdx.x + blockIdx.y * gx;
-  const int q = nb / kXcds, rm = nb % kXcds, x = i % kXcds, k = i / kXcds;
-  const int L = (x < rm ? x * (q + 1) : rm * (q + 1) + (x - rm) * q) + k;
-  tile = L % gx;
-  col = L / gx;
-}
 // rows requested ahead per wave: a row is 64 elements, so FP32 rows carry half the bytes of FP64 rows
 #ifndef GMRF_S2_AHEAD64
 #define GMRF_S2_AHEAD64 4
