@@ -21,8 +21,13 @@
  *   - "Device" pointers are HIP device allocations on the current device; "host" pointers
  *     are ordinary host memory.  The caller owns every buffer it passes; the library owns
  *     the memory behind a gmrf_op handle and its own scratch.
- *   - `stream` is a hipStream_t (NULL = the default stream).  Sample and log-det calls are
- *     blocking: they return after the results (and `info`) are complete.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are stream-ordered: their
+ *     kernels run after the work already queued on `stream` (a call that spreads its columns
+ *     over side streams forks them from `stream` with an event and joins them back), and work
+ *     queued on `stream` afterwards runs after them.  Sample, solve and log-det calls also
+ *     synchronise their own work before returning -- the stop polls read rho_j from the device,
+ *     and `info` and the host outputs are written after that internal sync -- so X is complete
+ *     on return; Z and X need to stay valid only for the duration of the call.
  *   - Calls that share one gmrf_op may run concurrently; each call has its own scratch.
  */
 #ifndef GMRF_H

@@ -111,6 +111,32 @@ def test_budget_admission_and_rejection(env):
     assert st["completed"] == len(reqs) and st["rejected"] == 1
 
 
+def test_budget_holds_in_the_librarys_own_accounting(env):
+    """The admission estimate against what the library really holds: with the library's scratch confined
+    to a region of exactly the budget's size (Z and X, which torch allocates, are outside it), every
+    admitted mix still runs -- a job that found the region fragmented is retried once others return
+    their scratch -- and the library holds nothing afterwards."""
+    gm, serve, ops = env
+    probe = serve.Server(ops, hbm_budget=1 << 40)
+    sizes = [probe.request_bytes(r) for r in _mix(serve)]
+    budget = int(max(sizes) * 1.3)
+    gm.pool_reserve(budget)
+    try:
+        a0 = gm.pool_info()["device_allocs"]
+        reqs = _mix(serve)
+        srv = serve.Server(ops, hbm_budget=budget, workers=4, keep_results=False).start()
+        for req in reqs:
+            srv.submit(req)
+        for req in reqs:
+            req.done.wait()
+        srv.stop()
+        assert all(not r.error for r in reqs), [r.error for r in reqs if r.error]
+        info = gm.pool_info()
+        assert info["in_use"] == 0 and info["device_allocs"] == a0 and info["largest_free_range"] >= budget
+    finally:
+        gm.pool_reserve(0)
+
+
 def test_served_sample_matches_oracle(env):
     import torch
     gm, serve, ops = env
