@@ -182,11 +182,159 @@ constexpr int kZSeg = kZThreads * kZEpt;        // points per segment
 constexpr int kZMaxN2 = kZSeg / 2;              // the two halo rows are loaded kZEpt per thread too
 constexpr long kZMinPoints = 1L << 20;          // lattices from this size march (smaller ones: box tiles)
 
+template <typename T, int VE> struct ZVec;
+template <typename T> struct ZVec<T, 1> { typedef T type; };
+template <> struct ZVec<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct ZVec<float, 2> { typedef float type __attribute__((ext_vector_type(2))); };
+
+// One block's run.  VE points per load (2 when the row length is even: every pair lies in one row and
+// starts at an even offset), so a thread holds kZEpt / VE groups of VE consecutive points; the terms of
+// every point and the order of every sum depend only on VE, which each block takes from its own lattice.
+template <typename T, bool LZ, int VE>
+__device__ __forceinline__ void z3_run(const StencilGeom& g, int tile, T* pl, const T* __restrict__ src,
+                                       T* __restrict__ dst, const T* __restrict__ prv, int j, double s_cur,
+                                       double s_prev, double bprev, double& acc) {
+  using V = typename ZVec<T, VE>::type;
+  constexpr int NS = kZEpt / VE;
+  const int n0 = g.n0, n1 = g.n1, n2 = g.n2;
+  const int seg = tile % g.tiles_x, zi = tile / g.tiles_x;
+  const int y0 = seg * g.band, rows = min(g.band, n1 - y0), E = rows * n2;
+  const int z0 = zi * g.zc, z1 = min(n0, z0 + g.zc);
+  const bool per = g.periodic != 0;
+  const size_t plane = (size_t)n1 * n2, sbase = (size_t)y0 * n2;
+  const int yup = y0 > 0 ? y0 - 1 : (per ? n1 - 1 : -1);               // halo rows (-1: none)
+  const int ydn = y0 + rows < n1 ? y0 + rows : (per ? 0 : -1);
+  const T k2 = (T)g.kappa2, tau = (T)g.tau;
+  const bool prev_term = LZ && j > 1;
+  auto first = [&](int i) { return VE * ((int)threadIdx.x + i * kZThreads); };   // first point of group i
+
+  int lx[kZEpt], ly[kZEpt];
+#pragma unroll
+  for (int i = 0; i < NS; ++i)
+#pragma unroll
+    for (int v = 0; v < VE; ++v) {
+      const int e = first(i) + v;
+      ly[i * VE + v] = e / n2;
+      lx[i * VE + v] = e - ly[i * VE + v] * n2;
+    }
+  auto get = [&](const T* p, size_t gi, T* out, double scale, bool scaled) {
+    const V raw = *(const V*)(p + gi);
+#pragma unroll
+    for (int v = 0; v < VE; ++v) {
+      T x;
+      if constexpr (VE == 1) x = raw;
+      else x = raw[v];
+      out[v] = scaled ? (T)((double)x * scale) : x;
+    }
+  };
+  // the segment of plane z (zeros for a plane beyond a free boundary)
+  auto load_seg = [&](int z, T* vv) {
+    const int zz = z < 0 ? (per ? z + n0 : -1) : (z >= n0 ? (per ? z - n0 : -1) : z);
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const int e = first(i);
+      if (zz >= 0 && e < E) get(src, (size_t)zz * plane + sbase + e, vv + i * VE, s_cur, LZ);
+      else
+#pragma unroll
+        for (int v = 0; v < VE; ++v) vv[i * VE + v] = (T)0;
+    }
+  };
+  // the halo rows of plane z (0 <= z < n0): points [0, n2) the row above, [n2, 2 n2) the row below
+  auto load_halo = [&](int z, T* h) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const int e = first(i);
+      const int row = e < n2 ? yup : ydn;
+      if (e < 2 * n2 && row >= 0) get(src, (size_t)z * plane + (size_t)row * n2 + (e < n2 ? e : e - n2), h + i * VE, s_cur, LZ);
+      else
+#pragma unroll
+        for (int v = 0; v < VE; ++v) h[i * VE + v] = (T)0;
+    }
+  };
+  auto load_prev = [&](int z, T* pp) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const int e = first(i);
+      if (prev_term && e < E) get(prv, (size_t)z * plane + sbase + e, pp + i * VE, s_prev, true);
+      else
+#pragma unroll
+        for (int v = 0; v < VE; ++v) pp[i * VE + v] = (T)0;
+    }
+  };
+
+  T vp[kZEpt], vc[kZEpt], vn[kZEpt], hc[kZEpt], hn[kZEpt], pc[kZEpt], pn[kZEpt];
+  load_seg(z0 - 1, vp);
+  load_seg(z0, vc);
+  load_halo(z0, hc);
+  load_prev(z0, pc);
+  for (int z = z0; z < z1; ++z) {
+    load_seg(z + 1, vn);
+    if (z + 1 < z1) {
+      load_halo(z + 1, hn);
+      load_prev(z + 1, pn);
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const int e0 = first(i);
+#pragma unroll
+      for (int v = 0; v < VE; ++v) {
+        const int e = e0 + v;
+        if (e < E) pl[n2 + e] = vc[i * VE + v];
+        if (e < 2 * n2) pl[e < n2 ? e : (rows + 1) * n2 + (e - n2)] = hc[i * VE + v];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const int e0 = first(i);
+      if (e0 >= E) continue;
+      T outv[VE];
+#pragma unroll
+      for (int v = 0; v < VE; ++v) {
+        const int q = i * VE + v, e = e0 + v;
+        const int x = lx[q], y = y0 + ly[q], c = n2 + e;
+        const T vv = vc[q];
+        T a = k2 * vv;
+        if (per || x - 1 >= 0) a += vv - pl[x > 0 ? c - 1 : c + n2 - 1];
+        if (per || x + 1 < n2) a += vv - pl[x + 1 < n2 ? c + 1 : c - n2 + 1];
+        if (per || y - 1 >= 0) a += vv - pl[c - n2];
+        if (per || y + 1 < n1) a += vv - pl[c + n2];
+        if (per || z - 1 >= 0) a += vv - vp[q];
+        if (per || z + 1 < n0) a += vv - vn[q];
+        const T out = tau * a;
+        if (LZ) {
+          double qd = (double)out;
+          if (prev_term) qd -= bprev * (double)pc[q];
+          const T qt = (T)qd;
+          outv[v] = qt;
+          acc += (double)vv * (double)qt;
+        } else {
+          outv[v] = out;
+        }
+      }
+      V ov;
+      if constexpr (VE == 1) ov = outv[0];
+      else
+#pragma unroll
+        for (int v = 0; v < VE; ++v) ov[v] = outv[v];
+      *(V*)(dst + (size_t)z * plane + sbase + e0) = ov;
+    }
+    __syncthreads();   // the plane buffer is rewritten next
+#pragma unroll
+    for (int q = 0; q < kZEpt; ++q) {
+      vp[q] = vc[q];
+      vc[q] = vn[q];
+      hc[q] = hn[q];
+      pc[q] = pn[q];
+    }
+  }
+}
+
 template <typename T, bool LZ>
 __global__ __launch_bounds__(kZThreads) void k_stencil3z(StencilGeom g0, const T* __restrict__ X, long xld,
                                                          T* __restrict__ Y, long yld, const T* __restrict__ Xprev,
                                                          LzState S, int j, const int* __restrict__ active) {
-  __shared__ T pl[kZSeg + 2 * kZMaxN2];       // halo row above, the segment, halo row below
+  __shared__ __align__(16) T pl[kZSeg + 2 * kZMaxN2];       // halo row above, the segment, halo row below
   __shared__ double red[kZThreads / kWave];
   __shared__ int flag[1];
   // XCD-contiguous order: the segments and runs that share halo rows and planes meet in one L2
@@ -200,111 +348,13 @@ __global__ __launch_bounds__(kZThreads) void k_stencil3z(StencilGeom g0, const T
   } else if (active && !active[r]) {
     return;
   }
-  const int n0 = g.n0, n1 = g.n1, n2 = g.n2;
-  const int seg = tile % g.tiles_x, zi = tile / g.tiles_x;
-  const int y0 = seg * g.band, rows = min(g.band, n1 - y0), E = rows * n2;
-  const int z0 = zi * g.zc, z1 = min(n0, z0 + g.zc);
-  const bool per = g.periodic != 0;
   const size_t roff = (LZ && S.col_off) ? (size_t)S.col_off[r] : (size_t)r * xld;
   const T* src = X + roff;
   T* dst = Y + ((LZ && S.col_off) ? roff : (size_t)r * yld);
   const T* prv = LZ ? Xprev + roff : nullptr;
-  const size_t plane = (size_t)n1 * n2, sbase = (size_t)y0 * n2;
-  const int yup = y0 > 0 ? y0 - 1 : (per ? n1 - 1 : -1);               // halo rows (-1: none)
-  const int ydn = y0 + rows < n1 ? y0 + rows : (per ? 0 : -1);
-  const T k2 = (T)g.kappa2, tau = (T)g.tau;
-  const bool prev_term = LZ && j > 1;
-
-  int lx[kZEpt], ly[kZEpt];
-#pragma unroll
-  for (int i = 0; i < kZEpt; ++i) {
-    const int e = (int)threadIdx.x + i * kZThreads;
-    ly[i] = e / n2;
-    lx[i] = e - ly[i] * n2;
-  }
-  auto ld = [&](size_t gi) -> T {
-    const T raw = src[gi];
-    return LZ ? (T)((double)raw * s_cur) : raw;
-  };
-  // the segment of plane z (zeros for a plane beyond a free boundary)
-  auto load_seg = [&](int z, T* v) {
-    const int zz = z < 0 ? (per ? z + n0 : -1) : (z >= n0 ? (per ? z - n0 : -1) : z);
-#pragma unroll
-    for (int i = 0; i < kZEpt; ++i) {
-      const int e = (int)threadIdx.x + i * kZThreads;
-      v[i] = (zz >= 0 && e < E) ? ld((size_t)zz * plane + sbase + e) : (T)0;
-    }
-  };
-  // the halo rows of plane z (0 <= z < n0): entries [0, n2) the row above, [n2, 2 n2) the row below
-  auto load_halo = [&](int z, T* h) {
-#pragma unroll
-    for (int i = 0; i < kZEpt; ++i) {
-      const int e = (int)threadIdx.x + i * kZThreads;
-      const int row = e < n2 ? yup : ydn;
-      h[i] = (e < 2 * n2 && row >= 0) ? ld((size_t)z * plane + (size_t)row * n2 + (e < n2 ? e : e - n2)) : (T)0;
-    }
-  };
-  auto load_prev = [&](int z, T* p) {
-#pragma unroll
-    for (int i = 0; i < kZEpt; ++i) {
-      const int e = (int)threadIdx.x + i * kZThreads;
-      p[i] = (prev_term && e < E) ? (T)((double)prv[(size_t)z * plane + sbase + e] * s_prev) : (T)0;
-    }
-  };
-
-  T vp[kZEpt], vc[kZEpt], vn[kZEpt], hc[kZEpt], hn[kZEpt], pc[kZEpt], pn[kZEpt];
-  load_seg(z0 - 1, vp);
-  load_seg(z0, vc);
-  load_halo(z0, hc);
-  load_prev(z0, pc);
   double acc = 0.0;
-  for (int z = z0; z < z1; ++z) {
-    load_seg(z + 1, vn);
-    if (z + 1 < z1) {
-      load_halo(z + 1, hn);
-      load_prev(z + 1, pn);
-    }
-#pragma unroll
-    for (int i = 0; i < kZEpt; ++i) {
-      const int e = (int)threadIdx.x + i * kZThreads;
-      if (e < E) pl[n2 + e] = vc[i];
-      if (e < 2 * n2) pl[e < n2 ? e : (rows + 1) * n2 + (e - n2)] = hc[i];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kZEpt; ++i) {
-      const int e = (int)threadIdx.x + i * kZThreads;
-      if (e >= E) continue;
-      const int x = lx[i], y = y0 + ly[i], c = n2 + e;
-      const T v = vc[i];
-      T a = k2 * v;
-      if (per || x - 1 >= 0) a += v - pl[x > 0 ? c - 1 : c + n2 - 1];
-      if (per || x + 1 < n2) a += v - pl[x + 1 < n2 ? c + 1 : c - n2 + 1];
-      if (per || y - 1 >= 0) a += v - pl[c - n2];
-      if (per || y + 1 < n1) a += v - pl[c + n2];
-      if (per || z - 1 >= 0) a += v - vp[i];
-      if (per || z + 1 < n0) a += v - vn[i];
-      const T out = tau * a;
-      const size_t gi = (size_t)z * plane + sbase + e;
-      if (LZ) {
-        double q = (double)out;
-        if (prev_term) q -= bprev * (double)pc[i];
-        const T qt = (T)q;
-        dst[gi] = qt;
-        acc += (double)v * (double)qt;
-      } else {
-        dst[gi] = out;
-      }
-    }
-    __syncthreads();   // the plane buffer is rewritten next
-#pragma unroll
-    for (int i = 0; i < kZEpt; ++i) {
-      vp[i] = vc[i];
-      vc[i] = vn[i];
-      hc[i] = hn[i];
-      pc[i] = pn[i];
-    }
-  }
+  if (g.n2 % 2 == 0) z3_run<T, LZ, 2>(g, tile, pl, src, dst, prv, j, s_cur, s_prev, bprev, acc);
+  else z3_run<T, LZ, 1>(g, tile, pl, src, dst, prv, j, s_cur, s_prev, bprev, acc);
   if (LZ) {
     const double bs = block_sum<kZThreads>(acc, red);
     if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + tile] = bs;
