@@ -96,8 +96,8 @@ __device__ void tri_view(const TriArgs& A, int r, int m, double* sa, double* sb,
 
 // Per node (one thread each): the backward pivots leave q_i = beta_i / d_{i+1} in the scratch rows, the
 // forward recurrence overwrites row i with w y_i (loads taken eight rows ahead, no cross-lane work in the
-// chain); then each wave sums whole rows over the block's nodes, and an LDS accumulator adds the
-// node blocks in order.
+// chain); then each thread sums whole rows over the block's nodes in node order, and the accumulator adds
+// the node blocks in order.
 template <bool LDS>
 __global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
   constexpr int LM = LDS ? kTriLdsM : 1;
@@ -122,12 +122,9 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
   const double h = 0.25;
   const double s_lo = 0.5 * log(lo) - kPad, s_hi = 0.5 * log(hi) + kPad;
   const int nq = (int)ceil((s_hi - s_lo) / h) + 1;
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  constexpr int NW = kTriThreads / kWave;
   constexpr int AH = 8;   // rows loaded ahead in the forward recurrence
-  // each row's sum is kept by the lane that adds to it (lane 0 of wave i mod NW), which also clears it
-  if (lane == 0)
-    for (int i = wv; i < m; i += NW) acc[i] = 0.0;
+  // each row's sum is kept by the thread that adds to it (thread i mod kTriThreads), which also clears it
+  for (int i = threadIdx.x; i < m; i += kTriThreads) acc[i] = 0.0;
   double* rs = A.scratch + (size_t)r * A.scr_m * kTriThreads;
   for (int base = 0; base < nq; base += kTriThreads) {
     const int l = base + threadIdx.x;
@@ -158,14 +155,18 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
     }
     rs[(size_t)(m - 1) * kTriThreads + threadIdx.x] = wgt * yi;
     __syncthreads();   // the block's rows are complete in memory
-    // row sums: wave wv takes rows wv, wv + NW, ...; a lane adds four nodes, then the wave butterfly
-    for (int i = wv; i < m; i += NW) {
-      const double* row = rs + (size_t)i * kTriThreads;
+    // row sums: thread t takes rows t, t + kTriThreads, ... and adds the row's nodes in order, 16 bytes per
+    // load with all of a row's loads independent (no cross-lane step in the chain)
+    for (int i = threadIdx.x; i < m; i += kTriThreads) {
+      const double2* row = (const double2*)(rs + (size_t)i * kTriThreads);
       double v = 0.0;
-#pragma unroll
-      for (int c = 0; c < kTriThreads / kWave; ++c) v += row[lane + c * kWave];
-      v = wave_sum(v);
-      if (lane == 0) acc[i] += v;
+#pragma unroll 16
+      for (int c = 0; c < kTriThreads / 2; ++c) {
+        const double2 pr = row[c];
+        v += pr.x;
+        v += pr.y;
+      }
+      acc[i] += v;
     }
     __syncthreads();   // the rows are rewritten by the next node block
   }
