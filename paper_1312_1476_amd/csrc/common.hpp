@@ -29,7 +29,7 @@ struct StencilGeom {
   int fepl;                // 2D one-pass Lanczos kernel: elements per lane (1 or 2)
   int ftiles_x;            // 2D one-pass Lanczos kernel: strips per row
   int band;                // 2D operator kernel: output rows per wave (0: kS2Band)
-  int ftiles_y;            // 2D one-pass Lanczos kernel: bands of kS2Waves x kS2Band rows
+  int ftiles_y;            // 2D one-pass Lanczos kernel: bands of kS2Waves x s2f_band(order) rows
   int tune;                // launch options that leave every result bit unchanged (kTune* bits)
   int zc;                  // 3D first-order lattices: planes per z-march block (0: box tiles)
 };

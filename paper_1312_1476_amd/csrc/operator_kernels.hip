@@ -371,6 +371,12 @@ __global__ __launch_bounds__(kZThreads) void k_stencil3z(StencilGeom g0, const T
 // (same terms in the same order as k_stencil).
 constexpr int kS2Waves = 4;     // waves per block (bands stacked vertically)
 constexpr int kS2Band = 32;     // output rows per wave
+// Output rows per wave of the one-pass kernel: each band re-reads 2 (ORDER + 1) halo rows, so the 13-point
+// step keeps 32-row bands while the 5-point step takes 24, which shortens each wave's row chain and
+// spreads large grids over more blocks (measured, FP64 5-point 2048^2 x 8: 32 / 24 / 16 rows -> 194.7 /
+// 184.2 / 182.0 us; 256^2 x 8 FP32: 20.2 / 16.2 / 13.3 us; the 256-field batch 43.6 / 42.1 / 45.2 ms;
+// 13-point 1024^2 x 64 FP32: 222.4 / 228.3 / 254.5 us, 64 rows 216.3 us but slower on small grids)
+__host__ __device__ constexpr int s2f_band(int order) { return order == 1 ? 24 : 32; }
 
 // rows requested ahead per wave: a row is 64 elements, so FP32 rows carry half the bytes of FP64 rows
 #ifndef GMRF_S2_AHEAD64
@@ -674,8 +680,9 @@ __device__ __forceinline__ void s2f_strip(const StencilGeom& g, int tx, int ty, 
   }
   const bool olane = lane * EPL >= HX && lane * EPL < RW - HX && xb >= 0 && xb < n2;
   const int lm = (lane * EPL - 1) & (RW - 1), lp = (lane * EPL + EPL) & (RW - 1);
-  const int y_lo = (ty * kS2Waves + w) * kS2Band;   // the one-pass kernel keeps full bands (ftiles_y)
-  const int y_hi = min(y_lo + kS2Band, n1);
+  constexpr int BAND = s2f_band(ORDER);
+  const int y_lo = (ty * kS2Waves + w) * BAND;   // the one-pass kernel keeps full bands (ftiles_y)
+  const int y_hi = min(y_lo + BAND, n1);
   const int count = y_hi > y_lo ? y_hi - y_lo + 2 * HV : 0;
   if (count == 0) return;
   const int ys = y_lo - HV;
@@ -1018,7 +1025,7 @@ void stencil_geom_tiles(StencilGeom& g, int dim, int order, int epl, int vbytes)
   }
   g.tiles_x = (g.n2 + TX - 1) / TX;
   g.ftiles_x = dim == 2 ? (g.n2 + s2f_out(order, g.fepl) - 1) / s2f_out(order, g.fepl) : 0;   // k_lanczos2d
-  g.ftiles_y = dim == 2 ? (g.n1 + kS2Waves * kS2Band - 1) / (kS2Waves * kS2Band) : 0;
+  g.ftiles_y = dim == 2 ? (g.n1 + kS2Waves * s2f_band(order) - 1) / (kS2Waves * s2f_band(order)) : 0;
   g.tiles_y = (g.n1 + TY - 1) / TY;
   g.tiles_z = (g.n0 + TZ - 1) / TZ;
 }
