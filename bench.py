@@ -293,6 +293,26 @@ def main():
                              "cache_resident": r["bytes"] < INFINITY_CACHE_BYTES}
         opb.close()
     result["spmv_13pt_1024x1024_32rhs"] = spmv_big
+    # the unpreconditioned one-pass Lanczos step (the C2/C3 and 2D serving kernel) on a large single field:
+    # 5-point, 2048 x 2048, 8 columns, 3 s n k bytes per step (805 MB FP64), tuned launch options
+    lz = {}
+    for storage in ("f64", "f32"):
+        opl = gm.Operator.lattice((2048, 2048), 1, 0.05, 1.0, "free", storage)
+        gm.autotune(opl, 8, reps=10, stream=stream)
+        r = gm.kernel_bench(opl, "lz2d", 8, reps=20, stream=stream)
+        lz[storage] = {"achieved_gbs": round(r["achieved_gbs"], 1), "frac_of_peak": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                       "avg_us": round(r["avg_us"], 2), "bytes_per_launch": r["bytes"]}
+        opl.close()
+    result["lanczos2d_5pt_2048x2048_8rhs"] = lz
+    # the 3D 7-point operator (z-marching kernel), 128^3 x 32: 1074 MB FP64 per launch
+    sp3 = {}
+    for storage in ("f64", "f32"):
+        op3 = gm.Operator.lattice((128, 128, 128), 1, 0.05, 1.0, "free", storage)
+        r = gm.kernel_bench(op3, "spmv", 32, reps=20, stream=stream)
+        sp3[storage] = {"achieved_gbs": round(r["achieved_gbs"], 1), "frac_of_peak": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                        "avg_us": round(r["avg_us"], 2), "bytes_per_launch": r["bytes"]}
+        op3.close()
+    result["spmv_7pt_128cubed_32rhs"] = sp3
 
     # ---- log-Gaussian Cox process proposal (Q + H, M = Q): Table 1 and throughput --------------------
     if not args.no_lgcp:
