@@ -337,7 +337,8 @@ gmrf_status gmrf_set_hbm_budget(size_t bytes);
 size_t gmrf_hbm_in_use(void);
 
 /* Reserve one device region of `bytes` (rounded up to 2 MiB) for the scratch pool: from then on
- * every call's scratch is carved from it (best fit over free ranges, merged when blocks return)
+ * every call's scratch is carved from it (blocks above 64 MiB best fit from the bottom, smaller
+ * ones from the top end; free ranges merged when blocks return)
  * and the pool makes no further device allocations or releases, whose cost on this part is
  * irregular (up to seconds for 100 GB, and a release waits for the whole device).  For servers
  * whose request sizes vary.  A call whose scratch finds no free range large enough returns

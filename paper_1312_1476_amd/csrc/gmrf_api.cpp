@@ -68,11 +68,13 @@ static gmrf_status check_device() {
 // freed blocks (a cached block at most 25% larger than asked is reused) or from hipMalloc.  Device
 // allocation and release are slow and irregular on this part when memory has been used before (seconds
 // for some 100 GB requests, and hipFree waits for the whole device), so a server with a varied mix of
-// request sizes reserves one region up front (gmrf_pool_reserve): blocks are then carved from it, best
-// fit in an address-ordered list of free ranges that merges neighbours when a block comes back, and the
-// pool calls into the device allocator no more.
+// request sizes reserves one region up front (gmrf_pool_reserve): blocks are then carved from it (large
+// ones best fit from the bottom, small ones from the top) in an address-ordered list of free ranges that
+// merges neighbours when a block comes back, and the pool calls into the device allocator no more.
 namespace {
 using Clock = std::chrono::steady_clock;
+
+constexpr size_t kPoolSmallBlock = (size_t)64 << 20;   // region blocks up to this size come from the top
 
 struct Pool {
   std::mutex mu;
@@ -117,16 +119,29 @@ struct Pool {
     if (budget && in_use + bytes > budget)
       return fail(GMRF_ENOMEM, "HBM budget %zu B exceeded (in use %zu B, request %zu B)", budget, in_use, bytes);
     if (region) {
-      auto best = holes.end();
-      for (auto it = holes.begin(); it != holes.end(); ++it)
-        if (it->second >= bytes && (best == holes.end() || it->second < best->second)) best = it;
-      if (best == holes.end())
+      // small blocks (scalars, partial sums, one-vector buffers) from the top end of the highest range that
+      // holds them, large ones (Krylov bases) best fit from the bottom: the small blocks of running calls
+      // then do not split the ranges that the next large basis needs
+      const bool small = bytes <= kPoolSmallBlock;
+      auto pick = holes.end();
+      for (auto it = holes.begin(); it != holes.end(); ++it) {
+        if (it->second < bytes) continue;
+        if (small) pick = it;                                             // the last fitting range: highest
+        else if (pick == holes.end() || it->second < pick->second) pick = it;
+      }
+      if (pick == holes.end())
         return fail(GMRF_ENOMEM, "reserved region of %zu B has no free range of %zu B (largest %zu B)", region_size,
                     bytes, largest_hole());
-      const size_t off = best->first, len = best->second;
-      holes.erase(best);
-      if (len > bytes) holes.emplace(off + bytes, len - bytes);
-      *out = region + off;
+      const size_t off = pick->first, len = pick->second;
+      holes.erase(pick);
+      size_t at = off;
+      if (small) {
+        at = off + len - bytes;
+        if (len > bytes) holes.emplace(off, len - bytes);
+      } else if (len > bytes) {
+        holes.emplace(off + bytes, len - bytes);
+      }
+      *out = region + at;
       *actual = bytes;
       in_use += bytes;
       return GMRF_OK;
