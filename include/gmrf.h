@@ -302,10 +302,13 @@ gmrf_status gmrf_kernel_bench(const gmrf_op* Q, int which, int64_t k, int32_t re
  * process-wide table keyed by (kernel, order, storage, ceil(log2) of each side, ceil(log2 k)).
  * The options are the tile order (linear, or XCD-contiguous so that each of the 8 XCDs, each with
  * its own L2, works through one range of neighbouring tiles) and the store policy of the output
- * (ordinary or non-temporal).  No option changes what is computed or the order of any sum, so
- * results are bitwise the same under every table state.  chosen (host, may be NULL): [2] chosen
- * option bits (1 = XCD-contiguous, 2 = non-temporal stores; -1 = kernel not used by Q).  Other
- * operators are left untuned (GMRF_OK, chosen = -1).                                           */
+ * (ordinary or non-temporal), and for the SpMM alone its tile shape: rows per wave and columns
+ * per lane.  No option changes what is computed or the order of any sum (the SpMM has no sums
+ * across points, so its tiling is free; the Lanczos step's partial sums follow its tiles, so its
+ * shape stays the lattice's rule), so results are bitwise the same under every table state.
+ * chosen (host, may be NULL): [2] chosen option bits (1 = XCD-contiguous, 2 = non-temporal
+ * stores; bits 2-3 rows per wave 0 = rule / 8 / 16 / 32, bits 4-5 columns per lane 0 = rule /
+ * 1 / 2 / 4; -1 = kernel not used by Q).  Other operators are left untuned (GMRF_OK, chosen = -1). */
 gmrf_status gmrf_autotune(const gmrf_op* Q, int64_t k, int32_t reps, int32_t* chosen, void* stream);
 
 /* The tuning table as `count` entries of 7 int32 (kernel 0 = SpMM, 1 = one-pass step; order;

@@ -286,7 +286,17 @@ TUNE_OPTIONS = {1: "xcd_order", 2: "nt_store"}
 
 
 def _options(bits):
-    return None if bits < 0 else [name for b, name in TUNE_OPTIONS.items() if bits & b]
+    """Names of the launch options in tuning bits: tile order and store policy, and for the operator kernel its
+    tile shape (rows per wave "band8/16/32", columns per lane "lanes1/2/4"; absent: the lattice's rule)."""
+    if bits < 0:
+        return None
+    out = [name for b, name in TUNE_OPTIONS.items() if bits & b]
+    band, epl = (bits >> 2) & 3, (bits >> 4) & 3
+    if band:
+        out.append(f"band{(0, 8, 16, 32)[band]}")
+    if epl:
+        out.append(f"lanes{(0, 1, 2, 4)[epl]}")
+    return out
 
 
 def autotune(op, k, reps=20, stream=None):

@@ -39,6 +39,11 @@ struct StencilGeom {
 enum : int {
   kTuneXcd = 1,   // XCD-contiguous tile order: workgroup i runs on XCD i mod 8, each XCD takes one range
   kTuneNtStore = 2,   // non-temporal stores of the kernel's output vector (selects a kernel instantiation)
+  // the operator kernel alone (Y = Q X, no partial sums): its tile shape, which changes no output bit either,
+  // since every output point's terms and their order are the same in every tiling
+  kTuneBandShift = 2,     // 2 bits: rows per wave 0 = the lattice's rule, 1 = 8, 2 = 16, 3 = 32
+  kTuneEplShift = 4,      // 2 bits: columns per lane 0 = the lattice's rule, 1 = 1, 2 = 2, 3 = 4 (FP32)
+  kTuneGeomMask = 0x3C,
 };
 
 // Per-call Lanczos state, all device memory.  Index conventions (1-based j as in

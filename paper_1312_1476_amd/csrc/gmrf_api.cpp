@@ -740,7 +740,8 @@ extern "C" gmrf_status gmrf_op_bytes_two_pass(const gmrf_op* Q, int64_t k, int32
 }
 
 // ---- autotuner table: launch options that leave every result bit unchanged --------------------------------
-// The table maps (kernel, order, storage, shape class, columns class) to kTune* bits (common.hpp); shape class =
+// The table maps (kernel, order, storage, shape class, columns class) to kTune* bits (common.hpp: tile order and
+// store policy for both kernels, tile shape for the operator kernel alone); shape class =
 // ceil(log2) of each lattice side, columns class = ceil(log2 k).  Entries come from gmrf_autotune, which times every
 // candidate with HIP events on scratch data of the call's shape and keeps the fastest, or from gmrf_tune_import.
 // A key without an entry launches with no options (linear tile order, ordinary stores).  Since no option changes a
@@ -775,10 +776,24 @@ int tune_lookup(int kernel, const gmrf_op* Q, int64_t k) {
   auto it = tune_table().find(tune_key(kernel, Q, k));
   return it == tune_table().end() ? 0 : it->second;
 }
-// the operator's geometry with the launch options of `kernel` for k columns (tune >= 0: those options instead)
+// tile shape coded in kTuneGeomMask bits: (rows per wave, columns per lane), 0 where the code asks for the rule
+// or does not suit the operator (four columns per lane: FP32 rows of a multiple of 4; two: even rows)
+void geom_code(const gmrf_op* Q, int bits, int& band, int& epl) {
+  static const int bands[4] = {0, 8, 16, 32}, epls[4] = {0, 1, 2, 4};
+  band = bands[(bits >> kTuneBandShift) & 3];
+  epl = epls[(bits >> kTuneEplShift) & 3];
+  if ((epl == 4 && (Q->storage != GMRF_F32 || Q->shape[2] % 4 != 0)) || (epl == 2 && Q->shape[2] % 2 != 0)) epl = 0;
+}
+// the operator's geometry with the launch options of `kernel` for k columns (tune >= 0: those options instead);
+// tile-shape bits apply to the operator kernel alone
 StencilGeom tuned_geom(int kernel, const gmrf_op* Q, int64_t k, int tune = -1) {
   StencilGeom g = Q->geom;
   g.tune = tune >= 0 ? tune : tune_lookup(kernel, Q, k);
+  if (kernel == kTuneKernelSpmm && (g.tune & kTuneGeomMask) && tunable(Q)) {
+    int band, epl;
+    geom_code(Q, g.tune, band, epl);
+    stencil_geom_shape(g, Q->order, band ? band : g.band, epl ? epl : g.epl);
+  }
   return g;
 }
 }  // namespace
@@ -1903,14 +1918,31 @@ static gmrf_status autotune_impl(const gmrf_op* Q, int k, int reps, int32_t* cho
       if (chosen) chosen[t] = -1;
       continue;
     }
+    // candidates: the four option sets, and for the operator kernel each with every tile shape that suits the
+    // operator (rows per wave 8 / 16 / 32 or the rule, columns per lane 1 / 2 / 4 or the rule)
+    std::vector<int> cand;
+    for (int c = 0; c < 4; ++c) {
+      if (kernels[t] != kTuneKernelSpmm) {
+        cand.push_back(kTuneCandidates[c]);
+        continue;
+      }
+      for (int bc = 0; bc < 4; ++bc)
+        for (int ec = 0; ec < 4; ++ec) {
+          const int bits = kTuneCandidates[c] | (bc << kTuneBandShift) | (ec << kTuneEplShift);
+          int band, epl;
+          geom_code(Q, bits, band, epl);
+          if (ec != 0 && epl == 0) continue;   // a lane width the operator cannot take
+          cand.push_back(bits);
+        }
+    }
     int best = 0;
     double best_us = 0.0;
-    for (int c = 0; c < 4; ++c) {
+    for (size_t c = 0; c < cand.size(); ++c) {
       double us = 0.0, b = 0.0;
-      gmrf_status s = kernel_bench_impl<T>(Q, which[t], k, reps, &us, &b, st, kTuneCandidates[c]);
+      gmrf_status s = kernel_bench_impl<T>(Q, which[t], k, reps, &us, &b, st, cand[c]);
       if (s != GMRF_OK) return s;
       if (c == 0 || us < best_us) {
-        best = kTuneCandidates[c];
+        best = cand[c];
         best_us = us;
       }
     }
@@ -1953,9 +1985,9 @@ extern "C" gmrf_status gmrf_tune_import(const int32_t* entries, int32_t count) {
   if (count < 0 || (count > 0 && !entries)) return fail(GMRF_EINVAL, "bad arguments");
   for (int i = 0; i < count; ++i) {
     const int32_t* e = entries + 7 * i;
+    const int allowed = kTuneXcd | kTuneNtStore | (e[0] == kTuneKernelSpmm ? kTuneGeomMask : 0);
     if (e[0] < 0 || e[0] >= kTuneKernels || (e[1] != 1 && e[1] != 2) || (e[2] != GMRF_F64 && e[2] != GMRF_F32) ||
-        e[3] < 0 || e[3] > 31 || e[4] < 0 || e[4] > 31 || e[5] < 0 || e[5] > 31 ||
-        (e[6] & ~(kTuneXcd | kTuneNtStore)) != 0)
+        e[3] < 0 || e[3] > 31 || e[4] < 0 || e[4] > 31 || e[5] < 0 || e[5] > 31 || (e[6] & ~allowed) != 0)
       return fail(GMRF_EINVAL, "tuning entry %d is not valid", i);
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);

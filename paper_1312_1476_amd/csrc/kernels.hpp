@@ -47,6 +47,7 @@ void launch_lanczos2d(const StencilGeom& g, int order, int mode, int grid_x, con
                       const T* Xprev, const LzState& S, int j, int k, double* out_a, double* out_b, double* out_c,
                       hipStream_t st);
 int stencil_blocks(const StencilGeom& g);
+void stencil_geom_shape(StencilGeom& g, int order, int band, int epl);
 template <typename T> void launch_stencil(const StencilGeom& g, int order, int dim, bool lz, const T* X, long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k, hipStream_t st);
 template <typename T> void launch_stencil_batch(int order, int dim, int max_tiles, const T* X, T* Y, const T* Xprev, const LzState& S, int j, hipStream_t st, bool zmarch);
 int csr_blocks(long n);

@@ -1030,6 +1030,16 @@ void stencil_geom_tiles(StencilGeom& g, int dim, int order, int epl, int vbytes)
   g.tiles_z = (g.n0 + TZ - 1) / TZ;
 }
 
+// 2D operator kernel with rows per wave `band` and columns per lane `epl` instead of the lattice's rule (the
+// caller checks that epl suits the storage type and the row length)
+void stencil_geom_shape(StencilGeom& g, int order, int band, int epl) {
+  g.band = band;
+  g.epl = epl;
+  g.tiles_x = (g.n2 + s2_out(order, epl) - 1) / s2_out(order, epl);
+  g.tiles_y = (g.n1 + kS2Waves * band - 1) / (kS2Waves * band);
+  g.tiles_z = 1;
+}
+
 int stencil_blocks(const StencilGeom& g) { return g.tiles_x * g.tiles_y * g.tiles_z; }
 
 template <typename T, int ORDER, int DIM, bool LZ>

@@ -1,7 +1,8 @@
 """Autotuner (gmrf_autotune and the tuning table), through the C ABI.
 
-The tuner chooses launch options that change no result bit: the tile order (linear or XCD-contiguous)
-and the store policy (ordinary or non-temporal).  So every option set must give bitwise-identical
+The tuner chooses launch options that change no result bit: the tile order (linear or XCD-contiguous),
+the store policy (ordinary or non-temporal) and, for the SpMM alone, its tile shape (rows per wave,
+columns per lane).  So every option set must give bitwise-identical
 outputs -- the SpMM, the one-pass Lanczos sampler (coefficients and samples), and a field sampled
 alone versus inside an uneven batch -- and the table must round-trip through its JSON form.
 """
@@ -16,6 +17,7 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 ALL_OPTIONS = (0, 1, 2, 3)
+SPMM_OPTIONS = tuple(range(64))       # with every tile shape code (rows per wave, columns per lane)
 
 
 @pytest.fixture(scope="module")
@@ -63,7 +65,7 @@ def test_spmm_bitwise_under_every_option(gm, shape, order, storage):
     dt = torch.float64 if storage == "f64" else torch.float32
     X = _t(np.random.default_rng(11).standard_normal((k, shape[0] * shape[1])), dt)
     ref = op.apply(X).clone()
-    for bits in ALL_OPTIONS:
+    for bits in SPMM_OPTIONS:
         _set(gm, "spmv", op, k, bits)
         assert torch.equal(op.apply(X), ref), bits
     gm.clear_tune()
@@ -118,8 +120,10 @@ def test_tune_import_rejects_invalid_entries(gm):
     import ctypes as C
     from paper_1312_1476_amd import _abi
     gm.clear_tune()
-    bad = (C.c_int32 * 7)(0, 2, 0, 9, 9, 5, 8)        # option bit 8 does not exist
+    bad = (C.c_int32 * 7)(0, 2, 0, 9, 9, 5, 64)       # option bit 64 does not exist
     assert _abi.lib().gmrf_tune_import(bad, 1) == _abi.GMRF_EINVAL
+    bad1 = (C.c_int32 * 7)(1, 2, 0, 9, 9, 5, 4)       # tile shapes are for the SpMM alone
+    assert _abi.lib().gmrf_tune_import(bad1, 1) == _abi.GMRF_EINVAL
     bad2 = (C.c_int32 * 7)(5, 2, 0, 9, 9, 5, 1)       # no kernel 5
     assert _abi.lib().gmrf_tune_import(bad2, 1) == _abi.GMRF_EINVAL
     assert gm.tune_table() == []
