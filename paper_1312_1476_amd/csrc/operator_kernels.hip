@@ -376,7 +376,13 @@ constexpr int kS2Band = 32;     // output rows per wave
 // spreads large grids over more blocks (measured, FP64 5-point 2048^2 x 8: 32 / 24 / 16 rows -> 194.7 /
 // 184.2 / 182.0 us; 256^2 x 8 FP32: 20.2 / 16.2 / 13.3 us; the 256-field batch 43.6 / 42.1 / 45.2 ms;
 // 13-point 1024^2 x 64 FP32: 222.4 / 228.3 / 254.5 us, 64 rows 216.3 us but slower on small grids)
-__host__ __device__ constexpr int s2f_band(int order) { return order == 1 ? 24 : 32; }
+#ifndef GMRF_S2F_BAND1
+#define GMRF_S2F_BAND1 24
+#endif
+#ifndef GMRF_S2F_BAND2
+#define GMRF_S2F_BAND2 32
+#endif
+__host__ __device__ constexpr int s2f_band(int order) { return order == 1 ? GMRF_S2F_BAND1 : GMRF_S2F_BAND2; }
 
 // rows requested ahead per wave: a row is 64 elements, so FP32 rows carry half the bytes of FP64 rows
 #ifndef GMRF_S2_AHEAD64
