@@ -63,6 +63,38 @@ def test_batch_matches_single_and_oracle(gm, storage, tol_par):
         col += k
 
 
+@pytest.mark.parametrize("storage,tol_par", [("f64", 1e-8), ("f32", 1e-5)])
+def test_batch_of_3d_fields(gm, storage, tol_par):
+    """3D first-order fields in one batch: small ones (box tiles) and, separately, fields of 2^20 points
+    and more (z-marching kernel, each block taking its lane width from its own field: odd and even row
+    lengths mixed).  Each field bitwise equal to the field alone and within tol of the oracle at its m."""
+    groups = [[((9, 10, 11), 0.2, 2), ((12, 8, 16), 0.05, 1), ((7, 7, 7), 0.5, 3)],
+              [((34, 181, 175), 0.3, 2), ((17, 256, 256), 0.1, 1), ((64, 128, 130), 0.5, 1)]]
+    for gi, specs in enumerate(groups):
+        ops = [gm.Operator.lattice(sh, 1, k2, 1.0, "free", storage) for sh, k2, _ in specs]
+        Zs = [workloads.gaussian_block(int(np.prod(sh)), k, 95, 10 * gi + f) for f, (sh, k2, k) in enumerate(specs)]
+        Xs, info = gm.sample_batch(ops, [_t(Z.T) for Z in Zs], tol=1e-7, m_max=300)
+        col = 0
+        for f, ((sh, k2, k), op, Z) in enumerate(zip(specs, ops, Zs)):
+            Xb = Xs[f].cpu().numpy()
+            Xa, ia = op.sample(_t(Z.T), tol=1e-7, m_max=300)
+            assert np.array_equal(Xb, Xa.cpu().numpy()), (gi, f)
+            Q = lattice.lattice_precision(sh, 1, k2, 1.0, "free")
+            for r in range(k):
+                m = info[col + r]["m_used"]
+                assert info[col + r]["status"] == "OK" and m == ia[r]["m_used"]
+                ref = lanczos.sample_csr(Q, Z[:, r], m, tol=0.0)
+                assert _rel(Xb[r], ref.x) <= tol_par, (gi, f, r, _rel(Xb[r], ref.x))
+            col += k
+        for op in ops:
+            op.close()
+    # a batch mixing the two kernels is refused
+    a = gm.Operator.lattice((9, 10, 11), 1, 0.2, 1.0, "free", storage)
+    b = gm.Operator.lattice((17, 256, 256), 1, 0.1, 1.0, "free", storage)
+    with pytest.raises(gm.GmrfError):
+        gm.sample_batch([a, b], [_t(np.ones((1, a.n))), _t(np.ones((1, b.n)))])
+
+
 def test_batch_rejects_incompatible(gm):
     a = gm.Operator.lattice((16, 16), 1, 0.1)
     b = gm.Operator.lattice((16, 16), 2, 0.1)
