@@ -383,6 +383,9 @@ constexpr int kS2Band = 32;     // output rows per wave
 #define GMRF_S2F_BAND2 32
 #endif
 __host__ __device__ constexpr int s2f_band(int order) { return order == 1 ? GMRF_S2F_BAND1 : GMRF_S2F_BAND2; }
+#ifndef GMRF_L2D_FEPL4
+#define GMRF_L2D_FEPL4 1       // the one-pass kernel may take four FP32 columns per lane (else two)
+#endif
 
 // rows requested ahead per wave: a row is 64 elements, so FP32 rows carry half the bytes of FP64 rows
 #ifndef GMRF_S2_AHEAD64
@@ -1008,7 +1011,7 @@ void stencil_geom_tiles(StencilGeom& g, int dim, int order, int epl, int vbytes)
     else g.epl = (vbytes == 4 && g.n2 % 4 == 0 && cover(4) <= 1.15 * cover(2)) ? 4 : 2;
     if (epl > 0) g.fepl = epl;
     else if (g.n2 % 2 != 0) g.fepl = 1;
-    else g.fepl = (vbytes == 4 && g.n2 % 4 == 0 && fcover(4) <= 1.15 * fcover(2)) ? 4 : 2;
+    else g.fepl = (GMRF_L2D_FEPL4 && vbytes == 4 && g.n2 % 4 == 0 && fcover(4) <= 1.15 * fcover(2)) ? 4 : 2;
   }
   if (dim == 1) { TZ = TileShape<1>::TZ; TY = TileShape<1>::TY; TX = TileShape<1>::TX; }
   else if (dim == 2) { TZ = 1; TY = kS2Waves * g.band; TX = s2_out(order, g.epl); }   // k_stencil2d
