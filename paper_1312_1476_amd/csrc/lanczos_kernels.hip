@@ -452,6 +452,68 @@ __global__ __launch_bounds__(kEwThreads) void k_combine(const T* __restrict__ V,
   double acc[kEwPerThread];
   EW_LOOP(q) acc[q] = 0.0;
   const bool bad = (st == kENOTSPD || st == kEINVAL);
+  if constexpr (sizeof(T) == 8) {
+    // FP64 columns at even offsets: each thread takes pairs of elements with one 16-byte non-temporal load per
+    // basis vector (the basis is read once); every element's sum is the same as below, in t order
+    if (!bad && ((voff | vs) & 1) == 0 && (len & 1) == 0 && ((uintptr_t)V & 15) == 0) {
+      typedef double d2 __attribute__((ext_vector_type(2)));
+      constexpr int NP = kEwPerThread / 2;
+      const long pbase = (long)blockIdx.x * kEwChunk + 2 * (long)threadIdx.x;
+      double pacc[NP][2];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) pacc[p][0] = pacc[p][1] = 0.0;
+      for (int t0 = 0; t0 < m; t0 += 1024) {
+        const int tn = min(1024, m - t0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < tn; t += kEwThreads)
+          cl[t] = beta0 * y[(size_t)r * ldy + t0 + t] / S.beta[lz_ib(S, r, t0 + t)];
+        __syncthreads();
+        int t = 0;
+        for (; t + 3 < tn; t += 4) {
+          const double* v0 = (const double*)V + (size_t)(t0 + t) * vs + voff;
+          d2 x[4][NP];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+              const long e = pbase + (long)p * 2 * kEwThreads;
+              x[u][p] = (e < len) ? __builtin_nontemporal_load((const d2*)(v0 + (size_t)u * vs + e)) : d2{0.0, 0.0};
+            }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double ct = cl[t + u];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+              pacc[p][0] += ct * x[u][p].x;
+              pacc[p][1] += ct * x[u][p].y;
+            }
+          }
+        }
+        for (; t < tn; ++t) {
+          const double* vt = (const double*)V + (size_t)(t0 + t) * vs + voff;
+          const double ct = cl[t];
+#pragma unroll
+          for (int p = 0; p < NP; ++p) {
+            const long e = pbase + (long)p * 2 * kEwThreads;
+            if (e < len) {
+              const d2 xv = *(const d2*)(vt + e);
+              pacc[p][0] += ct * xv.x;
+              pacc[p][1] += ct * xv.y;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const long e = pbase + (long)p * 2 * kEwThreads;
+        if (e < len) {
+          out[ooff + e] = (OutT)pacc[p][0];
+          out[ooff + e + 1] = (OutT)pacc[p][1];
+        }
+      }
+      return;
+    }
+  }
   if (!bad) {
     for (int t0 = 0; t0 < m; t0 += 1024) {
       const int tn = min(1024, m - t0);
