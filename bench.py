@@ -314,6 +314,15 @@ def main():
                         "avg_us": round(r["avg_us"], 2), "bytes_per_launch": r["bytes"]}
         op3.close()
     result["spmv_7pt_128cubed_32rhs"] = sp3
+    # the general CSR operator (gmrf_op_create_csr) holding the same 13-point Q on 512 x 512, 32 columns:
+    # each row's entries are read once for 8 right-hand sides
+    Pc = lattice_csr(512, 2, sp.kappa2)
+    opc = gm.Operator.csr(Pc.shape[0], Pc.indptr, Pc.indices, Pc.data)
+    r = gm.kernel_bench(opc, "spmv", 32, reps=20, stream=stream)
+    result["spmv_csr_13pt_512x512_32rhs"] = {"avg_us": round(r["avg_us"], 2), "nnz": int(Pc.nnz),
+                                             "bytes_per_launch": r["bytes"],   # X, Y and the matrix once
+                                             "achieved_gbs": round(r["achieved_gbs"], 1)}
+    opc.close()
 
     # ---- log-Gaussian Cox process proposal (Q + H, M = Q): Table 1 and throughput --------------------
     if not args.no_lgcp:
@@ -520,6 +529,16 @@ def logdet_leg(gm, torch):
 
 
 ICHOL_DROPTOLS = (None, -1.0, 1e-2, 1e-3, 1e-4, 1e-5)   # None: no preconditioner; -1: IC(0)
+
+
+def lattice_csr(N, order, kappa2):
+    """Q = (kappa2 I + L)^order as CSR, L the 5-point graph Laplacian of the free N x N grid."""
+    import scipy.sparse as sps
+    T = sps.diags([-np.ones(N - 1), np.r_[1.0, 2 * np.ones(N - 2), 1.0], -np.ones(N - 1)], [-1, 0, 1])
+    K = kappa2 * sps.identity(N * N) + sps.kron(T, sps.identity(N)) + sps.kron(sps.identity(N), T)
+    P = sps.csr_matrix(K @ K if order == 2 else K)
+    P.sort_indices()
+    return P
 
 
 def lgcp_posterior_csr(N, spec, d):

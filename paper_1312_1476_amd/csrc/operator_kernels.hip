@@ -929,55 +929,87 @@ sums:
 }
 
 // ---- CSR: one thread per row ----------------------------------------------------------------
-template <typename T, bool LZ>
+// One thread per row and KB columns per block: the row's entries (indices and values) are loaded once for
+// its KB right-hand sides.  Every column's sums are formed as with one column per block (entries in row
+// order; the block's partial sum over the same 256 rows), so the result bits do not depend on KB.
+template <typename T, bool LZ, int KB>
 __global__ __launch_bounds__(256) void k_csr(long n, const int64_t* __restrict__ rp,
                                              const int32_t* __restrict__ ci, const T* __restrict__ va,
                                              const T* __restrict__ X, long xld, T* __restrict__ Y,
-                                             long yld, const T* __restrict__ Xprev, LzState S, int j) {
+                                             long yld, const T* __restrict__ Xprev, LzState S, int j, int k) {
   __shared__ double red[256 / kWave];
   __shared__ int flag[1];
-  const int r = blockIdx.y;
-  double s_cur = 1.0, s_prev = 0.0, bprev = 0.0;
-  if (LZ) {
-    if (!lz_open<256>(S, r, j, blockIdx.x == 0, red, flag, s_cur, s_prev, bprev)) return;
+  const int r0 = blockIdx.y * KB;
+  double s_cur[KB], s_prev[KB], bprev[KB];
+  bool act[KB];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < KB; ++c) {
+    act[c] = r0 + c < k;    // uniform over the block
+    s_cur[c] = 1.0;
+    s_prev[c] = 0.0;
+    bprev[c] = 0.0;
+    if (LZ && act[c]) act[c] = lz_open<256>(S, r0 + c, j, blockIdx.x == 0, red, flag, s_cur[c], s_prev[c], bprev[c]);
+    any = any || act[c];
   }
+  if (!any) return;
   const long row = (long)blockIdx.x * 256 + threadIdx.x;
-  const T* src = X + (size_t)r * xld;
-  double acc = 0.0;
+  T s[KB];
+#pragma unroll
+  for (int c = 0; c < KB; ++c) s[c] = (T)0;
+  auto term = [&](int c, T a, int32_t col) {
+    const T raw = X[(size_t)(r0 + c) * xld + col];
+    s[c] += a * (LZ ? (T)((double)raw * s_cur[c]) : raw);
+  };
   if (row < n) {
-    T s = (T)0;
     const int64_t e1 = rp[row + 1];
     int64_t e = rp[row];
     for (; e + 3 < e1; e += 4) {   // four entries' loads issued before the sums (same order)
-      int32_t c[4];
-      T a[4], raw[4];
+      int32_t cc[4];
+      T a[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        c[u] = ci[e + u];
+        cc[u] = ci[e + u];
         a[u] = va[e + u];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) raw[u] = src[c[u]];
+      for (int c = 0; c < KB; ++c) {
+        if (!act[c]) continue;
+        T raw[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) s += a[u] * (LZ ? (T)((double)raw[u] * s_cur) : raw[u]);
+        for (int u = 0; u < 4; ++u) raw[u] = X[(size_t)(r0 + c) * xld + cc[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[c] += a[u] * (LZ ? (T)((double)raw[u] * s_cur[c]) : raw[u]);
+      }
     }
     for (; e < e1; ++e) {
-      const T raw1 = src[ci[e]];
-      s += va[e] * (LZ ? (T)((double)raw1 * s_cur) : raw1);
-    }
-    if (LZ) {
-      double q = (double)s;
-      if (j > 1) q -= bprev * (double)(T)((double)Xprev[(size_t)r * xld + row] * s_prev);
-      const T qt = (T)q;
-      Y[(size_t)r * yld + row] = qt;
-      acc = (double)(T)((double)src[row] * s_cur) * (double)qt;
-    } else {
-      Y[(size_t)r * yld + row] = s;
+      const int32_t c1 = ci[e];
+      const T a1 = va[e];
+#pragma unroll
+      for (int c = 0; c < KB; ++c)
+        if (act[c]) term(c, a1, c1);
     }
   }
-  if (LZ) {
-    const double bs = block_sum<256>(acc, red);
-    if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + blockIdx.x] = bs;
+#pragma unroll
+  for (int c = 0; c < KB; ++c) {
+    if (!act[c]) continue;
+    const int r = r0 + c;
+    double acc = 0.0;
+    if (row < n) {
+      if (LZ) {
+        double q = (double)s[c];
+        if (j > 1) q -= bprev[c] * (double)(T)((double)Xprev[(size_t)r * xld + row] * s_prev[c]);
+        const T qt = (T)q;
+        Y[(size_t)r * yld + row] = qt;
+        acc = (double)(T)((double)X[(size_t)r * xld + row] * s_cur[c]) * (double)qt;
+      } else {
+        Y[(size_t)r * yld + row] = s[c];
+      }
+    }
+    if (LZ) {
+      const double bs = block_sum<256>(acc, red);
+      if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + blockIdx.x] = bs;
+    }
   }
 }
 
@@ -1144,16 +1176,28 @@ template void launch_lanczos2d<float>(const StencilGeom&, int, int, int, const f
 
 int csr_blocks(long n) { return (int)((n + 255) / 256); }
 
+template <typename T, int KB>
+static void launch_csr_kb(long n, const int64_t* rp, const int32_t* ci, const T* va, bool lz, const T* X,
+                          long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k,
+                          hipStream_t st) {
+  const dim3 grid(csr_blocks(n), (k + KB - 1) / KB);
+  if (lz)
+    hipLaunchKernelGGL((k_csr<T, true, KB>), grid, dim3(256), 0, st, n, rp, ci, va, X, xld, Y, yld, Xprev, S, j, k);
+  else
+    hipLaunchKernelGGL((k_csr<T, false, KB>), grid, dim3(256), 0, st, n, rp, ci, va, X, xld, Y, yld, Xprev, S, j, k);
+}
+
+// Columns per block: 8 from 8 right-hand sides, 4 from 4, else 1 (no result bit depends on it).
+#ifndef GMRF_CSR_MAX_KB
+#define GMRF_CSR_MAX_KB 8
+#endif
 template <typename T>
 void launch_csr(long n, const int64_t* rp, const int32_t* ci, const T* va, bool lz, const T* X,
                 long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k,
                 hipStream_t st) {
-  if (lz)
-    hipLaunchKernelGGL((k_csr<T, true>), dim3(csr_blocks(n), k), dim3(256), 0, st, n, rp, ci, va, X, xld,
-                       Y, yld, Xprev, S, j);
-  else
-    hipLaunchKernelGGL((k_csr<T, false>), dim3(csr_blocks(n), k), dim3(256), 0, st, n, rp, ci, va, X,
-                       xld, Y, yld, Xprev, S, j);
+  if (GMRF_CSR_MAX_KB >= 8 && k >= 8) launch_csr_kb<T, 8>(n, rp, ci, va, lz, X, xld, Y, yld, Xprev, S, j, k, st);
+  else if (GMRF_CSR_MAX_KB >= 4 && k >= 4) launch_csr_kb<T, 4>(n, rp, ci, va, lz, X, xld, Y, yld, Xprev, S, j, k, st);
+  else launch_csr_kb<T, 1>(n, rp, ci, va, lz, X, xld, Y, yld, Xprev, S, j, k, st);
 }
 
 template void launch_stencil<double>(const StencilGeom&, int, int, bool, const double*, long, double*,
