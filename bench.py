@@ -103,7 +103,12 @@ def main():
         # another: spmv = the 13-point operator alone), then a plain device copy of known size whose
         # FETCH_SIZE / WRITE_SIZE readings scale the counters to bytes
         name = args.kernel or DOMINANT_KERNEL
-        if name != "spmv":
+        if name in ("lgcp_rows", "lgcp_cols"):   # the LGCP passes at 512 x 512 (periodic prior, diagonal H)
+            spec = workloads.lgcp_prior(args.side)
+            op = gm.Operator.lattice(spec.shape, 2, spec.kappa2, spec.tau, "periodic", args.storage)
+            op.set_diagonal(workloads.lgcp_diagonal(args.side))
+            op.set_circulant_precond()
+        elif name != "spmv":
             op = make(args.storage)
         elif args.dim == 3:      # the 3D 7-point operator (first order) of the serving pool's 3D lattices
             op = gm.Operator.lattice((args.side,) * 3, 1, 0.05, 1.0, "free", args.storage)
