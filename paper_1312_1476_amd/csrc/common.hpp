@@ -109,6 +109,60 @@ __device__ __forceinline__ int wave_min_int(int v) {
   return v;
 }
 
+// gfx950 cross-lane exchanges of doubles.  swap32(a, b): v_permlane32_swap on both halves, after which a lane's
+// a + b is the sum over its pair of lanes 32 apart of a (lanes 0..31) or of b (lanes 32..63); swap16 likewise
+// per 16-lane row with v_permlane16_swap (even rows: a, odd rows: b).  dpp<CTRL>: a DPP lane permutation.
+__device__ __forceinline__ void swap32(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ void swap16(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141, kDppQuadXor2 = 0x4E, kDppQuadXor1 = 0xB1;
+
+
+// Sum over the wave of 16 values per lane with no lane-dependent selects: afterwards every lane of 16-lane
+// row q (q = lane / 16) holds in v[i], i < 4, the total of value 4 q + i (v_permlane32_swap pairs the
+// halves, v_permlane16_swap the rows, then a row mirror, a half-row mirror and two quad permutes).
+__device__ __forceinline__ void wave_sum16(double (&v)[16]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    swap32(v[i], v[i + 8]);
+    v[i] += v[i + 8];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    swap16(v[i], v[i + 4]);
+    v[i] += v[i + 4];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i] += dpp<kDppRowMirror>(v[i]);
+    v[i] += dpp<kDppRowHalfMirror>(v[i]);
+    v[i] += dpp<kDppQuadXor2>(v[i]);
+    v[i] += dpp<kDppQuadXor1>(v[i]);
+  }
+}
+
+// Value of v on lane l (l uniform), for every lane.
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
 // Sum over the block; every thread receives the same value.  Fixed association order
 // (butterfly inside a wave, then waves in index order), hence bitwise reproducible.
 template <int NT>

@@ -698,7 +698,7 @@ size_t call_bytes(const gmrf_op* Q, int64_t k, int m_max, int reorth, bool ring3
   if (Q->precond && !lgcp_path(Q)) b += precond_step_bytes(Q->plan, Q->storage, (int)k);   // band tables
   b += (size_t)k * (m_max + 2) * 8 * 4 + (size_t)k * 32;  // scalars, flags, poll values
   b += (fused_path(Q, reorth) ? 6 : 3) * (size_t)k * z.pstride * 8;   // partials (two sets when fused)
-  if (reorth) b += (size_t)k * (m_max + 1) * (z.Pb + 1) * 8;
+  if (reorth) b += (size_t)k * (m_max + 1) * ((size_t)z.Pb * reorth_partial_sets(z.L) + 1) * 8;
   if (!ring3) b += (size_t)k * m_max * 8 + tri_scratch_doubles((int)k, m_max) * 8;
   return b;
 }
@@ -956,7 +956,7 @@ gmrf_status setup_state(Run<T>& R, Workspace& ws) {
   HIP_TRY(hipMemsetAsync(ibuf, 0, 2 * k * sizeof(int), R.st));
   HIP_TRY(hipMemsetD32Async((hipDeviceptr_t)S.active, 1, k, R.st));
   if (R.reorth) {
-    if ((s = ws.alloc((size_t)k * (m + 1) * R.z.Pb, &R.part_h)) != GMRF_OK) return s;
+    if ((s = ws.alloc((size_t)k * (m + 1) * R.z.Pb * reorth_partial_sets(R.z.L), &R.part_h)) != GMRF_OK) return s;
     if ((s = ws.alloc((size_t)k * (m + 1), &R.h)) != GMRF_OK) return s;
   }
   return GMRF_OK;

@@ -28,6 +28,9 @@ int reorth_blocks(long L);
 // Qb != nullptr: the reorthogonalisation also does the update step before it (w_j = q - alpha_j v_j into
 // slot j, alpha_j), where reorth_takes_update(L); the caller then launches no update kernel
 bool reorth_takes_update(long L);
+// sets of [k][hstride][reorth_blocks(L)] partials part_h must hold (the short-vector form keeps the two
+// passes' dots apart; h is then unused)
+int reorth_partial_sets(long L);
 template <typename T> void launch_reorth(T* V, long L, int j, double* part_h, double* h, int hstride, const LzState& S, hipStream_t st, const T* Qb = nullptr);
 // out (+)= beta_0 y_t v_{t+1} from slot t (t = 0 writes); S: the state of the pass that produced y
 template <typename T, typename OutT> void launch_accumulate(const T* Vt, long L, const double* y, int ldy, const LzState& S, int t, OutT* out, long old, hipStream_t st);

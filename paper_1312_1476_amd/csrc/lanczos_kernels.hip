@@ -294,139 +294,178 @@ __global__ __launch_bounds__(kEwThreads) void k_reorth_update(T* __restrict__ V,
   }
 }
 
-// Short vectors (L <= kRoSmallL), dot half: block (x, r, z) covers the kEwChunk elements of chunk x for
-// the basis vectors of slice z; wave g holds its 512 elements of w in registers (8 per lane) and
-// reduces each v_{t+1}^T w over them, the four wave sums added in wave order through LDS.  No load
-// waits on another: active[] is not written during the reorthogonalisation, so it is read directly.
-constexpr int kRoDotTs = 64;   // basis vectors per LDS round
+// Short vectors (L <= kRoSmallL): block (x, r) owns chunk x of column r, the kWave * EPL elements
+// e = x * kWave * EPL + i * kWave + lane (i < EPL), and takes every basis vector over it; wave g of the
+// block takes the basis vectors t = t0 + g + 8 u (u < 16) of each sweep of 128.  The update of one pass and
+// the dots of the next then touch only the block's own elements and share one launch, so one step of CGS2
+// is three launches:
+//   MODE 0  the dots h_t = v_{t+1}^T w, t < j, of w = slot j; given q, w is first formed here as
+//           w_j = q - alpha_j v_j from the operator's partial sums (the update step of Algorithm 1);
+//   MODE 1  w -= sum_t h_t v_{t+1}, h_t the sum of MODE 0's block partials, then the dots of the result
+//           (the second pass);
+//   MODE 2  the same update with the second pass's h_t, then the partial sums of ||w||^2.
+// These kernels are bound by the latency of dependent memory accesses (about 1.5 us each here), so every
+// load a sweep needs is issued at its start, and with j <= 128 the dots of MODE 1 take the basis values its
+// update loaded: one round of loads per launch.  Sums over lanes take the 16 values of a wave's share at
+// once (wave_sum16: lane swaps and DPP permutes, no lane-dependent selects, which the compiler would turn
+// into indexed register reads).  An element's update is summed per wave in t order, then over the waves in
+// wave order through LDS.  Every sum has a fixed order, so results are bitwise reproducible.
+constexpr int kCsThreads = 512;
+constexpr int kCsWaves = kCsThreads / kWave;
+constexpr int kCsGroup = 16;                   // basis vectors per wave and sweep (values folded together)
+constexpr int kCsSpan = kCsWaves * kCsGroup;   // basis vectors per sweep
+constexpr long kRoSmallL = 16384;
+constexpr int kCsMaxChunks = 128;              // chunks per column (partials per h_t: at most two per lane)
 
-// Qb != nullptr (first pass only): the kernel also does the update step that precedes the
-// reorthogonalisation.  Every block forms alpha_j from the operator's partial sums and
-// w_j = q - alpha_j v_j for its elements (the update kernel's arithmetic); the blocks of slice 0 store w_j
-// and alpha_j, so no block reads slot j in this launch.
-template <typename T>
-__global__ __launch_bounds__(kEwThreads) void k_reorth_dot_short(const T* V, T* Wj, const T* __restrict__ Qb, long L,
-                                                                 int j, double* __restrict__ part_h, int hstride,
-                                                                 int tslice, LzState S) {
-  constexpr int NW = kEwThreads / kWave;
-  constexpr int PER = kEwChunk / kEwThreads;
-  __shared__ double red[NW][kRoDotTs];
-  __shared__ double lds[NW];
-  const int r = blockIdx.y;
-  if (!S.active[r]) return;
-  const size_t vs = lz_slot(S, L);
-  const int lane = threadIdx.x & (kWave - 1), g = threadIdx.x / kWave;
-  const long base = (long)blockIdx.x * kEwChunk + (long)g * (kWave * PER) + lane;
-  const T* w = V + (size_t)j * vs + (size_t)r * L;
-  double wv[PER];
-  if (Qb) {
-    const double a = sum_partials<kEwThreads>(S.part_a + (size_t)r * S.pstride, lz_pa(S, r), lds);
-    if (blockIdx.x == 0 && blockIdx.z == 0 && threadIdx.x == 0) S.alpha[lz_ia(S, r, j)] = a;
-    const double sc = 1.0 / S.beta[lz_ib(S, r, j - 1)];
-    const T* vj = V + (size_t)(j - 1) * vs + (size_t)r * L;
-    const T* q = Qb + (size_t)r * L;
-    T* wr = Wj + (size_t)r * L;
+// Elements per lane and basis vector: chunks as small as kCsMaxChunks allows.
+int cgs_epl(long L) { return L <= (long)kWave * kCsMaxChunks ? 1 : 2; }
+
+// The basis values (clamped indices, masked where used) of wave gu's share of the sweep at t0, and beta_t of
+// its basis vector u = lane & 15 (a vector load issued with the others; lanes take 1 / beta by shuffles).
+template <typename T, int EPL>
+__device__ __forceinline__ void cgs_load(const T* Vr, size_t vs, long L, long base, int lane, int gu, int t0, int j,
+                                         const LzState& S, int r, double (&vv)[kCsGroup][EPL], double& bl) {
+  bl = S.beta[lz_ib(S, r, min(t0 + gu + (lane & (kCsGroup - 1)) * kCsWaves, j - 1))];
 #pragma unroll
-    for (int qq = 0; qq < PER; ++qq) {
-      const long e = base + (long)qq * kWave;
-      wv[qq] = 0.0;
-      if (e < L) {
-        const double v = (double)(T)((double)vj[e] * sc);
-        const T t = (T)((double)q[e] - a * v);
-        if (blockIdx.z == 0) wr[e] = t;
-        wv[qq] = ip_weight(S, e) * (double)t;
-      }
-    }
-  } else {
+  for (int u = 0; u < kCsGroup; ++u) {
+    const int tc = min(t0 + gu + u * kCsWaves, j - 1);
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const long e = base + (long)q * kWave;
-      wv[q] = (e < L) ? ip_weight(S, e) * (double)w[e] : 0.0;
-    }
-  }
-  const int t1 = min(j, (int)(blockIdx.z + 1) * tslice);
-  for (int t0 = (int)blockIdx.z * tslice; t0 < t1; t0 += kRoDotTs) {
-    const int tn = min(kRoDotTs, t1 - t0);
-    for (int u = 0; u < tn; ++u) {
-      const int t = t0 + u;
-      const T* vt = V + (size_t)t * vs + (size_t)r * L;
-      const double sc = 1.0 / S.beta[lz_ib(S, r, t)];
-      double acc = 0.0;
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const long e = base + (long)q * kWave;
-        if (e < L) acc += (double)(T)((double)vt[e] * sc) * wv[q];
-      }
-      acc = wave_sum(acc);
-      if (lane == 0) red[g][u] = acc;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < tn) {
-      double s = 0.0;
-#pragma unroll
-      for (int w2 = 0; w2 < NW; ++w2) s += red[w2][threadIdx.x];
-      part_h[((size_t)r * hstride + t0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
-    }
-    __syncthreads();
+    for (int i = 0; i < EPL; ++i) vv[u][i] = (double)Vr[(size_t)tc * vs + min(base + i * kWave + lane, L - 1)];
   }
 }
 
-// Short vectors (L <= kRoSmallL): w -= sum_t h_t v_{t+1} with the t sum split over the 16 waves of a
-// 1024-thread block (wave g takes t = g, g + 16, ...) over a 512-element chunk, the 16 partial sums
-// added in wave order through LDS, so every element's chain is j / 16 long instead of j.  h_t is
-// summed here from the dot kernel's P block partials (in block order), with no reduce launch.
-constexpr int kRoThreads = 1024;
-constexpr int kRoWaves = kRoThreads / kWave;
-constexpr int kRoChunk = 512;
-constexpr int kRoPer = kRoChunk / kWave;
-constexpr long kRoSmallL = 65536;
+// Partials of the sweep's h_t (lane l holds block partials l and l + 64), summed after the loads are issued.
+__device__ __forceinline__ void cgs_load_h(const double* pin, int hstride, int P, int r, int lane, int gu, int t0,
+                                           int j, double (&p)[kCsGroup]) {
+  double pv[2][kCsGroup];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int u = 0; u < kCsGroup; ++u) {
+      const int tc = min(t0 + gu + u * kCsWaves, j - 1);
+      pv[q][u] = pin[((size_t)r * hstride + tc) * P + min(lane + q * kWave, P - 1)];
+    }
+#pragma unroll
+  for (int u = 0; u < kCsGroup; ++u) {
+    p[u] = (lane < P) ? pv[0][u] : 0.0;
+    p[u] += (lane + kWave < P) ? pv[1][u] : 0.0;
+  }
+}
 
-template <typename T>
-__global__ __launch_bounds__(kRoThreads) void k_reorth_update_short(T* __restrict__ V, long L, int j,
-                                                                    const double* __restrict__ part_h,
-                                                                    int hstride, int P, int with_norm, LzState S) {
-  __shared__ double red[kRoWaves][kRoChunk];
-  __shared__ double lds[kRoWaves];
+template <typename T, int EPL, int MODE>
+__global__ __launch_bounds__(kCsThreads) void k_cgs_short(T* __restrict__ V, const T* __restrict__ Qb, long L, int j,
+                                                          const double* __restrict__ pin, double* __restrict__ pout,
+                                                          int hstride, LzState S) {
+  constexpr int kChunk = kWave * EPL;
+  __shared__ double red[kCsWaves][kChunk];
+  __shared__ double wl[kChunk];   // the weighted w the dots take
+  __shared__ double lds[kCsWaves];
   const int r = blockIdx.y;
-  if (!S.active[r]) return;   // not written during the reorthogonalisation: every thread reads the same value
+  const int act = S.active[r];    // not written during the reorthogonalisation: the same on every thread
+  const int P = (int)gridDim.x, x = (int)blockIdx.x;
+  const int tid = (int)threadIdx.x, lane = tid & (kWave - 1);
+  const int gu = __builtin_amdgcn_readfirstlane(tid / kWave);
   const size_t vs = lz_slot(S, L);
+  const T* Vr = V + (size_t)r * L;
   T* w = V + (size_t)j * vs + (size_t)r * L;
-  const long base = (long)blockIdx.x * kRoChunk;
-  const int lane = threadIdx.x & (kWave - 1), g = threadIdx.x / kWave;
-  const long ew = base + threadIdx.x;
-  const double w0 = ((int)threadIdx.x < kRoChunk && ew < L) ? (double)w[ew] : 0.0;   // in flight during the t loop
-  double acc[kRoPer];
+  const long base = (long)x * kChunk;
+  const long eo = base + tid;                 // the element thread tid < kChunk writes
+  const long ec = min(eo, L - 1);
+  double vv[kCsGroup][EPL], bl;
+  if constexpr (MODE == 0) {
+    cgs_load<T, EPL>(Vr, vs, L, base, lane, gu, 0, j, S, r, vv, bl);
+    if (!act) return;
+    if (Qb) {
+      const double bprev = S.beta[lz_ib(S, r, j - 1)];
+      const double vj = (double)V[(size_t)(j - 1) * vs + (size_t)r * L + ec];
+      const double qv = (double)Qb[(size_t)r * L + ec];
+      const double a = sum_partials<kCsThreads>(S.part_a + (size_t)r * S.pstride, lz_pa(S, r), lds);
+      if (x == 0 && tid == 0) S.alpha[lz_ia(S, r, j)] = a;
+      if (tid < kChunk) {
+        double wt = 0.0;
+        if (eo < L) {
+          const double v = (double)(T)(vj * (1.0 / bprev));
+          const T t = (T)(qv - a * v);
+          w[eo] = t;
+          wt = ip_weight(S, eo) * (double)t;
+        }
+        wl[tid] = wt;
+      }
+    } else {
+      const double wv0 = (double)w[ec];
+      if (tid < kChunk) wl[tid] = (eo < L) ? ip_weight(S, eo) * wv0 : 0.0;
+    }
+  } else {
+    const double w0 = (double)w[ec];
+    double acc[EPL];
 #pragma unroll
-  for (int q = 0; q < kRoPer; ++q) acc[q] = 0.0;
-  for (int t = g; t < j; t += kRoWaves) {
-    const T* vt = V + (size_t)t * vs + (size_t)r * L;
-    const double sc = 1.0 / S.beta[lz_ib(S, r, t)];
-    const double* ph = part_h + ((size_t)r * hstride + t) * P;
-    double ht = 0.0;
-    for (int b = 0; b < P; ++b) ht += ph[b];
+    for (int i = 0; i < EPL; ++i) acc[i] = 0.0;
+    for (int t0 = 0; t0 < j; t0 += kCsSpan) {
+      double p[kCsGroup];
+      cgs_load<T, EPL>(Vr, vs, L, base, lane, gu, t0, j, S, r, vv, bl);
+      cgs_load_h(pin, hstride, P, r, lane, gu, t0, j, p);
+      if (!act) return;
+      wave_sum16(p);
+      const double il = 1.0 / bl;
 #pragma unroll
-    for (int q = 0; q < kRoPer; ++q) {
-      const long e = base + lane + q * kWave;
-      if (e < L) acc[q] += ht * (double)(T)((double)vt[e] * sc);
+      for (int u = 0; u < kCsGroup; ++u) {
+        const double h = lane_read(p[u & 3], 16 * (u >> 2));
+        const bool ok = t0 + gu + u * kCsWaves < j;
+        const double s = lane_read(il, u);
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) acc[i] += (ok && base + i * kWave + lane < L) ? h * (double)(T)(vv[u][i] * s) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) red[gu][i * kWave + lane] = acc[i];
+    __syncthreads();
+    double nrm = 0.0;
+    if (tid < kChunk) {
+      double s = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < kCsWaves; ++w2) s += red[w2][tid];
+      double wt = 0.0;
+      if (eo < L) {
+        const T t = (T)(w0 - s);
+        w[eo] = t;
+        const double q = ip_weight(S, eo);
+        wt = q * (double)t;
+        nrm = q * (double)t * (double)t;
+      }
+      wl[tid] = wt;
+    }
+    if constexpr (MODE == 2) {
+      const double s = block_sum<kCsThreads>(nrm, lds);
+      if (tid == 0) S.part_b[(size_t)r * S.pstride + x] = s;
+      return;
     }
   }
+  if constexpr (MODE != 2) {
+    __syncthreads();
+    double wv[EPL];
 #pragma unroll
-  for (int q = 0; q < kRoPer; ++q) red[g][lane + q * kWave] = acc[q];
-  __syncthreads();
-  double nrm = 0.0;
-  if ((int)threadIdx.x < kRoChunk) {
-    double s = 0.0;
+    for (int i = 0; i < EPL; ++i) wv[i] = wl[i * kWave + lane];
+    for (int t0 = 0; t0 < j; t0 += kCsSpan) {
+      // the values of the last sweep are still in registers when there was only one (MODE 0: the first)
+      if ((MODE == 0 && t0 > 0) || (MODE == 1 && j > kCsSpan)) cgs_load<T, EPL>(Vr, vs, L, base, lane, gu, t0, j, S, r, vv, bl);
+      const double il = 1.0 / bl;
+      double p[kCsGroup];
 #pragma unroll
-    for (int w2 = 0; w2 < kRoWaves; ++w2) s += red[w2][threadIdx.x];
-    if (ew < L) {
-      const T t = (T)(w0 - s);
-      w[ew] = t;
-      nrm = ip_weight(S, ew) * (double)t * (double)t;
+      for (int u = 0; u < kCsGroup; ++u) {
+        const bool ok = t0 + gu + u * kCsWaves < j;
+        const double s = lane_read(il, u);
+        p[u] = 0.0;
+#pragma unroll
+        for (int i = 0; i < EPL; ++i) p[u] += ok ? (double)(T)(vv[u][i] * s) * wv[i] : 0.0;
+      }
+      wave_sum16(p);
+      // lane i < 4 of row q writes value 4 q + i
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int t = t0 + gu + (4 * (lane >> 4) + i) * kCsWaves;
+        if ((lane & 15) == i && t < j) pout[((size_t)r * hstride + t) * P + x] = p[i];
+      }
     }
-  }
-  if (with_norm) {
-    const double s = block_sum<kRoThreads>(nrm, lds);
-    if (threadIdx.x == 0) S.part_b[(size_t)r * S.pstride + blockIdx.x] = s;
   }
 }
 
@@ -763,41 +802,49 @@ void launch_norm_partials(const T* V0, long L, const LzState& S, hipStream_t st)
 void launch_finalize(const LzState& S, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(S.k), dim3(256), 0, st, S);
 }
-int reorth_blocks(long L) { return L <= kRoSmallL ? (int)((L + kRoChunk - 1) / kRoChunk) : ew_blocks(L); }
+int reorth_blocks(long L) {
+  return L <= kRoSmallL ? (int)((L + (long)kWave * cgs_epl(L) - 1) / ((long)kWave * cgs_epl(L))) : ew_blocks(L);
+}
 
 bool reorth_takes_update(long L) { return L <= kRoSmallL; }
 
-static size_t lz_slot_h(const LzState& S, long L) { return S.slot_stride ? (size_t)S.slot_stride : (size_t)S.k * L; }
+int reorth_partial_sets(long L) { return L <= kRoSmallL ? 2 : 1; }
+
+template <typename T, int EPL>
+static void launch_cgs_short(T* V, long L, int j, double* ph0, double* ph1, int hstride, const LzState& S,
+                             hipStream_t st, const T* Qb) {
+  const dim3 g((unsigned)reorth_blocks(L), S.k);
+  hipLaunchKernelGGL((k_cgs_short<T, EPL, 0>), g, dim3(kCsThreads), 0, st, V, Qb, L, j, (const double*)nullptr, ph0,
+                     hstride, S);
+  hipLaunchKernelGGL((k_cgs_short<T, EPL, 1>), g, dim3(kCsThreads), 0, st, V, (const T*)nullptr, L, j,
+                     (const double*)ph0, ph1, hstride, S);
+  hipLaunchKernelGGL((k_cgs_short<T, EPL, 2>), g, dim3(kCsThreads), 0, st, V, (const T*)nullptr, L, j,
+                     (const double*)ph1, (double*)nullptr, hstride, S);
+}
 
 template <typename T>
 void launch_reorth(T* V, long L, int j, double* part_h, double* h, int hstride, const LzState& S,
                    hipStream_t st, const T* Qb) {
+  if (L <= kRoSmallL) {
+    // two sets of partials, [k][hstride][P] each: the first pass's dots and the second's
+    double* ph1 = part_h + (size_t)S.k * hstride * reorth_blocks(L);
+    if (cgs_epl(L) == 1) launch_cgs_short<T, 1>(V, L, j, part_h, ph1, hstride, S, st, Qb);
+    else launch_cgs_short<T, 2>(V, L, j, part_h, ph1, hstride, S, st, Qb);
+    return;
+  }
   const dim3 g = ew_grid(L, S.k);
   // t slices for the dot kernel: enough blocks for about two per compute unit, with at least
-  // kEwThreads / kWave vectors per slice (one per block for short vectors)
+  // kEwThreads / kWave vectors per slice
   constexpr int NW = kEwThreads / kWave;
-  const bool short_v = L <= kRoSmallL;
-  const int tmin = short_v ? 1 : NW;
   const long blocks = (long)g.x * S.k;
-  int nz = (int)std::min<long>((j + tmin - 1) / tmin, std::max<long>(1, (512 + blocks - 1) / blocks));
-  const int tslice = ((j + nz - 1) / nz + tmin - 1) / tmin * tmin;
+  int nz = (int)std::min<long>((j + NW - 1) / NW, std::max<long>(1, (512 + blocks - 1) / blocks));
+  const int tslice = ((j + nz - 1) / nz + NW - 1) / NW * NW;
   nz = (j + tslice - 1) / tslice;
   const dim3 gd(g.x, g.y, (unsigned)nz);
-  const dim3 gu((unsigned)reorth_blocks(L), S.k);
   for (int pass = 0; pass < 2; ++pass) {
-    if (short_v)
-      hipLaunchKernelGGL(k_reorth_dot_short<T>, gd, dim3(kEwThreads), 0, st, (const T*)V, V + (size_t)j * lz_slot_h(S, L),
-                         pass == 0 ? Qb : (const T*)nullptr, L, j, part_h, hstride, tslice, S);
-    else
-      hipLaunchKernelGGL(k_reorth_dot<T>, gd, dim3(kEwThreads), 0, st, V, L, j, part_h, hstride, tslice, S);
-    if (short_v) {
-      hipLaunchKernelGGL(k_reorth_update_short<T>, gu, dim3(kRoThreads), 0, st, V, L, j, part_h, hstride,
-                         (int)g.x, pass == 1 ? 1 : 0, S);
-    } else {
-      hipLaunchKernelGGL(k_reorth_reduce, dim3(S.k), dim3(256), 0, st, part_h, hstride, (int)g.x, j, h, S);
-      hipLaunchKernelGGL(k_reorth_update<T>, g, dim3(kEwThreads), 0, st, V, L, j, h, hstride,
-                         pass == 1 ? 1 : 0, S);
-    }
+    hipLaunchKernelGGL(k_reorth_dot<T>, gd, dim3(kEwThreads), 0, st, V, L, j, part_h, hstride, tslice, S);
+    hipLaunchKernelGGL(k_reorth_reduce, dim3(S.k), dim3(256), 0, st, part_h, hstride, (int)g.x, j, h, S);
+    hipLaunchKernelGGL(k_reorth_update<T>, g, dim3(kEwThreads), 0, st, V, L, j, h, hstride, pass == 1 ? 1 : 0, S);
   }
 }
 template <typename T, typename OutT>

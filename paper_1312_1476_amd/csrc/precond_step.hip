@@ -184,26 +184,6 @@ struct GroupReduce {
 // lanes get lo[i] + lo[i+32], upper lanes hi[i-32] + hi[i]; likewise per 16-lane row with
 // v_permlane16_swap), the one at distance 8 the DPP row mirror (lane i <-> 15 - i), and the last three
 // a half-row mirror and two quad permutes.  No LDS traffic; LOW = 7, base from lane bits 5, 4, 3.
-__device__ __forceinline__ void swap32(double& a, double& b) {
-  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
-  a = __hiloint2double((int)hi[0], (int)lo[0]);
-  b = __hiloint2double((int)hi[1], (int)lo[1]);
-}
-__device__ __forceinline__ void swap16(double& a, double& b) {
-  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
-  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
-  a = __hiloint2double((int)hi[0], (int)lo[0]);
-  b = __hiloint2double((int)hi[1], (int)lo[1]);
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-constexpr int kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141, kDppQuadXor2 = 0x4E, kDppQuadXor1 = 0xB1;
-
 __device__ __forceinline__ int wave_reduce8(double& a0, double& a1, double& a2, double& a3, double& a4, double& a5,
                                             double& a6, double& a7, int lane) {
   swap32(a0, a4);
