@@ -223,11 +223,36 @@ __device__ __forceinline__ bool block_active(const LzState& S, int r, int* lds_f
 //   non-finite z: EINVAL).  With j = m_max + 1 it also closes a run that hit m_max.
 // On continuation it returns s_cur = 1/beta_{j-1} (scale of slot j-1, giving v_j),
 // s_prev = 1/beta_{j-2} (slot j-2, giving v_{j-1}) and bprev = beta_{j-1}.
+// Every load it needs is issued before the first wait (active[r] by one thread, broadcast with the partial
+// sums' block reduction, whose order is sum_partials'; the scalars of iteration j-1, which no block of
+// this launch writes, by every wave).
 template <int NT>
 __device__ bool lz_open(const LzState& S, int r, int j, bool writer, double* lds, int* lds_flag,
                         double& s_cur, double& s_prev, double& bprev) {
-  if (!block_active(S, r, lds_flag)) return false;
-  const double bsq = sum_partials<NT>(S.part_b + (size_t)r * S.pstride, lz_pb(S, r), lds);
+  constexpr int NW = NT / kWave;
+  const int tid = (int)threadIdx.x;
+  const int act0 = (tid == 0) ? S.active[r] : 0;
+  const int jm = j - 1;                        // iteration being closed (j >= 2)
+  double a = 0.0, bm1 = 0.0, dm1 = 1.0, rm1 = 1.0;
+  if (j >= 2) {
+    a = S.alpha[lz_ia(S, r, jm)];
+    bm1 = S.beta[lz_ib(S, r, jm - 1)];
+    rm1 = S.rho[lz_ia(S, r, jm - 1)];
+    if (jm >= 2) dm1 = S.dpiv[lz_ia(S, r, jm - 1)];
+  }
+  const double* pb = S.part_b + (size_t)r * S.pstride;
+  const int P = lz_pb(S, r);
+  double ps = 0.0;
+  for (int i = tid; i < P; i += NT) ps += pb[i];
+  ps = wave_sum(ps);
+  __syncthreads();
+  if ((tid & (kWave - 1)) == 0) lds[tid / kWave] = ps;
+  if (tid == 0) lds_flag[0] = act0;
+  __syncthreads();
+  if (!lds_flag[0]) return false;
+  double bsq = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) bsq += lds[i];
   const double b = sqrt(bsq);
   if (j == 1) {
     bool ok = (b > 0.0) && isfinite(b);
@@ -245,11 +270,9 @@ __device__ bool lz_open(const LzState& S, int r, int j, bool writer, double* lds
     bprev = 0.0;
     return ok;
   }
-  const int jm = j - 1;                        // iteration being closed
-  const double a = S.alpha[lz_ia(S, r, jm)];
-  const double bpp = (jm >= 2) ? S.beta[lz_ib(S, r, jm - 1)] : 0.0;   // beta_{j-2}
-  const double d = (jm == 1) ? a : a - bpp * bpp / S.dpiv[lz_ia(S, r, jm - 1)];
-  const double rh = S.rho[lz_ia(S, r, jm - 1)] * b / d;
+  const double bpp = (jm >= 2) ? bm1 : 0.0;   // beta_{j-2}
+  const double d = (jm == 1) ? a : a - bpp * bpp / dm1;
+  const double rh = rm1 * b / d;
   int st = kOK;
   bool stop = false;
   if (!(a > 0.0) || !(d > 0.0) || !isfinite(b)) {
@@ -273,7 +296,7 @@ __device__ bool lz_open(const LzState& S, int r, int j, bool writer, double* lds
   }
   if (stop) return false;
   s_cur = 1.0 / b;
-  s_prev = 1.0 / S.beta[lz_ib(S, r, jm - 1)];
+  s_prev = 1.0 / bm1;
   bprev = b;
   return true;
 }

@@ -247,13 +247,13 @@ def test_sample_fp32_storage(gm, reorth):
 
 
 @pytest.mark.parametrize("shape,k,m,storage", [((300, 300), 2, 30, "f64"), ((300, 300), 2, 20, "f32"),
-                                               ((256, 256), 2, 25, "f64"), ((65537,), 1, 20, "f64"),
+                                               ((128, 128), 2, 25, "f64"), ((16385,), 1, 20, "f64"),
                                                ((64, 64), 24, 40, "f64"), ((33, 31), 3, 45, "f32")],
                          ids=["long-f64", "long-f32", "at-limit", "limit+1", "many-columns", "odd-f32"])
 def test_reorth_tilings(gm, shape, k, m, storage):
-    """Both reorthogonalisation tilings (vectors of up to 65536 elements, and longer), the slices of
-    basis vectors the dot kernels take on small grids, and the FP32 combine with and without float4
-    loads, at a forced m against the oracle with CGS2."""
+    """Both reorthogonalisation tilings (vectors of up to 16384 elements in 64- or 128-element chunks per
+    block, and longer), the slices of basis vectors the general dot kernel takes on small grids, and the
+    FP32 combine with and without float4 loads, at a forced m against the oracle with CGS2."""
     op = gm.Operator.lattice(shape, 1, 0.05, 1.0, "free", storage)
     Q = lattice.lattice_precision(shape, 1, 0.05, 1.0, "free")
     Zh = workloads.gaussian_block(Q.shape[0], k, 97, 0)
@@ -263,6 +263,20 @@ def test_reorth_tilings(gm, shape, k, m, storage):
         assert info[r]["m_used"] == m
         ref = lanczos.sample_csr(Q, Zh[:, r], m, tol=0.0, reorth=True)
         assert _rel(X[:, r], ref.x) <= tol, (r, _rel(X[:, r], ref.x))
+
+
+def test_reorth_many_sweeps(gm):
+    """CGS2 past 128 basis vectors, which the short-vector kernels take in sweeps of 128: a 1D lattice of
+    800 points with kappa^2 = 0.002 needs about 510 steps to rho <= 1e-10 (four sweeps, the last one
+    partial); parity with the oracle at the GPU's m."""
+    op = gm.Operator.lattice((800,), 1, 0.002, 1.0, "free", "f64")
+    Q = lattice.lattice_precision((800,), 1, 0.002, 1.0, "free")
+    Zh = workloads.gaussian_block(800, 2, 96, 0)
+    X, info, _, _ = _gpu_sample(gm, op, Zh, tol=1e-10, m_max=700, reorth=True)
+    for r in range(2):
+        assert info[r]["status"] == "OK" and info[r]["m_used"] > 3 * 128, info[r]
+        ref = lanczos.sample_csr(Q, Zh[:, r], info[r]["m_used"], tol=0.0, reorth=True)
+        assert _rel(X[:, r], ref.x) <= 1e-8, (r, _rel(X[:, r], ref.x))
 
 
 def test_edge_cases(gm):
