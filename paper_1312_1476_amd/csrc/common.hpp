@@ -223,36 +223,39 @@ __device__ __forceinline__ bool block_active(const LzState& S, int r, int* lds_f
 //   non-finite z: EINVAL).  With j = m_max + 1 it also closes a run that hit m_max.
 // On continuation it returns s_cur = 1/beta_{j-1} (scale of slot j-1, giving v_j),
 // s_prev = 1/beta_{j-2} (slot j-2, giving v_{j-1}) and bprev = beta_{j-1}.
-// Every load it needs is issued before the first wait (active[r] by one thread, broadcast with the partial
-// sums' block reduction, whose order is sum_partials'; the scalars of iteration j-1, which no block of
-// this launch writes, by every wave).
+// The loads of the scalar step for column r, all issued before any wait: active[r] (by one thread, broadcast
+// with the partial sums' block reduction), this thread's share of the ||w_{j-1}||^2 partials (summed in
+// sum_partials' order), and the scalars of iteration j-1, which no block of this launch writes.
+struct LzOpenIn {
+  int act0;
+  double ps, a, bm1, dm1, rm1;
+};
 template <int NT>
-__device__ bool lz_open(const LzState& S, int r, int j, bool writer, double* lds, int* lds_flag,
-                        double& s_cur, double& s_prev, double& bprev) {
-  constexpr int NW = NT / kWave;
+__device__ __forceinline__ LzOpenIn lz_open_load(const LzState& S, int r, int j) {
+  LzOpenIn o;
   const int tid = (int)threadIdx.x;
-  const int act0 = (tid == 0) ? S.active[r] : 0;
-  const int jm = j - 1;                        // iteration being closed (j >= 2)
-  double a = 0.0, bm1 = 0.0, dm1 = 1.0, rm1 = 1.0;
+  o.act0 = (tid == 0) ? S.active[r] : 0;
+  o.a = 0.0;
+  o.bm1 = 0.0;
+  o.dm1 = 1.0;
+  o.rm1 = 1.0;
   if (j >= 2) {
-    a = S.alpha[lz_ia(S, r, jm)];
-    bm1 = S.beta[lz_ib(S, r, jm - 1)];
-    rm1 = S.rho[lz_ia(S, r, jm - 1)];
-    if (jm >= 2) dm1 = S.dpiv[lz_ia(S, r, jm - 1)];
+    const int jm = j - 1;
+    o.a = S.alpha[lz_ia(S, r, jm)];
+    o.bm1 = S.beta[lz_ib(S, r, jm - 1)];
+    o.rm1 = S.rho[lz_ia(S, r, jm - 1)];
+    if (jm >= 2) o.dm1 = S.dpiv[lz_ia(S, r, jm - 1)];
   }
   const double* pb = S.part_b + (size_t)r * S.pstride;
   const int P = lz_pb(S, r);
-  double ps = 0.0;
-  for (int i = tid; i < P; i += NT) ps += pb[i];
-  ps = wave_sum(ps);
-  __syncthreads();
-  if ((tid & (kWave - 1)) == 0) lds[tid / kWave] = ps;
-  if (tid == 0) lds_flag[0] = act0;
-  __syncthreads();
-  if (!lds_flag[0]) return false;
-  double bsq = 0.0;
-#pragma unroll
-  for (int i = 0; i < NW; ++i) bsq += lds[i];
+  o.ps = 0.0;
+  for (int i = tid; i < P; i += NT) o.ps += pb[i];
+  return o;
+}
+
+// The decision of the scalar step from beta_{j-1}^2 = bsq and the loaded scalars (see lz_open).
+__device__ __forceinline__ bool lz_decide(const LzState& S, int r, int j, bool writer, double bsq, const LzOpenIn& o,
+                                          double& s_cur, double& s_prev, double& bprev) {
   const double b = sqrt(bsq);
   if (j == 1) {
     bool ok = (b > 0.0) && isfinite(b);
@@ -270,9 +273,11 @@ __device__ bool lz_open(const LzState& S, int r, int j, bool writer, double* lds
     bprev = 0.0;
     return ok;
   }
-  const double bpp = (jm >= 2) ? bm1 : 0.0;   // beta_{j-2}
-  const double d = (jm == 1) ? a : a - bpp * bpp / dm1;
-  const double rh = rm1 * b / d;
+  const int jm = j - 1;                        // iteration being closed
+  const double a = o.a;
+  const double bpp = (jm >= 2) ? o.bm1 : 0.0;   // beta_{j-2}
+  const double d = (jm == 1) ? a : a - bpp * bpp / o.dm1;
+  const double rh = o.rm1 * b / d;
   int st = kOK;
   bool stop = false;
   if (!(a > 0.0) || !(d > 0.0) || !isfinite(b)) {
@@ -296,9 +301,57 @@ __device__ bool lz_open(const LzState& S, int r, int j, bool writer, double* lds
   }
   if (stop) return false;
   s_cur = 1.0 / b;
-  s_prev = 1.0 / bm1;
+  s_prev = 1.0 / o.bm1;
   bprev = b;
   return true;
+}
+
+template <int NT>
+__device__ bool lz_open(const LzState& S, int r, int j, bool writer, double* lds, int* lds_flag,
+                        double& s_cur, double& s_prev, double& bprev) {
+  constexpr int NW = NT / kWave;
+  const int tid = (int)threadIdx.x;
+  const LzOpenIn o = lz_open_load<NT>(S, r, j);
+  const double ps = wave_sum(o.ps);
+  __syncthreads();
+  if ((tid & (kWave - 1)) == 0) lds[tid / kWave] = ps;
+  if (tid == 0) lds_flag[0] = o.act0;
+  __syncthreads();
+  if (!lds_flag[0]) return false;
+  double bsq = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) bsq += lds[i];
+  return lz_decide(S, r, j, writer, bsq, o, s_cur, s_prev, bprev);
+}
+
+// lz_open for the KB columns r0 .. r0 + KB - 1 (those below k) of one block at once: every column's loads
+// are issued before the first wait and the reductions share two barriers.  lds: KB * NT / 64 doubles,
+// lds_flag: KB ints.  act[c] is true on return where column r0 + c continues.
+template <int NT, int KB>
+__device__ void lz_open_multi(const LzState& S, int r0, int k, int j, bool writer, double* lds, int* lds_flag,
+                              bool (&act)[KB], double (&s_cur)[KB], double (&s_prev)[KB], double (&bprev)[KB]) {
+  constexpr int NW = NT / kWave;
+  const int tid = (int)threadIdx.x;
+  LzOpenIn o[KB];
+#pragma unroll
+  for (int c = 0; c < KB; ++c) o[c] = lz_open_load<NT>(S, min(r0 + c, k - 1), j);
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < KB; ++c) {
+    const double ps = wave_sum(o[c].ps);
+    if ((tid & (kWave - 1)) == 0) lds[c * NW + tid / kWave] = ps;
+    if (tid == 0) lds_flag[c] = (r0 + c < k) ? o[c].act0 : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < KB; ++c) {
+    act[c] = lds_flag[c] != 0;
+    if (!act[c]) continue;
+    double bsq = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) bsq += lds[c * NW + i];
+    act[c] = lz_decide(S, r0 + c, j, writer, bsq, o[c], s_cur[c], s_prev[c], bprev[c]);
+  }
 }
 
 // Inner-product weight of storage element e (real index) of a vector.

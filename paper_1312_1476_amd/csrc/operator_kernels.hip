@@ -937,21 +937,22 @@ __global__ __launch_bounds__(256) void k_csr(long n, const int64_t* __restrict__
                                              const int32_t* __restrict__ ci, const T* __restrict__ va,
                                              const T* __restrict__ X, long xld, T* __restrict__ Y,
                                              long yld, const T* __restrict__ Xprev, LzState S, int j, int k) {
-  __shared__ double red[256 / kWave];
-  __shared__ int flag[1];
+  __shared__ double red[KB * (256 / kWave)];
+  __shared__ int flag[KB];
   const int r0 = blockIdx.y * KB;
   double s_cur[KB], s_prev[KB], bprev[KB];
   bool act[KB];
-  bool any = false;
 #pragma unroll
   for (int c = 0; c < KB; ++c) {
     act[c] = r0 + c < k;    // uniform over the block
     s_cur[c] = 1.0;
     s_prev[c] = 0.0;
     bprev[c] = 0.0;
-    if (LZ && act[c]) act[c] = lz_open<256>(S, r0 + c, j, blockIdx.x == 0, red, flag, s_cur[c], s_prev[c], bprev[c]);
-    any = any || act[c];
   }
+  if (LZ) lz_open_multi<256, KB>(S, r0, k, j, blockIdx.x == 0, red, flag, act, s_cur, s_prev, bprev);
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < KB; ++c) any = any || act[c];
   if (!any) return;
   const long row = (long)blockIdx.x * 256 + threadIdx.x;
   T s[KB];
@@ -1187,17 +1188,24 @@ static void launch_csr_kb(long n, const int64_t* rp, const int32_t* ci, const T*
     hipLaunchKernelGGL((k_csr<T, false, KB>), grid, dim3(256), 0, st, n, rp, ci, va, X, xld, Y, yld, Xprev, S, j, k);
 }
 
-// Columns per block: 8 from 8 right-hand sides, 4 from 4, else 1 (no result bit depends on it).
+// Columns per block (no result bit depends on it): 8 or 4 where the grid keeps at least kCsrMinBlocks blocks,
+// else 1.  Blocking saves re-reads of the matrix on large matrices; on small ones (the 900-row matrix of
+// Section 5.2 with 32 columns: 16 blocks at 8 columns each) the fewer, longer blocks are latency-bound.
 #ifndef GMRF_CSR_MAX_KB
 #define GMRF_CSR_MAX_KB 8
 #endif
+constexpr long kCsrMinBlocks = 512;
 template <typename T>
 void launch_csr(long n, const int64_t* rp, const int32_t* ci, const T* va, bool lz, const T* X,
                 long xld, T* Y, long yld, const T* Xprev, const LzState& S, int j, int k,
                 hipStream_t st) {
-  if (GMRF_CSR_MAX_KB >= 8 && k >= 8) launch_csr_kb<T, 8>(n, rp, ci, va, lz, X, xld, Y, yld, Xprev, S, j, k, st);
-  else if (GMRF_CSR_MAX_KB >= 4 && k >= 4) launch_csr_kb<T, 4>(n, rp, ci, va, lz, X, xld, Y, yld, Xprev, S, j, k, st);
-  else launch_csr_kb<T, 1>(n, rp, ci, va, lz, X, xld, Y, yld, Xprev, S, j, k, st);
+  const long rb = csr_blocks(n);
+  if (GMRF_CSR_MAX_KB >= 8 && k >= 8 && rb * ((k + 7) / 8) >= kCsrMinBlocks)
+    launch_csr_kb<T, 8>(n, rp, ci, va, lz, X, xld, Y, yld, Xprev, S, j, k, st);
+  else if (GMRF_CSR_MAX_KB >= 4 && k >= 4 && rb * ((k + 3) / 4) >= kCsrMinBlocks)
+    launch_csr_kb<T, 4>(n, rp, ci, va, lz, X, xld, Y, yld, Xprev, S, j, k, st);
+  else
+    launch_csr_kb<T, 1>(n, rp, ci, va, lz, X, xld, Y, yld, Xprev, S, j, k, st);
 }
 
 template void launch_stencil<double>(const StencilGeom&, int, int, bool, const double*, long, double*,

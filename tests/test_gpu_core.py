@@ -77,6 +77,30 @@ def test_apply_csr(gm, storage):
     assert np.abs(Y - ref).max() / np.abs(ref).max() <= (1e-14 if storage == "f64" else 1e-5)
 
 
+def test_csr_column_blocks_bitwise(gm):
+    """The CSR kernel takes 8, 4 or 1 right-hand sides per block by grid size (a 192 x 192 lattice's
+    36864 rows: 8 at 32 columns, 4 at 16, 1 at one).  A column's bits do not depend on it, in the
+    operator and in the Lanczos step, and the 32-column samples match the oracle."""
+    import scipy.sparse as sps
+    Q = sps.csr_matrix(lattice.lattice_precision((192, 192), 1, 0.05, 1.0, "free"))
+    Q.sort_indices()
+    op = gm.Operator.csr(Q.shape[0], Q.indptr, Q.indices, Q.data, "f64")
+    Zh = workloads.gaussian_block(Q.shape[0], 32, 95, 0)
+    Y32 = op.apply(_t(Zh.T)).cpu().numpy()
+    Y16 = op.apply(_t(Zh[:, :16].T)).cpu().numpy()
+    Y1 = op.apply(_t(Zh[:, 7:8].T)).cpu().numpy()
+    assert np.array_equal(Y16, Y32[:16]) and np.array_equal(Y1[0], Y32[7])
+    assert np.abs(Y32 - (Q @ Zh).T).max() <= 1e-13 * np.abs(Y32).max()
+    X32, i32, _, _ = _gpu_sample(gm, op, Zh, tol=1e-8, m_max=300)
+    X16, _, _, _ = _gpu_sample(gm, op, Zh[:, :16], tol=1e-8, m_max=300)
+    assert np.array_equal(X16, X32[:, :16])
+    for r in (0, 31):
+        X1, i1, _, _ = _gpu_sample(gm, op, Zh[:, r:r + 1], tol=1e-8, m_max=300)
+        assert i1[0]["m_used"] == i32[r]["m_used"] and np.array_equal(X1[:, 0], X32[:, r])
+        ref = lanczos.sample_csr(Q, Zh[:, r], i32[r]["m_used"], tol=0.0)
+        assert i32[r]["status"] == "OK" and _rel(X32[:, r], ref.x) <= 1e-8, (r, _rel(X32[:, r], ref.x))
+
+
 @pytest.mark.parametrize("n,nprobes,seed", [(1, 1, 0), (255, 2, 7), (1000, 3, 14761315), (70001, 2, 2 ** 63 + 5)])
 def test_rademacher_bit_exact(gm, n, nprobes, seed):
     P = gm.rademacher(seed, n, nprobes).cpu().numpy().astype(np.float64)
