@@ -692,15 +692,14 @@ def serving_leg(gm, torch, seconds):
     log-uniform on [64, 2048]) and 3D 7-point lattices (side 16..128), kappa2 log-uniform on
     [1e-3, 1], k uniform on 1..32; 75% samples, 25% log-det estimates.  Samples are served from
     FP32-storage operators at tol 1e-5 (m_max 600) and count only when their status is OK; log-dets
-    (m = 80) run on FP64-storage copies of the same lattices.  Each offered rate gets an arrival window
+    (m = 80) run on the same FP32-storage operators with FP64 scalars, as the 1024^2 log-det estimate does.  Each offered rate gets an arrival window
     of `seconds` after a 2 s warm-up whose requests are served but not counted; the rates rise until the
     server falls behind (the queue does not drain within max(2 s, 10% of the window) after the last
     arrival).  The sustainable rate is the highest one it kept up with; latency runs from arrival to
     result."""
     from paper_1312_1476_amd import serve
     pool = workloads.serving_pool()
-    ops = [gm.Operator.lattice(p.shape, p.order, p.kappa2, p.tau, "free", "f32") for p in pool] + \
-          [gm.Operator.lattice(p.shape, p.order, p.kappa2, p.tau, "free", "f64") for p in pool]
+    ops = [gm.Operator.lattice(p.shape, p.order, p.kappa2, p.tau, "free", "f32") for p in pool]
     gm.set_hbm_budget(0)           # returns the scratch the earlier legs left cached in the library's pool
     torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
@@ -708,14 +707,14 @@ def serving_leg(gm, torch, seconds):
     t0 = time.perf_counter()
     gm.pool_reserve(budget)        # one region for all scratch: no device allocation while serving
     t_reserve = time.perf_counter() - t0
-    out = {"pool": "64 lattices: 2D 5-point (80%), 3D 7-point (20%); samples FP32 storage, log-dets FP64",
+    out = {"pool": "64 lattices: 2D 5-point (80%), 3D 7-point (20%); FP32 storage, FP64 scalars",
            "workers": 4, "hbm_budget_gb": round(budget / 1e9, 1), "reserved_region_s": round(t_reserve, 2),
            "arrival_window_s": seconds, "warmup_s": SERVE_WARMUP_S,
            "sample_tol": SERVE_TOL, "sample_m_max": SERVE_M_MAX, "logdet_m": SERVE_LOGDET_M, "rates": {}}
     sustainable = None
     for rate in SERVE_RATES:
         trace = workloads.serving_trace(rate=rate, duration=seconds + SERVE_WARMUP_S)
-        reqs = [serve.ServeRequest(i, r.kind, r.op_index + (len(pool) if r.kind == "logdet" else 0), r.k, r.seed,
+        reqs = [serve.ServeRequest(i, r.kind, r.op_index, r.k, r.seed,
                                    tol=SERVE_TOL, m_max=(SERVE_M_MAX if r.kind == "sample" else SERVE_LOGDET_M),
                                    t_arrival=r.t_arrival) for i, r in enumerate(trace)]
         counted = [q for q, r in zip(reqs, trace) if r.t_arrival >= SERVE_WARMUP_S]

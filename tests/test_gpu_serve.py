@@ -1,11 +1,12 @@
 """Serving (continuous batching) over the C ABI: each result is identical alone, in a mix of
 overlapping jobs and coalesced into a batched job; admission never exceeds the HBM budget; a sample
 whose stored basis does not fit runs the two-pass sampler; requests too large even for that are
-rejected; and served samples (FP64 alone, FP32 storage in a batch) match the oracle."""
+rejected; and served samples (FP64 alone, FP32 storage in a batch) and FP32-storage log-dets match the
+oracle."""
 import numpy as np
 import pytest
 
-from oracle import lanczos, lattice
+from oracle import lanczos, lattice, logdet
 
 pytestmark = pytest.mark.gpu
 
@@ -179,6 +180,24 @@ def test_served_fp32_batch_matches_oracle(env):
         for c in range(r.k):
             ref = lanczos.sample_csr(Q, Z[c], res["info"][c]["m_used"], tol=0.0)
             assert np.linalg.norm(X[c] - ref.x) / np.linalg.norm(ref.x) <= 1e-5, (r.rid, c)
+
+
+def test_served_fp32_logdets_match_oracle(env):
+    """Two log-det requests on the FP32-storage lattice merged into one call (each request's own seed's
+    Rademacher probes, FP64 scalars), as the serving mix runs them: every per-probe quadrature is within
+    1e-5 (relative) of the oracle's on the same probes."""
+    import torch
+    gm, serve, ops = env
+    srv = serve.Server(ops, hbm_budget=64 << 30, workers=1)
+    reqs = [serve.ServeRequest(1, "logdet", 0, 5, 81, m_max=40), serve.ServeRequest(2, "logdet", 0, 3, 83, m_max=40)]
+    for r in reqs:
+        r.bytes = srv.request_bytes(r)
+    assert srv._batch_key(reqs[0]) == srv._batch_key(reqs[1]) is not None
+    results = srv._execute(reqs, torch.cuda.Stream())
+    Q = lattice.lattice_precision((96, 80), 1, 0.05, 1.0, "free")
+    for r, res in zip(reqs, results):
+        ref = logdet.hutchinson_csr(Q, r.k, r.m_max, seed=r.seed)
+        assert np.all(np.abs(res["per_probe"] - ref.per_probe) <= 1e-5 * np.abs(ref.per_probe)), r.rid
 
 
 def test_two_pass_fallback(env):
