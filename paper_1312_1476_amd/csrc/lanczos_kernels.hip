@@ -26,13 +26,16 @@ __global__ __launch_bounds__(kEwThreads) void k_init_from_f64(const double* __re
   const double* z = Z + (ext ? (size_t)ext[r] : (size_t)r * zld);
   T* v = V0 + lz_off(S, r, L);
   double acc = 0.0;
+  // every load issued before the first use, from a clamped index (a load behind a bounds branch waits for
+  // its own data); only the stores and the sum are masked
+  double zv[kEwPerThread];
+  EW_LOOP(q) zv[q] = z[min(base + (long)q * kEwThreads, len - 1)];
   EW_LOOP(q) {
     const long e = base + (long)q * kEwThreads;
-    if (e < len) {
-      const T t = (T)z[e];
-      v[e] = t;
-      acc += ip_weight(S, e) * (double)t * (double)t;
-    }
+    const T t = (T)zv[q];
+    if (e < len) v[e] = t;
+    const double tm = (e < len) ? (double)t : 0.0;   // the operand is masked, so the sum keeps its fused form
+    acc += ip_weight(S, e) * tm * tm;
   }
   const double s = block_sum<kEwThreads>(acc, lds);
   if (threadIdx.x == 0) S.part_b[(size_t)r * S.pstride + blockIdx.x] = s;
@@ -121,13 +124,14 @@ __global__ __launch_bounds__(kEwThreads) void k_init_from_i8(const int8_t* __res
   const int r = blockIdx.y;
   const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
   double acc = 0.0;
+  int8_t pv[kEwPerThread];
+  EW_LOOP(q) pv[q] = P[(size_t)r * L + min(base + (long)q * kEwThreads, L - 1)];   // clamped, masked below
   EW_LOOP(q) {
     const long e = base + (long)q * kEwThreads;
-    if (e < L) {
-      const T t = (T)P[(size_t)r * L + e];
-      V0[(size_t)r * L + e] = t;
-      acc += (double)t * (double)t;
-    }
+    const T t = (T)pv[q];
+    if (e < L) V0[(size_t)r * L + e] = t;
+    const double tm = (e < L) ? (double)t : 0.0;
+    acc += tm * tm;
   }
   const double s = block_sum<kEwThreads>(acc, lds);
   if (threadIdx.x == 0) S.part_b[(size_t)r * S.pstride + blockIdx.x] = s;
@@ -143,24 +147,31 @@ __global__ __launch_bounds__(kEwThreads) void k_update(const T* __restrict__ Qb,
   const int r = blockIdx.y;
   const long len = lz_len(S, r, L);
   if ((long)blockIdx.x * kEwChunk >= len) return;
-  if (!block_active(S, r, flag)) return;
-  const double a = sum_partials<kEwThreads>(S.part_a + (size_t)r * S.pstride, lz_pa(S, r), lds);
-  if (blockIdx.x == 0 && threadIdx.x == 0) S.alpha[lz_ia(S, r, j)] = a;
-  const double sc = 1.0 / S.beta[lz_ib(S, r, j - 1)];
   const size_t off = lz_off(S, r, L);
   const T* vj = Vj + off;
   T* w = W + off;
   const T* q = Qb + off;
   const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
+  // the elements' loads go out first, with the scalars' (clamped indices, masked below: a load behind a
+  // bounds branch waits for its own data)
+  T va[kEwPerThread], qa[kEwPerThread];
+  EW_LOOP(qq) {
+    const long ec = min(base + (long)qq * kEwThreads, len - 1);
+    va[qq] = vj[ec];
+    qa[qq] = q[ec];
+  }
+  if (!block_active(S, r, flag)) return;
+  const double a = sum_partials<kEwThreads>(S.part_a + (size_t)r * S.pstride, lz_pa(S, r), lds);
+  if (blockIdx.x == 0 && threadIdx.x == 0) S.alpha[lz_ia(S, r, j)] = a;
+  const double sc = 1.0 / S.beta[lz_ib(S, r, j - 1)];
   double acc = 0.0;
   EW_LOOP(qq) {
     const long e = base + (long)qq * kEwThreads;
-    if (e < len) {
-      const double v = (double)(T)((double)vj[e] * sc);
-      const T t = (T)((double)q[e] - a * v);
-      w[e] = t;
-      acc += ip_weight(S, e) * (double)t * (double)t;
-    }
+    const double v = (double)(T)((double)va[qq] * sc);
+    const T t = (T)((double)qa[qq] - a * v);
+    if (e < len) w[e] = t;
+    const double tm = (e < len) ? (double)t : 0.0;   // the operand is masked, so the sum keeps its fused form
+    acc += ip_weight(S, e) * tm * tm;
   }
   if (with_norm) {
     const double s = block_sum<kEwThreads>(acc, lds);
@@ -175,12 +186,12 @@ __global__ __launch_bounds__(kEwThreads) void k_norm_partials(const T* __restric
   const int r = blockIdx.y;
   const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
   double acc = 0.0;
+  double tv[kEwPerThread];
+  EW_LOOP(q) tv[q] = (double)V0[(size_t)r * L + min(base + (long)q * kEwThreads, L - 1)];   // clamped, masked below
   EW_LOOP(q) {
     const long e = base + (long)q * kEwThreads;
-    if (e < L) {
-      const double t = (double)V0[(size_t)r * L + e];
-      acc += ip_weight(S, e) * t * t;
-    }
+    const double tm = (e < L) ? tv[q] : 0.0;
+    acc += ip_weight(S, e) * tm * tm;
   }
   const double s = block_sum<kEwThreads>(acc, lds);
   if (threadIdx.x == 0) S.part_b[(size_t)r * S.pstride + blockIdx.x] = s;
@@ -259,11 +270,9 @@ __global__ __launch_bounds__(kEwThreads) void k_reorth_update(T* __restrict__ V,
   const size_t vs = lz_slot(S, L);
   T* w = V + (size_t)j * vs + (size_t)r * L;
   const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
+  // loads from clamped indices, masked in the sums (a load behind a bounds branch waits for its own data)
   double acc[kEwPerThread];
-  EW_LOOP(q) {
-    const long e = base + (long)q * kEwThreads;
-    acc[q] = (e < L) ? (double)w[e] : 0.0;
-  }
+  EW_LOOP(q) acc[q] = (double)w[min(base + (long)q * kEwThreads, L - 1)];
   for (int t0 = 0; t0 < j; t0 += 1024) {
     const int tn = min(1024, j - t0);
     __syncthreads();
@@ -273,20 +282,18 @@ __global__ __launch_bounds__(kEwThreads) void k_reorth_update(T* __restrict__ V,
       const T* vt = V + (size_t)(t0 + t) * vs + (size_t)r * L;
       const double sc = 1.0 / S.beta[lz_ib(S, r, t0 + t)];
       const double ht = cl[t];
-      EW_LOOP(q) {
-        const long e = base + (long)q * kEwThreads;
-        if (e < L) acc[q] -= ht * (double)(T)((double)vt[e] * sc);
-      }
+      double xv[kEwPerThread];
+      EW_LOOP(q) xv[q] = (double)vt[min(base + (long)q * kEwThreads, L - 1)];
+      EW_LOOP(q) acc[q] -= ht * ((base + (long)q * kEwThreads < L) ? (double)(T)(xv[q] * sc) : 0.0);
     }
   }
   double nrm = 0.0;
   EW_LOOP(q) {
     const long e = base + (long)q * kEwThreads;
-    if (e < L) {
-      const T t = (T)acc[q];
-      w[e] = t;
-      nrm += ip_weight(S, e) * (double)t * (double)t;
-    }
+    const T t = (T)acc[q];
+    if (e < L) w[e] = t;
+    const double tm = (e < L) ? (double)t : 0.0;
+    nrm += ip_weight(S, e) * tm * tm;
   }
   if (with_norm) {
     const double s = block_sum<kEwThreads>(nrm, lds);
@@ -565,25 +572,22 @@ __global__ __launch_bounds__(kEwThreads) void k_combine(const T* __restrict__ V,
       for (; t + 3 < tn; t += 4) {
         const T* v0 = V + (size_t)(t0 + t) * vs + voff;
         double x[4][kEwPerThread];
+        // clamped indices, masked in the sums (a load behind a bounds branch waits for its own data)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          EW_LOOP(q) {
-            const long e = base + (long)q * kEwThreads;
-            x[u][q] = (e < len) ? (double)v0[(size_t)u * vs + e] : 0.0;
-          }
+          EW_LOOP(q) x[u][q] = (double)v0[(size_t)u * vs + min(base + (long)q * kEwThreads, len - 1)];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const double ct = cl[t + u];
-          EW_LOOP(q) acc[q] += ct * x[u][q];
+          EW_LOOP(q) acc[q] += ct * ((base + (long)q * kEwThreads < len) ? x[u][q] : 0.0);   // fused, as before
         }
       }
       for (; t < tn; ++t) {
         const T* vt = V + (size_t)(t0 + t) * vs + voff;
         const double ct = cl[t];
-        EW_LOOP(q) {
-          const long e = base + (long)q * kEwThreads;
-          if (e < len) acc[q] += ct * (double)vt[e];
-        }
+        double xt[kEwPerThread];
+        EW_LOOP(q) xt[q] = (double)vt[min(base + (long)q * kEwThreads, len - 1)];
+        EW_LOOP(q) acc[q] += ct * ((base + (long)q * kEwThreads < len) ? xt[q] : 0.0);
       }
     }
   }
@@ -701,12 +705,20 @@ __global__ __launch_bounds__(kEwThreads) void k_accumulate(const T* __restrict__
   const T* v = Vt + (size_t)r * L;
   OutT* o = out + (size_t)r * old;
   const long base = (long)blockIdx.x * kEwChunk + threadIdx.x;
+  // both loads of every element issued first, from clamped indices (a load behind a bounds branch waits for
+  // its own data); only the stores are masked
+  double vv[kEwPerThread], ov[kEwPerThread];
+  EW_LOOP(q) vv[q] = (double)v[min(base + (long)q * kEwThreads, L - 1)];
+  if (t > 0) {
+    EW_LOOP(q) ov[q] = (double)o[min(base + (long)q * kEwThreads, L - 1)];
+  } else {
+    EW_LOOP(q) ov[q] = 0.0;
+  }
   EW_LOOP(q) {
     const long e = base + (long)q * kEwThreads;
-    if (e < L) {
-      const double cv = c * (double)v[e];
-      o[e] = t == 0 ? (OutT)(bad ? nanv : cv) : (OutT)((double)o[e] + cv);
-    }
+    const double cv = c * vv[q];
+    const OutT res = t == 0 ? (OutT)(bad ? nanv : cv) : (OutT)(ov[q] + cv);
+    if (e < L) o[e] = res;
   }
 }
 
