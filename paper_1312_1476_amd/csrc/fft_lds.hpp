@@ -148,10 +148,22 @@ __device__ __forceinline__ int xcd_col_block(int b, int nb) {
 template <typename T, int NT = kFftThreads>
 __device__ void apply_mult(C2<T>* buf, int nf, int c0, int N1, int H, const T* __restrict__ mult, T scale) {
   __syncthreads();
-  for (int idx = threadIdx.x; idx < nf * N1; idx += NT) {
-    const int k1 = idx / nf, c = idx % nf, cg = c0 + c;
-    if (cg == 0) continue;
-    const T m = mult[(size_t)k1 * mult_stride(H) + cg] * scale;
+  // at most ELEMS NT / kFftThreads values, a compile-time count per thread: every multiplier load is issued
+  // before the first is used (a load behind a bounds branch would wait for its own data)
+  constexpr int MI = FftCfg<T>::ELEMS / kFftThreads;
+  const int cnt = nf * N1;
+  T mv[MI];
+#pragma unroll
+  for (int it = 0; it < MI; ++it) {
+    const int idx = min((int)threadIdx.x + it * NT, cnt - 1);
+    const int k1 = idx / nf, cg = c0 + idx % nf;
+    mv[it] = mult[(size_t)k1 * mult_stride(H) + cg];
+  }
+#pragma unroll
+  for (int it = 0; it < MI; ++it) {
+    const int idx = (int)threadIdx.x + it * NT;
+    if (idx >= cnt || c0 + idx % nf == 0) continue;
+    const T m = mv[it] * scale;
     buf[idx] = {buf[idx].x * m, buf[idx].y * m};
   }
   if (c0 == 0) {

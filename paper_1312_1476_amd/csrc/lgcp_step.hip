@@ -79,38 +79,52 @@ __global__ __launch_bounds__(NT) void k_lgcp_rows(const C2<T>* __restrict__ T1, 
   const int row0 = 2 * np * blockIdx.x;
   const size_t fsz = (size_t)N1 * H;
   const C2<T>* src = T1 + (size_t)r * fsz;
-  // packed rows (A + i B of rows 2p, 2p+1) -> full-length sequence A + i B
-  for (int idx = threadIdx.x; idx < np * N2; idx += NT) {
+  // packed rows (A + i B of rows 2p, 2p+1) -> full-length sequence A + i B.  At most ELEMS NT / kFftThreads
+  // values, a compile-time count per thread: all loads are issued first, from the one packed index each
+  // value needs (a load behind a branch would wait for its own data), and the cases are selects.
+  constexpr int MI = FftCfg<T>::ELEMS / kFftThreads;
+  const int cnt = np * N2;
+  C2<T> ra[MI], rb[MI];
+#pragma unroll
+  for (int it = 0; it < MI; ++it) {
+    const int idx = min((int)threadIdx.x + it * NT, cnt - 1);
     const int p = idx / N2, k = idx % N2;
+    const int ks = (k == 0 || k == H) ? 0 : (k < H ? k : N2 - k);
     const C2<T>* PA = src + (size_t)(row0 + 2 * p) * H;
-    const C2<T>* PB = PA + H;
-    C2<T> a, b;
-    if (k == 0) {
-      a = {PA[0].x, (T)0};
-      b = {PB[0].x, (T)0};
-    } else if (k == H) {
-      a = {PA[0].y, (T)0};
-      b = {PB[0].y, (T)0};
-    } else if (k < H) {
-      a = PA[k];
-      b = PB[k];
-    } else {
-      a = {PA[N2 - k].x, -PA[N2 - k].y};
-      b = {PB[N2 - k].x, -PB[N2 - k].y};
-    }
-    buf[p * N2 + k] = {a.x - b.y, a.y + b.x};
+    ra[it] = PA[ks];
+    rb[it] = PA[H + ks];
+  }
+#pragma unroll
+  for (int it = 0; it < MI; ++it) {
+    const int idx = (int)threadIdx.x + it * NT;
+    if (idx >= cnt) continue;
+    const int k = idx % N2;
+    const C2<T> a = k == 0 ? C2<T>{ra[it].x, (T)0} : k == H ? C2<T>{ra[it].y, (T)0}
+                  : k < H ? ra[it] : C2<T>{ra[it].x, -ra[it].y};
+    const C2<T> b = k == 0 ? C2<T>{rb[it].x, (T)0} : k == H ? C2<T>{rb[it].y, (T)0}
+                  : k < H ? rb[it] : C2<T>{rb[it].x, -rb[it].y};
+    buf[idx] = {a.x - b.y, a.y + b.x};
   }
   __syncthreads();
   lds_fft<T, false, kRowsEarlyTw<T>, NT>(buf, N2, np, N2, 1, tw, true);
   // y = (1 / (beta_{j-1} sqrt n)) * (real rows), u = H y, partial y^T H y
   const T sc = (T)(s_cur * inv_sqrt_n);
   double acc = 0.0;
-  for (int idx = threadIdx.x; idx < np * N2; idx += NT) {
-    const int p = idx / N2, t = idx % N2;
-    const size_t ra = (size_t)(row0 + 2 * p) * N2;
+  T da[MI], db[MI];
+#pragma unroll
+  for (int it = 0; it < MI; ++it) {
+    const int idx = min((int)threadIdx.x + it * NT, cnt - 1);
+    const size_t rr = (size_t)(row0 + 2 * (idx / N2)) * N2 + idx % N2;
+    da[it] = d[rr];
+    db[it] = d[rr + N2];
+  }
+#pragma unroll
+  for (int it = 0; it < MI; ++it) {
+    const int idx = (int)threadIdx.x + it * NT;
+    if (idx >= cnt) continue;
     const C2<T> z = buf[idx];
     const T ya = z.x * sc, yb = z.y * sc;
-    const T ua = d[ra + t] * ya, ub = d[ra + N2 + t] * yb;
+    const T ua = da[it] * ya, ub = db[it] * yb;
     acc += (double)ya * (double)ua + (double)yb * (double)ub;
     buf[idx] = {ua, ub};
   }
@@ -173,9 +187,22 @@ __global__ __launch_bounds__(NT) void k_lgcp_cols(const C2<T>* __restrict__ X, c
     s_prev = j > 1 ? 1.0 / sh[2] : 0.0;
     bprev = j > 1 ? sh[1] : 0.0;
   }
-  for (int idx = threadIdx.x; idx < nf * N1; idx += NT) {
-    const int k1 = idx / nf, c = idx % nf;
-    buf[idx] = X[foff + (size_t)k1 * H + c0 + c];
+  // at most ELEMS NT / kFftThreads values, a compile-time count per thread: every load of a loop is issued
+  // before the first is used (a load behind a bounds branch would wait for its own data)
+  constexpr int MI = FftCfg<T>::ELEMS / kFftThreads;
+  const int cnt = nf * N1;
+  {
+    C2<T> xv[MI];
+#pragma unroll
+    for (int it = 0; it < MI; ++it) {
+      const int idx = min((int)threadIdx.x + it * NT, cnt - 1);
+      xv[it] = X[foff + (size_t)(idx / nf) * H + c0 + idx % nf];
+    }
+#pragma unroll
+    for (int it = 0; it < MI; ++it) {
+      const int idx = (int)threadIdx.x + it * NT;
+      if (idx < cnt) buf[idx] = xv[it];
+    }
   }
   if (MODE == 1) {
     __syncthreads();
@@ -183,7 +210,7 @@ __global__ __launch_bounds__(NT) void k_lgcp_cols(const C2<T>* __restrict__ X, c
     apply_mult<T, NT>(buf, nf, c0, N1, H, mult, (T)inv_sqrt_n);
     const T sc = (T)s_cur, sp = (T)s_prev, al = (T)alpha, bp = (T)bprev;
     double nb = 0.0, nc = 0.0;
-    for (int idx = threadIdx.x; idx < nf * N1; idx += NT) {
+    for (int idx = threadIdx.x; idx < cnt; idx += NT) {
       const int k1 = idx / nf, c = idx % nf;
       const size_t g = foff + (size_t)k1 * H + c0 + c;
       const C2<T> xv = Vj[g];
