@@ -29,10 +29,22 @@ __global__ __launch_bounds__(kFftThreads) void k_rows_r2c(const Tin* __restrict_
   const int H = N2 / 2;
   const int row0 = 2 * np * blockIdx.x;
   const Tin* src = in + (size_t)r * ild;
-  for (int idx = threadIdx.x; idx < np * N2; idx += kFftThreads) {
-    const int p = idx / N2, t = idx % N2;
-    const size_t ra = (size_t)(row0 + 2 * p) * N2;
-    buf[p * N2 + t] = {(T)src[ra + t], (T)src[ra + N2 + t]};
+  // at most ELEMS values, a compile-time count per thread: every load is issued before the first is used
+  // (one load per loop iteration would wait for its own data)
+  constexpr int MI = FftCfg<T>::ELEMS / kFftThreads;
+  const int cnt = np * N2;
+  Tin sa[MI], sb[MI];
+#pragma unroll
+  for (int it = 0; it < MI; ++it) {
+    const int idx = min((int)threadIdx.x + it * kFftThreads, cnt - 1);
+    const size_t ra = (size_t)(row0 + 2 * (idx / N2)) * N2 + idx % N2;
+    sa[it] = src[ra];
+    sb[it] = src[ra + N2];
+  }
+#pragma unroll
+  for (int it = 0; it < MI; ++it) {
+    const int idx = (int)threadIdx.x + it * kFftThreads;
+    if (idx < cnt) buf[idx] = {(T)sa[it], (T)sb[it]};
   }
   __syncthreads();
   lds_fft<T, false>(buf, N2, np, N2, 1, tw, false);
@@ -69,25 +81,30 @@ __global__ __launch_bounds__(kFftThreads) void k_rows_c2r(const C2<T>* __restric
   const int H = N2 / 2;
   const int row0 = 2 * np * blockIdx.x;
   const C2<T>* src = in + (size_t)r * ild;
-  for (int idx = threadIdx.x; idx < np * N2; idx += kFftThreads) {
+  // packed rows -> A + i B: every load issued first, from the one packed index each value needs (a load
+  // behind a branch waits for its own data); the four cases are selects
+  constexpr int MI = FftCfg<T>::ELEMS / kFftThreads;
+  const int cnt = np * N2;
+  C2<T> ra[MI], rb[MI];
+#pragma unroll
+  for (int it = 0; it < MI; ++it) {
+    const int idx = min((int)threadIdx.x + it * kFftThreads, cnt - 1);
     const int p = idx / N2, k = idx % N2;
+    const int ks = (k == 0 || k == H) ? 0 : (k < H ? k : N2 - k);
     const C2<T>* PA = src + (size_t)(row0 + 2 * p) * H;
-    const C2<T>* PB = PA + H;
-    C2<T> a, b;
-    if (k == 0) {
-      a = {PA[0].x, (T)0};
-      b = {PB[0].x, (T)0};
-    } else if (k == H) {
-      a = {PA[0].y, (T)0};
-      b = {PB[0].y, (T)0};
-    } else if (k < H) {
-      a = PA[k];
-      b = PB[k];
-    } else {
-      a = {PA[N2 - k].x, -PA[N2 - k].y};
-      b = {PB[N2 - k].x, -PB[N2 - k].y};
-    }
-    buf[p * N2 + k] = {a.x - b.y, a.y + b.x};   // A + i B
+    ra[it] = PA[ks];
+    rb[it] = PA[H + ks];
+  }
+#pragma unroll
+  for (int it = 0; it < MI; ++it) {
+    const int idx = (int)threadIdx.x + it * kFftThreads;
+    if (idx >= cnt) continue;
+    const int k = idx % N2;
+    const C2<T> a = k == 0 ? C2<T>{ra[it].x, (T)0} : k == H ? C2<T>{ra[it].y, (T)0}
+                  : k < H ? ra[it] : C2<T>{ra[it].x, -ra[it].y};
+    const C2<T> b = k == 0 ? C2<T>{rb[it].x, (T)0} : k == H ? C2<T>{rb[it].y, (T)0}
+                  : k < H ? rb[it] : C2<T>{rb[it].x, -rb[it].y};
+    buf[idx] = {a.x - b.y, a.y + b.x};   // A + i B
   }
   __syncthreads();
   lds_fft<T, false>(buf, N2, np, N2, 1, tw, true);
@@ -118,9 +135,21 @@ __global__ __launch_bounds__(kFftThreads) void k_cols(const C2<T>* __restrict__ 
   const int c0 = xcd_col_block(blockIdx.x, gridDim.x) * nf;
   const size_t fsz = (size_t)N1 * H;   // complex values per field
   const C2<T>* src = in + (size_t)r * fsz;
-  for (int idx = threadIdx.x; idx < nf * N1; idx += kFftThreads) {
-    const int k1 = idx / nf, c = idx % nf;
-    buf[idx] = src[(size_t)k1 * H + c0 + c];
+  {
+    // every load issued before the first is used (one load per loop iteration would wait for its own data)
+    constexpr int MI = FftCfg<T>::ELEMS / kFftThreads;
+    const int cnt = nf * N1;
+    C2<T> xv[MI];
+#pragma unroll
+    for (int it = 0; it < MI; ++it) {
+      const int idx = min((int)threadIdx.x + it * kFftThreads, cnt - 1);
+      xv[it] = src[(size_t)(idx / nf) * H + c0 + idx % nf];
+    }
+#pragma unroll
+    for (int it = 0; it < MI; ++it) {
+      const int idx = (int)threadIdx.x + it * kFftThreads;
+      if (idx < cnt) buf[idx] = xv[it];
+    }
   }
   if (MODE == kColInvOut) apply_mult(buf, nf, c0, N1, H, mult, scale);
   else __syncthreads();
