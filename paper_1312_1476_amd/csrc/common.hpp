@@ -132,7 +132,6 @@ __device__ __forceinline__ double dpp(double v) {
 }
 constexpr int kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141, kDppQuadXor2 = 0x4E, kDppQuadXor1 = 0xB1;
 
-
 // Sum over the wave of 16 values per lane with no lane-dependent selects: afterwards every lane of 16-lane
 // row q (q = lane / 16) holds in v[i], i < 4, the total of value 4 q + i (v_permlane32_swap pairs the
 // halves, v_permlane16_swap the rows, then a row mirror, a half-row mirror and two quad permutes).
@@ -213,16 +212,6 @@ __device__ __forceinline__ bool block_active(const LzState& S, int r, int* lds_f
   return lds_flag[0] != 0;
 }
 
-// Scalar step that opens iteration j for RHS r (Algorithm 1 with the Theorem 1 stopping
-// quantity).  Every block working on RHS r calls it with identical inputs and so reaches
-// the same decision; only `writer` stores it.  For j >= 2 it finishes iteration j-1:
-//   beta_{j-1} = ||w_{j-1}|| from the partial sums, d_{j-1} = alpha_{j-1} - beta_{j-2}^2/d_{j-2},
-//   rho_{j-1} = rho_{j-2} beta_{j-1} / d_{j-1}; stop on non-positive alpha or pivot
-//   (not SPD), on breakdown beta_{j-1} <= 64 eps (|alpha_{j-1}| + beta_{j-2}), or on
-//   rho_{j-1} <= tol.  For j = 1 it forms beta_0 = ||z|| (zero z: x = 0 with m = 0;
-//   non-finite z: EINVAL).  With j = m_max + 1 it also closes a run that hit m_max.
-// On continuation it returns s_cur = 1/beta_{j-1} (scale of slot j-1, giving v_j),
-// s_prev = 1/beta_{j-2} (slot j-2, giving v_{j-1}) and bprev = beta_{j-1}.
 // The loads of the scalar step for column r, all issued before any wait: active[r] (by one thread, broadcast
 // with the partial sums' block reduction), this thread's share of the ||w_{j-1}||^2 partials (summed in
 // sum_partials' order), and the scalars of iteration j-1, which no block of this launch writes.
@@ -306,6 +295,16 @@ __device__ __forceinline__ bool lz_decide(const LzState& S, int r, int j, bool w
   return true;
 }
 
+// Scalar step that opens iteration j for RHS r (Algorithm 1 with the Theorem 1 stopping
+// quantity).  Every block working on RHS r calls it with identical inputs and so reaches
+// the same decision; only `writer` stores it.  For j >= 2 it finishes iteration j-1:
+//   beta_{j-1} = ||w_{j-1}|| from the partial sums, d_{j-1} = alpha_{j-1} - beta_{j-2}^2/d_{j-2},
+//   rho_{j-1} = rho_{j-2} beta_{j-1} / d_{j-1}; stop on non-positive alpha or pivot
+//   (not SPD), on breakdown beta_{j-1} <= 64 eps (|alpha_{j-1}| + beta_{j-2}), or on
+//   rho_{j-1} <= tol.  For j = 1 it forms beta_0 = ||z|| (zero z: x = 0 with m = 0;
+//   non-finite z: EINVAL).  With j = m_max + 1 it also closes a run that hit m_max.
+// On continuation it returns s_cur = 1/beta_{j-1} (scale of slot j-1, giving v_j),
+// s_prev = 1/beta_{j-2} (slot j-2, giving v_{j-1}) and bprev = beta_{j-1}.
 template <int NT>
 __device__ bool lz_open(const LzState& S, int r, int j, bool writer, double* lds, int* lds_flag,
                         double& s_cur, double& s_prev, double& bprev) {

@@ -311,11 +311,12 @@ __global__ __launch_bounds__(kEwThreads) void k_reorth_update(T* __restrict__ V,
 //   MODE 1  w -= sum_t h_t v_{t+1}, h_t the sum of MODE 0's block partials, then the dots of the result
 //           (the second pass);
 //   MODE 2  the same update with the second pass's h_t, then the partial sums of ||w||^2.
-// These kernels are bound by the latency of dependent memory accesses (about 1.5 us each here), so every
-// load a sweep needs is issued at its start, and with j <= 128 the dots of MODE 1 take the basis values its
-// update loaded: one round of loads per launch.  Sums over lanes take the 16 values of a wave's share at
-// once (wave_sum16: lane swaps and DPP permutes, no lane-dependent selects, which the compiler would turn
-// into indexed register reads).  An element's update is summed per wave in t order, then over the waves in
+// Each launch re-reads its share of the basis and the other blocks' dot partials from beyond L2 (on a 64^2
+// lattice about 80 KB per block at j = 81), so every load a sweep needs is issued at its start, and with
+// j <= 128 the dots of MODE 1 take the basis values its update loaded: one round of loads per launch.  The
+// 64-element chunks balance the two kinds of traffic (8 j (L / P + P) bytes per block, least at P = sqrt L).
+// Sums over lanes take the 16 values of a wave's share at once (wave_sum16: lane swaps and DPP permutes; a
+// select between register-array elements chosen by lane compiles to compare-and-select chains).  An element's update is summed per wave in t order, then over the waves in
 // wave order through LDS.  Every sum has a fixed order, so results are bitwise reproducible.
 constexpr int kCsThreads = 512;
 constexpr int kCsWaves = kCsThreads / kWave;
