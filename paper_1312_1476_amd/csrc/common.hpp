@@ -323,6 +323,45 @@ __device__ bool lz_open(const LzState& S, int r, int j, bool writer, double* lds
   return lz_decide(S, r, j, writer, bsq, o, s_cur, s_prev, bprev);
 }
 
+// lz_open plus the sums of two more sets of P_a partials of column r (sum_partials' order), all loaded
+// before the first wait and reduced under the same two barriers: qa from pa, qc from pc (0 without pc).
+// lds: 3 * NT / 64 doubles.
+template <int NT>
+__device__ bool lz_open_with(const LzState& S, int r, int j, bool writer, double* lds, int* lds_flag,
+                             const double* pa, const double* pc, double& s_cur, double& s_prev, double& bprev,
+                             double& qa, double& qc) {
+  constexpr int NW = NT / kWave;
+  const int tid = (int)threadIdx.x;
+  const LzOpenIn o = lz_open_load<NT>(S, r, j);
+  const int Pa = lz_pa(S, r);
+  double sa = 0.0, sc = 0.0;
+  for (int i = tid; i < Pa; i += NT) sa += pa[i];
+  if (pc)
+    for (int i = tid; i < Pa; i += NT) sc += pc[i];
+  const double ps = wave_sum(o.ps);
+  sa = wave_sum(sa);
+  sc = wave_sum(sc);
+  __syncthreads();
+  if ((tid & (kWave - 1)) == 0) {
+    lds[tid / kWave] = ps;
+    lds[NW + tid / kWave] = sa;
+    lds[2 * NW + tid / kWave] = sc;
+  }
+  if (tid == 0) lds_flag[0] = o.act0;
+  __syncthreads();
+  if (!lds_flag[0]) return false;
+  double bsq = 0.0;
+  qa = 0.0;
+  qc = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    bsq += lds[i];
+    qa += lds[NW + i];
+    qc += lds[2 * NW + i];
+  }
+  return lz_decide(S, r, j, writer, bsq, o, s_cur, s_prev, bprev);
+}
+
 // lz_open for the KB columns r0 .. r0 + KB - 1 (those below k) of one block at once: every column's loads
 // are issued before the first wait and the reductions share two barriers.  lds: KB * NT / 64 doubles,
 // lds_flag: KB ints.  act[c] is true on return where column r0 + c continues.
