@@ -323,21 +323,21 @@ __device__ bool lz_open(const LzState& S, int r, int j, bool writer, double* lds
   return lz_decide(S, r, j, writer, bsq, o, s_cur, s_prev, bprev);
 }
 
-// lz_open plus the sums of two more sets of P_a partials of column r (sum_partials' order), all loaded
-// before the first wait and reduced under the same two barriers: qa from pa, qc from pc (0 without pc).
+// lz_open plus the sums of up to two more partial sets of column r (pa: Pa values, pc: Pc values; nullptr:
+// 0), in sum_partials' order, all loaded before the first wait and reduced under the same two barriers.
 // lds: 3 * NT / 64 doubles.
 template <int NT>
 __device__ bool lz_open_with(const LzState& S, int r, int j, bool writer, double* lds, int* lds_flag,
-                             const double* pa, const double* pc, double& s_cur, double& s_prev, double& bprev,
-                             double& qa, double& qc) {
+                             const double* pa, int Pa, const double* pc, int Pc, double& s_cur, double& s_prev,
+                             double& bprev, double& qa, double& qc) {
   constexpr int NW = NT / kWave;
   const int tid = (int)threadIdx.x;
   const LzOpenIn o = lz_open_load<NT>(S, r, j);
-  const int Pa = lz_pa(S, r);
   double sa = 0.0, sc = 0.0;
-  for (int i = tid; i < Pa; i += NT) sa += pa[i];
+  if (pa)
+    for (int i = tid; i < Pa; i += NT) sa += pa[i];
   if (pc)
-    for (int i = tid; i < Pa; i += NT) sc += pc[i];
+    for (int i = tid; i < Pc; i += NT) sc += pc[i];
   const double ps = wave_sum(o.ps);
   sa = wave_sum(sa);
   sc = wave_sum(sc);
@@ -360,6 +360,32 @@ __device__ bool lz_open_with(const LzState& S, int r, int j, bool writer, double
     qc += lds[2 * NW + i];
   }
   return lz_decide(S, r, j, writer, bsq, o, s_cur, s_prev, bprev);
+}
+
+// The update step's scalars of column r at step j, loaded together: active[r] (one thread, broadcast),
+// alpha_j = the sum of the operator's Pa partials (sum_partials' order) and beta_{j-1}.  lds: NT / 64
+// doubles.  Returns false for a column that has stopped.
+template <int NT>
+__device__ bool lz_update_scalars(const LzState& S, int r, int j, double* lds, int* lds_flag, double& a,
+                                  double& bj1) {
+  constexpr int NW = NT / kWave;
+  const int tid = (int)threadIdx.x;
+  const int act0 = (tid == 0) ? S.active[r] : 0;
+  bj1 = S.beta[lz_ib(S, r, j - 1)];
+  const double* pa = S.part_a + (size_t)r * S.pstride;
+  const int Pa = lz_pa(S, r);
+  double sa = 0.0;
+  for (int i = tid; i < Pa; i += NT) sa += pa[i];
+  sa = wave_sum(sa);
+  __syncthreads();
+  if ((tid & (kWave - 1)) == 0) lds[tid / kWave] = sa;
+  if (tid == 0) lds_flag[0] = act0;
+  __syncthreads();
+  if (!lds_flag[0]) return false;
+  a = 0.0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) a += lds[i];
+  return true;
 }
 
 // lz_open for the KB columns r0 .. r0 + KB - 1 (those below k) of one block at once: every column's loads

@@ -160,10 +160,10 @@ __global__ __launch_bounds__(kEwThreads) void k_update(const T* __restrict__ Qb,
     va[qq] = vj[ec];
     qa[qq] = q[ec];
   }
-  if (!block_active(S, r, flag)) return;
-  const double a = sum_partials<kEwThreads>(S.part_a + (size_t)r * S.pstride, lz_pa(S, r), lds);
+  double a, bj1;
+  if (!lz_update_scalars<kEwThreads>(S, r, j, lds, flag, a, bj1)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) S.alpha[lz_ia(S, r, j)] = a;
-  const double sc = 1.0 / S.beta[lz_ib(S, r, j - 1)];
+  const double sc = 1.0 / bj1;
   double acc = 0.0;
   EW_LOOP(qq) {
     const long e = base + (long)qq * kEwThreads;

@@ -65,16 +65,17 @@ __global__ __launch_bounds__(NT) void k_lgcp_rows(const C2<T>* __restrict__ T1, 
                                                            const C2<T>* __restrict__ tw, LzState S, int j,
                                                            int use_c, int Pc, double inv_sqrt_n) {
   __shared__ C2<T> buf[FftCfg<T>::ELEMS * NT / kFftThreads];
-  __shared__ double red[NT / kWave];
+  __shared__ double red[3 * (NT / kWave)];   // lz_open_with takes three sets
   __shared__ int flag;
   const int r = blockIdx.y;
   const bool writer = blockIdx.x == 0;
-  double s_cur, s_prev, bprev;
-  if (!lz_open<NT>(S, r, j, writer, red, &flag, s_cur, s_prev, bprev)) return;
-  if (writer) {
-    const double c = (use_c && j > 1) ? sum_partials<NT>(S.part_c + (size_t)r * S.pstride, Pc, red) : 0.0;
-    if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + gridDim.x] = c;
-  }
+  double s_cur, s_prev, bprev, qa, c;
+  // the <w_{j-1}, v_{j-1}> partials (the writer's) load with the opener's
+  const bool with_c = writer && use_c && j > 1;
+  if (!lz_open_with<NT>(S, r, j, writer, red, &flag, nullptr, 0, with_c ? S.part_c + (size_t)r * S.pstride : nullptr,
+                        Pc, s_cur, s_prev, bprev, qa, c))
+    return;
+  if (writer && threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + gridDim.x] = c;
   const int H = N2 / 2;
   const int row0 = 2 * np * blockIdx.x;
   const size_t fsz = (size_t)N1 * H;

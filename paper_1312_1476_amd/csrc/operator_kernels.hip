@@ -930,8 +930,9 @@ __global__ __launch_bounds__(256, GMRF_L2D_WAVES) void k_lanczos2d(StencilGeom g
     // the scalar step, and alpha_j from the previous pass's partial sums (fixed order; the same in every
     // block), their loads issued together
     double qf, cc;
-    if (!lz_open_with<256>(S, r, j, tile == 0, red, flag, S.part_a + (size_t)r * S.pstride,
-                           j > 1 ? S.part_c + (size_t)r * S.pstride : nullptr, s_cur, s_prev, bprev, qf, cc))
+    if (!lz_open_with<256>(S, r, j, tile == 0, red, flag, S.part_a + (size_t)r * S.pstride, lz_pa(S, r),
+                           j > 1 ? S.part_c + (size_t)r * S.pstride : nullptr, lz_pa(S, r), s_cur, s_prev, bprev,
+                           qf, cc))
       return;
     alpha = qf * s_cur * s_cur - cc;
     if (tile == 0 && threadIdx.x == 0) S.alpha[lz_ia(S, r, j)] = alpha;

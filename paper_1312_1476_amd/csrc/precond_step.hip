@@ -392,12 +392,12 @@ __global__ __launch_bounds__(kStepThreads, kStepWaves) void k_dots(const C2<T>* 
 template <int NT>
 __device__ __forceinline__ bool band_open(const LzState& S, int r, int j, int use_c, double* red, int* flag,
                                           double& s_cur) {
-  double s_prev, bprev;
-  if (!lz_open<NT>(S, r, j, blockIdx.x == 0, red, flag, s_cur, s_prev, bprev)) return false;
-  if (blockIdx.x == 2) {
-    const double c = (use_c && j > 1) ? sum_partials<NT>(S.part_c + (size_t)r * S.pstride, lz_pb(S, r), red) : 0.0;
-    if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + kBandBlocks] = c;
-  }
+  double s_prev, bprev, qa, c;
+  const bool with_c = blockIdx.x == 2 && use_c && j > 1;   // the <w_{j-1}, v_{j-1}> partials load with the opener's
+  if (!lz_open_with<NT>(S, r, j, blockIdx.x == 0, red, flag, nullptr, 0,
+                        with_c ? S.part_c + (size_t)r * S.pstride : nullptr, lz_pb(S, r), s_cur, s_prev, bprev, qa, c))
+    return false;
+  if (blockIdx.x == 2 && threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + kBandBlocks] = c;
   return true;
 }
 
@@ -466,7 +466,7 @@ __global__ __launch_bounds__(kFftThreads) void k_band_global(int N1, int N2, con
                                                       int j, int use_c, int periodic, StepIO<T> io) {
   constexpr int NT = kFftThreads;
   __shared__ C2<T> buf[FftCfg<T>::ELEMS];
-  __shared__ double red[NT / kWave];
+  __shared__ double red[3 * (NT / kWave)];   // lz_open_with takes three sets
   __shared__ int flag[1];
   const int r = blockIdx.y;
   double s_cur;
@@ -727,7 +727,7 @@ __global__ __launch_bounds__(kFftThreads) void k_band_lds(int N1, int N2, const 
   __shared__ C2<T> buf[EX];
   __shared__ C2<T> aux[EX];
   __shared__ C2<T> tl1[TWL], tl2[TWL];
-  __shared__ double red[NT / kWave];
+  __shared__ double red[3 * (NT / kWave)];   // lz_open_with takes three sets
   __shared__ int flag[1];
   const int r = blockIdx.y;
   const int tid = threadIdx.x;
