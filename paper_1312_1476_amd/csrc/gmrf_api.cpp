@@ -576,6 +576,7 @@ gmrf_status upload_trsv(const std::vector<int64_t>& rp, const std::vector<int32_
                         const std::vector<double>& diag, const std::vector<int32_t>& lvl_ptr,
                         const std::vector<int32_t>& lvl_rows, int storage, TrsvDev& d) {
   const size_t n = lvl_rows.size();
+  d.max_row = 0;
   std::vector<int64_t> prp(n + 1, 0);
   std::vector<int32_t> pci;
   std::vector<double> pva, pdinv(n);
@@ -589,6 +590,7 @@ gmrf_status upload_trsv(const std::vector<int64_t>& rp, const std::vector<int32_
     }
     prp[p + 1] = (int64_t)pci.size();
     pdinv[p] = 1.0 / diag[(size_t)i];
+    d.max_row = std::max(d.max_row, (int)(prp[p + 1] - prp[p]));
   }
   gmrf_status s;
   if ((s = upload(lvl_ptr, &d.lvl_ptr)) != GMRF_OK || (s = upload(lvl_rows, &d.rows)) != GMRF_OK ||

@@ -38,6 +38,7 @@ struct TrsvDev {
   void* dinv = nullptr;
   int nlev = 0;
   int64_t nnz = 0;      // strictly-triangular entries
+  int max_row = 0;      // most strictly-triangular entries in one row
 };
 struct IcholDev {
   TrsvDev fwd, bwd;     // L y = b, L^T x = y

@@ -14,8 +14,45 @@ constexpr size_t kTrsvLdsMaxBytes = 160 * 1024;   // whole solve in LDS up to th
 
 // x = T^{-1} b, T = D + N with N strictly triangular, stored in level order (TrsvDev).  Only the x
 // values carry the dependency between levels; every row's indices and values are known in advance.
+// G lanes share a row: lane g takes the row's entries g, g + G, ..., four of them per round with all
+// loads issued before the sums, and the G partial sums are added across the lanes by DPP (lane 0 of
+// the group starts from b_i).  G = 1 is one thread per row with the entries summed in order.  The
+// level's rows go in passes of kTrsvThreads / G.
+template <int G>
+__device__ __forceinline__ double trsv_group_sum(double v) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "a lane group lies within one DPP row");
+  if (G >= 2) v += dpp<kDppQuadXor1>(v);
+  if (G >= 4) v += dpp<kDppQuadXor2>(v);
+  if (G >= 8) v += dpp<kDppRowHalfMirror>(v);
+  if (G >= 16) v += dpp<kDppRowMirror>(v);
+  return v;
+}
+
+// s -= sum over the entries q of the row taken by lane g (g, g + G, ... below q1) of va[q] x[ci[q]]; an
+// entry past the row's end is loaded from the round's first entry (in range) and counts with value 0.
+template <int G, typename Idx, typename LoadC, typename LoadV, typename LoadX>
+__device__ __forceinline__ double trsv_row(double s, Idx q0, Idx q1, int g, LoadC lc, LoadV lv_, LoadX lx) {
+  for (Idx e = q0 + g; e < q1; e += 4 * G) {
+    int c[4];
+    double xv[4], lv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const Idx eu = e + u * G;
+      const Idx ec = eu < q1 ? eu : e;
+      c[u] = lc(ec);
+      const double v = lv_(ec);
+      lv[u] = eu < q1 ? v : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xv[u] = lx(c[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s -= lv[u] * xv[u];
+  }
+  return s;
+}
+
 // XLDS: x lives in LDS (n <= kTrsvLdsRows) and is written out once at the end.
-template <typename T, typename OutT, bool XLDS>
+template <typename T, typename OutT, bool XLDS, int G>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv_levels(const int32_t* __restrict__ lvl_ptr,
                                                               const int32_t* __restrict__ rows,
                                                               const int64_t* __restrict__ rp,
@@ -28,30 +65,26 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_levels(const int32_t* __r
   if (active && !active[r]) return;   // one value per block: the whole block returns or none does
   const T* b = B + (size_t)r * bld;
   OutT* x = X + (size_t)r * xld;
+  const int g = (int)threadIdx.x % G;
   for (int lev = 0; lev < nlev; ++lev) {
     const int e0 = lvl_ptr[lev], e1 = lvl_ptr[lev + 1];
-    for (int p = e0 + (int)threadIdx.x; p < e1; p += kTrsvThreads) {
-      const int i = rows[p];
-      double s = (double)b[i];
-      const int64_t q1 = rp[p + 1];
-      int64_t e = rp[p];
-      for (; e + 3 < q1; e += 4) {   // four entries' loads issued before the sums (same order)
-        int c[4];
-        double xv[4], lv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          c[u] = ci[e + u];
-          lv[u] = (double)va[e + u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) xv[u] = XLDS ? xs[c[u]] : (double)x[c[u]];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) s -= lv[u] * xv[u];
+    for (int pb = e0; pb < e1; pb += kTrsvThreads / G) {   // the same trip count in every lane
+      const int p = pb + (int)threadIdx.x / G;
+      const bool live = p < e1;
+      const int pc = live ? p : e0;   // a lane past the level's end works on its first row and writes nothing
+      const int i = rows[pc];
+      const int64_t q0 = rp[pc], q1 = live ? rp[pc + 1] : q0;
+      const double bi = (double)b[i];
+      double s = g == 0 ? bi : 0.0;
+      s = trsv_row<G>(s, q0, q1, g, [&](int64_t q) { return ci[q]; }, [&](int64_t q) { return (double)va[q]; },
+                      [&](int c) { return XLDS ? xs[c] : (double)x[c]; });
+      s = trsv_group_sum<G>(s);
+      const double di = (double)dinv[pc];
+      if (live && g == 0) {
+        s *= di;
+        if (XLDS) xs[i] = s;
+        else x[i] = (OutT)s;
       }
-      for (; e < q1; ++e) s -= (double)va[e] * (XLDS ? xs[ci[e]] : (double)x[ci[e]]);
-      s *= (double)dinv[p];
-      if (XLDS) xs[i] = s;
-      else x[i] = (OutT)s;
     }
     __syncthreads();   // this level's x are visible to the block before the next level reads them
   }
@@ -61,9 +94,9 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_levels(const int32_t* __r
 
 // The same solve with the whole factor in LDS as well (values, column indices, row starts, level
 // pointers and 1 / l_ii), staged once per block: every level's loads are then LDS loads, not two
-// dependent L2 round trips.  x starts as b in LDS (a row's own entry is read only by itself).  Same
-// arithmetic in the same order as k_trsv_levels.
-template <typename T, typename OutT>
+// dependent L2 round trips.  x starts as b in LDS (a row's own entry is read only by its own lane
+// group).  Same arithmetic in the same order as k_trsv_levels with the same G.
+template <typename T, typename OutT, int G>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __restrict__ lvl_ptr,
                                                            const int32_t* __restrict__ rows,
                                                            const int64_t* __restrict__ rp,
@@ -95,28 +128,22 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __rest
   }
   for (int l = threadIdx.x; l <= nlev; l += kTrsvThreads) slv[l] = lvl_ptr[l];
   __syncthreads();
+  const int g = (int)threadIdx.x % G;
   for (int lev = 0; lev < nlev; ++lev) {
     const int e0 = slv[lev], e1 = slv[lev + 1];
-    for (int p = e0 + (int)threadIdx.x; p < e1; p += kTrsvThreads) {
-      const int i = srow[p];
-      double s = xs[i];
-      const int q1 = srp[p + 1];
-      int e = srp[p];
-      for (; e + 3 < q1; e += 4) {   // four entries' index and x loads issued before the sums (same order)
-        int c[4];
-        double xv[4], lv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) c[u] = sci[e + u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          xv[u] = xs[c[u]];
-          lv[u] = (double)sv[e + u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) s -= lv[u] * xv[u];
-      }
-      for (; e < q1; ++e) s -= (double)sv[e] * xs[sci[e]];
-      xs[i] = s * (double)sd[p];
+    for (int pb = e0; pb < e1; pb += kTrsvThreads / G) {   // the same trip count in every lane
+      const int p = pb + (int)threadIdx.x / G;
+      const bool live = p < e1;
+      const int pc = live ? p : e0;   // a lane past the level's end works on its first row and writes nothing
+      const int i = srow[pc];
+      const int q0 = srp[pc], q1 = live ? srp[pc + 1] : q0;
+      const double bi = xs[i];
+      double s = g == 0 ? bi : 0.0;
+      s = trsv_row<G>(s, q0, q1, g, [&](int q) { return sci[q]; }, [&](int q) { return (double)sv[q]; },
+                      [&](int c) { return xs[c]; });
+      s = trsv_group_sum<G>(s);
+      const double di = (double)sd[pc];
+      if (live && g == 0) xs[i] = s * di;
     }
     __syncthreads();   // this level's x are visible to the block before the next level reads them
   }
@@ -159,32 +186,48 @@ __global__ __launch_bounds__(kEwThreads) void k_pre_lz(const T* __restrict__ AX,
   if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + blockIdx.x] = s;
 }
 
-template <typename T, typename OutT>
-void launch_trsv(const IcholDev& f, bool upper, const T* B, long bld, OutT* X, long xld, const int* active, int k,
-                 hipStream_t st) {
-  const TrsvDev& d = upper ? f.bwd : f.fwd;
+// Lanes per row for a factor whose longest row holds max_row strictly-triangular entries: one round
+// of four loads per lane covers rows of up to 4 G entries.
+static int trsv_group(int max_row) { return max_row <= 4 ? 1 : max_row <= 16 ? 4 : 16; }
+
+template <typename T, typename OutT, int G>
+static void launch_trsv_g(const IcholDev& f, const TrsvDev& d, const T* B, long bld, OutT* X, long xld,
+                          const int* active, int k, hipStream_t st) {
   const size_t lb = trsv_lds_bytes<T>(d, f.n);
   if (lb) {
     // the launch needs more than the default dynamic LDS; set once (thread-safe static initialisation)
     static const bool attr_set = [] {
-      const bool ok = hipFuncSetAttribute((const void*)k_trsv_lds<T, OutT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          (int)kTrsvLdsMaxBytes) == hipSuccess;
+      const bool ok = hipFuncSetAttribute((const void*)k_trsv_lds<T, OutT, G>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTrsvLdsMaxBytes) ==
+                      hipSuccess;
       (void)hipGetLastError();
       return ok;
     }();
     if (attr_set || lb <= 65536) {
-      hipLaunchKernelGGL((k_trsv_lds<T, OutT>), dim3(k), dim3(kTrsvThreads), lb, st, d.lvl_ptr, d.rows, d.rp, d.ci,
-                         (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, (long)d.nnz, B, bld, X, xld, active);
+      hipLaunchKernelGGL((k_trsv_lds<T, OutT, G>), dim3(k), dim3(kTrsvThreads), lb, st, d.lvl_ptr, d.rows, d.rp,
+                         d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, (long)d.nnz, B, bld, X, xld,
+                         active);
       return;
     }
   }
   if (f.n <= kTrsvLdsRows)
-    hipLaunchKernelGGL((k_trsv_levels<T, OutT, true>), dim3(k), dim3(kTrsvThreads), (size_t)f.n * sizeof(double), st,
-                       d.lvl_ptr, d.rows, d.rp, d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, B, bld,
+    hipLaunchKernelGGL((k_trsv_levels<T, OutT, true, G>), dim3(k), dim3(kTrsvThreads), (size_t)f.n * sizeof(double),
+                       st, d.lvl_ptr, d.rows, d.rp, d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, B, bld,
                        X, xld, active);
   else
-    hipLaunchKernelGGL((k_trsv_levels<T, OutT, false>), dim3(k), dim3(kTrsvThreads), 0, st, d.lvl_ptr, d.rows, d.rp,
-                       d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, B, bld, X, xld, active);
+    hipLaunchKernelGGL((k_trsv_levels<T, OutT, false, G>), dim3(k), dim3(kTrsvThreads), 0, st, d.lvl_ptr, d.rows,
+                       d.rp, d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, B, bld, X, xld, active);
+}
+
+template <typename T, typename OutT>
+void launch_trsv(const IcholDev& f, bool upper, const T* B, long bld, OutT* X, long xld, const int* active, int k,
+                 hipStream_t st) {
+  const TrsvDev& d = upper ? f.bwd : f.fwd;
+  switch (trsv_group(d.max_row)) {
+    case 1: launch_trsv_g<T, OutT, 1>(f, d, B, bld, X, xld, active, k, st); break;
+    case 4: launch_trsv_g<T, OutT, 4>(f, d, B, bld, X, xld, active, k, st); break;
+    default: launch_trsv_g<T, OutT, 16>(f, d, B, bld, X, xld, active, k, st); break;
+  }
 }
 
 template <typename T>
