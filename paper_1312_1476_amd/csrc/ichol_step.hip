@@ -92,11 +92,12 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_levels(const int32_t* __r
     for (long i = threadIdx.x; i < n; i += kTrsvThreads) x[i] = (OutT)xs[i];
 }
 
-// The same solve with the whole factor in LDS as well (values, column indices, row starts, level
-// pointers and 1 / l_ii), staged once per block: every level's loads are then LDS loads, not two
-// dependent L2 round trips.  x starts as b in LDS (a row's own entry is read only by its own lane
-// group).  Same arithmetic in the same order as k_trsv_levels with the same G.
-template <typename T, typename OutT, int G>
+// The same solve with the factor's tables in LDS (row starts, rows, level pointers and 1 / l_ii),
+// staged once per block, and with VLDS the entries too (values and column indices): every level's
+// loads are then LDS loads, or without VLDS one L2 round for the entries, instead of three dependent
+// rounds.  x starts as b in LDS (a row's own entry is read only by its own lane group).  Same
+// arithmetic in the same order as k_trsv_levels with the same G.
+template <typename T, typename OutT, int G, bool VLDS>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __restrict__ lvl_ptr,
                                                            const int32_t* __restrict__ rows,
                                                            const int64_t* __restrict__ rp,
@@ -108,12 +109,13 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __rest
   extern __shared__ double smem[];
   const int r = blockIdx.x;
   if (active && !active[r]) return;   // one value per block: the whole block returns or none does
+  const long nv = VLDS ? nnz : 0;      // entries staged in LDS
   double* xs = smem;
   T* sd = (T*)(xs + n);
   T* sv = sd + n;
-  int32_t* srp = (int32_t*)(sv + nnz);
+  int32_t* srp = (int32_t*)(sv + nv);
   int32_t* sci = srp + n + 1;
-  int32_t* srow = sci + nnz;
+  int32_t* srow = sci + nv;
   int32_t* slv = srow + n;
   const T* b = B + (size_t)r * bld;
   for (long i = threadIdx.x; i < n; i += kTrsvThreads) {
@@ -122,12 +124,14 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __rest
     srow[i] = rows[i];
   }
   for (long i = threadIdx.x; i <= n; i += kTrsvThreads) srp[i] = (int32_t)rp[i];
-  for (long e = threadIdx.x; e < nnz; e += kTrsvThreads) {
+  for (long e = threadIdx.x; e < nv; e += kTrsvThreads) {
     sv[e] = va[e];
     sci[e] = ci[e];
   }
   for (int l = threadIdx.x; l <= nlev; l += kTrsvThreads) slv[l] = lvl_ptr[l];
   __syncthreads();
+  const int32_t* fc = VLDS ? sci : ci;
+  const T* fv = VLDS ? sv : va;
   const int g = (int)threadIdx.x % G;
   for (int lev = 0; lev < nlev; ++lev) {
     const int e0 = slv[lev], e1 = slv[lev + 1];
@@ -139,7 +143,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __rest
       const int q0 = srp[pc], q1 = live ? srp[pc + 1] : q0;
       const double bi = xs[i];
       double s = g == 0 ? bi : 0.0;
-      s = trsv_row<G>(s, q0, q1, g, [&](int q) { return sci[q]; }, [&](int q) { return (double)sv[q]; },
+      s = trsv_row<G>(s, q0, q1, g, [&](int q) { return fc[q]; }, [&](int q) { return (double)fv[q]; },
                       [&](int c) { return xs[c]; });
       s = trsv_group_sum<G>(s);
       const double di = (double)sd[pc];
@@ -151,10 +155,12 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __rest
   for (long i = threadIdx.x; i < n; i += kTrsvThreads) x[i] = (OutT)xs[i];
 }
 
-// LDS bytes of k_trsv_lds for a solve (0: does not fit)
+// LDS bytes of k_trsv_lds for a solve, with the entries (VLDS) or without (0: does not fit)
 template <typename T>
-static size_t trsv_lds_bytes(const TrsvDev& d, int64_t n) {
-  const size_t b = (size_t)n * 8 + (size_t)(n + d.nnz) * sizeof(T) + (size_t)(2 * n + 1 + d.nnz + d.nlev + 1) * 4;
+static size_t trsv_lds_bytes(const TrsvDev& d, int64_t n, bool vlds) {
+  if (d.nnz >= ((int64_t)1 << 31)) return 0;   // row starts are staged as 32-bit offsets
+  const int64_t nv = vlds ? d.nnz : 0;
+  const size_t b = (size_t)n * 8 + (size_t)(n + nv) * sizeof(T) + (size_t)(2 * n + 1 + nv + d.nlev + 1) * 4;
   return b <= kTrsvLdsMaxBytes ? b : 0;
 }
 
@@ -190,26 +196,31 @@ __global__ __launch_bounds__(kEwThreads) void k_pre_lz(const T* __restrict__ AX,
 // of four loads per lane covers rows of up to 4 G entries.
 static int trsv_group(int max_row) { return max_row <= 4 ? 1 : max_row <= 16 ? 4 : 16; }
 
+// k_trsv_lds above the default dynamic LDS size needs the attribute; set once per instance
+// (thread-safe static initialisation)
+template <typename T, typename OutT, int G, bool VLDS>
+static bool trsv_lds_launch(const IcholDev& f, const TrsvDev& d, size_t lb, const T* B, long bld, OutT* X, long xld,
+                            const int* active, int k, hipStream_t st) {
+  static const bool attr_set = [] {
+    const bool ok = hipFuncSetAttribute((const void*)k_trsv_lds<T, OutT, G, VLDS>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTrsvLdsMaxBytes) ==
+                    hipSuccess;
+    (void)hipGetLastError();
+    return ok;
+  }();
+  if (!attr_set && lb > 65536) return false;
+  hipLaunchKernelGGL((k_trsv_lds<T, OutT, G, VLDS>), dim3(k), dim3(kTrsvThreads), lb, st, d.lvl_ptr, d.rows, d.rp,
+                     d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, (long)d.nnz, B, bld, X, xld, active);
+  return true;
+}
+
 template <typename T, typename OutT, int G>
 static void launch_trsv_g(const IcholDev& f, const TrsvDev& d, const T* B, long bld, OutT* X, long xld,
                           const int* active, int k, hipStream_t st) {
-  const size_t lb = trsv_lds_bytes<T>(d, f.n);
-  if (lb) {
-    // the launch needs more than the default dynamic LDS; set once (thread-safe static initialisation)
-    static const bool attr_set = [] {
-      const bool ok = hipFuncSetAttribute((const void*)k_trsv_lds<T, OutT, G>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTrsvLdsMaxBytes) ==
-                      hipSuccess;
-      (void)hipGetLastError();
-      return ok;
-    }();
-    if (attr_set || lb <= 65536) {
-      hipLaunchKernelGGL((k_trsv_lds<T, OutT, G>), dim3(k), dim3(kTrsvThreads), lb, st, d.lvl_ptr, d.rows, d.rp,
-                         d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, (long)d.nnz, B, bld, X, xld,
-                         active);
-      return;
-    }
-  }
+  size_t lb = trsv_lds_bytes<T>(d, f.n, true);
+  if (lb && trsv_lds_launch<T, OutT, G, true>(f, d, lb, B, bld, X, xld, active, k, st)) return;
+  lb = trsv_lds_bytes<T>(d, f.n, false);
+  if (lb && trsv_lds_launch<T, OutT, G, false>(f, d, lb, B, bld, X, xld, active, k, st)) return;
   if (f.n <= kTrsvLdsRows)
     hipLaunchKernelGGL((k_trsv_levels<T, OutT, true, G>), dim3(k), dim3(kTrsvThreads), (size_t)f.n * sizeof(double),
                        st, d.lvl_ptr, d.rows, d.rp, d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, B, bld,

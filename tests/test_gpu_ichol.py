@@ -123,6 +123,43 @@ def test_lattice_as_csr_ic0(gm):
         assert _rel(X[:, r], ref.x) <= 1e-8
 
 
+@pytest.mark.parametrize("n,w", [(7000, 1), (7000, 20), (9000, 6)])
+def test_banded_exact_factor_large(gm, n, w):
+    """Solves too large for the LDS-staged kernels: n = 7000 keeps x in LDS with the factor's tables in
+    global memory, n = 9000 keeps x there too.  Half-bandwidths 1 / 6 / 20 give rows for one thread,
+    4 lanes and 16 lanes.  IC(0) of a banded matrix with a full band is its Cholesky factor, so the
+    preconditioned sample is one step and equals L^{-T} z; the reference takes L from LAPACK's banded
+    Cholesky and solves with scipy's sparse triangular solve."""
+    import scipy.linalg as sl
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    rng = np.random.default_rng(500 + w)
+    offs = [rng.uniform(-1.0, 1.0, n - k) for k in range(1, w + 1)]
+    diag = np.ones(n)
+    for k, o in enumerate(offs, start=1):
+        diag[k:] += np.abs(o)
+        diag[:-k] += np.abs(o)
+    Q = sp.diags([diag] + offs + offs, [0] + list(range(1, w + 1)) + [-k for k in range(1, w + 1)],
+                 format="csr")
+    Q.sort_indices()
+    op, shift = _op(gm, Q, -1.0)
+    assert shift == 0.0
+    ab = np.zeros((w + 1, n))
+    ab[0] = diag
+    for k, o in enumerate(offs, start=1):
+        ab[k, :n - k] = o
+    lb = sl.cholesky_banded(ab, lower=True)
+    L = sp.diags([lb[k, :n - k] for k in range(w + 1)], [-k for k in range(w + 1)], format="csr")
+    z = rng.standard_normal((2, n))
+    X, info = op.sample(_t(z), tol=1e-9, m_max=20, reorth=True)
+    X = X.cpu().numpy()
+    for r in range(2):
+        assert info[r]["status"] == "OK" and info[r]["m_used"] == 1
+        x = spl.spsolve_triangular(L.T.tocsr(), z[r], lower=False)
+        assert _rel(X[r], x) <= 1e-10
+    op.close()
+
+
 def test_logdet(gm):
     op, _ = _op(gm, SEC52, 1e-4)
     L, _ = ichol.ichol(SEC52, 1e-4)
