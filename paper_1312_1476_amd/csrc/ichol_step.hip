@@ -108,7 +108,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __rest
                                                            const int* __restrict__ active) {
   extern __shared__ double smem[];
   const int r = blockIdx.x;
-  if (active && !active[r]) return;   // one value per block: the whole block returns or none does
+  if (n <= 0 || (active && !active[r])) return;   // one value per block: the whole block returns or none does
   const long nv = VLDS ? nnz : 0;      // entries staged in LDS
   double* xs = smem;
   T* sd = (T*)(xs + n);
@@ -118,41 +118,115 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __rest
   int32_t* srow = sci + nv;
   int32_t* slv = srow + n;
   const T* b = B + (size_t)r * bld;
-  for (long i = threadIdx.x; i < n; i += kTrsvThreads) {
-    xs[i] = (double)b[i];
-    sd[i] = dinv[i];
-    srow[i] = rows[i];
+  // Staging in two passes, per-row tables (n + 1 >= nlev + 1 positions) and entries: a thread's loads
+  // of a trip are issued before its LDS stores (clamped addresses, stores masked), so a pass costs a
+  // memory round per kSU or kSE loop trips instead of one per trip.
+  constexpr int kSU = 4, kSE = 8;
+  for (long base = threadIdx.x; base <= n; base += kSU * kTrsvThreads) {
+    double bv[kSU];
+    T dv[kSU];
+    int32_t rw[kSU], lp[kSU];
+    int64_t rs[kSU];
+#pragma unroll
+    for (int u = 0; u < kSU; ++u) {
+      const long t = base + (long)u * kTrsvThreads;
+      const long tr = min(t, n - 1);
+      bv[u] = (double)b[tr];
+      dv[u] = dinv[tr];
+      rw[u] = rows[tr];
+      rs[u] = rp[min(t, n)];
+      lp[u] = lvl_ptr[min(t, (long)nlev)];
+    }
+#pragma unroll
+    for (int u = 0; u < kSU; ++u) {
+      const long t = base + (long)u * kTrsvThreads;
+      if (t < n) {
+        xs[t] = bv[u];
+        sd[t] = dv[u];
+        srow[t] = rw[u];
+      }
+      if (t <= n) srp[t] = (int32_t)rs[u];
+      if (t <= nlev) slv[t] = lp[u];
+    }
   }
-  for (long i = threadIdx.x; i <= n; i += kTrsvThreads) srp[i] = (int32_t)rp[i];
-  for (long e = threadIdx.x; e < nv; e += kTrsvThreads) {
-    sv[e] = va[e];
-    sci[e] = ci[e];
+  for (long base = threadIdx.x; base < nv; base += kSE * kTrsvThreads) {
+    T v[kSE];
+    int32_t c[kSE];
+#pragma unroll
+    for (int u = 0; u < kSE; ++u) {
+      const long e = min(base + (long)u * kTrsvThreads, nv - 1);
+      v[u] = va[e];
+      c[u] = ci[e];
+    }
+#pragma unroll
+    for (int u = 0; u < kSE; ++u) {
+      const long e = base + (long)u * kTrsvThreads;
+      if (e < nv) {
+        sv[e] = v[u];
+        sci[e] = c[u];
+      }
+    }
   }
-  for (int l = threadIdx.x; l <= nlev; l += kTrsvThreads) slv[l] = lvl_ptr[l];
   __syncthreads();
   const int32_t* fc = VLDS ? sci : ci;
   const T* fv = VLDS ? sv : va;
   const int g = (int)threadIdx.x % G;
+  // A level's first pass takes positions e0 + slot.  Their tables (row, entry range, 1 / l_ii) do not
+  // depend on x, so they are read at the end of the previous level, after its x stores and before
+  // its barrier: a level then starts with its entries' loads.  A position past the level's end is
+  // clamped to a valid one and its lane writes nothing; further passes of a wide level read their
+  // tables in place.
+  const int slot = (int)threadIdx.x / G;
+  const int nlast = (int)n - 1;
+  int e0 = 0, e1 = 0, i = 0, q0 = 0, q1n = 0;
+  double di = 0.0;
+  if (nlev > 0) {
+    e0 = slv[0];
+    e1 = slv[1];
+    const int pn = min(e0 + slot, nlast);
+    i = srow[pn];
+    q0 = srp[pn];
+    q1n = srp[pn + 1];
+    di = (double)sd[pn];
+  }
   for (int lev = 0; lev < nlev; ++lev) {
-    const int e0 = slv[lev], e1 = slv[lev + 1];
-    for (int pb = e0; pb < e1; pb += kTrsvThreads / G) {   // the same trip count in every lane
-      const int p = pb + (int)threadIdx.x / G;
-      const bool live = p < e1;
-      const int pc = live ? p : e0;   // a lane past the level's end works on its first row and writes nothing
-      const int i = srow[pc];
-      const int q0 = srp[pc], q1 = live ? srp[pc + 1] : q0;
+    {
+      const bool live = e0 + slot < e1;
       const double bi = xs[i];
       double s = g == 0 ? bi : 0.0;
-      s = trsv_row<G>(s, q0, q1, g, [&](int q) { return fc[q]; }, [&](int q) { return (double)fv[q]; },
+      s = trsv_row<G>(s, q0, live ? q1n : q0, g, [&](int q) { return fc[q]; }, [&](int q) { return (double)fv[q]; },
                       [&](int c) { return xs[c]; });
       s = trsv_group_sum<G>(s);
-      const double di = (double)sd[pc];
       if (live && g == 0) xs[i] = s * di;
+    }
+    for (int pb = e0 + kTrsvThreads / G; pb < e1; pb += kTrsvThreads / G) {   // the same trip count in every lane
+      const int p = pb + slot;
+      const bool live = p < e1;
+      const int pc = live ? p : e0;   // a lane past the level's end works on its first row and writes nothing
+      const int ip = srow[pc];
+      const int p0 = srp[pc], p1 = live ? srp[pc + 1] : p0;
+      const double bi = xs[ip];
+      double s = g == 0 ? bi : 0.0;
+      s = trsv_row<G>(s, p0, p1, g, [&](int q) { return fc[q]; }, [&](int q) { return (double)fv[q]; },
+                      [&](int c) { return xs[c]; });
+      s = trsv_group_sum<G>(s);
+      const double dp = (double)sd[pc];
+      if (live && g == 0) xs[ip] = s * dp;
+    }
+    if (lev + 1 < nlev) {   // the next level's first-pass tables
+      const int e2 = slv[lev + 2];
+      const int pn = min(e1 + slot, nlast);
+      i = srow[pn];
+      q0 = srp[pn];
+      q1n = srp[pn + 1];
+      di = (double)sd[pn];
+      e0 = e1;
+      e1 = e2;
     }
     __syncthreads();   // this level's x are visible to the block before the next level reads them
   }
   OutT* x = X + (size_t)r * xld;
-  for (long i = threadIdx.x; i < n; i += kTrsvThreads) x[i] = (OutT)xs[i];
+  for (long t = threadIdx.x; t < n; t += kTrsvThreads) x[t] = (OutT)xs[t];
 }
 
 // LDS bytes of k_trsv_lds for a solve, with the entries (VLDS) or without (0: does not fit)
