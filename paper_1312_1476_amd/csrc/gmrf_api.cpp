@@ -599,6 +599,8 @@ gmrf_status upload_trsv(const std::vector<int64_t>& rp, const std::vector<int32_
     return s;
   d.nlev = (int)lvl_ptr.size() - 1;
   d.nnz = (int64_t)pci.size();
+  d.max_width = 0;
+  for (int l = 0; l < d.nlev; ++l) d.max_width = std::max(d.max_width, lvl_ptr[(size_t)l + 1] - lvl_ptr[(size_t)l]);
   return GMRF_OK;
 }
 }  // namespace

@@ -39,6 +39,7 @@ struct TrsvDev {
   int nlev = 0;
   int64_t nnz = 0;      // strictly-triangular entries
   int max_row = 0;      // most strictly-triangular entries in one row
+  int max_width = 0;    // most rows in one level
 };
 struct IcholDev {
   TrsvDev fwd, bwd;     // L y = b, L^T x = y

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_levels(const int32_t* __r
 // loads are then LDS loads, or without VLDS one L2 round for the entries, instead of three dependent
 // rounds.  x starts as b in LDS (a row's own entry is read only by its own lane group).  Same
 // arithmetic in the same order as k_trsv_levels with the same G.
-template <typename T, typename OutT, int G, bool VLDS>
+template <typename T, typename OutT, int G, bool VLDS, bool WAVE1>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __restrict__ lvl_ptr,
                                                            const int32_t* __restrict__ rows,
                                                            const int64_t* __restrict__ rp,
@@ -171,59 +171,98 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __rest
   const int32_t* fc = VLDS ? sci : ci;
   const T* fv = VLDS ? sv : va;
   const int g = (int)threadIdx.x % G;
-  // A level's first pass takes positions e0 + slot.  Their tables (row, entry range, 1 / l_ii) do not
-  // depend on x, so they are read at the end of the previous level, after its x stores and before
-  // its barrier: a level then starts with its entries' loads.  A position past the level's end is
-  // clamped to a valid one and its lane writes nothing; further passes of a wide level read their
-  // tables in place.
-  const int slot = (int)threadIdx.x / G;
-  const int nlast = (int)n - 1;
-  int e0 = 0, e1 = 0, i = 0, q0 = 0, q1n = 0;
-  double di = 0.0;
-  if (nlev > 0) {
-    e0 = slv[0];
-    e1 = slv[1];
-    const int pn = min(e0 + slot, nlast);
-    i = srow[pn];
-    q0 = srp[pn];
-    q1n = srp[pn + 1];
-    di = (double)sd[pn];
-  }
-  for (int lev = 0; lev < nlev; ++lev) {
-    {
-      const bool live = e0 + slot < e1;
-      const double bi = xs[i];
-      double s = g == 0 ? bi : 0.0;
-      s = trsv_row<G>(s, q0, live ? q1n : q0, g, [&](int q) { return fc[q]; }, [&](int q) { return (double)fv[q]; },
-                      [&](int c) { return xs[c]; });
-      s = trsv_group_sum<G>(s);
-      if (live && g == 0) xs[i] = s * di;
+  if constexpr (WAVE1) {
+    // Every level fits one pass of one wave (at most kWave / G rows): wave 0 solves all of them and
+    // the other waves wait at the closing barrier.  Between levels the wave needs no block barrier: a
+    // wave's LDS operations execute in order, so the next level's reads see this level's x stores;
+    // wavefront-scope fences around the wave barrier keep the compiler from moving memory accesses
+    // across it.  The next level's tables are read at the end of a level, as below.
+    if (threadIdx.x < kWave) {
+      const int slot = (int)threadIdx.x / G;
+      const int nlast = (int)n - 1;
+      int e0 = slv[0], e1 = slv[min(1, nlev)];
+      int pn = min(e0 + slot, nlast);
+      int i = srow[pn], q0 = srp[pn], q1n = srp[pn + 1];
+      double di = (double)sd[pn];
+      for (int lev = 0; lev < nlev; ++lev) {
+        const bool live = e0 + slot < e1;
+        const double bi = xs[i];
+        double s = g == 0 ? bi : 0.0;
+        s = trsv_row<G>(s, q0, live ? q1n : q0, g, [&](int q) { return fc[q]; },
+                        [&](int q) { return (double)fv[q]; }, [&](int c) { return xs[c]; });
+        s = trsv_group_sum<G>(s);
+        if (live && g == 0) xs[i] = s * di;
+        if (lev + 1 < nlev) {   // the next level's tables
+          const int e2 = slv[lev + 2];
+          pn = min(e1 + slot, nlast);
+          i = srow[pn];
+          q0 = srp[pn];
+          q1n = srp[pn + 1];
+          di = (double)sd[pn];
+          e0 = e1;
+          e1 = e2;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
     }
-    for (int pb = e0 + kTrsvThreads / G; pb < e1; pb += kTrsvThreads / G) {   // the same trip count in every lane
-      const int p = pb + slot;
-      const bool live = p < e1;
-      const int pc = live ? p : e0;   // a lane past the level's end works on its first row and writes nothing
-      const int ip = srow[pc];
-      const int p0 = srp[pc], p1 = live ? srp[pc + 1] : p0;
-      const double bi = xs[ip];
-      double s = g == 0 ? bi : 0.0;
-      s = trsv_row<G>(s, p0, p1, g, [&](int q) { return fc[q]; }, [&](int q) { return (double)fv[q]; },
-                      [&](int c) { return xs[c]; });
-      s = trsv_group_sum<G>(s);
-      const double dp = (double)sd[pc];
-      if (live && g == 0) xs[ip] = s * dp;
-    }
-    if (lev + 1 < nlev) {   // the next level's first-pass tables
-      const int e2 = slv[lev + 2];
-      const int pn = min(e1 + slot, nlast);
+    __syncthreads();   // the solve is complete before the block writes x out
+  } else {
+    // A level's first pass takes positions e0 + slot.  Their tables (row, entry range, 1 / l_ii) do not
+    // depend on x, so they are read at the end of the previous level, after its x stores and before
+    // its barrier: a level then starts with its entries' loads.  A position past the level's end is
+    // clamped to a valid one and its lane writes nothing; further passes of a wide level read their
+    // tables in place.
+    const int slot = (int)threadIdx.x / G;
+    const int nlast = (int)n - 1;
+    int e0 = 0, e1 = 0, i = 0, q0 = 0, q1n = 0;
+    double di = 0.0;
+    if (nlev > 0) {
+      e0 = slv[0];
+      e1 = slv[1];
+      const int pn = min(e0 + slot, nlast);
       i = srow[pn];
       q0 = srp[pn];
       q1n = srp[pn + 1];
       di = (double)sd[pn];
-      e0 = e1;
-      e1 = e2;
     }
-    __syncthreads();   // this level's x are visible to the block before the next level reads them
+    for (int lev = 0; lev < nlev; ++lev) {
+      {
+        const bool live = e0 + slot < e1;
+        const double bi = xs[i];
+        double s = g == 0 ? bi : 0.0;
+        s = trsv_row<G>(s, q0, live ? q1n : q0, g, [&](int q) { return fc[q]; }, [&](int q) { return (double)fv[q]; },
+                        [&](int c) { return xs[c]; });
+        s = trsv_group_sum<G>(s);
+        if (live && g == 0) xs[i] = s * di;
+      }
+      for (int pb = e0 + kTrsvThreads / G; pb < e1; pb += kTrsvThreads / G) {   // the same trip count in every lane
+        const int p = pb + slot;
+        const bool live = p < e1;
+        const int pc = live ? p : e0;   // a lane past the level's end works on its first row and writes nothing
+        const int ip = srow[pc];
+        const int p0 = srp[pc], p1 = live ? srp[pc + 1] : p0;
+        const double bi = xs[ip];
+        double s = g == 0 ? bi : 0.0;
+        s = trsv_row<G>(s, p0, p1, g, [&](int q) { return fc[q]; }, [&](int q) { return (double)fv[q]; },
+                        [&](int c) { return xs[c]; });
+        s = trsv_group_sum<G>(s);
+        const double dp = (double)sd[pc];
+        if (live && g == 0) xs[ip] = s * dp;
+      }
+      if (lev + 1 < nlev) {   // the next level's first-pass tables
+        const int e2 = slv[lev + 2];
+        const int pn = min(e1 + slot, nlast);
+        i = srow[pn];
+        q0 = srp[pn];
+        q1n = srp[pn + 1];
+        di = (double)sd[pn];
+        e0 = e1;
+        e1 = e2;
+      }
+      __syncthreads();   // this level's x are visible to the block before the next level reads them
+    }
   }
   OutT* x = X + (size_t)r * xld;
   for (long t = threadIdx.x; t < n; t += kTrsvThreads) x[t] = (OutT)xs[t];
@@ -272,29 +311,36 @@ static int trsv_group(int max_row) { return max_row <= 4 ? 1 : max_row <= 16 ? 4
 
 // k_trsv_lds above the default dynamic LDS size needs the attribute; set once per instance
 // (thread-safe static initialisation)
-template <typename T, typename OutT, int G, bool VLDS>
+template <typename T, typename OutT, int G, bool VLDS, bool WAVE1>
 static bool trsv_lds_launch(const IcholDev& f, const TrsvDev& d, size_t lb, const T* B, long bld, OutT* X, long xld,
                             const int* active, int k, hipStream_t st) {
   static const bool attr_set = [] {
-    const bool ok = hipFuncSetAttribute((const void*)k_trsv_lds<T, OutT, G, VLDS>,
+    const bool ok = hipFuncSetAttribute((const void*)k_trsv_lds<T, OutT, G, VLDS, WAVE1>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTrsvLdsMaxBytes) ==
                     hipSuccess;
     (void)hipGetLastError();
     return ok;
   }();
   if (!attr_set && lb > 65536) return false;
-  hipLaunchKernelGGL((k_trsv_lds<T, OutT, G, VLDS>), dim3(k), dim3(kTrsvThreads), lb, st, d.lvl_ptr, d.rows, d.rp,
-                     d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, (long)d.nnz, B, bld, X, xld, active);
+  hipLaunchKernelGGL((k_trsv_lds<T, OutT, G, VLDS, WAVE1>), dim3(k), dim3(kTrsvThreads), lb, st, d.lvl_ptr,
+                     d.rows, d.rp, d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, (long)d.nnz, B, bld, X,
+                     xld, active);
   return true;
 }
 
 template <typename T, typename OutT, int G>
 static void launch_trsv_g(const IcholDev& f, const TrsvDev& d, const T* B, long bld, OutT* X, long xld,
                           const int* active, int k, hipStream_t st) {
+  // one wave takes every level when each fits one pass of kWave / G rows
+  const bool wave1 = d.max_width <= kWave / G;
   size_t lb = trsv_lds_bytes<T>(d, f.n, true);
-  if (lb && trsv_lds_launch<T, OutT, G, true>(f, d, lb, B, bld, X, xld, active, k, st)) return;
+  if (lb && (wave1 ? trsv_lds_launch<T, OutT, G, true, true>(f, d, lb, B, bld, X, xld, active, k, st)
+                   : trsv_lds_launch<T, OutT, G, true, false>(f, d, lb, B, bld, X, xld, active, k, st)))
+    return;
   lb = trsv_lds_bytes<T>(d, f.n, false);
-  if (lb && trsv_lds_launch<T, OutT, G, false>(f, d, lb, B, bld, X, xld, active, k, st)) return;
+  if (lb && (wave1 ? trsv_lds_launch<T, OutT, G, false, true>(f, d, lb, B, bld, X, xld, active, k, st)
+                   : trsv_lds_launch<T, OutT, G, false, false>(f, d, lb, B, bld, X, xld, active, k, st)))
+    return;
   if (f.n <= kTrsvLdsRows)
     hipLaunchKernelGGL((k_trsv_levels<T, OutT, true, G>), dim3(k), dim3(kTrsvThreads), (size_t)f.n * sizeof(double),
                        st, d.lvl_ptr, d.rows, d.rp, d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, B, bld,
