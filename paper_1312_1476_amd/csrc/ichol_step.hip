@@ -305,9 +305,30 @@ __global__ __launch_bounds__(kEwThreads) void k_pre_lz(const T* __restrict__ AX,
   if (threadIdx.x == 0) S.part_a[(size_t)r * S.pstride + blockIdx.x] = s;
 }
 
-// Lanes per row for a factor whose longest row holds max_row strictly-triangular entries: one round
-// of four loads per lane covers rows of up to 4 G entries.
-static int trsv_group(int max_row) { return max_row <= 4 ? 1 : max_row <= 16 ? 4 : 16; }
+// Lanes per row G and the form of the LDS solve.  A round of four loads per lane covers 4 G entries of a
+// row; one wave holds kWave / G rows.  Block form: the least G whose round covers the longest row.  One
+// wave (no barrier between levels): the G with the fewest rounds whose pass holds the widest level,
+// taken when it needs no more rounds than the block form's G (on Section 5.2's matrix a second round
+// cost more than the barriers it saved: droptol 1e-4 3.87 -> 4.69 ms per batch).
+struct TrsvShape {
+  int g_block = 16;   // G of the block form (and of the large-matrix kernel)
+  int g_wave = 0;     // G of the one-wave form, 0: not taken
+};
+static TrsvShape trsv_shape(const TrsvDev& d) {
+  static constexpr int kG[4] = {1, 4, 8, 16};
+  auto rounds = [&](int G) { return (d.max_row + 4 * G - 1) / (4 * G); };
+  TrsvShape sh;
+  for (int G : kG)
+    if (4 * G >= d.max_row) {
+      sh.g_block = G;
+      break;
+    }
+  int best = 0;
+  for (int G : kG)
+    if (d.max_width <= kWave / G && (best == 0 || rounds(G) < rounds(best))) best = G;
+  if (best && rounds(best) <= rounds(sh.g_block)) sh.g_wave = best;
+  return sh;
+}
 
 // k_trsv_lds above the default dynamic LDS size needs the attribute; set once per instance
 // (thread-safe static initialisation)
@@ -329,10 +350,8 @@ static bool trsv_lds_launch(const IcholDev& f, const TrsvDev& d, size_t lb, cons
 }
 
 template <typename T, typename OutT, int G>
-static void launch_trsv_g(const IcholDev& f, const TrsvDev& d, const T* B, long bld, OutT* X, long xld,
+static void launch_trsv_g(const IcholDev& f, const TrsvDev& d, bool wave1, const T* B, long bld, OutT* X, long xld,
                           const int* active, int k, hipStream_t st) {
-  // one wave takes every level when each fits one pass of kWave / G rows
-  const bool wave1 = d.max_width <= kWave / G;
   size_t lb = trsv_lds_bytes<T>(d, f.n, true);
   if (lb && (wave1 ? trsv_lds_launch<T, OutT, G, true, true>(f, d, lb, B, bld, X, xld, active, k, st)
                    : trsv_lds_launch<T, OutT, G, true, false>(f, d, lb, B, bld, X, xld, active, k, st)))
@@ -354,10 +373,15 @@ template <typename T, typename OutT>
 void launch_trsv(const IcholDev& f, bool upper, const T* B, long bld, OutT* X, long xld, const int* active, int k,
                  hipStream_t st) {
   const TrsvDev& d = upper ? f.bwd : f.fwd;
-  switch (trsv_group(d.max_row)) {
-    case 1: launch_trsv_g<T, OutT, 1>(f, d, B, bld, X, xld, active, k, st); break;
-    case 4: launch_trsv_g<T, OutT, 4>(f, d, B, bld, X, xld, active, k, st); break;
-    default: launch_trsv_g<T, OutT, 16>(f, d, B, bld, X, xld, active, k, st); break;
+  const TrsvShape sh = trsv_shape(d);
+  // the one-wave form exists only for the LDS kernels
+  const bool lds = trsv_lds_bytes<T>(d, f.n, true) || trsv_lds_bytes<T>(d, f.n, false);
+  const bool wave1 = lds && sh.g_wave;
+  switch (wave1 ? sh.g_wave : sh.g_block) {
+    case 1: launch_trsv_g<T, OutT, 1>(f, d, wave1, B, bld, X, xld, active, k, st); break;
+    case 4: launch_trsv_g<T, OutT, 4>(f, d, wave1, B, bld, X, xld, active, k, st); break;
+    case 8: launch_trsv_g<T, OutT, 8>(f, d, wave1, B, bld, X, xld, active, k, st); break;
+    default: launch_trsv_g<T, OutT, 16>(f, d, wave1, B, bld, X, xld, active, k, st); break;
   }
 }
 

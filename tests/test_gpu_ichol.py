@@ -123,11 +123,11 @@ def test_lattice_as_csr_ic0(gm):
         assert _rel(X[:, r], ref.x) <= 1e-8
 
 
-@pytest.mark.parametrize("n,w", [(7000, 1), (7000, 20), (9000, 6)])
+@pytest.mark.parametrize("n,w", [(7000, 1), (7000, 20), (7000, 40), (9000, 6)])
 def test_banded_exact_factor_large(gm, n, w):
     """Solves too large for the LDS-staged kernels: n = 7000 keeps x in LDS with the factor's tables in
-    global memory, n = 9000 keeps x there too.  Half-bandwidths 1 / 6 / 20 give rows for one thread,
-    4 lanes and 16 lanes.  IC(0) of a banded matrix with a full band is its Cholesky factor, so the
+    global memory, n = 9000 keeps x there too.  Half-bandwidths 1 / 6 / 20 / 40 give rows for one
+    thread, 4, 8 and 16 lanes.  IC(0) of a banded matrix with a full band is its Cholesky factor, so the
     preconditioned sample is one step and equals L^{-T} z; the reference takes L from LAPACK's banded
     Cholesky and solves with scipy's sparse triangular solve."""
     import scipy.linalg as sl
