@@ -2,7 +2,8 @@
 // A v = L^{-1} Q L^{-T} v as a backward solve, the operator, a forward solve; then the opener below and
 // the update kernel finish Algorithm 1's step.  The triangular solves are sequential by nature: rows run
 // level by level (a level holds rows whose dependencies all lie in earlier levels), one block per
-// right-hand side with a barrier between levels, so no block ever waits on another.
+// right-hand side, so no block ever waits on another: a barrier separates the levels, or, where every
+// level fits one wave, that wave takes them all in order.
 #include "ichol.hpp"
 #include "kernels.hpp"
 
