@@ -24,6 +24,9 @@
 namespace gmrf {
 
 constexpr int kTriThreads = 256;
+// T^{-1/2} e_1 takes 512 threads: one node block holds every quadrature node up to an eigenvalue
+// spread of e^107, so the per-node recurrences over m run once
+constexpr int kTriInvThreads = 512;
 constexpr int kTriLdsM = 1024;      // T in LDS up to this many steps
 constexpr int kTriMaxM = 16384;     // longest recurrence the tridiagonal step accepts
 constexpr double kPad = 37.0;
@@ -39,19 +42,20 @@ struct TriArgs {
   double* out;          // y (ldy per RHS) or scalar per RHS
   int ldy;
   int* status_out;      // may be nullptr; only written (ENOTSPD) when T is not SPD
-  double* scratch;      // [k][scr_m][kTriThreads] for the sample
+  double* scratch;      // [k][scr_m][kTriInvThreads] for the sample
   int scr_m;
 };
 
 // Spectrum bracket of T (LDS copies a, b of length m): returns false if T is not SPD.
+template <int NT>
 __device__ bool tri_bracket(const double* a, const double* b, int m, double* red, int* ired,
                             double& lo, double& hi) {
   double g = 0.0;
-  for (int i = threadIdx.x; i < m; i += kTriThreads) {
+  for (int i = threadIdx.x; i < m; i += NT) {
     const double bl = i > 0 ? fabs(b[i - 1]) : 0.0, br = i + 1 < m ? fabs(b[i]) : 0.0;
     g = fmax(g, a[i] + bl + br);
   }
-  hi = block_max<kTriThreads>(g, red);
+  hi = block_max<NT>(g, red);
   // Sturm count at x_t = hi 2^{-t/2}: number of negative pivots of T - x I
   const int t = threadIdx.x;
   const double x = hi * exp2(-0.5 * (double)t);
@@ -69,7 +73,7 @@ __device__ bool tri_bracket(const double* a, const double* b, int m, double* red
   if ((threadIdx.x & (kWave - 1)) == 0) ired[threadIdx.x / kWave] = cand;
   __syncthreads();
   int best = 1 << 30;
-  for (int w = 0; w < kTriThreads / kWave; ++w) best = min(best, ired[w]);
+  for (int w = 0; w < NT / kWave; ++w) best = min(best, ired[w]);
   if (!(hi > 0.0) || !isfinite(hi) || best >= (1 << 30)) return false;
   lo = hi * exp2(-0.5 * (double)best);
   return true;
@@ -99,11 +103,11 @@ __device__ void tri_view(const TriArgs& A, int r, int m, double* sa, double* sb,
 // chain); then each thread sums whole rows over the block's nodes in node order, and the accumulator adds
 // the node blocks in order.
 template <bool LDS>
-__global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
+__global__ __launch_bounds__(kTriInvThreads) void k_tri_invsqrt(TriArgs A) {
   constexpr int LM = LDS ? kTriLdsM : 1;
   __shared__ double sa[LM], sb[LM], sacc[LM];
-  __shared__ double red[kTriThreads / kWave];
-  __shared__ int ired[kTriThreads / kWave];
+  __shared__ double red[kTriInvThreads / kWave];
+  __shared__ int ired[kTriInvThreads / kWave];
   const int r = blockIdx.x;
   // m never exceeds the LDS copy, the scratch rows or the output row
   const int m = min(min(A.m ? A.m[r] : A.m_fixed, LDS ? kTriLdsM : kTriMaxM), min(A.scr_m, A.ldy));
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
   tri_view<LDS>(A, r, m, sa, sb, a, b);
   double* acc = LDS ? sacc : y;     // the node blocks' sums, in order
   double lo, hi;
-  const bool spd = tri_bracket(a, b, m, red, ired, lo, hi);
+  const bool spd = tri_bracket<kTriInvThreads>(a, b, m, red, ired, lo, hi);
   if (!spd) {
     if (threadIdx.x == 0 && A.status_out) A.status_out[r] = kENOTSPD;
     return;
@@ -123,10 +127,10 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
   const double s_lo = 0.5 * log(lo) - kPad, s_hi = 0.5 * log(hi) + kPad;
   const int nq = (int)ceil((s_hi - s_lo) / h) + 1;
   constexpr int AH = 8;   // rows loaded ahead in the forward recurrence
-  // each row's sum is kept by the thread that adds to it (thread i mod kTriThreads), which also clears it
-  for (int i = threadIdx.x; i < m; i += kTriThreads) acc[i] = 0.0;
-  double* rs = A.scratch + (size_t)r * A.scr_m * kTriThreads;
-  for (int base = 0; base < nq; base += kTriThreads) {
+  // each row's sum is kept by the thread that adds to it (thread i mod kTriInvThreads), which also clears it
+  for (int i = threadIdx.x; i < m; i += kTriInvThreads) acc[i] = 0.0;
+  double* rs = A.scratch + (size_t)r * A.scr_m * kTriInvThreads;
+  for (int base = 0; base < nq; base += kTriInvThreads) {
     const int l = base + threadIdx.x;
     const double s = s_lo + h * (double)l;
     const double es = exp(s);
@@ -136,7 +140,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
     double d = a[m - 1] + sigma;
     for (int i = m - 2; i >= 0; --i) {
       const double q = b[i] / d;
-      rs[(size_t)i * kTriThreads + threadIdx.x] = q;
+      rs[(size_t)i * kTriInvThreads + threadIdx.x] = q;
       d = a[i] + sigma - b[i] * q;
     }
     // forward: y_0 = 1 / d_0, y_i = -q_{i-1} y_{i-1}; row i-1 then receives w y_{i-1}
@@ -144,24 +148,24 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
     for (int i0 = 1; i0 < m; i0 += AH) {
       double qv[AH];
 #pragma unroll
-      for (int u = 0; u < AH; ++u) qv[u] = i0 + u < m ? rs[(size_t)(i0 + u - 1) * kTriThreads + threadIdx.x] : 0.0;
+      for (int u = 0; u < AH; ++u) qv[u] = i0 + u < m ? rs[(size_t)(i0 + u - 1) * kTriInvThreads + threadIdx.x] : 0.0;
 #pragma unroll
       for (int u = 0; u < AH; ++u) {
         if (i0 + u < m) {
-          rs[(size_t)(i0 + u - 1) * kTriThreads + threadIdx.x] = wgt * yi;
+          rs[(size_t)(i0 + u - 1) * kTriInvThreads + threadIdx.x] = wgt * yi;
           yi = -qv[u] * yi;
         }
       }
     }
-    rs[(size_t)(m - 1) * kTriThreads + threadIdx.x] = wgt * yi;
+    rs[(size_t)(m - 1) * kTriInvThreads + threadIdx.x] = wgt * yi;
     __syncthreads();   // the block's rows are complete in memory
-    // row sums: thread t takes rows t, t + kTriThreads, ... and adds the row's nodes in order, 16 bytes per
+    // row sums: thread t takes rows t, t + kTriInvThreads, ... and adds the row's nodes in order, 16 bytes per
     // load with all of a row's loads independent (no cross-lane step in the chain)
-    for (int i = threadIdx.x; i < m; i += kTriThreads) {
-      const double2* row = (const double2*)(rs + (size_t)i * kTriThreads);
+    for (int i = threadIdx.x; i < m; i += kTriInvThreads) {
+      const double2* row = (const double2*)(rs + (size_t)i * kTriInvThreads);
       double v = 0.0;
 #pragma unroll 16
-      for (int c = 0; c < kTriThreads / 2; ++c) {
+      for (int c = 0; c < kTriInvThreads / 2; ++c) {
         const double2 pr = row[c];
         v += pr.x;
         v += pr.y;
@@ -171,7 +175,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_invsqrt(TriArgs A) {
     __syncthreads();   // the rows are rewritten by the next node block
   }
   if constexpr (LDS)
-    for (int i = threadIdx.x; i < m; i += kTriThreads) y[i] = acc[i];
+    for (int i = threadIdx.x; i < m; i += kTriInvThreads) y[i] = acc[i];
 }
 
 template <bool LDS>
@@ -187,7 +191,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tri_log(TriArgs A) {
   const double *a, *b;
   tri_view<LDS>(A, r, m, sa, sb, a, b);
   double lo, hi;
-  const bool spd = tri_bracket(a, b, m, red, ired, lo, hi);
+  const bool spd = tri_bracket<kTriThreads>(a, b, m, red, ired, lo, hi);
   if (!spd) {
     if (threadIdx.x == 0) {
       if (A.status_out) A.status_out[r] = kENOTSPD;
@@ -252,7 +256,7 @@ void launch_tri_solve(const double* alpha, int lda, int a_off, const double* bet
 }
 
 int tri_max_m() { return kTriMaxM; }
-size_t tri_scratch_doubles(int k, int m_cap) { return (size_t)k * m_cap * kTriThreads; }
+size_t tri_scratch_doubles(int k, int m_cap) { return (size_t)k * m_cap * kTriInvThreads; }
 
 void launch_tri_invsqrt(const double* alpha, int lda, int a_off, const double* beta, int ldb, int b_off,
                         const int* m, int m_fixed, const int* status_in, double* y, int ldy,
@@ -260,8 +264,8 @@ void launch_tri_invsqrt(const double* alpha, int lda, int a_off, const double* b
   TriArgs A{alpha, lda, a_off, beta, ldb, b_off, m, m_fixed, status_in, y, ldy, status_out, scratch, scr_m};
   // the form follows the caller's capacity (scratch rows), never the data, so a column gets the same form
   // whichever m it stopped at
-  if (scr_m <= kTriLdsM) hipLaunchKernelGGL(k_tri_invsqrt<true>, dim3(k), dim3(kTriThreads), 0, st, A);
-  else hipLaunchKernelGGL(k_tri_invsqrt<false>, dim3(k), dim3(kTriThreads), 0, st, A);
+  if (scr_m <= kTriLdsM) hipLaunchKernelGGL(k_tri_invsqrt<true>, dim3(k), dim3(kTriInvThreads), 0, st, A);
+  else hipLaunchKernelGGL(k_tri_invsqrt<false>, dim3(k), dim3(kTriInvThreads), 0, st, A);
 }
 
 void launch_tri_log(const double* alpha, int lda, int a_off, const double* beta, int ldb, int b_off,
