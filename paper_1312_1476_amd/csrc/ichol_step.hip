@@ -98,7 +98,8 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_levels(const int32_t* __r
 // loads are then LDS loads, or without VLDS one L2 round for the entries, instead of three dependent
 // rounds.  x starts as b in LDS (a row's own entry is read only by its own lane group).  Same
 // arithmetic in the same order as k_trsv_levels with the same G.
-template <typename T, typename OutT, int G, bool VLDS, bool WAVE1>
+// WAVE: 0 block form, 1 one wave with one pass per level, 2 one wave with up to two passes per level.
+template <typename T, typename OutT, int G, bool VLDS, int WAVE>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __restrict__ lvl_ptr,
                                                            const int32_t* __restrict__ rows,
                                                            const int64_t* __restrict__ rp,
@@ -172,9 +173,9 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __rest
   const int32_t* fc = VLDS ? sci : ci;
   const T* fv = VLDS ? sv : va;
   const int g = (int)threadIdx.x % G;
-  if constexpr (WAVE1) {
-    // Every level fits one pass of one wave (at most kWave / G rows): wave 0 solves all of them and
-    // the other waves wait at the closing barrier.  Between levels the wave needs no block barrier: a
+  if constexpr (WAVE > 0) {
+    // Every level fits one wave (kWave / G rows a pass, a wide level in further passes): wave 0 solves
+    // all of them and the other waves wait at the closing barrier.  Between levels the wave needs no block barrier: a
     // wave's LDS operations execute in order, so the next level's reads see this level's x stores;
     // wavefront-scope fences around the wave barrier keep the compiler from moving memory accesses
     // across it.  The next level's tables are read at the end of a level, as below.
@@ -193,6 +194,21 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __rest
                         [&](int q) { return (double)fv[q]; }, [&](int c) { return xs[c]; });
         s = trsv_group_sum<G>(s);
         if (live && g == 0) xs[i] = s * di;
+        if constexpr (WAVE == 2)
+        for (int pb = e0 + kWave / G; pb < e1; pb += kWave / G) {   // the second pass of a wide level
+          const int p = pb + slot;
+          const bool lp = p < e1;
+          const int pc = lp ? p : e0;
+          const int ip = srow[pc];
+          const int p0 = srp[pc], p1 = lp ? srp[pc + 1] : p0;
+          const double bp = xs[ip];
+          double sp = g == 0 ? bp : 0.0;
+          sp = trsv_row<G>(sp, p0, p1, g, [&](int q) { return fc[q]; }, [&](int q) { return (double)fv[q]; },
+                           [&](int c) { return xs[c]; });
+          sp = trsv_group_sum<G>(sp);
+          const double dp = (double)sd[pc];
+          if (lp && g == 0) xs[ip] = sp * dp;
+        }
         if (lev + 1 < nlev) {   // the next level's tables
           const int e2 = slv[lev + 2];
           pn = min(e1 + slot, nlast);
@@ -307,17 +323,20 @@ __global__ __launch_bounds__(kEwThreads) void k_pre_lz(const T* __restrict__ AX,
 }
 
 // Lanes per row G and the form of the LDS solve.  A round of four loads per lane covers 4 G entries of a
-// row; one wave holds kWave / G rows.  Block form: the least G whose round covers the longest row.  One
-// wave (no barrier between levels): the G with the fewest rounds whose pass holds the widest level,
-// taken when it needs no more rounds than the block form's G (on Section 5.2's matrix a second round
-// cost more than the barriers it saved: droptol 1e-4 3.87 -> 4.69 ms per batch).
+// row; one wave holds kWave / G rows a pass.  Block form: the least G whose round covers the longest row.
+// One wave (no barrier between levels): among the G whose wave holds the widest level in at most two
+// passes, the fewest rounds, then the fewest passes; taken when it needs no more rounds than the block
+// form's G (on Section 5.2's matrix a second round cost more than the barriers it saved: droptol 1e-4
+// at G = 8, 3.87 -> 4.69 ms per batch).
 struct TrsvShape {
   int g_block = 16;   // G of the block form (and of the large-matrix kernel)
   int g_wave = 0;     // G of the one-wave form, 0: not taken
+  int passes = 0;     // passes per level of the one-wave form (1 or 2)
 };
 static TrsvShape trsv_shape(const TrsvDev& d) {
   static constexpr int kG[4] = {1, 4, 8, 16};
   auto rounds = [&](int G) { return (d.max_row + 4 * G - 1) / (4 * G); };
+  auto passes = [&](int G) { return (d.max_width + kWave / G - 1) / (kWave / G); };
   TrsvShape sh;
   for (int G : kG)
     if (4 * G >= d.max_row) {
@@ -325,42 +344,53 @@ static TrsvShape trsv_shape(const TrsvDev& d) {
       break;
     }
   int best = 0;
-  for (int G : kG)
-    if (d.max_width <= kWave / G && (best == 0 || rounds(G) < rounds(best))) best = G;
-  if (best && rounds(best) <= rounds(sh.g_block)) sh.g_wave = best;
+  for (int G : kG) {
+    if (passes(G) > 2) continue;
+    if (best == 0 || rounds(G) < rounds(best) || (rounds(G) == rounds(best) && passes(G) < passes(best))) best = G;
+  }
+  if (best && rounds(best) <= rounds(sh.g_block)) {
+    sh.g_wave = best;
+    sh.passes = passes(best);
+  }
   return sh;
 }
 
 // k_trsv_lds above the default dynamic LDS size needs the attribute; set once per instance
 // (thread-safe static initialisation)
-template <typename T, typename OutT, int G, bool VLDS, bool WAVE1>
+template <typename T, typename OutT, int G, bool VLDS, int WAVE>
 static bool trsv_lds_launch(const IcholDev& f, const TrsvDev& d, size_t lb, const T* B, long bld, OutT* X, long xld,
                             const int* active, int k, hipStream_t st) {
   static const bool attr_set = [] {
-    const bool ok = hipFuncSetAttribute((const void*)k_trsv_lds<T, OutT, G, VLDS, WAVE1>,
+    const bool ok = hipFuncSetAttribute((const void*)k_trsv_lds<T, OutT, G, VLDS, WAVE>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTrsvLdsMaxBytes) ==
                     hipSuccess;
     (void)hipGetLastError();
     return ok;
   }();
   if (!attr_set && lb > 65536) return false;
-  hipLaunchKernelGGL((k_trsv_lds<T, OutT, G, VLDS, WAVE1>), dim3(k), dim3(kTrsvThreads), lb, st, d.lvl_ptr,
+  hipLaunchKernelGGL((k_trsv_lds<T, OutT, G, VLDS, WAVE>), dim3(k), dim3(kTrsvThreads), lb, st, d.lvl_ptr,
                      d.rows, d.rp, d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, (long)d.nnz, B, bld, X,
                      xld, active);
   return true;
 }
 
+template <typename T, typename OutT, int G, bool VLDS>
+static bool trsv_lds_form(const IcholDev& f, const TrsvDev& d, int wave, size_t lb, const T* B, long bld, OutT* X,
+                          long xld, const int* active, int k, hipStream_t st) {
+  switch (wave) {
+    case 1: return trsv_lds_launch<T, OutT, G, VLDS, 1>(f, d, lb, B, bld, X, xld, active, k, st);
+    case 2: return trsv_lds_launch<T, OutT, G, VLDS, 2>(f, d, lb, B, bld, X, xld, active, k, st);
+    default: return trsv_lds_launch<T, OutT, G, VLDS, 0>(f, d, lb, B, bld, X, xld, active, k, st);
+  }
+}
+
 template <typename T, typename OutT, int G>
-static void launch_trsv_g(const IcholDev& f, const TrsvDev& d, bool wave1, const T* B, long bld, OutT* X, long xld,
+static void launch_trsv_g(const IcholDev& f, const TrsvDev& d, int wave, const T* B, long bld, OutT* X, long xld,
                           const int* active, int k, hipStream_t st) {
   size_t lb = trsv_lds_bytes<T>(d, f.n, true);
-  if (lb && (wave1 ? trsv_lds_launch<T, OutT, G, true, true>(f, d, lb, B, bld, X, xld, active, k, st)
-                   : trsv_lds_launch<T, OutT, G, true, false>(f, d, lb, B, bld, X, xld, active, k, st)))
-    return;
+  if (lb && trsv_lds_form<T, OutT, G, true>(f, d, wave, lb, B, bld, X, xld, active, k, st)) return;
   lb = trsv_lds_bytes<T>(d, f.n, false);
-  if (lb && (wave1 ? trsv_lds_launch<T, OutT, G, false, true>(f, d, lb, B, bld, X, xld, active, k, st)
-                   : trsv_lds_launch<T, OutT, G, false, false>(f, d, lb, B, bld, X, xld, active, k, st)))
-    return;
+  if (lb && trsv_lds_form<T, OutT, G, false>(f, d, wave, lb, B, bld, X, xld, active, k, st)) return;
   if (f.n <= kTrsvLdsRows)
     hipLaunchKernelGGL((k_trsv_levels<T, OutT, true, G>), dim3(k), dim3(kTrsvThreads), (size_t)f.n * sizeof(double),
                        st, d.lvl_ptr, d.rows, d.rp, d.ci, (const T*)d.va, (const T*)d.dinv, d.nlev, (long)f.n, B, bld,
@@ -377,12 +407,12 @@ void launch_trsv(const IcholDev& f, bool upper, const T* B, long bld, OutT* X, l
   const TrsvShape sh = trsv_shape(d);
   // the one-wave form exists only for the LDS kernels
   const bool lds = trsv_lds_bytes<T>(d, f.n, true) || trsv_lds_bytes<T>(d, f.n, false);
-  const bool wave1 = lds && sh.g_wave;
-  switch (wave1 ? sh.g_wave : sh.g_block) {
-    case 1: launch_trsv_g<T, OutT, 1>(f, d, wave1, B, bld, X, xld, active, k, st); break;
-    case 4: launch_trsv_g<T, OutT, 4>(f, d, wave1, B, bld, X, xld, active, k, st); break;
-    case 8: launch_trsv_g<T, OutT, 8>(f, d, wave1, B, bld, X, xld, active, k, st); break;
-    default: launch_trsv_g<T, OutT, 16>(f, d, wave1, B, bld, X, xld, active, k, st); break;
+  const int wave = lds && sh.g_wave ? sh.passes : 0;
+  switch (wave ? sh.g_wave : sh.g_block) {
+    case 1: launch_trsv_g<T, OutT, 1>(f, d, wave, B, bld, X, xld, active, k, st); break;
+    case 4: launch_trsv_g<T, OutT, 4>(f, d, wave, B, bld, X, xld, active, k, st); break;
+    case 8: launch_trsv_g<T, OutT, 8>(f, d, wave, B, bld, X, xld, active, k, st); break;
+    default: launch_trsv_g<T, OutT, 16>(f, d, wave, B, bld, X, xld, active, k, st); break;
   }
 }
 
