@@ -194,20 +194,21 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv_lds(const int32_t* __rest
                         [&](int q) { return (double)fv[q]; }, [&](int c) { return xs[c]; });
         s = trsv_group_sum<G>(s);
         if (live && g == 0) xs[i] = s * di;
-        if constexpr (WAVE == 2)
-        for (int pb = e0 + kWave / G; pb < e1; pb += kWave / G) {   // the second pass of a wide level
-          const int p = pb + slot;
-          const bool lp = p < e1;
-          const int pc = lp ? p : e0;
-          const int ip = srow[pc];
-          const int p0 = srp[pc], p1 = lp ? srp[pc + 1] : p0;
-          const double bp = xs[ip];
-          double sp = g == 0 ? bp : 0.0;
-          sp = trsv_row<G>(sp, p0, p1, g, [&](int q) { return fc[q]; }, [&](int q) { return (double)fv[q]; },
-                           [&](int c) { return xs[c]; });
-          sp = trsv_group_sum<G>(sp);
-          const double dp = (double)sd[pc];
-          if (lp && g == 0) xs[ip] = sp * dp;
+        if constexpr (WAVE == 2) {
+          for (int pb = e0 + kWave / G; pb < e1; pb += kWave / G) {   // further passes of a wide level
+            const int p = pb + slot;
+            const bool lp = p < e1;
+            const int pc = lp ? p : e0;
+            const int ip = srow[pc];
+            const int p0 = srp[pc], p1 = lp ? srp[pc + 1] : p0;
+            const double bp = xs[ip];
+            double sp = g == 0 ? bp : 0.0;
+            sp = trsv_row<G>(sp, p0, p1, g, [&](int q) { return fc[q]; }, [&](int q) { return (double)fv[q]; },
+                             [&](int c) { return xs[c]; });
+            sp = trsv_group_sum<G>(sp);
+            const double dp = (double)sd[pc];
+            if (lp && g == 0) xs[ip] = sp * dp;
+          }
         }
         if (lev + 1 < nlev) {   // the next level's tables
           const int e2 = slv[lev + 2];
