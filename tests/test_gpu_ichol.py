@@ -160,6 +160,35 @@ def test_banded_exact_factor_large(gm, n, w):
     op.close()
 
 
+@pytest.mark.parametrize("n,bs", [(2000, 2), (2400, 12)])
+def test_block_diagonal_exact_factor_wide_levels(gm, n, bs):
+    """Levels wider than one wave's two passes, in a solve that fits LDS: the block form of the LDS
+    kernel.  Q is block diagonal with dense SPD blocks of size bs, so IC(0) is its Cholesky factor and
+    every level holds one row of each block (n / bs rows).  bs = 2: the entries in LDS, one thread per
+    row; bs = 12: the entries in global memory (they do not fit beside the tables), 4 lanes per row.
+    One step samples x = L^{-T} z; the reference factors each block with numpy's Cholesky."""
+    import scipy.sparse as sp
+    import scipy.linalg as sl
+    rng = np.random.default_rng(600 + bs)
+    blocks = []
+    for _ in range(n // bs):
+        M = rng.standard_normal((bs, bs))
+        blocks.append(M @ M.T + bs * np.eye(bs))
+    Q = sp.block_diag(blocks, format="csr")
+    Q.sort_indices()
+    op, shift = _op(gm, Q, -1.0)
+    assert shift == 0.0
+    L = sl.block_diag(*[np.linalg.cholesky(B) for B in blocks])
+    z = rng.standard_normal((2, n))
+    X, info = op.sample(_t(z), tol=1e-9, m_max=20, reorth=True)
+    X = X.cpu().numpy()
+    for r in range(2):
+        assert info[r]["status"] == "OK" and info[r]["m_used"] == 1
+        x = sl.solve_triangular(L, z[r], lower=True, trans="T")
+        assert _rel(X[r], x) <= 1e-10
+    op.close()
+
+
 def test_logdet(gm):
     op, _ = _op(gm, SEC52, 1e-4)
     L, _ = ichol.ichol(SEC52, 1e-4)
